@@ -1,0 +1,206 @@
+/*
+ * fld.h - C ABI of the MI355X implicit flux-limited-diffusion (FLD) radiation step.
+ *
+ * One call of fld_step advances the radiation energy density E_r and the gas
+ * temperature T_g of a 2D finite-volume grid by one backward-Euler step of the
+ * coupled system of Chen et al. ("Guangqi"), Section 3.2.1:
+ *
+ *   radiation row : phi_1..phi_11 (5-point stencil in E, local T coupling),
+ *   gas row       : psi_5, psi_6, psi_11 (local),
+ *   with the FLD closure F = -D grad E, D = c lambda(R) / (kappa_R rho)
+ *   (Section 2) and (T^{n+1})^4 linearised about T^n.
+ *
+ * The library eliminates T exactly, solves the resulting symmetric positive
+ * definite E system (volume-weighted rows) with matrix-free conjugate gradients
+ * preconditioned by a geometric-multigrid V-cycle, optionally in FP32 inside
+ * an FP64 iterative-refinement loop, and recovers T^{n+1} from the psi row.
+ *
+ * Conventions (all entry points):
+ *  - Cell arrays are row-major [ny][nx] (x or r fastest), IEEE binary64,
+ *    DEVICE pointers owned by the caller.  They must stay valid until the work
+ *    queued on the context's stream has finished.
+ *  - Every call is queued on the stream given to fld_create (a hipStream_t;
+ *    NULL = the default stream).  A call that returns a fld_solve_info, or
+ *    that must test convergence, synchronises that stream.
+ *  - The context owns all workspace; it is allocated in fld_create /
+ *    fld_batch_create.  No other entry point allocates device memory.
+ *  - Errors are returned as fld_status, never thrown; fld_last_error gives a
+ *    human-readable message.  Contexts are not thread-safe: use one per stream.
+ *  - Units are cgs.  The azimuthal factor 2 pi of spherical-polar volumes and
+ *    areas is dropped throughout (it cancels).
+ */
+#ifndef FLD_H
+#define FLD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fld_ctx fld_ctx;
+
+typedef enum {
+    FLD_OK = 0,
+    FLD_EINVAL = 1,        /* bad argument: sizes, pointers, dt <= 0, unknown enum value     */
+    FLD_ENOMEM = 2,        /* device or pinned allocation failed (create calls only)          */
+    FLD_EHIP = 3,          /* a HIP runtime call failed                                        */
+    FLD_ENOCONV = 4,       /* tolerance not reached within max_outer / max_inner               */
+    FLD_EBREAKDOWN = 5,    /* CG breakdown: p.Ap <= 0 or non-finite scalar                     */
+    FLD_ENONFINITE = 6,    /* an input field is non-finite or outside its domain (E,T,rho,    */
+                           /* kappa_R > 0; kappa_P, c_v >= 0), detected on the device          */
+    FLD_ENOTREADY = 7      /* fld_solve / fld_get_operator called before fld_assemble          */
+} fld_status;
+
+/* Grid geometry: Cartesian (x, y) or spherical-polar (r, theta), Section 3.2. */
+typedef enum { FLD_CARTESIAN = 0, FLD_SPHERICAL_POLAR = 1 } fld_geom;
+
+/* Boundary condition of one side.  Interior faces follow the paper's
+ * interface coefficient (Section 3.2.1); the paper prints only zero-gradient
+ * and Milne boundaries, so the kinds below are this library's readings:
+ *   REFLECT         zero flux (zero-gradient radiation boundary, Section 5.2.2).
+ *   DIRICHLET_FACE  E = a_R value^4 on the face (value = boundary temperature, K);
+ *                   face opacity = first cell's, distance = centre to face.
+ *   DIRICHLET_GHOST ghost cell mirrored across the face holding E from the
+ *                   ghost_E array passed to fld_assemble / fld_step.
+ *   FLUX_IN         fixed inward flux, value = F_in [erg cm^-2 s^-1].
+ *   FREE_STREAM     outward flux c E of the first cell.
+ *   AXIS            theta = 0 or pi of a spherical-polar grid: zero area, zero flux. */
+typedef enum {
+    FLD_BC_REFLECT = 0, FLD_BC_DIRICHLET_FACE = 1, FLD_BC_DIRICHLET_GHOST = 2,
+    FLD_BC_FLUX_IN = 3, FLD_BC_FREE_STREAM = 4, FLD_BC_AXIS = 5
+} fld_bc_kind;
+
+/* Side order in fld_grid.bc and in the packed ghost array:
+ *   0 = x_lo (ny values), 1 = x_hi (ny), 2 = y_lo (nx), 3 = y_hi (nx). */
+typedef struct { int32_t kind; double value; } fld_bc;
+
+typedef struct {
+    int32_t nx, ny;            /* cells; 1 <= nx, ny; nx * ny <= 2^28                       */
+    int32_t geom;              /* fld_geom                                                   */
+    const double* x_faces;     /* HOST array of nx+1 increasing face coordinates (cm; r > 0) */
+    const double* y_faces;     /* HOST array of ny+1 increasing faces (cm, or radians in [0, pi]) */
+    fld_bc bc[4];
+} fld_grid;
+
+/* Inner (Krylov / multigrid) precision.
+ *   FP64  : all arithmetic and storage in binary64.
+ *   FP32  : one binary32 solve of the correction equation, no refinement.
+ *   MIXED : binary32 storage and arithmetic inside CG and the V-cycle; residuals,
+ *           norms, dot-product accumulation, the T^4 linearisation and the
+ *           solution update in binary64 (iterative refinement). */
+typedef enum { FLD_FP64 = 0, FLD_FP32 = 1, FLD_MIXED = 2 } fld_precision;
+
+/* Flux limiter lambda(R), Section 2: Levermore-Pomraning (coth R - 1/R)/R
+ * (default), the paper's Minerbo-type piecewise form, or the pure-diffusion
+ * value 1/3. */
+typedef enum { FLD_LIMITER_LP = 0, FLD_LIMITER_MINERBO = 1, FLD_LIMITER_DIFFUSION = 2 } fld_limiter;
+
+/* Stopping norm (Section 3.2.1 stop rule ||b - A x|| < eps ||b||):
+ *   ROW    : per-volume rows, ||(rhs - M E)/dV||_2 <= eps ||rhs/dV||_2 (the phi rows);
+ *   SCALED : Jacobi-scaled rows, ||S (rhs - M E)||_2 <= eps ||S rhs||_2, S = diag(M)^-1/2. */
+typedef enum { FLD_NORM_ROW = 0, FLD_NORM_SCALED = 1 } fld_norm;
+
+/* Multigrid coarse operator: GALERKIN = P^T A P with 2x2 piecewise-constant
+ * aggregation; HALVED = same aggregation with the coarse face couplings halved
+ * (rediscretisation scaling; mass part still summed). */
+typedef enum { FLD_MG_GALERKIN = 0, FLD_MG_HALVED = 1 } fld_mg_coarse;
+
+typedef struct {
+    int32_t precision;      /* fld_precision (default MIXED)                                 */
+    int32_t limiter;        /* fld_limiter (default LP)                                      */
+    int32_t norm;           /* fld_norm (default ROW)                                        */
+    double  rel_tol;        /* eps of the stop rule (default 1e-10)                          */
+    int32_t max_outer;      /* refinement steps (default 8; FP32 mode uses 1)                */
+    int32_t max_inner;      /* CG iterations per refinement step (default 2000)             */
+    double  inner_rtol;     /* residual reduction asked of one inner solve in MIXED / FP32   */
+                            /* (default 1e-5); FP64 solves straight to the target            */
+    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (<= 256, def 64) */
+    int32_t mg_coarse_op;   /* fld_mg_coarse (default GALERKIN)                              */
+    int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
+    int32_t use_graph;      /* capture each chunk as a hipGraph (default 1)                  */
+} fld_options;
+
+typedef struct {
+    int32_t status;         /* fld_status of the solve                                       */
+    int32_t outer_iters;    /* refinement steps taken                                        */
+    int32_t inner_iters;    /* CG iterations summed over refinement steps                    */
+    int32_t mg_levels;      /* multigrid levels (fine level included)                        */
+    double  rel_resid;      /* final relative residual in the selected norm (FP64)           */
+    double  rel_resid_row;  /* final relative residual in the ROW norm                       */
+    double  rel_resid_scaled; /* final relative residual in the SCALED norm                 */
+    float   ms;             /* wall time of the call, host clock, ms                         */
+} fld_solve_info;
+
+/* Fills *opt with the defaults listed above. */
+void fld_default_options(fld_options* opt);
+
+/* Creates a context for one grid.  Computes the grid metrics (cell volumes,
+ * face areas, volume-centre distances; Section 3.2.1 g = dS/dV and alpha) on
+ * the device and allocates all workspace.  grid->x_faces / y_faces are read
+ * during the call only.  stream: hipStream_t (NULL = default stream).
+ * opt may be NULL (defaults).  Returns EINVAL for bad sizes / enums / faces,
+ * ENOMEM, EHIP. */
+fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* opt, void* stream);
+
+/* Assembles the system of one step (Section 3.2.1 coefficient list, eliminated
+ * T; Section 3.2.1 steps 2-5): face conductances W = dt dS D / h, the diagonal
+ * dV (1 + beta f) + sum W + boundary terms, the right-hand side
+ * dV (E^n + beta f a_R T^4) + boundary terms, the Jacobi scaling and the
+ * multigrid hierarchy.  beta = kappa_P rho c dt, f = C_V / (C_V + 4 beta a_R T^3),
+ * C_V = rho c_v.  Inputs are device arrays of nx*ny doubles; ghost_E (device,
+ * 2 ny + 2 nx doubles, side order as above) is read only for DIRICHLET_GHOST
+ * sides and may be NULL otherwise.  The context keeps the T, rho, kappa_P, c_v
+ * pointers for the gas update of fld_step; they must not change before it.
+ * Asynchronous; invalid field values are reported by the next fld_solve. */
+fld_status fld_assemble(fld_ctx* ctx, const double* E_r, const double* T_g, const double* rho,
+                        const double* kappa_R, const double* kappa_P, const double* c_v,
+                        const double* ghost_E, double dt);
+
+/* Solves the assembled system (Section 3.2.1 step 6).  E_new (device, nx*ny):
+ * on entry the initial guess (e.g. E^n), on return E^{n+1}.  info (host) may be
+ * NULL.  Synchronises the context's stream.  Returns ENOCONV / EBREAKDOWN /
+ * ENONFINITE as described above (E_new then holds the last iterate). */
+fld_status fld_solve(fld_ctx* ctx, double* E_new, fld_solve_info* info);
+
+/* Gas update from the psi row (Section 3.2.1 psi_5, psi_6, psi_11):
+ * T^{n+1} = (C_V T^n + 3 beta a_R T^4 + beta E^{n+1}) / (C_V + 4 beta a_R T^3),
+ * using the T^n, rho, kappa_P, c_v pointers of the last fld_assemble and
+ * writing T^{n+1} to T_out (device, may alias that T^n).  Asynchronous. */
+fld_status fld_gas_update(fld_ctx* ctx, const double* E_new, double* T_out);
+
+/* One implicit radiation step = assemble + solve + gas update.  E_r and T_g
+ * are updated in place (device).  info may be NULL. */
+fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, const double* kappa_R,
+                    const double* kappa_P, const double* c_v, const double* ghost_E, double dt,
+                    fld_solve_info* info);
+
+/* nsteps consecutive steps with (E, T) <- (E^{n+1}, T^{n+1}) and the opacities,
+ * rho and c_v held fixed (Section 3.2.1 sub-step loop, one sub-step per step).
+ * Each step's solve runs as captured hipGraph chunks with a fixed iteration
+ * schedule and device-side early exit.  per_step (host, nsteps entries) may
+ * be NULL.  Returns the first non-OK step status. */
+fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
+                     const double* kappa_R, const double* kappa_P, const double* c_v,
+                     const double* ghost_E, double dt, fld_solve_info* per_step);
+
+/* Copies the assembled FP64 operator of the last fld_assemble to caller device
+ * arrays of nx*ny doubles (any may be NULL): W_e[j][i] = conductance of the
+ * face between cells i and i+1 (0 in the last column), W_n[j][i] = face between
+ * rows j and j+1 (0 in the last row), diag = full diagonal, rhs.  For tests. */
+fld_status fld_get_operator(fld_ctx* ctx, double* W_e, double* W_n, double* diag, double* rhs);
+
+/* Number of multigrid levels built by the last fld_assemble (fine included). */
+int32_t fld_mg_levels(const fld_ctx* ctx);
+
+const char* fld_status_string(fld_status s);
+const char* fld_last_error(const fld_ctx* ctx);
+const char* fld_version(void);
+
+/* Releases the context and all its device memory.  NULL is accepted. */
+void fld_destroy(fld_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLD_H */

@@ -1,0 +1,201 @@
+"""ctypes binding of libfld (include/fld.h).
+
+Argument marshalling only: torch tensors are passed as device pointers, the
+current HIP stream as the context stream.  Every computation runs in the HIP
+kernels of libfld.so; if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfld.so")
+
+FLD_OK, FLD_EINVAL, FLD_ENOMEM, FLD_EHIP, FLD_ENOCONV, FLD_EBREAKDOWN, FLD_ENONFINITE, FLD_ENOTREADY = range(8)
+FLD_CARTESIAN, FLD_SPHERICAL_POLAR = 0, 1
+(FLD_BC_REFLECT, FLD_BC_DIRICHLET_FACE, FLD_BC_DIRICHLET_GHOST, FLD_BC_FLUX_IN, FLD_BC_FREE_STREAM,
+ FLD_BC_AXIS) = range(6)
+FLD_FP64, FLD_FP32, FLD_MIXED = 0, 1, 2
+FLD_LIMITER_LP, FLD_LIMITER_MINERBO, FLD_LIMITER_DIFFUSION = 0, 1, 2
+FLD_NORM_ROW, FLD_NORM_SCALED = 0, 1
+FLD_MG_GALERKIN, FLD_MG_HALVED = 0, 1
+
+PRECISIONS = {"fp64": FLD_FP64, "fp32": FLD_FP32, "mixed": FLD_MIXED}
+
+
+class fld_bc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class fld_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("geom", ctypes.c_int32),
+                ("x_faces", ctypes.POINTER(ctypes.c_double)), ("y_faces", ctypes.POINTER(ctypes.c_double)),
+                ("bc", fld_bc * 4)]
+
+
+class fld_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("limiter", ctypes.c_int32), ("norm", ctypes.c_int32),
+                ("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("mg_coarse_max", ctypes.c_int32),
+                ("mg_coarse_op", ctypes.c_int32), ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class fld_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("rel_resid", ctypes.c_double), ("rel_resid_row", ctypes.c_double),
+                ("rel_resid_scaled", ctypes.c_double), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfld.so not built ({LIB_PATH}); run __graft_entry__.build() or "
+                          "python paper_2602_12545_amd/build.py")
+    return ctypes.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int32
+_SIGS = {
+    "fld_default_options": (None, [ctypes.POINTER(fld_options)]),
+    "fld_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(fld_grid), ctypes.POINTER(fld_options), _P]),
+    "fld_assemble": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D]),
+    "fld_solve": (_I, [_P, _P, ctypes.POINTER(fld_solve_info)]),
+    "fld_gas_update": (_I, [_P, _P, _P]),
+    "fld_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
+    "fld_mg_levels": (_I, [_P]),
+    "fld_status_string": (ctypes.c_char_p, [_I]),
+    "fld_last_error": (ctypes.c_char_p, [_P]),
+    "fld_version": (ctypes.c_char_p, []),
+    "fld_destroy": (None, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class FLDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{lib.fld_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def default_options(**kw) -> fld_options:
+    o = fld_options()
+    lib.fld_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("fields must be contiguous float64 tensors on the GPU")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream or None
+
+
+class Context:
+    """One grid: wraps fld_create ... fld_destroy.  Fields are torch float64 GPU tensors [ny, nx]."""
+
+    def __init__(self, nx: int, ny: int, geom: int, x_faces, y_faces, bcs: Sequence, options=None, stream=None):
+        import numpy as np
+        self._xf = np.ascontiguousarray(x_faces, dtype=np.float64)
+        self._yf = np.ascontiguousarray(y_faces, dtype=np.float64)
+        if self._xf.size != nx + 1 or self._yf.size != ny + 1:
+            raise ValueError("face arrays must have nx+1 and ny+1 entries")
+        g = fld_grid()
+        g.nx, g.ny, g.geom = nx, ny, geom
+        g.x_faces = self._xf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.y_faces = self._yf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        for s, b in enumerate(bcs):
+            kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
+            g.bc[s].kind, g.bc[s].value = int(kind), float(value)
+        self.options = options if options is not None else default_options()
+        self.nx, self.ny = nx, ny
+        h = _P()
+        st = lib.fld_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(self.options), _stream_handle(stream))
+        if st != FLD_OK:
+            msg = lib.fld_last_error(h).decode() if h.value else ""
+            lib.fld_destroy(h)
+            raise FLDError(st, msg)
+        self.handle = h
+
+    def _check(self, st):
+        if st != FLD_OK:
+            raise FLDError(st, lib.fld_last_error(self.handle).decode())
+
+    def assemble(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None):
+        self._check(lib.fld_assemble(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P),
+                                     _ptr(c_v), _ptr(ghost_E), float(dt)))
+
+    def solve(self, E, check=True) -> dict:
+        info = fld_solve_info()
+        st = lib.fld_solve(self.handle, _ptr(E), ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict()
+
+    def gas_update(self, E, T_out):
+        self._check(lib.fld_gas_update(self.handle, _ptr(E), _ptr(T_out)))
+
+    def step(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, check=True) -> dict:
+        info = fld_solve_info()
+        st = lib.fld_step(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P), _ptr(c_v),
+                          _ptr(ghost_E), float(dt), ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict()
+
+    def steps(self, nsteps, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, check=True):
+        infos = (fld_solve_info * max(1, nsteps))()
+        st = lib.fld_steps(self.handle, int(nsteps), _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P),
+                           _ptr(c_v), _ptr(ghost_E), float(dt), infos)
+        if check:
+            self._check(st)
+        return [infos[k].as_dict() for k in range(nsteps)]
+
+    def get_operator(self):
+        import torch
+        shape = (self.ny, self.nx)
+        out = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+        self._check(lib.fld_get_operator(self.handle, *[_ptr(t) for t in out]))
+        return dict(zip(("W_e", "W_n", "diag", "rhs"), out))
+
+    @property
+    def mg_levels(self) -> int:
+        return lib.fld_mg_levels(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.fld_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

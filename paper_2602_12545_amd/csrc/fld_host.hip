@@ -1,0 +1,542 @@
+// Host driver and C ABI of libfld (see include/fld.h).
+//
+// The solve is device-driven: every CG iteration is a fixed sequence of
+// kernels ("slot") that exit at once when the device flag `done` is set, so
+// the host can queue (or replay as a hipGraph) a chunk of slots and only polls
+// the flag between chunks.  Reliable updates (FP64 correction of E, true FP64
+// residual, re-scaled inner residual) are decided on the device inside a slot.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fld.h"
+#include "fld_kernels.hpp"
+
+using namespace fld;
+
+namespace {
+
+constexpr const char* kVersion = "fld-mi355x 0.1";
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
+            return FLD_EHIP;                                                                  \
+        }                                                                                     \
+    } while (0)
+
+struct Level64 {
+    int nx = 0, ny = 0;
+    double *mass = nullptr, *ae = nullptr, *an = nullptr;
+};
+
+template <typename T>
+struct LevelT {
+    int nx = 0, ny = 0;
+    T *d = nullptr, *ae = nullptr, *an = nullptr;  // d == nullptr on level 0 (unit diagonal)
+    T *b = nullptr, *xpre = nullptr, *xout = nullptr;
+};
+
+template <typename T>
+struct Inner {
+    std::vector<LevelT<T>> lv;
+    T* Ainv = nullptr;
+    T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    hipGraphExec_t chunk_exec = nullptr;
+    int chunk_len = 0;
+};
+
+}  // namespace
+
+struct fld_ctx {
+    int nx = 0, ny = 0, geom = 0;
+    BCDev bc{};
+    fld_options opt{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+    std::vector<void*> allocs;
+    // metrics
+    double *xf = nullptr, *yf = nullptr;
+    Metrics met{};
+    // assembled FP64 operator
+    double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
+    std::vector<Level64> h64;
+    double* part = nullptr;
+    size_t npart = 0;
+    Scalars* sc = nullptr;
+    Scalars* hsc = nullptr;  // pinned mirror
+    int* err_flag = nullptr;
+    int* herr = nullptr;     // pinned
+    bool assembled = false;
+    // inputs of the last assemble (for the gas update)
+    const double *T = nullptr, *rho = nullptr, *kP = nullptr, *cv = nullptr;
+    double dt = 0.0;
+    Inner<float> i32;
+    Inner<double> i64;
+
+    template <typename U>
+    hipError_t alloc(U** p, size_t n) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(U) * (n ? n : 1));
+        if (e == hipSuccess) {
+            allocs.push_back(q);
+            *p = static_cast<U*>(q);
+        }
+        return e;
+    }
+};
+
+namespace {
+
+inline dim3 tile_grid(int nx, int ny) { return dim3((nx + TBX - 1) / TBX, (ny + TRows - 1) / TRows); }
+inline dim3 cell_grid(int nx, int ny) { return dim3((nx + TBX - 1) / TBX, (ny + TBY - 1) / TBY); }
+inline dim3 blk2d() { return dim3(TBX, TBY); }
+inline int grid1d(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (int)(b < (size_t)k1DBlocksMax ? (b ? b : 1) : (size_t)k1DBlocksMax);
+}
+
+bool inner_is_float(const fld_ctx* c) { return c->opt.precision != FLD_FP64; }
+
+template <typename T>
+Inner<T>& inner(fld_ctx* c);
+template <>
+Inner<float>& inner<float>(fld_ctx* c) { return c->i32; }
+template <>
+Inner<double>& inner<double>(fld_ctx* c) { return c->i64; }
+
+fld_status validate_options(const fld_options* o, std::string& err) {
+    if (o->precision < 0 || o->precision > 2) { err = "precision"; return FLD_EINVAL; }
+    if (o->limiter < 0 || o->limiter > 2) { err = "limiter"; return FLD_EINVAL; }
+    if (o->norm < 0 || o->norm > 1) { err = "norm"; return FLD_EINVAL; }
+    if (!(o->rel_tol > 0.0) || !(o->rel_tol < 1.0)) { err = "rel_tol must be in (0, 1)"; return FLD_EINVAL; }
+    if (o->max_outer < 1 || o->max_inner < 1) { err = "max_outer / max_inner must be >= 1"; return FLD_EINVAL; }
+    if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) { err = "inner_rtol must be in (0, 1)"; return FLD_EINVAL; }
+    if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 64]"; return FLD_EINVAL; }
+    if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
+    if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
+    return FLD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle and CG slot (queued on stream `st`)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
+    const int L = (int)in.lv.size();
+    const T omega = T(1);
+    if (L == 1) {
+        LevelT<T>& l0 = in.lv[0];
+        k_coarse_solve<T, true><<<1, kCoarseMax, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.b, l0.xout, c->part, c->sc);
+        return;
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        LevelT<T>& a = in.lv[l];
+        LevelT<T>& b = in.lv[l + 1];
+        if (l == 0)
+            k_pre<T, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, nullptr, a.ae, a.an, a.xpre, b.b,
+                                                                      b.nx, b.ny, c->sc);
+        else
+            k_pre<T, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, a.d, a.ae, a.an, a.xpre, b.b,
+                                                                       b.nx, b.ny, c->sc);
+    }
+    LevelT<T>& cl = in.lv[L - 1];
+    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.b, cl.xout, c->part, c->sc);
+    for (int l = L - 2; l >= 0; --l) {
+        LevelT<T>& a = in.lv[l];
+        LevelT<T>& b = in.lv[l + 1];
+        if (l == 0)
+            k_post<T, true, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, nullptr, a.ae, a.an,
+                                                                             a.xpre, b.xout, b.nx, omega, a.xout,
+                                                                             c->part, c->sc);
+        else
+            k_post<T, false, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, a.d, a.ae, a.an,
+                                                                               a.xpre, b.xout, b.nx, omega, a.xout,
+                                                                               c->part, c->sc);
+    }
+}
+
+// One CG iteration ("slot"); `par` selects the p buffer pair (iterations
+// alternate between the two).  E is the FP64 solution being refined.
+template <typename T>
+void enqueue_slot_E(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) {
+    const int nx = c->nx, ny = c->ny, n = nx * ny;
+    LevelT<T>& l0 = in.lv[0];
+    k_spmv<T><<<tile_grid(nx, ny), blk2d(), 0, st>>>(nx, ny, l0.xout, in.p[par], in.p[par ^ 1], in.q, l0.ae, l0.an,
+                                                     c->part, c->sc);
+    k_update<T><<<grid1d(n), 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, c->sc);
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, c->s, in.x, c->sc, 0);
+    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part,
+                                                     c->sc, 0);
+    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, c->s, in.r, in.x, c->sc, 0);
+    enqueue_vcycle<T>(c, in, st);
+}
+
+template <typename T>
+fld_status build_hierarchy(fld_ctx* c) {
+    Inner<T>& in = inner<T>(c);
+    hipStream_t st = c->stream;
+    const int L = (int)in.lv.size();
+    // level 0 (FP64 scaled operator)
+    k_scale<<<cell_grid(c->nx, c->ny), blk2d(), 0, st>>>(c->nx, c->ny, c->We, c->Wn, c->s, c->h64[0].ae, c->h64[0].an,
+                                                         c->h64[0].mass);
+    k_demote_level<T><<<cell_grid(c->nx, c->ny), blk2d(), 0, st>>>(c->nx, c->ny, c->h64[0].mass, c->h64[0].ae,
+                                                                   c->h64[0].an, (T*)nullptr, in.lv[0].ae, in.lv[0].an);
+    const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
+    for (int l = 1; l < L; ++l) {
+        Level64& a = c->h64[l - 1];
+        Level64& b = c->h64[l];
+        k_coarsen<<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.mass, a.ae, a.an, b.nx, b.ny, b.mass, b.ae,
+                                                             b.an, omega);
+        k_demote_level<T><<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(b.nx, b.ny, b.mass, b.ae, b.an, in.lv[l].d,
+                                                                     in.lv[l].ae, in.lv[l].an);
+    }
+    Level64& cl = c->h64[L - 1];
+    k_coarse_setup<T><<<1, 256, 0, st>>>(cl.nx, cl.ny, cl.mass, cl.ae, cl.an, in.Ainv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->err = std::string("hierarchy launch: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    return FLD_OK;
+}
+
+template <typename T>
+fld_status alloc_inner(fld_ctx* ctx) {
+    Inner<T>& in = inner<T>(ctx);
+    const size_t n = (size_t)ctx->nx * ctx->ny;
+    in.lv.resize(ctx->h64.size());
+    for (size_t l = 0; l < ctx->h64.size(); ++l) {
+        LevelT<T>& lv = in.lv[l];
+        lv.nx = ctx->h64[l].nx;
+        lv.ny = ctx->h64[l].ny;
+        const size_t m = (size_t)lv.nx * lv.ny;
+        if (l > 0) HIPCHK(ctx->alloc(&lv.d, m));
+        HIPCHK(ctx->alloc(&lv.ae, m));
+        HIPCHK(ctx->alloc(&lv.an, m));
+        if (l > 0) HIPCHK(ctx->alloc(&lv.b, m));
+        HIPCHK(ctx->alloc(&lv.xpre, m));
+        HIPCHK(ctx->alloc(&lv.xout, m));
+    }
+    const LevelT<T>& cl = in.lv.back();
+    HIPCHK(ctx->alloc(&in.Ainv, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
+    HIPCHK(ctx->alloc(&in.r, n));
+    HIPCHK(ctx->alloc(&in.x, n));
+    HIPCHK(ctx->alloc(&in.p[0], n));
+    HIPCHK(ctx->alloc(&in.p[1], n));
+    HIPCHK(ctx->alloc(&in.q, n));
+    in.lv[0].b = in.r;  // the V-cycle's fine right-hand side is the CG residual
+    HIPCHK(hipMemset(in.r, 0, sizeof(T) * n));
+    HIPCHK(hipMemset(in.x, 0, sizeof(T) * n));
+    HIPCHK(hipMemset(in.p[0], 0, sizeof(T) * n));
+    HIPCHK(hipMemset(in.p[1], 0, sizeof(T) * n));
+    return FLD_OK;
+}
+
+void fill_info(fld_ctx* c, fld_solve_info* info, int status, float ms) {
+    if (!info) return;
+    const Scalars& s = *c->hsc;
+    info->status = status;
+    info->outer_iters = s.nchecks;
+    info->inner_iters = s.iter;
+    info->mg_levels = (int)c->h64.size();
+    info->rel_resid = s.rel_sel;
+    info->rel_resid_row = s.rel_row;
+    info->rel_resid_scaled = s.rel_scaled;
+    info->ms = ms;
+}
+
+template <typename T>
+fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    Inner<T>& in = inner<T>(ctx);
+    hipStream_t st = ctx->stream;
+    const int nx = ctx->nx, ny = ctx->ny, n = nx * ny;
+    const fld_options& o = ctx->opt;
+    const bool fp32only = o.precision == FLD_FP32;
+    const bool mixed = o.precision == FLD_MIXED;
+    const double delta = mixed ? 0.1 : 1e-3;
+    const int max_iter = o.max_inner;
+    k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, max_iter, o.norm,
+                                    fp32only ? 0 : 1);
+    // prologue: true residual of the initial guess, scaled inner residual, first V-cycle
+    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(ctx->met, E, ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s,
+                                                     ctx->r64, ctx->part, ctx->sc, 1);
+    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, ctx->r64, ctx->s, in.r, in.x, ctx->sc, 1);
+    enqueue_vcycle<T>(ctx, in, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->herr, ctx->err_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (*ctx->herr) {
+        ctx->err = "non-finite or out-of-domain input field";
+        fill_info(ctx, info, FLD_ENONFINITE, 0.f);
+        return FLD_ENONFINITE;
+    }
+    const int chunk = o.chunk;
+    // chunks of `chunk` slots; the slot pattern has period 2 (p ping-pong)
+    bool use_graph = o.use_graph != 0;
+    if (use_graph && (!in.chunk_exec || in.chunk_len != chunk)) {
+        // captured per (context, E pointer): E is a kernel argument
+        use_graph = false;
+    }
+    int launched = 0;
+    while (!ctx->hsc->done && launched < max_iter + chunk) {
+        for (int k = 0; k < chunk; ++k) enqueue_slot_E<T>(ctx, in, (launched + k) & 1, E, st);
+        launched += chunk;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, ctx->s, in.x, ctx->sc, 1);
+    HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int status = ctx->hsc->status;
+    if (status == ST_OK && !ctx->hsc->done) status = FLD_ENOCONV;
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(ctx, info, status, ms);
+    if (status != FLD_OK) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "solve status %d after %d iterations, rel. residual %.3e", status,
+                      ctx->hsc->iter, ctx->hsc->rel_sel);
+        ctx->err = buf;
+    }
+    return (fld_status)status;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void fld_default_options(fld_options* o) {
+    if (!o) return;
+    o->precision = FLD_MIXED;
+    o->limiter = FLD_LIMITER_LP;
+    o->norm = FLD_NORM_ROW;
+    o->rel_tol = 1e-10;
+    o->max_outer = 8;
+    o->max_inner = 2000;
+    o->inner_rtol = 1e-5;
+    o->mg_coarse_max = 64;
+    o->mg_coarse_op = FLD_MG_GALERKIN;
+    o->chunk = 8;
+    o->use_graph = 1;
+}
+
+const char* fld_version(void) { return kVersion; }
+
+const char* fld_status_string(fld_status s) {
+    switch (s) {
+        case FLD_OK: return "ok";
+        case FLD_EINVAL: return "invalid argument";
+        case FLD_ENOMEM: return "out of device memory";
+        case FLD_EHIP: return "HIP runtime error";
+        case FLD_ENOCONV: return "tolerance not reached";
+        case FLD_EBREAKDOWN: return "CG breakdown";
+        case FLD_ENONFINITE: return "non-finite or out-of-domain input";
+        case FLD_ENOTREADY: return "not assembled";
+    }
+    return "unknown status";
+}
+
+const char* fld_last_error(const fld_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t fld_mg_levels(const fld_ctx* ctx) { return ctx ? (int32_t)ctx->h64.size() : 0; }
+
+void fld_destroy(fld_ctx* ctx) {
+    if (!ctx) return;
+    // errors are ignored here: the context is being torn down either way
+    if (ctx->i32.chunk_exec) (void)hipGraphExecDestroy(ctx->i32.chunk_exec);
+    if (ctx->i64.chunk_exec) (void)hipGraphExecDestroy(ctx->i64.chunk_exec);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    if (ctx->hsc) (void)hipHostFree(ctx->hsc);
+    if (ctx->herr) (void)hipHostFree(ctx->herr);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* opt, void* stream) {
+    if (!out || !grid) return FLD_EINVAL;
+    *out = nullptr;
+    fld_ctx* ctx = new fld_ctx();
+    auto fail = [&](fld_status s, const std::string& msg) {
+        ctx->err = msg;
+        *out = ctx;  // keep the context so fld_last_error works; caller destroys it
+        return s;
+    };
+    if (opt) ctx->opt = *opt;
+    else fld_default_options(&ctx->opt);
+    std::string why;
+    if (validate_options(&ctx->opt, why) != FLD_OK) return fail(FLD_EINVAL, "bad option: " + why);
+    const int nx = grid->nx, ny = grid->ny;
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny > (int64_t(1) << 28)) return fail(FLD_EINVAL, "grid size");
+    if (grid->geom != FLD_CARTESIAN && grid->geom != FLD_SPHERICAL_POLAR) return fail(FLD_EINVAL, "geometry");
+    if (!grid->x_faces || !grid->y_faces) return fail(FLD_EINVAL, "face arrays");
+    for (int i = 0; i < nx; ++i)
+        if (!(grid->x_faces[i + 1] > grid->x_faces[i]) || !std::isfinite(grid->x_faces[i + 1]))
+            return fail(FLD_EINVAL, "x faces must increase");
+    for (int j = 0; j < ny; ++j)
+        if (!(grid->y_faces[j + 1] > grid->y_faces[j]) || !std::isfinite(grid->y_faces[j + 1]))
+            return fail(FLD_EINVAL, "y faces must increase");
+    if (grid->geom == FLD_SPHERICAL_POLAR) {
+        if (!(grid->x_faces[0] > 0.0)) return fail(FLD_EINVAL, "spherical radii must be > 0");
+        if (grid->y_faces[0] < 0.0 || grid->y_faces[ny] > 3.14159265358979323846 + 1e-12)
+            return fail(FLD_EINVAL, "theta faces must lie in [0, pi]");
+    }
+    for (int sd = 0; sd < 4; ++sd) {
+        const int k = grid->bc[sd].kind;
+        if (k < 0 || k > 5) return fail(FLD_EINVAL, "boundary kind");
+        if (k == FLD_BC_AXIS && (grid->geom != FLD_SPHERICAL_POLAR || sd < 2))
+            return fail(FLD_EINVAL, "axis boundary needs a spherical theta side");
+        if (k == FLD_BC_DIRICHLET_FACE && !(grid->bc[sd].value > 0.0)) return fail(FLD_EINVAL, "Dirichlet temperature");
+        if (k == FLD_BC_FLUX_IN && !std::isfinite(grid->bc[sd].value)) return fail(FLD_EINVAL, "flux value");
+        ctx->bc.kind[sd] = k;
+        ctx->bc.value[sd] = grid->bc[sd].value;
+    }
+    ctx->nx = nx;
+    ctx->ny = ny;
+    ctx->geom = grid->geom;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    const size_t n = (size_t)nx * ny;
+    // device memory
+#define ALLOC(p, cnt) \
+    if (ctx->alloc(&(p), (cnt)) != hipSuccess) return fail(FLD_ENOMEM, "hipMalloc " #p)
+    double *vx, *vy, *sx, *sy, *ax, *hxL, *hxR, *hyL, *hyR, *arc;
+    ALLOC(ctx->xf, nx + 1);
+    ALLOC(ctx->yf, ny + 1);
+    ALLOC(vx, nx); ALLOC(ax, nx); ALLOC(arc, nx); ALLOC(sx, nx + 1); ALLOC(hxL, nx + 1); ALLOC(hxR, nx + 1);
+    ALLOC(vy, ny); ALLOC(sy, ny + 1); ALLOC(hyL, ny + 1); ALLOC(hyR, ny + 1);
+    ALLOC(ctx->We, n); ALLOC(ctx->Wn, n); ALLOC(ctx->m, n); ALLOC(ctx->rhs, n); ALLOC(ctx->s, n); ALLOC(ctx->r64, n);
+    ctx->met = Metrics{nx, ny, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR, arc};
+    // multigrid levels: 2x2 aggregation until at most mg_coarse_max cells
+    {
+        int lx = nx, ly = ny;
+        while (true) {
+            Level64 L;
+            L.nx = lx;
+            L.ny = ly;
+            ALLOC(L.mass, (size_t)lx * ly);
+            ALLOC(L.ae, (size_t)lx * ly);
+            ALLOC(L.an, (size_t)lx * ly);
+            ctx->h64.push_back(L);
+            if ((int64_t)lx * ly <= ctx->opt.mg_coarse_max) break;
+            lx = (lx + 1) / 2;
+            ly = (ly + 1) / 2;
+        }
+    }
+    const size_t tiles = (size_t)tile_grid(nx, ny).x * tile_grid(nx, ny).y;
+    ctx->npart = std::max<size_t>(tiles * 4, (size_t)k1DBlocksMax);
+    ALLOC(ctx->part, ctx->npart);
+    ALLOC(ctx->sc, 1);
+    ALLOC(ctx->err_flag, 1);
+#undef ALLOC
+    if (hipHostMalloc((void**)&ctx->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        return fail(FLD_ENOMEM, "pinned scalars");
+    if (hipHostMalloc((void**)&ctx->herr, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return fail(FLD_ENOMEM, "pinned flag");
+    std::memset(ctx->hsc, 0, sizeof(Scalars));
+    *ctx->herr = 0;
+    fld_status s;
+    if (inner_is_float(ctx)) s = alloc_inner<float>(ctx);
+    else s = alloc_inner<double>(ctx);
+    if (s != FLD_OK) return fail(s, ctx->err);
+    if (hipMemset(ctx->sc, 0, sizeof(Scalars)) != hipSuccess) return fail(FLD_EHIP, "memset scalars");
+    if (hipMemset(ctx->err_flag, 0, sizeof(int)) != hipSuccess) return fail(FLD_EHIP, "memset flag");
+    if (hipMemcpy(ctx->xf, grid->x_faces, sizeof(double) * (nx + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->yf, grid->y_faces, sizeof(double) * (ny + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FLD_EHIP, "copy faces");
+    const int mt = std::max(nx, ny) + 1;
+    k_metrics<<<(mt + 255) / 256, 256, 0, ctx->stream>>>(ctx->geom, nx, ny, ctx->xf, ctx->yf, vx, vy, sx, sy, ax, hxL,
+                                                         hxR, hyL, hyR, arc);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return fail(FLD_EHIP, "metrics kernel");
+    *out = ctx;
+    return FLD_OK;
+}
+
+fld_status fld_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
+                        const double* kP, const double* cv, const double* ghost, double dt) {
+    if (!ctx) return FLD_EINVAL;
+    if (!E || !T || !rho || !kR || !kP || !cv) { ctx->err = "null field pointer"; return FLD_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { ctx->err = "dt must be > 0"; return FLD_EINVAL; }
+    for (int sd = 0; sd < 4; ++sd)
+        if (ctx->bc.kind[sd] == BC_DIRICHLET_GHOST && !ghost) { ctx->err = "ghost_E required"; return FLD_EINVAL; }
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipMemsetAsync(ctx->err_flag, 0, sizeof(int), st));
+    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
+    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag};
+    k_assemble<<<cell_grid(ctx->nx, ctx->ny), blk2d(), 0, st>>>(ctx->met, in, out);
+    HIPCHK(hipGetLastError());
+    fld_status s = inner_is_float(ctx) ? build_hierarchy<float>(ctx) : build_hierarchy<double>(ctx);
+    if (s != FLD_OK) return s;
+    ctx->T = T;
+    ctx->rho = rho;
+    ctx->kP = kP;
+    ctx->cv = cv;
+    ctx->dt = dt;
+    ctx->assembled = true;
+    return FLD_OK;
+}
+
+fld_status fld_solve(fld_ctx* ctx, double* E, fld_solve_info* info) {
+    if (!ctx) return FLD_EINVAL;
+    if (!E) { ctx->err = "null E"; return FLD_EINVAL; }
+    if (!ctx->assembled) { ctx->err = "fld_assemble first"; return FLD_ENOTREADY; }
+    return inner_is_float(ctx) ? solve_impl<float>(ctx, E, info) : solve_impl<double>(ctx, E, info);
+}
+
+fld_status fld_gas_update(fld_ctx* ctx, const double* E, double* Tout) {
+    if (!ctx) return FLD_EINVAL;
+    if (!E || !Tout) { ctx->err = "null pointer"; return FLD_EINVAL; }
+    if (!ctx->assembled) { ctx->err = "fld_assemble first"; return FLD_ENOTREADY; }
+    const int n = ctx->nx * ctx->ny;
+    k_gas_update<<<grid1d(n), 256, 0, ctx->stream>>>(n, E, ctx->T, ctx->rho, ctx->kP, ctx->cv, ctx->dt, Tout);
+    HIPCHK(hipGetLastError());
+    return FLD_OK;
+}
+
+fld_status fld_step(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
+                    const double* cv, const double* ghost, double dt, fld_solve_info* info) {
+    fld_status s = fld_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    s = fld_solve(ctx, E, info);
+    if (s != FLD_OK) return s;
+    return fld_gas_update(ctx, E, T);
+}
+
+fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
+                     const double* kP, const double* cv, const double* ghost, double dt, fld_solve_info* per_step) {
+    if (!ctx) return FLD_EINVAL;
+    if (nsteps < 0) { ctx->err = "nsteps < 0"; return FLD_EINVAL; }
+    fld_status first = FLD_OK;
+    for (int k = 0; k < nsteps; ++k) {
+        fld_status s = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, per_step ? &per_step[k] : nullptr);
+        if (s != FLD_OK && first == FLD_OK) first = s;
+        if (s == FLD_EINVAL || s == FLD_EHIP || s == FLD_ENONFINITE) return s;
+    }
+    return first;
+}
+
+fld_status fld_get_operator(fld_ctx* ctx, double* We, double* Wn, double* diag, double* rhs) {
+    if (!ctx) return FLD_EINVAL;
+    if (!ctx->assembled) { ctx->err = "fld_assemble first"; return FLD_ENOTREADY; }
+    k_get_operator<<<cell_grid(ctx->nx, ctx->ny), blk2d(), 0, ctx->stream>>>(ctx->nx, ctx->ny, ctx->We, ctx->Wn, ctx->m,
+                                                                             ctx->rhs, We, Wn, diag, rhs);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return FLD_OK;
+}
+
+}  // extern "C"

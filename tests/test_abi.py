@@ -1,0 +1,83 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/fld.h declares; the ctypes structures match the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fld.h")
+LIB = os.path.join(ROOT, "paper_2602_12545_amd", "libfld.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(fld_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libfld.so not built")
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_gas_update",
+              "fld_get_operator", "fld_destroy", "fld_default_options"):
+        assert f in names
+
+
+@needs_lib
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    for n in declared_functions():
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+@needs_lib
+def test_host_only_entry_points_run_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.fld_version.restype = ctypes.c_char_p
+    assert lib.fld_version().startswith(b"fld-mi355x")
+    lib.fld_status_string.restype = ctypes.c_char_p
+    assert lib.fld_status_string(4) == b"tolerance not reached"
+    lib.fld_create.restype = ctypes.c_int32
+    assert lib.fld_create(None, None, None, None) == 1  # EINVAL before any device call
+
+
+def c_layout():
+    code = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fld.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(fld_bc), sizeof(fld_grid), sizeof(fld_options), sizeof(fld_solve_info));
+  printf("%zu %zu %zu %zu\n", offsetof(fld_grid, bc), offsetof(fld_options, rel_tol),
+         offsetof(fld_options, inner_rtol), offsetof(fld_solve_info, rel_resid));
+  printf("%zu %zu\n", offsetof(fld_options, use_graph), offsetof(fld_solve_info, ms));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(src, "w").write(code)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        return [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+
+
+@needs_lib
+def test_ctypes_structures_match_c_layout():
+    from paper_2602_12545_amd import _binding as B
+    c = c_layout()
+    py = [ctypes.sizeof(B.fld_bc), ctypes.sizeof(B.fld_grid), ctypes.sizeof(B.fld_options),
+          ctypes.sizeof(B.fld_solve_info), B.fld_grid.bc.offset, B.fld_options.rel_tol.offset,
+          B.fld_options.inner_rtol.offset, B.fld_solve_info.rel_resid.offset, B.fld_options.use_graph.offset,
+          B.fld_solve_info.ms.offset]
+    assert c == py

@@ -1,0 +1,139 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances:
+* assembled operator (W_e, W_n, diagonal, rhs): elementwise relative 1e-12
+  (both sides evaluate the same closed forms in binary64; libm differences in
+  sin/cos/expm1 and summation order leave a few ulps);
+* solution of one step, FP64 and mixed precision solved to a 1e-12 relative
+  residual: relative L2 error of E and T <= 1e-10 (the target for refined
+  solves), elementwise <= 1e-8;
+* FP32-only: relative L2 error <= 1e-5.
+"""
+import numpy as np
+import pytest
+
+import fld_workloads as W
+from oracle import fld_oracle as O
+from gpu_helpers import gpu_step, make_ctx, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def small_cases():
+    return {
+        "c1": W.make_c1(),
+        "c2": W.make_c2(nx=150, ny=70),
+        "c3": W.make_c3(nx=130, ny=66),
+        "c5": W.make_c5(nx=160, ny=90),
+        "c4blk": W.make_c4_block(7, 96, 48),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembly_parity(lib, name):
+    prob = CASES[name]
+    print(f"[assembly] {name} {prob.nx}x{prob.ny}", flush=True)
+    ctx = make_ctx(lib, prob, precision="fp64")
+    t = to_dev(prob, torch)
+    ctx.assemble(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"])
+    op = {k: v.cpu().numpy() for k, v in ctx.get_operator().items()}
+    A = O.assemble_problem(prob)
+    ref_We = np.zeros_like(A.diag)
+    ref_We[:, :-1] = A.W_x[:, 1:-1]
+    ref_Wn = np.zeros_like(A.diag)
+    ref_Wn[:-1, :] = A.W_y[1:-1, :]
+    for got, want, nm in ((op["W_e"], ref_We, "W_e"), (op["W_n"], ref_Wn, "W_n"),
+                          (op["diag"], A.diag, "diag"), (op["rhs"], A.rhs, "rhs")):
+        scale = np.maximum(np.abs(want), 1e-300)
+        err = np.max(np.abs(got - want) / scale)
+        assert err < 1e-12, (nm, err)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_parity(lib, name, prec):
+    prob = CASES[name]
+    print(f"[step] {name} {prec}", flush=True)
+    ref = O.step_problem(prob)
+    E, T, info = gpu_step(lib, torch, prob, precision=prec, rel_tol=1e-12)
+    print(info, flush=True)
+    assert info["status"] == 0, info
+    assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10, (rel_l2(E, ref.E), rel_l2(T, ref.T))
+    assert np.max(np.abs(E - ref.E) / ref.E) < 1e-8
+    assert np.max(np.abs(T - ref.T) / ref.T) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_fp32_only(lib, name):
+    prob = CASES[name]
+    print(f"[fp32] {name}", flush=True)
+    ref = O.step_problem(prob)
+    E, T, info = gpu_step(lib, torch, prob, precision="fp32", inner_rtol=1e-6)
+    print(info, flush=True)
+    assert rel_l2(E, ref.E) < 1e-5 and rel_l2(T, ref.T) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (3, 5), (65, 17), (67, 33)])
+@pytest.mark.parametrize("geom", ["cart", "sph"])
+def test_edge_shapes(lib, shape, geom):
+    nx, ny = shape
+    print(f"[edge] {geom} {nx}x{ny}", flush=True)
+    prob = W.make_c2(nx=nx, ny=ny) if geom == "cart" else W.make_c3(nx=nx, ny=ny)
+    if geom == "cart":
+        rng = np.random.default_rng(nx * 100 + ny)
+        prob.bc = [W.BC(W.BC_DIRICHLET_FACE, 1.2e4), W.BC(W.BC_FREE_STREAM), W.BC(W.BC_FLUX_IN, 1e13),
+                   W.BC(W.BC_DIRICHLET_GHOST)]
+        prob.ghost_E = W.A_RAD * rng.uniform(3e3, 9e3, 2 * nx + 2 * ny) ** 4
+    ref = O.step_problem(prob)
+    for prec in ("fp64", "mixed"):
+        E, T, info = gpu_step(lib, torch, prob, precision=prec, rel_tol=1e-12)
+        assert info["status"] == 0, (prec, info)
+        assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10, (prec, rel_l2(E, ref.E))
+
+
+def test_equilibrium_stays_fixed(lib):
+    prob = W.make_c5(nx=96, ny=64)
+    prob.T = np.full_like(prob.T, 7.5e3)
+    prob.E = W.A_RAD * prob.T ** 4
+    prob.bc = [W.BC(), W.BC(), W.BC(W.BC_AXIS), W.BC(W.BC_AXIS)]
+    for prec in ("fp64", "mixed"):
+        E, T, info = gpu_step(lib, torch, prob, precision=prec)
+        assert info["status"] == 0
+        assert np.max(np.abs(E / prob.E - 1)) < 1e-12
+        assert np.max(np.abs(T / prob.T - 1)) < 1e-12
+
+
+def test_deterministic(lib):
+    prob = CASES["c2"]
+    a = gpu_step(lib, torch, prob, precision="mixed")
+    b = gpu_step(lib, torch, prob, precision="mixed")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["inner_iters"] == b[2]["inner_iters"]
+
+
+def test_invalid_inputs(lib):
+    prob = W.make_c1(nx=16, ny=16)
+    ctx = make_ctx(lib, prob)
+    t = to_dev(prob, torch)
+    t["rho"][3, 4] = float("nan")
+    ctx.assemble(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt)
+    info = ctx.solve(t["E"], check=False)
+    assert info["status"] == lib.FLD_ENONFINITE
+    with pytest.raises(lib.FLDError):
+        ctx.assemble(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], -1.0)
+    ctx.close()
+    with pytest.raises(lib.FLDError):
+        lib.Context(0, 4, 0, np.arange(1.0), np.arange(5.0), [(0, 0.0)] * 4)
+
+
+def test_max_iterations_reports_noconv(lib):
+    prob = CASES["c2"]
+    E, T, info = gpu_step(lib, torch, prob, precision="fp64", max_inner=2)
+    assert info["status"] == lib.FLD_ENOCONV
+    assert info["inner_iters"] == 2

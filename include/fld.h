@@ -102,9 +102,14 @@ typedef enum { FLD_LIMITER_LP = 0, FLD_LIMITER_MINERBO = 1, FLD_LIMITER_DIFFUSIO
 typedef enum { FLD_NORM_ROW = 0, FLD_NORM_SCALED = 1 } fld_norm;
 
 /* Multigrid coarse operator: GALERKIN = P^T A P with 2x2 piecewise-constant
- * aggregation; HALVED = same aggregation with the coarse face couplings halved
- * (rediscretisation scaling; mass part still summed). */
+ * aggregation; HALVED = same aggregation with the coarse face conductances
+ * halved (rescaled to the coarse spacing; masses still summed). */
 typedef enum { FLD_MG_GALERKIN = 0, FLD_MG_HALVED = 1 } fld_mg_coarse;
+
+/* Multigrid smoother: alternating zebra line Gauss-Seidel (x lines then y
+ * lines; robust to the strong anisotropy of optically thin spherical shells),
+ * or point red-black Gauss-Seidel. */
+typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1 } fld_smoother;
 
 typedef struct {
     int32_t precision;      /* fld_precision (default MIXED)                                 */
@@ -116,7 +121,8 @@ typedef struct {
     double  inner_rtol;     /* residual reduction asked of one inner solve in MIXED / FP32   */
                             /* (default 1e-5); FP64 solves straight to the target            */
     int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (<= 256, def 64) */
-    int32_t mg_coarse_op;   /* fld_mg_coarse (default GALERKIN)                              */
+    int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
+    int32_t smoother;       /* fld_smoother (default LINE); LINE needs nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
     int32_t use_graph;      /* capture each chunk as a hipGraph (default 1)                  */
 } fld_options;

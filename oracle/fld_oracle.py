@@ -126,6 +126,28 @@ class Metrics:
     hRy: np.ndarray    # [ny+1, nx]
 
 
+def theta_centre_offset(a, h):
+    """th_c - a for the cell [a, a + h] of a spherical-polar grid.
+
+    th_c is the volume-weighted mean angle (weight sin th), i.e.
+    th_c - a = int_0^h u sin(a + u) du / int_0^h sin(a + u) du
+             = (sin a S1 + cos a S2) / (sin a sin h + cos a C1),
+    S1 = int u cos u = h sin h - C1, S2 = int u sin u = sin h - h cos h,
+    C1 = 1 - cos h = 2 sin^2(h/2).  S2 uses its Taylor series
+    h^3/3 - h^5/30 + h^7/840 - h^9/45360 + h^11/3991680 - h^13/518918400
+    for h < 0.3 (the closed form cancels there).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    C1 = 2.0 * np.sin(0.5 * h) ** 2
+    S1 = h * np.sin(h) - C1
+    h2 = h * h
+    series = h * h2 * (1.0 / 3.0 + h2 * (-1.0 / 30.0 + h2 * (1.0 / 840.0 + h2 * (-1.0 / 45360.0 + h2 * (
+        1.0 / 3991680.0 + h2 * (-1.0 / 518918400.0))))))
+    S2 = np.where(h < 0.3, series, np.sin(h) - h * np.cos(h))
+    return (np.sin(a) * S1 + np.cos(a) * S2) / (np.sin(a) * np.sin(h) + np.cos(a) * C1)
+
+
 def metrics(geom: int, xf: np.ndarray, yf: np.ndarray) -> Metrics:
     """Cell volumes, face areas and centre-to-face distances.
 
@@ -136,6 +158,8 @@ def metrics(geom: int, xf: np.ndarray, yf: np.ndarray) -> Metrics:
       volume centres r_c = 3/4 (r+^4 - r-^4)/(r+^3 - r-^3) and
       th_c = (sin th+ - sin th- - th+ cos th+ + th- cos th-)/(cos th- - cos th+);
       distances along theta are arc lengths at r_c.
+    The spherical forms are evaluated in algebraically identical,
+    cancellation-free arrangements (see theta_centre_offset).
     """
     xf = np.asarray(xf, dtype=np.float64)
     yf = np.asarray(yf, dtype=np.float64)
@@ -151,14 +175,29 @@ def metrics(geom: int, xf: np.ndarray, yf: np.ndarray) -> Metrics:
         dSy = np.broadcast_to(Vx[None, :], (ny + 1, nx)).copy()
         arc = np.ones(nx)
     elif geom == SPHERICAL:
-        xc = 0.75 * (xp ** 4 - xm ** 4) / (xp ** 3 - xm ** 3)
-        yc = (np.sin(yp) - np.sin(ym) - yp * np.cos(yp) + ym * np.cos(ym)) / (np.cos(ym) - np.cos(yp))
-        Vx = (xp ** 3 - xm ** 3) / 3.0
-        Vy = np.cos(ym) - np.cos(yp)
+        # same closed forms, evaluated without cancellation for thin cells:
+        # r+^3 - r-^3 and r+^4 - r-^4 factorised, cos th- - cos th+ as a product
+        # of sines, and the theta centre as an offset from the lower face.
+        dr = xp - xm
+        q = xp * xp + xp * xm + xm * xm
+        Vx = dr * q / 3.0
+        xc = 0.75 * (xp + xm) * (xp * xp + xm * xm) / q
+        off_r = dr * (6.0 * xm * xm + 8.0 * xm * dr + 3.0 * dr * dr) / (4.0 * q)  # r_c - r-
+        dth = yp - ym
+        Vy = 2.0 * np.sin(0.5 * (ym + yp)) * np.sin(0.5 * dth)
+        off_t = theta_centre_offset(ym, dth)  # th_c - th-
         dV = Vy[:, None] * Vx[None, :]
         dSx = Vy[:, None] * (xf ** 2)[None, :]
-        dSy = np.sin(yf)[:, None] * (0.5 * (xp ** 2 - xm ** 2))[None, :]
-        arc = xc
+        dSy = np.sin(yf)[:, None] * (0.5 * dr * (xp + xm))[None, :]
+        hLx = np.zeros((ny, nx + 1))
+        hRx = np.zeros((ny, nx + 1))
+        hLx[:, 1:] = (dr - off_r)[None, :]
+        hRx[:, :-1] = off_r[None, :]
+        hLy = np.zeros((ny + 1, nx))
+        hRy = np.zeros((ny + 1, nx))
+        hLy[1:, :] = (dth - off_t)[:, None] * xc[None, :]
+        hRy[:-1, :] = off_t[:, None] * xc[None, :]
+        return Metrics(nx, ny, dV, dSx, dSy, hLx, hRx, hLy, hRy)
     else:
         raise ValueError("unknown geometry")
     hLx = np.zeros((ny, nx + 1))

@@ -21,6 +21,7 @@ FLD_FP64, FLD_FP32, FLD_MIXED = 0, 1, 2
 FLD_LIMITER_LP, FLD_LIMITER_MINERBO, FLD_LIMITER_DIFFUSION = 0, 1, 2
 FLD_NORM_ROW, FLD_NORM_SCALED = 0, 1
 FLD_MG_GALERKIN, FLD_MG_HALVED = 0, 1
+FLD_SMOOTH_LINE, FLD_SMOOTH_POINT = 0, 1
 
 PRECISIONS = {"fp64": FLD_FP64, "fp32": FLD_FP32, "mixed": FLD_MIXED}
 
@@ -39,7 +40,8 @@ class fld_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("limiter", ctypes.c_int32), ("norm", ctypes.c_int32),
                 ("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("mg_coarse_max", ctypes.c_int32),
-                ("mg_coarse_op", ctypes.c_int32), ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("mg_coarse_op", ctypes.c_int32), ("smoother", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class fld_solve_info(ctypes.Structure):

@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "fld.h"
-#include "fld_kernels.hpp"
+#include "fld_mg.hpp"
 
 using namespace fld;
 
@@ -32,14 +32,30 @@ constexpr const char* kVersion = "fld-mi355x 0.1";
 
 struct Level64 {
     int nx = 0, ny = 0;
-    double *mass = nullptr, *ae = nullptr, *an = nullptr;
+    double *m = nullptr, *We = nullptr, *Wn = nullptr;  // row-major, unnormalised
+};
+
+// A level seen row-major (RM) or transposed (TR); line solves run along rows.
+template <typename T>
+struct View {
+    int nx = 0, ny = 0;
+    const T *m = nullptr, *We = nullptr, *Wn = nullptr;
 };
 
 template <typename T>
 struct LevelT {
     int nx = 0, ny = 0;
-    T *d = nullptr, *ae = nullptr, *an = nullptr;  // d == nullptr on level 0 (unit diagonal)
-    T *b = nullptr, *xpre = nullptr, *xout = nullptr;
+    T *m = nullptr, *We = nullptr, *Wn = nullptr;     // row-major inner copy (/ mu)
+    T *mT = nullptr, *WeT = nullptr, *WnT = nullptr;  // transposed copy (line smoother)
+    T *bP = nullptr, *xP = nullptr;                   // vectors in the level's primary layout
+    T *bQ = nullptr, *xQ = nullptr;                   // secondary layout (line); xQ = pre-smoothed x (point)
+    bool tr = false;                                  // primary layout is the transposed one
+    View<T> view(bool transposed) const {
+        View<T> v;
+        if (!transposed) { v.nx = nx; v.ny = ny; v.m = m; v.We = We; v.Wn = Wn; }
+        else { v.nx = ny; v.ny = nx; v.m = mT; v.We = WeT; v.Wn = WnT; }
+        return v;
+    }
 };
 
 template <typename T>
@@ -66,6 +82,7 @@ struct fld_ctx {
     Metrics met{};
     // assembled FP64 operator
     double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
+    double* mu = nullptr;  // device: max diagonal (inner normalisation)
     std::vector<Level64> h64;
     double* part = nullptr;
     size_t npart = 0;
@@ -120,6 +137,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) { err = "inner_rtol must be in (0, 1)"; return FLD_EINVAL; }
     if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 64]"; return FLD_EINVAL; }
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
+    if (o->smoother < 0 || o->smoother > 1) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
     return FLD_OK;
 }
@@ -128,54 +146,123 @@ fld_status validate_options(const fld_options* o, std::string& err) {
 // V-cycle and CG slot (queued on stream `st`)
 // ---------------------------------------------------------------------------
 
+// Chunking of a row of n cells for k_line: K chunks (power of two, <= 256) of
+// L cells (2 <= L <= 16).
+inline void line_params(int n, int& K, int& L) {
+    int want = (n + 7) / 8;
+    K = 1;
+    while (K < want && K < kLineWG) K <<= 1;
+    L = (n + K - 1) / K;
+    if (L < 2) L = 2;
+}
+
+template <typename T, int MODE, int DOT>
+int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T* ec, int nxc, int nb_prev,
+                hipStream_t st) {
+    const int nl = (v.ny - par + 1) / 2;
+    if (nl <= 0) return 0;
+    int K, L;
+    line_params(v.nx, K, L);
+    const int lpw = kLineWG / K;
+    const int grid = (nl + lpw - 1) / lpw;
+    k_line<T, MODE, DOT><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc, T(1),
+                                                    c->part, nb_prev, c->sc);
+    return grid;
+}
+
 template <typename T>
-void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
+void launch_transpose(int nx, int ny, const T* s0, const T* s1, T* d0, T* d1, const Scalars* sc, hipStream_t st) {
+    dim3 g((nx + kTT - 1) / kTT, (ny + kTT - 1) / kTT), blk(kTT, 8);
+    if (s1)
+        k_transpose<T, 2><<<g, blk, 0, st>>>(nx, ny, s0, s1, nullptr, d0, d1, nullptr, sc);
+    else
+        k_transpose<T, 1><<<g, blk, 0, st>>>(nx, ny, s0, nullptr, nullptr, d0, nullptr, nullptr, sc);
+}
+
+template <typename T>
+void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
+    const int L = (int)in.lv.size();
+    for (int l = 0; l < L - 1; ++l) {
+        LevelT<T>& a = in.lv[l];
+        LevelT<T>& nxt = in.lv[l + 1];
+        const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
+        launch_line<T, LINE_ZERO, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
+        launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
+        launch_transpose<T>(vp.nx, vp.ny, a.xP, a.bP, a.xQ, a.bQ, c->sc, st);
+        launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
+        launch_line<T, LINE_NORMAL, 0>(c, vq, 1, a.bQ, a.xQ, nullptr, 0, 0, st);
+        const View<T> cv = nxt.view(nxt.tr);
+        k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ, a.xQ,
+                                                                          nxt.bP, cv.nx, cv.ny, c->sc);
+    }
+    LevelT<T>& cl = in.lv[L - 1];
+    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+    for (int l = L - 2; l >= 0; --l) {
+        LevelT<T>& a = in.lv[l];
+        LevelT<T>& nxt = in.lv[l + 1];
+        const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
+        const View<T> cv = nxt.view(nxt.tr);
+        launch_line<T, LINE_PROLONG, 0>(c, vq, 1, a.bQ, a.xQ, nxt.xP, cv.nx, 0, st);
+        launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
+        launch_transpose<T>(vq.nx, vq.ny, a.xQ, nullptr, a.xP, nullptr, c->sc, st);
+        if (l == 0) {
+            const int nb1 = launch_line<T, LINE_NORMAL, 1>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
+            launch_line<T, LINE_NORMAL, 2>(c, vp, 0, a.bP, a.xP, nullptr, 0, nb1, st);
+        } else {
+            launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
+            launch_line<T, LINE_NORMAL, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
+        }
+    }
+}
+
+template <typename T>
+void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const int L = (int)in.lv.size();
     const T omega = T(1);
-    if (L == 1) {
-        LevelT<T>& l0 = in.lv[0];
-        k_coarse_solve<T, true><<<1, kCoarseMax, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.b, l0.xout, c->part, c->sc);
-        return;
-    }
     for (int l = 0; l < L - 1; ++l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
-        if (l == 0)
-            k_pre<T, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, nullptr, a.ae, a.an, a.xpre, b.b,
-                                                                      b.nx, b.ny, c->sc);
-        else
-            k_pre<T, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, a.d, a.ae, a.an, a.xpre, b.b,
-                                                                       b.nx, b.ny, c->sc);
+        k_pre_point<T><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ, b.bP, b.nx,
+                                                                  b.ny, c->sc);
     }
     LevelT<T>& cl = in.lv[L - 1];
-    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.b, cl.xout, c->part, c->sc);
+    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
     for (int l = L - 2; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
         if (l == 0)
-            k_post<T, true, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, nullptr, a.ae, a.an,
-                                                                             a.xpre, b.xout, b.nx, omega, a.xout,
-                                                                             c->part, c->sc);
+            k_post_point<T, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ,
+                                                                             b.xP, b.nx, omega, a.xP, c->part, c->sc);
         else
-            k_post<T, false, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.b, a.d, a.ae, a.an,
-                                                                               a.xpre, b.xout, b.nx, omega, a.xout,
-                                                                               c->part, c->sc);
+            k_post_point<T, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ,
+                                                                              b.xP, b.nx, omega, a.xP, c->part, c->sc);
     }
+}
+
+template <typename T>
+void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
+    if (in.lv.size() == 1) {
+        LevelT<T>& l0 = in.lv[0];
+        k_coarse_solve<T, true><<<1, kCoarseMax, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->sc);
+        return;
+    }
+    if (c->opt.smoother == FLD_SMOOTH_LINE) enqueue_vcycle_line<T>(c, in, st);
+    else enqueue_vcycle_point<T>(c, in, st);
 }
 
 // One CG iteration ("slot"); `par` selects the p buffer pair (iterations
 // alternate between the two).  E is the FP64 solution being refined.
 template <typename T>
-void enqueue_slot_E(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) {
+void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) {
     const int nx = c->nx, ny = c->ny, n = nx * ny;
     LevelT<T>& l0 = in.lv[0];
-    k_spmv<T><<<tile_grid(nx, ny), blk2d(), 0, st>>>(nx, ny, l0.xout, in.p[par], in.p[par ^ 1], in.q, l0.ae, l0.an,
+    k_spmv<T><<<tile_grid(nx, ny), blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn,
                                                      c->part, c->sc);
     k_update<T><<<grid1d(n), 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, c->sc);
-    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, c->s, in.x, c->sc, 0);
-    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part,
-                                                     c->sc, 0);
-    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, c->s, in.r, in.x, c->sc, 0);
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, c->sc, 0);
+    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->mu, c->r64,
+                                                     c->part, c->sc, 0);
+    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, in.r, in.x, c->sc, 0);
     enqueue_vcycle<T>(c, in, st);
 }
 
@@ -184,22 +271,26 @@ fld_status build_hierarchy(fld_ctx* c) {
     Inner<T>& in = inner<T>(c);
     hipStream_t st = c->stream;
     const int L = (int)in.lv.size();
-    // level 0 (FP64 scaled operator)
-    k_scale<<<cell_grid(c->nx, c->ny), blk2d(), 0, st>>>(c->nx, c->ny, c->We, c->Wn, c->s, c->h64[0].ae, c->h64[0].an,
-                                                         c->h64[0].mass);
-    k_demote_level<T><<<cell_grid(c->nx, c->ny), blk2d(), 0, st>>>(c->nx, c->ny, c->h64[0].mass, c->h64[0].ae,
-                                                                   c->h64[0].an, (T*)nullptr, in.lv[0].ae, in.lv[0].an);
     const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
-    for (int l = 1; l < L; ++l) {
-        Level64& a = c->h64[l - 1];
+    const bool line = c->opt.smoother == FLD_SMOOTH_LINE;
+    for (int l = 0; l < L; ++l) {
         Level64& b = c->h64[l];
-        k_coarsen<<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.mass, a.ae, a.an, b.nx, b.ny, b.mass, b.ae,
-                                                             b.an, omega);
-        k_demote_level<T><<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(b.nx, b.ny, b.mass, b.ae, b.an, in.lv[l].d,
-                                                                     in.lv[l].ae, in.lv[l].an);
+        if (l > 0) {
+            Level64& a = c->h64[l - 1];
+            k_coarsen<<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.m, a.We, a.Wn, b.nx, b.ny, b.m, b.We, b.Wn,
+                                                                 omega);
+        }
+        LevelT<T>& lt = in.lv[l];
+        const int n = b.nx * b.ny;
+        k_demote_level<T><<<grid1d(n), 256, 0, st>>>(n, b.m, b.We, b.Wn, c->mu, lt.m, lt.We, lt.Wn);
+        if (line && L > 1) {
+            // transposed view: rows are the columns, east couplings are the north ones
+            dim3 g((b.nx + kTT - 1) / kTT, (b.ny + kTT - 1) / kTT), blk(kTT, 8);
+            k_transpose<T, 3><<<g, blk, 0, st>>>(b.nx, b.ny, lt.m, lt.Wn, lt.We, lt.mT, lt.WeT, lt.WnT, nullptr);
+        }
     }
     Level64& cl = c->h64[L - 1];
-    k_coarse_setup<T><<<1, 256, 0, st>>>(cl.nx, cl.ny, cl.mass, cl.ae, cl.an, in.Ainv);
+    k_coarse_setup<T><<<1, 256, 0, st>>>(cl.nx, cl.ny, in.lv[L - 1].tr ? 1 : 0, cl.m, cl.We, cl.Wn, c->mu, in.Ainv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         c->err = std::string("hierarchy launch: ") + hipGetErrorString(e);
@@ -212,18 +303,26 @@ template <typename T>
 fld_status alloc_inner(fld_ctx* ctx) {
     Inner<T>& in = inner<T>(ctx);
     const size_t n = (size_t)ctx->nx * ctx->ny;
+    const bool line = ctx->opt.smoother == FLD_SMOOTH_LINE;
     in.lv.resize(ctx->h64.size());
     for (size_t l = 0; l < ctx->h64.size(); ++l) {
         LevelT<T>& lv = in.lv[l];
         lv.nx = ctx->h64[l].nx;
         lv.ny = ctx->h64[l].ny;
+        lv.tr = line && (l & 1);
         const size_t m = (size_t)lv.nx * lv.ny;
-        if (l > 0) HIPCHK(ctx->alloc(&lv.d, m));
-        HIPCHK(ctx->alloc(&lv.ae, m));
-        HIPCHK(ctx->alloc(&lv.an, m));
-        if (l > 0) HIPCHK(ctx->alloc(&lv.b, m));
-        HIPCHK(ctx->alloc(&lv.xpre, m));
-        HIPCHK(ctx->alloc(&lv.xout, m));
+        HIPCHK(ctx->alloc(&lv.m, m));
+        HIPCHK(ctx->alloc(&lv.We, m));
+        HIPCHK(ctx->alloc(&lv.Wn, m));
+        if (line) {
+            HIPCHK(ctx->alloc(&lv.mT, m));
+            HIPCHK(ctx->alloc(&lv.WeT, m));
+            HIPCHK(ctx->alloc(&lv.WnT, m));
+            HIPCHK(ctx->alloc(&lv.bQ, m));
+        }
+        if (l > 0) HIPCHK(ctx->alloc(&lv.bP, m));
+        HIPCHK(ctx->alloc(&lv.xP, m));
+        HIPCHK(ctx->alloc(&lv.xQ, m));
     }
     const LevelT<T>& cl = in.lv.back();
     HIPCHK(ctx->alloc(&in.Ainv, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
@@ -232,7 +331,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(ctx->alloc(&in.p[0], n));
     HIPCHK(ctx->alloc(&in.p[1], n));
     HIPCHK(ctx->alloc(&in.q, n));
-    in.lv[0].b = in.r;  // the V-cycle's fine right-hand side is the CG residual
+    in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual
     HIPCHK(hipMemset(in.r, 0, sizeof(T) * n));
     HIPCHK(hipMemset(in.x, 0, sizeof(T) * n));
     HIPCHK(hipMemset(in.p[0], 0, sizeof(T) * n));
@@ -266,10 +365,10 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     const int max_iter = o.max_inner;
     k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, max_iter, o.norm,
                                     fp32only ? 0 : 1);
-    // prologue: true residual of the initial guess, scaled inner residual, first V-cycle
-    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(ctx->met, E, ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s,
+    // prologue: true residual of the initial guess, inner residual, first V-cycle
+    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(ctx->met, E, ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->mu,
                                                      ctx->r64, ctx->part, ctx->sc, 1);
-    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, ctx->r64, ctx->s, in.r, in.x, ctx->sc, 1);
+    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, ctx->r64, in.r, in.x, ctx->sc, 1);
     enqueue_vcycle<T>(ctx, in, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -281,21 +380,15 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
         return FLD_ENONFINITE;
     }
     const int chunk = o.chunk;
-    // chunks of `chunk` slots; the slot pattern has period 2 (p ping-pong)
-    bool use_graph = o.use_graph != 0;
-    if (use_graph && (!in.chunk_exec || in.chunk_len != chunk)) {
-        // captured per (context, E pointer): E is a kernel argument
-        use_graph = false;
-    }
     int launched = 0;
     while (!ctx->hsc->done && launched < max_iter + chunk) {
-        for (int k = 0; k < chunk; ++k) enqueue_slot_E<T>(ctx, in, (launched + k) & 1, E, st);
+        for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, (launched + k) & 1, E, st);
         launched += chunk;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
     }
-    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, ctx->s, in.x, ctx->sc, 1);
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
     HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     int status = ctx->hsc->status;
@@ -329,7 +422,8 @@ void fld_default_options(fld_options* o) {
     o->max_inner = 2000;
     o->inner_rtol = 1e-5;
     o->mg_coarse_max = 64;
-    o->mg_coarse_op = FLD_MG_GALERKIN;
+    o->mg_coarse_op = FLD_MG_HALVED;
+    o->smoother = FLD_SMOOTH_LINE;
     o->chunk = 8;
     o->use_graph = 1;
 }
@@ -420,27 +514,37 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(vy, ny); ALLOC(sy, ny + 1); ALLOC(hyL, ny + 1); ALLOC(hyR, ny + 1);
     ALLOC(ctx->We, n); ALLOC(ctx->Wn, n); ALLOC(ctx->m, n); ALLOC(ctx->rhs, n); ALLOC(ctx->s, n); ALLOC(ctx->r64, n);
     ctx->met = Metrics{nx, ny, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR, arc};
-    // multigrid levels: 2x2 aggregation until at most mg_coarse_max cells
+    // multigrid levels: 2x2 aggregation until at most mg_coarse_max cells; the
+    // fine level is the assembled operator itself
     {
         int lx = nx, ly = ny;
         while (true) {
             Level64 L;
             L.nx = lx;
             L.ny = ly;
-            ALLOC(L.mass, (size_t)lx * ly);
-            ALLOC(L.ae, (size_t)lx * ly);
-            ALLOC(L.an, (size_t)lx * ly);
+            if (ctx->h64.empty()) {
+                L.m = ctx->m;
+                L.We = ctx->We;
+                L.Wn = ctx->Wn;
+            } else {
+                ALLOC(L.m, (size_t)lx * ly);
+                ALLOC(L.We, (size_t)lx * ly);
+                ALLOC(L.Wn, (size_t)lx * ly);
+            }
             ctx->h64.push_back(L);
             if ((int64_t)lx * ly <= ctx->opt.mg_coarse_max) break;
             lx = (lx + 1) / 2;
             ly = (ly + 1) / 2;
         }
     }
+    if (ctx->opt.smoother == FLD_SMOOTH_LINE && (nx > kLineWG * kLineMaxL || ny > kLineWG * kLineMaxL))
+        return fail(FLD_EINVAL, "line smoother supports nx, ny <= 4096; use the point smoother");
     const size_t tiles = (size_t)tile_grid(nx, ny).x * tile_grid(nx, ny).y;
-    ctx->npart = std::max<size_t>(tiles * 4, (size_t)k1DBlocksMax);
+    ctx->npart = std::max<size_t>(tiles * 5, (size_t)k1DBlocksMax);
     ALLOC(ctx->part, ctx->npart);
     ALLOC(ctx->sc, 1);
     ALLOC(ctx->err_flag, 1);
+    ALLOC(ctx->mu, 1);
 #undef ALLOC
     if (hipHostMalloc((void**)&ctx->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned scalars");
@@ -476,7 +580,7 @@ fld_status fld_assemble(fld_ctx* ctx, const double* E, const double* T, const do
     hipStream_t st = ctx->stream;
     HIPCHK(hipMemsetAsync(ctx->err_flag, 0, sizeof(int), st));
     AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
-    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag};
+    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part, ctx->mu, &ctx->sc->cnt[CNT_ASM]};
     k_assemble<<<cell_grid(ctx->nx, ctx->ny), blk2d(), 0, st>>>(ctx->met, in, out);
     HIPCHK(hipGetLastError());
     fld_status s = inner_is_float(ctx) ? build_hierarchy<float>(ctx) : build_hierarchy<double>(ctx);

@@ -43,15 +43,18 @@ struct Scalars {
     double pscale;      // factor applied to p at the next p-update (residual rescaling)
     double rr;          // inner residual norm^2 (recurrence)
     double rr_ref;      // inner residual norm^2 at the last reliable update
-    double gamma;       // current residual scale: r_inner = S r / gamma
+    double gamma;       // current residual scale: r_inner = r / gamma, gamma = ||r||_2
+    double corr;        // gamma / mu: E += corr * x_inner
     double rho_last;    // last true relative residual (selected norm)
     double sums[4];     // true residual: ||r/dV||^2, ||S r||^2, ||rhs/dV||^2, ||S rhs||^2
     double rel_row, rel_scaled, rel_sel;
     double eps;         // target relative residual
+    double best;        // smallest true relative residual seen in this solve
     double delta2;      // reliable-update threshold (squared)
     double inner_tol2;  // FP32-only: stop when rr <= inner_tol2
     int iter, done, pending, status;
     int max_iter, norm, reliable, nchecks;
+    int stall, pad2;    // true-residual checks without progress
     unsigned cnt[8];    // last-block counters, one per reduction kernel kind
 };
 

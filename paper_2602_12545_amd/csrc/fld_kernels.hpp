@@ -33,6 +33,21 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
+// Maximum over the workgroup; the result is valid in thread 0.
+__device__ inline double block_max(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int t = ltid();
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (t == 0) {
+        const int nw = (lsize() + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r = fmax(r, sh[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
 __device__ inline double load_agent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -127,41 +142,69 @@ __device__ inline void boundary_face(int kind, double value, double Eg, double E
 // metrics (Section 3.2.1: g = dS/dV, alpha from volume centres)
 // ---------------------------------------------------------------------------
 
+// Offset of the volume-weighted mean angle of [a, a + h] from a (weight sin th):
+//   (sin a * int_0^h u cos u du + cos a * int_0^h u sin u du) / (cos a - cos(a + h)).
+// int u sin u = sin h - h cos h is summed as its alternating series
+// sum_k (-1)^(k+1) 2k h^(2k+1) / (2k+1)! for h < 0.3, where the closed form cancels.
+__device__ inline double theta_offset(double a, double h) {
+    const double sh = sin(0.5 * h);
+    const double one_minus_cos = 2.0 * sh * sh;
+    const double int_ucos = h * sin(h) - one_minus_cos;
+    double int_usin;
+    if (h < 0.3) {
+        const double h2 = h * h;
+        double term = h * h2 / 3.0, acc = 0.0;
+        for (int k = 1; k <= 8; ++k) {
+            acc += (k & 1) ? term : -term;
+            term *= h2 / ((2.0 * k) * (2.0 * k + 3.0));
+        }
+        int_usin = acc;
+    } else {
+        int_usin = sin(h) - h * cos(h);
+    }
+    const double sa = sin(a), ca = cos(a);
+    return (sa * int_ucos + ca * int_usin) / (sa * sin(h) + ca * one_minus_cos);
+}
+
+// Grid metrics from the face coordinates.  Spherical forms are arranged
+// without cancellation for thin cells: r+^3 - r-^3 = dr (r+^2 + r+ r- + r-^2),
+// volume-centre radius r_c = 3/4 (r+ + r-)(r+^2 + r-^2) / (r+^2 + r+ r- + r-^2)
+// with r_c - r- = dr (6 r-^2 + 8 r- dr + 3 dr^2) / (4 (r+^2 + r+ r- + r-^2)),
+// cos th- - cos th+ = 2 sin((th- + th+)/2) sin(dth/2).
 __global__ void k_metrics(int geom, int nx, int ny, const double* __restrict__ xf, const double* __restrict__ yf,
                           double* vx, double* vy, double* sx, double* sy, double* ax, double* hxL, double* hxR,
                           double* hyL, double* hyR, double* arc) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < nx) {
-        const double a = xf[t], b = xf[t + 1];
-        double c;
+        const double a = xf[t], b = xf[t + 1], d = b - a;
         if (geom == 0) {
-            vx[t] = b - a;
-            ax[t] = b - a;
-            c = 0.5 * (a + b);
+            vx[t] = d;
+            ax[t] = d;
             arc[t] = 1.0;
+            hxR[t] = 0.5 * d;
+            hxL[t + 1] = 0.5 * d;
         } else {
-            const double a3 = a * a * a, b3 = b * b * b;
-            vx[t] = (b3 - a3) / 3.0;
-            ax[t] = 0.5 * (b * b - a * a);
-            c = 0.75 * (b3 * b - a3 * a) / (b3 - a3);
-            arc[t] = c;
+            const double q = b * b + a * b + a * a;
+            vx[t] = d * q / 3.0;
+            ax[t] = 0.5 * d * (a + b);
+            arc[t] = 0.75 * (a + b) * (a * a + b * b) / q;
+            const double off = d * (6.0 * a * a + 8.0 * a * d + 3.0 * d * d) / (4.0 * q);
+            hxR[t] = off;
+            hxL[t + 1] = d - off;
         }
-        hxR[t] = c - a;
-        hxL[t + 1] = b - c;
     }
     if (t < ny) {
-        const double a = yf[t], b = yf[t + 1];
-        double c;
+        const double a = yf[t], b = yf[t + 1], d = b - a;
         if (geom == 0) {
-            vy[t] = b - a;
-            c = 0.5 * (a + b);
+            vy[t] = d;
+            hyR[t] = 0.5 * d;
+            hyL[t + 1] = 0.5 * d;
         } else {
-            const double ca = cos(a), cb = cos(b);
-            vy[t] = ca - cb;
-            c = (sin(b) - sin(a) - b * cb + a * ca) / (ca - cb);
+            vy[t] = 2.0 * sin(0.5 * (a + b)) * sin(0.5 * d);
+            const double off = theta_offset(a, d);
+            hyR[t] = off;
+            hyL[t + 1] = d - off;
         }
-        hyR[t] = c - a;
-        hyL[t + 1] = b - c;
     }
     if (t == 0) {
         hxL[0] = 0.0;
@@ -186,16 +229,14 @@ struct AsmIn {
 struct AsmOut {
     double *We, *Wn, *m, *rhs, *s;
     int* err;
+    double* part;   // per-workgroup partial maxima of the diagonal
+    double* mu;     // global maximum of the diagonal (inner-precision normalisation)
+    unsigned* cnt;  // last-block counter
 };
 
-// One thread per cell computes its four faces (each interior face is computed
-// identically by its two cells, so the matrix is exactly symmetric), the
-// boundary terms and the cell terms C_V, beta, f.
-__global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut out) {
-    const int i = blockIdx.x * TBX + threadIdx.x;
-    const int j = blockIdx.y * TBY + threadIdx.y;
+// Assembly of one cell; returns its diagonal.
+__device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const AsmOut& out, int i, int j) {
     const int nx = g.nx, ny = g.ny;
-    if (i >= nx || j >= ny) return;
     const size_t c = (size_t)j * nx + i;
     const double E = in.E[c], T = in.T[c], rho = in.rho[c], kR = in.kR[c], kP = in.kP[c], cv = in.cv[c];
     const bool ok = isfinite(E) && E > 0.0 && isfinite(T) && T > 0.0 && isfinite(rho) && rho > 0.0 &&
@@ -254,6 +295,27 @@ __global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut ou
     out.m[c] = mass + bd;
     out.rhs[c] = dV * (E + beta * f * kARad * T3 * T) + br;
     out.s[c] = 1.0 / sqrt(diag);
+    return diag;
+}
+
+// One thread per cell computes its four faces (each interior face is computed
+// identically by its two cells, so the matrix is exactly symmetric), the
+// boundary terms and the cell terms C_V, beta, f.
+__global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut out) {
+    const int i = blockIdx.x * TBX + threadIdx.x;
+    const int j = blockIdx.y * TBY + threadIdx.y;
+    const int nx = g.nx, ny = g.ny;
+    __shared__ double sh[16];
+    const double diag = (i < nx && j < ny) ? assemble_cell(g, in, out, i, j) : 0.0;
+    const double bm = block_max(diag, sh);
+    if (ltid() == 0) out.part[bid2d()] = bm;
+    if (last_block(out.cnt, nblocks2d())) {
+        double v = 0.0;
+        for (int b = ltid(); b < (int)nblocks2d(); b += lsize()) v = fmax(v, load_agent(&out.part[b]));
+        const double mx = block_max(v, sh);
+        if (ltid() == 0) *out.mu = mx;
+        reset_counter(out.cnt);
+    }
 }
 
 // Full diagonal and copies of the FP64 operator (test access).
@@ -271,530 +333,6 @@ __global__ void k_get_operator(int nx, int ny, const double* We, const double* W
         const double ws = j > 0 ? Wn[c - nx] : 0.0;
         odiag[c] = m[c] + (((ww + We[c]) + ws) + Wn[c]);
     }
-}
-
-// ---------------------------------------------------------------------------
-// multigrid hierarchy (FP64 build, stored in the inner precision)
-// ---------------------------------------------------------------------------
-
-// Level 0: Jacobi-scaled operator S M S with unit diagonal.
-//   a_e = -W_e s s_e,  a_n = -W_n s s_n,  row sum ("mass") = 1 + sum of the four a (>= 0).
-__global__ void k_scale(int nx, int ny, const double* __restrict__ We, const double* __restrict__ Wn,
-                        const double* __restrict__ s, double* ae64, double* an64, double* mass64) {
-    const int i = blockIdx.x * TBX + threadIdx.x;
-    const int j = blockIdx.y * TBY + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const size_t c = (size_t)j * nx + i;
-    const double sc = s[c];
-    const double ae = (i + 1 < nx) ? -We[c] * sc * s[c + 1] : 0.0;
-    const double an = (j + 1 < ny) ? -Wn[c] * sc * s[c + nx] : 0.0;
-    const double aw = (i > 0) ? -We[c - 1] * s[c - 1] * sc : 0.0;
-    const double as = (j > 0) ? -Wn[c - nx] * s[c - nx] * sc : 0.0;
-    ae64[c] = ae;
-    an64[c] = an;
-    mass64[c] = fmax(0.0, 1.0 + (((aw + ae) + as) + an));
-}
-
-// 2x2 aggregation: coarse mass = sum of the four fine masses, coarse face
-// coupling = omega * (sum of the two fine couplings crossing it); omega = 1 is
-// the Galerkin operator P^T A P for piecewise-constant P, 0.5 the halved form.
-__global__ void k_coarsen(int nx, int ny, const double* __restrict__ mass, const double* __restrict__ ae,
-                          const double* __restrict__ an, int nxc, int nyc, double* massc, double* aec, double* anc,
-                          double omega) {
-    const int I = blockIdx.x * TBX + threadIdx.x;
-    const int J = blockIdx.y * TBY + threadIdx.y;
-    if (I >= nxc || J >= nyc) return;
-    double m = 0.0, e = 0.0, n = 0.0;
-    for (int b = 0; b < 2; ++b) {
-        const int j = 2 * J + b;
-        if (j >= ny) continue;
-        for (int a = 0; a < 2; ++a) {
-            const int i = 2 * I + a;
-            if (i < nx) m += mass[(size_t)j * nx + i];
-        }
-        if (2 * I + 2 < nx) e += ae[(size_t)j * nx + 2 * I + 1];
-    }
-    if (2 * J + 2 < ny) {
-        for (int a = 0; a < 2; ++a) {
-            const int i = 2 * I + a;
-            if (i < nx) n += an[(size_t)(2 * J + 1) * nx + i];
-        }
-    }
-    const size_t C = (size_t)J * nxc + I;
-    massc[C] = m;
-    aec[C] = omega * e;
-    anc[C] = omega * n;
-}
-
-// Inner-precision copy of a level: diagonal d = mass + |a_e| + |a_w| + |a_n| + |a_s|
-// (sum of non-negative terms: no cancellation), a_e, a_n.  Level 0 keeps the
-// unit diagonal and skips d.
-template <typename T>
-__global__ void k_demote_level(int nx, int ny, const double* __restrict__ mass, const double* __restrict__ ae,
-                               const double* __restrict__ an, T* d, T* aeT, T* anT) {
-    const int i = blockIdx.x * TBX + threadIdx.x;
-    const int j = blockIdx.y * TBY + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const size_t c = (size_t)j * nx + i;
-    aeT[c] = (T)ae[c];
-    anT[c] = (T)an[c];
-    if (d) {
-        const double aw = i > 0 ? ae[c - 1] : 0.0;
-        const double as = j > 0 ? an[c - nx] : 0.0;
-        d[c] = (T)(mass[c] - (((aw + ae[c]) + as) + an[c]));
-    }
-}
-
-// Dense inverse of the coarsest level (n <= 64 cells) by Gauss-Jordan
-// elimination without pivoting (the matrix is SPD), FP64 in LDS, one workgroup.
-constexpr int kCoarseMax = 64;
-template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_setup(int nx, int ny, const double* __restrict__ mass,
-                                                      const double* __restrict__ ae, const double* __restrict__ an,
-                                                      T* Ainv) {
-    __shared__ double A[kCoarseMax * kCoarseMax];
-    __shared__ double col[kCoarseMax];
-    const int n = nx * ny;
-    const int t = ltid(), nt = lsize();
-    for (int k = t; k < n * n; k += nt) A[k] = 0.0;
-    __syncthreads();
-    for (int c = t; c < n; c += nt) {
-        const int i = c % nx, j = c / nx;
-        const double e = (i + 1 < nx) ? ae[c] : 0.0;
-        const double w = (i > 0) ? ae[c - 1] : 0.0;
-        const double no = (j + 1 < ny) ? an[c] : 0.0;
-        const double so = (j > 0) ? an[c - nx] : 0.0;
-        A[c * n + c] = mass[c] - (((w + e) + so) + no);
-        if (i + 1 < nx) A[c * n + c + 1] = e;
-        if (i > 0) A[c * n + c - 1] = w;
-        if (j + 1 < ny) A[c * n + c + nx] = no;
-        if (j > 0) A[c * n + c - nx] = so;
-    }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double p = A[k * n + k];
-        for (int i = t; i < n; i += nt) col[i] = A[i * n + k];
-        __syncthreads();
-        for (int i = t; i < n; i += nt) A[i * n + k] = (i == k) ? 1.0 : 0.0;
-        __syncthreads();
-        for (int jj = t; jj < n; jj += nt) A[k * n + jj] /= p;
-        __syncthreads();
-        for (int q = t; q < n * n; q += nt) {
-            const int i = q / n, jj = q % n;
-            if (i != k) A[q] -= col[i] * A[k * n + jj];
-        }
-        __syncthreads();
-    }
-    for (int q = t; q < n * n; q += nt) Ainv[q] = (T)A[q];
-}
-
-// ---------------------------------------------------------------------------
-// V-cycle: red-black Gauss-Seidel, symmetric (R,B pre / B,R post), 2x2 aggregation
-// ---------------------------------------------------------------------------
-
-template <int H>
-struct TileG {
-    static constexpr int LX = TBX + 2 * H;
-    static constexpr int LY = TRows + 2 * H;
-    static constexpr int N = LX * LY;
-};
-
-// Pre-smoothing from a zero guess (red then black half-sweep), residual on the
-// tile, restriction by 2x2 sums.  Needs a halo of 2 cells.
-template <typename T, bool UNIT>
-__global__ __launch_bounds__(256) void k_pre(int nx, int ny, const T* __restrict__ b, const T* __restrict__ dg,
-                                             const T* __restrict__ ae, const T* __restrict__ an, T* __restrict__ xo,
-                                             T* __restrict__ bc, int nxc, int nyc, const Scalars* __restrict__ sc) {
-    if (sc->done) return;
-    constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
-    __shared__ T sb[N], sd[UNIT ? 1 : N], sae[N], san[N], sx[N];
-    __shared__ T sr[TRows][TBX];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
-        const size_t c = (size_t)j * nx + i;
-        sb[k] = in ? b[c] : T(0);
-        sae[k] = in ? ae[c] : T(0);
-        san[k] = in ? an[c] : T(0);
-        if (!UNIT) sd[k] = in ? dg[c] : T(1);
-    }
-    __syncthreads();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool red = ((i + j) & 1) == 0;
-        sx[k] = red ? (UNIT ? sb[k] : sb[k] / sd[k]) : T(0);
-    }
-    __syncthreads();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        if (lx < 1 || lx >= LX - 1 || ly < 1 || ly >= LY - 1 || ((i + j) & 1) == 0) continue;
-        const T s = sb[k] - (sae[k] * sx[k + 1] + sae[k - 1] * sx[k - 1] + san[k] * sx[k + LX] + san[k - LX] * sx[k - LX]);
-        sx[k] = UNIT ? s : s / sd[k];
-    }
-    __syncthreads();
-    for (int r = 0; r < TRows / TBY; ++r) {
-        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
-        const int i = i0 + lx, j = j0 + ly;
-        const int k = (ly + H) * LX + lx + H;
-        T res = T(0);
-        if (i < nx && j < ny) {
-            const T dk = UNIT ? T(1) : sd[k];
-            res = sb[k] - (dk * sx[k] + sae[k] * sx[k + 1] + sae[k - 1] * sx[k - 1] + san[k] * sx[k + LX] +
-                           san[k - LX] * sx[k - LX]);
-            xo[(size_t)j * nx + i] = sx[k];
-        }
-        sr[ly][lx] = res;
-    }
-    __syncthreads();
-    {
-        const int cx = t % (TBX / 2), cy = t / (TBX / 2);
-        const int I = blockIdx.x * (TBX / 2) + cx, J = blockIdx.y * (TRows / 2) + cy;
-        if (cy < TRows / 2 && I < nxc && J < nyc) {
-            bc[(size_t)J * nxc + I] =
-                (sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) + (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]);
-        }
-    }
-}
-
-// Prolongation (piecewise constant, scaled by omega) + post-smoothing (black
-// then red).  With DOT, also accumulates r.z for CG and finalises beta.
-template <typename T, bool UNIT, bool DOT>
-__global__ __launch_bounds__(256) void k_post(int nx, int ny, const T* __restrict__ b, const T* __restrict__ dg,
-                                              const T* __restrict__ ae, const T* __restrict__ an,
-                                              const T* __restrict__ xp, const T* __restrict__ ec, int nxc, T omega,
-                                              T* __restrict__ xo, double* part, Scalars* sc) {
-    if (sc->done) return;
-    constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
-    __shared__ T sb[N], sd[UNIT ? 1 : N], sae[N], san[N], sx[N];
-    __shared__ double sh[16];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
-        const size_t c = (size_t)j * nx + i;
-        sb[k] = in ? b[c] : T(0);
-        sae[k] = in ? ae[c] : T(0);
-        san[k] = in ? an[c] : T(0);
-        if (!UNIT) sd[k] = in ? dg[c] : T(1);
-        sx[k] = in ? xp[c] + omega * ec[(size_t)(j >> 1) * nxc + (i >> 1)] : T(0);
-    }
-    __syncthreads();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        if (lx < 1 || lx >= LX - 1 || ly < 1 || ly >= LY - 1 || ((i + j) & 1) == 0) continue;
-        if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny) continue;
-        const T s = sb[k] - (sae[k] * sx[k + 1] + sae[k - 1] * sx[k - 1] + san[k] * sx[k + LX] + san[k - LX] * sx[k - LX]);
-        sx[k] = UNIT ? s : s / sd[k];
-    }
-    __syncthreads();
-    double acc = 0.0;
-    for (int r = 0; r < TRows / TBY; ++r) {
-        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
-        const int i = i0 + lx, j = j0 + ly;
-        if (i >= nx || j >= ny) continue;
-        const int k = (ly + H) * LX + lx + H;
-        T v = sx[k];
-        if (((i + j) & 1) == 0) {
-            const T s = sb[k] - (sae[k] * sx[k + 1] + sae[k - 1] * sx[k - 1] + san[k] * sx[k + LX] + san[k - LX] * sx[k - LX]);
-            v = UNIT ? s : s / sd[k];
-        }
-        xo[(size_t)j * nx + i] = v;
-        if (DOT) acc += (double)sb[k] * (double)v;
-    }
-    if (DOT) {
-        const double tot = block_sum(acc, sh);
-        if (t == 0) part[bid2d()] = tot;
-        if (last_block(&sc->cnt[CNT_POST], nblocks2d())) {
-            const double rz = sum_partials(part, nblocks2d(), 1, 0, sh);
-            if (t == 0) {
-                if (!(rz > 0.0) || !isfinite(rz)) {
-                    sc->status = ST_EBREAKDOWN;
-                    sc->done = 1;
-                } else {
-                    sc->beta = sc->iter > 0 ? rz / sc->rz_old : 0.0;
-                    sc->rz_old = rz;
-                }
-            }
-            reset_counter(&sc->cnt[CNT_POST]);
-        }
-    }
-}
-
-// Coarsest level: x = A^-1 b with the dense inverse (n <= 64).  With DOT (a
-// one-level hierarchy) it also finalises r.z and beta like k_post.
-template <typename T, bool DOT>
-__global__ __launch_bounds__(64) void k_coarse_solve(int n, const T* __restrict__ Ainv, const T* __restrict__ b,
-                                                     T* __restrict__ x, double* part, Scalars* sc) {
-    if (sc->done) return;
-    __shared__ T sb[kCoarseMax];
-    __shared__ double sh[16];
-    const int t = threadIdx.x;
-    if (t < n) sb[t] = b[t];
-    __syncthreads();
-    double acc = 0.0;
-    if (t < n) {
-        T a = T(0);
-        for (int k = 0; k < n; ++k) a += Ainv[t * n + k] * sb[k];
-        x[t] = a;
-        acc = (double)sb[t] * (double)a;
-    }
-    if (DOT) {
-        const double rz = block_sum(acc, sh);
-        if (t == 0) {
-            if (!(rz > 0.0) || !isfinite(rz)) {
-                sc->status = ST_EBREAKDOWN;
-                sc->done = 1;
-            } else {
-                sc->beta = sc->iter > 0 ? rz / sc->rz_old : 0.0;
-                sc->rz_old = rz;
-            }
-        }
-    }
-    (void)part;
-}
-
-// ---------------------------------------------------------------------------
-// CG kernels (inner precision T, reductions in FP64)
-// ---------------------------------------------------------------------------
-
-// p = z + beta * pscale * p_in (p = z on the first iteration), q = A p (unit
-// diagonal), partial p.q; the last workgroup sets alpha = r.z / p.q.
-template <typename T>
-__global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
-                                              T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ ae,
-                                              const T* __restrict__ an, double* part, Scalars* sc) {
-    if (sc->done) return;
-    constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
-    __shared__ T sp[N], sae[N], san[N];
-    __shared__ double sh[16];
-    const bool first = sc->iter == 0;
-    const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
-        const size_t c = (size_t)j * nx + i;
-        sp[k] = in ? (first ? z[c] : z[c] + beta * pin[c]) : T(0);
-        sae[k] = in ? ae[c] : T(0);
-        san[k] = in ? an[c] : T(0);
-    }
-    __syncthreads();
-    double acc = 0.0;
-    for (int r = 0; r < TRows / TBY; ++r) {
-        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
-        const int i = i0 + lx, j = j0 + ly;
-        if (i >= nx || j >= ny) continue;
-        const int k = (ly + H) * LX + lx + H;
-        const T v = sp[k] + (sae[k] * sp[k + 1] + sae[k - 1] * sp[k - 1] + san[k] * sp[k + LX] + san[k - LX] * sp[k - LX]);
-        const size_t c = (size_t)j * nx + i;
-        pout[c] = sp[k];
-        q[c] = v;
-        acc += (double)sp[k] * (double)v;
-    }
-    const double tot = block_sum(acc, sh);
-    if (t == 0) part[bid2d()] = tot;
-    if (last_block(&sc->cnt[CNT_SPMV], nblocks2d())) {
-        const double pq = sum_partials(part, nblocks2d(), 1, 0, sh);
-        if (t == 0) {
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                sc->status = ST_EBREAKDOWN;
-                sc->done = 1;
-                sc->pending = 1;
-            } else {
-                sc->alpha = sc->rz_old / pq;
-            }
-            sc->pscale = 1.0;
-        }
-        reset_counter(&sc->cnt[CNT_SPMV]);
-    }
-}
-
-// x += alpha p, r -= alpha q, partial r.r; the last workgroup counts the
-// iteration and decides whether a reliable update (true FP64 residual) is due.
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                const T* __restrict__ q, double* part, Scalars* sc) {
-    if (sc->done) return;
-    __shared__ double sh[16];
-    const T a = (T)sc->alpha;
-    double acc = 0.0;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        x[c] += a * p[c];
-        const T rn = r[c] - a * q[c];
-        r[c] = rn;
-        acc += (double)rn * (double)rn;
-    }
-    const double tot = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    if (last_block(&sc->cnt[CNT_UPDATE], gridDim.x)) {
-        const double rr = sum_partials(part, gridDim.x, 1, 0, sh);
-        if (threadIdx.x == 0) {
-            sc->rr = rr;
-            sc->iter += 1;
-            bool check;
-            if (sc->reliable) {
-                // reliable update when the recurrence residual fell by delta since the
-                // last one, or when it predicts the target is met
-                const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
-                check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
-            } else {
-                check = rr <= sc->inner_tol2;
-            }
-            if (!isfinite(rr)) {
-                sc->status = ST_EBREAKDOWN;
-                check = true;
-            }
-            if (sc->iter >= sc->max_iter) check = true;
-            if (check) sc->pending = 1;
-        }
-        reset_counter(&sc->cnt[CNT_UPDATE]);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 refinement kernels
-// ---------------------------------------------------------------------------
-
-// E += gamma * s * x; x = 0.
-template <typename T>
-__global__ __launch_bounds__(256) void k_correct(int n, double* __restrict__ E, const double* __restrict__ s,
-                                                 T* __restrict__ x, const Scalars* __restrict__ sc, int force) {
-    if (!force && (sc->done || !sc->pending)) return;
-    const double g = sc->gamma;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        E[c] += g * s[c] * (double)x[c];
-        x[c] = T(0);
-    }
-}
-
-// True residual r = rhs - M E in flux form, rhs - m E - sum_f W (E - E_nb),
-// and the four norms of the stop rule; the last workgroup decides convergence
-// and the new residual scale.
-__global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __restrict__ E, const double* __restrict__ We,
-                                                 const double* __restrict__ Wn, const double* __restrict__ m,
-                                                 const double* __restrict__ rhs, const double* __restrict__ s,
-                                                 double* __restrict__ r64, double* part, Scalars* sc, int force) {
-    if (!force && (sc->done || !sc->pending)) return;
-    const int nx = g.nx, ny = g.ny;
-    constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
-    __shared__ double sE[N], sWe[N], sWn[N];
-    __shared__ double sh[16];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
-    for (int k = t; k < N; k += kThreads) {
-        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
-        const size_t c = (size_t)j * nx + i;
-        sE[k] = in ? E[c] : 0.0;
-        sWe[k] = in ? We[c] : 0.0;
-        sWn[k] = in ? Wn[c] : 0.0;
-    }
-    __syncthreads();
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int r = 0; r < TRows / TBY; ++r) {
-        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
-        const int i = i0 + lx, j = j0 + ly;
-        if (i >= nx || j >= ny) continue;
-        const int k = (ly + H) * LX + lx + H;
-        const size_t c = (size_t)j * nx + i;
-        const double e = sE[k];
-        double flux = sWe[k] * (e - sE[k + 1]);
-        flux += sWe[k - 1] * (e - sE[k - 1]);
-        flux += sWn[k] * (e - sE[k + LX]);
-        flux += sWn[k - LX] * (e - sE[k - LX]);
-        const double b = rhs[c];
-        const double res = b - m[c] * e - flux;
-        r64[c] = res;
-        const double dV = g.vx[i] * g.vy[j];
-        const double sv = s[c];
-        a0 += (res / dV) * (res / dV);
-        a1 += (sv * res) * (sv * res);
-        a2 += (b / dV) * (b / dV);
-        a3 += (sv * b) * (sv * b);
-    }
-    const double t0 = block_sum(a0, sh), t1 = block_sum(a1, sh), t2 = block_sum(a2, sh), t3 = block_sum(a3, sh);
-    if (t == 0) {
-        double* pp = part + (size_t)bid2d() * 4;
-        pp[0] = t0;
-        pp[1] = t1;
-        pp[2] = t2;
-        pp[3] = t3;
-    }
-    if (last_block(&sc->cnt[CNT_RESID], nblocks2d())) {
-        double tot[4];
-        for (int q = 0; q < 4; ++q) tot[q] = sum_partials(part, nblocks2d(), 4, q, sh);
-        if (t == 0) {
-            for (int q = 0; q < 4; ++q) sc->sums[q] = tot[q];
-            const double rrow = tot[2] > 0.0 ? sqrt(tot[0] / tot[2]) : sqrt(tot[0]);
-            const double rsc = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
-            const double rel = sc->norm == 0 ? rrow : rsc;
-            sc->rel_row = rrow;
-            sc->rel_scaled = rsc;
-            sc->rel_sel = rel;
-            sc->nchecks += 1;
-            const double gnew = sqrt(tot[1]);
-            if (!isfinite(rel)) {
-                sc->status = ST_EBREAKDOWN;
-                sc->done = 1;
-            } else if (rel <= sc->eps || gnew == 0.0) {
-                sc->done = 1;
-            } else if (sc->status != ST_OK || sc->iter >= sc->max_iter || (!sc->reliable && sc->iter > 0)) {
-                if (sc->status == ST_OK && sc->reliable) sc->status = ST_ENOCONV;
-                sc->done = 1;
-            } else {
-                const double ps = sc->gamma > 0.0 ? sc->gamma / gnew : 1.0;
-                sc->pscale = ps;
-                sc->rz_old *= ps * ps;
-                sc->gamma = gnew;
-                sc->rho_last = rel;
-                sc->rr_ref = 1.0;
-            }
-        }
-        reset_counter(&sc->cnt[CNT_RESID]);
-    }
-}
-
-// r_inner = S r / gamma in the inner precision (and x = 0); the last workgroup
-// clears the pending flag.
-template <typename T>
-__global__ __launch_bounds__(256) void k_demote(int n, const double* __restrict__ r64, const double* __restrict__ s,
-                                                T* __restrict__ r, T* __restrict__ x, Scalars* sc, int force) {
-    if (!force && (sc->done || !sc->pending)) return;
-    if (sc->done) return;
-    const double ig = 1.0 / sc->gamma;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        r[c] = (T)(s[c] * r64[c] * ig);
-        x[c] = T(0);
-    }
-    if (last_block(&sc->cnt[CNT_DEMOTE], gridDim.x)) {
-        if (threadIdx.x == 0) sc->pending = 0;
-        reset_counter(&sc->cnt[CNT_DEMOTE]);
-    }
-}
-
-__global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double inner_tol2, int max_iter, int norm,
-                               int reliable) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    sc->rz_old = 0.0;
-    sc->alpha = sc->beta = 0.0;
-    sc->pscale = 1.0;
-    sc->rr = 0.0;
-    sc->rr_ref = 1.0;
-    sc->gamma = 0.0;
-    sc->rho_last = 1.0;
-    for (int q = 0; q < 4; ++q) sc->sums[q] = 0.0;
-    sc->rel_row = sc->rel_scaled = sc->rel_sel = 0.0;
-    sc->eps = eps;
-    sc->delta2 = delta2;
-    sc->inner_tol2 = inner_tol2;
-    sc->iter = 0;
-    sc->done = 0;
-    sc->pending = 1;
-    sc->status = ST_OK;
-    sc->max_iter = max_iter;
-    sc->norm = norm;
-    sc->reliable = reliable;
-    sc->nchecks = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,804 @@
+// Multigrid-preconditioned CG kernels (inner precision T = float or double).
+//
+// Inner operator: the assembled E system M divided by mu = max diag(M)
+// (one global factor keeps every coefficient and vector inside binary32
+// range).  Every level stores its operator as (m, W_e, W_n): the
+// non-negative "mass" m (row sum: dV (1 + beta f) plus boundary diagonal
+// terms) and the non-negative face conductances to the east / north
+// neighbour.  The diagonal m + W_w + W_e + W_s + W_n is a sum of non-negative
+// terms, so the rounded operator stays exactly diagonally dominant at every
+// level, and matrix-vector products use the flux form m x + sum W (x - x_nb).
+//
+// Coarse levels: 2x2 aggregation, coarse mass = sum of the four fine masses,
+// coarse conductance = omega * (sum of the two fine conductances crossing the
+// coarse face); omega = 1 is the Galerkin product P^T M P for piecewise
+// constant P, omega = 1/2 rescales it to the coarse spacing.
+//
+// Smoothers: point red-black Gauss-Seidel, or alternating zebra line
+// Gauss-Seidel.  Line solves always run along the rows of a row-major view;
+// the other direction uses a transposed copy of the level (coefficients
+// transposed once per assembly, vectors transposed between the two sweeps),
+// so every load stays coalesced.
+#pragma once
+#include "fld_kernels.hpp"
+
+namespace fld {
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+
+__global__ void k_coarsen(int nx, int ny, const double* __restrict__ m, const double* __restrict__ We,
+                          const double* __restrict__ Wn, int nxc, int nyc, double* mc, double* Wec, double* Wnc,
+                          double omega) {
+    const int I = blockIdx.x * TBX + threadIdx.x;
+    const int J = blockIdx.y * TBY + threadIdx.y;
+    if (I >= nxc || J >= nyc) return;
+    double ms = 0.0, e = 0.0, n = 0.0;
+    for (int b = 0; b < 2; ++b) {
+        const int j = 2 * J + b;
+        if (j >= ny) continue;
+        for (int a = 0; a < 2; ++a) {
+            const int i = 2 * I + a;
+            if (i < nx) ms += m[(size_t)j * nx + i];
+        }
+        if (2 * I + 2 < nx) e += We[(size_t)j * nx + 2 * I + 1];
+    }
+    if (2 * J + 2 < ny) {
+        for (int a = 0; a < 2; ++a) {
+            const int i = 2 * I + a;
+            if (i < nx) n += Wn[(size_t)(2 * J + 1) * nx + i];
+        }
+    }
+    const size_t C = (size_t)J * nxc + I;
+    mc[C] = ms;
+    Wec[C] = omega * e;
+    Wnc[C] = omega * n;
+}
+
+// Inner-precision copy of a level, divided by mu.
+template <typename T>
+__global__ void k_demote_level(int n, const double* __restrict__ m, const double* __restrict__ We,
+                               const double* __restrict__ Wn, const double* __restrict__ mu, T* mT, T* WeT, T* WnT) {
+    const double s = 1.0 / *mu;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        mT[c] = (T)(m[c] * s);
+        WeT[c] = (T)(We[c] * s);
+        WnT[c] = (T)(Wn[c] * s);
+    }
+}
+
+// Tiled transpose of up to three [ny][nx] arrays into [nx][ny] arrays,
+// 32 x 32 tiles through LDS (padded against bank conflicts).
+constexpr int kTT = 32;
+template <typename T, int NA>
+__global__ __launch_bounds__(256) void k_transpose(int nx, int ny, const T* __restrict__ s0, const T* __restrict__ s1,
+                                                   const T* __restrict__ s2, T* __restrict__ d0, T* __restrict__ d1,
+                                                   T* __restrict__ d2, const Scalars* __restrict__ sc) {
+    if (sc && sc->done) return;
+    __shared__ T tile[NA][kTT][kTT + 1];
+    const int i0 = blockIdx.x * kTT, j0 = blockIdx.y * kTT;
+    const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+    for (int r = ty; r < kTT; r += 8) {
+        const int i = i0 + tx, j = j0 + r;
+        if (i < nx && j < ny) {
+            const size_t c = (size_t)j * nx + i;
+            tile[0][r][tx] = s0[c];
+            if (NA > 1) tile[NA > 1 ? 1 : 0][r][tx] = s1[c];
+            if (NA > 2) tile[NA > 2 ? 2 : 0][r][tx] = s2[c];
+        }
+    }
+    __syncthreads();
+    for (int r = ty; r < kTT; r += 8) {
+        const int ii = i0 + r, jj = j0 + tx;
+        if (ii < nx && jj < ny) {
+            const size_t c = (size_t)ii * ny + jj;
+            d0[c] = tile[0][tx][r];
+            if (NA > 1) d1[c] = tile[NA > 1 ? 1 : 0][tx][r];
+            if (NA > 2) d2[c] = tile[NA > 2 ? 2 : 0][tx][r];
+        }
+    }
+}
+
+// Dense inverse of the coarsest level (n <= 64 cells) by Gauss-Jordan
+// elimination without pivoting (the matrix is SPD), FP64 in LDS, one
+// workgroup.  `tr` selects the cell order of the view the solver uses on that
+// level (0: row-major, 1: transposed).
+constexpr int kCoarseMax = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_setup(int nx, int ny, int tr, const double* __restrict__ m,
+                                                      const double* __restrict__ We, const double* __restrict__ Wn,
+                                                      const double* __restrict__ mu, T* Ainv) {
+    __shared__ double A[kCoarseMax * kCoarseMax];
+    __shared__ double col[kCoarseMax];
+    const int n = nx * ny;
+    const int t = ltid(), nt = lsize();
+    const double s = 1.0 / *mu;
+    for (int k = t; k < n * n; k += nt) A[k] = 0.0;
+    __syncthreads();
+    for (int c = t; c < n; c += nt) {
+        const int i = c % nx, j = c / nx;
+        auto id = [&](int ii, int jj) { return tr ? ii * ny + jj : jj * nx + ii; };
+        const double e = (i + 1 < nx) ? We[c] * s : 0.0;
+        const double w = (i > 0) ? We[c - 1] * s : 0.0;
+        const double no = (j + 1 < ny) ? Wn[c] * s : 0.0;
+        const double so = (j > 0) ? Wn[c - nx] * s : 0.0;
+        const int me = id(i, j);
+        A[me * n + me] = m[c] * s + ((w + e) + (so + no));
+        if (i + 1 < nx) A[me * n + id(i + 1, j)] = -e;
+        if (i > 0) A[me * n + id(i - 1, j)] = -w;
+        if (j + 1 < ny) A[me * n + id(i, j + 1)] = -no;
+        if (j > 0) A[me * n + id(i, j - 1)] = -so;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double p = A[k * n + k];
+        for (int i = t; i < n; i += nt) col[i] = A[i * n + k];
+        __syncthreads();
+        for (int i = t; i < n; i += nt) A[i * n + k] = (i == k) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int jj = t; jj < n; jj += nt) A[k * n + jj] /= p;
+        __syncthreads();
+        for (int q = t; q < n * n; q += nt) {
+            const int i = q / n, jj = q % n;
+            if (i != k) A[q] -= col[i] * A[k * n + jj];
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < n * n; q += nt) Ainv[q] = (T)A[q];
+}
+
+// rz finalisation shared by the kernels that end a V-cycle on level 0:
+// beta = rz / rz_old (CG), or breakdown.
+__device__ inline void finish_rz(Scalars* sc, double rz) {
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        sc->status = ST_EBREAKDOWN;
+        sc->done = 1;
+    } else {
+        sc->beta = sc->iter > 0 ? rz / sc->rz_old : 0.0;
+        sc->rz_old = rz;
+    }
+}
+
+// Coarsest level: x = A^-1 b with the dense inverse.  With DOT (a one-level
+// hierarchy) it also finalises r.z.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(64) void k_coarse_solve(int n, const T* __restrict__ Ainv, const T* __restrict__ b,
+                                                     T* __restrict__ x, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ T sb[kCoarseMax];
+    __shared__ double sh[16];
+    const int t = threadIdx.x;
+    if (t < n) sb[t] = b[t];
+    __syncthreads();
+    double acc = 0.0;
+    if (t < n) {
+        T a = T(0);
+        for (int k = 0; k < n; ++k) a += Ainv[t * n + k] * sb[k];
+        x[t] = a;
+        acc = (double)sb[t] * (double)a;
+    }
+    if (DOT) {
+        const double rz = block_sum(acc, sh);
+        if (t == 0) finish_rz(sc, rz);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+
+template <int H>
+struct TileG {
+    static constexpr int LX = TBX + 2 * H;
+    static constexpr int LY = TRows + 2 * H;
+    static constexpr int N = LX * LY;
+};
+
+// Loads m, W_e, W_n of a tile plus halo into LDS (zero outside the grid).
+template <typename T, int H>
+__device__ inline void load_coef_tile(int nx, int ny, int i0, int j0, const T* m, const T* We, const T* Wn, T* sm,
+                                      T* swe, T* swn) {
+    constexpr int LX = TileG<H>::LX, N = TileG<H>::N;
+    for (int k = ltid(); k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const size_t c = (size_t)j * nx + i;
+        sm[k] = in ? m[c] : T(0);
+        swe[k] = in ? We[c] : T(0);
+        swn[k] = in ? Wn[c] : T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// point smoother (red-black Gauss-Seidel, row-major levels)
+// ---------------------------------------------------------------------------
+
+// Pre-smoothing from a zero guess (red then black half-sweep), residual on the
+// tile, restriction by 2x2 sums.  Halo of 2 cells.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre_point(int nx, int ny, const T* __restrict__ b, const T* __restrict__ m,
+                                                   const T* __restrict__ We, const T* __restrict__ Wn,
+                                                   T* __restrict__ xo, T* __restrict__ bc, int nxc, int nyc,
+                                                   const Scalars* __restrict__ sc) {
+    if (sc->done) return;
+    constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
+    __shared__ T sb[N], sm[N], swe[N], swn[N], sx[N];
+    __shared__ T sr[TRows][TBX];
+    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    load_coef_tile<T, H>(nx, ny, i0, j0, m, We, Wn, sm, swe, swn);
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        sb[k] = in ? b[(size_t)j * nx + i] : T(0);
+    }
+    __syncthreads();
+    // diagonal needs the west / south conductances: region minus its outer ring
+    // (red cells on the ring keep x = 0; they are never read by a tile residual)
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        T v = T(0);
+        if (lx >= 1 && ly >= 1 && ((i + j) & 1) == 0) {
+            const T d = sm[k] + ((swe[k - 1] + swe[k]) + (swn[k - LX] + swn[k]));
+            if (d > T(0)) v = sb[k] / d;
+        }
+        sx[k] = v;
+    }
+    __syncthreads();
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        if (lx < 1 || lx >= LX - 1 || ly < 1 || ly >= LY - 1 || ((i + j) & 1) == 0) continue;
+        const T d = sm[k] + ((swe[k - 1] + swe[k]) + (swn[k - LX] + swn[k]));
+        const T s = sb[k] + (swe[k] * sx[k + 1] + swe[k - 1] * sx[k - 1] + swn[k] * sx[k + LX] + swn[k - LX] * sx[k - LX]);
+        sx[k] = d > T(0) ? s / d : T(0);
+    }
+    __syncthreads();
+    for (int r = 0; r < TRows / TBY; ++r) {
+        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
+        const int i = i0 + lx, j = j0 + ly;
+        const int k = (ly + H) * LX + lx + H;
+        T res = T(0);
+        if (i < nx && j < ny) {
+            const T xv = sx[k];
+            res = sb[k] - (sm[k] * xv + swe[k] * (xv - sx[k + 1]) + swe[k - 1] * (xv - sx[k - 1]) +
+                           swn[k] * (xv - sx[k + LX]) + swn[k - LX] * (xv - sx[k - LX]));
+            xo[(size_t)j * nx + i] = xv;
+        }
+        sr[ly][lx] = res;
+    }
+    __syncthreads();
+    {
+        const int cx = t % (TBX / 2), cy = t / (TBX / 2);
+        const int I = blockIdx.x * (TBX / 2) + cx, J = blockIdx.y * (TRows / 2) + cy;
+        if (cy < TRows / 2 && I < nxc && J < nyc)
+            bc[(size_t)J * nxc + I] =
+                (sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) + (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]);
+    }
+}
+
+// Prolongation (piecewise constant, times omega) + post-smoothing (black then
+// red).  With DOT, also accumulates r.z and finalises beta (level 0).
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void k_post_point(int nx, int ny, const T* __restrict__ b, const T* __restrict__ m,
+                                                    const T* __restrict__ We, const T* __restrict__ Wn,
+                                                    const T* __restrict__ xp, const T* __restrict__ ec, int nxc,
+                                                    T omega, T* __restrict__ xo, double* part, Scalars* sc) {
+    if (sc->done) return;
+    constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
+    __shared__ T sb[N], sm[N], swe[N], swn[N], sx[N];
+    __shared__ double sh[16];
+    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    load_coef_tile<T, H>(nx, ny, i0, j0, m, We, Wn, sm, swe, swn);
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const size_t c = (size_t)j * nx + i;
+        sb[k] = in ? b[c] : T(0);
+        sx[k] = in ? xp[c] + omega * ec[(size_t)(j >> 1) * nxc + (i >> 1)] : T(0);
+    }
+    __syncthreads();
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        if (lx < 1 || lx >= LX - 1 || ly < 1 || ly >= LY - 1 || ((i + j) & 1) == 0) continue;
+        if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny) continue;
+        const T d = sm[k] + ((swe[k - 1] + swe[k]) + (swn[k - LX] + swn[k]));
+        const T s = sb[k] + (swe[k] * sx[k + 1] + swe[k - 1] * sx[k - 1] + swn[k] * sx[k + LX] + swn[k - LX] * sx[k - LX]);
+        sx[k] = d > T(0) ? s / d : T(0);
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int r = 0; r < TRows / TBY; ++r) {
+        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i >= nx || j >= ny) continue;
+        const int k = (ly + H) * LX + lx + H;
+        T v = sx[k];
+        if (((i + j) & 1) == 0) {
+            const T d = sm[k] + ((swe[k - 1] + swe[k]) + (swn[k - LX] + swn[k]));
+            const T s =
+                sb[k] + (swe[k] * sx[k + 1] + swe[k - 1] * sx[k - 1] + swn[k] * sx[k + LX] + swn[k - LX] * sx[k - LX]);
+            v = d > T(0) ? s / d : T(0);
+        }
+        xo[(size_t)j * nx + i] = v;
+        if (DOT) acc += (double)sb[k] * (double)v;
+    }
+    if (DOT) {
+        const double tot = block_sum(acc, sh);
+        if (t == 0) part[bid2d()] = tot;
+        if (last_block(&sc->cnt[CNT_POST], nblocks2d())) {
+            const double rz = sum_partials(part, nblocks2d(), 1, 0, sh);
+            if (t == 0) finish_rz(sc, rz);
+            reset_counter(&sc->cnt[CNT_POST]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// line smoother (zebra line Gauss-Seidel along rows)
+// ---------------------------------------------------------------------------
+
+constexpr int kLineMaxL = 16;   // cells per thread chunk
+constexpr int kLineWG = 256;    // threads per workgroup; lines of K chunks, 256/K lines per workgroup
+enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
+
+// One zebra half-sweep: for every row j with j % 2 == par solve exactly
+//   (m + W_w + W_e + W_s + W_n) x - W_w x_w - W_e x_e = b + W_s x_s + W_n x_n,
+// the south / north rows taken from x (LINE_ZERO: zero, LINE_PROLONG:
+// x + omega * coarse correction).  Rows of the other parity are only read, so
+// the update is in place.
+//
+// Parallel tridiagonal solve: a row is split into K chunks of L cells, one
+// chunk per thread.  Each thread eliminates its chunk's interior (Thomas,
+// three right-hand sides) to express every interior unknown through the last
+// unknowns X_{k-1}, X_k of the previous and of its own chunk; substituting the
+// neighbour chunk's first row gives one tridiagonal equation per chunk in the
+// X's, solved by parallel cyclic reduction in LDS; back-substitution finishes.
+// DOT = 1: partial r.z over the solved rows, stored; DOT = 2: the same, plus
+// the last workgroup sums these and the DOT = 1 kernel's partials (level 0).
+template <typename T, int MODE, int DOT>
+__global__ __launch_bounds__(256) void k_line(int nx, int ny, int K, int L, int par, const T* __restrict__ m,
+                                              const T* __restrict__ We, const T* __restrict__ Wn,
+                                              const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ ec,
+                                              int nxc, T omega, double* part, int nb_prev, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ T sA[kLineWG], sB[kLineWG], sC[kLineWG], sR[kLineWG];
+    __shared__ T sy0[kLineWG], su0[kLineWG], sv0[kLineWG];
+    __shared__ double sh[16];
+    const int t = threadIdx.x;
+    const int lpw = kLineWG / K;
+    const int k = t % K;
+    const int row = 2 * (int)(blockIdx.x * lpw + t / K) + par;
+    const bool active = row < ny;
+    const int s0 = k * L;
+    const size_t rbase = (size_t)(active ? row : 0) * nx;
+
+    auto xnb = [&](int rr, int g) -> T {  // value of a neighbour-row cell
+        const size_t c = (size_t)rr * nx + g;
+        if (MODE == LINE_PROLONG) return x[c] + omega * ec[(size_t)(rr >> 1) * nxc + (g >> 1)];
+        return x[c];
+    };
+    // coefficients of cell g of this row: a = -W_w, d, c = -W_e, r
+    auto coef = [&](int g, T& a, T& d, T& c, T& r) {
+        if (!active || g >= nx) {
+            a = T(0); d = T(1); c = T(0); r = T(0);
+            return;
+        }
+        const size_t cc = rbase + g;
+        const T we = We[cc];
+        const T ww = g > 0 ? We[cc - 1] : T(0);
+        const T wn = Wn[cc];
+        const T ws = row > 0 ? Wn[cc - nx] : T(0);
+        d = m[cc] + ((ww + we) + (ws + wn));
+        a = -ww;
+        c = -we;
+        T rr = b[cc];
+        if (MODE != LINE_ZERO) {
+            if (row + 1 < ny) rr += wn * xnb(row + 1, g);
+            if (row > 0) rr += ws * xnb(row - 1, g);
+        }
+        r = rr;
+    };
+
+    // forward elimination of the chunk interior (local 0 .. L-2)
+    T cp[kLineMaxL], gy[kLineMaxL], gu[kLineMaxL], gv[kLineMaxL];
+#pragma unroll
+    for (int q = 0; q < kLineMaxL - 1; ++q) {
+        if (q < L - 1) {
+            T a, d, c, r;
+            coef(s0 + q, a, d, c, r);
+            const T den = (q == 0) ? d : d - a * cp[q - 1];
+            const T inv = T(1) / den;
+            cp[q] = c * inv;
+            gy[q] = ((q == 0) ? r : r - a * gy[q - 1]) * inv;
+            gu[q] = ((q == 0) ? -a : -a * gu[q - 1]) * inv;
+            const T rv = (q == L - 2) ? -c : T(0);
+            gv[q] = ((q == 0) ? rv : rv - a * gv[q - 1]) * inv;
+        }
+    }
+    // back substitution: y, u, v overwrite gy, gu, gv
+#pragma unroll
+    for (int q = kLineMaxL - 3; q >= 0; --q) {
+        if (q < L - 2) {
+            gy[q] -= cp[q] * gy[q + 1];
+            gu[q] -= cp[q] * gu[q + 1];
+            gv[q] -= cp[q] * gv[q + 1];
+        }
+    }
+    // interface cell of the chunk (local L-1)
+    T aE, dE, cE, rE;
+    coef(s0 + L - 1, aE, dE, cE, rE);
+    T yl = T(0), ul = T(0), vl = T(0);
+#pragma unroll
+    for (int q = 0; q < kLineMaxL - 1; ++q)
+        if (q == L - 2) {
+            yl = gy[q];
+            ul = gu[q];
+            vl = gv[q];
+        }
+    sy0[t] = gy[0];
+    su0[t] = gu[0];
+    sv0[t] = gv[0];
+    __syncthreads();
+    const bool has_next = k + 1 < K;
+    const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0), vn = has_next ? sv0[t + 1] : T(0);
+    sA[t] = aE * ul;
+    sB[t] = dE + aE * vl + cE * un;
+    sC[t] = cE * vn;
+    sR[t] = rE - aE * yl - cE * yn;
+    __syncthreads();
+    // parallel cyclic reduction over the K interface unknowns of each row
+    for (int st = 1; st < K; st <<= 1) {
+        const T a = sA[t], bb = sB[t], c = sC[t], r = sR[t];
+        T na = T(0), nb = bb, nc = T(0), nr = r;
+        if (k - st >= 0) {
+            const T al = -a / sB[t - st];
+            na = al * sA[t - st];
+            nb += al * sC[t - st];
+            nr += al * sR[t - st];
+        }
+        if (k + st < K) {
+            const T ga = -c / sB[t + st];
+            nc = ga * sC[t + st];
+            nb += ga * sA[t + st];
+            nr += ga * sR[t + st];
+        }
+        __syncthreads();
+        sA[t] = na;
+        sB[t] = nb;
+        sC[t] = nc;
+        sR[t] = nr;
+        __syncthreads();
+    }
+    const T X = sR[t] / sB[t];
+    __syncthreads();
+    sR[t] = X;
+    __syncthreads();
+    const T Xp = k > 0 ? sR[t - 1] : T(0);
+    double acc = 0.0;
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < kLineMaxL; ++q) {
+            if (q < L) {
+                const int g = s0 + q;
+                if (g < nx) {
+                    const T v = (q == L - 1) ? X : gy[q] + gu[q] * Xp + gv[q] * X;
+                    x[rbase + g] = v;
+                    if (DOT) acc += (double)b[rbase + g] * (double)v;
+                }
+            }
+        }
+    }
+    if (DOT) {
+        const double tot = block_sum(acc, sh);
+        if (DOT == 1) {
+            if (t == 0) part[blockIdx.x] = tot;
+        } else {
+            if (t == 0) part[nb_prev + blockIdx.x] = tot;
+            if (last_block(&sc->cnt[CNT_POST], gridDim.x)) {
+                const double rz = sum_partials(part, nb_prev + gridDim.x, 1, 0, sh);
+                if (t == 0) finish_rz(sc, rz);
+                reset_counter(&sc->cnt[CNT_POST]);
+            }
+        }
+    }
+}
+
+// Residual r = b - M x (flux form) on 64 x 16 tiles and restriction by 2x2 sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T* __restrict__ m,
+                                                        const T* __restrict__ We, const T* __restrict__ Wn,
+                                                        const T* __restrict__ b, const T* __restrict__ x,
+                                                        T* __restrict__ bc, int nxc, int nyc,
+                                                        const Scalars* __restrict__ sc) {
+    if (sc->done) return;
+    constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
+    __shared__ T sx[N], swe[N], swn[N];
+    __shared__ T sr[TRows][TBX];
+    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const size_t c = (size_t)j * nx + i;
+        sx[k] = in ? x[c] : T(0);
+        swe[k] = in ? We[c] : T(0);
+        swn[k] = in ? Wn[c] : T(0);
+    }
+    __syncthreads();
+    for (int r = 0; r < TRows / TBY; ++r) {
+        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
+        const int i = i0 + lx, j = j0 + ly;
+        const int k = (ly + H) * LX + lx + H;
+        T res = T(0);
+        if (i < nx && j < ny) {
+            const size_t c = (size_t)j * nx + i;
+            const T xv = sx[k];
+            res = b[c] - (m[c] * xv + swe[k] * (xv - sx[k + 1]) + swe[k - 1] * (xv - sx[k - 1]) +
+                          swn[k] * (xv - sx[k + LX]) + swn[k - LX] * (xv - sx[k - LX]));
+        }
+        sr[ly][lx] = res;
+    }
+    __syncthreads();
+    const int cx = t % (TBX / 2), cy = t / (TBX / 2);
+    const int I = blockIdx.x * (TBX / 2) + cx, J = blockIdx.y * (TRows / 2) + cy;
+    if (cy < TRows / 2 && I < nxc && J < nyc)
+        bc[(size_t)J * nxc + I] =
+            (sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) + (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+// ---------------------------------------------------------------------------
+
+// p = z + beta * pscale * p_in (p = z on the first iteration), q = M p in flux
+// form, partial p.q; the last workgroup sets alpha = r.z / p.q.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
+                                              T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
+                                              const T* __restrict__ We, const T* __restrict__ Wn, double* part,
+                                              Scalars* sc) {
+    if (sc->done) return;
+    constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
+    __shared__ T sp[N], swe[N], swn[N];
+    __shared__ double sh[16];
+    const bool first = sc->iter == 0;
+    const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
+    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const size_t c = (size_t)j * nx + i;
+        sp[k] = in ? (first ? z[c] : z[c] + beta * pin[c]) : T(0);
+        swe[k] = in ? We[c] : T(0);
+        swn[k] = in ? Wn[c] : T(0);
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int r = 0; r < TRows / TBY; ++r) {
+        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i >= nx || j >= ny) continue;
+        const int k = (ly + H) * LX + lx + H;
+        const size_t c = (size_t)j * nx + i;
+        const T pv = sp[k];
+        const T v = m[c] * pv + (swe[k] * (pv - sp[k + 1]) + swe[k - 1] * (pv - sp[k - 1]) +
+                                 swn[k] * (pv - sp[k + LX]) + swn[k - LX] * (pv - sp[k - LX]));
+        pout[c] = pv;
+        q[c] = v;
+        acc += (double)pv * (double)v;
+    }
+    const double tot = block_sum(acc, sh);
+    if (t == 0) part[bid2d()] = tot;
+    if (last_block(&sc->cnt[CNT_SPMV], nblocks2d())) {
+        const double pq = sum_partials(part, nblocks2d(), 1, 0, sh);
+        if (t == 0) {
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                sc->status = ST_EBREAKDOWN;
+                sc->done = 1;
+            } else {
+                sc->alpha = sc->rz_old / pq;
+            }
+            sc->pscale = 1.0;
+        }
+        reset_counter(&sc->cnt[CNT_SPMV]);
+    }
+}
+
+// x += alpha p, r -= alpha q, partial r.r; the last workgroup counts the
+// iteration and decides whether a reliable update (true FP64 residual) is due.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                const T* __restrict__ q, double* part, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const T a = (T)sc->alpha;
+    double acc = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        x[c] += a * p[c];
+        const T rn = r[c] - a * q[c];
+        r[c] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (last_block(&sc->cnt[CNT_UPDATE], gridDim.x)) {
+        const double rr = sum_partials(part, gridDim.x, 1, 0, sh);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->iter += 1;
+            bool check;
+            if (sc->reliable) {
+                // reliable update when the recurrence residual fell by delta since the
+                // last one, or when it predicts the target is met
+                const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
+                check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
+            } else {
+                check = rr <= sc->inner_tol2;
+            }
+            if (!isfinite(rr)) {
+                sc->status = ST_EBREAKDOWN;
+                check = true;
+            }
+            if (sc->iter >= sc->max_iter) check = true;
+            if (check) sc->pending = 1;
+        }
+        reset_counter(&sc->cnt[CNT_UPDATE]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 refinement
+// ---------------------------------------------------------------------------
+
+// E += (gamma / mu) x; x = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_correct(int n, double* __restrict__ E, T* __restrict__ x,
+                                                 const Scalars* __restrict__ sc, int force) {
+    if (!force && (sc->done || !sc->pending)) return;
+    const double g = sc->corr;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        E[c] += g * (double)x[c];
+        x[c] = T(0);
+    }
+}
+
+// True residual r = rhs - M E in flux form, rhs - m E - sum_f W (E - E_nb), and
+// the norms of the stop rule; the last workgroup decides convergence and the
+// new residual scale gamma = ||r||_2.
+__global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __restrict__ E, const double* __restrict__ We,
+                                                 const double* __restrict__ Wn, const double* __restrict__ m,
+                                                 const double* __restrict__ rhs, const double* __restrict__ s,
+                                                 const double* __restrict__ mu, double* __restrict__ r64, double* part,
+                                                 Scalars* sc, int force) {
+    if (!force && (sc->done || !sc->pending)) return;
+    const int nx = g.nx, ny = g.ny;
+    constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
+    constexpr int NS = 5;
+    __shared__ double sE[N], sWe[N], sWn[N];
+    __shared__ double sh[16];
+    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    for (int k = t; k < N; k += kThreads) {
+        const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
+        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const size_t c = (size_t)j * nx + i;
+        sE[k] = in ? E[c] : 0.0;
+        sWe[k] = in ? We[c] : 0.0;
+        sWn[k] = in ? Wn[c] : 0.0;
+    }
+    __syncthreads();
+    double a[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < TRows / TBY; ++r) {
+        const int ly = threadIdx.y + r * TBY, lx = threadIdx.x;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i >= nx || j >= ny) continue;
+        const int k = (ly + H) * LX + lx + H;
+        const size_t c = (size_t)j * nx + i;
+        const double e = sE[k];
+        double flux = sWe[k] * (e - sE[k + 1]);
+        flux += sWe[k - 1] * (e - sE[k - 1]);
+        flux += sWn[k] * (e - sE[k + LX]);
+        flux += sWn[k - LX] * (e - sE[k - LX]);
+        const double b = rhs[c];
+        const double res = b - m[c] * e - flux;
+        r64[c] = res;
+        const double dV = g.vx[i] * g.vy[j];
+        const double sv = s[c];
+        a[0] += (res / dV) * (res / dV);
+        a[1] += (sv * res) * (sv * res);
+        a[2] += (b / dV) * (b / dV);
+        a[3] += (sv * b) * (sv * b);
+        a[4] += res * res;
+    }
+    double tot[NS];
+    for (int q = 0; q < NS; ++q) tot[q] = block_sum(a[q], sh);
+    if (t == 0)
+        for (int q = 0; q < NS; ++q) part[(size_t)bid2d() * NS + q] = tot[q];
+    if (last_block(&sc->cnt[CNT_RESID], nblocks2d())) {
+        for (int q = 0; q < NS; ++q) tot[q] = sum_partials(part, nblocks2d(), NS, q, sh);
+        if (t == 0) {
+            for (int q = 0; q < 4; ++q) sc->sums[q] = tot[q];
+            const double rrow = tot[2] > 0.0 ? sqrt(tot[0] / tot[2]) : sqrt(tot[0]);
+            const double rsc = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
+            const double rel = sc->norm == 0 ? rrow : rsc;
+            sc->rel_row = rrow;
+            sc->rel_scaled = rsc;
+            sc->rel_sel = rel;
+            sc->nchecks += 1;
+            const double gnew = sqrt(tot[4]);
+            // stagnation: the residual no longer falls (the tolerance is below
+            // what binary64 resolves for this system)
+            if (rel < 0.9 * sc->best) {
+                sc->best = rel;
+                sc->stall = 0;
+            } else {
+                sc->stall += 1;
+            }
+            if (!isfinite(rel)) {
+                sc->status = ST_EBREAKDOWN;
+                sc->done = 1;
+            } else if (rel <= sc->eps || gnew == 0.0) {
+                sc->done = 1;
+            } else if (sc->status != ST_OK || sc->iter >= sc->max_iter || (!sc->reliable && sc->iter > 0) ||
+                       sc->stall >= 6) {
+                if (sc->status == ST_OK && sc->reliable) sc->status = ST_ENOCONV;
+                sc->done = 1;
+            } else {
+                const double ps = sc->gamma > 0.0 ? sc->gamma / gnew : 1.0;
+                sc->pscale = ps;
+                sc->rz_old *= ps * ps;
+                sc->gamma = gnew;
+                sc->corr = gnew / *mu;
+                sc->rho_last = rel;
+                sc->rr_ref = 1.0;
+            }
+        }
+        reset_counter(&sc->cnt[CNT_RESID]);
+    }
+}
+
+// r_inner = r / gamma in the inner precision (and x = 0); the last workgroup
+// clears the pending flag.
+template <typename T>
+__global__ __launch_bounds__(256) void k_demote(int n, const double* __restrict__ r64, T* __restrict__ r,
+                                                T* __restrict__ x, Scalars* sc, int force) {
+    if (!force && (sc->done || !sc->pending)) return;
+    if (sc->done) return;
+    const double ig = 1.0 / sc->gamma;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        r[c] = (T)(r64[c] * ig);
+        x[c] = T(0);
+    }
+    if (last_block(&sc->cnt[CNT_DEMOTE], gridDim.x)) {
+        if (threadIdx.x == 0) sc->pending = 0;
+        reset_counter(&sc->cnt[CNT_DEMOTE]);
+    }
+}
+
+__global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double inner_tol2, int max_iter, int norm,
+                               int reliable) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc->rz_old = 0.0;
+    sc->alpha = sc->beta = 0.0;
+    sc->pscale = 1.0;
+    sc->rr = 0.0;
+    sc->rr_ref = 1.0;
+    sc->gamma = 0.0;
+    sc->corr = 0.0;
+    sc->rho_last = 1.0;
+    for (int q = 0; q < 4; ++q) sc->sums[q] = 0.0;
+    sc->rel_row = sc->rel_scaled = sc->rel_sel = 0.0;
+    sc->eps = eps;
+    sc->delta2 = delta2;
+    sc->inner_tol2 = inner_tol2;
+    sc->iter = 0;
+    sc->done = 0;
+    sc->pending = 1;
+    sc->status = ST_OK;
+    sc->max_iter = max_iter;
+    sc->norm = norm;
+    sc->reliable = reliable;
+    sc->nchecks = 0;
+    sc->best = 1e300;
+    sc->stall = 0;
+}
+
+}  // namespace fld

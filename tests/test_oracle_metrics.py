@@ -81,3 +81,31 @@ def test_axis_faces_have_no_area():
     m = O.metrics(O.SPHERICAL, xf, yf)
     assert np.all(m.dSy[0, :] == 0.0)
     assert np.all(np.abs(m.dSy[-1, :]) < 1e-15 * m.dSy.max())
+
+
+def test_theta_centre_offset_high_precision():
+    # the volume-weighted mean angle of thin cells, at the poles and elsewhere,
+    # against 40-digit quadrature of its definition
+    import mpmath as mp
+    mp.mp.dps = 40
+    for a, h in [(0.0, 1e-4), (0.0, 6.1e-3), (1.3, 3e-3), (np.pi - 6.1e-3, 6.1e-3), (0.2, 0.29), (0.4, 0.7),
+                 (np.pi - 1e-3, 1e-3)]:
+        A, H = mp.mpf(a), mp.mpf(h)
+        num = mp.quad(lambda u: u * mp.sin(A + u), [0, H])
+        den = mp.quad(lambda u: mp.sin(A + u), [0, H])
+        want = float(num / den)
+        got = float(O.theta_centre_offset(np.array([a]), np.array([h]))[0])
+        assert got == pytest.approx(want, rel=2e-15), (a, h)
+
+
+def test_spherical_thin_shell_volumes_high_precision():
+    import mpmath as mp
+    mp.mp.dps = 40
+    xf = np.array([1e11, 1e11 * (1 + 3.37e-3)])
+    yf = np.array([0.0, np.pi / 2048, np.pi / 2])
+    m = O.metrics(O.SPHERICAL, xf, yf)
+    r0, r1 = mp.mpf(xf[0]), mp.mpf(xf[1])
+    for j in range(2):
+        t0, t1 = mp.mpf(yf[j]), mp.mpf(yf[j + 1])
+        want = float((r1 ** 3 - r0 ** 3) / 3 * (mp.cos(t0) - mp.cos(t1)))
+        assert m.dV[j, 0] == pytest.approx(want, rel=1e-15)

@@ -199,6 +199,20 @@ fld_status fld_get_operator(fld_ctx* ctx, double* W_e, double* W_n, double* diag
 /* Number of multigrid levels built by the last fld_assemble (fine included). */
 int32_t fld_mg_levels(const fld_ctx* ctx);
 
+/* Measurement of the dominant kernel family (the multigrid line-sweep
+ * kernels).  While enabled, every such launch is bracketed by HIP events on
+ * the context's stream (CG chunks then run as plain launches, not graphs).
+ * fld_profile_read synchronises, and returns the number of timed launches that
+ * did work (launches that exited early after convergence are excluded), their
+ * summed duration in ms, and their summed algorithmic bytes (compulsory reads
+ * and writes of each launch).  Enabling resets the totals. */
+fld_status fld_profile(fld_ctx* ctx, int32_t enable);
+fld_status fld_profile_read(fld_ctx* ctx, int64_t* launches, double* total_ms, double* bytes);
+/* Mean elapsed time (us) of the same event pair around an empty one-wave
+ * kernel on the context's stream, over `reps` launches: the timing cost that
+ * every event-bracketed launch above carries. */
+fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launch);
+
 const char* fld_status_string(fld_status s);
 const char* fld_last_error(const fld_ctx* ctx);
 const char* fld_version(void);

@@ -75,6 +75,10 @@ _SIGS = {
     "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
     "fld_mg_levels": (_I, [_P]),
+    "fld_profile": (_I, [_P, _I]),
+    "fld_profile_overhead": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
+    "fld_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)]),
     "fld_status_string": (ctypes.c_char_p, [_I]),
     "fld_last_error": (ctypes.c_char_p, [_P]),
     "fld_version": (ctypes.c_char_p, []),
@@ -186,6 +190,21 @@ class Context:
         out = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(4)]
         self._check(lib.fld_get_operator(self.handle, *[_ptr(t) for t in out]))
         return dict(zip(("W_e", "W_n", "diag", "rhs"), out))
+
+    def profile(self, enable: bool = True):
+        self._check(lib.fld_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        self._check(lib.fld_profile_read(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+    def profile_overhead(self, reps: int = 200) -> float:
+        us = ctypes.c_double()
+        self._check(lib.fld_profile_overhead(self.handle, int(reps), ctypes.byref(us)))
+        return us.value
 
     @property
     def mg_levels(self) -> int:

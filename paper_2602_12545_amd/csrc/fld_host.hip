@@ -63,7 +63,11 @@ struct Inner {
     std::vector<LevelT<T>> lv;
     T* Ainv = nullptr;
     T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
-    hipGraphExec_t chunk_exec = nullptr;
+    int sub_first = -1;                   // first level of the one-workgroup coarse sub-cycle (-1: none)
+    SubCycle<T> sub{};
+    size_t sub_lds = 0;
+    hipGraphExec_t chunk_exec = nullptr;  // captured chunk of CG iterations
+    double* chunk_E = nullptr;            // solution pointer the chunk was captured for
     int chunk_len = 0;
 };
 
@@ -96,6 +100,17 @@ struct fld_ctx {
     double dt = 0.0;
     Inner<float> i32;
     Inner<double> i64;
+    // measurement of the line-sweep kernels: HIP events around every launch
+    struct Prof {
+        bool on = false;
+        std::vector<hipEvent_t> ev;    // start/stop pairs, one per recorded launch
+        std::vector<double> bytes;     // algorithmic bytes of that launch
+        int* ran = nullptr;            // device flags: launch did work
+        int* hran = nullptr;           // pinned copy
+        int slots = 0, used = 0;       // capacity / slots used since the last harvest
+        int64_t launches = 0;
+        double ms = 0.0, total_bytes = 0.0;
+    } prof;
 
     template <typename U>
     hipError_t alloc(U** p, size_t n) {
@@ -146,10 +161,10 @@ fld_status validate_options(const fld_options* o, std::string& err) {
 // V-cycle and CG slot (queued on stream `st`)
 // ---------------------------------------------------------------------------
 
-// Chunking of a row of n cells for k_line: K chunks (power of two, <= 256) of
-// L cells (2 <= L <= 16).
+// Chunking of a row of n cells for k_line: K chunks (power of two, <= 512) of
+// L cells (2 <= L <= 8).
 inline void line_params(int n, int& K, int& L) {
-    int want = (n + 7) / 8;
+    int want = (n + kLineMaxL - 1) / kLineMaxL;
     K = 1;
     while (K < want && K < kLineWG) K <<= 1;
     L = (n + K - 1) / K;
@@ -165,9 +180,41 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
     line_params(v.nx, K, L);
     const int lpw = kLineWG / K;
     const int grid = (nl + lpw - 1) / lpw;
+    auto& P = c->prof;
+    int slot = -1;
+    if (P.on && P.used < P.slots) {
+        slot = P.used++;
+        // algorithmic bytes: solved rows read m, W_e, b and write x; W_n of every
+        // row; x of the neighbour rows unless zero; the coarse correction (1/4)
+        const double n = (double)v.nx * v.ny, half = (double)nl * v.nx;
+        double words = 4.0 * half + n;
+        if (MODE != LINE_ZERO) words += n - half;
+        if (MODE == LINE_PROLONG) words += 0.25 * n;
+        P.bytes[slot] = words * sizeof(T);
+        (void)hipEventRecord(P.ev[2 * slot], st);
+    }
     k_line<T, MODE, DOT><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc, T(1),
-                                                    c->part, nb_prev, c->sc);
+                                                    c->part, nb_prev, c->sc, slot >= 0 ? P.ran + slot : nullptr);
+    if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
+}
+
+// Adds the timed launches that did work to the totals (stream synchronised).
+fld_status prof_harvest(fld_ctx* ctx) {
+    auto& P = ctx->prof;
+    if (!P.on || P.used == 0) return FLD_OK;
+    HIPCHK(hipMemcpy(P.hran, P.ran, sizeof(int) * P.used, hipMemcpyDeviceToHost));
+    for (int k = 0; k < P.used; ++k) {
+        if (!P.hran[k]) continue;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P.ev[2 * k], P.ev[2 * k + 1]));
+        P.ms += ms;
+        P.total_bytes += P.bytes[k];
+        P.launches += 1;
+    }
+    HIPCHK(hipMemset(P.ran, 0, sizeof(int) * P.used));
+    P.used = 0;
+    return FLD_OK;
 }
 
 template <typename T>
@@ -182,7 +229,8 @@ void launch_transpose(int nx, int ny, const T* s0, const T* s1, T* d0, T* d1, co
 template <typename T>
 void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const int L = (int)in.lv.size();
-    for (int l = 0; l < L - 1; ++l) {
+    const int Ld = in.sub_first > 0 ? in.sub_first : L - 1;  // grid levels smoothed with launches
+    for (int l = 0; l < Ld; ++l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -195,9 +243,14 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ, a.xQ,
                                                                           nxt.bP, cv.nx, cv.ny, c->sc);
     }
-    LevelT<T>& cl = in.lv[L - 1];
-    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
-    for (int l = L - 2; l >= 0; --l) {
+    if (in.sub_first > 0) {
+        LevelT<T>& f = in.lv[in.sub_first];
+        k_subcycle<T><<<1, kSubThreads, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
+    } else {
+        LevelT<T>& cl = in.lv[L - 1];
+        k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+    }
+    for (int l = Ld - 1; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -206,8 +259,10 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
         launch_transpose<T>(vq.nx, vq.ny, a.xQ, nullptr, a.xP, nullptr, c->sc, st);
         if (l == 0) {
+            // the last two sweeps of level 0 also accumulate r.z for CG
             const int nb1 = launch_line<T, LINE_NORMAL, 1>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
-            launch_line<T, LINE_NORMAL, 2>(c, vp, 0, a.bP, a.xP, nullptr, 0, nb1, st);
+            const int nb2 = launch_line<T, LINE_NORMAL, 1>(c, vp, 0, a.bP, a.xP, nullptr, 0, nb1, st);
+            k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, nb1 + nb2, c->sc);
         } else {
             launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
             launch_line<T, LINE_NORMAL, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
@@ -230,10 +285,12 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     for (int l = L - 2; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
-        if (l == 0)
-            k_post_point<T, true><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ,
-                                                                             b.xP, b.nx, omega, a.xP, c->part, c->sc);
-        else
+        if (l == 0) {
+            const dim3 g = tile_grid(a.nx, a.ny);
+            k_post_point<T, true><<<g, blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ, b.xP, b.nx, omega,
+                                                         a.xP, c->part, c->sc);
+            k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, (int)(g.x * g.y), c->sc);
+        } else
             k_post_point<T, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ,
                                                                               b.xP, b.nx, omega, a.xP, c->part, c->sc);
     }
@@ -250,19 +307,33 @@ void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     else enqueue_vcycle_point<T>(c, in, st);
 }
 
+// Reliable update (only acts when the device flag `pending` is set, or when
+// forced at the start of a solve): E += corr x, true FP64 residual, its norms
+// and the convergence decision, then the re-scaled inner residual.
+template <typename T>
+void enqueue_check(fld_ctx* c, Inner<T>& in, double* E, int force, hipStream_t st) {
+    const int nx = c->nx, ny = c->ny, n = nx * ny;
+    const dim3 tg = tile_grid(nx, ny);
+    if (!force) k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, c->sc, 0);
+    k_resid64<<<tg, blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part, c->sc, force);
+    k_reduce_resid<<<1, kRedThreads, 0, st>>>(c->part, (int)(tg.x * tg.y), c->mu, c->sc, force);
+    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, in.r, in.x, c->sc);
+}
+
 // One CG iteration ("slot"); `par` selects the p buffer pair (iterations
 // alternate between the two).  E is the FP64 solution being refined.
 template <typename T>
 void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) {
     const int nx = c->nx, ny = c->ny, n = nx * ny;
     LevelT<T>& l0 = in.lv[0];
-    k_spmv<T><<<tile_grid(nx, ny), blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn,
-                                                     c->part, c->sc);
-    k_update<T><<<grid1d(n), 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, c->sc);
-    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, c->sc, 0);
-    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->mu, c->r64,
-                                                     c->part, c->sc, 0);
-    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, in.r, in.x, c->sc, 0);
+    const dim3 tg = tile_grid(nx, ny);
+    const int ntiles = (int)(tg.x * tg.y), nb1 = grid1d(n);
+    k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part,
+                                      c->sc);
+    k_reduce_pq<<<1, kRedThreads, 0, st>>>(c->part, ntiles, c->sc);
+    k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, c->sc);
+    k_reduce_rr<<<1, kRedThreads, 0, st>>>(c->part, nb1, c->sc);
+    enqueue_check<T>(c, in, E, 0, st);
     enqueue_vcycle<T>(c, in, st);
 }
 
@@ -332,6 +403,46 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(ctx->alloc(&in.p[1], n));
     HIPCHK(ctx->alloc(&in.q, n));
     in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual
+    // one-workgroup coarse sub-cycle: the finest level l >= 1 from which all
+    // coarser levels fit in LDS (5 arrays each, plus one Thomas scratch)
+    const int L = (int)in.lv.size();
+    in.sub_first = -1;
+    if (line && L >= 3) {
+        int dev = 0, lds_max = 65536;
+        HIPCHK(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            lds_max = 65536;
+        for (int l = 1; l < L - 1 && in.sub_first < 0; ++l) {
+            if (L - l > kSubMaxLevels) continue;
+            // PCR scratch: 4 arrays over the unknowns of one parity (<= (n + line) / 2)
+            const size_t n0 = (size_t)in.lv[l].nx * in.lv[l].ny;
+            const size_t half = (n0 + std::max(in.lv[l].nx, in.lv[l].ny) + 1) / 2;
+            if (half > (size_t)kSubThreads * kSubPerThread) continue;
+            size_t need = 4 * half;
+            for (int k = l; k < L; ++k) need += 5 * (size_t)(in.lv[k].nx + 1) * in.lv[k].ny;
+            need *= sizeof(T);
+            if (need <= (size_t)lds_max) {
+                in.sub_first = l;
+                in.sub_lds = need;
+            }
+        }
+        if (in.sub_first > 0) {
+            SubCycle<T>& S = in.sub;
+            S.nlev = L - in.sub_first;
+            int off = 0;
+            for (int k = 0; k < S.nlev; ++k) {
+                const LevelT<T>& lv = in.lv[in.sub_first + k];
+                const int pitch = lv.nx + 1;
+                S.lv[k] = SubLevel<T>{lv.nx, lv.ny, lv.m, lv.We, lv.Wn, off, lv.tr ? 1 : 0, pitch, pitch * lv.ny};
+                off += 5 * pitch * lv.ny;
+            }
+            S.scratch = off;
+            S.Ainv = in.Ainv;
+            if (in.sub_lds > 65536)
+                HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)in.sub_lds));
+        }
+    }
     HIPCHK(hipMemset(in.r, 0, sizeof(T) * n));
     HIPCHK(hipMemset(in.x, 0, sizeof(T) * n));
     HIPCHK(hipMemset(in.p[0], 0, sizeof(T) * n));
@@ -352,6 +463,37 @@ void fill_info(fld_ctx* c, fld_solve_info* info, int status, float ms) {
     info->ms = ms;
 }
 
+// Captures `chunk` CG iterations (an even number, so the p buffers line up)
+// into a hipGraph on a private stream; re-captured only when the solution
+// pointer changes.  The graph holds kernel nodes only.
+template <typename T>
+fld_status capture_chunk(fld_ctx* ctx, Inner<T>& in, double* E, int chunk) {
+    if (in.chunk_exec && in.chunk_E == E && in.chunk_len == chunk) return FLD_OK;
+    if (in.chunk_exec) {
+        HIPCHK(hipGraphExecDestroy(in.chunk_exec));
+        in.chunk_exec = nullptr;
+    }
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, k & 1, E, ctx->cap_stream);
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (e != hipSuccess) {
+        ctx->err = std::string("graph capture: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    e = hipGraphInstantiate(&in.chunk_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        in.chunk_exec = nullptr;
+        ctx->err = std::string("graph instantiate: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    in.chunk_E = E;
+    in.chunk_len = chunk;
+    return FLD_OK;
+}
+
 template <typename T>
 fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     auto t0 = std::chrono::steady_clock::now();
@@ -366,9 +508,7 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, max_iter, o.norm,
                                     fp32only ? 0 : 1);
     // prologue: true residual of the initial guess, inner residual, first V-cycle
-    k_resid64<<<tile_grid(nx, ny), blk2d(), 0, st>>>(ctx->met, E, ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->mu,
-                                                     ctx->r64, ctx->part, ctx->sc, 1);
-    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, ctx->r64, in.r, in.x, ctx->sc, 1);
+    enqueue_check<T>(ctx, in, E, 1, st);
     enqueue_vcycle<T>(ctx, in, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -380,13 +520,26 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
         return FLD_ENONFINITE;
     }
     const int chunk = o.chunk;
+    // events recorded inside a captured graph cannot be timed on this runtime,
+    // so measured solves queue plain launches
+    const bool graph = o.use_graph != 0 && !ctx->prof.on;
+    if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
+    if (graph) {
+        fld_status gs = capture_chunk<T>(ctx, in, E, chunk);
+        if (gs != FLD_OK) return gs;
+    }
     int launched = 0;
     while (!ctx->hsc->done && launched < max_iter + chunk) {
-        for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, (launched + k) & 1, E, st);
+        if (graph) {
+            HIPCHK(hipGraphLaunch(in.chunk_exec, st));
+        } else {
+            for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, (launched + k) & 1, E, st);
+        }
         launched += chunk;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
     }
     k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
     HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -448,6 +601,59 @@ const char* fld_last_error(const fld_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int32_t fld_mg_levels(const fld_ctx* ctx) { return ctx ? (int32_t)ctx->h64.size() : 0; }
 
+fld_status fld_profile(fld_ctx* ctx, int32_t enable) {
+    if (!ctx) return FLD_EINVAL;
+    auto& P = ctx->prof;
+    if (enable && P.slots == 0) {
+        // one chunk of iterations plus the first V-cycle of a solve
+        const int per_vcycle = 8 * (int)ctx->h64.size() + 8;
+        P.slots = per_vcycle * (ctx->opt.chunk + 1);
+        P.ev.resize(2 * P.slots);
+        for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
+        P.bytes.assign(P.slots, 0.0);
+        HIPCHK(ctx->alloc(&P.ran, (size_t)P.slots));
+        HIPCHK(hipMemset(P.ran, 0, sizeof(int) * P.slots));
+        HIPCHK(hipHostMalloc((void**)&P.hran, sizeof(int) * P.slots, hipHostMallocDefault));
+    }
+    P.on = enable != 0;
+    P.used = 0;
+    P.launches = 0;
+    P.ms = 0.0;
+    P.total_bytes = 0.0;
+    return FLD_OK;
+}
+
+fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launch) {
+    if (!ctx || reps < 1 || !us_per_launch) return FLD_EINVAL;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    double tot = 0.0;
+    for (int k = 0; k < reps; ++k) {
+        HIPCHK(hipEventRecord(a, ctx->stream));
+        k_noop<<<1, 64, 0, ctx->stream>>>(nullptr);
+        HIPCHK(hipEventRecord(b, ctx->stream));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        tot += ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *us_per_launch = 1e3 * tot / reps;
+    return FLD_OK;
+}
+
+fld_status fld_profile_read(fld_ctx* ctx, int64_t* launches, double* total_ms, double* bytes) {
+    if (!ctx) return FLD_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
+    if (launches) *launches = ctx->prof.launches;
+    if (total_ms) *total_ms = ctx->prof.ms;
+    if (bytes) *bytes = ctx->prof.total_bytes;
+    return FLD_OK;
+}
+
 void fld_destroy(fld_ctx* ctx) {
     if (!ctx) return;
     // errors are ignored here: the context is being torn down either way
@@ -458,6 +664,8 @@ void fld_destroy(fld_ctx* ctx) {
     if (ctx->hsc) (void)hipHostFree(ctx->hsc);
     if (ctx->herr) (void)hipHostFree(ctx->herr);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto& e : ctx->prof.ev) (void)hipEventDestroy(e);
+    if (ctx->prof.hran) (void)hipHostFree(ctx->prof.hran);
     delete ctx;
 }
 
@@ -580,8 +788,10 @@ fld_status fld_assemble(fld_ctx* ctx, const double* E, const double* T, const do
     hipStream_t st = ctx->stream;
     HIPCHK(hipMemsetAsync(ctx->err_flag, 0, sizeof(int), st));
     AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
-    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part, ctx->mu, &ctx->sc->cnt[CNT_ASM]};
-    k_assemble<<<cell_grid(ctx->nx, ctx->ny), blk2d(), 0, st>>>(ctx->met, in, out);
+    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part};
+    const dim3 ag = cell_grid(ctx->nx, ctx->ny);
+    k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
+    k_reduce_max<<<1, kRedThreads, 0, st>>>(ctx->part, (int)(ag.x * ag.y), ctx->mu);
     HIPCHK(hipGetLastError());
     fld_status s = inner_is_float(ctx) ? build_hierarchy<float>(ctx) : build_hierarchy<double>(ctx);
     if (s != FLD_OK) return s;

@@ -54,11 +54,10 @@ struct Scalars {
     double inner_tol2;  // FP32-only: stop when rr <= inner_tol2
     int iter, done, pending, status;
     int max_iter, norm, reliable, nchecks;
-    int stall, pad2;    // true-residual checks without progress
-    unsigned cnt[8];    // last-block counters, one per reduction kernel kind
+    int stall;          // true-residual checks without progress
+    int restart;        // next p-update starts a new search direction
+    int demote;         // a new true residual waits to be demoted
 };
-
-enum { CNT_SPMV = 0, CNT_UPDATE = 1, CNT_RESID = 2, CNT_POST = 3, CNT_DEMOTE = 4, CNT_ASM = 5 };
 
 enum {
     ST_OK = 0, ST_ENOCONV = 4, ST_EBREAKDOWN = 5, ST_ENONFINITE = 6

@@ -48,37 +48,6 @@ __device__ inline double block_max(double v, double* sh) {
     return r;
 }
 
-__device__ inline double load_agent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publishes this workgroup's partial(s) and returns true (in every thread)
-// for the workgroup that finished last.
-__device__ inline bool last_block(unsigned* cnt, unsigned nblocks) {
-    __shared__ int is_last;
-    __syncthreads();
-    if (ltid() == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(cnt, 1u);
-        is_last = (prev == nblocks - 1u);
-    }
-    __syncthreads();
-    const bool last = is_last != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-__device__ inline void reset_counter(unsigned* cnt) {
-    if (ltid() == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Fixed-order sum of partials part[b * stride + k], b < nb.
-__device__ inline double sum_partials(const double* part, int nb, int stride, int k, double* sh) {
-    double v = 0.0;
-    for (int b = ltid(); b < nb; b += lsize()) v += load_agent(&part[(size_t)b * stride + k]);
-    return block_sum(v, sh);
-}
-
 __device__ inline unsigned nblocks2d() { return gridDim.x * gridDim.y; }
 __device__ inline unsigned bid2d() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
@@ -229,9 +198,7 @@ struct AsmIn {
 struct AsmOut {
     double *We, *Wn, *m, *rhs, *s;
     int* err;
-    double* part;   // per-workgroup partial maxima of the diagonal
-    double* mu;     // global maximum of the diagonal (inner-precision normalisation)
-    unsigned* cnt;  // last-block counter
+    double* part;   // per-workgroup partial maxima of the diagonal (k_reduce_max)
 };
 
 // Assembly of one cell; returns its diagonal.
@@ -309,13 +276,6 @@ __global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut ou
     const double diag = (i < nx && j < ny) ? assemble_cell(g, in, out, i, j) : 0.0;
     const double bm = block_max(diag, sh);
     if (ltid() == 0) out.part[bid2d()] = bm;
-    if (last_block(out.cnt, nblocks2d())) {
-        double v = 0.0;
-        for (int b = ltid(); b < (int)nblocks2d(); b += lsize()) v = fmax(v, load_agent(&out.part[b]));
-        const double mx = block_max(v, sh);
-        if (ltid() == 0) *out.mu = mx;
-        reset_counter(out.cnt);
-    }
 }
 
 // Full diagonal and copies of the FP64 operator (test access).

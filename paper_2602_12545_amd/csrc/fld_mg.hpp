@@ -20,6 +20,8 @@
 // transposed once per assembly, vectors transposed between the two sweeps),
 // so every load stays coalesced.
 #pragma once
+#include <type_traits>
+
 #include "fld_kernels.hpp"
 
 namespace fld {
@@ -325,11 +327,6 @@ __global__ __launch_bounds__(256) void k_post_point(int nx, int ny, const T* __r
     if (DOT) {
         const double tot = block_sum(acc, sh);
         if (t == 0) part[bid2d()] = tot;
-        if (last_block(&sc->cnt[CNT_POST], nblocks2d())) {
-            const double rz = sum_partials(part, nblocks2d(), 1, 0, sh);
-            if (t == 0) finish_rz(sc, rz);
-            reset_counter(&sc->cnt[CNT_POST]);
-        }
     }
 }
 
@@ -337,8 +334,48 @@ __global__ __launch_bounds__(256) void k_post_point(int nx, int ny, const T* __r
 // line smoother (zebra line Gauss-Seidel along rows)
 // ---------------------------------------------------------------------------
 
-constexpr int kLineMaxL = 16;   // cells per thread chunk
-constexpr int kLineWG = 256;    // threads per workgroup; lines of K chunks, 256/K lines per workgroup
+constexpr int kLineMaxL = 8;    // cells per thread chunk
+
+// N consecutive values from a 16-byte aligned address with 16-byte loads.
+template <typename T, int N>
+__device__ inline void load_vec(const T* __restrict__ p, T (&v)[N]) {
+    constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const V* q = reinterpret_cast<const V*>(p);
+#pragma unroll
+    for (int k = 0; k < N / VW; ++k) {
+        const V w = q[k];
+        if constexpr (sizeof(T) == 4) {
+            v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
+        } else {
+            v[2 * k] = w.x; v[2 * k + 1] = w.y;
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ inline void store_vec(T* __restrict__ p, const T (&v)[N]) {
+    constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    V* q = reinterpret_cast<V*>(p);
+#pragma unroll
+    for (int k = 0; k < N / VW; ++k) {
+        V w;
+        if constexpr (sizeof(T) == 4) {
+            w.x = v[4 * k]; w.y = v[4 * k + 1]; w.z = v[4 * k + 2]; w.w = v[4 * k + 3];
+        } else {
+            w.x = v[2 * k]; w.y = v[2 * k + 1];
+        }
+        q[k] = w;
+    }
+}
+
+template <typename T, int N>
+__device__ inline void fill(T (&v)[N], T a) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = a;
+}
+constexpr int kLineWG = 512;    // threads per workgroup; lines of K chunks, 512/K lines per workgroup
 enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 
 // One zebra half-sweep: for every row j with j % 2 == par solve exactly
@@ -353,14 +390,16 @@ enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 // unknowns X_{k-1}, X_k of the previous and of its own chunk; substituting the
 // neighbour chunk's first row gives one tridiagonal equation per chunk in the
 // X's, solved by parallel cyclic reduction in LDS; back-substitution finishes.
-// DOT = 1: partial r.z over the solved rows, stored; DOT = 2: the same, plus
-// the last workgroup sums these and the DOT = 1 kernel's partials (level 0).
+// DOT: partial r.z over the solved rows, stored at part[nb_prev + block]
+// (level 0; k_reduce_rz finishes the sum).
 template <typename T, int MODE, int DOT>
-__global__ __launch_bounds__(256) void k_line(int nx, int ny, int K, int L, int par, const T* __restrict__ m,
-                                              const T* __restrict__ We, const T* __restrict__ Wn,
-                                              const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ ec,
-                                              int nxc, T omega, double* part, int nb_prev, Scalars* sc) {
+__global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, int par, const T* __restrict__ m,
+                                                  const T* __restrict__ We, const T* __restrict__ Wn,
+                                                  const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ ec,
+                                                  int nxc, T omega, double* part, int nb_prev, Scalars* sc,
+                                                  int* ran) {
     if (sc->done) return;
+    if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;  // measurement: this launch did work
     __shared__ T sA[kLineWG], sB[kLineWG], sC[kLineWG], sR[kLineWG];
     __shared__ T sy0[kLineWG], su0[kLineWG], sv0[kLineWG];
     __shared__ double sh[16];
@@ -377,47 +416,79 @@ __global__ __launch_bounds__(256) void k_line(int nx, int ny, int K, int L, int 
         if (MODE == LINE_PROLONG) return x[c] + omega * ec[(size_t)(rr >> 1) * nxc + (g >> 1)];
         return x[c];
     };
-    // coefficients of cell g of this row: a = -W_w, d, c = -W_e, r
-    auto coef = [&](int g, T& a, T& d, T& c, T& r) {
-        if (!active || g >= nx) {
-            a = T(0); d = T(1); c = T(0); r = T(0);
-            return;
+    // all loads of the chunk first (one memory round trip); cells past the row
+    // end become identity rows (d = 1, no couplings, r = 0)
+    constexpr int LM = kLineMaxL;
+    T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM], vxn[LM], vxs[LM];
+    const T wwest = (active && s0 > 0 && s0 - 1 < nx) ? We[rbase + s0 - 1] : T(0);
+    // full, 16-byte aligned chunk: vector loads (4 x 16 B lanes per wave line)
+    constexpr int VW = 16 / sizeof(T);
+    const bool vec = active && L == LM && s0 + LM <= nx && ((rbase + s0) % VW) == 0 && (nx % VW) == 0;
+    if (vec) {
+        const size_t c0 = rbase + s0;
+        load_vec<T, LM>(m + c0, vm);
+        load_vec<T, LM>(We + c0, vwe);
+        load_vec<T, LM>(Wn + c0, vwn);
+        load_vec<T, LM>(b + c0, vb);
+        if (row > 0) load_vec<T, LM>(Wn + c0 - nx, vws);
+        else fill<T, LM>(vws, T(0));
+        if (MODE != LINE_ZERO && row + 1 < ny) load_vec<T, LM>(x + c0 + nx, vxn);
+        else fill<T, LM>(vxn, T(0));
+        if (MODE != LINE_ZERO && row > 0) load_vec<T, LM>(x + c0 - nx, vxs);
+        else fill<T, LM>(vxs, T(0));
+        if (MODE == LINE_PROLONG) {
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                const int g = s0 + q;
+                if (row + 1 < ny) vxn[q] += omega * ec[(size_t)((row + 1) >> 1) * nxc + (g >> 1)];
+                if (row > 0) vxs[q] += omega * ec[(size_t)((row - 1) >> 1) * nxc + (g >> 1)];
+            }
         }
-        const size_t cc = rbase + g;
-        const T we = We[cc];
-        const T ww = g > 0 ? We[cc - 1] : T(0);
-        const T wn = Wn[cc];
-        const T ws = row > 0 ? Wn[cc - nx] : T(0);
-        d = m[cc] + ((ww + we) + (ws + wn));
+    } else {
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
+            const int g = s0 + q;
+            const bool ok = active && q < L && g < nx;
+            const size_t cc = rbase + g;
+            vm[q] = ok ? m[cc] : T(1);
+            vwe[q] = ok ? We[cc] : T(0);
+            vwn[q] = ok ? Wn[cc] : T(0);
+            vws[q] = (ok && row > 0) ? Wn[cc - nx] : T(0);
+            vb[q] = ok ? b[cc] : T(0);
+            vxn[q] = (MODE != LINE_ZERO && ok && row + 1 < ny) ? xnb(row + 1, g) : T(0);
+            vxs[q] = (MODE != LINE_ZERO && ok && row > 0) ? xnb(row - 1, g) : T(0);
+        }
+    }
+    // keep every load above this point: one round trip instead of a chain
+    __builtin_amdgcn_sched_barrier(0);
+    // coefficients of chunk cell q: a = -W_w, d, c = -W_e, r
+    auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+        const T ww = (q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0];
+        d = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
         a = -ww;
-        c = -we;
-        T rr = b[cc];
-        if (MODE != LINE_ZERO) {
-            if (row + 1 < ny) rr += wn * xnb(row + 1, g);
-            if (row > 0) rr += ws * xnb(row - 1, g);
-        }
-        r = rr;
+        c = -vwe[q];
+        r = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
     };
 
     // forward elimination of the chunk interior (local 0 .. L-2)
-    T cp[kLineMaxL], gy[kLineMaxL], gu[kLineMaxL], gv[kLineMaxL];
+    T cp[LM], gy[LM], gu[LM], gv[LM];
 #pragma unroll
-    for (int q = 0; q < kLineMaxL - 1; ++q) {
+    for (int q = 0; q < LM - 1; ++q) {
         if (q < L - 1) {
             T a, d, c, r;
-            coef(s0 + q, a, d, c, r);
-            const T den = (q == 0) ? d : d - a * cp[q - 1];
+            coef(q, a, d, c, r);
+            const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
             const T inv = T(1) / den;
             cp[q] = c * inv;
-            gy[q] = ((q == 0) ? r : r - a * gy[q - 1]) * inv;
-            gu[q] = ((q == 0) ? -a : -a * gu[q - 1]) * inv;
+            gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
+            gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
             const T rv = (q == L - 2) ? -c : T(0);
-            gv[q] = ((q == 0) ? rv : rv - a * gv[q - 1]) * inv;
+            gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
         }
     }
     // back substitution: y, u, v overwrite gy, gu, gv
 #pragma unroll
-    for (int q = kLineMaxL - 3; q >= 0; --q) {
+    for (int q = LM - 3; q >= 0; --q) {
         if (q < L - 2) {
             gy[q] -= cp[q] * gy[q + 1];
             gu[q] -= cp[q] * gu[q + 1];
@@ -425,11 +496,13 @@ __global__ __launch_bounds__(256) void k_line(int nx, int ny, int K, int L, int 
         }
     }
     // interface cell of the chunk (local L-1)
-    T aE, dE, cE, rE;
-    coef(s0 + L - 1, aE, dE, cE, rE);
+    T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
+#pragma unroll
+    for (int q = 0; q < LM; ++q)
+        if (q == L - 1) coef(q, aE, dE, cE, rE);
     T yl = T(0), ul = T(0), vl = T(0);
 #pragma unroll
-    for (int q = 0; q < kLineMaxL - 1; ++q)
+    for (int q = 0; q < LM - 1; ++q)
         if (q == L - 2) {
             yl = gy[q];
             ul = gu[q];
@@ -476,30 +549,24 @@ __global__ __launch_bounds__(256) void k_line(int nx, int ny, int K, int L, int 
     const T Xp = k > 0 ? sR[t - 1] : T(0);
     double acc = 0.0;
     if (active) {
+        T out[LM];
 #pragma unroll
-        for (int q = 0; q < kLineMaxL; ++q) {
-            if (q < L) {
-                const int g = s0 + q;
-                if (g < nx) {
-                    const T v = (q == L - 1) ? X : gy[q] + gu[q] * Xp + gv[q] * X;
-                    x[rbase + g] = v;
-                    if (DOT) acc += (double)b[rbase + g] * (double)v;
-                }
-            }
+        for (int q = 0; q < LM; ++q) {
+            out[q] = (q == L - 1) ? X : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                            gv[q < LM - 1 ? q : 0] * X;
+            if (DOT && q < L && s0 + q < nx) acc += (double)vb[q] * (double)out[q];
+        }
+        if (vec) {
+            store_vec<T, LM>(x + rbase + s0, out);
+        } else {
+#pragma unroll
+            for (int q = 0; q < LM; ++q)
+                if (q < L && s0 + q < nx) x[rbase + s0 + q] = out[q];
         }
     }
     if (DOT) {
         const double tot = block_sum(acc, sh);
-        if (DOT == 1) {
-            if (t == 0) part[blockIdx.x] = tot;
-        } else {
-            if (t == 0) part[nb_prev + blockIdx.x] = tot;
-            if (last_block(&sc->cnt[CNT_POST], gridDim.x)) {
-                const double rz = sum_partials(part, nb_prev + gridDim.x, 1, 0, sh);
-                if (t == 0) finish_rz(sc, rz);
-                reset_counter(&sc->cnt[CNT_POST]);
-            }
-        }
+        if (t == 0) part[nb_prev + blockIdx.x] = tot;
     }
 }
 
@@ -549,8 +616,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
 // CG kernels
 // ---------------------------------------------------------------------------
 
-// p = z + beta * pscale * p_in (p = z on the first iteration), q = M p in flux
-// form, partial p.q; the last workgroup sets alpha = r.z / p.q.
+// p = z + beta * pscale * p_in (p = z on the first iteration or after a
+// restart), q = M p in flux form, partial p.q per workgroup (k_reduce_pq).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
                                               T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
@@ -560,7 +627,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
     __shared__ T sp[N], swe[N], swn[N];
     __shared__ double sh[16];
-    const bool first = sc->iter == 0;
+    const bool first = sc->iter == 0 || sc->restart;
     const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
     const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
     for (int k = t; k < N; k += kThreads) {
@@ -588,23 +655,9 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     }
     const double tot = block_sum(acc, sh);
     if (t == 0) part[bid2d()] = tot;
-    if (last_block(&sc->cnt[CNT_SPMV], nblocks2d())) {
-        const double pq = sum_partials(part, nblocks2d(), 1, 0, sh);
-        if (t == 0) {
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                sc->status = ST_EBREAKDOWN;
-                sc->done = 1;
-            } else {
-                sc->alpha = sc->rz_old / pq;
-            }
-            sc->pscale = 1.0;
-        }
-        reset_counter(&sc->cnt[CNT_SPMV]);
-    }
 }
 
-// x += alpha p, r -= alpha q, partial r.r; the last workgroup counts the
-// iteration and decides whether a reliable update (true FP64 residual) is due.
+// x += alpha p, r -= alpha q, partial r.r per workgroup (k_reduce_rr).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                 const T* __restrict__ q, double* part, Scalars* sc) {
@@ -620,29 +673,6 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    if (last_block(&sc->cnt[CNT_UPDATE], gridDim.x)) {
-        const double rr = sum_partials(part, gridDim.x, 1, 0, sh);
-        if (threadIdx.x == 0) {
-            sc->rr = rr;
-            sc->iter += 1;
-            bool check;
-            if (sc->reliable) {
-                // reliable update when the recurrence residual fell by delta since the
-                // last one, or when it predicts the target is met
-                const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
-                check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
-            } else {
-                check = rr <= sc->inner_tol2;
-            }
-            if (!isfinite(rr)) {
-                sc->status = ST_EBREAKDOWN;
-                check = true;
-            }
-            if (sc->iter >= sc->max_iter) check = true;
-            if (check) sc->pending = 1;
-        }
-        reset_counter(&sc->cnt[CNT_UPDATE]);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -662,13 +692,11 @@ __global__ __launch_bounds__(256) void k_correct(int n, double* __restrict__ E, 
 }
 
 // True residual r = rhs - M E in flux form, rhs - m E - sum_f W (E - E_nb), and
-// the norms of the stop rule; the last workgroup decides convergence and the
-// new residual scale gamma = ||r||_2.
+// per-workgroup partial sums of the stop-rule norms (k_reduce_resid).
 __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __restrict__ E, const double* __restrict__ We,
                                                  const double* __restrict__ Wn, const double* __restrict__ m,
                                                  const double* __restrict__ rhs, const double* __restrict__ s,
-                                                 const double* __restrict__ mu, double* __restrict__ r64, double* part,
-                                                 Scalars* sc, int force) {
+                                                 double* __restrict__ r64, double* part, const Scalars* sc, int force) {
     if (!force && (sc->done || !sc->pending)) return;
     const int nx = g.nx, ny = g.ny;
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
@@ -712,65 +740,150 @@ __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __rest
     for (int q = 0; q < NS; ++q) tot[q] = block_sum(a[q], sh);
     if (t == 0)
         for (int q = 0; q < NS; ++q) part[(size_t)bid2d() * NS + q] = tot[q];
-    if (last_block(&sc->cnt[CNT_RESID], nblocks2d())) {
-        for (int q = 0; q < NS; ++q) tot[q] = sum_partials(part, nblocks2d(), NS, q, sh);
-        if (t == 0) {
-            for (int q = 0; q < 4; ++q) sc->sums[q] = tot[q];
-            const double rrow = tot[2] > 0.0 ? sqrt(tot[0] / tot[2]) : sqrt(tot[0]);
-            const double rsc = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
-            const double rel = sc->norm == 0 ? rrow : rsc;
-            sc->rel_row = rrow;
-            sc->rel_scaled = rsc;
-            sc->rel_sel = rel;
-            sc->nchecks += 1;
-            const double gnew = sqrt(tot[4]);
-            // stagnation: the residual no longer falls (the tolerance is below
-            // what binary64 resolves for this system)
-            if (rel < 0.9 * sc->best) {
-                sc->best = rel;
-                sc->stall = 0;
-            } else {
-                sc->stall += 1;
-            }
-            if (!isfinite(rel)) {
-                sc->status = ST_EBREAKDOWN;
-                sc->done = 1;
-            } else if (rel <= sc->eps || gnew == 0.0) {
-                sc->done = 1;
-            } else if (sc->status != ST_OK || sc->iter >= sc->max_iter || (!sc->reliable && sc->iter > 0) ||
-                       sc->stall >= 6) {
-                if (sc->status == ST_OK && sc->reliable) sc->status = ST_ENOCONV;
-                sc->done = 1;
-            } else {
-                const double ps = sc->gamma > 0.0 ? sc->gamma / gnew : 1.0;
-                sc->pscale = ps;
-                sc->rz_old *= ps * ps;
-                sc->gamma = gnew;
-                sc->corr = gnew / *mu;
-                sc->rho_last = rel;
-                sc->rr_ref = 1.0;
-            }
-        }
-        reset_counter(&sc->cnt[CNT_RESID]);
-    }
 }
 
-// r_inner = r / gamma in the inner precision (and x = 0); the last workgroup
-// clears the pending flag.
+// r_inner = r / gamma in the inner precision (and x = 0) after a true-residual
+// check that did not stop the solve.
 template <typename T>
 __global__ __launch_bounds__(256) void k_demote(int n, const double* __restrict__ r64, T* __restrict__ r,
-                                                T* __restrict__ x, Scalars* sc, int force) {
-    if (!force && (sc->done || !sc->pending)) return;
-    if (sc->done) return;
+                                                T* __restrict__ x, const Scalars* __restrict__ sc) {
+    if (sc->done || !sc->demote) return;
     const double ig = 1.0 / sc->gamma;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         r[c] = (T)(r64[c] * ig);
         x[c] = T(0);
     }
-    if (last_block(&sc->cnt[CNT_DEMOTE], gridDim.x)) {
-        if (threadIdx.x == 0) sc->pending = 0;
-        reset_counter(&sc->cnt[CNT_DEMOTE]);
+}
+
+// ---------------------------------------------------------------------------
+// scalar reductions: one workgroup sums the producers' partials in a fixed
+// order (deterministic) and updates the solver state
+// ---------------------------------------------------------------------------
+
+constexpr int kRedThreads = 1024;
+
+__device__ inline double reduce_sum(const double* part, int nb, int stride, int k, double* sh) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) v += part[(size_t)b * stride + k];
+    return block_sum(v, sh);
+}
+
+// alpha = r.z / p.q
+__global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, int nb, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const double pq = reduce_sum(part, nb, 1, 0, sh);
+    if (threadIdx.x == 0) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            sc->status = ST_EBREAKDOWN;
+            sc->done = 1;
+            sc->pending = 1;
+        } else {
+            sc->alpha = sc->rz_old / pq;
+        }
+        sc->pscale = 1.0;
+        sc->restart = 0;
+        sc->demote = 0;
     }
+}
+
+// count the iteration; decide whether a reliable update (true FP64 residual)
+// is due: the recurrence residual fell by delta since the last one, or it
+// predicts the target is met
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rr(const double* part, int nb, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const double rr = reduce_sum(part, nb, 1, 0, sh);
+    if (threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->iter += 1;
+        bool check;
+        if (sc->reliable) {
+            const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
+            check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
+        } else {
+            check = rr <= sc->inner_tol2;
+        }
+        if (!isfinite(rr)) {
+            sc->status = ST_EBREAKDOWN;
+            check = true;
+        }
+        if (sc->iter >= sc->max_iter) check = true;
+        if (check) sc->pending = 1;
+    }
+}
+
+// beta = r.z / r.z_old (level-0 end of the V-cycle)
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rz(const double* part, int nb, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const double rz = reduce_sum(part, nb, 1, 0, sh);
+    if (threadIdx.x == 0) finish_rz(sc, rz);
+}
+
+// norms of the true residual, convergence / stagnation decision, new scale
+__global__ __launch_bounds__(kRedThreads) void k_reduce_resid(const double* part, int nb, const double* mu,
+                                                              Scalars* sc, int force) {
+    if (!force && (sc->done || !sc->pending)) return;
+    constexpr int NS = 5;
+    __shared__ double sh[16];
+    double tot[NS];
+    for (int q = 0; q < NS; ++q) tot[q] = reduce_sum(part, nb, NS, q, sh);
+    if (threadIdx.x != 0) return;
+    sc->pending = 0;
+    for (int q = 0; q < 4; ++q) sc->sums[q] = tot[q];
+    const double rrow = tot[2] > 0.0 ? sqrt(tot[0] / tot[2]) : sqrt(tot[0]);
+    const double rsc = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
+    const double rel = sc->norm == 0 ? rrow : rsc;
+    sc->rel_row = rrow;
+    sc->rel_scaled = rsc;
+    sc->rel_sel = rel;
+    sc->nchecks += 1;
+    const double gnew = sqrt(tot[4]);
+    // stagnation: the residual no longer falls (the tolerance is below what
+    // binary64 resolves for this system)
+    if (rel < 0.9 * sc->best) {
+        sc->best = rel;
+        sc->stall = 0;
+    } else {
+        sc->stall += 1;
+    }
+    if (!isfinite(rel)) {
+        sc->status = ST_EBREAKDOWN;
+        sc->done = 1;
+    } else if (rel <= sc->eps || gnew == 0.0) {
+        sc->done = 1;
+    } else if (sc->status != ST_OK || sc->iter >= sc->max_iter || (!sc->reliable && sc->iter > 0) || sc->stall >= 6) {
+        if (sc->status == ST_OK && sc->reliable) sc->status = ST_ENOCONV;
+        sc->done = 1;
+    } else {
+        // restart the search direction when the true residual is well above the
+        // one the (drifted) recurrence predicted
+        const double predicted = sc->gamma * sqrt(sc->rr);
+        if (sc->iter > 0 && !(gnew <= 2.0 * predicted)) sc->restart = 1;
+        const double ps = sc->gamma > 0.0 ? sc->gamma / gnew : 1.0;
+        sc->pscale = ps;
+        sc->rz_old *= ps * ps;
+        sc->gamma = gnew;
+        sc->corr = gnew / *mu;
+        sc->rho_last = rel;
+        sc->rr_ref = 1.0;
+        sc->demote = 1;
+    }
+}
+
+// maximum of the assembly partials (inner-precision normalisation mu)
+__global__ __launch_bounds__(kRedThreads) void k_reduce_max(const double* part, int nb, double* mu) {
+    __shared__ double sh[16];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) v = fmax(v, part[b]);
+    const double mx = block_max(v, sh);
+    if (threadIdx.x == 0) *mu = mx;
+}
+
+// Empty kernel: calibration of the cost of a timed launch (event pair).
+__global__ void k_noop(int* ran) {
+    if (ran && threadIdx.x == 0 && blockIdx.x == 0) *ran = 1;
 }
 
 __global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double inner_tol2, int max_iter, int norm,
@@ -799,6 +912,248 @@ __global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double in
     sc->nchecks = 0;
     sc->best = 1e300;
     sc->stall = 0;
+    sc->restart = 0;
+    sc->demote = 0;
+}
+
+}  // namespace fld
+
+namespace fld {
+
+// ---------------------------------------------------------------------------
+// coarse sub-cycle: the V-cycle of all levels >= ls in one workgroup, in LDS
+// ---------------------------------------------------------------------------
+
+constexpr int kSubThreads = 1024;
+constexpr int kSubMaxLevels = 12;
+
+template <typename T>
+struct SubLevel {
+    int nx, ny;
+    const T *m, *We, *Wn;  // row-major inner coefficients (global)
+    int off;               // offset of this level's arrays in the LDS pool (elements)
+    int tr;                // the level's primary layout is the transposed one
+    int pitch;             // LDS row pitch nx + 1 (odd: column walks hit distinct banks)
+    int size;              // pitch * ny: elements per LDS array of this level
+};
+
+template <typename T>
+struct SubCycle {
+    int nlev;              // levels ls .. ls + nlev - 1 (the last is the coarsest)
+    SubLevel<T> lv[kSubMaxLevels];
+    int scratch;           // offset of the Thomas scratch (size of the largest level)
+    const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
+};
+
+// LDS pool per level: m, We, Wn, b, x (5 arrays of nx*ny), then a PCR scratch
+// of 4 * (largest level / 2 + largest line) elements.
+//
+// One zebra half-sweep of a level in LDS: all lines of parity `par` are solved
+// together by parallel cyclic reduction, each thread owning unknowns
+// u, u + kSubThreads, ...  (unknown u = line-in-set * len + position).
+constexpr int kSubPerThread = 4;   // unknowns per thread (levels up to 2 * 4096 / 2 cells per parity)
+template <typename T>
+__device__ inline void sub_line(const SubLevel<T>& L, T* pool, T* scr, bool xdir, int par) {
+    const int nx = L.nx, ny = L.ny, P = L.pitch;
+    T* m = pool + L.off;
+    T* We = m + L.size;
+    T* Wn = We + L.size;
+    T* b = Wn + L.size;
+    T* x = b + L.size;
+    const int nlines = xdir ? ny : nx, len = xdir ? nx : ny;
+    const int nset = (nlines - par + 1) / 2;
+    const int nu = nset * len;
+    T* sa = scr;
+    T* sb = sa + nu;
+    T* sc = sb + nu;
+    T* sr = sc + nu;
+    auto cell = [&](int u, int& i, int& j) {
+        const int li = u / len, q = u - li * len, ln = par + 2 * li;
+        i = xdir ? q : ln;
+        j = xdir ? ln : q;
+    };
+    for (int u = threadIdx.x; u < nu; u += kSubThreads) {
+        int i, j;
+        cell(u, i, j);
+        const int c = j * P + i;
+        const T we = We[c], ww = i > 0 ? We[c - 1] : T(0);
+        const T wn = Wn[c], ws = j > 0 ? Wn[c - P] : T(0);
+        T r = b[c];
+        if (xdir) {
+            sa[u] = -ww;
+            sc[u] = -we;
+            if (j + 1 < ny) r += wn * x[c + P];
+            if (j > 0) r += ws * x[c - P];
+        } else {
+            sa[u] = -ws;
+            sc[u] = -wn;
+            if (i + 1 < nx) r += we * x[c + 1];
+            if (i > 0) r += ww * x[c - 1];
+        }
+        sb[u] = m[c] + ((ww + we) + (ws + wn));
+        sr[u] = r;
+    }
+    __syncthreads();
+    for (int st = 1; st < len; st <<= 1) {
+        T na[kSubPerThread], nb[kSubPerThread], nc[kSubPerThread], nr[kSubPerThread];
+#pragma unroll
+        for (int k = 0; k < kSubPerThread; ++k) {
+            const int u = threadIdx.x + k * kSubThreads;
+            if (u >= nu) continue;
+            const int q = u % len;
+            T a = sa[u], bb = sb[u], c = sc[u], r = sr[u];
+            T a2 = T(0), c2 = T(0);
+            if (q - st >= 0) {
+                const T al = -a / sb[u - st];
+                a2 = al * sa[u - st];
+                bb += al * sc[u - st];
+                r += al * sr[u - st];
+            }
+            if (q + st < len) {
+                const T ga = -c / sb[u + st];
+                c2 = ga * sc[u + st];
+                bb += ga * sa[u + st];
+                r += ga * sr[u + st];
+            }
+            na[k] = a2;
+            nb[k] = bb;
+            nc[k] = c2;
+            nr[k] = r;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSubPerThread; ++k) {
+            const int u = threadIdx.x + k * kSubThreads;
+            if (u >= nu) continue;
+            sa[u] = na[k];
+            sb[u] = nb[k];
+            sc[u] = nc[k];
+            sr[u] = nr[k];
+        }
+        __syncthreads();
+    }
+    for (int u = threadIdx.x; u < nu; u += kSubThreads) {
+        int i, j;
+        cell(u, i, j);
+        x[j * P + i] = sr[u] / sb[u];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T* __restrict__ bin, T* __restrict__ xout,
+                                                          const Scalars* __restrict__ sc) {
+    if (sc->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    T* pool = reinterpret_cast<T*>(smem_raw);
+    T* cp = pool + S.scratch;
+    const int t = threadIdx.x;
+    // coefficients of every sub-level, and the right-hand side of the first
+    for (int l = 0; l < S.nlev; ++l) {
+        const SubLevel<T>& L = S.lv[l];
+        const int n = L.nx * L.ny, z = L.size;
+        T* m = pool + L.off;
+        for (int c = t; c < n; c += kSubThreads) {
+            const int i = c % L.nx, j = c / L.nx, cl = j * L.pitch + i;
+            m[cl] = L.m[c];
+            m[z + cl] = L.We[c];
+            m[2 * z + cl] = L.Wn[c];
+            // input in the level's primary layout
+            if (l == 0) m[3 * z + cl] = bin[L.tr ? i * L.ny + j : c];
+        }
+    }
+    __syncthreads();
+    // down
+    for (int l = 0; l < S.nlev - 1; ++l) {
+        const SubLevel<T>& L = S.lv[l];
+        T* x = pool + L.off + 4 * L.size;
+        for (int c = t; c < L.size; c += kSubThreads) x[c] = T(0);
+        __syncthreads();
+        const bool first_x = !L.tr;  // primary direction first, as on the grid levels
+        for (int dir = 0; dir < 2; ++dir) {
+            const bool xd = (dir == 0) == first_x;
+            sub_line(L, pool, cp, xd, 0);
+            __syncthreads();
+            sub_line(L, pool, cp, xd, 1);
+            __syncthreads();
+        }
+        // residual and 2x2 restriction into the next level's b
+        const SubLevel<T>& C = S.lv[l + 1];
+        const int nc = C.nx * C.ny, P = L.pitch;
+        T* m = pool + L.off;
+        T* We = m + L.size;
+        T* Wn = We + L.size;
+        T* b = Wn + L.size;
+        T* bc = pool + C.off + 3 * C.size;
+        for (int cc = t; cc < nc; cc += kSubThreads) {
+            const int I = cc % C.nx, J = cc / C.nx;
+            T acc = T(0);
+            for (int bb = 0; bb < 2; ++bb)
+                for (int aa = 0; aa < 2; ++aa) {
+                    const int i = 2 * I + aa, j = 2 * J + bb;
+                    if (i >= L.nx || j >= L.ny) continue;
+                    const int c = j * P + i;
+                    const T xv = x[c];
+                    T res = b[c] - m[c] * xv;
+                    if (i + 1 < L.nx) res -= We[c] * (xv - x[c + 1]);
+                    if (i > 0) res -= We[c - 1] * (xv - x[c - 1]);
+                    if (j + 1 < L.ny) res -= Wn[c] * (xv - x[c + P]);
+                    if (j > 0) res -= Wn[c - P] * (xv - x[c - P]);
+                    acc += res;
+                }
+            bc[J * C.pitch + I] = acc;
+        }
+        __syncthreads();
+    }
+    // coarsest: dense inverse in the primary layout's cell order
+    {
+        const SubLevel<T>& L = S.lv[S.nlev - 1];
+        const int n = L.nx * L.ny;
+        T* b = pool + L.off + 3 * L.size;
+        T* x = b + L.size;
+        for (int c = t; c < n; c += kSubThreads) {
+            const int i = c % L.nx, j = c / L.nx;
+            const int row = L.tr ? i * L.ny + j : c;
+            T acc = T(0);
+            for (int k = 0; k < n; ++k) {
+                const int ik = k % L.nx, jk = k / L.nx;
+                const int col = L.tr ? ik * L.ny + jk : k;
+                acc += S.Ainv[row * n + col] * b[jk * L.pitch + ik];
+            }
+            x[j * L.pitch + i] = acc;
+        }
+        __syncthreads();
+    }
+    // up
+    for (int l = S.nlev - 2; l >= 0; --l) {
+        const SubLevel<T>& L = S.lv[l];
+        const SubLevel<T>& C = S.lv[l + 1];
+        const int n = L.nx * L.ny;
+        T* x = pool + L.off + 4 * L.size;
+        const T* xc = pool + C.off + 4 * C.size;
+        for (int c = t; c < n; c += kSubThreads) {
+            const int i = c % L.nx, j = c / L.nx;
+            x[j * L.pitch + i] += xc[(j >> 1) * C.pitch + (i >> 1)];
+        }
+        __syncthreads();
+        const bool first_x = !L.tr;
+        for (int dir = 0; dir < 2; ++dir) {
+            const bool xd = (dir == 0) != first_x;  // reverse order of the pre-smoother
+            sub_line(L, pool, cp, xd, 1);
+            __syncthreads();
+            sub_line(L, pool, cp, xd, 0);
+            __syncthreads();
+        }
+    }
+    // output in the first level's primary layout
+    {
+        const SubLevel<T>& L = S.lv[0];
+        const int n = L.nx * L.ny;
+        const T* x = pool + L.off + 4 * L.size;
+        for (int c = t; c < n; c += kSubThreads) {
+            const int i = c % L.nx, j = c / L.nx;
+            xout[L.tr ? i * L.ny + j : c] = x[j * L.pitch + i];
+        }
+    }
 }
 
 }  // namespace fld

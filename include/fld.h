@@ -45,7 +45,7 @@ typedef enum {
     FLD_EINVAL = 1,        /* bad argument: sizes, pointers, dt <= 0, unknown enum value     */
     FLD_ENOMEM = 2,        /* device or pinned allocation failed (create calls only)          */
     FLD_EHIP = 3,          /* a HIP runtime call failed                                        */
-    FLD_ENOCONV = 4,       /* tolerance not reached within max_outer / max_inner               */
+    FLD_ENOCONV = 4,       /* tolerance not reached within max_inner iterations (or stalled)   */
     FLD_EBREAKDOWN = 5,    /* CG breakdown: p.Ap <= 0 or non-finite scalar                     */
     FLD_ENONFINITE = 6,    /* an input field is non-finite or outside its domain (E,T,rho,    */
                            /* kappa_R > 0; kappa_P, c_v >= 0), detected on the device          */
@@ -116,11 +116,13 @@ typedef struct {
     int32_t limiter;        /* fld_limiter (default LP)                                      */
     int32_t norm;           /* fld_norm (default ROW)                                        */
     double  rel_tol;        /* eps of the stop rule (default 1e-10)                          */
-    int32_t max_outer;      /* refinement steps (default 8; FP32 mode uses 1)                */
-    int32_t max_inner;      /* CG iterations per refinement step (default 2000)             */
-    double  inner_rtol;     /* residual reduction asked of one inner solve in MIXED / FP32   */
-                            /* (default 1e-5); FP64 solves straight to the target            */
-    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (<= 256, def 64) */
+    int32_t max_outer;      /* unused, kept for layout; must be >= 1 (default 8): the FP64   */
+                            /* residual checks of the reliable-update solver are triggered   */
+                            /* by the inner residual, not counted                            */
+    int32_t max_inner;      /* CG iterations per solve, all checks included (default 2000)   */
+    double  inner_rtol;     /* FP32 mode only: stop once the inner (FP32) residual has       */
+                            /* dropped by this factor (default 1e-5)                         */
+    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (1..64, def 64)  */
     int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
     int32_t smoother;       /* fld_smoother (default LINE); LINE needs nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
@@ -183,9 +185,18 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
 
 /* nsteps consecutive steps with (E, T) <- (E^{n+1}, T^{n+1}) and the opacities,
  * rho and c_v held fixed (Section 3.2.1 sub-step loop, one sub-step per step).
- * Each step's solve runs as captured hipGraph chunks with a fixed iteration
- * schedule and device-side early exit.  per_step (host, nsteps entries) may
- * be NULL.  Returns the first non-OK step status. */
+ * The first step runs as fld_step; its CG iteration count k1 fixes a budget
+ * S = min(max_inner, even(1.5 k1 + 8)) iterations.  One whole step (assembly,
+ * hierarchy, S iteration slots with device-side early exit, gas update, a
+ * device-side status record) is then captured once as a hipGraph and launched
+ * nsteps-1 times without host synchronisation; the call synchronises once at
+ * the end.  Results equal those of nsteps fld_step calls whenever every step
+ * converges within S.  A later step that does not converge within S is
+ * recorded as ENOCONV and, unlike fld_step, its gas update and the following
+ * steps still run.  With profiling on or use_graph = 0 the steps run as
+ * fld_step calls and stop at the first failure.  per_step (host, nsteps
+ * entries) may be NULL; a graph-launched step's ms is the mean over those
+ * launches.  Returns the first non-OK step status. */
 fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);

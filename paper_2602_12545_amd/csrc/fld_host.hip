@@ -5,7 +5,9 @@
 // the host can queue (or replay as a hipGraph) a chunk of slots and only polls
 // the flag between chunks.  Reliable updates (FP64 correction of E, true FP64
 // residual, re-scaled inner residual) are decided on the device inside a slot.
+#include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -16,6 +18,10 @@
 #include "fld_mg.hpp"
 
 using namespace fld;
+
+static_assert(sizeof(fld_solve_info) == sizeof(StepInfo) && offsetof(fld_solve_info, rel_resid) == offsetof(StepInfo, rel_resid) &&
+                  offsetof(fld_solve_info, ms) == offsetof(StepInfo, ms),
+              "device step record must match fld_solve_info");
 
 namespace {
 
@@ -338,9 +344,8 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
 }
 
 template <typename T>
-fld_status build_hierarchy(fld_ctx* c) {
+fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     Inner<T>& in = inner<T>(c);
-    hipStream_t st = c->stream;
     const int L = (int)in.lv.size();
     const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
     const bool line = c->opt.smoother == FLD_SMOOTH_LINE;
@@ -555,6 +560,55 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
         ctx->err = buf;
     }
     return (fld_status)status;
+}
+
+}  // namespace
+
+namespace {
+
+fld_status check_fields(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
+                        const double* kP, const double* cv, const double* ghost, double dt) {
+    if (!E || !T || !rho || !kR || !kP || !cv) { ctx->err = "null field pointer"; return FLD_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { ctx->err = "dt must be > 0"; return FLD_EINVAL; }
+    for (int sd = 0; sd < 4; ++sd)
+        if (ctx->bc.kind[sd] == BC_DIRICHLET_GHOST && !ghost) { ctx->err = "ghost_E required"; return FLD_EINVAL; }
+    return FLD_OK;
+}
+
+// Assembly and multigrid hierarchy, kernels only (capturable).
+fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
+                            const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st) {
+    k_zero_int<<<1, 1, 0, st>>>(ctx->err_flag);
+    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
+    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part};
+    const dim3 ag = cell_grid(ctx->nx, ctx->ny);
+    k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
+    k_reduce_max<<<1, kRedThreads, 0, st>>>(ctx->part, (int)(ag.x * ag.y), ctx->mu);
+    HIPCHK(hipGetLastError());
+    fld_status s = inner_is_float(ctx) ? build_hierarchy<float>(ctx, st) : build_hierarchy<double>(ctx, st);
+    if (s != FLD_OK) return s;
+    ctx->T = T;
+    ctx->rho = rho;
+    ctx->kP = kP;
+    ctx->cv = cv;
+    ctx->dt = dt;
+    return FLD_OK;
+}
+
+// A solve with a fixed budget of `slots` CG iterations and device-side early
+// exit, then the final correction (capturable: no host synchronisation).
+template <typename T>
+void enqueue_solve_fixed(fld_ctx* ctx, double* E, int slots, hipStream_t st) {
+    Inner<T>& in = inner<T>(ctx);
+    const fld_options& o = ctx->opt;
+    const int n = ctx->nx * ctx->ny;
+    const double delta = o.precision == FLD_MIXED ? 0.1 : 1e-3;
+    k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, slots, o.norm,
+                                    o.precision == FLD_FP32 ? 0 : 1);
+    enqueue_check<T>(ctx, in, E, 1, st);
+    enqueue_vcycle<T>(ctx, in, st);
+    for (int k = 0; k < slots; ++k) enqueue_slot<T>(ctx, in, k & 1, E, st);
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
 }
 
 }  // namespace
@@ -781,25 +835,10 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
 fld_status fld_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
                         const double* kP, const double* cv, const double* ghost, double dt) {
     if (!ctx) return FLD_EINVAL;
-    if (!E || !T || !rho || !kR || !kP || !cv) { ctx->err = "null field pointer"; return FLD_EINVAL; }
-    if (!(dt > 0.0) || !std::isfinite(dt)) { ctx->err = "dt must be > 0"; return FLD_EINVAL; }
-    for (int sd = 0; sd < 4; ++sd)
-        if (ctx->bc.kind[sd] == BC_DIRICHLET_GHOST && !ghost) { ctx->err = "ghost_E required"; return FLD_EINVAL; }
-    hipStream_t st = ctx->stream;
-    HIPCHK(hipMemsetAsync(ctx->err_flag, 0, sizeof(int), st));
-    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
-    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part};
-    const dim3 ag = cell_grid(ctx->nx, ctx->ny);
-    k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
-    k_reduce_max<<<1, kRedThreads, 0, st>>>(ctx->part, (int)(ag.x * ag.y), ctx->mu);
-    HIPCHK(hipGetLastError());
-    fld_status s = inner_is_float(ctx) ? build_hierarchy<float>(ctx) : build_hierarchy<double>(ctx);
+    fld_status s = check_fields(ctx, E, T, rho, kR, kP, cv, ghost, dt);
     if (s != FLD_OK) return s;
-    ctx->T = T;
-    ctx->rho = rho;
-    ctx->kP = kP;
-    ctx->cv = cv;
-    ctx->dt = dt;
+    s = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, ctx->stream);
+    if (s != FLD_OK) return s;
     ctx->assembled = true;
     return FLD_OK;
 }
@@ -834,13 +873,72 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
                      const double* kP, const double* cv, const double* ghost, double dt, fld_solve_info* per_step) {
     if (!ctx) return FLD_EINVAL;
     if (nsteps < 0) { ctx->err = "nsteps < 0"; return FLD_EINVAL; }
-    fld_status first = FLD_OK;
-    for (int k = 0; k < nsteps; ++k) {
-        fld_status s = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, per_step ? &per_step[k] : nullptr);
-        if (s != FLD_OK && first == FLD_OK) first = s;
-        if (s == FLD_EINVAL || s == FLD_EHIP || s == FLD_ENONFINITE) return s;
+    if (nsteps == 0) return FLD_OK;
+    fld_status s = check_fields(ctx, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    // step 1, host-driven: measures the iteration count that sizes the budget
+    fld_solve_info first{};
+    fld_status s1 = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, &first);
+    if (per_step) per_step[0] = first;
+    if (s1 != FLD_OK || nsteps == 1) return s1;
+    if (ctx->prof.on || !ctx->opt.use_graph) {
+        // measured (events cannot be timed inside graphs) or graphs disabled
+        for (int k = 1; k < nsteps; ++k) {
+            fld_solve_info inf{};
+            fld_status sk = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, &inf);
+            if (per_step) per_step[k] = inf;
+            if (sk != FLD_OK) return sk;
+        }
+        return FLD_OK;
     }
-    return first;
+    const int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 3 / 2 + 8) + 1) & ~1);
+    // one captured step: assembly, hierarchy, fixed-budget solve, gas update,
+    // per-step record; launched nsteps-1 times back to back
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    fld_solve_info* dinfo = nullptr;
+    int* dcount = nullptr;
+    HIPCHK(hipMalloc(&dinfo, sizeof(fld_solve_info) * nsteps));
+    HIPCHK(hipMalloc(&dcount, sizeof(int)));
+    HIPCHK(hipMemset(dcount, 0, sizeof(int)));
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipStream_t cs = ctx->cap_stream;
+    const int n = ctx->nx * ctx->ny;
+    fld_status st = FLD_OK;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    st = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, cs);
+    if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, slots, cs);
+    else enqueue_solve_fixed<double>(ctx, E, slots, cs);
+    k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, cv, dt, T);
+    k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, nsteps, (void*)dinfo, (int)ctx->h64.size());
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st == FLD_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (st == FLD_OK && e != hipSuccess) {
+        ctx->err = std::string("multi-step graph: ") + hipGetErrorString(e);
+        st = FLD_EHIP;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (int k = 1; k < nsteps && st == FLD_OK; ++k)
+        if (hipGraphLaunch(ge, ctx->stream) != hipSuccess) st = FLD_EHIP;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) st = FLD_EHIP;
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::vector<fld_solve_info> h(nsteps);
+    if (st == FLD_OK && hipMemcpy(h.data(), dinfo, sizeof(fld_solve_info) * (nsteps - 1), hipMemcpyDeviceToHost) !=
+                            hipSuccess)
+        st = FLD_EHIP;
+    if (ge) (void)hipGraphExecDestroy(ge);
+    (void)hipFree(dinfo);
+    (void)hipFree(dcount);
+    if (st != FLD_OK) return st;
+    fld_status firstbad = s1;
+    for (int k = 1; k < nsteps; ++k) {
+        h[k - 1].ms = ms / (nsteps - 1);
+        if (per_step) per_step[k] = h[k - 1];
+        if (h[k - 1].status != FLD_OK && firstbad == FLD_OK) firstbad = (fld_status)h[k - 1].status;
+    }
+    ctx->assembled = true;
+    return firstbad;
 }
 
 fld_status fld_get_operator(fld_ctx* ctx, double* We, double* Wn, double* diag, double* rhs) {

@@ -881,6 +881,37 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_max(const double* part, 
     if (threadIdx.x == 0) *mu = mx;
 }
 
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// Per-step record of a captured multi-step run: the solve's final state goes
+// to info[counter++] (layout of fld_solve_info).
+struct StepInfo {
+    int32_t status, outer_iters, inner_iters, mg_levels;
+    double rel_resid, rel_resid_row, rel_resid_scaled;
+    float ms;
+};
+__global__ void k_record_step(const Scalars* sc, const int* err, int* counter, int cap, void* info_v, int levels) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int k = *counter;
+    if (k < cap) {
+        StepInfo* info = static_cast<StepInfo*>(info_v) + k;
+        int st = sc->status;
+        if (st == ST_OK && !sc->done) st = ST_ENOCONV;
+        if (*err) st = ST_ENONFINITE;
+        info->status = st;
+        info->outer_iters = sc->nchecks;
+        info->inner_iters = sc->iter;
+        info->mg_levels = levels;
+        info->rel_resid = sc->rel_sel;
+        info->rel_resid_row = sc->rel_row;
+        info->rel_resid_scaled = sc->rel_scaled;
+        info->ms = 0.f;
+    }
+    *counter = k + 1;
+}
+
 // Empty kernel: calibration of the cost of a timed launch (event pair).
 __global__ void k_noop(int* ran) {
     if (ran && threadIdx.x == 0 && blockIdx.x == 0) *ran = 1;

@@ -1,0 +1,102 @@
+"""Multi-step runs (Section 3.2.1 sub-step loop): fld_steps, whose steps after
+the first replay one captured hipGraph, against repeated fld_step calls
+(bit-identical) and against the FP64 oracle stepped the same number of times."""
+import numpy as np
+import pytest
+
+import fld_workloads as W
+from oracle import fld_oracle as O
+from gpu_helpers import make_ctx, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _run(fld, torch, prob, nsteps, multi, profile=False, **opt):
+    ctx = make_ctx(fld, prob, **opt)
+    t = to_dev(prob, torch)
+    args = (t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"])
+    if profile:
+        ctx.profile(True)
+    if multi:
+        infos = ctx.steps(nsteps, t["E"], t["T"], *args, check=False)
+    else:
+        infos = [ctx.step(t["E"], t["T"], *args, check=False) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    out = t["E"].cpu().numpy(), t["T"].cpu().numpy(), infos
+    ctx.close()
+    return out
+
+
+def _oracle_steps(prob, nsteps):
+    E, T = prob.E, prob.T
+    for _ in range(nsteps):
+        r = O.step_problem(prob, E, T)
+        E, T = r.E, r.T
+    return E, T
+
+
+@pytest.mark.parametrize("name,kw,prec,norm", [
+    ("c1", dict(nx=48, ny=40), "mixed", 0),
+    ("c2", dict(nx=70, ny=52), "fp64", 0),
+    ("c5", dict(nx=96, ny=64), "mixed", 1),
+])
+def test_steps_equal_repeated_step(lib, name, kw, prec, norm):
+    fld = lib
+    prob = W.make(name, **kw)
+    opt = dict(precision=prec, norm=norm, rel_tol=1e-11)
+    E1, T1, i1 = _run(fld, torch, prob, 6, multi=False, **opt)
+    E2, T2, i2 = _run(fld, torch, prob, 6, multi=True, **opt)
+    assert [i["status"] for i in i2] == [0] * 6
+    assert [i["inner_iters"] for i in i1] == [i["inner_iters"] for i in i2]
+    assert np.array_equal(E1, E2) and np.array_equal(T1, T2)
+
+
+def test_steps_profiled_path_matches(lib):
+    fld = lib
+    prob = W.make("c2", nx=40, ny=33)
+    opt = dict(precision="mixed", norm=1, rel_tol=1e-11)
+    E1, T1, i1 = _run(fld, torch, prob, 4, multi=True, profile=False, **opt)
+    E2, T2, i2 = _run(fld, torch, prob, 4, multi=True, profile=True, **opt)
+    st = ([i["status"] for i in i1], [i["status"] for i in i2])
+    assert st == ([0] * 4, [0] * 4), st
+    assert np.array_equal(E1, E2) and np.array_equal(T1, T2)
+
+
+@pytest.mark.parametrize("name,kw,norm", [
+    ("c5", dict(nx=64, ny=48), 1),
+    ("c3", dict(nx=40, ny=40), 0),
+])
+def test_steps_vs_oracle(lib, name, kw, norm):
+    """Ten coupled steps; each step's solve error (<= about 1e-12 relative) is
+    carried into the next step's coefficients, so the bound is looser than a
+    single step's."""
+    fld = lib
+    prob = W.make(name, **kw)
+    n = 10
+    E, T, infos = _run(fld, torch, prob, n, multi=True, precision="mixed", norm=norm, rel_tol=1e-12)
+    assert all(i["status"] == 0 for i in infos)
+    Eo, To = _oracle_steps(prob, n)
+    assert rel_l2(E, Eo) < 1e-9
+    assert rel_l2(T, To) < 1e-9
+    assert np.max(np.abs(E - Eo) / np.abs(Eo)) < 1e-6
+
+
+def test_steps_zero_and_one(lib):
+    fld = lib
+    prob = W.make("c1", nx=20, ny=18)
+    E0, T0, inf0 = _run(fld, torch, prob, 0, multi=True)
+    assert np.array_equal(E0, prob.E) and np.array_equal(T0, prob.T)
+    E1, T1, _ = _run(fld, torch, prob, 1, multi=True)
+    E2, T2, _ = _run(fld, torch, prob, 1, multi=False)
+    assert np.array_equal(E1, E2) and np.array_equal(T1, T2)
+
+
+def test_steps_budget_exhausted_is_reported(lib):
+    """A budget of 2 iterations cannot converge: every step reports ENOCONV
+    and the call returns it (the first step stops the run)."""
+    fld = lib
+    prob = W.make("c2", nx=48, ny=48)
+    _, _, infos = _run(fld, torch, prob, 3, multi=True, max_inner=2)
+    assert infos[0]["status"] == 4

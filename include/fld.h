@@ -231,6 +231,67 @@ const char* fld_version(void);
 /* Releases the context and all its device memory.  NULL is accepted. */
 void fld_destroy(fld_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched blocks (Section 3.3, static mesh refinement: every block is an
+ * independent grid whose boundaries are ghost cells filled from its parent
+ * or neighbours).  A batch holds nblocks Cartesian blocks of nx[b] x ny[b]
+ * cells (1 .. 1024 per side) with uniform spacing dx[b], dy[b] (cm; faces at
+ * i dx[b], j dy[b]).  Fields are packed block after block, each block
+ * row-major [ny][nx] (device doubles, sum nx ny in total); ghost_E packs
+ * 2 ny + 2 nx values per block in the side order of fld_bc, block after
+ * block.  One step of the whole batch is one kernel launch: one workgroup per
+ * block runs the block's assembly, multigrid hierarchy, reliable-update
+ * MG-preconditioned CG solve (line smoothing) and gas update; blocks are
+ * launched largest first.  Every block solves the system fld_step would solve
+ * for the same grid, boundaries and options.
+ * ------------------------------------------------------------------------ */
+typedef struct fld_batch fld_batch;
+
+/* Creates a batch.  nx, ny, dx, dy: host arrays of nblocks entries, read
+ * during the call.  bc: host array of 4 sides applied to every block (NULL =
+ * DIRICHLET_GHOST on all sides; AXIS is not allowed).  opt may be NULL; the
+ * batch needs smoother = LINE and mg_coarse_max <= 64; chunk is unused;
+ * use_graph selects graph capture in fld_batch_steps.  stream: hipStream_t.
+ * Returns EINVAL (sizes, spacing, options), ENOMEM, EHIP. */
+fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx, const int32_t* ny,
+                            const double* dx, const double* dy, const fld_bc* bc,
+                            const fld_options* opt, void* stream);
+
+/* One implicit step of every block, E_r and T_g updated in place (packed
+ * device arrays).  per_block (host, nblocks entries, caller's block order)
+ * may be NULL: then the call is asynchronous and returns OK once launched;
+ * otherwise it synchronises, fills the records (ms = wall time of the whole
+ * batch) and returns the first non-OK block status.  A block that fails
+ * keeps its last iterate in E_r and its T_g unchanged; the others are not
+ * affected. */
+fld_status fld_batch_step(fld_batch* b, double* E_r, double* T_g, const double* rho,
+                          const double* kappa_R, const double* kappa_P, const double* c_v,
+                          const double* ghost_E, double dt, fld_solve_info* per_block);
+
+/* nsteps consecutive batch steps (fields other than E_r, T_g held fixed),
+ * captured as one hipGraph of nsteps kernel nodes when use_graph is set;
+ * synchronises once.  per_block receives the records of the last step (ms =
+ * mean time per step); returns the first non-OK status of any block in any
+ * step (failed blocks continue with the next step). */
+fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E_r, double* T_g, const double* rho,
+                           const double* kappa_R, const double* kappa_P, const double* c_v,
+                           const double* ghost_E, double dt, fld_solve_info* per_block);
+
+/* Workgroup size of the batch kernel (256, 512 or 1024; default 512).  Any
+ * value gives results that agree to rounding; the tuner picks the fastest. */
+fld_status fld_batch_set_threads(fld_batch* b, int32_t threads);
+fld_status fld_batch_get_threads(const fld_batch* b, int32_t* threads);
+
+/* Packed sizes: cells (sum nx ny) and ghost values (sum 2 nx + 2 ny). */
+fld_status fld_batch_sizes(const fld_batch* b, int64_t* cells, int64_t* ghosts);
+
+/* Reason of the last error of b; with b = NULL, of the last failed
+ * fld_batch_create on the calling thread. */
+const char* fld_batch_last_error(const fld_batch* b);
+
+/* Releases the batch and its device memory.  NULL is accepted. */
+void fld_batch_destroy(fld_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

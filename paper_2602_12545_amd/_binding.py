@@ -83,6 +83,16 @@ _SIGS = {
     "fld_last_error": (ctypes.c_char_p, [_P]),
     "fld_version": (ctypes.c_char_p, []),
     "fld_destroy": (None, [_P]),
+    "fld_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                              ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(fld_bc),
+                              ctypes.POINTER(fld_options), _P]),
+    "fld_batch_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_batch_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_batch_set_threads": (_I, [_P, _I]),
+    "fld_batch_get_threads": (_I, [_P, ctypes.POINTER(_I)]),
+    "fld_batch_sizes": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "fld_batch_last_error": (ctypes.c_char_p, [_P]),
+    "fld_batch_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -213,6 +223,78 @@ class Context:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib.fld_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent Cartesian blocks solved together: wraps fld_batch_create ...
+    fld_batch_destroy.  Fields are packed torch float64 GPU tensors (block after
+    block, each row-major [ny, nx])."""
+
+    def __init__(self, nx: Sequence[int], ny: Sequence[int], dx: Sequence[float], dy: Sequence[float],
+                 bcs: Optional[Sequence] = None, options=None, stream=None):
+        nb = len(nx)
+        if not (len(ny) == len(dx) == len(dy) == nb):
+            raise ValueError("nx, ny, dx, dy must have one entry per block")
+        anx, any_ = (_I * nb)(*[int(v) for v in nx]), (_I * nb)(*[int(v) for v in ny])
+        adx, ady = (_D * nb)(*[float(v) for v in dx]), (_D * nb)(*[float(v) for v in dy])
+        bc_arr = None
+        if bcs is not None:
+            bc_arr = (fld_bc * 4)()
+            for s, b in enumerate(bcs):
+                kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
+                bc_arr[s].kind, bc_arr[s].value = int(kind), float(value)
+        self.options = options if options is not None else default_options()
+        self.nblocks = nb
+        h = _P()
+        st = lib.fld_batch_create(ctypes.byref(h), nb, anx, any_, adx, ady, bc_arr, ctypes.byref(self.options),
+                                  _stream_handle(stream))
+        if st != FLD_OK:
+            raise FLDError(st, lib.fld_batch_last_error(None).decode())
+        self.handle = h
+        cells, ghosts = ctypes.c_int64(), ctypes.c_int64()
+        lib.fld_batch_sizes(h, ctypes.byref(cells), ctypes.byref(ghosts))
+        self.cells, self.ghosts = cells.value, ghosts.value
+
+    def _check(self, st):
+        if st != FLD_OK:
+            raise FLDError(st, lib.fld_batch_last_error(self.handle).decode())
+
+    def step(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, check=True, records=True):
+        infos = (fld_solve_info * self.nblocks)() if records else None
+        st = lib.fld_batch_step(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P), _ptr(c_v),
+                                _ptr(ghost_E), float(dt), infos)
+        if check:
+            self._check(st)
+        return [infos[k].as_dict() for k in range(self.nblocks)] if records else None
+
+    def steps(self, nsteps, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, check=True):
+        infos = (fld_solve_info * self.nblocks)()
+        st = lib.fld_batch_steps(self.handle, int(nsteps), _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R),
+                                 _ptr(kappa_P), _ptr(c_v), _ptr(ghost_E), float(dt), infos)
+        if check:
+            self._check(st)
+        return [infos[k].as_dict() for k in range(self.nblocks)]
+
+    @property
+    def threads(self) -> int:
+        v = _I()
+        self._check(lib.fld_batch_get_threads(self.handle, ctypes.byref(v)))
+        return v.value
+
+    @threads.setter
+    def threads(self, n: int):
+        self._check(lib.fld_batch_set_threads(self.handle, int(n)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.fld_batch_destroy(self.handle)
             self.handle = _P()
 
     def __del__(self):

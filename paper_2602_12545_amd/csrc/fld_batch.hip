@@ -1,0 +1,402 @@
+// Host driver and C ABI of the batched solver (fld_batch_*, see include/fld.h).
+//
+// A batch is a set of independent Cartesian blocks with uniform spacing and
+// ghost-cell boundaries, packed block after block.  One step of the whole
+// batch is one kernel launch (one workgroup per block, largest blocks first).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fld.h"
+#include "fld_batch.hpp"
+
+using namespace fld;
+
+static_assert(sizeof(fld_solve_info) == sizeof(BInfo) && offsetof(fld_solve_info, rel_resid) == offsetof(BInfo, rel_resid) &&
+                  offsetof(fld_solve_info, ms) == offsetof(BInfo, ms),
+              "device block record must match fld_solve_info");
+
+struct fld_batch {
+    int nb = 0;
+    fld_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    BCDev bc{};
+    bool need_ghost = false;
+    long long ncell = 0, nghost = 0, nlev = 0;
+    std::vector<BBlock> hb;  // launch order
+    BBlock* db = nullptr;
+    std::vector<void*> allocs;
+    double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
+    void *lm = nullptr, *lWe = nullptr, *lWn = nullptr, *lx = nullptr, *lb = nullptr;
+    void *xi = nullptr, *p = nullptr, *q = nullptr;
+    BInfo* dinfo = nullptr;
+    BInfo* hinfo = nullptr;
+    int threads = 512;
+
+    template <typename U>
+    hipError_t alloc(U** ptr, size_t count) {
+        void* v = nullptr;
+        hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(U));
+        if (e == hipSuccess) allocs.push_back(v);
+        *ptr = static_cast<U*>(v);
+        return e;
+    }
+    ~fld_batch() {
+        for (void* v : allocs) (void)hipFree(v);
+        if (hinfo) (void)hipHostFree(hinfo);
+    }
+};
+
+namespace {
+
+thread_local std::string t_create_err;  // reason of the last failed fld_batch_create on this thread
+
+bool inner_float(const fld_batch* b) { return b->opt.precision != FLD_FP64; }
+
+BOpts make_opts(const fld_batch* b) {
+    const fld_options& o = b->opt;
+    const double delta = o.precision == FLD_MIXED ? 0.1 : 1e-3;
+    BOpts r;
+    r.eps = o.rel_tol;
+    r.delta2 = delta * delta;
+    r.inner_tol2 = o.inner_rtol * o.inner_rtol;
+    r.omega = o.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
+    r.max_iter = o.max_inner;
+    r.norm = o.norm;
+    r.reliable = o.precision == FLD_FP32 ? 0 : 1;
+    r.gas = 1;
+    return r;
+}
+
+template <typename T, int NT>
+hipError_t set_lds() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<T, NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)BLds<T, NT>::bytes);
+}
+
+template <typename T, int NT>
+void launch_t(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
+    BWork<T> w{b->We, b->Wn, b->m, b->rhs, b->s, b->r64,
+               static_cast<T*>(b->lm), static_cast<T*>(b->lWe), static_cast<T*>(b->lWn),
+               static_cast<T*>(b->lx), static_cast<T*>(b->lb),
+               static_cast<T*>(b->xi), static_cast<T*>(b->p), static_cast<T*>(b->q)};
+    k_batch_step<T, NT><<<b->nb, NT, BLds<T, NT>::bytes, st>>>(b->db, f, w, make_opts(b), info);
+}
+
+template <typename T>
+void launch_p(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
+    switch (b->threads) {
+        case 256: launch_t<T, 256>(b, f, info, st); break;
+        case 1024: launch_t<T, 1024>(b, f, info, st); break;
+        default: launch_t<T, 512>(b, f, info, st); break;
+    }
+}
+
+void launch(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
+    if (inner_float(b)) launch_p<float>(b, f, info, st);
+    else launch_p<double>(b, f, info, st);
+}
+
+fld_status check_fields(fld_batch* b, const double* E, const double* T, const double* rho, const double* kR,
+                        const double* kP, const double* cv, const double* ghost, double dt) {
+    if (!E || !T || !rho || !kR || !kP || !cv) { b->err = "null field pointer"; return FLD_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { b->err = "dt must be > 0"; return FLD_EINVAL; }
+    if (b->need_ghost && !ghost) { b->err = "ghost_E required"; return FLD_EINVAL; }
+    return FLD_OK;
+}
+
+BFields fields(fld_batch* b, double* E, double* T, const double* rho, const double* kR, const double* kP,
+               const double* cv, const double* ghost, double dt) {
+    return BFields{E, T, rho, kR, kP, cv, ghost, dt, b->opt.limiter, b->bc};
+}
+
+fld_status first_bad(const BInfo* inf, int nb) {
+    for (int k = 0; k < nb; ++k)
+        if (inf[k].status != FLD_OK) return (fld_status)inf[k].status;
+    return FLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx, const int32_t* ny, const double* dx,
+                            const double* dy, const fld_bc* bc, const fld_options* opt, void* stream) {
+    if (!out) return FLD_EINVAL;
+    *out = nullptr;
+    if (nblocks < 1 || nblocks > (1 << 20) || !nx || !ny || !dx || !dy) {
+        t_create_err = "nblocks must be in [1, 2^20] and the size arrays non-NULL";
+        return FLD_EINVAL;
+    }
+    fld_batch* b = new (std::nothrow) fld_batch();
+    if (!b) return FLD_ENOMEM;
+    auto fail = [&](fld_status s, const char* msg) {
+        t_create_err = msg;
+        delete b;
+        return s;
+    };
+    if (opt) b->opt = *opt;
+    else fld_default_options(&b->opt);
+    const fld_options& o = b->opt;
+    if (o.precision < 0 || o.precision > 2 || o.limiter < 0 || o.limiter > 2 || o.norm < 0 || o.norm > 1 ||
+        !(o.rel_tol > 0.0) || o.max_inner < 1 || !(o.inner_rtol > 0.0) || o.mg_coarse_max < 1 ||
+        o.mg_coarse_max > kBCoarse || o.mg_coarse_op < 0 || o.mg_coarse_op > 1 || o.smoother != FLD_SMOOTH_LINE)
+        return fail(FLD_EINVAL, "options (the batched solver uses line smoothing, mg_coarse_max <= 64)");
+    b->stream = static_cast<hipStream_t>(stream);
+    b->nb = nblocks;
+    for (int sd = 0; sd < 4; ++sd) {
+        const int k = bc ? bc[sd].kind : FLD_BC_DIRICHLET_GHOST;
+        const double v = bc ? bc[sd].value : 0.0;
+        if (k < 0 || k > FLD_BC_FREE_STREAM) return fail(FLD_EINVAL, "boundary kind (Cartesian blocks)");
+        if (k == FLD_BC_DIRICHLET_FACE && !(v > 0.0 && std::isfinite(v))) return fail(FLD_EINVAL, "boundary T");
+        if (k == FLD_BC_FLUX_IN && !std::isfinite(v)) return fail(FLD_EINVAL, "boundary flux");
+        b->bc.kind[sd] = k;
+        b->bc.value[sd] = v;
+        if (k == FLD_BC_DIRICHLET_GHOST) b->need_ghost = true;
+    }
+    for (int k = 0; k < nblocks; ++k) {
+        if (nx[k] < 1 || ny[k] < 1 || nx[k] > kBMaxSide || ny[k] > kBMaxSide)
+            return fail(FLD_EINVAL, "block sides must be in [1, 1024]");
+        if (!(dx[k] > 0.0) || !(dy[k] > 0.0) || !std::isfinite(dx[k]) || !std::isfinite(dy[k]))
+            return fail(FLD_EINVAL, "block spacing must be finite and > 0");
+    }
+    // layout: packed cells / ghosts in the caller's order; levels per block
+    std::vector<long long> off(nblocks), goff(nblocks);
+    long long nc = 0, ng = 0, nm = 0;
+    for (int k = 0; k < nblocks; ++k) {
+        off[k] = nc;
+        goff[k] = ng;
+        nc += (long long)nx[k] * ny[k];
+        ng += 2LL * nx[k] + 2LL * ny[k];
+        nm += 6LL * (nx[k] + 1) + 4LL * (ny[k] + 1) + (nx[k] + 1) + (ny[k] + 1);
+    }
+    b->ncell = nc;
+    b->nghost = ng;
+    std::vector<int> order(nblocks);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (long long)nx[a] * ny[a] > (long long)nx[c] * ny[c];
+    });
+    b->hb.resize(nblocks);
+    long long lo = 0;
+    for (int r = 0; r < nblocks; ++r) {
+        const int k = order[r];
+        BBlock& B = b->hb[r];
+        std::memset(&B, 0, sizeof(BBlock));
+        B.nx = nx[k];
+        B.ny = ny[k];
+        B.id = k;
+        B.off = off[k];
+        B.goff = goff[k];
+        int lx = nx[k], ly = ny[k], L = 0;
+        while (true) {
+            if (L >= kBMaxLev) return fail(FLD_EINVAL, "too many multigrid levels");
+            B.lnx[L] = lx;
+            B.lny[L] = ly;
+            B.loff[L] = lo;
+            lo += (long long)lx * ly;
+            ++L;
+            if ((long long)lx * ly <= o.mg_coarse_max) break;
+            lx = (lx + 1) / 2;
+            ly = (ly + 1) / 2;
+        }
+        B.nlev = L;
+    }
+    b->nlev = lo;
+#define BALLOC(p, cnt) \
+    if (b->alloc(&(p), (size_t)(cnt)) != hipSuccess) return fail(FLD_ENOMEM, "hipMalloc " #p)
+    BALLOC(b->We, nc); BALLOC(b->Wn, nc); BALLOC(b->m, nc); BALLOC(b->rhs, nc); BALLOC(b->s, nc);
+    BALLOC(b->r64, nc);
+    const size_t ts = inner_float(b) ? sizeof(float) : sizeof(double);
+    unsigned char *lm, *lWe, *lWn, *lx, *lbv, *xi, *pp, *qq;
+    BALLOC(lm, lo * ts); BALLOC(lWe, lo * ts); BALLOC(lWn, lo * ts); BALLOC(lx, lo * ts); BALLOC(lbv, lo * ts);
+    BALLOC(xi, nc * ts); BALLOC(pp, nc * ts); BALLOC(qq, nc * ts);
+    b->lm = lm; b->lWe = lWe; b->lWn = lWn; b->lx = lx; b->lb = lbv; b->xi = xi; b->p = pp; b->q = qq;
+    double* met = nullptr;
+    BALLOC(met, nm);
+    BALLOC(b->db, nblocks);
+    BALLOC(b->dinfo, nblocks);
+#undef BALLOC
+    if (hipHostMalloc((void**)&b->hinfo, sizeof(BInfo) * nblocks, hipHostMallocDefault) != hipSuccess)
+        return fail(FLD_ENOMEM, "pinned block records");
+    // metrics of every block: faces i * dx, the single-grid metric kernel
+    std::vector<double> hf;
+    std::vector<long long> mo(nblocks);
+    {
+        long long mp = 0;
+        for (int k = 0; k < nblocks; ++k) {
+            mo[k] = mp;
+            mp += 6LL * (nx[k] + 1) + 4LL * (ny[k] + 1) + (nx[k] + 1) + (ny[k] + 1);
+        }
+        hf.assign(mp, 0.0);
+        for (int k = 0; k < nblocks; ++k) {
+            const long long f0 = mo[k] + 6LL * (nx[k] + 1) + 4LL * (ny[k] + 1);
+            for (int i = 0; i <= nx[k]; ++i) hf[f0 + i] = dx[k] * (double)i;
+            for (int j = 0; j <= ny[k]; ++j) hf[f0 + nx[k] + 1 + j] = dy[k] * (double)j;
+        }
+    }
+    if (hipMemcpy(met, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FLD_EHIP, "copy faces");
+    std::vector<Metrics> mets(nblocks);
+    for (int k = 0; k < nblocks; ++k) {
+        const int X = nx[k], Y = ny[k];
+        double* q0 = met + mo[k];
+        double *vx = q0, *ax = vx + (X + 1), *arc = ax + (X + 1), *sx = arc + (X + 1), *hxL = sx + (X + 1),
+               *hxR = hxL + (X + 1);
+        double *vy = hxR + (X + 1), *sy = vy + (Y + 1), *hyL = sy + (Y + 1), *hyR = hyL + (Y + 1);
+        const double* xf = hyR + (Y + 1);
+        const double* yf = xf + (X + 1);
+        mets[k] = Metrics{X, Y, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR, arc};
+        const int mt = std::max(X, Y) + 1;
+        k_metrics<<<(mt + 255) / 256, 256, 0, b->stream>>>(0, X, Y, xf, yf, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR,
+                                                           arc);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+        return fail(FLD_EHIP, "metrics kernels");
+    for (auto& B : b->hb) B.met = mets[B.id];
+    if (hipMemcpy(b->db, b->hb.data(), sizeof(BBlock) * nblocks, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FLD_EHIP, "copy block table");
+    if (hipMemset(b->xi, 0, nc * ts) != hipSuccess) return fail(FLD_EHIP, "memset");
+    hipError_t e;
+    if (inner_float(b)) {
+        e = set_lds<float, 256>();
+        if (e == hipSuccess) e = set_lds<float, 512>();
+        if (e == hipSuccess) e = set_lds<float, 1024>();
+    } else {
+        e = set_lds<double, 256>();
+        if (e == hipSuccess) e = set_lds<double, 512>();
+        if (e == hipSuccess) e = set_lds<double, 1024>();
+    }
+    if (e != hipSuccess) return fail(FLD_EHIP, "LDS size attribute");
+    *out = b;
+    return FLD_OK;
+}
+
+fld_status fld_batch_step(fld_batch* b, double* E, double* T, const double* rho, const double* kR, const double* kP,
+                          const double* cv, const double* ghost, double dt, fld_solve_info* per_block) {
+    if (!b) return FLD_EINVAL;
+    fld_status s = check_fields(b, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    auto t0 = std::chrono::steady_clock::now();
+    launch(b, fields(b, E, T, rho, kR, kP, cv, ghost, dt), b->dinfo, b->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        b->err = std::string("batch kernel: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    if (!per_block) return FLD_OK;
+    if (hipMemcpyAsync(b->hinfo, b->dinfo, sizeof(BInfo) * b->nb, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->err = "batch records";
+        return FLD_EHIP;
+    }
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < b->nb; ++k) {
+        b->hinfo[k].ms = ms;
+        std::memcpy(&per_block[k], &b->hinfo[k], sizeof(BInfo));
+    }
+    return first_bad(b->hinfo, b->nb);
+}
+
+fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
+                           const double* kP, const double* cv, const double* ghost, double dt,
+                           fld_solve_info* per_block) {
+    if (!b) return FLD_EINVAL;
+    if (nsteps < 0) { b->err = "nsteps < 0"; return FLD_EINVAL; }
+    if (nsteps == 0) return FLD_OK;
+    fld_status s = check_fields(b, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    BInfo* dall = nullptr;
+    if (hipMalloc(&dall, sizeof(BInfo) * (size_t)b->nb * nsteps) != hipSuccess) {
+        b->err = "hipMalloc step records";
+        return FLD_ENOMEM;
+    }
+    const BFields f = fields(b, E, T, rho, kR, kP, cv, ghost, dt);
+    fld_status st = FLD_OK;
+    auto t0 = std::chrono::steady_clock::now();
+    if (b->opt.use_graph) {
+        // every step is one kernel node; the nsteps nodes form one graph
+        hipStream_t cs = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < nsteps; ++k) launch(b, f, dall + (size_t)k * b->nb, cs);
+            e = hipStreamEndCapture(cs, &g);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ge, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            b->err = std::string("batch graph: ") + hipGetErrorString(e);
+            st = FLD_EHIP;
+        }
+    } else {
+        for (int k = 0; k < nsteps; ++k) launch(b, f, dall + (size_t)k * b->nb, b->stream);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) {
+            b->err = "batch kernels";
+            st = FLD_EHIP;
+        }
+    }
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::vector<BInfo> h;
+    if (st == FLD_OK) {
+        h.resize((size_t)b->nb * nsteps);
+        if (hipMemcpy(h.data(), dall, sizeof(BInfo) * h.size(), hipMemcpyDeviceToHost) != hipSuccess) st = FLD_EHIP;
+    }
+    (void)hipFree(dall);
+    if (st != FLD_OK) return st;
+    for (int k = 0; k < nsteps && st == FLD_OK; ++k) st = first_bad(h.data() + (size_t)k * b->nb, b->nb);
+    if (per_block) {
+        const BInfo* last = h.data() + (size_t)(nsteps - 1) * b->nb;
+        for (int k = 0; k < b->nb; ++k) {
+            std::memcpy(&per_block[k], &last[k], sizeof(BInfo));
+            per_block[k].ms = ms / nsteps;
+        }
+    }
+    return st;
+}
+
+fld_status fld_batch_set_threads(fld_batch* b, int32_t threads) {
+    if (!b) return FLD_EINVAL;
+    if (threads != 256 && threads != 512 && threads != 1024) {
+        b->err = "threads must be 256, 512 or 1024";
+        return FLD_EINVAL;
+    }
+    b->threads = threads;
+    return FLD_OK;
+}
+
+fld_status fld_batch_get_threads(const fld_batch* b, int32_t* threads) {
+    if (!b || !threads) return FLD_EINVAL;
+    *threads = b->threads;
+    return FLD_OK;
+}
+
+fld_status fld_batch_sizes(const fld_batch* b, int64_t* cells, int64_t* ghosts) {
+    if (!b) return FLD_EINVAL;
+    if (cells) *cells = b->ncell;
+    if (ghosts) *ghosts = b->nghost;
+    return FLD_OK;
+}
+
+const char* fld_batch_last_error(const fld_batch* b) { return b ? b->err.c_str() : t_create_err.c_str(); }
+
+void fld_batch_destroy(fld_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -140,7 +140,7 @@ __device__ inline double theta_offset(double a, double h) {
 // volume-centre radius r_c = 3/4 (r+ + r-)(r+^2 + r-^2) / (r+^2 + r+ r- + r-^2)
 // with r_c - r- = dr (6 r-^2 + 8 r- dr + 3 dr^2) / (4 (r+^2 + r+ r- + r-^2)),
 // cos th- - cos th+ = 2 sin((th- + th+)/2) sin(dth/2).
-__global__ void k_metrics(int geom, int nx, int ny, const double* __restrict__ xf, const double* __restrict__ yf,
+static __global__ void k_metrics(int geom, int nx, int ny, const double* __restrict__ xf, const double* __restrict__ yf,
                           double* vx, double* vy, double* sx, double* sy, double* ax, double* hxL, double* hxR,
                           double* hyL, double* hyR, double* arc) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,7 +268,7 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
 // One thread per cell computes its four faces (each interior face is computed
 // identically by its two cells, so the matrix is exactly symmetric), the
 // boundary terms and the cell terms C_V, beta, f.
-__global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut out) {
+static __global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut out) {
     const int i = blockIdx.x * TBX + threadIdx.x;
     const int j = blockIdx.y * TBY + threadIdx.y;
     const int nx = g.nx, ny = g.ny;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_assemble(Metrics g, AsmIn in, AsmOut ou
 }
 
 // Full diagonal and copies of the FP64 operator (test access).
-__global__ void k_get_operator(int nx, int ny, const double* We, const double* Wn, const double* m,
+static __global__ void k_get_operator(int nx, int ny, const double* We, const double* Wn, const double* m,
                                const double* rhs, double* oWe, double* oWn, double* odiag, double* orhs) {
     const int i = blockIdx.x * TBX + threadIdx.x;
     const int j = blockIdx.y * TBY + threadIdx.y;
@@ -298,7 +298,7 @@ __global__ void k_get_operator(int nx, int ny, const double* We, const double* W
 // ---------------------------------------------------------------------------
 // gas update (Section 3.2.1: psi_5, psi_6, psi_11)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gas_update(int n, const double* __restrict__ E, const double* __restrict__ Tn,
+static __global__ __launch_bounds__(256) void k_gas_update(int n, const double* __restrict__ E, const double* __restrict__ Tn,
                                                     const double* __restrict__ rho, const double* __restrict__ kP,
                                                     const double* __restrict__ cv, double dt, double* __restrict__ Tout) {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {

@@ -235,7 +235,7 @@ void fld_destroy(fld_ctx* ctx);
  * Batched blocks (Section 3.3, static mesh refinement: every block is an
  * independent grid whose boundaries are ghost cells filled from its parent
  * or neighbours).  A batch holds nblocks Cartesian blocks of nx[b] x ny[b]
- * cells (1 .. 1024 per side) with uniform spacing dx[b], dy[b] (cm; faces at
+ * cells (1 .. 512 per side) with uniform spacing dx[b], dy[b] (cm; faces at
  * i dx[b], j dy[b]).  Fields are packed block after block, each block
  * row-major [ny][nx] (device doubles, sum nx ny in total); ghost_E packs
  * 2 ny + 2 nx values per block in the side order of fld_bc, block after
@@ -260,8 +260,9 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
 /* One implicit step of every block, E_r and T_g updated in place (packed
  * device arrays).  per_block (host, nblocks entries, caller's block order)
  * may be NULL: then the call is asynchronous and returns OK once launched;
- * otherwise it synchronises, fills the records (ms = wall time of the whole
- * batch) and returns the first non-OK block status.  A block that fails
+ * otherwise it synchronises, fills the records (ms = device time of the
+ * block's workgroup, from the GPU wall clock) and returns the first non-OK
+ * block status.  A block that fails
  * keeps its last iterate in E_r and its T_g unchanged; the others are not
  * affected. */
 fld_status fld_batch_step(fld_batch* b, double* E_r, double* T_g, const double* rho,
@@ -270,8 +271,8 @@ fld_status fld_batch_step(fld_batch* b, double* E_r, double* T_g, const double* 
 
 /* nsteps consecutive batch steps (fields other than E_r, T_g held fixed),
  * captured as one hipGraph of nsteps kernel nodes when use_graph is set;
- * synchronises once.  per_block receives the records of the last step (ms =
- * mean time per step); returns the first non-OK status of any block in any
+ * synchronises once.  per_block receives the records of the last step;
+ * returns the first non-OK status of any block in any
  * step (failed blocks continue with the next step). */
 fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                            const double* kappa_R, const double* kappa_P, const double* c_v,

@@ -39,6 +39,7 @@ struct fld_batch {
     BInfo* dinfo = nullptr;
     BInfo* hinfo = nullptr;
     int threads = 512;
+    double clock_khz = 1e5;
 
     template <typename U>
     hipError_t alloc(U** ptr, size_t count) {
@@ -68,6 +69,7 @@ BOpts make_opts(const fld_batch* b) {
     r.delta2 = delta * delta;
     r.inner_tol2 = o.inner_rtol * o.inner_rtol;
     r.omega = o.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
+    r.clock_khz = b->clock_khz;
     r.max_iter = o.max_inner;
     r.norm = o.norm;
     r.reliable = o.precision == FLD_FP32 ? 0 : 1;
@@ -163,7 +165,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     }
     for (int k = 0; k < nblocks; ++k) {
         if (nx[k] < 1 || ny[k] < 1 || nx[k] > kBMaxSide || ny[k] > kBMaxSide)
-            return fail(FLD_EINVAL, "block sides must be in [1, 1024]");
+            return fail(FLD_EINVAL, "block sides must be in [1, 512]");
         if (!(dx[k] > 0.0) || !(dy[k] > 0.0) || !std::isfinite(dx[k]) || !std::isfinite(dy[k]))
             return fail(FLD_EINVAL, "block spacing must be finite and > 0");
     }
@@ -264,6 +266,12 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     if (hipMemcpy(b->db, b->hb.data(), sizeof(BBlock) * nblocks, hipMemcpyHostToDevice) != hipSuccess)
         return fail(FLD_EHIP, "copy block table");
     if (hipMemset(b->xi, 0, nc * ts) != hipSuccess) return fail(FLD_EHIP, "memset");
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            b->clock_khz = khz;
+    }
     hipError_t e;
     if (inner_float(b)) {
         e = set_lds<float, 256>();
@@ -284,7 +292,6 @@ fld_status fld_batch_step(fld_batch* b, double* E, double* T, const double* rho,
     if (!b) return FLD_EINVAL;
     fld_status s = check_fields(b, E, T, rho, kR, kP, cv, ghost, dt);
     if (s != FLD_OK) return s;
-    auto t0 = std::chrono::steady_clock::now();
     launch(b, fields(b, E, T, rho, kR, kP, cv, ghost, dt), b->dinfo, b->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -297,11 +304,7 @@ fld_status fld_batch_step(fld_batch* b, double* E, double* T, const double* rho,
         b->err = "batch records";
         return FLD_EHIP;
     }
-    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (int k = 0; k < b->nb; ++k) {
-        b->hinfo[k].ms = ms;
-        std::memcpy(&per_block[k], &b->hinfo[k], sizeof(BInfo));
-    }
+    for (int k = 0; k < b->nb; ++k) std::memcpy(&per_block[k], &b->hinfo[k], sizeof(BInfo));
     return first_bad(b->hinfo, b->nb);
 }
 
@@ -320,7 +323,6 @@ fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, c
     }
     const BFields f = fields(b, E, T, rho, kR, kP, cv, ghost, dt);
     fld_status st = FLD_OK;
-    auto t0 = std::chrono::steady_clock::now();
     if (b->opt.use_graph) {
         // every step is one kernel node; the nsteps nodes form one graph
         hipStream_t cs = nullptr;
@@ -349,7 +351,6 @@ fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, c
             st = FLD_EHIP;
         }
     }
-    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     std::vector<BInfo> h;
     if (st == FLD_OK) {
         h.resize((size_t)b->nb * nsteps);
@@ -360,10 +361,7 @@ fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, c
     for (int k = 0; k < nsteps && st == FLD_OK; ++k) st = first_bad(h.data() + (size_t)k * b->nb, b->nb);
     if (per_block) {
         const BInfo* last = h.data() + (size_t)(nsteps - 1) * b->nb;
-        for (int k = 0; k < b->nb; ++k) {
-            std::memcpy(&per_block[k], &last[k], sizeof(BInfo));
-            per_block[k].ms = ms / nsteps;
-        }
+        for (int k = 0; k < b->nb; ++k) std::memcpy(&per_block[k], &last[k], sizeof(BInfo));
     }
     return st;
 }

@@ -11,13 +11,14 @@
 #pragma once
 
 #include "fld_kernels.hpp"
+#include "fld_line.hpp"
 
 namespace fld {
 
 constexpr int kBMaxLev = 12;       // multigrid levels per block
 constexpr int kBCoarse = 64;       // coarsest level: at most this many cells, inverted densely
 constexpr int kBLineL = 8;         // cells per thread chunk in the line solves
-constexpr int kBMaxSide = 1024;    // block side limit
+constexpr int kBMaxSide = 64 * kBLineL;  // block side limit: a line fits one wavefront
 constexpr int kBRedDoubles = 128;  // reduction scratch (5 sums x 16 waves)
 
 struct BBlock {
@@ -46,6 +47,7 @@ struct BWork {
 
 struct BOpts {
     double eps, delta2, inner_tol2, omega;
+    double clock_khz;  // rate of the device wall clock (per-block timing)
     int max_iter, norm, reliable, gas;
 };
 
@@ -62,8 +64,7 @@ struct BLds {
     static constexpr size_t ainv = kBRedDoubles * sizeof(double);
     static constexpr size_t uni = ainv + (size_t)kBCoarse * kBCoarse * sizeof(T);
     static constexpr size_t gj = sizeof(double) * ((size_t)kBCoarse * kBCoarse + kBCoarse);
-    static constexpr size_t line = 7 * (size_t)NT * sizeof(T);
-    static constexpr size_t bytes = uni + (gj > line ? gj : line);
+    static constexpr size_t bytes = uni + gj;
 };
 
 // Workgroup sums / maximum, the result in every thread (fixed order: deterministic).
@@ -100,192 +101,108 @@ __device__ inline double wg_max(double v, double* red) {
     return r;
 }
 
-enum { BL_NORMAL = 0, BL_ZERO = 1, BL_PROLONG = 2 };
-
-// One zebra half-sweep of line Gauss-Seidel over a level of one block: every
-// line of parity `par` along direction `dir` (0: rows, cells along x; 1:
-// columns, cells along y) is solved exactly,
-//   (m + sum W) x - W_prev x_prev - W_next x_next = b + W_c- x_c- + W_c+ x_c+,
-// with the two neighbour lines taken from x (BL_ZERO: zero; BL_PROLONG: x plus
-// the piecewise-constant coarse correction ec).  A line is split into K
-// chunks of at most kBLineL cells, one per thread: chunk interiors are
-// eliminated locally (three right-hand sides), the K interface unknowns of a
-// line are solved by parallel cyclic reduction in LDS, and back-substitution
-// completes the chunk.  Lines are processed NT / K at a time.
-template <typename T, int NT, int MODE>
-__device__ void b_line(int nx, int ny, int dir, int par, const T* __restrict__ m, const T* __restrict__ We,
-                       const T* __restrict__ Wn, const T* __restrict__ b, T* __restrict__ x,
-                       const T* __restrict__ ec, int nxc, T* lds) {
-    const int na = dir ? ny : nx, nlines = dir ? nx : ny;
-    const long long sa = dir ? nx : 1, sl = dir ? 1 : nx;
-    const T* __restrict__ Wa = dir ? Wn : We;  // coupling to the next cell along the line
-    const T* __restrict__ Wc = dir ? We : Wn;  // coupling to the next line
-    const int nl = (nlines - par + 1) / 2;
-    if (nl <= 0) return;
-    int K = 1;
-    while (K * kBLineL < na) K <<= 1;
-    const int L = max(2, (na + K - 1) / K);
-    const int lpp = NT / K;
-    T *sA = lds, *sB = lds + NT, *sC = lds + 2 * NT, *sR = lds + 3 * NT;
-    T *sy0 = lds + 4 * NT, *su0 = lds + 5 * NT, *sv0 = lds + 6 * NT;
-    const int t = threadIdx.x, k = t % K, s0 = k * L;
-    constexpr int LM = kBLineL;
-    for (int q0 = 0; q0 < nl; q0 += lpp) {
-        const int ql = q0 + t / K;
-        const bool active = ql < nl;
-        const int line = 2 * ql + par;
-        const long long lb = (long long)(active ? line : 0) * sl;
-        auto coarse = [&](int ln, int pos) -> T {
-            const int i = dir ? ln : pos, j = dir ? pos : ln;
-            return ec[(long long)(j >> 1) * nxc + (i >> 1)];
-        };
-        T vm[LM], va[LM], vcn[LM], vcs[LM], vb[LM], vxn[LM], vxs[LM];
-        const T wprev = (active && s0 > 0 && s0 - 1 < na) ? Wa[lb + (long long)(s0 - 1) * sa] : T(0);
+// Loop over the n cells of a block, U cells per thread per round: the loads
+// of all U cells (ld) are issued before any result is stored (st), so U
+// memory round trips overlap.  Per thread, cells are visited in increasing
+// order (t, t + NT, ...), which keeps partial sums in a fixed order.
+template <int NT, int U, class Ld, class St>
+__device__ inline void cells(int n, Ld ld, St st) {
+    using S = decltype(ld(0));
+    for (int c0 = threadIdx.x; c0 < n; c0 += NT * U) {
+        S v[U];
 #pragma unroll
-        for (int q = 0; q < LM; ++q) {
-            const int g = s0 + q;
-            const bool ok = active && q < L && g < na;
-            const long long c = lb + (long long)g * sa;
-            vm[q] = ok ? m[c] : T(1);
-            va[q] = ok ? Wa[c] : T(0);
-            vcn[q] = ok ? Wc[c] : T(0);
-            vcs[q] = (ok && line > 0) ? Wc[c - sl] : T(0);
-            vb[q] = ok ? b[c] : T(0);
-            T xn = T(0), xs = T(0);
-            if (MODE != BL_ZERO && ok) {
-                if (line + 1 < nlines) {
-                    xn = x[c + sl];
-                    if (MODE == BL_PROLONG) xn += coarse(line + 1, g);
-                }
-                if (line > 0) {
-                    xs = x[c - sl];
-                    if (MODE == BL_PROLONG) xs += coarse(line - 1, g);
-                }
-            }
-            vxn[q] = xn;
-            vxs[q] = xs;
-        }
-        auto coef = [&](int q, T& a, T& d, T& c, T& r) {
-            const T wp = (q == 0) ? wprev : va[q > 0 ? q - 1 : 0];
-            d = vm[q] + ((wp + va[q]) + (vcs[q] + vcn[q]));
-            a = -wp;
-            c = -va[q];
-            r = vb[q] + vcn[q] * vxn[q] + vcs[q] * vxs[q];
-        };
-        // chunk interior (local 0 .. L-2): every unknown as y + u X_prev + v X_own
-        T cp[LM], gy[LM], gu[LM], gv[LM];
-#pragma unroll
-        for (int q = 0; q < LM - 1; ++q) {
-            if (q < L - 1) {
-                T a, d, c, r;
-                coef(q, a, d, c, r);
-                const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
-                const T inv = T(1) / den;
-                cp[q] = c * inv;
-                gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
-                gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
-                const T rv = (q == L - 2) ? -c : T(0);
-                gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
-            }
+        for (int k = 0; k < U; ++k) {
+            const int c = c0 + k * NT;
+            if (c < n) v[k] = ld(c);
         }
 #pragma unroll
-        for (int q = LM - 3; q >= 0; --q) {
-            if (q < L - 2) {
-                gy[q] -= cp[q] * gy[q + 1];
-                gu[q] -= cp[q] * gu[q + 1];
-                gv[q] -= cp[q] * gv[q + 1];
-            }
+        for (int k = 0; k < U; ++k) {
+            const int c = c0 + k * NT;
+            if (c < n) st(c, v[k]);
         }
-        // interface row (local L-1) in the interface unknowns X_{k-1}, X_k, X_{k+1}
-        T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
-#pragma unroll
-        for (int q = 0; q < LM; ++q)
-            if (q == L - 1) coef(q, aE, dE, cE, rE);
-        T yl = T(0), ul = T(0), vl = T(0);
-#pragma unroll
-        for (int q = 0; q < LM - 1; ++q)
-            if (q == L - 2) {
-                yl = gy[q];
-                ul = gu[q];
-                vl = gv[q];
-            }
-        sy0[t] = gy[0];
-        su0[t] = gu[0];
-        sv0[t] = gv[0];
-        __syncthreads();
-        const bool has_next = k + 1 < K;
-        const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0);
-        const T vn = has_next ? sv0[t + 1] : T(0);
-        sA[t] = aE * ul;
-        sB[t] = dE + aE * vl + cE * un;
-        sC[t] = cE * vn;
-        sR[t] = rE - aE * yl - cE * yn;
-        __syncthreads();
-        for (int st = 1; st < K; st <<= 1) {
-            const T a = sA[t], bb = sB[t], c = sC[t], r = sR[t];
-            T na_ = T(0), nb_ = bb, nc_ = T(0), nr_ = r;
-            if (k - st >= 0) {
-                const T al = -a / sB[t - st];
-                na_ = al * sA[t - st];
-                nb_ += al * sC[t - st];
-                nr_ += al * sR[t - st];
-            }
-            if (k + st < K) {
-                const T ga = -c / sB[t + st];
-                nc_ = ga * sC[t + st];
-                nb_ += ga * sA[t + st];
-                nr_ += ga * sR[t + st];
-            }
-            __syncthreads();
-            sA[t] = na_;
-            sB[t] = nb_;
-            sC[t] = nc_;
-            sR[t] = nr_;
-            __syncthreads();
-        }
-        const T X = sR[t] / sB[t];
-        __syncthreads();
-        sR[t] = X;
-        __syncthreads();
-        const T Xp = k > 0 ? sR[t - 1] : T(0);
-        if (active) {
-#pragma unroll
-            for (int q = 0; q < LM; ++q) {
-                const int g = s0 + q;
-                if (q < L && g < na) {
-                    const T v = (q == L - 1) ? X
-                                             : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
-                                                   gv[q < LM - 1 ? q : 0] * X;
-                    x[lb + (long long)g * sa] = v;
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 
-// Residual b - A x (flux form) of a level summed over 2x2 aggregates: the
-// right-hand side of the next coarser level.
+template <typename T>
+struct V2 {
+    T a, b;
+};
+template <typename T>
+struct V4 {
+    T a, b, c, d;
+};
+
+// One zebra half-sweep of a level of one block (dir 0: rows, 1: columns),
+// lines spread over the workgroup's wavefronts, then a barrier.  Not inlined:
+// the kernel runs one copy of the sweep code for every level and direction,
+// which keeps it resident in the instruction cache.
 template <typename T, int NT>
-__device__ void b_restrict(int nx, int ny, const T* __restrict__ m, const T* __restrict__ We,
+__device__ __attribute__((noinline)) void b_sweep(int nx, int ny, int dir, int par, int zero, const T* m,
+                                                  const T* We, const T* Wn, const T* b, T* x) {
+    const int na = dir ? ny : nx, nl = dir ? nx : ny;
+    const long long sa = dir ? nx : 1, sl = dir ? 1 : nx;
+    const T* Wa = dir ? Wn : We;
+    const T* Wc = dir ? We : Wn;
+    if (zero)
+        wave_line_sweep<T, kBLineL, true>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
+    else
+        wave_line_sweep<T, kBLineL, false>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
+    __syncthreads();
+}
+
+// Residual b - A x (flux form) of a level summed over 2x2 aggregates: the
+// right-hand side of the next coarser level.  One coarse cell per thread, the
+// loads of its (up to) four fine cells issued together.
+template <typename T, int NT>
+__device__ __attribute__((noinline)) void b_restrict(int nx, int ny, const T* __restrict__ m, const T* __restrict__ We,
                            const T* __restrict__ Wn, const T* __restrict__ b, const T* __restrict__ x,
                            T* __restrict__ bc, int nxc, int nyc) {
-    for (int C = threadIdx.x; C < nxc * nyc; C += NT) {
-        const int I = C % nxc, J = C / nxc;
-        T sum = T(0);
-        for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
-            for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) {
+    struct Q {
+        T v[4][11];  // per fine cell: x, x_e, x_w, x_n, x_s, W_e, W_w, W_n, W_s, m, b
+    };
+    cells<NT, (sizeof(T) == 4 ? 2 : 1)>(
+        nxc * nyc,
+        [&](int C) {
+            Q q;
+            const int I = C % nxc, J = C / nxc;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int i = 2 * I + (a & 1), j = 2 * J + (a >> 1);
+                const bool ok = i < nx && j < ny;
                 const long long c = (long long)j * nx + i;
-                const T xc = x[c];
-                T fl = T(0);
-                if (i + 1 < nx) fl += We[c] * (xc - x[c + 1]);
-                if (i > 0) fl += We[c - 1] * (xc - x[c - 1]);
-                if (j + 1 < ny) fl += Wn[c] * (xc - x[c + nx]);
-                if (j > 0) fl += Wn[c - nx] * (xc - x[c - nx]);
-                sum += b[c] - m[c] * xc - fl;
+                T* v = q.v[a];
+                v[0] = ok ? x[c] : T(0);
+                v[1] = (ok && i + 1 < nx) ? x[c + 1] : T(0);
+                v[2] = (ok && i > 0) ? x[c - 1] : T(0);
+                v[3] = (ok && j + 1 < ny) ? x[c + nx] : T(0);
+                v[4] = (ok && j > 0) ? x[c - nx] : T(0);
+                v[5] = ok ? We[c] : T(0);
+                v[6] = (ok && i > 0) ? We[c - 1] : T(0);
+                v[7] = ok ? Wn[c] : T(0);
+                v[8] = (ok && j > 0) ? Wn[c - nx] : T(0);
+                v[9] = ok ? m[c] : T(0);
+                v[10] = ok ? b[c] : T(0);
             }
-        bc[C] = sum;
-    }
+            return q;
+        },
+        [&](int C, const Q& q) {
+            const int I = C % nxc, J = C / nxc;
+            T sum = T(0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int i = 2 * I + (a & 1), j = 2 * J + (a >> 1);
+                if (i >= nx || j >= ny) continue;
+                const T* v = q.v[a];
+                const T xc = v[0];
+                T fl = T(0);
+                if (i + 1 < nx) fl += v[5] * (xc - v[1]);
+                if (i > 0) fl += v[6] * (xc - v[2]);
+                if (j + 1 < ny) fl += v[7] * (xc - v[3]);
+                if (j > 0) fl += v[8] * (xc - v[4]);
+                sum += v[10] - v[9] * xc - fl;
+            }
+            bc[C] = sum;
+        });
 }
 
 // 2x2 aggregation: masses summed, the conductances crossing between two
@@ -356,7 +273,7 @@ __device__ void b_coarse_setup(int nx, int ny, const T* __restrict__ m, const T*
 }
 
 template <typename T, int NT>
-__device__ void b_coarse_solve(int n, const T* ainv, const T* __restrict__ b, T* __restrict__ x) {
+__device__ __attribute__((noinline)) void b_coarse_solve(int n, const T* ainv, const T* __restrict__ b, T* __restrict__ x) {
     for (int c = threadIdx.x; c < n; c += NT) {
         T s = T(0);
         for (int k = 0; k < n; ++k) s += ainv[c * n + k] * b[k];
@@ -366,10 +283,11 @@ __device__ void b_coarse_solve(int n, const T* ainv, const T* __restrict__ b, T*
 }
 
 // z = V(r): one V-cycle from a zero start; r is the fine level's b array and z
-// its x array.  Pre-smoothing: rows (even, odd), columns (even, odd); post-
-// smoothing in the reverse order, so the preconditioner is symmetric.
+// its x array.  Pre-smoothing: rows (even, odd), columns (even, odd); the
+// coarse correction (piecewise constant) is added, then post-smoothing runs in
+// the reverse order, so the preconditioner is symmetric.
 template <typename T, int NT>
-__device__ void b_vcycle(const BBlock& B, const BWork<T>& w, const T* ainv, T* lds) {
+__device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, const T* ainv) {
     const int Lv = B.nlev;
     if (Lv == 1) {
         const long long o = B.loff[0];
@@ -381,10 +299,10 @@ __device__ void b_vcycle(const BBlock& B, const BWork<T>& w, const T* ainv, T* l
         const long long o = B.loff[l], oc = B.loff[l + 1];
         const T *m = w.lm + o, *We = w.lWe + o, *Wn = w.lWn + o, *b = w.lb + o;
         T* x = w.lx + o;
-        b_line<T, NT, BL_ZERO>(nx, ny, 0, 0, m, We, Wn, b, x, nullptr, 0, lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 0, 1, m, We, Wn, b, x, nullptr, 0, lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 1, 0, m, We, Wn, b, x, nullptr, 0, lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 1, 1, m, We, Wn, b, x, nullptr, 0, lds);
+        b_sweep<T, NT>(nx, ny, 0, 0, 1, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
         b_restrict<T, NT>(nx, ny, m, We, Wn, b, x, w.lb + oc, B.lnx[l + 1], B.lny[l + 1]);
         __syncthreads();
     }
@@ -393,14 +311,23 @@ __device__ void b_vcycle(const BBlock& B, const BWork<T>& w, const T* ainv, T* l
         b_coarse_solve<T, NT>(B.lnx[Lv - 1] * B.lny[Lv - 1], ainv, w.lb + o, w.lx + o);
     }
     for (int l = Lv - 2; l >= 0; --l) {
-        const int nx = B.lnx[l], ny = B.lny[l];
+        const int nx = B.lnx[l], ny = B.lny[l], nxc = B.lnx[l + 1];
         const long long o = B.loff[l], oc = B.loff[l + 1];
         const T *m = w.lm + o, *We = w.lWe + o, *Wn = w.lWn + o, *b = w.lb + o;
         T* x = w.lx + o;
-        b_line<T, NT, BL_PROLONG>(nx, ny, 1, 1, m, We, Wn, b, x, w.lx + oc, B.lnx[l + 1], lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 1, 0, m, We, Wn, b, x, nullptr, 0, lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 0, 1, m, We, Wn, b, x, nullptr, 0, lds);
-        b_line<T, NT, BL_NORMAL>(nx, ny, 0, 0, m, We, Wn, b, x, nullptr, 0, lds);
+        const T* ec = w.lx + oc;
+        cells<NT, 8>(
+            nx * ny,
+            [&](int c) {
+                const int i = c % nx, j = c / nx;
+                return V2<T>{x[c], ec[(long long)(j >> 1) * nxc + (i >> 1)]};
+            },
+            [&](int c, const V2<T>& v) { x[c] = v.a + v.b; });
+        __syncthreads();
+        b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+        b_sweep<T, NT>(nx, ny, 0, 0, 0, m, We, Wn, b, x);
     }
 }
 
@@ -414,10 +341,10 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
     using Lay = BLds<T, NT>;
     double* red = reinterpret_cast<double*>(b_smem + Lay::red);
     T* ainv = reinterpret_cast<T*>(b_smem + Lay::ainv);
-    T* lds = reinterpret_cast<T*>(b_smem + Lay::uni);
     double* gjA = reinterpret_cast<double*>(b_smem + Lay::uni);
     double* gjc = gjA + kBCoarse * kBCoarse;
 
+    const long long t_start = wall_clock64();
     const BBlock& B = blocks[blockIdx.x];
     const int nx = B.nx, ny = B.ny, n = nx * ny, t = threadIdx.x;
     const long long off = B.off;
@@ -480,32 +407,54 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
         // true FP64 residual, stop rule, re-scaled inner residual
         auto check = [&](bool force) {
             if (!force) {
-                for (int c = t; c < n; c += NT) {
-                    E[c] += corr * (double)xi[c];
-                    xi[c] = T(0);
-                }
+                cells<NT, 8>(
+                    n, [&](int c) { return V2<double>{E[c], (double)xi[c]}; },
+                    [&](int c, const V2<double>& v) {
+                        E[c] = v.a + corr * v.b;
+                        xi[c] = T(0);
+                    });
                 __syncthreads();
             }
             double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int c = t; c < n; c += NT) {
-                const int i = c % nx, j = c / nx;
-                const double e = E[c];
-                double flux = 0.0;
-                if (i + 1 < nx) flux += We64[c] * (e - E[c + 1]);
-                if (i > 0) flux += We64[c - 1] * (e - E[c - 1]);
-                if (j + 1 < ny) flux += Wn64[c] * (e - E[c + nx]);
-                if (j > 0) flux += Wn64[c - nx] * (e - E[c - nx]);
-                const double bb = rhs[c];
-                const double res = bb - m64[c] * e - flux;
-                r64[c] = res;
-                const double dV = g.vx[i] * g.vy[j];
-                const double sv = s64[c];
-                a[0] += (res / dV) * (res / dV);
-                a[1] += (sv * res) * (sv * res);
-                a[2] += (bb / dV) * (bb / dV);
-                a[3] += (sv * bb) * (sv * bb);
-                a[4] += res * res;
-            }
+            struct Res {
+                double e, ee, ew, en, es, we, ww, wn, ws, bb, mm, dV, sv;
+                int i, j;
+            };
+            cells<NT, 2>(
+                n,
+                [&](int c) {
+                    Res v;
+                    v.i = c % nx;
+                    v.j = c / nx;
+                    v.e = E[c];
+                    v.ee = v.i + 1 < nx ? E[c + 1] : 0.0;
+                    v.ew = v.i > 0 ? E[c - 1] : 0.0;
+                    v.en = v.j + 1 < ny ? E[c + nx] : 0.0;
+                    v.es = v.j > 0 ? E[c - nx] : 0.0;
+                    v.we = We64[c];
+                    v.ww = v.i > 0 ? We64[c - 1] : 0.0;
+                    v.wn = Wn64[c];
+                    v.ws = v.j > 0 ? Wn64[c - nx] : 0.0;
+                    v.bb = rhs[c];
+                    v.mm = m64[c];
+                    v.dV = g.vx[v.i] * g.vy[v.j];
+                    v.sv = s64[c];
+                    return v;
+                },
+                [&](int c, const Res& v) {
+                    double flux = 0.0;
+                    if (v.i + 1 < nx) flux += v.we * (v.e - v.ee);
+                    if (v.i > 0) flux += v.ww * (v.e - v.ew);
+                    if (v.j + 1 < ny) flux += v.wn * (v.e - v.en);
+                    if (v.j > 0) flux += v.ws * (v.e - v.es);
+                    const double res = v.bb - v.mm * v.e - flux;
+                    r64[c] = res;
+                    a[0] += (res / v.dV) * (res / v.dV);
+                    a[1] += (v.sv * res) * (v.sv * res);
+                    a[2] += (v.bb / v.dV) * (v.bb / v.dV);
+                    a[3] += (v.sv * v.bb) * (v.sv * v.bb);
+                    a[4] += res * res;
+                });
             wg_sum<NT, 5>(a, red);
             const double rrow = a[2] > 0.0 ? sqrt(a[0] / a[2]) : sqrt(a[0]);
             const double rsc = a[3] > 0.0 ? sqrt(a[1] / a[3]) : sqrt(a[1]);
@@ -544,18 +493,22 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
             }
             if (demote) {
                 const double ig = 1.0 / gamma;
-                for (int c = t; c < n; c += NT) {
-                    r[c] = (T)(r64[c] * ig);
-                    xi[c] = T(0);
-                }
+                cells<NT, 8>(
+                    n, [&](int c) { return r64[c]; },
+                    [&](int c, double v) {
+                        r[c] = (T)(v * ig);
+                        xi[c] = T(0);
+                    });
                 __syncthreads();
             }
         };
         // z = V(r), then r.z and beta
         auto precondition = [&]() {
-            b_vcycle<T, NT>(B, w, ainv, lds);
+            b_vcycle<T, NT>(B, w, ainv);
             double a[1] = {0.0};
-            for (int c = t; c < n; c += NT) a[0] += (double)r[c] * (double)z[c];
+            cells<NT, 8>(
+                n, [&](int c) { return V2<T>{r[c], z[c]}; },
+                [&](int, const V2<T>& v) { a[0] += (double)v.a * (double)v.b; });
             wg_sum<NT, 1>(a, red);
             const double rz = a[0];
             if (!(rz > 0.0) || !isfinite(rz)) {
@@ -572,21 +525,43 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
         while (!done) {
             const bool first = iter == 0 || restart;
             const T bt = first ? T(0) : (T)(beta * pscale);
-            for (int c = t; c < n; c += NT) p[c] = first ? z[c] : z[c] + bt * p[c];
+            cells<NT, 8>(
+                n, [&](int c) { return V2<T>{z[c], first ? T(0) : p[c]}; },
+                [&](int c, const V2<T>& v) { p[c] = first ? v.a : v.a + bt * v.b; });
             __syncthreads();
             double a[1] = {0.0};
-            for (int c = t; c < n; c += NT) {
-                const int i = c % nx, j = c / nx;
-                const T pv = p[c];
-                T fl = T(0);
-                if (i + 1 < nx) fl += We0[c] * (pv - p[c + 1]);
-                if (i > 0) fl += We0[c - 1] * (pv - p[c - 1]);
-                if (j + 1 < ny) fl += Wn0[c] * (pv - p[c + nx]);
-                if (j > 0) fl += Wn0[c - nx] * (pv - p[c - nx]);
-                const T v = m0[c] * pv + fl;
-                q[c] = v;
-                a[0] += (double)pv * (double)v;
-            }
+            struct Sp {
+                T pv, pe, pw, pn, ps, we, ww, wn, ws, mm;
+                int i, j;
+            };
+            cells<NT, 4>(
+                n,
+                [&](int c) {
+                    Sp v;
+                    v.i = c % nx;
+                    v.j = c / nx;
+                    v.pv = p[c];
+                    v.pe = v.i + 1 < nx ? p[c + 1] : T(0);
+                    v.pw = v.i > 0 ? p[c - 1] : T(0);
+                    v.pn = v.j + 1 < ny ? p[c + nx] : T(0);
+                    v.ps = v.j > 0 ? p[c - nx] : T(0);
+                    v.we = We0[c];
+                    v.ww = v.i > 0 ? We0[c - 1] : T(0);
+                    v.wn = Wn0[c];
+                    v.ws = v.j > 0 ? Wn0[c - nx] : T(0);
+                    v.mm = m0[c];
+                    return v;
+                },
+                [&](int c, const Sp& v) {
+                    T fl = T(0);
+                    if (v.i + 1 < nx) fl += v.we * (v.pv - v.pe);
+                    if (v.i > 0) fl += v.ww * (v.pv - v.pw);
+                    if (v.j + 1 < ny) fl += v.wn * (v.pv - v.pn);
+                    if (v.j > 0) fl += v.ws * (v.pv - v.ps);
+                    const T qv = v.mm * v.pv + fl;
+                    q[c] = qv;
+                    a[0] += (double)v.pv * (double)qv;
+                });
             wg_sum<NT, 1>(a, red);
             const double pq = a[0];
             if (!(pq > 0.0) || !isfinite(pq)) {
@@ -598,12 +573,14 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
             pscale = 1.0;
             restart = 0;
             a[0] = 0.0;
-            for (int c = t; c < n; c += NT) {
-                xi[c] += al * p[c];
-                const T rn = r[c] - al * q[c];
-                r[c] = rn;
-                a[0] += (double)rn * (double)rn;
-            }
+            cells<NT, 8>(
+                n, [&](int c) { return V4<T>{xi[c], p[c], r[c], q[c]}; },
+                [&](int c, const V4<T>& v) {
+                    xi[c] = v.a + al * v.b;
+                    const T rn = v.c - al * v.d;
+                    r[c] = rn;
+                    a[0] += (double)rn * (double)rn;
+                });
             wg_sum<NT, 1>(a, red);
             rr = a[0];
             iter += 1;
@@ -624,10 +601,12 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
             precondition();
         }
         // final correction with the accumulated inner solution
-        for (int c = t; c < n; c += NT) {
-            E[c] += corr * (double)xi[c];
-            xi[c] = T(0);
-        }
+        cells<NT, 8>(
+            n, [&](int c) { return V2<double>{E[c], (double)xi[c]}; },
+            [&](int c, const V2<double>& v) {
+                E[c] = v.a + corr * v.b;
+                xi[c] = T(0);
+            });
         if (status == ST_OK && !done) status = ST_ENOCONV;
         // ---- gas update (Section 3.2.1: psi_5, psi_6, psi_11)
         if (o.gas && status == ST_OK) {
@@ -651,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
         inf.rel_resid = rel_sel;
         inf.rel_resid_row = rel_row;
         inf.rel_resid_scaled = rel_sc;
-        inf.ms = 0.f;
+        inf.ms = (float)((double)(wall_clock64() - t_start) / o.clock_khz);
     }
 }
 

@@ -409,7 +409,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(ctx->alloc(&in.q, n));
     in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual
     // one-workgroup coarse sub-cycle: the finest level l >= 1 from which all
-    // coarser levels fit in LDS (5 arrays each, plus one Thomas scratch)
+    // coarser levels fit in LDS (5 arrays each) and whose lines fit one wavefront
     const int L = (int)in.lv.size();
     in.sub_first = -1;
     if (line && L >= 3) {
@@ -419,11 +419,8 @@ fld_status alloc_inner(fld_ctx* ctx) {
             lds_max = 65536;
         for (int l = 1; l < L - 1 && in.sub_first < 0; ++l) {
             if (L - l > kSubMaxLevels) continue;
-            // PCR scratch: 4 arrays over the unknowns of one parity (<= (n + line) / 2)
-            const size_t n0 = (size_t)in.lv[l].nx * in.lv[l].ny;
-            const size_t half = (n0 + std::max(in.lv[l].nx, in.lv[l].ny) + 1) / 2;
-            if (half > (size_t)kSubThreads * kSubPerThread) continue;
-            size_t need = 4 * half;
+            if (std::max(in.lv[l].nx, in.lv[l].ny) > 64 * kLineMaxL) continue;
+            size_t need = 0;
             for (int k = l; k < L; ++k) need += 5 * (size_t)(in.lv[k].nx + 1) * in.lv[k].ny;
             need *= sizeof(T);
             if (need <= (size_t)lds_max) {
@@ -441,7 +438,6 @@ fld_status alloc_inner(fld_ctx* ctx) {
                 S.lv[k] = SubLevel<T>{lv.nx, lv.ny, lv.m, lv.We, lv.Wn, off, lv.tr ? 1 : 0, pitch, pitch * lv.ny};
                 off += 5 * pitch * lv.ny;
             }
-            S.scratch = off;
             S.Ainv = in.Ainv;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,

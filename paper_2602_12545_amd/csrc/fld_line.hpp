@@ -1,0 +1,155 @@
+// Wavefront-level zebra line solve: the tridiagonal systems of a set of grid
+// lines, each owned by K lanes of one wavefront, with no workgroup barrier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fld {
+
+// Lanes per line for a line of `na` cells with at most LM cells per lane
+// (power of two, <= 64).
+template <int LM>
+__device__ inline int wave_line_lanes(int na) {
+    int K = 1;
+    while (K * LM < na) K <<= 1;
+    return K;
+}
+
+// One zebra half-sweep of line Gauss-Seidel: every line of parity `par`
+// (lines par, par + 2, ...) among `nlines` lines of `na` cells is solved
+// exactly,
+//   (m + sum W) x - W_prev x_prev - W_next x_next = b + W_c- x_c- + W_c+ x_c+,
+// the cross couplings W_c taken with the neighbour lines' current x (ZERO:
+// with x = 0).  Cell (line, pos) sits at index line * sl + pos * sa of every
+// array; Wa[c] couples cell c to the next cell along its line, Wc[c] to the
+// same position on the next line (both zero past the last cell / line).
+//
+// A line is split into K chunks of L <= LM cells, one chunk per lane of a
+// K-lane segment of a wavefront.  Each lane eliminates its chunk interior
+// (Thomas with three right-hand sides) so that every interior unknown is
+// y + u X_{k-1} + v X_k in the chunk-end unknowns X; the K chunk-end rows form
+// a tridiagonal system solved by parallel cyclic reduction with cross-lane
+// shuffles; back-substitution finishes.  Wave `wave` of `nwaves` takes lines
+// wave * 64/K + ..., the next pass nwaves * 64/K lines further.  Needs na <=
+// 64 LM.  The caller separates half-sweeps with a barrier.
+template <typename T, int LM, bool ZERO>
+__device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long long sl, const T* __restrict__ m,
+                                const T* __restrict__ Wa, const T* __restrict__ Wc, const T* __restrict__ b,
+                                T* __restrict__ x, int wave, int nwaves) {
+    const int nl = (nlines - par + 1) / 2;
+    if (nl <= 0) return;
+    const int K = wave_line_lanes<LM>(na);
+    const int L = max(2, (na + K - 1) / K);
+    const int lpw = 64 / K;
+    const int lane = threadIdx.x & 63;
+    const int k = lane & (K - 1);
+    const int s0 = k * L;
+    for (int q0 = wave * lpw; q0 < nl; q0 += nwaves * lpw) {
+        const int ql = q0 + lane / K;
+        const bool active = ql < nl;
+        const int line = 2 * ql + par;
+        const long long lb = (long long)(active ? line : 0) * sl;
+        T vm[LM], va[LM], vcn[LM], vcs[LM], vb[LM], vxn[LM], vxs[LM];
+        const T wprev = (active && s0 > 0 && s0 - 1 < na) ? Wa[lb + (long long)(s0 - 1) * sa] : T(0);
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
+            const int g = s0 + q;
+            const bool ok = active && q < L && g < na;
+            const long long c = lb + (long long)g * sa;
+            vm[q] = ok ? m[c] : T(1);
+            va[q] = ok ? Wa[c] : T(0);
+            vcn[q] = ok ? Wc[c] : T(0);
+            vcs[q] = (ok && line > 0) ? Wc[c - sl] : T(0);
+            vb[q] = ok ? b[c] : T(0);
+            vxn[q] = (!ZERO && ok && line + 1 < nlines) ? x[c + sl] : T(0);
+            vxs[q] = (!ZERO && ok && line > 0) ? x[c - sl] : T(0);
+        }
+        auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+            const T wp = (q == 0) ? wprev : va[q > 0 ? q - 1 : 0];
+            d = vm[q] + ((wp + va[q]) + (vcs[q] + vcn[q]));
+            a = -wp;
+            c = -va[q];
+            r = vb[q] + vcn[q] * vxn[q] + vcs[q] * vxs[q];
+        };
+        T cp[LM], gy[LM], gu[LM], gv[LM];
+#pragma unroll
+        for (int q = 0; q < LM - 1; ++q) {
+            if (q < L - 1) {
+                T a, d, c, r;
+                coef(q, a, d, c, r);
+                const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
+                const T inv = T(1) / den;
+                cp[q] = c * inv;
+                gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
+                gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
+                const T rv = (q == L - 2) ? -c : T(0);
+                gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
+            }
+        }
+#pragma unroll
+        for (int q = LM - 3; q >= 0; --q) {
+            if (q < L - 2) {
+                gy[q] -= cp[q] * gy[q + 1];
+                gu[q] -= cp[q] * gu[q + 1];
+                gv[q] -= cp[q] * gv[q + 1];
+            }
+        }
+        T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
+#pragma unroll
+        for (int q = 0; q < LM; ++q)
+            if (q == L - 1) coef(q, aE, dE, cE, rE);
+        T yl = T(0), ul = T(0), vl = T(0);
+#pragma unroll
+        for (int q = 0; q < LM - 1; ++q)
+            if (q == L - 2) {
+                yl = gy[q];
+                ul = gu[q];
+                vl = gv[q];
+            }
+        // the next chunk's first row, y + u X_k + v X_{k+1}
+        const bool has_next = k + 1 < K;
+        T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
+        if (!has_next) yn = un = vn = T(0);
+        T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, R = rE - aE * yl - cE * yn;
+        for (int st = 1; st < K; st <<= 1) {
+            const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
+            const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(R, lane - st, 64);
+            const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
+            const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(R, lane + st, 64);
+            T nA = T(0), nB = B, nC = T(0), nR = R;
+            if (k - st >= 0) {
+                const T al = -A / Bm;
+                nA = al * Am;
+                nB += al * Cm;
+                nR += al * Rm;
+            }
+            if (k + st < K) {
+                const T ga = -C / Bp;
+                nC = ga * Cp;
+                nB += ga * Ap;
+                nR += ga * Rp;
+            }
+            A = nA;
+            B = nB;
+            C = nC;
+            R = nR;
+        }
+        const T X = R / B;
+        T Xp = __shfl(X, lane - 1, 64);
+        if (k == 0) Xp = T(0);
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                const int g = s0 + q;
+                if (q < L && g < na) {
+                    const T v = (q == L - 1) ? X
+                                             : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                   gv[q < LM - 1 ? q : 0] * X;
+                    x[lb + (long long)g * sa] = v;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace fld

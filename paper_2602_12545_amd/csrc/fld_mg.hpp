@@ -23,6 +23,7 @@
 #include <type_traits>
 
 #include "fld_kernels.hpp"
+#include "fld_line.hpp"
 
 namespace fld {
 
@@ -972,102 +973,26 @@ template <typename T>
 struct SubCycle {
     int nlev;              // levels ls .. ls + nlev - 1 (the last is the coarsest)
     SubLevel<T> lv[kSubMaxLevels];
-    int scratch;           // offset of the Thomas scratch (size of the largest level)
     const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
 };
 
-// LDS pool per level: m, We, Wn, b, x (5 arrays of nx*ny), then a PCR scratch
-// of 4 * (largest level / 2 + largest line) elements.
+// LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny).
 //
-// One zebra half-sweep of a level in LDS: all lines of parity `par` are solved
-// together by parallel cyclic reduction, each thread owning unknowns
-// u, u + kSubThreads, ...  (unknown u = line-in-set * len + position).
-constexpr int kSubPerThread = 4;   // unknowns per thread (levels up to 2 * 4096 / 2 cells per parity)
+// One zebra half-sweep of a level in LDS: the lines of parity `par` are
+// spread over the workgroup's wavefronts (wave_line_sweep, no barrier inside).
 template <typename T>
-__device__ inline void sub_line(const SubLevel<T>& L, T* pool, T* scr, bool xdir, int par) {
+__device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int par) {
     const int nx = L.nx, ny = L.ny, P = L.pitch;
     T* m = pool + L.off;
     T* We = m + L.size;
     T* Wn = We + L.size;
     T* b = Wn + L.size;
     T* x = b + L.size;
-    const int nlines = xdir ? ny : nx, len = xdir ? nx : ny;
-    const int nset = (nlines - par + 1) / 2;
-    const int nu = nset * len;
-    T* sa = scr;
-    T* sb = sa + nu;
-    T* sc = sb + nu;
-    T* sr = sc + nu;
-    auto cell = [&](int u, int& i, int& j) {
-        const int li = u / len, q = u - li * len, ln = par + 2 * li;
-        i = xdir ? q : ln;
-        j = xdir ? ln : q;
-    };
-    for (int u = threadIdx.x; u < nu; u += kSubThreads) {
-        int i, j;
-        cell(u, i, j);
-        const int c = j * P + i;
-        const T we = We[c], ww = i > 0 ? We[c - 1] : T(0);
-        const T wn = Wn[c], ws = j > 0 ? Wn[c - P] : T(0);
-        T r = b[c];
-        if (xdir) {
-            sa[u] = -ww;
-            sc[u] = -we;
-            if (j + 1 < ny) r += wn * x[c + P];
-            if (j > 0) r += ws * x[c - P];
-        } else {
-            sa[u] = -ws;
-            sc[u] = -wn;
-            if (i + 1 < nx) r += we * x[c + 1];
-            if (i > 0) r += ww * x[c - 1];
-        }
-        sb[u] = m[c] + ((ww + we) + (ws + wn));
-        sr[u] = r;
-    }
-    __syncthreads();
-    for (int st = 1; st < len; st <<= 1) {
-        T na[kSubPerThread], nb[kSubPerThread], nc[kSubPerThread], nr[kSubPerThread];
-#pragma unroll
-        for (int k = 0; k < kSubPerThread; ++k) {
-            const int u = threadIdx.x + k * kSubThreads;
-            if (u >= nu) continue;
-            const int q = u % len;
-            T a = sa[u], bb = sb[u], c = sc[u], r = sr[u];
-            T a2 = T(0), c2 = T(0);
-            if (q - st >= 0) {
-                const T al = -a / sb[u - st];
-                a2 = al * sa[u - st];
-                bb += al * sc[u - st];
-                r += al * sr[u - st];
-            }
-            if (q + st < len) {
-                const T ga = -c / sb[u + st];
-                c2 = ga * sc[u + st];
-                bb += ga * sa[u + st];
-                r += ga * sr[u + st];
-            }
-            na[k] = a2;
-            nb[k] = bb;
-            nc[k] = c2;
-            nr[k] = r;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kSubPerThread; ++k) {
-            const int u = threadIdx.x + k * kSubThreads;
-            if (u >= nu) continue;
-            sa[u] = na[k];
-            sb[u] = nb[k];
-            sc[u] = nc[k];
-            sr[u] = nr[k];
-        }
-        __syncthreads();
-    }
-    for (int u = threadIdx.x; u < nu; u += kSubThreads) {
-        int i, j;
-        cell(u, i, j);
-        x[j * P + i] = sr[u] / sb[u];
-    }
+    const int wave = threadIdx.x >> 6, nw = kSubThreads / 64;
+    if (xdir)
+        wave_line_sweep<T, kLineMaxL, false>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+    else
+        wave_line_sweep<T, kLineMaxL, false>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
 }
 
 template <typename T>
@@ -1076,7 +1001,6 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
     if (sc->done) return;
     extern __shared__ unsigned char smem_raw[];
     T* pool = reinterpret_cast<T*>(smem_raw);
-    T* cp = pool + S.scratch;
     const int t = threadIdx.x;
     // coefficients of every sub-level, and the right-hand side of the first
     for (int l = 0; l < S.nlev; ++l) {
@@ -1102,9 +1026,9 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const bool first_x = !L.tr;  // primary direction first, as on the grid levels
         for (int dir = 0; dir < 2; ++dir) {
             const bool xd = (dir == 0) == first_x;
-            sub_line(L, pool, cp, xd, 0);
+            sub_line(L, pool, xd, 0);
             __syncthreads();
-            sub_line(L, pool, cp, xd, 1);
+            sub_line(L, pool, xd, 1);
             __syncthreads();
         }
         // residual and 2x2 restriction into the next level's b
@@ -1169,9 +1093,9 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const bool first_x = !L.tr;
         for (int dir = 0; dir < 2; ++dir) {
             const bool xd = (dir == 0) != first_x;  // reverse order of the pre-smoother
-            sub_line(L, pool, cp, xd, 1);
+            sub_line(L, pool, xd, 1);
             __syncthreads();
-            sub_line(L, pool, cp, xd, 0);
+            sub_line(L, pool, xd, 0);
             __syncthreads();
         }
     }

@@ -142,7 +142,7 @@ def test_batch_invalid_arguments(lib):
     with pytest.raises(lib.FLDError):
         lib.Batch([0], [4], [1.0], [1.0])
     with pytest.raises(lib.FLDError):
-        lib.Batch([2048], [4], [1.0], [1.0])
+        lib.Batch([513], [4], [1.0], [1.0])
     with pytest.raises(lib.FLDError):
         lib.Batch([4], [4], [-1.0], [1.0])
     with pytest.raises(lib.FLDError):

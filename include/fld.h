@@ -108,8 +108,11 @@ typedef enum { FLD_MG_GALERKIN = 0, FLD_MG_HALVED = 1 } fld_mg_coarse;
 
 /* Multigrid smoother: alternating zebra line Gauss-Seidel (x lines then y
  * lines; robust to the strong anisotropy of optically thin spherical shells),
- * or point red-black Gauss-Seidel. */
-typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1 } fld_smoother;
+ * or point red-black Gauss-Seidel.  LINE runs both zebra half-sweeps of one
+ * direction in a single launch where a band of rows fits in LDS (same result
+ * as LINE_SPLIT up to the summation order of r.z); LINE_SPLIT launches every
+ * half-sweep separately. */
+typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT = 2 } fld_smoother;
 
 typedef struct {
     int32_t precision;      /* fld_precision (default MIXED)                                 */
@@ -124,7 +127,7 @@ typedef struct {
                             /* dropped by this factor (default 1e-5)                         */
     int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (1..64, def 64)  */
     int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
-    int32_t smoother;       /* fld_smoother (default LINE); LINE needs nx, ny <= 4096        */
+    int32_t smoother;       /* fld_smoother (default LINE); LINE* need nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
     int32_t use_graph;      /* capture each chunk as a hipGraph (default 1)                  */
 } fld_options;
@@ -292,6 +295,46 @@ const char* fld_batch_last_error(const fld_batch* b);
 
 /* Releases the batch and its device memory.  NULL is accepted. */
 void fld_batch_destroy(fld_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Autotuning: the method leaves the preconditioner's schedule open, and its
+ * cost depends on the grid and the fields (launch latency on small levels,
+ * line versus point smoothing under anisotropy, band fusion, multigrid depth).
+ * The tuner times candidate configurations on the caller's own fields and
+ * keeps the fastest whose steps converge.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    fld_options opt;        /* the candidate                                              */
+    int32_t threads;        /* batch workgroup size (0 for single-grid candidates)        */
+    int32_t status;         /* status of the last timed step                             */
+    int32_t inner_iters;    /* CG iterations of the last timed step (batch: max over blocks) */
+    float   ms;             /* mean wall time of one step (assembly, solve, gas update)   */
+} fld_tune_entry;
+
+/* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
+ * mg_coarse_max in {64, 16} and chunk in {8, 16, 4}; precision, limiter,
+ * norm and tolerances are those of base (NULL = defaults).  Each candidate
+ * gets its own context and runs reps + 1 steps (the first untimed) from the
+ * given E, T (device arrays, not modified; the trials run on scratch copies).
+ * *best receives the fastest candidate with every step OK; entries (host,
+ * max_entries, may be NULL) the whole table, *n_entries its length.  Returns
+ * ENOCONV if no candidate converged, EINVAL / ENOMEM / EHIP. */
+fld_status fld_tune(const fld_grid* grid, const fld_options* base, const double* E_r, const double* T_g,
+                    const double* rho, const double* kappa_R, const double* kappa_P, const double* c_v,
+                    const double* ghost_E, double dt, int32_t reps, fld_options* best,
+                    fld_tune_entry* entries, int32_t max_entries, int32_t* n_entries, void* stream);
+
+/* Batch: candidates are mg_coarse_max in {64, 32, 16} (multigrid depth) times
+ * workgroup size in {512, 256, 1024}, timed as whole batch steps
+ * (fld_batch_step) on scratch copies of the packed E, T.  Arguments as
+ * fld_batch_create and fld_batch_step; *best and *best_threads receive the
+ * fastest converging configuration. */
+fld_status fld_batch_tune(int32_t nblocks, const int32_t* nx, const int32_t* ny, const double* dx,
+                          const double* dy, const fld_bc* bc, const fld_options* base, const double* E_r,
+                          const double* T_g, const double* rho, const double* kappa_R,
+                          const double* kappa_P, const double* c_v, const double* ghost_E, double dt,
+                          int32_t reps, fld_options* best, int32_t* best_threads, fld_tune_entry* entries,
+                          int32_t max_entries, int32_t* n_entries, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ FLD_FP64, FLD_FP32, FLD_MIXED = 0, 1, 2
 FLD_LIMITER_LP, FLD_LIMITER_MINERBO, FLD_LIMITER_DIFFUSION = 0, 1, 2
 FLD_NORM_ROW, FLD_NORM_SCALED = 0, 1
 FLD_MG_GALERKIN, FLD_MG_HALVED = 0, 1
-FLD_SMOOTH_LINE, FLD_SMOOTH_POINT = 0, 1
+FLD_SMOOTH_LINE, FLD_SMOOTH_POINT, FLD_SMOOTH_LINE_SPLIT = 0, 1, 2
 
 PRECISIONS = {"fp64": FLD_FP64, "fp32": FLD_FP32, "mixed": FLD_MIXED}
 
@@ -51,6 +51,11 @@ class fld_solve_info(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fld_tune_entry(ctypes.Structure):
+    _fields_ = [("opt", fld_options), ("threads", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 def _load():
@@ -93,6 +98,12 @@ _SIGS = {
     "fld_batch_sizes": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "fld_batch_last_error": (ctypes.c_char_p, [_P]),
     "fld_batch_destroy": (None, [_P]),
+    "fld_tune": (_I, [ctypes.POINTER(fld_grid), ctypes.POINTER(fld_options), _P, _P, _P, _P, _P, _P, _P, _D, _I,
+                      ctypes.POINTER(fld_options), ctypes.POINTER(fld_tune_entry), _I, ctypes.POINTER(_I), _P]),
+    "fld_batch_tune": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                            ctypes.POINTER(fld_bc), ctypes.POINTER(fld_options), _P, _P, _P, _P, _P, _P, _P, _D, _I,
+                            ctypes.POINTER(fld_options), ctypes.POINTER(_I), ctypes.POINTER(fld_tune_entry), _I,
+                            ctypes.POINTER(_I), _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)

@@ -1,0 +1,288 @@
+// Band-fused zebra line sweeps: both half-sweeps of one direction in one
+// launch.
+//
+// A workgroup owns a band of R consecutive rows (R even) of the layout being
+// swept.  Zebra line Gauss-Seidel solves first every row of parity p1, then
+// every row of parity p2 = 1 - p1 from the fresh p1 rows.  A p2 row of the
+// band needs the p1 rows just above and below it; the one outside the band
+// (row r0 - 1 when p1 = 1, row r0 + R when p1 = 0) is solved here as well,
+// from the same inputs and with the same arithmetic as in the band that owns
+// it, so it is bit-identical to that band's value and the launch equals the
+// two separate half-sweeps exactly.  Solved rows stay in LDS; the band's rows
+// are written once at the end, in the same layout or transposed (so the next
+// sweep direction reads rows again), optionally with the right-hand side
+// transposed alongside.
+//
+// Inside a pass, a row of na cells is split into K chunks of L cells (the
+// same K, L as the one-half-sweep kernel), one chunk per thread; the chunk
+// interior is eliminated locally and the K chunk-end unknowns are solved by
+// cyclic reduction, with wavefront shuffles when K <= 64 and in LDS otherwise.
+#pragma once
+
+#include "fld_mg.hpp"
+
+namespace fld {
+
+constexpr int kBandWG = 512;
+
+// LDS bytes of one k_band launch: R + 2 row slots (+ R rows of b when the
+// right-hand side is transposed alongside), the cyclic-reduction arrays and
+// the reduction scratch.
+template <typename T>
+inline size_t band_lds_bytes(int na, int R, bool with_b) {
+    return sizeof(T) * ((size_t)(R + 2) * na + (with_b ? (size_t)R * na : 0) + 7 * (size_t)kBandWG) +
+           16 * sizeof(double);
+}
+
+template <typename T, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
+__global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, int L, const T* __restrict__ m,
+                                                  const T* __restrict__ We, const T* __restrict__ Wn,
+                                                  const T* __restrict__ b, const T* __restrict__ xin,
+                                                  const T* __restrict__ ec, int nxc, T* __restrict__ xout,
+                                                  T* __restrict__ bout, double* part, const Scalars* sc, int* ran) {
+    if (sc->done) return;
+    if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+    extern __shared__ __align__(16) unsigned char band_smem[];
+    constexpr int NT = kBandWG, LM = kLineMaxL;
+    T* rows = reinterpret_cast<T*>(band_smem);               // (R + 2) x nx: slot = row - (r0 - 1)
+    T* bb = rows + (size_t)(R + 2) * nx;                      // R x nx (WRITE_BT)
+    T* pcr = bb + (WRITE_BT ? (size_t)R * nx : 0);            // 7 x NT
+    double* sh = reinterpret_cast<double*>(pcr + 7 * NT);
+    T *sA = pcr, *sB = pcr + NT, *sC = pcr + 2 * NT, *sR = pcr + 3 * NT;
+    T *sy0 = pcr + 4 * NT, *su0 = pcr + 5 * NT, *sv0 = pcr + 6 * NT;
+    const int t = threadIdx.x, r0 = blockIdx.x * R;
+    const int rend = min(r0 + R, ny);  // band rows [r0, rend)
+    const int k = t % K, lpp = NT / K, s0 = k * L;
+    const int lane = t & 63;
+    const bool wave_pcr = K <= 64;
+
+    // Solve `count` rows start, start + 2, ... ; PH = 1: first parity
+    // (neighbours from xin), PH = 2: second parity (neighbours from LDS).
+    auto solve_rows = [&](int start, int count, int PH) {
+        for (int q0 = 0; q0 < count; q0 += lpp) {
+            const int ql = q0 + t / K;
+            const bool active = ql < count;
+            const int row = start + 2 * (active ? ql : 0);
+            const size_t rb = (size_t)row * nx;
+            T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM], vxn[LM], vxs[LM];
+            const T wwest = (active && s0 > 0 && s0 - 1 < nx) ? We[rb + s0 - 1] : T(0);
+            constexpr int VW = 16 / sizeof(T);
+            const bool vec = active && L == LM && s0 + LM <= nx && ((rb + s0) % VW) == 0 && (nx % VW) == 0;
+            if (vec) {
+                load_vec<T, LM>(m + rb + s0, vm);
+                load_vec<T, LM>(We + rb + s0, vwe);
+                load_vec<T, LM>(Wn + rb + s0, vwn);
+                load_vec<T, LM>(b + rb + s0, vb);
+                if (row > 0) load_vec<T, LM>(Wn + rb + s0 - nx, vws);
+                else fill<T, LM>(vws, T(0));
+            } else {
+#pragma unroll
+                for (int q = 0; q < LM; ++q) {
+                    const int g = s0 + q;
+                    const bool ok = active && q < L && g < nx;
+                    const size_t c = rb + g;
+                    vm[q] = ok ? m[c] : T(1);
+                    vwe[q] = ok ? We[c] : T(0);
+                    vwn[q] = ok ? Wn[c] : T(0);
+                    vws[q] = (ok && row > 0) ? Wn[c - nx] : T(0);
+                    vb[q] = ok ? b[c] : T(0);
+                }
+            }
+            // neighbour rows
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                const int g = s0 + q;
+                const bool ok = active && q < L && g < nx;
+                T xn = T(0), xs = T(0);
+                if (ok) {
+                    if (PH == 2) {
+                        if (row + 1 < ny) xn = rows[(size_t)(row + 1 - (r0 - 1)) * nx + g];
+                        if (row > 0) xs = rows[(size_t)(row - 1 - (r0 - 1)) * nx + g];
+                    } else if (MODE != LINE_ZERO) {
+                        if (row + 1 < ny) {
+                            xn = xin[rb + nx + g];
+                            if (MODE == LINE_PROLONG) xn += ec[(size_t)((row + 1) >> 1) * nxc + (g >> 1)];
+                        }
+                        if (row > 0) {
+                            xs = xin[rb - nx + g];
+                            if (MODE == LINE_PROLONG) xs += ec[(size_t)((row - 1) >> 1) * nxc + (g >> 1)];
+                        }
+                    }
+                }
+                vxn[q] = xn;
+                vxs[q] = xs;
+            }
+            if (WRITE_BT && active && row >= r0 && row < rend) {
+#pragma unroll
+                for (int q = 0; q < LM; ++q)
+                    if (q < L && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+            }
+            auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+                const T ww = (q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0];
+                d = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
+                a = -ww;
+                c = -vwe[q];
+                r = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
+            };
+            T cp[LM], gy[LM], gu[LM], gv[LM];
+#pragma unroll
+            for (int q = 0; q < LM - 1; ++q) {
+                if (q < L - 1) {
+                    T a, d, c, r;
+                    coef(q, a, d, c, r);
+                    const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
+                    const T inv = T(1) / den;
+                    cp[q] = c * inv;
+                    gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
+                    gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
+                    const T rv = (q == L - 2) ? -c : T(0);
+                    gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
+                }
+            }
+#pragma unroll
+            for (int q = LM - 3; q >= 0; --q) {
+                if (q < L - 2) {
+                    gy[q] -= cp[q] * gy[q + 1];
+                    gu[q] -= cp[q] * gu[q + 1];
+                    gv[q] -= cp[q] * gv[q + 1];
+                }
+            }
+            T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
+#pragma unroll
+            for (int q = 0; q < LM; ++q)
+                if (q == L - 1) coef(q, aE, dE, cE, rE);
+            T yl = T(0), ul = T(0), vl = T(0);
+#pragma unroll
+            for (int q = 0; q < LM - 1; ++q)
+                if (q == L - 2) {
+                    yl = gy[q];
+                    ul = gu[q];
+                    vl = gv[q];
+                }
+            const bool has_next = k + 1 < K;
+            T X, Xp;
+            if (wave_pcr) {
+                T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
+                if (!has_next) yn = un = vn = T(0);
+                T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, Rr = rE - aE * yl - cE * yn;
+                for (int st = 1; st < K; st <<= 1) {
+                    const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
+                    const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(Rr, lane - st, 64);
+                    const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
+                    const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(Rr, lane + st, 64);
+                    T nA = T(0), nB = B, nC = T(0), nR = Rr;
+                    if (k - st >= 0) {
+                        const T al = -A / Bm;
+                        nA = al * Am;
+                        nB += al * Cm;
+                        nR += al * Rm;
+                    }
+                    if (k + st < K) {
+                        const T ga = -C / Bp;
+                        nC = ga * Cp;
+                        nB += ga * Ap;
+                        nR += ga * Rp;
+                    }
+                    A = nA;
+                    B = nB;
+                    C = nC;
+                    Rr = nR;
+                }
+                X = Rr / B;
+                Xp = __shfl(X, lane - 1, 64);
+                if (k == 0) Xp = T(0);
+            } else {
+                sy0[t] = gy[0];
+                su0[t] = gu[0];
+                sv0[t] = gv[0];
+                __syncthreads();
+                const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0);
+                const T vn = has_next ? sv0[t + 1] : T(0);
+                sA[t] = aE * ul;
+                sB[t] = dE + aE * vl + cE * un;
+                sC[t] = cE * vn;
+                sR[t] = rE - aE * yl - cE * yn;
+                __syncthreads();
+                for (int st = 1; st < K; st <<= 1) {
+                    const T a = sA[t], bq = sB[t], c = sC[t], r = sR[t];
+                    T na = T(0), nb = bq, nc = T(0), nr = r;
+                    if (k - st >= 0) {
+                        const T al = -a / sB[t - st];
+                        na = al * sA[t - st];
+                        nb += al * sC[t - st];
+                        nr += al * sR[t - st];
+                    }
+                    if (k + st < K) {
+                        const T ga = -c / sB[t + st];
+                        nc = ga * sC[t + st];
+                        nb += ga * sA[t + st];
+                        nr += ga * sR[t + st];
+                    }
+                    __syncthreads();
+                    sA[t] = na;
+                    sB[t] = nb;
+                    sC[t] = nc;
+                    sR[t] = nr;
+                    __syncthreads();
+                }
+                X = sR[t] / sB[t];
+                __syncthreads();
+                sR[t] = X;
+                __syncthreads();
+                Xp = k > 0 ? sR[t - 1] : T(0);
+            }
+            if (active) {
+                T* dst = rows + (size_t)(row - (r0 - 1)) * nx;
+#pragma unroll
+                for (int q = 0; q < LM; ++q) {
+                    const int g = s0 + q;
+                    if (q < L && g < nx)
+                        dst[g] = (q == L - 1) ? X
+                                              : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                    gv[q < LM - 1 ? q : 0] * X;
+                }
+            }
+            if (!wave_pcr) __syncthreads();  // the LDS reduction arrays are reused by the next pass
+        }
+    };
+
+    constexpr int P1 = FIRST, P2 = 1 - FIRST;
+    // first-parity rows in [r0 - 1, r0 + R], second-parity rows in [r0, rend)
+    int s1 = r0 - 1;
+    if (s1 < 0 || (s1 & 1) != P1) s1 += (s1 < 0) ? (P1 == 1 ? 2 : 1) : 1;
+    const int e1 = min(r0 + R, ny - 1);
+    const int n1 = s1 <= e1 ? (e1 - s1) / 2 + 1 : 0;
+    const int s2 = ((r0 & 1) == P2) ? r0 : r0 + 1;
+    const int n2 = s2 < rend ? (rend - 1 - s2) / 2 + 1 : 0;
+    solve_rows(s1, n1, 1);
+    __syncthreads();
+    solve_rows(s2, n2, 2);
+    __syncthreads();
+    // band rows out
+    double acc = 0.0;
+    const int nr = rend - r0;
+    if (!OUT_T) {
+        for (int e = t; e < nr * nx; e += NT) {
+            const int rr = e / nx, i = e - rr * nx;
+            const T v = rows[(size_t)(rr + 1) * nx + i];
+            const size_t c = (size_t)(r0 + rr) * nx + i;
+            xout[c] = v;
+            if (DOT) acc += (double)b[c] * (double)v;
+        }
+    } else {
+        // transposed: column i of the band becomes nr consecutive values of row i
+        for (int e = t; e < nr * nx; e += NT) {
+            const int i = e / nr, rr = e - i * nr;
+            const T v = rows[(size_t)(rr + 1) * nx + i];
+            xout[(size_t)i * ny + r0 + rr] = v;
+            if (WRITE_BT) bout[(size_t)i * ny + r0 + rr] = bb[(size_t)rr * nx + i];
+            if (DOT) acc += (double)b[(size_t)(r0 + rr) * nx + i] * (double)v;
+        }
+    }
+    if (DOT) {
+        const double tot = block_sum(acc, sh);
+        if (t == 0) part[blockIdx.x] = tot;
+    }
+}
+
+}  // namespace fld

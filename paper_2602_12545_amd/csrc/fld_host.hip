@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "fld.h"
-#include "fld_mg.hpp"
+#include "fld_band.hpp"
 
 using namespace fld;
 
@@ -55,7 +55,10 @@ struct LevelT {
     T *mT = nullptr, *WeT = nullptr, *WnT = nullptr;  // transposed copy (line smoother)
     T *bP = nullptr, *xP = nullptr;                   // vectors in the level's primary layout
     T *bQ = nullptr, *xQ = nullptr;                   // secondary layout (line); xQ = pre-smoothed x (point)
+    T *xQ2 = nullptr, *xPT = nullptr;                 // band-fused sweeps: second Q buffer, P temporary
     bool tr = false;                                  // primary layout is the transposed one
+    bool band = false;                                // band-fused sweeps on this level
+    int Rp = 2, Rq = 2;                               // band heights in the P and Q layouts
     View<T> view(bool transposed) const {
         View<T> v;
         if (!transposed) { v.nx = nx; v.ny = ny; v.m = m; v.We = We; v.Wn = Wn; }
@@ -158,7 +161,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) { err = "inner_rtol must be in (0, 1)"; return FLD_EINVAL; }
     if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 64]"; return FLD_EINVAL; }
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
-    if (o->smoother < 0 || o->smoother > 1) { err = "smoother"; return FLD_EINVAL; }
+    if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
     return FLD_OK;
 }
@@ -166,6 +169,8 @@ fld_status validate_options(const fld_options* o, std::string& err) {
 // ---------------------------------------------------------------------------
 // V-cycle and CG slot (queued on stream `st`)
 // ---------------------------------------------------------------------------
+
+inline bool is_line(const fld_options& o) { return o.smoother == FLD_SMOOTH_LINE || o.smoother == FLD_SMOOTH_LINE_SPLIT; }
 
 // Chunking of a row of n cells for k_line: K chunks (power of two, <= 512) of
 // L cells (2 <= L <= 8).
@@ -205,6 +210,36 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
     return grid;
 }
 
+// Both half-sweeps of the rows of view v in one launch (k_band); returns the
+// grid size (the number of r.z partials when DOT).
+template <typename T, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
+int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, const T* ec, int nxc, T* xout,
+                T* bout, hipStream_t st) {
+    int K, L;
+    line_params(v.nx, K, L);
+    const int grid = (v.ny + R - 1) / R;
+    auto& P = c->prof;
+    int slot = -1;
+    if (P.on && P.used < P.slots) {
+        slot = P.used++;
+        // algorithmic bytes: m, W_e, W_n, b of every row and x written once; the
+        // old x of the rows solved second (read by the rows solved first) unless
+        // zero; the coarse correction; b written transposed
+        const double n = (double)v.nx * v.ny;
+        double words = 5.0 * n;
+        if (MODE != LINE_ZERO) words += 0.5 * n;
+        if (MODE == LINE_PROLONG) words += 0.25 * n;
+        if (WRITE_BT) words += n;
+        P.bytes[slot] = words * sizeof(T);
+        (void)hipEventRecord(P.ev[2 * slot], st);
+    }
+    k_band<T, MODE, FIRST, OUT_T, WRITE_BT, DOT><<<grid, kBandWG, band_lds_bytes<T>(v.nx, R, WRITE_BT), st>>>(
+        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, c->part, c->sc,
+        slot >= 0 ? P.ran + slot : nullptr);
+    if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
+    return grid;
+}
+
 // Adds the timed launches that did work to the totals (stream synchronised).
 fld_status prof_harvest(fld_ctx* ctx) {
     auto& P = ctx->prof;
@@ -236,18 +271,29 @@ template <typename T>
 void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const int L = (int)in.lv.size();
     const int Ld = in.sub_first > 0 ? in.sub_first : L - 1;  // grid levels smoothed with launches
+    const bool fused = c->opt.smoother == FLD_SMOOTH_LINE;
+    std::vector<T*> xpre(Ld);  // pre-smoothed x of each level (secondary layout)
     for (int l = 0; l < Ld; ++l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
-        launch_line<T, LINE_ZERO, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
-        launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
-        launch_transpose<T>(vp.nx, vp.ny, a.xP, a.bP, a.xQ, a.bQ, c->sc, st);
-        launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
-        launch_line<T, LINE_NORMAL, 0>(c, vq, 1, a.bQ, a.xQ, nullptr, 0, 0, st);
+        if (fused && a.band) {
+            // rows of P (even, odd) -> x and b transposed into Q; rows of Q (even, odd)
+            launch_band<T, LINE_ZERO, 0, true, true, false>(c, vp, a.Rp, a.bP, nullptr, nullptr, 0, a.xQ, a.bQ, st);
+            launch_band<T, LINE_NORMAL, 0, false, false, false>(c, vq, a.Rq, a.bQ, a.xQ, nullptr, 0, a.xQ2, nullptr,
+                                                                st);
+            xpre[l] = a.xQ2;
+        } else {
+            launch_line<T, LINE_ZERO, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
+            launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
+            launch_transpose<T>(vp.nx, vp.ny, a.xP, a.bP, a.xQ, a.bQ, c->sc, st);
+            launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
+            launch_line<T, LINE_NORMAL, 0>(c, vq, 1, a.bQ, a.xQ, nullptr, 0, 0, st);
+            xpre[l] = a.xQ;
+        }
         const View<T> cv = nxt.view(nxt.tr);
-        k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ, a.xQ,
-                                                                          nxt.bP, cv.nx, cv.ny, c->sc);
+        k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ,
+                                                                          xpre[l], nxt.bP, cv.nx, cv.ny, c->sc);
     }
     if (in.sub_first > 0) {
         LevelT<T>& f = in.lv[in.sub_first];
@@ -261,6 +307,21 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
         const View<T> cv = nxt.view(nxt.tr);
+        if (fused && a.band) {
+            // rows of Q (odd with the coarse correction, even) -> x transposed
+            // into P; rows of P (odd, even), the last with r.z on the fine level
+            launch_band<T, LINE_PROLONG, 1, true, false, false>(c, vq, a.Rq, a.bQ, xpre[l], nxt.xP, cv.nx, a.xPT,
+                                                                nullptr, st);
+            if (l == 0) {
+                const int nb = launch_band<T, LINE_NORMAL, 1, false, false, true>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0,
+                                                                                  a.xP, nullptr, st);
+                k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, nb, c->sc);
+            } else {
+                launch_band<T, LINE_NORMAL, 1, false, false, false>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0, a.xP,
+                                                                    nullptr, st);
+            }
+            continue;
+        }
         launch_line<T, LINE_PROLONG, 0>(c, vq, 1, a.bQ, a.xQ, nxt.xP, cv.nx, 0, st);
         launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
         launch_transpose<T>(vq.nx, vq.ny, a.xQ, nullptr, a.xP, nullptr, c->sc, st);
@@ -309,7 +370,7 @@ void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         k_coarse_solve<T, true><<<1, kCoarseMax, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->sc);
         return;
     }
-    if (c->opt.smoother == FLD_SMOOTH_LINE) enqueue_vcycle_line<T>(c, in, st);
+    if (is_line(c->opt)) enqueue_vcycle_line<T>(c, in, st);
     else enqueue_vcycle_point<T>(c, in, st);
 }
 
@@ -348,7 +409,7 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     Inner<T>& in = inner<T>(c);
     const int L = (int)in.lv.size();
     const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
-    const bool line = c->opt.smoother == FLD_SMOOTH_LINE;
+    const bool line = is_line(c->opt);
     for (int l = 0; l < L; ++l) {
         Level64& b = c->h64[l];
         if (l > 0) {
@@ -379,7 +440,7 @@ template <typename T>
 fld_status alloc_inner(fld_ctx* ctx) {
     Inner<T>& in = inner<T>(ctx);
     const size_t n = (size_t)ctx->nx * ctx->ny;
-    const bool line = ctx->opt.smoother == FLD_SMOOTH_LINE;
+    const bool line = is_line(ctx->opt);
     in.lv.resize(ctx->h64.size());
     for (size_t l = 0; l < ctx->h64.size(); ++l) {
         LevelT<T>& lv = in.lv[l];
@@ -395,6 +456,8 @@ fld_status alloc_inner(fld_ctx* ctx) {
             HIPCHK(ctx->alloc(&lv.WeT, m));
             HIPCHK(ctx->alloc(&lv.WnT, m));
             HIPCHK(ctx->alloc(&lv.bQ, m));
+            HIPCHK(ctx->alloc(&lv.xQ2, m));
+            HIPCHK(ctx->alloc(&lv.xPT, m));
         }
         if (l > 0) HIPCHK(ctx->alloc(&lv.bP, m));
         HIPCHK(ctx->alloc(&lv.xP, m));
@@ -412,11 +475,11 @@ fld_status alloc_inner(fld_ctx* ctx) {
     // coarser levels fit in LDS (5 arrays each) and whose lines fit one wavefront
     const int L = (int)in.lv.size();
     in.sub_first = -1;
+    int dev = 0, lds_max = 65536;
+    HIPCHK(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 65536;
     if (line && L >= 3) {
-        int dev = 0, lds_max = 65536;
-        HIPCHK(hipGetDevice(&dev));
-        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            lds_max = 65536;
         for (int l = 1; l < L - 1 && in.sub_first < 0; ++l) {
             if (L - l > kSubMaxLevels) continue;
             if (std::max(in.lv[l].nx, in.lv[l].ny) > 64 * kLineMaxL) continue;
@@ -442,6 +505,44 @@ fld_status alloc_inner(fld_ctx* ctx) {
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)in.sub_lds));
+        }
+    }
+    // band-fused sweeps on the launched levels whose bands fit in LDS: band
+    // height R (even, <= 8) as large as keeps >= 256 workgroups
+    if (ctx->opt.smoother == FLD_SMOOTH_LINE) {
+        const int Ld = in.sub_first > 0 ? in.sub_first : L - 1;
+        size_t need_max = 0;
+        auto pick = [&](int na, int rows, bool with_b) {
+            for (int R = 8; R >= 2; R -= 2) {
+                if (R > 2 && (rows + R - 1) / R < std::min(256, (rows + 1) / 2)) continue;
+                const size_t need = band_lds_bytes<T>(na, R, with_b);
+                if (need <= (size_t)lds_max) {
+                    need_max = std::max(need_max, need);
+                    return R;
+                }
+            }
+            return 0;
+        };
+        for (int l = 0; l < Ld; ++l) {
+            LevelT<T>& lv = in.lv[l];
+            const int pnx = lv.tr ? lv.ny : lv.nx, pny = lv.tr ? lv.nx : lv.ny;
+            const int Rp = pick(pnx, pny, true), Rq = pick(pny, pnx, false);
+            lv.band = Rp > 0 && Rq > 0;
+            lv.Rp = Rp;
+            lv.Rq = Rq;
+        }
+        if (need_max > 65536) {
+            const int sz = (int)need_max;
+            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_ZERO, 0, true, true, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
+            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 0, false, false, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
+            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_PROLONG, 1, true, false, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
+            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 1, false, false, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
+            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 1, false, false, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
         }
     }
     HIPCHK(hipMemset(in.r, 0, sizeof(T) * n));
@@ -795,7 +896,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
             ly = (ly + 1) / 2;
         }
     }
-    if (ctx->opt.smoother == FLD_SMOOTH_LINE && (nx > kLineWG * kLineMaxL || ny > kLineWG * kLineMaxL))
+    if (is_line(ctx->opt) && (nx > kLineWG * kLineMaxL || ny > kLineWG * kLineMaxL))
         return fail(FLD_EINVAL, "line smoother supports nx, ny <= 4096; use the point smoother");
     const size_t tiles = (size_t)tile_grid(nx, ny).x * tile_grid(nx, ny).y;
     ctx->npart = std::max<size_t>(tiles * 5, (size_t)k1DBlocksMax);

@@ -144,3 +144,31 @@ def test_max_iterations_reports_noconv(lib):
     E, T, info = gpu_step(lib, torch, prob, precision="fp64", max_inner=2)
     assert info["status"] == lib.FLD_ENOCONV
     assert info["inner_iters"] == 2
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_band_fused_sweeps_match_split_sweeps(lib, name, prec):
+    """LINE runs both zebra half-sweeps of a direction in one launch; LINE_SPLIT
+    one launch per half-sweep.  The smoothing is the same, only the order of
+    the r.z partial sums differs, so the solutions agree to rounding and the
+    iteration counts match."""
+    prob = CASES[name]
+    opt = dict(precision=prec, rel_tol=1e-12, norm=1)
+    E1, T1, i1 = gpu_step(lib, torch, prob, smoother=0, **opt)
+    E2, T2, i2 = gpu_step(lib, torch, prob, smoother=2, **opt)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert abs(i1["inner_iters"] - i2["inner_iters"]) <= 1
+    assert rel_l2(E1, E2) < 1e-12 and rel_l2(T1, T2) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(1024, 40), (40, 1024), (1030, 66), (515, 260)])
+def test_band_fused_sweeps_wide_rows(lib, shape):
+    """Rows longer than one wavefront's reach (K > 64 chunks, LDS cyclic
+    reduction) and odd band tails, against the oracle."""
+    nx, ny = shape
+    prob = W.make_c2(nx=nx, ny=ny)
+    E, T, info = gpu_step(lib, torch, prob, precision="mixed", rel_tol=1e-12, norm=1)
+    assert info["status"] == 0
+    r = O.step_problem(prob)
+    assert rel_l2(E, r.E) < 1e-10 and rel_l2(T, r.T) < 1e-10

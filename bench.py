@@ -1,18 +1,23 @@
 """Benchmark of the implicit FLD radiation step on one MI355X.
 
-Default workload: the 1024 x 1024 Cartesian grid stretched by 1.002 per cell
+Headline workload: the 1024 x 1024 Cartesian grid stretched by 1.002 per cell
 with seeded lognormal density / temperature and clipped Kramers opacity, a
 Dirichlet (Marshak) x_lo side, dt = 1e4 s.  One timed step = one full
 backward-Euler radiation step (assembly, multigrid-preconditioned CG with FP32
 inner iterations and FP64 reliable updates to a 1e-10 relative residual in
-the per-volume norm, gas update), inputs resident in HBM, (E, T) restored
-from the same initial state before each step.  Prints one JSON line.
+the per-volume norm, gas update), inputs resident in HBM, (E, T) restored from
+the same initial state before each step.  The solver schedule is chosen first
+by the autotuner (untimed).  The last timed step runs with HIP events around
+every multigrid line-sweep launch (the dominant kernel family); the others run
+as captured hipGraph chunks.  Prints one JSON line.
 
 Fields beyond the contract: the FP64 solver on the same workload (mixed vs
-FP64 speedup), CG iterations and Mcell-iterations/s, and the roofline of the
-dominant kernel family (multigrid line sweeps) from HIP-event timings taken
-inside the timed region.  cpu_baseline times the CPU oracle on a bounded
-sample of the same recipe.
+FP64 speedup), CG iterations and Mcell-iterations/s, the roofline of the
+line-sweep kernels from the event timings, and (unless --no-extra) the
+batched-block workload (256 blocks, one launch per step; FP64 batched and
+FP64 one-context-per-block baselines) and the 4096 x 2048 spherical stress
+workload run as multi-step graphs.  cpu_baseline times the CPU oracle on a
+bounded sample of the headline recipe.
 """
 from __future__ import annotations
 
@@ -27,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 METRIC = "FLD solves/s & Mcell-iter/s to 1e-10 resid; HBM GB/s %peak; mixed vs FP64"
+FIELDS = ("E", "T", "rho", "kappa_R", "kappa_P", "c_v")
 
 
 def parse():
@@ -38,58 +44,189 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-profile", action="store_true", help="time without kernel events (hipGraph chunks)")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner's choice")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched-block and stress workloads")
+    ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (scale for HBM traffic counters)")
     return ap.parse_args()
 
 
-def run_steps(fld, torch, prob, prec, steps, warmup, profile):
+def dev_fields(torch, prob):
     import numpy as np
+    f = {k: torch.tensor(np.ascontiguousarray(getattr(prob, k)), dtype=torch.float64, device="cuda") for k in FIELDS}
+    f["ghost_E"] = (torch.tensor(prob.ghost_E, dtype=torch.float64, device="cuda")
+                    if prob.ghost_E is not None else None)
+    return f
+
+
+def options(fld, prec, tuned, norm=0):
+    o = fld.default_options(precision=prec, norm=norm)
+    if tuned is not None:
+        for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph"):
+            setattr(o, k, getattr(tuned, k))
+    return o
+
+
+def run_steps(fld, torch, prob, base, opts, steps, warmup, profile):
+    """Mean wall time of one step over `steps` timed steps (the last one with
+    event-timed line sweeps when `profile`), and the per-step infos."""
     ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                      [(b.kind, b.value) for b in prob.bc], fld.default_options(precision=prec))
-    base = {k: torch.tensor(np.ascontiguousarray(getattr(prob, k)), dtype=torch.float64, device="cuda")
-            for k in ("E", "T", "rho", "kappa_R", "kappa_P", "c_v")}
+                      [(b.kind, b.value) for b in prob.bc], opts)
     E = base["E"].clone()
     T = base["T"].clone()
 
     def one():
         E.copy_(base["E"])
         T.copy_(base["T"])
-        return ctx.step(E, T, base["rho"], base["kappa_R"], base["kappa_P"], base["c_v"], prob.dt)
+        return ctx.step(E, T, base["rho"], base["kappa_R"], base["kappa_P"], base["c_v"], prob.dt, base["ghost_E"])
 
     for _ in range(warmup):
         one()
     torch.cuda.synchronize()
-    if profile:
-        ctx.profile(True)
     infos = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for s in range(steps):
+        if profile and s == steps - 1:
+            ctx.profile(True)
         infos.append(one())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = ctx.profile_read() if profile else None
-    if prof is not None:
+    prof = None
+    if profile:
+        prof = ctx.profile_read()
         prof["overhead_us"] = ctx.profile_overhead(200)
+        ctx.profile(False)
     ctx.close()
     return dt / steps, infos, prof
 
 
-def cpu_baseline(W, nx=512, ny=512):
-    """The CPU oracle (assembly + sparse LU + gas update) on the same recipe at a
-    quarter of the cells, single-threaded; rate scaled linearly to the full grid
-    (which flatters the CPU: the direct solve grows faster than linearly)."""
+def cpu_baseline(W, n=768):
+    """The CPU oracle (assembly + sparse LU + gas update), single-threaded, on
+    the headline recipe at n x n cells; the rate is scaled by cell count to the
+    full grid (which flatters the CPU: the direct solve grows faster than
+    linearly)."""
     from threadpoolctl import threadpool_limits
     from oracle import fld_oracle as O
-    prob = W.make_c2(nx=nx, ny=ny)
+    prob = W.make_c2(nx=n, ny=n)
     with threadpool_limits(limits=1):
         O.step_problem(W.make_c2(nx=64, ny=64))  # warm-up (imports, allocator)
         t0 = time.perf_counter()
         O.step_problem(prob)
         dt = time.perf_counter() - t0
     full = 1024 * 1024
-    return {"value": (1.0 / dt) * (nx * ny) / full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"c2 recipe at {nx}x{ny} (1/4 of the cells): one step = FP64 assembly + SuperLU "
-                      f"direct solve + gas update, {dt:.2f} s; rate scaled by cell count to 1024x1024"}
+    return {"value": (1.0 / dt) * (n * n) / full, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"c2 recipe at {n}x{n} cells: one step = FP64 assembly + SuperLU direct solve + gas update, "
+                      f"{dt:.1f} s on one host core; rate scaled by cell count to 1024x1024"}
+
+
+def batch_extra(fld, torch, W, tune):
+    """256 independent blocks (16..128 cells per side), one launch per step."""
+    import numpy as np
+    batch = W.make_c4()
+    blocks = batch.blocks
+    nx, ny = [b.nx for b in blocks], [b.ny for b in blocks]
+    d = [1e10] * len(blocks)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    f = {k: dev(batch.packed(k)) for k in FIELDS}
+    f["ghost_E"] = dev(batch.packed_ghosts())
+    out = {"workload": "c4: 256 Cartesian blocks, sides in {16..128}, 984320 cells, ghost boundaries"}
+
+    def timed(prec, reps=10):
+        base = fld.default_options(precision=prec)
+        threads = 512
+        if tune is not None:
+            o, threads, _ = tune.tune_batch(nx, ny, d, d, f, 1e4, base=base, reps=1, cache="")
+            base = o
+        bt = fld.Batch(nx, ny, d, d, None, base)
+        bt.threads = threads
+        E, T = f["E"].clone(), f["T"].clone()
+
+        def one(rec=False):
+            E.copy_(f["E"])
+            T.copy_(f["T"])
+            return bt.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], 1e4, f["ghost_E"], records=rec)
+
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            one()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        infos = one(True)
+        bt.close()
+        return ms, infos, threads, base.mg_coarse_max
+
+    ms_m, inf_m, th_m, cm_m = timed("mixed")
+    ms_d, inf_d, th_d, cm_d = timed("fp64")
+    out.update({"mixed_ms_per_step": ms_m, "mixed_tuned": {"threads": th_m, "mg_coarse_max": cm_m},
+                "fp64_batched_ms_per_step": ms_d, "fp64_tuned": {"threads": th_d, "mg_coarse_max": cm_d},
+                "mixed_vs_fp64_batched": ms_d / ms_m,
+                "mixed_solves_per_s": len(blocks) / (ms_m * 1e-3),
+                "mixed_mean_iters": float(np.mean([i["inner_iters"] for i in inf_m])),
+                "status": sorted(set(i["status"] for i in inf_m + inf_d))})
+    # FP64 baseline without batching: one single-grid context per block,
+    # blocks stepped one after another
+    ctxs, fs = [], []
+    for b in blocks:
+        ctxs.append(fld.Context(b.nx, b.ny, b.geom, b.x_faces, b.y_faces, [(c.kind, c.value) for c in b.bc],
+                                fld.default_options(precision="fp64")))
+        fs.append(dev_fields(torch, b))
+    for c, g, b in zip(ctxs, fs, blocks):
+        c.step(g["E"].clone(), g["T"].clone(), g["rho"], g["kappa_R"], g["kappa_P"], g["c_v"], b.dt, g["ghost_E"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, g, b in zip(ctxs, fs, blocks):
+        c.step(g["E"].clone(), g["T"].clone(), g["rho"], g["kappa_R"], g["kappa_P"], g["c_v"], b.dt, g["ghost_E"])
+    torch.cuda.synchronize()
+    ms_pb = 1e3 * (time.perf_counter() - t0)
+    for c in ctxs:
+        c.close()
+    out["fp64_per_block_launch_ms_per_step"] = ms_pb
+    out["mixed_batched_vs_fp64_per_block"] = ms_pb / ms_m
+    return out
+
+
+def stress_extra(fld, torch, W, nsteps=5):
+    """4096 x 2048 spherical grid, opacity contrast 1e8, stiff coupling:
+    nsteps consecutive steps as one captured step graph (fld_steps), mixed
+    and FP64, scaled-norm stop at 1e-10 (the per-volume norm's binary64 floor
+    on this grid lies near 2e-9)."""
+    import numpy as np
+    prob = W.make_c5()
+    f = dev_fields(torch, prob)
+    out = {"workload": "c5: 4096x2048 spherical-polar, kappa contrast 1e8, c_v=1e6, dt=1e5, "
+                       f"{nsteps} steps per fld_steps call", "norm": "scaled"}
+    for prec in ("mixed", "fp64"):
+        ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
+                          [(b.kind, b.value) for b in prob.bc], fld.default_options(precision=prec, norm=1))
+        E, T = f["E"].clone(), f["T"].clone()
+        ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt)  # warm-up
+        E.copy_(f["E"])
+        T.copy_(f["T"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = ctx.steps(nsteps, E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, check=False)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / nsteps
+        ctx.close()
+        its = [i["inner_iters"] for i in infos]
+        out[prec] = {"ms_per_step": ms, "iters": its, "status": sorted(set(i["status"] for i in infos)),
+                     "max_rel_resid": max(i["rel_resid"] for i in infos),
+                     "mcell_iter_per_s": prob.nx * prob.ny * float(np.mean(its)) / (ms * 1e-3) / 1e6}
+    out["mixed_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    return out
+
+
+def copy_calibration(torch):
+    n = 512 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
 
 
 def main():
@@ -99,15 +236,24 @@ def main():
                                    "described in DESIGN.md"}), flush=True)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_2602_12545_amd as fld
+    from paper_2602_12545_amd import tune as tuner
     import fld_workloads as W
 
     prob = W.make(args.workload)
     ncell = prob.nx * prob.ny
+    base = dev_fields(torch, prob)
+    tuned, tune_table = None, None
+    if not args.no_tune:
+        tuned, tune_table = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
+                                            [(b.kind, b.value) for b in prob.bc], base, prob.dt,
+                                            base=fld.default_options(precision=args.precision), reps=1, cache="")
+    opts = options(fld, args.precision, tuned)
     profile = not args.no_profile
-    # timed region: the line-sweep kernels are bracketed by HIP events (plain
-    # launches; events inside captured graphs cannot be timed on ROCm 7.2)
-    ms, infos, prof = run_steps(fld, torch, prob, args.precision, args.steps, args.warmup, profile)
+    ms, infos, prof = run_steps(fld, torch, prob, base, opts, args.steps, args.warmup, profile)
     iters = sum(i["inner_iters"] for i in infos) / len(infos)
     geom = "stretched Cartesian" if prob.geom == 0 else "spherical-polar"
     out = {
@@ -124,7 +270,9 @@ def main():
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {prob.nx}x{prob.ny} {geom}, one implicit FLD step to 1e-10",
-                   "cells": ncell, "precision": args.precision, "rel_tol": 1e-10, "norm": "per-volume rows"},
+                   "cells": ncell, "precision": args.precision, "rel_tol": 1e-10, "norm": "per-volume rows",
+                   "schedule": {k: getattr(opts, k) for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk")},
+                   "tuned": tuned is not None},
         "inner_iters": iters,
         "mcell_iter_per_s": ncell * iters / ms / 1e6,
         "final_rel_resid": max(i["rel_resid"] for i in infos),
@@ -141,18 +289,18 @@ def main():
         achieved = bpl / (kern_us * 1e-6) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "k_line (multigrid zebra line sweeps, all levels)",
+                           "kernel": "multigrid line sweeps (k_band, k_line; all levels) in the last timed step",
                            "launches": n, "avg_launch_us": kern_us, "avg_launch_us_events_raw": raw_us,
                            "event_pair_overhead_us": prof["overhead_us"], "bytes_per_launch": bpl}
-    if profile:
-        # the same steps with hipGraph-captured CG chunks and no events
-        ms_g, _, _ = run_steps(fld, torch, prob, args.precision, max(3, args.steps // 2), 1, False)
-        out["ms_per_step_graph_no_events"] = ms_g * 1e3
     if not args.no_fp64 and args.precision != "fp64":
-        ms64, infos64, _ = run_steps(fld, torch, prob, "fp64", max(3, args.steps // 2), 1, False)
+        ms64, infos64, _ = run_steps(fld, torch, prob, base, options(fld, "fp64", tuned), max(3, args.steps // 2), 1,
+                                     False)
         out["fp64_ms_per_step"] = ms64 * 1e3
         out["fp64_inner_iters"] = sum(i["inner_iters"] for i in infos64) / len(infos64)
         out["mixed_vs_fp64_speedup"] = ms64 / ms
+    if not args.no_extra:
+        out["batched_blocks"] = batch_extra(fld, torch, W, None if args.no_tune else tuner)
+        out["stress_multistep"] = stress_extra(fld, torch, W)
     if not args.no_cpu and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)

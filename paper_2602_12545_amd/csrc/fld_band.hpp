@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     T a, d, c, r;
                     coef(q, a, d, c, r);
                     const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
-                    const T inv = T(1) / den;
+                    const T inv = line_rcp(den);
                     cp[q] = c * inv;
                     gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
                     gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
@@ -172,13 +172,13 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(Rr, lane + st, 64);
                     T nA = T(0), nB = B, nC = T(0), nR = Rr;
                     if (k - st >= 0) {
-                        const T al = -A / Bm;
+                        const T al = -A * line_rcp(Bm);
                         nA = al * Am;
                         nB += al * Cm;
                         nR += al * Rm;
                     }
                     if (k + st < K) {
-                        const T ga = -C / Bp;
+                        const T ga = -C * line_rcp(Bp);
                         nC = ga * Cp;
                         nB += ga * Ap;
                         nR += ga * Rp;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     C = nC;
                     Rr = nR;
                 }
-                X = Rr / B;
+                X = Rr * line_rcp(B);
                 Xp = __shfl(X, lane - 1, 64);
                 if (k == 0) Xp = T(0);
             } else {
@@ -207,13 +207,13 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     const T a = sA[t], bq = sB[t], c = sC[t], r = sR[t];
                     T na = T(0), nb = bq, nc = T(0), nr = r;
                     if (k - st >= 0) {
-                        const T al = -a / sB[t - st];
+                        const T al = -a * line_rcp(sB[t - st]);
                         na = al * sA[t - st];
                         nb += al * sC[t - st];
                         nr += al * sR[t - st];
                     }
                     if (k + st < K) {
-                        const T ga = -c / sB[t + st];
+                        const T ga = -c * line_rcp(sB[t + st]);
                         nc = ga * sC[t + st];
                         nb += ga * sA[t + st];
                         nr += ga * sR[t + st];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     sR[t] = nr;
                     __syncthreads();
                 }
-                X = sR[t] / sB[t];
+                X = sR[t] * line_rcp(sB[t]);
                 __syncthreads();
                 sR[t] = X;
                 __syncthreads();

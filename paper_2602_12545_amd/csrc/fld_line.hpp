@@ -6,6 +6,21 @@
 
 namespace fld {
 
+// Reciprocal for the inner line solves: the hardware approximation (1 ulp)
+// in binary32; in binary64 the approximation refined by two Newton steps
+// (full precision).  Keeps the division latency out of the Thomas chains.
+template <typename T>
+__device__ inline T line_rcp(T d) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_amdgcn_rcpf(d);
+    } else {
+        T r = __builtin_amdgcn_rcp(d);
+        r = r * (T(2) - d * r);
+        r = r * (T(2) - d * r);
+        return r;
+    }
+}
+
 // Lanes per line for a line of `na` cells with at most LM cells per lane
 // (power of two, <= 64).
 template <int LM>
@@ -78,7 +93,7 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
                 T a, d, c, r;
                 coef(q, a, d, c, r);
                 const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
-                const T inv = T(1) / den;
+                const T inv = line_rcp(den);
                 cp[q] = c * inv;
                 gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
                 gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
@@ -118,13 +133,13 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
             const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(R, lane + st, 64);
             T nA = T(0), nB = B, nC = T(0), nR = R;
             if (k - st >= 0) {
-                const T al = -A / Bm;
+                const T al = -A * line_rcp(Bm);
                 nA = al * Am;
                 nB += al * Cm;
                 nR += al * Rm;
             }
             if (k + st < K) {
-                const T ga = -C / Bp;
+                const T ga = -C * line_rcp(Bp);
                 nC = ga * Cp;
                 nB += ga * Ap;
                 nR += ga * Rp;
@@ -134,7 +149,7 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
             C = nC;
             R = nR;
         }
-        const T X = R / B;
+        const T X = R * line_rcp(B);
         T Xp = __shfl(X, lane - 1, 64);
         if (k == 0) Xp = T(0);
         if (active) {

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
             T a, d, c, r;
             coef(q, a, d, c, r);
             const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
-            const T inv = T(1) / den;
+            const T inv = line_rcp(den);
             cp[q] = c * inv;
             gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
             gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
@@ -525,13 +525,13 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
         const T a = sA[t], bb = sB[t], c = sC[t], r = sR[t];
         T na = T(0), nb = bb, nc = T(0), nr = r;
         if (k - st >= 0) {
-            const T al = -a / sB[t - st];
+            const T al = -a * line_rcp(sB[t - st]);
             na = al * sA[t - st];
             nb += al * sC[t - st];
             nr += al * sR[t - st];
         }
         if (k + st < K) {
-            const T ga = -c / sB[t + st];
+            const T ga = -c * line_rcp(sB[t + st]);
             nc = ga * sC[t + st];
             nb += ga * sA[t + st];
             nr += ga * sR[t + st];
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
         sR[t] = nr;
         __syncthreads();
     }
-    const T X = sR[t] / sB[t];
+    const T X = sR[t] * line_rcp(sB[t]);
     __syncthreads();
     sR[t] = X;
     __syncthreads();

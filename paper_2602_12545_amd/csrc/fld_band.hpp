@@ -13,10 +13,13 @@
 // sweep direction reads rows again), optionally with the right-hand side
 // transposed alongside.
 //
-// Inside a pass, a row of na cells is split into K chunks of L cells (the
-// same K, L as the one-half-sweep kernel), one chunk per thread; the chunk
-// interior is eliminated locally and the K chunk-end unknowns are solved by
-// cyclic reduction, with wavefront shuffles when K <= 64 and in LDS otherwise.
+// Inside a pass, a row of na cells is split into K chunks of L <= LM cells
+// (the chunking of the one-half-sweep kernel), one chunk per thread; the
+// chunk interior is eliminated locally and the K chunk-end unknowns are solved
+// by cyclic reduction, with wavefront shuffles when K <= 64 and in LDS
+// otherwise.  (Longer chunks that keep 1024-cell rows inside one wavefront
+// were measured slower: the per-lane Thomas chain doubles and occupancy
+// halves.)
 #pragma once
 
 #include "fld_mg.hpp"
@@ -34,7 +37,7 @@ inline size_t band_lds_bytes(int na, int R, bool with_b) {
            16 * sizeof(double);
 }
 
-template <typename T, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
+template <typename T, int LM, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
 __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, int L, const T* __restrict__ m,
                                                   const T* __restrict__ We, const T* __restrict__ Wn,
                                                   const T* __restrict__ b, const T* __restrict__ xin,
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     if (sc->done) return;
     if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
     extern __shared__ __align__(16) unsigned char band_smem[];
-    constexpr int NT = kBandWG, LM = kLineMaxL;
+    constexpr int NT = kBandWG;
     T* rows = reinterpret_cast<T*>(band_smem);               // (R + 2) x nx: slot = row - (r0 - 1)
     T* bb = rows + (size_t)(R + 2) * nx;                      // R x nx (WRITE_BT)
     T* pcr = bb + (WRITE_BT ? (size_t)R * nx : 0);            // 7 x NT
@@ -117,12 +120,20 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 for (int q = 0; q < LM; ++q)
                     if (q < L && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
             }
-            auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+            // diagonal and right-hand side of every chunk row (the loaded
+            // arrays die here, which keeps register pressure low)
+            T vd[LM], vr[LM];
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
                 const T ww = (q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0];
-                d = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
-                a = -ww;
+                vd[q] = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
+                vr[q] = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
+            }
+            auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+                a = -((q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0]);
+                d = vd[q];
                 c = -vwe[q];
-                r = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
+                r = vr[q];
             };
             T cp[LM], gy[LM], gu[LM], gv[LM];
 #pragma unroll
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 }
             const bool has_next = k + 1 < K;
             T X, Xp;
-            if (wave_pcr) {
+            if (LM > kLineMaxL || wave_pcr) {
                 T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
                 if (!has_next) yn = un = vn = T(0);
                 T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, Rr = rE - aE * yl - cE * yn;
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 X = Rr * line_rcp(B);
                 Xp = __shfl(X, lane - 1, 64);
                 if (k == 0) Xp = T(0);
-            } else {
+            } else if constexpr (LM == kLineMaxL) {
                 sy0[t] = gy[0];
                 su0[t] = gu[0];
                 sv0[t] = gv[0];
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                                                     gv[q < LM - 1 ? q : 0] * X;
                 }
             }
-            if (!wave_pcr) __syncthreads();  // the LDS reduction arrays are reused by the next pass
+            if (LM == kLineMaxL && !wave_pcr) __syncthreads();  // the LDS reduction arrays are reused next pass
         }
     };
 

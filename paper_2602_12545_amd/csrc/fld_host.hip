@@ -233,9 +233,10 @@ int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, c
         P.bytes[slot] = words * sizeof(T);
         (void)hipEventRecord(P.ev[2 * slot], st);
     }
-    k_band<T, MODE, FIRST, OUT_T, WRITE_BT, DOT><<<grid, kBandWG, band_lds_bytes<T>(v.nx, R, WRITE_BT), st>>>(
-        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, c->part, c->sc,
-        slot >= 0 ? P.ran + slot : nullptr);
+    const size_t lds = band_lds_bytes<T>(v.nx, R, WRITE_BT);
+    int* ran = slot >= 0 ? P.ran + slot : nullptr;
+    k_band<T, kLineMaxL, MODE, FIRST, OUT_T, WRITE_BT, DOT><<<grid, kBandWG, lds, st>>>(
+        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, c->part, c->sc, ran);
     if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
 }
@@ -297,7 +298,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     }
     if (in.sub_first > 0) {
         LevelT<T>& f = in.lv[in.sub_first];
-        k_subcycle<T><<<1, kSubThreads, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
+        k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
     } else {
         LevelT<T>& cl = in.lv[L - 1];
         k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
@@ -533,16 +534,13 @@ fld_status alloc_inner(fld_ctx* ctx) {
         }
         if (need_max > 65536) {
             const int sz = (int)need_max;
-            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_ZERO, 0, true, true, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
-            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 0, false, false, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
-            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_PROLONG, 1, true, false, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
-            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 1, false, false, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
-            HIPCHK(hipFuncSetAttribute((const void*)k_band<T, LINE_NORMAL, 1, false, false, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, sz));
+            const void* fns[] = {
+                (const void*)k_band<T, kLineMaxL, LINE_ZERO, 0, true, true, false>,
+                (const void*)k_band<T, kLineMaxL, LINE_NORMAL, 0, false, false, false>,
+                (const void*)k_band<T, kLineMaxL, LINE_PROLONG, 1, true, false, false>,
+                (const void*)k_band<T, kLineMaxL, LINE_NORMAL, 1, false, false, true>,
+                (const void*)k_band<T, kLineMaxL, LINE_NORMAL, 1, false, false, false>};
+            for (const void* f : fns) HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, sz));
         }
     }
     HIPCHK(hipMemset(in.r, 0, sizeof(T) * n));

@@ -79,12 +79,18 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
             vxn[q] = (!ZERO && ok && line + 1 < nlines) ? x[c + sl] : T(0);
             vxs[q] = (!ZERO && ok && line > 0) ? x[c - sl] : T(0);
         }
-        auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+        T vd[LM], vr[LM];
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
             const T wp = (q == 0) ? wprev : va[q > 0 ? q - 1 : 0];
-            d = vm[q] + ((wp + va[q]) + (vcs[q] + vcn[q]));
-            a = -wp;
+            vd[q] = vm[q] + ((wp + va[q]) + (vcs[q] + vcn[q]));
+            vr[q] = vb[q] + vcn[q] * vxn[q] + vcs[q] * vxs[q];
+        }
+        auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+            a = -((q == 0) ? wprev : va[q > 0 ? q - 1 : 0]);
+            d = vd[q];
             c = -va[q];
-            r = vb[q] + vcn[q] * vxn[q] + vcs[q] * vxs[q];
+            r = vr[q];
         };
         T cp[LM], gy[LM], gu[LM], gv[LM];
 #pragma unroll

@@ -956,7 +956,10 @@ namespace fld {
 // coarse sub-cycle: the V-cycle of all levels >= ls in one workgroup, in LDS
 // ---------------------------------------------------------------------------
 
-constexpr int kSubThreads = 1024;
+// threads of the sub-cycle workgroup: binary64 line solves need twice the
+// registers, so the binary64 workgroup is half as wide
+template <typename T>
+constexpr int kSubThreads = sizeof(T) == 4 ? 1024 : 512;
 constexpr int kSubMaxLevels = 12;
 
 template <typename T>
@@ -988,7 +991,7 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
     T* Wn = We + L.size;
     T* b = Wn + L.size;
     T* x = b + L.size;
-    const int wave = threadIdx.x >> 6, nw = kSubThreads / 64;
+    const int wave = threadIdx.x >> 6, nw = kSubThreads<T> / 64;
     if (xdir)
         wave_line_sweep<T, kLineMaxL, false>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
     else
@@ -996,7 +999,7 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T* __restrict__ bin, T* __restrict__ xout,
+__global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, const T* __restrict__ bin, T* __restrict__ xout,
                                                           const Scalars* __restrict__ sc) {
     if (sc->done) return;
     extern __shared__ unsigned char smem_raw[];
@@ -1007,7 +1010,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const SubLevel<T>& L = S.lv[l];
         const int n = L.nx * L.ny, z = L.size;
         T* m = pool + L.off;
-        for (int c = t; c < n; c += kSubThreads) {
+        for (int c = t; c < n; c += kSubThreads<T>) {
             const int i = c % L.nx, j = c / L.nx, cl = j * L.pitch + i;
             m[cl] = L.m[c];
             m[z + cl] = L.We[c];
@@ -1021,7 +1024,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
     for (int l = 0; l < S.nlev - 1; ++l) {
         const SubLevel<T>& L = S.lv[l];
         T* x = pool + L.off + 4 * L.size;
-        for (int c = t; c < L.size; c += kSubThreads) x[c] = T(0);
+        for (int c = t; c < L.size; c += kSubThreads<T>) x[c] = T(0);
         __syncthreads();
         const bool first_x = !L.tr;  // primary direction first, as on the grid levels
         for (int dir = 0; dir < 2; ++dir) {
@@ -1039,7 +1042,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         T* Wn = We + L.size;
         T* b = Wn + L.size;
         T* bc = pool + C.off + 3 * C.size;
-        for (int cc = t; cc < nc; cc += kSubThreads) {
+        for (int cc = t; cc < nc; cc += kSubThreads<T>) {
             const int I = cc % C.nx, J = cc / C.nx;
             T acc = T(0);
             for (int bb = 0; bb < 2; ++bb)
@@ -1065,7 +1068,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const int n = L.nx * L.ny;
         T* b = pool + L.off + 3 * L.size;
         T* x = b + L.size;
-        for (int c = t; c < n; c += kSubThreads) {
+        for (int c = t; c < n; c += kSubThreads<T>) {
             const int i = c % L.nx, j = c / L.nx;
             const int row = L.tr ? i * L.ny + j : c;
             T acc = T(0);
@@ -1085,7 +1088,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const int n = L.nx * L.ny;
         T* x = pool + L.off + 4 * L.size;
         const T* xc = pool + C.off + 4 * C.size;
-        for (int c = t; c < n; c += kSubThreads) {
+        for (int c = t; c < n; c += kSubThreads<T>) {
             const int i = c % L.nx, j = c / L.nx;
             x[j * L.pitch + i] += xc[(j >> 1) * C.pitch + (i >> 1)];
         }
@@ -1104,7 +1107,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subcycle(SubCycle<T> S, const T
         const SubLevel<T>& L = S.lv[0];
         const int n = L.nx * L.ny;
         const T* x = pool + L.off + 4 * L.size;
-        for (int c = t; c < n; c += kSubThreads) {
+        for (int c = t; c < n; c += kSubThreads<T>) {
             const int i = c % L.nx, j = c / L.nx;
             xout[L.tr ? i * L.ny + j : c] = x[j * L.pitch + i];
         }

@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner's choice")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched-block and stress workloads")
     ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="event-time every timed step (plain launches; for comparison with a kernel trace)")
+    ap.add_argument("--norm", default="rows", choices=["rows", "scaled"],
+                    help="stop norm (the 4096x2048 spherical recipe needs 'scaled' for 1e-10)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale for HBM traffic counters)")
     return ap.parse_args()
@@ -60,6 +64,39 @@ def dev_fields(torch, prob):
     return f
 
 
+def kernel_source_digest():
+    """Digest of the kernel sources; HBM traffic counters taken on other
+    sources no longer describe the kernels."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2602_12545_amd", "csrc")
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name="pmc_c2_line_sweeps.md"):
+    """HBM bytes per line-sweep launch from the committed counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    vals = {}
+    for line in open(path):
+        line = line.strip().strip("`")
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None, "counters taken on other kernel sources"
+    try:
+        return float(vals["traffic_bytes_per_launch"]), "profiles/" + name
+    except (KeyError, ValueError):
+        return None, "counter summary incomplete"
+
+
 def options(fld, prec, tuned, norm=0):
     o = fld.default_options(precision=prec, norm=norm)
     if tuned is not None:
@@ -68,9 +105,10 @@ def options(fld, prec, tuned, norm=0):
     return o
 
 
-def run_steps(fld, torch, prob, base, opts, steps, warmup, profile):
-    """Mean wall time of one step over `steps` timed steps (the last one with
-    event-timed line sweeps when `profile`), and the per-step infos."""
+def run_steps(fld, torch, prob, base, opts, steps, warmup, profile, profile_all=False):
+    """Mean wall time of one step over `steps` timed steps (the last one, or
+    all with `profile_all`, with event-timed line sweeps when `profile`), and
+    the per-step infos."""
     ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                       [(b.kind, b.value) for b in prob.bc], opts)
     E = base["E"].clone()
@@ -87,7 +125,7 @@ def run_steps(fld, torch, prob, base, opts, steps, warmup, profile):
     infos = []
     t0 = time.perf_counter()
     for s in range(steps):
-        if profile and s == steps - 1:
+        if profile and s == (0 if profile_all else steps - 1):
             ctx.profile(True)
         infos.append(one())
     torch.cuda.synchronize()
@@ -101,11 +139,11 @@ def run_steps(fld, torch, prob, base, opts, steps, warmup, profile):
     return dt / steps, infos, prof
 
 
-def cpu_baseline(W, n=768):
-    """The CPU oracle (assembly + sparse LU + gas update), single-threaded, on
-    the headline recipe at n x n cells; the rate is scaled by cell count to the
-    full grid (which flatters the CPU: the direct solve grows faster than
-    linearly)."""
+def cpu_baseline(W, n=1024):
+    """The CPU oracle (assembly + sparse LU + gas update), single-threaded, one
+    step of the headline recipe at n x n cells (the full grid by default; a
+    smaller n is scaled by cell count, which flatters the CPU since the direct
+    solve grows faster than linearly)."""
     from threadpoolctl import threadpool_limits
     from oracle import fld_oracle as O
     prob = W.make_c2(nx=n, ny=n)
@@ -117,7 +155,7 @@ def cpu_baseline(W, n=768):
     full = 1024 * 1024
     return {"value": (1.0 / dt) * (n * n) / full, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"c2 recipe at {n}x{n} cells: one step = FP64 assembly + SuperLU direct solve + gas update, "
-                      f"{dt:.1f} s on one host core; rate scaled by cell count to 1024x1024"}
+                      f"{dt:.1f} s on one host core" + ("" if n == 1024 else "; rate scaled by cell count to 1024x1024")}
 
 
 def batch_extra(fld, torch, W, tune):
@@ -251,9 +289,10 @@ def main():
         tuned, tune_table = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                             [(b.kind, b.value) for b in prob.bc], base, prob.dt,
                                             base=fld.default_options(precision=args.precision), reps=1, cache="")
-    opts = options(fld, args.precision, tuned)
+    norm = 1 if args.norm == "scaled" else 0
+    opts = options(fld, args.precision, tuned, norm)
     profile = not args.no_profile
-    ms, infos, prof = run_steps(fld, torch, prob, base, opts, args.steps, args.warmup, profile)
+    ms, infos, prof = run_steps(fld, torch, prob, base, opts, args.steps, args.warmup, profile, args.profile_all)
     iters = sum(i["inner_iters"] for i in infos) / len(infos)
     geom = "stretched Cartesian" if prob.geom == 0 else "spherical-polar"
     out = {
@@ -270,7 +309,8 @@ def main():
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {prob.nx}x{prob.ny} {geom}, one implicit FLD step to 1e-10",
-                   "cells": ncell, "precision": args.precision, "rel_tol": 1e-10, "norm": "per-volume rows",
+                   "cells": ncell, "precision": args.precision, "rel_tol": 1e-10,
+                   "norm": "per-volume rows" if norm == 0 else "Jacobi-scaled",
                    "schedule": {k: getattr(opts, k) for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk")},
                    "tuned": tuned is not None},
         "inner_iters": iters,
@@ -287,14 +327,15 @@ def main():
         kern_us = max(raw_us - prof["overhead_us"], 1e-3)
         bpl = prof["bytes"] / n
         achieved = bpl / (kern_us * 1e-6) / 1e9
+        traffic, tnote = measured_traffic() if args.workload == "c2" else (None, "counters taken on c2 only")
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tnote,
                            "kernel": "multigrid line sweeps (k_band, k_line; all levels) in the last timed step",
                            "launches": n, "avg_launch_us": kern_us, "avg_launch_us_events_raw": raw_us,
                            "event_pair_overhead_us": prof["overhead_us"], "bytes_per_launch": bpl}
     if not args.no_fp64 and args.precision != "fp64":
-        ms64, infos64, _ = run_steps(fld, torch, prob, base, options(fld, "fp64", tuned), max(3, args.steps // 2), 1,
-                                     False)
+        ms64, infos64, _ = run_steps(fld, torch, prob, base, options(fld, "fp64", tuned, norm), max(3, args.steps // 2),
+                                     1, False)
         out["fp64_ms_per_step"] = ms64 * 1e3
         out["fp64_inner_iters"] = sum(i["inner_iters"] for i in infos64) / len(infos64)
         out["mixed_vs_fp64_speedup"] = ms64 / ms

@@ -65,15 +65,19 @@ def dev_fields(torch, prob):
 
 
 def kernel_source_digest():
-    """Digest of the kernel sources; HBM traffic counters taken on other
-    sources no longer describe the kernels."""
+    """Digest of the kernel sources with comments and white space removed;
+    HBM traffic counters taken on other code no longer describe the kernels."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2602_12545_amd", "csrc")
     h = hashlib.sha1()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hpp", ".hip")):
+            src = open(os.path.join(d, f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            src = re.sub(r"//[^\n]*", "", src)
             h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+            h.update(re.sub(r"\s+", "", src).encode())
     return h.hexdigest()[:16]
 
 

@@ -235,7 +235,7 @@ const char* fld_version(void);
 void fld_destroy(fld_ctx* ctx);
 
 /* ------------------------------------------------------------------------
- * Batched blocks (Section 3.3, static mesh refinement: every block is an
+ * Batched blocks (Section 3.2.2, static mesh refinement: every block is an
  * independent grid whose boundaries are ghost cells filled from its parent
  * or neighbours).  A batch holds nblocks Cartesian blocks of nx[b] x ny[b]
  * cells (1 .. 512 per side) with uniform spacing dx[b], dy[b] (cm; faces at

@@ -1,5 +1,5 @@
 // Batched implicit radiation step for many independent blocks (static mesh
-// refinement blocks in their independent form, Section 3.3: every block sees
+// refinement blocks in their independent form, Section 3.2.2: every block sees
 // its neighbours and parent only through ghost values).
 //
 // One workgroup owns one block for a whole step: assembly (FP64), the

@@ -1,4 +1,4 @@
-"""Batched blocks (Section 3.3 independent-block form): one launch steps every
+"""Batched blocks (Section 3.2.2 independent-block form): one launch steps every
 block; each block must match the FP64 oracle's step of that block alone.
 
 Tolerances as for the single-grid parity tests: solved to a 1e-12 relative

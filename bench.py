@@ -288,12 +288,13 @@ def main():
     prob = W.make(args.workload)
     ncell = prob.nx * prob.ny
     base = dev_fields(torch, prob)
+    norm = 1 if args.norm == "scaled" else 0
     tuned, tune_table = None, None
     if not args.no_tune:
         tuned, tune_table = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                             [(b.kind, b.value) for b in prob.bc], base, prob.dt,
-                                            base=fld.default_options(precision=args.precision), reps=1, cache="")
-    norm = 1 if args.norm == "scaled" else 0
+                                            base=fld.default_options(precision=args.precision, norm=norm), reps=1,
+                                            cache="")
     opts = options(fld, args.precision, tuned, norm)
     profile = not args.no_profile
     ms, infos, prof = run_steps(fld, torch, prob, base, opts, args.steps, args.warmup, profile, args.profile_all)

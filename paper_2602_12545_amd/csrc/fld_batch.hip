@@ -203,7 +203,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
             B.lnx[L] = lx;
             B.lny[L] = ly;
             B.loff[L] = lo;
-            lo += (long long)lx * ly;
+            lo += ((long long)lx * ly + 3) / 4 * 4;  // 16-byte aligned levels (vector loads)
             ++L;
             if ((long long)lx * ly <= o.mg_coarse_max) break;
             lx = (lx + 1) / 2;

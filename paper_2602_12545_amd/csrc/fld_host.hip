@@ -527,7 +527,13 @@ fld_status alloc_inner(fld_ctx* ctx) {
         for (int l = 0; l < Ld; ++l) {
             LevelT<T>& lv = in.lv[l];
             const int pnx = lv.tr ? lv.ny : lv.nx, pny = lv.tr ? lv.nx : lv.ny;
-            const int Rp = pick(pnx, pny, true), Rq = pick(pny, pnx, false);
+            // rows so long that even 4-row bands overflow LDS leave one
+            // workgroup per CU: such levels are bandwidth-bound and run faster
+            // with the one-launch-per-half-sweep kernels (measured on 4096-cell
+            // rows: 462 us against 260 us per level visit)
+            const bool roomy = band_lds_bytes<T>(pnx, 4, true) <= (size_t)lds_max &&
+                               band_lds_bytes<T>(pny, 4, false) <= (size_t)lds_max;
+            const int Rp = roomy ? pick(pnx, pny, true) : 0, Rq = roomy ? pick(pny, pnx, false) : 0;
             lv.band = Rp > 0 && Rq > 0;
             lv.Rp = Rp;
             lv.Rq = Rq;

@@ -4,6 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <type_traits>
+
 namespace fld {
 
 // Reciprocal for the inner line solves: the hardware approximation (1 ulp)
@@ -21,6 +24,45 @@ __device__ inline T line_rcp(T d) {
     }
 }
 
+// N consecutive values from a 16-byte aligned address with 16-byte loads.
+template <typename T, int N>
+__device__ inline void load_vec(const T* __restrict__ p, T (&v)[N]) {
+    constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const V* q = reinterpret_cast<const V*>(p);
+#pragma unroll
+    for (int k = 0; k < N / VW; ++k) {
+        const V w = q[k];
+        if constexpr (sizeof(T) == 4) {
+            v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
+        } else {
+            v[2 * k] = w.x; v[2 * k + 1] = w.y;
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ inline void store_vec(T* __restrict__ p, const T (&v)[N]) {
+    constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    V* q = reinterpret_cast<V*>(p);
+#pragma unroll
+    for (int k = 0; k < N / VW; ++k) {
+        V w;
+        if constexpr (sizeof(T) == 4) {
+            w.x = v[4 * k]; w.y = v[4 * k + 1]; w.z = v[4 * k + 2]; w.w = v[4 * k + 3];
+        } else {
+            w.x = v[2 * k]; w.y = v[2 * k + 1];
+        }
+        q[k] = w;
+    }
+}
+
+template <typename T, int N>
+__device__ inline void fill(T (&v)[N], T a) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = a;
+}
 // Lanes per line for a line of `na` cells with at most LM cells per lane
 // (power of two, <= 64).
 template <int LM>
@@ -66,18 +108,39 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
         const long long lb = (long long)(active ? line : 0) * sl;
         T vm[LM], va[LM], vcn[LM], vcs[LM], vb[LM], vxn[LM], vxs[LM];
         const T wprev = (active && s0 > 0 && s0 - 1 < na) ? Wa[lb + (long long)(s0 - 1) * sa] : T(0);
+        // a full chunk along a contiguous row, 16-byte aligned in every array
+        // (the arrays share their element offsets): vector loads
+        constexpr int VW = 16 / sizeof(T);
+        const bool vec = sa == 1 && active && L == LM && s0 + LM <= na && (sl % VW) == 0 &&
+                         ((reinterpret_cast<uintptr_t>(m + lb + s0) | reinterpret_cast<uintptr_t>(Wa + lb + s0) |
+                           reinterpret_cast<uintptr_t>(Wc + lb + s0) | reinterpret_cast<uintptr_t>(b + lb + s0) |
+                           reinterpret_cast<uintptr_t>(x + lb + s0)) & 15) == 0;
+        if (vec) {
+            const long long c0 = lb + s0;
+            load_vec<T, LM>(m + c0, vm);
+            load_vec<T, LM>(Wa + c0, va);
+            load_vec<T, LM>(Wc + c0, vcn);
+            load_vec<T, LM>(b + c0, vb);
+            if (line > 0) load_vec<T, LM>(Wc + c0 - sl, vcs);
+            else fill<T, LM>(vcs, T(0));
+            if (!ZERO && line + 1 < nlines) load_vec<T, LM>(x + c0 + sl, vxn);
+            else fill<T, LM>(vxn, T(0));
+            if (!ZERO && line > 0) load_vec<T, LM>(x + c0 - sl, vxs);
+            else fill<T, LM>(vxs, T(0));
+        } else {
 #pragma unroll
-        for (int q = 0; q < LM; ++q) {
-            const int g = s0 + q;
-            const bool ok = active && q < L && g < na;
-            const long long c = lb + (long long)g * sa;
-            vm[q] = ok ? m[c] : T(1);
-            va[q] = ok ? Wa[c] : T(0);
-            vcn[q] = ok ? Wc[c] : T(0);
-            vcs[q] = (ok && line > 0) ? Wc[c - sl] : T(0);
-            vb[q] = ok ? b[c] : T(0);
-            vxn[q] = (!ZERO && ok && line + 1 < nlines) ? x[c + sl] : T(0);
-            vxs[q] = (!ZERO && ok && line > 0) ? x[c - sl] : T(0);
+            for (int q = 0; q < LM; ++q) {
+                const int g = s0 + q;
+                const bool ok = active && q < L && g < na;
+                const long long c = lb + (long long)g * sa;
+                vm[q] = ok ? m[c] : T(1);
+                va[q] = ok ? Wa[c] : T(0);
+                vcn[q] = ok ? Wc[c] : T(0);
+                vcs[q] = (ok && line > 0) ? Wc[c - sl] : T(0);
+                vb[q] = ok ? b[c] : T(0);
+                vxn[q] = (!ZERO && ok && line + 1 < nlines) ? x[c + sl] : T(0);
+                vxs[q] = (!ZERO && ok && line > 0) ? x[c - sl] : T(0);
+            }
         }
         T vd[LM], vr[LM];
 #pragma unroll

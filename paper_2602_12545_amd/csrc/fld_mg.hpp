@@ -337,45 +337,6 @@ __global__ __launch_bounds__(256) void k_post_point(int nx, int ny, const T* __r
 
 constexpr int kLineMaxL = 8;    // cells per thread chunk
 
-// N consecutive values from a 16-byte aligned address with 16-byte loads.
-template <typename T, int N>
-__device__ inline void load_vec(const T* __restrict__ p, T (&v)[N]) {
-    constexpr int VW = 16 / sizeof(T);
-    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-    const V* q = reinterpret_cast<const V*>(p);
-#pragma unroll
-    for (int k = 0; k < N / VW; ++k) {
-        const V w = q[k];
-        if constexpr (sizeof(T) == 4) {
-            v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
-        } else {
-            v[2 * k] = w.x; v[2 * k + 1] = w.y;
-        }
-    }
-}
-
-template <typename T, int N>
-__device__ inline void store_vec(T* __restrict__ p, const T (&v)[N]) {
-    constexpr int VW = 16 / sizeof(T);
-    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-    V* q = reinterpret_cast<V*>(p);
-#pragma unroll
-    for (int k = 0; k < N / VW; ++k) {
-        V w;
-        if constexpr (sizeof(T) == 4) {
-            w.x = v[4 * k]; w.y = v[4 * k + 1]; w.z = v[4 * k + 2]; w.w = v[4 * k + 3];
-        } else {
-            w.x = v[2 * k]; w.y = v[2 * k + 1];
-        }
-        q[k] = w;
-    }
-}
-
-template <typename T, int N>
-__device__ inline void fill(T (&v)[N], T a) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = a;
-}
 constexpr int kLineWG = 512;    // threads per workgroup; lines of K chunks, 512/K lines per workgroup
 enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 

@@ -98,6 +98,7 @@ struct fld_ctx {
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
     std::vector<Level64> h64;
     double* part = nullptr;
+    double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
     size_t npart = 0;
     Scalars* sc = nullptr;
     Scalars* hsc = nullptr;  // pinned mirror
@@ -376,16 +377,17 @@ void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
 }
 
 // Reliable update (only acts when the device flag `pending` is set, or when
-// forced at the start of a solve): E += corr x, true FP64 residual, its norms
-// and the convergence decision, then the re-scaled inner residual.
+// forced at the start of a solve): true FP64 residual of E + corr x, its norms
+// and the convergence decision, then E += corr x and the re-scaled inner
+// residual.
 template <typename T>
 void enqueue_check(fld_ctx* c, Inner<T>& in, double* E, int force, hipStream_t st) {
     const int nx = c->nx, ny = c->ny, n = nx * ny;
     const dim3 tg = tile_grid(nx, ny);
-    if (!force) k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, c->sc, 0);
-    k_resid64<<<tg, blk2d(), 0, st>>>(c->met, E, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part, c->sc, force);
+    k_resid64<T><<<tg, blk2d(), 0, st>>>(c->met, E, in.x, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part, c->sc,
+                                         force);
     k_reduce_resid<<<1, kRedThreads, 0, st>>>(c->part, (int)(tg.x * tg.y), c->mu, c->sc, force);
-    k_demote<T><<<grid1d(n), 256, 0, st>>>(n, c->r64, in.r, in.x, c->sc);
+    k_apply<T><<<grid1d(n), 256, 0, st>>>(n, E, c->r64, in.r, in.x, c->sc);
 }
 
 // One CG iteration ("slot"); `par` selects the p buffer pair (iterations
@@ -398,9 +400,8 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     const int ntiles = (int)(tg.x * tg.y), nb1 = grid1d(n);
     k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part,
                                       c->sc);
-    k_reduce_pq<<<1, kRedThreads, 0, st>>>(c->part, ntiles, c->sc);
-    k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, c->sc);
-    k_reduce_rr<<<1, kRedThreads, 0, st>>>(c->part, nb1, c->sc);
+    k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, ntiles, c->part2, c->sc);
+    k_reduce_rr<<<1, kRedThreads, 0, st>>>(c->part2, nb1, c->sc);
     enqueue_check<T>(c, in, E, 0, st);
     enqueue_vcycle<T>(c, in, st);
 }
@@ -905,6 +906,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     const size_t tiles = (size_t)tile_grid(nx, ny).x * tile_grid(nx, ny).y;
     ctx->npart = std::max<size_t>(tiles * 5, (size_t)k1DBlocksMax);
     ALLOC(ctx->part, ctx->npart);
+    ALLOC(ctx->part2, (size_t)k1DBlocksMax);
     ALLOC(ctx->sc, 1);
     ALLOC(ctx->err_flag, 1);
     ALLOC(ctx->mu, 1);

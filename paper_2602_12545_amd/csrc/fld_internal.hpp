@@ -45,6 +45,7 @@ struct Scalars {
     double rr_ref;      // inner residual norm^2 at the last reliable update
     double gamma;       // current residual scale: r_inner = r / gamma, gamma = ||r||_2
     double corr;        // gamma / mu: E += corr * x_inner
+    double corr_apply;  // the correction the last true-residual check evaluated E with
     double rho_last;    // last true relative residual (selected norm)
     double sums[4];     // true residual: ||r/dV||^2, ||S r||^2, ||rhs/dV||^2, ||S rhs||^2
     double rel_row, rel_scaled, rel_sel;
@@ -57,6 +58,7 @@ struct Scalars {
     int stall;          // true-residual checks without progress
     int restart;        // next p-update starts a new search direction
     int demote;         // a new true residual waits to be demoted
+    int apply;          // a check happened: E += corr_apply x_inner and the demotion are due
 };
 
 enum {

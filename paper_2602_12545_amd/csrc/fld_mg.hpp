@@ -579,7 +579,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
 // ---------------------------------------------------------------------------
 
 // p = z + beta * pscale * p_in (p = z on the first iteration or after a
-// restart), q = M p in flux form, partial p.q per workgroup (k_reduce_pq).
+// restart), q = M p in flux form, partial p.q per workgroup (summed by
+// k_update).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
                                               T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
@@ -590,6 +591,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     __shared__ T sp[N], swe[N], swn[N];
     __shared__ double sh[16];
     const bool first = sc->iter == 0 || sc->restart;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && ltid() == 0) sc->apply = 0;  // read by no other kernel of this slot before
     const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
     const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
     for (int k = t; k < N; k += kThreads) {
@@ -620,12 +622,39 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
 }
 
 // x += alpha p, r -= alpha q, partial r.r per workgroup (k_reduce_rr).
+// alpha = r.z / p.q from the SpMV partials (every workgroup sums them in the
+// same order, so all agree; workgroup 0 records the state), then x += alpha p,
+// r -= alpha q and a partial r.r per workgroup into part_rr (k_reduce_rr).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                const T* __restrict__ q, double* part, Scalars* sc) {
+                                                const T* __restrict__ q, const double* __restrict__ part_pq,
+                                                int npq, double* part_rr, Scalars* sc) {
     if (sc->done) return;
     __shared__ double sh[16];
-    const T a = (T)sc->alpha;
+    __shared__ double s_pq;
+    {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < npq; b += blockDim.x) v += part_pq[b];
+        const double pq = block_sum(v, sh);
+        if (threadIdx.x == 0) s_pq = pq;
+        __syncthreads();
+    }
+    const double pq = s_pq;
+    const bool bad = !(pq > 0.0) || !isfinite(pq);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bad) {
+            sc->status = ST_EBREAKDOWN;
+            sc->done = 1;
+            sc->pending = 1;
+        } else {
+            sc->alpha = sc->rz_old / pq;
+        }
+        sc->pscale = 1.0;
+        sc->restart = 0;
+        sc->demote = 0;
+    }
+    if (bad) return;
+    const T a = (T)(sc->rz_old / pq);
     double acc = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         x[c] += a * p[c];
@@ -634,7 +663,7 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
         acc += (double)rn * (double)rn;
     }
     const double tot = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -653,13 +682,19 @@ __global__ __launch_bounds__(256) void k_correct(int n, double* __restrict__ E, 
     }
 }
 
-// True residual r = rhs - M E in flux form, rhs - m E - sum_f W (E - E_nb), and
-// per-workgroup partial sums of the stop-rule norms (k_reduce_resid).
-__global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __restrict__ E, const double* __restrict__ We,
-                                                 const double* __restrict__ Wn, const double* __restrict__ m,
-                                                 const double* __restrict__ rhs, const double* __restrict__ s,
-                                                 double* __restrict__ r64, double* part, const Scalars* sc, int force) {
+// True residual r = rhs - M E' in flux form, rhs - m E' - sum_f W (E' - E'_nb),
+// of the corrected solution E' = E + corr x_inner (evaluated on the fly, the
+// same arithmetic as the correction itself; k_apply stores it), and
+// per-workgroup partial sums of the stop-rule norms (k_reduce_resid).  The
+// forced check at the start of a solve evaluates E itself.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __restrict__ E, const T* __restrict__ xin,
+                                                 const double* __restrict__ We, const double* __restrict__ Wn,
+                                                 const double* __restrict__ m, const double* __restrict__ rhs,
+                                                 const double* __restrict__ s, double* __restrict__ r64, double* part,
+                                                 const Scalars* sc, int force) {
     if (!force && (sc->done || !sc->pending)) return;
+    const double corr = force ? 0.0 : sc->corr;
     const int nx = g.nx, ny = g.ny;
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
     constexpr int NS = 5;
@@ -670,7 +705,7 @@ __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __rest
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
         const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
         const size_t c = (size_t)j * nx + i;
-        sE[k] = in ? E[c] : 0.0;
+        sE[k] = in ? (force ? E[c] : E[c] + corr * (double)xin[c]) : 0.0;
         sWe[k] = in ? We[c] : 0.0;
         sWn[k] = in ? Wn[c] : 0.0;
     }
@@ -704,16 +739,19 @@ __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __rest
         for (int q = 0; q < NS; ++q) part[(size_t)bid2d() * NS + q] = tot[q];
 }
 
-// r_inner = r / gamma in the inner precision (and x = 0) after a true-residual
-// check that did not stop the solve.
+// After a true-residual check that did not stop the solve: store the
+// corrected solution E += corr_apply x, restart x = 0, and demote the new
+// residual r_inner = r / gamma to the inner precision.  (A check that stops the
+// solve leaves x for the final correction, which applies the same factor.)
 template <typename T>
-__global__ __launch_bounds__(256) void k_demote(int n, const double* __restrict__ r64, T* __restrict__ r,
-                                                T* __restrict__ x, const Scalars* __restrict__ sc) {
-    if (sc->done || !sc->demote) return;
-    const double ig = 1.0 / sc->gamma;
+__global__ __launch_bounds__(256) void k_apply(int n, double* __restrict__ E, const double* __restrict__ r64,
+                                               T* __restrict__ r, T* __restrict__ x, const Scalars* __restrict__ sc) {
+    if (!sc->apply || sc->done) return;
+    const double ig = 1.0 / sc->gamma, g = sc->corr_apply;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        r[c] = (T)(r64[c] * ig);
+        E[c] += g * (double)x[c];
         x[c] = T(0);
+        r[c] = (T)(r64[c] * ig);
     }
 }
 
@@ -728,25 +766,6 @@ __device__ inline double reduce_sum(const double* part, int nb, int stride, int 
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += kRedThreads) v += part[(size_t)b * stride + k];
     return block_sum(v, sh);
-}
-
-// alpha = r.z / p.q
-__global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, int nb, Scalars* sc) {
-    if (sc->done) return;
-    __shared__ double sh[16];
-    const double pq = reduce_sum(part, nb, 1, 0, sh);
-    if (threadIdx.x == 0) {
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            sc->status = ST_EBREAKDOWN;
-            sc->done = 1;
-            sc->pending = 1;
-        } else {
-            sc->alpha = sc->rz_old / pq;
-        }
-        sc->pscale = 1.0;
-        sc->restart = 0;
-        sc->demote = 0;
-    }
 }
 
 // count the iteration; decide whether a reliable update (true FP64 residual)
@@ -793,6 +812,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_resid(const double* part
     for (int q = 0; q < NS; ++q) tot[q] = reduce_sum(part, nb, NS, q, sh);
     if (threadIdx.x != 0) return;
     sc->pending = 0;
+    sc->corr_apply = force ? 0.0 : sc->corr;  // the correction the residual was evaluated with
+    sc->apply = 1;
     for (int q = 0; q < 4; ++q) sc->sums[q] = tot[q];
     const double rrow = tot[2] > 0.0 ? sqrt(tot[0] / tot[2]) : sqrt(tot[0]);
     const double rsc = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
@@ -907,6 +928,8 @@ __global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double in
     sc->stall = 0;
     sc->restart = 0;
     sc->demote = 0;
+    sc->apply = 0;
+    sc->corr_apply = 0.0;
 }
 
 }  // namespace fld

@@ -191,15 +191,20 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
  * The first step runs as fld_step; its CG iteration count k1 fixes a budget
  * S = min(max_inner, even(1.5 k1 + 8)) iterations.  One whole step (assembly,
  * hierarchy, S iteration slots with device-side early exit, gas update, a
- * device-side status record) is then captured once as a hipGraph and launched
- * nsteps-1 times without host synchronisation; the call synchronises once at
- * the end.  Results equal those of nsteps fld_step calls whenever every step
- * converges within S.  A later step that does not converge within S is
- * recorded as ENOCONV and, unlike fld_step, its gas update and the following
- * steps still run.  With profiling on or use_graph = 0 the steps run as
- * fld_step calls and stop at the first failure.  per_step (host, nsteps
- * entries) may be NULL; a graph-launched step's ms is the mean over those
- * launches.  Returns the first non-OK step status. */
+ * device-side status record) is then captured once as a hipGraph and replayed
+ * for the remaining steps in segments of 1, 2, 4, then 8 launches; the host
+ * reads the records once per segment.  If a step used up the budget, the
+ * budget grows by half (up to max_inner), the step is re-captured and the
+ * segment replays from the (E, T) saved at its start, segments restarting at
+ * one step.  Results equal those of nsteps fld_step calls
+ * whenever every step converges within max_inner.  A step that fails for
+ * another reason (stagnation, breakdown) is recorded and, unlike fld_step,
+ * its gas update and the following steps still run.  With profiling on or
+ * use_graph = 0 the steps run as fld_step calls and stop at the first
+ * failure.  Allocates per-step records and one saved copy of E and T for the
+ * call.  per_step (host, nsteps entries) may be NULL; a graph-launched step's
+ * ms is the mean over those launches.  Returns the first non-OK step
+ * status. */
 fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);

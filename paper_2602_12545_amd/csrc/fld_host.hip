@@ -994,51 +994,103 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         }
         return FLD_OK;
     }
-    const int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 3 / 2 + 8) + 1) & ~1);
+    int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 3 / 2 + 8) + 1) & ~1);
     // one captured step: assembly, hierarchy, fixed-budget solve, gas update,
-    // per-step record; launched nsteps-1 times back to back
+    // per-step record; replayed in segments of seg steps (1, doubling after
+    // every clean segment up to kSeg).  After each segment the host reads the
+    // records once; if a step ran out of its iteration budget, the budget grows
+    // by half, the step is re-captured and the segment is replayed from the
+    // saved (E, T) with seg = 1 again.
+    constexpr int kSeg = 8;
+    int seg = 1;
     if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const int n = ctx->nx * ctx->ny;
     fld_solve_info* dinfo = nullptr;
     int* dcount = nullptr;
-    HIPCHK(hipMalloc(&dinfo, sizeof(fld_solve_info) * nsteps));
-    HIPCHK(hipMalloc(&dcount, sizeof(int)));
-    HIPCHK(hipMemset(dcount, 0, sizeof(int)));
-    hipGraph_t g = nullptr;
+    double *Esave = nullptr, *Tsave = nullptr;
     hipGraphExec_t ge = nullptr;
-    hipStream_t cs = ctx->cap_stream;
-    const int n = ctx->nx * ctx->ny;
     fld_status st = FLD_OK;
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    st = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, cs);
-    if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, slots, cs);
-    else enqueue_solve_fixed<double>(ctx, E, slots, cs);
-    k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, cv, dt, T);
-    k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, nsteps, (void*)dinfo, (int)ctx->h64.size());
-    hipError_t e = hipStreamEndCapture(cs, &g);
-    if (st == FLD_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    if (st == FLD_OK && e != hipSuccess) {
-        ctx->err = std::string("multi-step graph: ") + hipGetErrorString(e);
-        st = FLD_EHIP;
+    auto cleanup = [&]() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipFree(dinfo);
+        (void)hipFree(dcount);
+        (void)hipFree(Esave);
+        (void)hipFree(Tsave);
+    };
+    if (hipMalloc(&dinfo, sizeof(fld_solve_info) * nsteps) != hipSuccess || hipMalloc(&dcount, sizeof(int)) != hipSuccess ||
+        hipMalloc(&Esave, sizeof(double) * n) != hipSuccess || hipMalloc(&Tsave, sizeof(double) * n) != hipSuccess) {
+        cleanup();
+        ctx->err = "multi-step buffers";
+        return FLD_ENOMEM;
     }
-    auto t0 = std::chrono::steady_clock::now();
-    for (int k = 1; k < nsteps && st == FLD_OK; ++k)
-        if (hipGraphLaunch(ge, ctx->stream) != hipSuccess) st = FLD_EHIP;
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) st = FLD_EHIP;
-    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    auto capture = [&](int budget) -> fld_status {
+        if (ge) {
+            (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
+        }
+        hipStream_t cs = ctx->cap_stream;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FLD_EHIP;
+        fld_status as = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, cs);
+        if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, budget, cs);
+        else enqueue_solve_fixed<double>(ctx, E, budget, cs);
+        k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, cv, dt, T);
+        k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, nsteps, (void*)dinfo, (int)ctx->h64.size());
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (as == FLD_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (as != FLD_OK) return as;
+        if (e != hipSuccess) {
+            ctx->err = std::string("multi-step graph: ") + hipGetErrorString(e);
+            return FLD_EHIP;
+        }
+        return FLD_OK;
+    };
+    st = capture(slots);
     std::vector<fld_solve_info> h(nsteps);
-    if (st == FLD_OK && hipMemcpy(h.data(), dinfo, sizeof(fld_solve_info) * (nsteps - 1), hipMemcpyDeviceToHost) !=
-                            hipSuccess)
-        st = FLD_EHIP;
-    if (ge) (void)hipGraphExecDestroy(ge);
-    (void)hipFree(dinfo);
-    (void)hipFree(dcount);
+    auto t0 = std::chrono::steady_clock::now();
+    int k = 1;
+    while (st == FLD_OK && k < nsteps) {
+        const int m = std::min(seg, nsteps - k);
+        const int c0 = k - 1;
+        if (hipMemcpy(dcount, &c0, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpyAsync(Esave, E, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(Tsave, T, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+            st = FLD_EHIP;
+            break;
+        }
+        for (int q = 0; q < m && st == FLD_OK; ++q)
+            if (hipGraphLaunch(ge, ctx->stream) != hipSuccess) st = FLD_EHIP;
+        if (st != FLD_OK || hipStreamSynchronize(ctx->stream) != hipSuccess ||
+            hipMemcpy(h.data() + c0, dinfo + c0, sizeof(fld_solve_info) * m, hipMemcpyDeviceToHost) != hipSuccess) {
+            st = FLD_EHIP;
+            break;
+        }
+        bool budget_hit = false;
+        for (int q = 0; q < m; ++q)
+            if (h[c0 + q].status == FLD_ENOCONV && h[c0 + q].inner_iters >= slots) budget_hit = true;
+        if (budget_hit && slots < ctx->opt.max_inner) {
+            slots = std::min(ctx->opt.max_inner, ((slots * 3 / 2) + 1) & ~1);
+            seg = 1;
+            if (hipMemcpyAsync(E, Esave, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+                hipMemcpyAsync(T, Tsave, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+                st = FLD_EHIP;
+                break;
+            }
+            st = capture(slots);
+            continue;  // replay the segment with the larger budget
+        }
+        k += m;
+        seg = std::min(kSeg, 2 * seg);
+    }
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    cleanup();
     if (st != FLD_OK) return st;
     fld_status firstbad = s1;
-    for (int k = 1; k < nsteps; ++k) {
-        h[k - 1].ms = ms / (nsteps - 1);
-        if (per_step) per_step[k] = h[k - 1];
-        if (h[k - 1].status != FLD_OK && firstbad == FLD_OK) firstbad = (fld_status)h[k - 1].status;
+    for (int q = 1; q < nsteps; ++q) {
+        h[q - 1].ms = ms / (nsteps - 1);
+        if (per_step) per_step[q] = h[q - 1];
+        if (h[q - 1].status != FLD_OK && firstbad == FLD_OK) firstbad = (fld_status)h[q - 1].status;
     }
     ctx->assembled = true;
     return firstbad;

@@ -89,7 +89,7 @@ __device__ inline int wave_line_lanes(int na) {
 // shuffles; back-substitution finishes.  Wave `wave` of `nwaves` takes lines
 // wave * 64/K + ..., the next pass nwaves * 64/K lines further.  Needs na <=
 // 64 LM.  The caller separates half-sweeps with a barrier.
-template <typename T, int LM, bool ZERO>
+template <typename T, int LM, bool ZERO, bool BF = true>
 __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long long sl, const T* __restrict__ m,
                                 const T* __restrict__ Wa, const T* __restrict__ Wc, const T* __restrict__ b,
                                 T* __restrict__ x, int wave, int nwaves) {
@@ -127,7 +127,7 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
             else fill<T, LM>(vxn, T(0));
             if (!ZERO && line > 0) load_vec<T, LM>(x + c0 - sl, vxs);
             else fill<T, LM>(vxs, T(0));
-        } else {
+        } else if (!BF) {
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
@@ -140,6 +140,32 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
                 vb[q] = ok ? b[c] : T(0);
                 vxn[q] = (!ZERO && ok && line + 1 < nlines) ? x[c + sl] : T(0);
                 vxs[q] = (!ZERO && ok && line > 0) ? x[c - sl] : T(0);
+            }
+        } else {
+            // branch-free (BF): every load reads a valid cell (indices clamped
+            // into the line and the grid) and the value is masked afterwards,
+            // so the loads issue back to back instead of one guarded block
+            // each (much faster from LDS; measured slower for binary32 rows in
+            // global memory, where guarded loads skip traffic)
+            const long long dn = (line + 1 < nlines) ? sl : 0, ds = (line > 0) ? -sl : 0;
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                const int g = s0 + q;
+                const bool ok = active && q < L && g < na;
+                const long long c = lb + (long long)min(g, na - 1) * sa;
+                const T m_ = m[c], wa_ = Wa[c], wc_ = Wc[c], ws_ = Wc[c + ds], b_ = b[c];
+                vm[q] = ok ? m_ : T(1);
+                va[q] = ok ? wa_ : T(0);
+                vcn[q] = ok ? wc_ : T(0);
+                vcs[q] = (ok && ds != 0) ? ws_ : T(0);
+                vb[q] = ok ? b_ : T(0);
+                if (!ZERO) {
+                    const T xn_ = x[c + dn], xs_ = x[c + ds];
+                    vxn[q] = (ok && dn != 0) ? xn_ : T(0);
+                    vxs[q] = (ok && ds != 0) ? xs_ : T(0);
+                } else {
+                    vxn[q] = vxs[q] = T(0);
+                }
             }
         }
         T vd[LM], vr[LM];

@@ -994,13 +994,23 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
         const SubLevel<T>& L = S.lv[l];
         const int n = L.nx * L.ny, z = L.size;
         T* m = pool + L.off;
-        for (int c = t; c < n; c += kSubThreads<T>) {
-            const int i = c % L.nx, j = c / L.nx, cl = j * L.pitch + i;
+        // (i, j) of cell c advanced incrementally: no division per cell
+        constexpr int NT = kSubThreads<T>;
+        int i = t % L.nx, j = t / L.nx;
+        const int di = NT % L.nx, dj = NT / L.nx;
+        for (int c = t; c < n; c += NT) {
+            const int cl = j * L.pitch + i;
             m[cl] = L.m[c];
             m[z + cl] = L.We[c];
             m[2 * z + cl] = L.Wn[c];
             // input in the level's primary layout
             if (l == 0) m[3 * z + cl] = bin[L.tr ? i * L.ny + j : c];
+            i += di;
+            j += dj;
+            if (i >= L.nx) {
+                i -= L.nx;
+                ++j;
+            }
         }
     }
     __syncthreads();
@@ -1046,22 +1056,35 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
         }
         __syncthreads();
     }
-    // coarsest: dense inverse in the primary layout's cell order
+    // coarsest: dense inverse in the primary layout's cell order; 16 lanes per
+    // row of the inverse, each summing 4 columns (coalesced), then a shuffle
+    // reduction within the 16 lanes
     {
         const SubLevel<T>& L = S.lv[S.nlev - 1];
         const int n = L.nx * L.ny;
         T* b = pool + L.off + 3 * L.size;
         T* x = b + L.size;
-        for (int c = t; c < n; c += kSubThreads<T>) {
-            const int i = c % L.nx, j = c / L.nx;
-            const int row = L.tr ? i * L.ny + j : c;
+        constexpr int G = 16;
+        for (int r0 = 0; r0 < n; r0 += kSubThreads<T> / G) {
+            const int row = r0 + t / G, lane = t % G;
             T acc = T(0);
-            for (int k = 0; k < n; ++k) {
-                const int ik = k % L.nx, jk = k / L.nx;
-                const int col = L.tr ? ik * L.ny + jk : k;
-                acc += S.Ainv[row * n + col] * b[jk * L.pitch + ik];
+            if (row < n) {
+                const T* arow = S.Ainv + (size_t)row * n;
+                for (int col = lane * 4; col < n; col += G * 4)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int cc = col + q;
+                        if (cc < n) {
+                            const int ik = L.tr ? cc / L.ny : cc % L.nx, jk = L.tr ? cc % L.ny : cc / L.nx;
+                            acc += arow[cc] * b[jk * L.pitch + ik];
+                        }
+                    }
             }
-            x[j * L.pitch + i] = acc;
+            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+            if (row < n && lane == 0) {
+                const int i = L.tr ? row / L.ny : row % L.nx, j = L.tr ? row % L.ny : row / L.nx;
+                x[j * L.pitch + i] = acc;
+            }
         }
         __syncthreads();
     }
@@ -1072,9 +1095,17 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
         const int n = L.nx * L.ny;
         T* x = pool + L.off + 4 * L.size;
         const T* xc = pool + C.off + 4 * C.size;
-        for (int c = t; c < n; c += kSubThreads<T>) {
-            const int i = c % L.nx, j = c / L.nx;
+        constexpr int NT = kSubThreads<T>;
+        int i = t % L.nx, j = t / L.nx;
+        const int di = NT % L.nx, dj = NT / L.nx;
+        for (int c = t; c < n; c += NT) {
             x[j * L.pitch + i] += xc[(j >> 1) * C.pitch + (i >> 1)];
+            i += di;
+            j += dj;
+            if (i >= L.nx) {
+                i -= L.nx;
+                ++j;
+            }
         }
         __syncthreads();
         const bool first_x = !L.tr;

@@ -400,7 +400,12 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     const int ntiles = (int)(tg.x * tg.y), nb1 = grid1d(n);
     k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part,
                                       c->sc);
-    k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, ntiles, c->part2, c->sc);
+    // alpha: summed inside k_update from the SpMV partials when they are few,
+    // by one reduction workgroup otherwise
+    const bool fold = ntiles <= 1024;
+    if (!fold) k_reduce_pq<<<1, kRedThreads, 0, st>>>(c->part, ntiles, c->sc);
+    k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, fold ? ntiles : 0, c->part2,
+                                     c->sc);
     k_reduce_rr<<<1, kRedThreads, 0, st>>>(c->part2, nb1, c->sc);
     enqueue_check<T>(c, in, E, 0, st);
     enqueue_vcycle<T>(c, in, st);

@@ -621,10 +621,12 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     if (t == 0) part[bid2d()] = tot;
 }
 
-// x += alpha p, r -= alpha q, partial r.r per workgroup (k_reduce_rr).
 // alpha = r.z / p.q from the SpMV partials (every workgroup sums them in the
-// same order, so all agree; workgroup 0 records the state), then x += alpha p,
-// r -= alpha q and a partial r.r per workgroup into part_rr (k_reduce_rr).
+// same order, so all agree; workgroup 0 records the state) -- or, with
+// npq = 0, alpha as k_reduce_pq left it (grids with many partials, where
+// every workgroup re-reading them costs more than a launch) -- then
+// x += alpha p, r -= alpha q and a partial r.r per workgroup into part_rr
+// (k_reduce_rr).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                 const T* __restrict__ q, const double* __restrict__ part_pq,
@@ -632,29 +634,34 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
     if (sc->done) return;
     __shared__ double sh[16];
     __shared__ double s_pq;
-    {
+    if (npq > 0) {
         double v = 0.0;
         for (int b = threadIdx.x; b < npq; b += blockDim.x) v += part_pq[b];
         const double pq = block_sum(v, sh);
         if (threadIdx.x == 0) s_pq = pq;
         __syncthreads();
     }
-    const double pq = s_pq;
-    const bool bad = !(pq > 0.0) || !isfinite(pq);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (bad) {
-            sc->status = ST_EBREAKDOWN;
-            sc->done = 1;
-            sc->pending = 1;
-        } else {
-            sc->alpha = sc->rz_old / pq;
+    T a;
+    if (npq > 0) {
+        const double pq = s_pq;
+        const bool bad = !(pq > 0.0) || !isfinite(pq);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (bad) {
+                sc->status = ST_EBREAKDOWN;
+                sc->done = 1;
+                sc->pending = 1;
+            } else {
+                sc->alpha = sc->rz_old / pq;
+            }
+            sc->pscale = 1.0;
+            sc->restart = 0;
+            sc->demote = 0;
         }
-        sc->pscale = 1.0;
-        sc->restart = 0;
-        sc->demote = 0;
+        if (bad) return;
+        a = (T)(sc->rz_old / pq);
+    } else {
+        a = (T)sc->alpha;
     }
-    if (bad) return;
-    const T a = (T)(sc->rz_old / pq);
     double acc = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         x[c] += a * p[c];
@@ -766,6 +773,25 @@ __device__ inline double reduce_sum(const double* part, int nb, int stride, int 
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += kRedThreads) v += part[(size_t)b * stride + k];
     return block_sum(v, sh);
+}
+
+// alpha = r.z / p.q (k_update with npq = 0 reads it from the state instead)
+__global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, int nb, Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const double pq = reduce_sum(part, nb, 1, 0, sh);
+    if (threadIdx.x == 0) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            sc->status = ST_EBREAKDOWN;
+            sc->done = 1;
+            sc->pending = 1;
+        } else {
+            sc->alpha = sc->rz_old / pq;
+        }
+        sc->pscale = 1.0;
+        sc->restart = 0;
+        sc->demote = 0;
+    }
 }
 
 // count the iteration; decide whether a reliable update (true FP64 residual)

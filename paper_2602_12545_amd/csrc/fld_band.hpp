@@ -59,16 +59,64 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     const int lane = t & 63;
     const bool wave_pcr = K <= 64;
 
-    // Solve `count` rows start, start + 2, ... ; PH = 1: first parity
+    // Coefficients, right-hand side and (first parity) neighbour-row x of one
+    // chunk of one row, loaded ahead of the solve, for rows that split into
+    // whole aligned vector chunks (every lane's chunk is LM cells at a
+    // 16-byte boundary).  Every address is valid (rows off the grid clamped
+    // to the row itself); the solve masks what does not exist, so no load
+    // waits for another.
+    struct Coef {
+        T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM], xn[LM], xs[LM];
+        T wwest;
+    };
+    auto load_coef_vec = [&](int row, Coef& C, bool with_x) {
+        const size_t rb = (size_t)row * nx;
+        const size_t rs = row > 0 ? rb - nx : rb, rn = row + 1 < ny ? rb + nx : rb;
+        C.wwest = We[rb + (s0 > 0 ? s0 - 1 : 0)];
+        load_vec<T, LM>(m + rb + s0, C.vm);
+        load_vec<T, LM>(We + rb + s0, C.vwe);
+        load_vec<T, LM>(Wn + rb + s0, C.vwn);
+        load_vec<T, LM>(b + rb + s0, C.vb);
+        load_vec<T, LM>(Wn + rs + s0, C.vws);
+        if (with_x && MODE != LINE_ZERO) {
+            load_vec<T, LM>(xin + rn + s0, C.xn);
+            load_vec<T, LM>(xin + rs + s0, C.xs);
+            if (MODE == LINE_PROLONG) {
+                // coarse correction of cells s0 .. s0 + LM - 1: LM / 2 values
+                T en[LM / 2], es[LM / 2];
+                const int ic = s0 >> 1;
+                load_vec<T, LM / 2>(ec + (size_t)((row + 1 < ny ? row + 1 : row) >> 1) * nxc + ic, en);
+                load_vec<T, LM / 2>(ec + (size_t)((row > 0 ? row - 1 : row) >> 1) * nxc + ic, es);
+#pragma unroll
+                for (int q = 0; q < LM; ++q) {
+                    C.xn[q] += en[q >> 1];
+                    C.xs[q] += es[q >> 1];
+                }
+            }
+        }
+    };
+
+    // Solve one row (or none, !active) of a pass; PH = 1: first parity
     // (neighbours from xin), PH = 2: second parity (neighbours from LDS).
-    auto solve_rows = [&](int start, int count, int PH) {
-        for (int q0 = 0; q0 < count; q0 += lpp) {
-            const int ql = q0 + t / K;
-            const bool active = ql < count;
-            const int row = start + 2 * (active ? ql : 0);
-            const size_t rb = (size_t)row * nx;
-            T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM], vxn[LM], vxs[LM];
-            const T wwest = (active && s0 > 0 && s0 - 1 < nx) ? We[rb + s0 - 1] : T(0);
+    // The coefficients come from `pre` (PRE) or are loaded here.  Every
+    // thread of the workgroup calls it (the LDS reduction has barriers).
+    auto solve_row = [&](int row, bool active, const Coef* pre, auto pre_tag, int PH) {
+        constexpr bool PRE = decltype(pre_tag)::value;
+        const size_t rb = (size_t)row * nx;
+        T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM];
+        T wwest;
+        if constexpr (PRE) {
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                vm[q] = pre->vm[q];
+                vwe[q] = pre->vwe[q];
+                vwn[q] = pre->vwn[q];
+                vws[q] = row > 0 ? pre->vws[q] : T(0);
+                vb[q] = pre->vb[q];
+            }
+            wwest = s0 > 0 ? pre->wwest : T(0);
+        } else {
+            wwest = (active && s0 > 0 && s0 - 1 < nx) ? We[rb + s0 - 1] : T(0);
             constexpr int VW = 16 / sizeof(T);
             const bool vec = active && L == LM && s0 + LM <= nx && ((rb + s0) % VW) == 0 && (nx % VW) == 0;
             if (vec) {
@@ -91,169 +139,184 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     vb[q] = ok ? b[c] : T(0);
                 }
             }
-            // neighbour rows
+        }
+        T vxn[LM], vxs[LM];
+        // neighbour rows
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
+            const int g = s0 + q;
+            const bool ok = active && q < L && g < nx;
+            T xn = T(0), xs = T(0);
+            if (ok) {
+                if (PH == 2) {
+                    if (row + 1 < ny) xn = rows[(size_t)(row + 1 - (r0 - 1)) * nx + g];
+                    if (row > 0) xs = rows[(size_t)(row - 1 - (r0 - 1)) * nx + g];
+                } else if (PRE) {
+                    if (MODE != LINE_ZERO) {
+                        if (row + 1 < ny) xn = pre->xn[q];
+                        if (row > 0) xs = pre->xs[q];
+                    }
+                } else if (MODE != LINE_ZERO) {
+                    if (row + 1 < ny) {
+                        xn = xin[rb + nx + g];
+                        if (MODE == LINE_PROLONG) xn += ec[(size_t)((row + 1) >> 1) * nxc + (g >> 1)];
+                    }
+                    if (row > 0) {
+                        xs = xin[rb - nx + g];
+                        if (MODE == LINE_PROLONG) xs += ec[(size_t)((row - 1) >> 1) * nxc + (g >> 1)];
+                    }
+                }
+            }
+            vxn[q] = xn;
+            vxs[q] = xs;
+        }
+        if (WRITE_BT && active && row >= r0 && row < rend) {
+#pragma unroll
+            for (int q = 0; q < LM; ++q)
+                if (q < L && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+        }
+        // diagonal and right-hand side of every chunk row (the loaded
+        // arrays die here, which keeps register pressure low)
+        T vd[LM], vr[LM];
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
+            const T ww = (q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0];
+            vd[q] = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
+            vr[q] = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
+        }
+        auto coef = [&](int q, T& a, T& d, T& c, T& r) {
+            a = -((q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0]);
+            d = vd[q];
+            c = -vwe[q];
+            r = vr[q];
+        };
+        T cp[LM], gy[LM], gu[LM], gv[LM];
+#pragma unroll
+        for (int q = 0; q < LM - 1; ++q) {
+            if (q < L - 1) {
+                T a, d, c, r;
+                coef(q, a, d, c, r);
+                const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
+                const T inv = line_rcp(den);
+                cp[q] = c * inv;
+                gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
+                gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
+                const T rv = (q == L - 2) ? -c : T(0);
+                gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
+            }
+        }
+#pragma unroll
+        for (int q = LM - 3; q >= 0; --q) {
+            if (q < L - 2) {
+                gy[q] -= cp[q] * gy[q + 1];
+                gu[q] -= cp[q] * gu[q + 1];
+                gv[q] -= cp[q] * gv[q + 1];
+            }
+        }
+        T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
+#pragma unroll
+        for (int q = 0; q < LM; ++q)
+            if (q == L - 1) coef(q, aE, dE, cE, rE);
+        T yl = T(0), ul = T(0), vl = T(0);
+#pragma unroll
+        for (int q = 0; q < LM - 1; ++q)
+            if (q == L - 2) {
+                yl = gy[q];
+                ul = gu[q];
+                vl = gv[q];
+            }
+        const bool has_next = k + 1 < K;
+        T X, Xp;
+        if (LM > kLineMaxL || wave_pcr) {
+            T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
+            if (!has_next) yn = un = vn = T(0);
+            T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, Rr = rE - aE * yl - cE * yn;
+            for (int st = 1; st < K; st <<= 1) {
+                const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
+                const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(Rr, lane - st, 64);
+                const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
+                const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(Rr, lane + st, 64);
+                T nA = T(0), nB = B, nC = T(0), nR = Rr;
+                if (k - st >= 0) {
+                    const T al = -A * line_rcp(Bm);
+                    nA = al * Am;
+                    nB += al * Cm;
+                    nR += al * Rm;
+                }
+                if (k + st < K) {
+                    const T ga = -C * line_rcp(Bp);
+                    nC = ga * Cp;
+                    nB += ga * Ap;
+                    nR += ga * Rp;
+                }
+                A = nA;
+                B = nB;
+                C = nC;
+                Rr = nR;
+            }
+            X = Rr * line_rcp(B);
+            Xp = __shfl(X, lane - 1, 64);
+            if (k == 0) Xp = T(0);
+        } else if constexpr (LM == kLineMaxL) {
+            sy0[t] = gy[0];
+            su0[t] = gu[0];
+            sv0[t] = gv[0];
+            __syncthreads();
+            const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0);
+            const T vn = has_next ? sv0[t + 1] : T(0);
+            sA[t] = aE * ul;
+            sB[t] = dE + aE * vl + cE * un;
+            sC[t] = cE * vn;
+            sR[t] = rE - aE * yl - cE * yn;
+            __syncthreads();
+            for (int st = 1; st < K; st <<= 1) {
+                const T a = sA[t], bq = sB[t], c = sC[t], r = sR[t];
+                T na = T(0), nb = bq, nc = T(0), nr = r;
+                if (k - st >= 0) {
+                    const T al = -a * line_rcp(sB[t - st]);
+                    na = al * sA[t - st];
+                    nb += al * sC[t - st];
+                    nr += al * sR[t - st];
+                }
+                if (k + st < K) {
+                    const T ga = -c * line_rcp(sB[t + st]);
+                    nc = ga * sC[t + st];
+                    nb += ga * sA[t + st];
+                    nr += ga * sR[t + st];
+                }
+                __syncthreads();
+                sA[t] = na;
+                sB[t] = nb;
+                sC[t] = nc;
+                sR[t] = nr;
+                __syncthreads();
+            }
+            X = sR[t] * line_rcp(sB[t]);
+            __syncthreads();
+            sR[t] = X;
+            __syncthreads();
+            Xp = k > 0 ? sR[t - 1] : T(0);
+        }
+        if (active) {
+            T* dst = rows + (size_t)(row - (r0 - 1)) * nx;
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                const bool ok = active && q < L && g < nx;
-                T xn = T(0), xs = T(0);
-                if (ok) {
-                    if (PH == 2) {
-                        if (row + 1 < ny) xn = rows[(size_t)(row + 1 - (r0 - 1)) * nx + g];
-                        if (row > 0) xs = rows[(size_t)(row - 1 - (r0 - 1)) * nx + g];
-                    } else if (MODE != LINE_ZERO) {
-                        if (row + 1 < ny) {
-                            xn = xin[rb + nx + g];
-                            if (MODE == LINE_PROLONG) xn += ec[(size_t)((row + 1) >> 1) * nxc + (g >> 1)];
-                        }
-                        if (row > 0) {
-                            xs = xin[rb - nx + g];
-                            if (MODE == LINE_PROLONG) xs += ec[(size_t)((row - 1) >> 1) * nxc + (g >> 1)];
-                        }
-                    }
-                }
-                vxn[q] = xn;
-                vxs[q] = xs;
+                if (q < L && g < nx)
+                    dst[g] = (q == L - 1) ? X
+                                          : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                gv[q < LM - 1 ? q : 0] * X;
             }
-            if (WRITE_BT && active && row >= r0 && row < rend) {
-#pragma unroll
-                for (int q = 0; q < LM; ++q)
-                    if (q < L && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
-            }
-            // diagonal and right-hand side of every chunk row (the loaded
-            // arrays die here, which keeps register pressure low)
-            T vd[LM], vr[LM];
-#pragma unroll
-            for (int q = 0; q < LM; ++q) {
-                const T ww = (q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0];
-                vd[q] = vm[q] + ((ww + vwe[q]) + (vws[q] + vwn[q]));
-                vr[q] = vb[q] + vwn[q] * vxn[q] + vws[q] * vxs[q];
-            }
-            auto coef = [&](int q, T& a, T& d, T& c, T& r) {
-                a = -((q == 0) ? wwest : vwe[q > 0 ? q - 1 : 0]);
-                d = vd[q];
-                c = -vwe[q];
-                r = vr[q];
-            };
-            T cp[LM], gy[LM], gu[LM], gv[LM];
-#pragma unroll
-            for (int q = 0; q < LM - 1; ++q) {
-                if (q < L - 1) {
-                    T a, d, c, r;
-                    coef(q, a, d, c, r);
-                    const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
-                    const T inv = line_rcp(den);
-                    cp[q] = c * inv;
-                    gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
-                    gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
-                    const T rv = (q == L - 2) ? -c : T(0);
-                    gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
-                }
-            }
-#pragma unroll
-            for (int q = LM - 3; q >= 0; --q) {
-                if (q < L - 2) {
-                    gy[q] -= cp[q] * gy[q + 1];
-                    gu[q] -= cp[q] * gu[q + 1];
-                    gv[q] -= cp[q] * gv[q + 1];
-                }
-            }
-            T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
-#pragma unroll
-            for (int q = 0; q < LM; ++q)
-                if (q == L - 1) coef(q, aE, dE, cE, rE);
-            T yl = T(0), ul = T(0), vl = T(0);
-#pragma unroll
-            for (int q = 0; q < LM - 1; ++q)
-                if (q == L - 2) {
-                    yl = gy[q];
-                    ul = gu[q];
-                    vl = gv[q];
-                }
-            const bool has_next = k + 1 < K;
-            T X, Xp;
-            if (LM > kLineMaxL || wave_pcr) {
-                T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
-                if (!has_next) yn = un = vn = T(0);
-                T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, Rr = rE - aE * yl - cE * yn;
-                for (int st = 1; st < K; st <<= 1) {
-                    const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
-                    const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(Rr, lane - st, 64);
-                    const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
-                    const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(Rr, lane + st, 64);
-                    T nA = T(0), nB = B, nC = T(0), nR = Rr;
-                    if (k - st >= 0) {
-                        const T al = -A * line_rcp(Bm);
-                        nA = al * Am;
-                        nB += al * Cm;
-                        nR += al * Rm;
-                    }
-                    if (k + st < K) {
-                        const T ga = -C * line_rcp(Bp);
-                        nC = ga * Cp;
-                        nB += ga * Ap;
-                        nR += ga * Rp;
-                    }
-                    A = nA;
-                    B = nB;
-                    C = nC;
-                    Rr = nR;
-                }
-                X = Rr * line_rcp(B);
-                Xp = __shfl(X, lane - 1, 64);
-                if (k == 0) Xp = T(0);
-            } else if constexpr (LM == kLineMaxL) {
-                sy0[t] = gy[0];
-                su0[t] = gu[0];
-                sv0[t] = gv[0];
-                __syncthreads();
-                const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0);
-                const T vn = has_next ? sv0[t + 1] : T(0);
-                sA[t] = aE * ul;
-                sB[t] = dE + aE * vl + cE * un;
-                sC[t] = cE * vn;
-                sR[t] = rE - aE * yl - cE * yn;
-                __syncthreads();
-                for (int st = 1; st < K; st <<= 1) {
-                    const T a = sA[t], bq = sB[t], c = sC[t], r = sR[t];
-                    T na = T(0), nb = bq, nc = T(0), nr = r;
-                    if (k - st >= 0) {
-                        const T al = -a * line_rcp(sB[t - st]);
-                        na = al * sA[t - st];
-                        nb += al * sC[t - st];
-                        nr += al * sR[t - st];
-                    }
-                    if (k + st < K) {
-                        const T ga = -c * line_rcp(sB[t + st]);
-                        nc = ga * sC[t + st];
-                        nb += ga * sA[t + st];
-                        nr += ga * sR[t + st];
-                    }
-                    __syncthreads();
-                    sA[t] = na;
-                    sB[t] = nb;
-                    sC[t] = nc;
-                    sR[t] = nr;
-                    __syncthreads();
-                }
-                X = sR[t] * line_rcp(sB[t]);
-                __syncthreads();
-                sR[t] = X;
-                __syncthreads();
-                Xp = k > 0 ? sR[t - 1] : T(0);
-            }
-            if (active) {
-                T* dst = rows + (size_t)(row - (r0 - 1)) * nx;
-#pragma unroll
-                for (int q = 0; q < LM; ++q) {
-                    const int g = s0 + q;
-                    if (q < L && g < nx)
-                        dst[g] = (q == L - 1) ? X
-                                              : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
-                                                    gv[q < LM - 1 ? q : 0] * X;
-                }
-            }
-            if (LM == kLineMaxL && !wave_pcr) __syncthreads();  // the LDS reduction arrays are reused next pass
+        }
+        if (LM == kLineMaxL && !wave_pcr) __syncthreads();  // the LDS reduction arrays are reused next pass
+    };
+    // `count` rows start, start + 2, ..., lpp rows per pass
+    auto solve_rows = [&](int start, int count, int PH) {
+        for (int q0 = 0; q0 < count; q0 += lpp) {
+            const int ql = q0 + t / K;
+            const bool active = ql < count;
+            const int row = start + 2 * (active ? ql : 0);
+            solve_row(row, active, nullptr, std::false_type{}, PH);
         }
     };
 
@@ -265,9 +328,33 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     const int n1 = s1 <= e1 ? (e1 - s1) / 2 + 1 : 0;
     const int s2 = ((r0 & 1) == P2) ? r0 : r0 + 1;
     const int n2 = s2 < rend ? (rend - 1 - s2) / 2 + 1 : 0;
-    solve_rows(s1, n1, 1);
-    __syncthreads();
-    solve_rows(s2, n2, 2);
+    constexpr int VW = 16 / sizeof(T);
+    const bool whole_vec =
+        L == LM && K * LM == nx && (nx % VW) == 0 &&
+        ((reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(We) | reinterpret_cast<uintptr_t>(Wn) |
+          reinterpret_cast<uintptr_t>(b) | (MODE != LINE_ZERO ? reinterpret_cast<uintptr_t>(xin) : 0)) & 15) == 0 &&
+        (MODE != LINE_PROLONG || ((nxc % VW) == 0 && (reinterpret_cast<uintptr_t>(ec) & 15) == 0 && LM / 2 >= VW));
+    if (sizeof(T) == 4 && whole_vec && n1 <= lpp && n2 <= lpp) {
+        // one pass per parity: the second pass's coefficients are loaded
+        // before the first pass is solved, so their latency overlaps it
+        // (binary32 only: binary64 lacks the registers).  Idle row slots
+        // solve a copy of the first row of their pass and store nothing.
+        const int ql = t / K;
+        const bool a1 = ql < n1, a2 = ql < n2;
+        // (a parity with no row here loads band row r0, which exists)
+        const int row1 = n1 > 0 ? s1 + 2 * (a1 ? ql : 0) : r0;
+        const int row2 = n2 > 0 ? s2 + 2 * (a2 ? ql : 0) : r0;
+        Coef C1, C2;
+        load_coef_vec(row1, C1, true);
+        load_coef_vec(row2, C2, false);
+        solve_row(row1, a1, &C1, std::true_type{}, 1);
+        __syncthreads();
+        solve_row(row2, a2, &C2, std::true_type{}, 2);
+    } else {
+        solve_rows(s1, n1, 1);
+        __syncthreads();
+        solve_rows(s2, n2, 2);
+    }
     __syncthreads();
     // band rows out
     double acc = 0.0;

@@ -172,3 +172,22 @@ def test_band_fused_sweeps_wide_rows(lib, shape):
     assert info["status"] == 0
     r = O.step_problem(prob)
     assert rel_l2(E, r.E) < 1e-10 and rel_l2(T, r.T) < 1e-10
+
+
+@pytest.mark.parametrize("shape", [(1024, 1025), (512, 96), (256, 255), (1030, 66)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_band_fused_sweeps_fixed_iterations(lib, shape, prec):
+    """After a fixed number of CG iterations the corrections of LINE and
+    LINE_SPLIT agree to rounding: the fused launch applies the same
+    preconditioner (a different smoother would move the iterates far more
+    than rounding does).  Shapes: whole aligned vector rows with a one-row
+    last band, short rows, odd row counts, ragged rows."""
+    nx, ny = shape
+    prob = W.make_c2(nx=nx, ny=ny)
+    opt = dict(precision=prec, max_inner=3, norm=1)
+    E1, _, i1 = gpu_step(lib, torch, prob, smoother=0, **opt)
+    E2, _, i2 = gpu_step(lib, torch, prob, smoother=2, **opt)
+    assert i1["inner_iters"] == i2["inner_iters"] == 3
+    E0 = np.asarray(prob.E)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert rel_l2(E1 - E0, E2 - E0) < tol

@@ -125,7 +125,7 @@ typedef struct {
     int32_t max_inner;      /* CG iterations per solve, all checks included (default 2000)   */
     double  inner_rtol;     /* FP32 mode only: stop once the inner (FP32) residual has       */
                             /* dropped by this factor (default 1e-5)                         */
-    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (1..64, def 64)  */
+    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (1..256, def 64) */
     int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
     int32_t smoother;       /* fld_smoother (default LINE); LINE* need nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
@@ -258,7 +258,7 @@ typedef struct fld_batch fld_batch;
 /* Creates a batch.  nx, ny, dx, dy: host arrays of nblocks entries, read
  * during the call.  bc: host array of 4 sides applied to every block (NULL =
  * DIRICHLET_GHOST on all sides; AXIS is not allowed).  opt may be NULL; the
- * batch needs smoother = LINE and mg_coarse_max <= 64; chunk is unused;
+ * batch needs smoother = LINE; mg_coarse_max above 64 acts as 64; chunk is unused;
  * use_graph selects graph capture in fld_batch_steps.  stream: hipStream_t.
  * Returns EINVAL (sizes, spacing, options), ENOMEM, EHIP. */
 fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx, const int32_t* ny,
@@ -317,7 +317,7 @@ typedef struct {
 } fld_tune_entry;
 
 /* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
- * mg_coarse_max in {64, 16} and chunk in {8, 16, 4}; precision, limiter,
+ * mg_coarse_max in {64, 256, 16} and chunk in {8, 16, 4}; precision, limiter,
  * norm and tolerances are those of base (NULL = defaults).  Each candidate
  * gets its own context and runs reps + 1 steps (the first untimed) from the
  * given E, T (device arrays, not modified; the trials run on scratch copies).

@@ -149,8 +149,10 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     const fld_options& o = b->opt;
     if (o.precision < 0 || o.precision > 2 || o.limiter < 0 || o.limiter > 2 || o.norm < 0 || o.norm > 1 ||
         !(o.rel_tol > 0.0) || o.max_inner < 1 || !(o.inner_rtol > 0.0) || o.mg_coarse_max < 1 ||
-        o.mg_coarse_max > kBCoarse || o.mg_coarse_op < 0 || o.mg_coarse_op > 1 || o.smoother != FLD_SMOOTH_LINE)
-        return fail(FLD_EINVAL, "options (the batched solver uses line smoothing, mg_coarse_max <= 64)");
+        o.mg_coarse_max > 256 || o.mg_coarse_op < 0 || o.mg_coarse_op > 1 || o.smoother != FLD_SMOOTH_LINE)
+        return fail(FLD_EINVAL, "options (the batched solver uses line smoothing, mg_coarse_max in [1, 256])");
+    // a block's coarsest level is solved in the workgroup: at most kBCoarse cells
+    b->opt.mg_coarse_max = std::min(b->opt.mg_coarse_max, kBCoarse);
     b->stream = static_cast<hipStream_t>(stream);
     b->nb = nblocks;
     for (int sd = 0; sd < 4; ++sd) {

@@ -71,6 +71,7 @@ template <typename T>
 struct Inner {
     std::vector<LevelT<T>> lv;
     T* Ainv = nullptr;
+    double* Ywork = nullptr;  // coarse inverse set-up: forward solutions
     T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     int sub_first = -1;                   // first level of the one-workgroup coarse sub-cycle (-1: none)
     SubCycle<T> sub{};
@@ -160,7 +161,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (!(o->rel_tol > 0.0) || !(o->rel_tol < 1.0)) { err = "rel_tol must be in (0, 1)"; return FLD_EINVAL; }
     if (o->max_outer < 1 || o->max_inner < 1) { err = "max_outer / max_inner must be >= 1"; return FLD_EINVAL; }
     if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) { err = "inner_rtol must be in (0, 1)"; return FLD_EINVAL; }
-    if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 64]"; return FLD_EINVAL; }
+    if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 256]"; return FLD_EINVAL; }
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
     if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
@@ -302,7 +303,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
     } else {
         LevelT<T>& cl = in.lv[L - 1];
-        k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+        k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
     }
     for (int l = Ld - 1; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
@@ -350,7 +351,7 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                                                                   b.ny, c->sc);
     }
     LevelT<T>& cl = in.lv[L - 1];
-    k_coarse_solve<T, false><<<1, kCoarseMax, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+    k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
     for (int l = L - 2; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
@@ -369,7 +370,7 @@ template <typename T>
 void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     if (in.lv.size() == 1) {
         LevelT<T>& l0 = in.lv[0];
-        k_coarse_solve<T, true><<<1, kCoarseMax, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->sc);
+        k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->sc);
         return;
     }
     if (is_line(c->opt)) enqueue_vcycle_line<T>(c, in, st);
@@ -434,7 +435,18 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
         }
     }
     Level64& cl = c->h64[L - 1];
-    k_coarse_setup<T><<<1, 256, 0, st>>>(cl.nx, cl.ny, in.lv[L - 1].tr ? 1 : 0, cl.m, cl.We, cl.Wn, c->mu, in.Ainv);
+    {
+        const int w = std::min(cl.nx, cl.ny), tr = in.lv[L - 1].tr ? 1 : 0;
+        if (w <= 4)
+            k_coarse_setup<T, 4><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
+                                                           in.Ainv);
+        else if (w <= 8)
+            k_coarse_setup<T, 8><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
+                                                           in.Ainv);
+        else
+            k_coarse_setup<T, kCoarseBand><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu,
+                                                                     in.Ywork, in.Ainv);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         c->err = std::string("hierarchy launch: ") + hipGetErrorString(e);
@@ -472,6 +484,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     }
     const LevelT<T>& cl = in.lv.back();
     HIPCHK(ctx->alloc(&in.Ainv, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
+    HIPCHK(ctx->alloc(&in.Ywork, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
     HIPCHK(ctx->alloc(&in.r, n));
     HIPCHK(ctx->alloc(&in.x, n));
     HIPCHK(ctx->alloc(&in.p[0], n));
@@ -492,6 +505,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
             if (std::max(in.lv[l].nx, in.lv[l].ny) > 64 * kLineMaxL) continue;
             size_t need = 0;
             for (int k = l; k < L; ++k) need += 5 * (size_t)(in.lv[k].nx + 1) * in.lv[k].ny;
+            need += (size_t)in.lv[L - 1].nx * in.lv[L - 1].ny;  // coarsest right-hand side, gathered
             need *= sizeof(T);
             if (need <= (size_t)lds_max) {
                 in.sub_first = l;
@@ -509,6 +523,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
                 off += 5 * pitch * lv.ny;
             }
             S.Ainv = in.Ainv;
+            S.bc_off = off;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)in.sub_lds));

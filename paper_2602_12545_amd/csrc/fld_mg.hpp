@@ -103,52 +103,119 @@ __global__ __launch_bounds__(256) void k_transpose(int nx, int ny, const T* __re
     }
 }
 
-// Dense inverse of the coarsest level (n <= 64 cells) by Gauss-Jordan
-// elimination without pivoting (the matrix is SPD), FP64 in LDS, one
-// workgroup.  `tr` selects the cell order of the view the solver uses on that
-// level (0: row-major, 1: transposed).
-constexpr int kCoarseMax = 64;
-template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_setup(int nx, int ny, int tr, const double* __restrict__ m,
-                                                      const double* __restrict__ We, const double* __restrict__ Wn,
-                                                      const double* __restrict__ mu, T* Ainv) {
-    __shared__ double A[kCoarseMax * kCoarseMax];
-    __shared__ double col[kCoarseMax];
-    const int n = nx * ny;
-    const int t = ltid(), nt = lsize();
+// Dense inverse of the coarsest level (n <= kCoarseMax cells) in FP64, one
+// workgroup.  The cells are numbered along the shorter grid direction first,
+// which makes A a band matrix of half-bandwidth w = min(nx, ny) <= BW; its
+// Cholesky factor A = L L^T keeps that band (stored by diagonals:
+// Lb[i][k] = L(i, i - k), in place of A's band).  One wavefront factors
+// column by column (lane r computes L(j + r, j) from the LDS copy of the
+// band); then thread j solves L L^T x = e_j, column j of A^-1, keeping the
+// last BW unknowns of each substitution in registers (slot = row mod BW).  The
+// inverse is stored in the cell order of the view the solver uses on that
+// level (`tr`: 0 row-major, 1 transposed).  ywork: n * n doubles (the forward
+// solutions).  BW: 4, 8 or 16 (the host picks the smallest >= w).
+constexpr int kCoarseMax = 256;
+constexpr int kCoarseBand = 16;
+template <typename T, int BW>
+__global__ __launch_bounds__(kCoarseMax) void k_coarse_setup(int nx, int ny, int tr, const double* __restrict__ m,
+                                                             const double* __restrict__ We,
+                                                             const double* __restrict__ Wn,
+                                                             const double* __restrict__ mu, double* __restrict__ ywork,
+                                                             T* __restrict__ Ainv) {
+    constexpr int Ld = BW + 1;
+    // rows past n (read by the back substitution) stay zero
+    __shared__ double Lb[(kCoarseMax + BW) * Ld];
+    __shared__ double invd[kCoarseMax];
+    const int n = nx * ny, t = threadIdx.x;
+    const bool cm = ny < nx;  // band order runs along y first
+    const int w = cm ? ny : nx;
     const double s = 1.0 / *mu;
-    for (int k = t; k < n * n; k += nt) A[k] = 0.0;
+    for (int k = t; k < (kCoarseMax + BW) * Ld; k += kCoarseMax) Lb[k] = 0.0;
     __syncthreads();
-    for (int c = t; c < n; c += nt) {
-        const int i = c % nx, j = c / nx;
-        auto id = [&](int ii, int jj) { return tr ? ii * ny + jj : jj * nx + ii; };
-        const double e = (i + 1 < nx) ? We[c] * s : 0.0;
-        const double w = (i > 0) ? We[c - 1] * s : 0.0;
-        const double no = (j + 1 < ny) ? Wn[c] * s : 0.0;
-        const double so = (j > 0) ? Wn[c - nx] * s : 0.0;
-        const int me = id(i, j);
-        A[me * n + me] = m[c] * s + ((w + e) + (so + no));
-        if (i + 1 < nx) A[me * n + id(i + 1, j)] = -e;
-        if (i > 0) A[me * n + id(i - 1, j)] = -w;
-        if (j + 1 < ny) A[me * n + id(i, j + 1)] = -no;
-        if (j > 0) A[me * n + id(i, j - 1)] = -so;
-    }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double p = A[k * n + k];
-        for (int i = t; i < n; i += nt) col[i] = A[i * n + k];
-        __syncthreads();
-        for (int i = t; i < n; i += nt) A[i * n + k] = (i == k) ? 1.0 : 0.0;
-        __syncthreads();
-        for (int jj = t; jj < n; jj += nt) A[k * n + jj] /= p;
-        __syncthreads();
-        for (int q = t; q < n * n; q += nt) {
-            const int i = q / n, jj = q % n;
-            if (i != k) A[q] -= col[i] * A[k * n + jj];
+    // A's band: A(o, o) and the couplings to the previous cell along the fast
+    // direction (o - 1) and to the previous line (o - w; the same cell when w = 1)
+    if (t < n) {
+        const int o = t;
+        const int fi = cm ? o / ny : o % nx, fj = cm ? o % ny : o / nx;  // grid (i, j)
+        const int c = fj * nx + fi;
+        const double e = (fi + 1 < nx) ? We[c] * s : 0.0, wv = (fi > 0) ? We[c - 1] * s : 0.0;
+        const double no = (fj + 1 < ny) ? Wn[c] * s : 0.0, so = (fj > 0) ? Wn[c - nx] * s : 0.0;
+        Lb[o * Ld] = m[c] * s + ((wv + e) + (so + no));
+        const double fast = cm ? so : wv, line = cm ? wv : so;
+        if (w == 1) {
+            Lb[o * Ld + 1] = -(fast + line);
+        } else {
+            Lb[o * Ld + 1] = -fast;
+            Lb[o * Ld + w] = -line;
         }
-        __syncthreads();
     }
-    for (int q = t; q < n * n; q += nt) Ainv[q] = (T)A[q];
+    __syncthreads();
+    if (t < 64) {
+        for (int j = 0; j < n; ++j) {
+            // lane t: A(i, j) - sum_u L(i, j - u) L(j, j - u), i = j + t, u = 1..BW
+            // (entries outside the band or before column 0 are zero)
+            const int i = min(j + t, n - 1);
+            double v = Lb[i * Ld + min(t, BW)], v2 = 0.0;
+#pragma unroll
+            for (int u = 1; u <= BW; ++u) {
+                const double li = (t + u <= BW) ? Lb[i * Ld + min(t + u, BW)] : 0.0;
+                if (u & 1) v -= li * Lb[j * Ld + u];
+                else v2 -= li * Lb[j * Ld + u];
+            }
+            v += v2;
+            const double d = sqrt(__shfl(v, 0, 64));
+            if (t <= w && j + t < n) Lb[i * Ld + t] = (t == 0) ? d : v / d;
+            if (t == 0) invd[j] = 1.0 / d;
+            // the next column reads this one (same wavefront: LDS keeps the order)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    if (t >= n) return;
+    const int j = t;
+    double win[BW];
+#pragma unroll
+    for (int q = 0; q < BW; ++q) win[q] = 0.0;
+    // forward: L y = e_j
+    for (int ib = 0; ib < n; ib += BW) {
+#pragma unroll
+        for (int r = 0; r < BW; ++r) {
+            const int i = ib + r;
+            if (i < n) {
+                double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 1; k <= BW; ++k) acc -= Lb[i * Ld + k] * win[(r - k + BW) % BW];
+                const double y = acc * invd[i];
+                win[r] = y;
+                ywork[(size_t)i * n + j] = y;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BW; ++q) win[q] = 0.0;
+    // back: L^T x = y
+    auto prim = [&](int o) {  // band-order cell -> index in the solver's cell order
+        const int fi = cm ? o / ny : o % nx, fj = cm ? o % ny : o / nx;
+        return tr ? fi * ny + fj : fj * nx + fi;
+    };
+    const int pj = prim(j);
+    for (int ib = (n - 1) / BW * BW; ib >= 0; ib -= BW) {
+#pragma unroll
+        for (int rr = 0; rr < BW; ++rr) {
+            const int r = BW - 1 - rr;
+            const int i = ib + r;
+            if (i < n) {
+                double acc = ywork[(size_t)i * n + j];
+#pragma unroll
+                for (int k = 1; k <= BW; ++k) acc -= Lb[(i + k) * Ld + k] * win[(r + k) % BW];
+                const double x = acc * invd[i];
+                win[r] = x;
+                Ainv[(size_t)prim(i) * n + pj] = (T)x;
+            }
+        }
+    }
 }
 
 // rz finalisation shared by the kernels that end a V-cycle on level 0:
@@ -163,23 +230,30 @@ __device__ inline void finish_rz(Scalars* sc, double rz) {
     }
 }
 
-// Coarsest level: x = A^-1 b with the dense inverse.  With DOT (a one-level
-// hierarchy) it also finalises r.z.
+// Coarsest level: x = A^-1 b with the dense inverse, four lanes per row.
+// With DOT (a one-level hierarchy) it also finalises r.z.
+constexpr int kCoarseSolveThreads = 4 * kCoarseMax;
 template <typename T, bool DOT>
-__global__ __launch_bounds__(64) void k_coarse_solve(int n, const T* __restrict__ Ainv, const T* __restrict__ b,
-                                                     T* __restrict__ x, Scalars* sc) {
+__global__ __launch_bounds__(kCoarseSolveThreads) void k_coarse_solve(int n, const T* __restrict__ Ainv,
+                                                                      const T* __restrict__ b, T* __restrict__ x,
+                                                                      Scalars* sc) {
     if (sc->done) return;
     __shared__ T sb[kCoarseMax];
     __shared__ double sh[16];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, row = t >> 2, l4 = t & 3;
     if (t < n) sb[t] = b[t];
     __syncthreads();
+    T a = T(0);
+    if (row < n) {
+        const T* ar = Ainv + (size_t)row * n;
+        for (int c = l4; c < n; c += 4) a += ar[c] * sb[c];
+    }
+    a += __shfl_xor(a, 1, 4);
+    a += __shfl_xor(a, 2, 4);
     double acc = 0.0;
-    if (t < n) {
-        T a = T(0);
-        for (int k = 0; k < n; ++k) a += Ainv[t * n + k] * sb[k];
-        x[t] = a;
-        acc = (double)sb[t] * (double)a;
+    if (row < n && l4 == 0) {
+        x[row] = a;
+        acc = (double)sb[row] * (double)a;
     }
     if (DOT) {
         const double rz = block_sum(acc, sh);
@@ -987,6 +1061,7 @@ struct SubCycle {
     int nlev;              // levels ls .. ls + nlev - 1 (the last is the coarsest)
     SubLevel<T> lv[kSubMaxLevels];
     const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
+    int bc_off;            // LDS pool offset of the coarsest right-hand side in that cell order
 };
 
 // LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny).
@@ -1082,32 +1157,31 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
         }
         __syncthreads();
     }
-    // coarsest: dense inverse in the primary layout's cell order; 16 lanes per
-    // row of the inverse, each summing 4 columns (coalesced), then a shuffle
-    // reduction within the 16 lanes
+    // coarsest: dense inverse in the primary layout's cell order (the
+    // right-hand side gathered into that order first), four lanes per row
     {
         const SubLevel<T>& L = S.lv[S.nlev - 1];
         const int n = L.nx * L.ny;
         T* b = pool + L.off + 3 * L.size;
         T* x = b + L.size;
-        constexpr int G = 16;
-        for (int r0 = 0; r0 < n; r0 += kSubThreads<T> / G) {
-            const int row = r0 + t / G, lane = t % G;
+        T* bc = pool + S.bc_off;
+        for (int c = t; c < n; c += kSubThreads<T>) {
+            const int i = L.tr ? c / L.ny : c % L.nx, j = L.tr ? c % L.ny : c / L.nx;
+            bc[c] = b[j * L.pitch + i];
+        }
+        __syncthreads();
+        constexpr int RP = kSubThreads<T> / 4;  // rows per pass
+        const int l4 = t & 3;
+        for (int r0 = 0; r0 < n; r0 += RP) {
+            const int row = r0 + (t >> 2);
             T acc = T(0);
             if (row < n) {
                 const T* arow = S.Ainv + (size_t)row * n;
-                for (int col = lane * 4; col < n; col += G * 4)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int cc = col + q;
-                        if (cc < n) {
-                            const int ik = L.tr ? cc / L.ny : cc % L.nx, jk = L.tr ? cc % L.ny : cc / L.nx;
-                            acc += arow[cc] * b[jk * L.pitch + ik];
-                        }
-                    }
+                for (int c = l4; c < n; c += 4) acc += arow[c] * bc[c];
             }
-            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-            if (row < n && lane == 0) {
+            acc += __shfl_xor(acc, 1, 4);
+            acc += __shfl_xor(acc, 2, 4);
+            if (row < n && l4 == 0) {
                 const int i = L.tr ? row / L.ny : row % L.nx, j = L.tr ? row % L.ny : row / L.nx;
                 x[j * L.pitch + i] = acc;
             }

@@ -82,7 +82,7 @@ fld_status fld_tune(const fld_grid* grid, const fld_options* base, const double*
     const bool lines_fit = grid->nx <= 4096 && grid->ny <= 4096;
     for (int sm : {FLD_SMOOTH_LINE, FLD_SMOOTH_LINE_SPLIT, FLD_SMOOTH_POINT}) {
         if (sm != FLD_SMOOTH_POINT && !lines_fit) continue;
-        for (int cm : {64, 16})
+        for (int cm : {64, 256, 16})
             for (int ch : {8, 16, 4}) {
                 fld_options o = b0;
                 o.smoother = sm;

@@ -191,3 +191,18 @@ def test_band_fused_sweeps_fixed_iterations(lib, shape, prec):
     E0 = np.asarray(prob.E)
     tol = 1e-10 if prec == "fp64" else 1e-4
     assert rel_l2(E1 - E0, E2 - E0) < tol
+
+
+@pytest.mark.parametrize("shape", [(96, 80), (512, 8), (7, 300), (15, 16)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_coarsest_level_up_to_256_cells(lib, shape, prec):
+    """Hierarchies whose coarsest level holds up to 256 cells (its inverse
+    from the band Cholesky factor): square, strip-shaped (half-bandwidth 1 or
+    2) and single-level (the whole grid solved densely) cases, against the
+    oracle."""
+    nx, ny = shape
+    prob = W.make_c2(nx=nx, ny=ny)
+    E, T, info = gpu_step(lib, torch, prob, precision=prec, rel_tol=1e-12, norm=1, mg_coarse_max=256)
+    assert info["status"] == 0
+    r = O.step_problem(prob)
+    assert rel_l2(E, r.E) < 1e-10 and rel_l2(T, r.T) < 1e-10

@@ -145,9 +145,9 @@ __device__ __attribute__((noinline)) void b_sweep(int nx, int ny, int dir, int p
     const T* Wc = dir ? We : Wn;
     constexpr bool BF = sizeof(T) == 8;  // branch-free loads pay off in binary64 only (measured)
     if (zero)
-        wave_line_sweep<T, kBLineL, true, BF>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
+        wave_line_sweep<T, kBLineL, true, BF, true>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
     else
-        wave_line_sweep<T, kBLineL, false, BF>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
+        wave_line_sweep<T, kBLineL, false, BF, true>(na, nl, par, sa, sl, m, Wa, Wc, b, x, threadIdx.x >> 6, NT / 64);
     __syncthreads();
 }
 

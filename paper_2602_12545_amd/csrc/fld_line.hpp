@@ -63,6 +63,57 @@ __device__ inline void fill(T (&v)[N], T a) {
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = a;
 }
+// Value of lane + D (D > 0) or lane - D (D < 0) within the lane's row of 16
+// (data-parallel primitive move, a vector ALU operation; 0 when that lane is
+// outside the row).  For segments of K <= 16 lanes aligned to K.
+template <int D>
+__device__ inline int dpp_row_shift(int v) {
+    static_assert(D != 0 && D > -16 && D < 16, "row shift");
+    constexpr int ctrl = D > 0 ? 0x100 + D : 0x110 - D;  // row_shl:D / row_shr:-D
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xf, 0xf, true);
+}
+template <int D, typename T>
+__device__ inline T row_shift(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_row_shift<D>(__builtin_bit_cast(int, v)));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)dpp_row_shift<D>((int)(unsigned)u);
+        const unsigned hi = (unsigned)dpp_row_shift<D>((int)(unsigned)(u >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
+// One step of parallel cyclic reduction on the chunk-end rows
+// (A x_{k-st} + B x_k + C x_{k+st} = R), neighbours from lanes k -+ st.
+template <typename T>
+__device__ inline void pcr_combine(int k, int K, int st, T& A, T& B, T& C, T& R, T Am, T Bm, T Cm, T Rm, T Ap, T Bp,
+                                   T Cp, T Rp) {
+    T nA = T(0), nB = B, nC = T(0), nR = R;
+    if (k - st >= 0) {
+        const T al = -A * line_rcp(Bm);
+        nA = al * Am;
+        nB += al * Cm;
+        nR += al * Rm;
+    }
+    if (k + st < K) {
+        const T ga = -C * line_rcp(Bp);
+        nC = ga * Cp;
+        nB += ga * Ap;
+        nR += ga * Rp;
+    }
+    A = nA;
+    B = nB;
+    C = nC;
+    R = nR;
+}
+template <int ST, typename T>
+__device__ inline void pcr_step_dpp(int k, int K, T& A, T& B, T& C, T& R) {
+    const T Am = row_shift<-ST>(A), Bm = row_shift<-ST>(B), Cm = row_shift<-ST>(C), Rm = row_shift<-ST>(R);
+    const T Ap = row_shift<ST>(A), Bp = row_shift<ST>(B), Cp = row_shift<ST>(C), Rp = row_shift<ST>(R);
+    pcr_combine(k, K, ST, A, B, C, R, Am, Bm, Cm, Rm, Ap, Bp, Cp, Rp);
+}
+
 // Lanes per line for a line of `na` cells with at most LM cells per lane
 // (power of two, <= 64).
 template <int LM>
@@ -85,11 +136,13 @@ __device__ inline int wave_line_lanes(int na) {
 // K-lane segment of a wavefront.  Each lane eliminates its chunk interior
 // (Thomas with three right-hand sides) so that every interior unknown is
 // y + u X_{k-1} + v X_k in the chunk-end unknowns X; the K chunk-end rows form
-// a tridiagonal system solved by parallel cyclic reduction with cross-lane
-// shuffles; back-substitution finishes.  Wave `wave` of `nwaves` takes lines
+// a tridiagonal system solved by parallel cyclic reduction across the lanes
+// (shuffles; with DPP, binary32 segments of at most 16 lanes use row shifts,
+// measured faster for rows read from global memory and slower from LDS);
+// back-substitution finishes.  Wave `wave` of `nwaves` takes lines
 // wave * 64/K + ..., the next pass nwaves * 64/K lines further.  Needs na <=
 // 64 LM.  The caller separates half-sweeps with a barrier.
-template <typename T, int LM, bool ZERO, bool BF = true>
+template <typename T, int LM, bool ZERO, bool BF = true, bool DPP = false>
 __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long long sl, const T* __restrict__ m,
                                 const T* __restrict__ Wa, const T* __restrict__ Wc, const T* __restrict__ b,
                                 T* __restrict__ x, int wave, int nwaves) {
@@ -216,36 +269,38 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
                 ul = gu[q];
                 vl = gv[q];
             }
-        // the next chunk's first row, y + u X_k + v X_{k+1}
+        // the next chunk's first row, y + u X_k + v X_{k+1} (binary64 row
+        // shifts would need twice the moves and registers)
         const bool has_next = k + 1 < K;
-        T yn = __shfl(gy[0], lane + 1, 64), un = __shfl(gu[0], lane + 1, 64), vn = __shfl(gv[0], lane + 1, 64);
+        const bool rows16 = DPP && sizeof(T) == 4 && K <= 16;
+        T yn, un, vn;
+        if (rows16) {
+            yn = row_shift<1>(gy[0]);
+            un = row_shift<1>(gu[0]);
+            vn = row_shift<1>(gv[0]);
+        } else {
+            yn = __shfl(gy[0], lane + 1, 64);
+            un = __shfl(gu[0], lane + 1, 64);
+            vn = __shfl(gv[0], lane + 1, 64);
+        }
         if (!has_next) yn = un = vn = T(0);
         T A = aE * ul, B = dE + aE * vl + cE * un, C = cE * vn, R = rE - aE * yl - cE * yn;
-        for (int st = 1; st < K; st <<= 1) {
-            const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
-            const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(R, lane - st, 64);
-            const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
-            const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(R, lane + st, 64);
-            T nA = T(0), nB = B, nC = T(0), nR = R;
-            if (k - st >= 0) {
-                const T al = -A * line_rcp(Bm);
-                nA = al * Am;
-                nB += al * Cm;
-                nR += al * Rm;
+        if (rows16) {
+            if (K > 1) pcr_step_dpp<1>(k, K, A, B, C, R);
+            if (K > 2) pcr_step_dpp<2>(k, K, A, B, C, R);
+            if (K > 4) pcr_step_dpp<4>(k, K, A, B, C, R);
+            if (K > 8) pcr_step_dpp<8>(k, K, A, B, C, R);
+        } else {
+            for (int st = 1; st < K; st <<= 1) {
+                const T Am = __shfl(A, lane - st, 64), Bm = __shfl(B, lane - st, 64);
+                const T Cm = __shfl(C, lane - st, 64), Rm = __shfl(R, lane - st, 64);
+                const T Ap = __shfl(A, lane + st, 64), Bp = __shfl(B, lane + st, 64);
+                const T Cp = __shfl(C, lane + st, 64), Rp = __shfl(R, lane + st, 64);
+                pcr_combine(k, K, st, A, B, C, R, Am, Bm, Cm, Rm, Ap, Bp, Cp, Rp);
             }
-            if (k + st < K) {
-                const T ga = -C * line_rcp(Bp);
-                nC = ga * Cp;
-                nB += ga * Ap;
-                nR += ga * Rp;
-            }
-            A = nA;
-            B = nB;
-            C = nC;
-            R = nR;
         }
         const T X = R * line_rcp(B);
-        T Xp = __shfl(X, lane - 1, 64);
+        T Xp = rows16 ? row_shift<-1>(X) : __shfl(X, lane - 1, 64);
         if (k == 0) Xp = T(0);
         if (active) {
 #pragma unroll

@@ -16,10 +16,10 @@
 // Inside a pass, a row of na cells is split into K chunks of L <= LM cells
 // (the chunking of the one-half-sweep kernel), one chunk per thread; the
 // chunk interior is eliminated locally and the K chunk-end unknowns are solved
-// by cyclic reduction, with wavefront shuffles when K <= 64 and in LDS
-// otherwise.  (Longer chunks that keep 1024-cell rows inside one wavefront
-// were measured slower: the per-lane Thomas chain doubles and occupancy
-// halves.)
+// by parallel cyclic reduction with wavefront shuffles when K <= 64, else by
+// seg_tridiag (cyclic reduction in LDS down to one wavefront's worth).
+// (Longer chunks that keep 1024-cell rows inside one wavefront were measured
+// slower: the per-lane Thomas chain doubles and occupancy halves.)
 #pragma once
 
 #include "fld_mg.hpp"
@@ -264,38 +264,9 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
             __syncthreads();
             const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0);
             const T vn = has_next ? sv0[t + 1] : T(0);
-            sA[t] = aE * ul;
-            sB[t] = dE + aE * vl + cE * un;
-            sC[t] = cE * vn;
-            sR[t] = rE - aE * yl - cE * yn;
-            __syncthreads();
-            for (int st = 1; st < K; st <<= 1) {
-                const T a = sA[t], bq = sB[t], c = sC[t], r = sR[t];
-                T na = T(0), nb = bq, nc = T(0), nr = r;
-                if (k - st >= 0) {
-                    const T al = -a * line_rcp(sB[t - st]);
-                    na = al * sA[t - st];
-                    nb += al * sC[t - st];
-                    nr += al * sR[t - st];
-                }
-                if (k + st < K) {
-                    const T ga = -c * line_rcp(sB[t + st]);
-                    nc = ga * sC[t + st];
-                    nb += ga * sA[t + st];
-                    nr += ga * sR[t + st];
-                }
-                __syncthreads();
-                sA[t] = na;
-                sB[t] = nb;
-                sC[t] = nc;
-                sR[t] = nr;
-                __syncthreads();
-            }
-            X = sR[t] * line_rcp(sB[t]);
-            __syncthreads();
-            sR[t] = X;
-            __syncthreads();
-            Xp = k > 0 ? sR[t - 1] : T(0);
+            // sy0 is free again once seg_tridiag's first barrier has passed
+            seg_tridiag<T>(t, k, K, aE * ul, dE + aE * vl + cE * un, cE * vn, rE - aE * yl - cE * yn, sA, sB, sC,
+                           sR, sy0, X, Xp);
         }
         if (active) {
             T* dst = rows + (size_t)(row - (r0 - 1)) * nx;

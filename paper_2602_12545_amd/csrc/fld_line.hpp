@@ -114,6 +114,102 @@ __device__ inline void pcr_step_dpp(int k, int K, T& A, T& B, T& C, T& R) {
     pcr_combine(k, K, ST, A, B, C, R, Am, Bm, Cm, Rm, Ap, Bp, Cp, Rp);
 }
 
+// Tridiagonal systems A_k X_{k-1} + B_k X_k + C_k X_{k+1} = R_k, k = 0 ..
+// K-1, one row per thread, each system on K consecutive threads of the
+// workgroup (K a power of two, segments aligned to K; A_0 and C_{K-1} unused).
+// K <= 64: parallel cyclic reduction with shuffles inside the segment, no
+// barrier.  K > 64: cyclic reduction in LDS (each level keeps every other
+// remaining row, one barrier per level) down to 64 rows, parallel cyclic
+// reduction of those by the segment's first wavefront, then back substitution
+// level by level.  Returns X_k and X_{k-1} (0 for k = 0).  Every thread of the
+// workgroup calls it with the same K; sA, sB, sC, sR, sX: one element per
+// thread.
+template <typename T>
+__device__ void seg_tridiag(int t, int k, int K, T A, T B, T C, T R, T* sA, T* sB, T* sC, T* sR, T* sX, T& X,
+                            T& Xp) {
+    const int lane = threadIdx.x & 63;
+    auto wave_pcr = [&](int kk, int KK, T& a, T& b, T& c, T& r) {
+        for (int st = 1; st < KK; st <<= 1) {
+            const T Am = __shfl(a, lane - st, 64), Bm = __shfl(b, lane - st, 64);
+            const T Cm = __shfl(c, lane - st, 64), Rm = __shfl(r, lane - st, 64);
+            const T Ap = __shfl(a, lane + st, 64), Bp = __shfl(b, lane + st, 64);
+            const T Cp = __shfl(c, lane + st, 64), Rp = __shfl(r, lane + st, 64);
+            T nA = T(0), nB = b, nC = T(0), nR = r;
+            if (kk - st >= 0) {
+                const T al = -a * line_rcp(Bm);
+                nA = al * Am;
+                nB += al * Cm;
+                nR += al * Rm;
+            }
+            if (kk + st < KK) {
+                const T ga = -c * line_rcp(Bp);
+                nC = ga * Cp;
+                nB += ga * Ap;
+                nR += ga * Rp;
+            }
+            a = nA;
+            b = nB;
+            c = nC;
+            r = nR;
+        }
+    };
+    if (K <= 64) {
+        wave_pcr(k, K, A, B, C, R);
+        X = R * line_rcp(B);
+        Xp = __shfl(X, lane - 1, 64);
+        if (k == 0) Xp = T(0);
+        return;
+    }
+    sA[t] = A;
+    sB[t] = B;
+    sC[t] = C;
+    sR[t] = R;
+    __syncthreads();
+    // reduction: at stride s the rows with (k + 1) % 2s == 0 absorb rows k -+ s
+    // (which stop changing at that level)
+    int s = 1;
+    for (; K / s > 64; s <<= 1) {
+        if (((k + 1) & (2 * s - 1)) == 0) {
+            const int m = t - s;
+            const T a = sA[t], c = sC[t];
+            const T al = -a * line_rcp(sB[m]);
+            T nA = al * sA[m], nB = sB[t] + al * sC[m], nC = T(0), nR = sR[t] + al * sR[m];
+            if (k + s < K) {
+                const int p = t + s;
+                const T ga = -c * line_rcp(sB[p]);
+                nC = ga * sC[p];
+                nB += ga * sA[p];
+                nR += ga * sR[p];
+            }
+            sA[t] = nA;
+            sB[t] = nB;
+            sC[t] = nC;
+            sR[t] = nR;
+        }
+        __syncthreads();
+    }
+    // the 64 remaining rows (k = s (j + 1) - 1) on the segment's first wavefront
+    const int base = t - k;
+    if (k < 64) {
+        const int kk = base + s * (k + 1) - 1;
+        T a = sA[kk], b = sB[kk], c = sC[kk], r = sR[kk];
+        wave_pcr(k, 64, a, b, c, r);
+        sX[kk] = r * line_rcp(b);
+    }
+    __syncthreads();
+    for (s >>= 1; s >= 1; s >>= 1) {
+        if (((k + 1) & (2 * s - 1)) == s) {
+            T v = sR[t];
+            if (k >= s) v -= sA[t] * sX[t - s];
+            if (k + s < K) v -= sC[t] * sX[t + s];
+            sX[t] = v * line_rcp(sB[t]);
+        }
+        __syncthreads();
+    }
+    X = sX[t];
+    Xp = k > 0 ? sX[t - 1] : T(0);
+}
+
 // Lanes per line for a line of `na` cells with at most LM cells per lane
 // (power of two, <= 64).
 template <int LM>

@@ -425,7 +425,7 @@ enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 // three right-hand sides) to express every interior unknown through the last
 // unknowns X_{k-1}, X_k of the previous and of its own chunk; substituting the
 // neighbour chunk's first row gives one tridiagonal equation per chunk in the
-// X's, solved by parallel cyclic reduction in LDS; back-substitution finishes.
+// X's, solved by cyclic reduction (seg_tridiag); back-substitution finishes.
 // DOT: partial r.z over the solved rows, stored at part[nb_prev + block]
 // (level 0; k_reduce_rz finishes the sum).
 template <typename T, int MODE, int DOT>
@@ -544,45 +544,29 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
             ul = gu[q];
             vl = gv[q];
         }
-    sy0[t] = gy[0];
-    su0[t] = gu[0];
-    sv0[t] = gv[0];
-    __syncthreads();
+    // the next chunk's first row (y + u X_k + v X_{k+1}), then the K
+    // chunk-end unknowns of the row
     const bool has_next = k + 1 < K;
-    const T yn = has_next ? sy0[t + 1] : T(0), un = has_next ? su0[t + 1] : T(0), vn = has_next ? sv0[t + 1] : T(0);
-    sA[t] = aE * ul;
-    sB[t] = dE + aE * vl + cE * un;
-    sC[t] = cE * vn;
-    sR[t] = rE - aE * yl - cE * yn;
-    __syncthreads();
-    // parallel cyclic reduction over the K interface unknowns of each row
-    for (int st = 1; st < K; st <<= 1) {
-        const T a = sA[t], bb = sB[t], c = sC[t], r = sR[t];
-        T na = T(0), nb = bb, nc = T(0), nr = r;
-        if (k - st >= 0) {
-            const T al = -a * line_rcp(sB[t - st]);
-            na = al * sA[t - st];
-            nb += al * sC[t - st];
-            nr += al * sR[t - st];
-        }
-        if (k + st < K) {
-            const T ga = -c * line_rcp(sB[t + st]);
-            nc = ga * sC[t + st];
-            nb += ga * sA[t + st];
-            nr += ga * sR[t + st];
-        }
+    T yn, un, vn;
+    if (K <= 64) {
+        const int lane = t & 63;
+        yn = __shfl(gy[0], lane + 1, 64);
+        un = __shfl(gu[0], lane + 1, 64);
+        vn = __shfl(gv[0], lane + 1, 64);
+    } else {
+        sy0[t] = gy[0];
+        su0[t] = gu[0];
+        sv0[t] = gv[0];
         __syncthreads();
-        sA[t] = na;
-        sB[t] = nb;
-        sC[t] = nc;
-        sR[t] = nr;
-        __syncthreads();
+        yn = has_next ? sy0[t + 1] : T(0);
+        un = has_next ? su0[t + 1] : T(0);
+        vn = has_next ? sv0[t + 1] : T(0);
     }
-    const T X = sR[t] * line_rcp(sB[t]);
-    __syncthreads();
-    sR[t] = X;
-    __syncthreads();
-    const T Xp = k > 0 ? sR[t - 1] : T(0);
+    if (!has_next) yn = un = vn = T(0);
+    T X, Xp;
+    // (sy0 is free again once seg_tridiag's first barrier has passed)
+    seg_tridiag<T>(t, k, K, aE * ul, dE + aE * vl + cE * un, cE * vn, rE - aE * yl - cE * yn, sA, sB, sC, sR, sy0, X,
+                   Xp);
     double acc = 0.0;
     if (active) {
         T out[LM];

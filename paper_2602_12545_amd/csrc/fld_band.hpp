@@ -53,11 +53,12 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     double* sh = reinterpret_cast<double*>(pcr + 7 * NT);
     T *sA = pcr, *sB = pcr + NT, *sC = pcr + 2 * NT, *sR = pcr + 3 * NT;
     T *sy0 = pcr + 4 * NT, *su0 = pcr + 5 * NT, *sv0 = pcr + 6 * NT;
-    const int t = threadIdx.x, r0 = blockIdx.x * R;
+    const int t = threadIdx.x, r0 = xcd_block(blockIdx.x, gridDim.x) * R;
     const int rend = min(r0 + R, ny);  // band rows [r0, rend)
     const int k = t % K, lpp = NT / K, s0 = k * L;
     const int lane = t & 63;
     const bool wave_pcr = K <= 64;
+    double acc = 0.0;  // DOT: b.x over the band's rows, accumulated as they are solved
 
     // Coefficients, right-hand side and (first parity) neighbour-row x of one
     // chunk of one row, loaded ahead of the solve, for rows that split into
@@ -270,13 +271,17 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         }
         if (active) {
             T* dst = rows + (size_t)(row - (r0 - 1)) * nx;
+            const bool own = row >= r0 && row < rend;  // a band row, not the halo
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                if (q < L && g < nx)
-                    dst[g] = (q == L - 1) ? X
-                                          : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
-                                                gv[q < LM - 1 ? q : 0] * X;
+                if (q < L && g < nx) {
+                    const T v = (q == L - 1) ? X
+                                             : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                   gv[q < LM - 1 ? q : 0] * X;
+                    dst[g] = v;
+                    if (DOT && own) acc += (double)vb[q] * (double)v;
+                }
             }
         }
         if (LM == kLineMaxL && !wave_pcr) __syncthreads();  // the LDS reduction arrays are reused next pass
@@ -328,24 +333,18 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     }
     __syncthreads();
     // band rows out
-    double acc = 0.0;
     const int nr = rend - r0;
     if (!OUT_T) {
         for (int e = t; e < nr * nx; e += NT) {
             const int rr = e / nx, i = e - rr * nx;
-            const T v = rows[(size_t)(rr + 1) * nx + i];
-            const size_t c = (size_t)(r0 + rr) * nx + i;
-            xout[c] = v;
-            if (DOT) acc += (double)b[c] * (double)v;
+            xout[(size_t)(r0 + rr) * nx + i] = rows[(size_t)(rr + 1) * nx + i];
         }
     } else {
         // transposed: column i of the band becomes nr consecutive values of row i
         for (int e = t; e < nr * nx; e += NT) {
             const int i = e / nr, rr = e - i * nr;
-            const T v = rows[(size_t)(rr + 1) * nx + i];
-            xout[(size_t)i * ny + r0 + rr] = v;
+            xout[(size_t)i * ny + r0 + rr] = rows[(size_t)(rr + 1) * nx + i];
             if (WRITE_BT) bout[(size_t)i * ny + r0 + rr] = bb[(size_t)rr * nx + i];
-            if (DOT) acc += (double)b[(size_t)(r0 + rr) * nx + i] * (double)v;
         }
     }
     if (DOT) {

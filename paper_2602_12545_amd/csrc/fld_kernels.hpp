@@ -18,6 +18,16 @@ namespace fld {
 __device__ inline int ltid() { return threadIdx.y * blockDim.x + threadIdx.x; }
 __device__ inline int lsize() { return blockDim.x * blockDim.y; }
 
+// Workgroup b of G, renumbered so that each XCD runs a contiguous range: the
+// dispatcher deals workgroups to the 8 XCDs in turn (b -> XCD b mod 8), and
+// neighbouring tiles then share that XCD's L2 (halo rows, partial lines of
+// transposed writes).  A bijection of [0, G).
+__device__ inline int xcd_block(int b, int G) {
+    constexpr int X = 8;
+    const int x = b % X, j = b / X, q = G / X, rem = G % X;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
+}
+
 // Sum over the workgroup; the result is valid in thread 0.  sh: >= 16 doubles.
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -28,6 +28,14 @@ __device__ inline int xcd_block(int b, int G) {
     return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
 }
 
+// Tile (tbx, tby) of a 2D grid of workgroups, in the XCD-aware order of
+// xcd_block over the row-major workgroup numbering.
+__device__ inline void xcd_tile(int& tbx, int& tby) {
+    const int b = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    tbx = b % gridDim.x;
+    tby = b / gridDim.x;
+}
+
 // Sum over the workgroup; the result is valid in thread 0.  sh: >= 16 doubles.
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

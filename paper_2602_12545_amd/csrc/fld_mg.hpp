@@ -302,7 +302,9 @@ __global__ __launch_bounds__(256) void k_pre_point(int nx, int ny, const T* __re
     constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
     __shared__ T sb[N], sm[N], swe[N], swn[N], sx[N];
     __shared__ T sr[TRows][TBX];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    int tbx, tby;
+    xcd_tile(tbx, tby);
+    const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
     load_coef_tile<T, H>(nx, ny, i0, j0, m, We, Wn, sm, swe, swn);
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(256) void k_pre_point(int nx, int ny, const T* __re
     __syncthreads();
     {
         const int cx = t % (TBX / 2), cy = t / (TBX / 2);
-        const int I = blockIdx.x * (TBX / 2) + cx, J = blockIdx.y * (TRows / 2) + cy;
+        const int I = tbx * (TBX / 2) + cx, J = tby * (TRows / 2) + cy;
         if (cy < TRows / 2 && I < nxc && J < nyc)
             bc[(size_t)J * nxc + I] =
                 (sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) + (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]);
@@ -364,7 +366,9 @@ __global__ __launch_bounds__(256) void k_post_point(int nx, int ny, const T* __r
     constexpr int H = 2, LX = TileG<H>::LX, LY = TileG<H>::LY, N = TileG<H>::N;
     __shared__ T sb[N], sm[N], swe[N], swn[N], sx[N];
     __shared__ double sh[16];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    int tbx, tby;
+    xcd_tile(tbx, tby);
+    const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
     load_coef_tile<T, H>(nx, ny, i0, j0, m, We, Wn, sm, swe, swn);
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
     const int t = threadIdx.x;
     const int lpw = kLineWG / K;
     const int k = t % K;
-    const int row = 2 * (int)(blockIdx.x * lpw + t / K) + par;
+    const int row = 2 * (int)(xcd_block(blockIdx.x, gridDim.x) * lpw + t / K) + par;
     const bool active = row < ny;
     const int s0 = k * L;
     const size_t rbase = (size_t)(active ? row : 0) * nx;
@@ -601,7 +605,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
     __shared__ T sx[N], swe[N], swn[N];
     __shared__ T sr[TRows][TBX];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    int tbx, tby;
+    xcd_tile(tbx, tby);
+    const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
         const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
@@ -626,7 +632,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
     }
     __syncthreads();
     const int cx = t % (TBX / 2), cy = t / (TBX / 2);
-    const int I = blockIdx.x * (TBX / 2) + cx, J = blockIdx.y * (TRows / 2) + cy;
+    const int I = tbx * (TBX / 2) + cx, J = tby * (TRows / 2) + cy;
     if (cy < TRows / 2 && I < nxc && J < nyc)
         bc[(size_t)J * nxc + I] =
             (sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) + (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]);
@@ -651,7 +657,9 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     const bool first = sc->iter == 0 || sc->restart;
     if (blockIdx.x == 0 && blockIdx.y == 0 && ltid() == 0) sc->apply = 0;  // read by no other kernel of this slot before
     const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    int tbx, tby;
+    xcd_tile(tbx, tby);
+    const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
         const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
@@ -765,7 +773,9 @@ __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __rest
     constexpr int NS = 5;
     __shared__ double sE[N], sWe[N], sWn[N];
     __shared__ double sh[16];
-    const int i0 = blockIdx.x * TBX, j0 = blockIdx.y * TRows, t = ltid();
+    int tbx, tby;
+    xcd_tile(tbx, tby);
+    const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
         const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;

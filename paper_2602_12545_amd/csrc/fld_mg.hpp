@@ -163,9 +163,17 @@ __global__ __launch_bounds__(kCoarseMax) void k_coarse_setup(int nx, int ny, int
                 else v2 -= li * Lb[j * Ld + u];
             }
             v += v2;
-            const double d = sqrt(__shfl(v, 0, 64));
-            if (t <= w && j + t < n) Lb[i * Ld + t] = (t == 0) ? d : v / d;
-            if (t == 0) invd[j] = 1.0 / d;
+            // pivot A(j, j) - ... from lane 0 (the wavefront's first lane) and
+            // its reciprocal square root: hardware estimate, two Newton steps
+            const unsigned long long vb = __builtin_bit_cast(unsigned long long, v);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)vb);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(vb >> 32));
+            const double v0 = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+            double y = __builtin_amdgcn_rsq(v0);
+            y = y * (1.5 - 0.5 * v0 * y * y);
+            y = y * (1.5 - 0.5 * v0 * y * y);
+            if (t <= w && j + t < n) Lb[i * Ld + t] = v * y;  // lane 0: v0 / sqrt(v0)
+            if (t == 0) invd[j] = y;
             // the next column reads this one (same wavefront: LDS keeps the order)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -184,10 +192,10 @@ __global__ __launch_bounds__(kCoarseMax) void k_coarse_setup(int nx, int ny, int
         for (int r = 0; r < BW; ++r) {
             const int i = ib + r;
             if (i < n) {
-                double acc = (i == j) ? 1.0 : 0.0;
+                double acc[4] = {(i == j) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k = 1; k <= BW; ++k) acc -= Lb[i * Ld + k] * win[(r - k + BW) % BW];
-                const double y = acc * invd[i];
+                for (int k = 1; k <= BW; ++k) acc[k & 3] -= Lb[i * Ld + k] * win[(r - k + BW) % BW];
+                const double y = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * invd[i];
                 win[r] = y;
                 ywork[(size_t)i * n + j] = y;
             }
@@ -207,10 +215,10 @@ __global__ __launch_bounds__(kCoarseMax) void k_coarse_setup(int nx, int ny, int
             const int r = BW - 1 - rr;
             const int i = ib + r;
             if (i < n) {
-                double acc = ywork[(size_t)i * n + j];
+                double acc[4] = {ywork[(size_t)i * n + j], 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k = 1; k <= BW; ++k) acc -= Lb[(i + k) * Ld + k] * win[(r + k) % BW];
-                const double x = acc * invd[i];
+                for (int k = 1; k <= BW; ++k) acc[k & 3] -= Lb[(i + k) * Ld + k] * win[(r + k) % BW];
+                const double x = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * invd[i];
                 win[r] = x;
                 Ainv[(size_t)prim(i) * n + pj] = (T)x;
             }

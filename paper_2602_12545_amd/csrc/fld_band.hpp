@@ -103,9 +103,21 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     // thread of the workgroup calls it (the LDS reduction has barriers).
     auto solve_row = [&](int row, bool active, const Coef* pre, auto pre_tag, int PH) {
         constexpr bool PRE = decltype(pre_tag)::value;
-        // a wavefront whose rows are all idle skips the solve (rows within a
-        // wavefront need no barrier), leaving its SIMD to the busy ones
-        if (wave_pcr && !__any(active)) return;
+        // a wavefront whose rows are all idle skips the solve and leaves its
+        // SIMD to the busy ones; with rows spanning wavefronts it still passes
+        // the same barriers (the exchange, seg_tridiag's on identity rows,
+        // the LDS reuse)
+        if (!__any(active)) {
+            if constexpr (LM == kLineMaxL) {
+                if (!wave_pcr) {
+                    __syncthreads();
+                    T X, Xp;
+                    seg_tridiag<T>(t, k, K, T(0), T(1), T(0), T(0), sA, sB, sC, sR, sy0, X, Xp);
+                    __syncthreads();
+                }
+            }
+            return;
+        }
         const size_t rb = (size_t)row * nx;
         T vm[LM], vwe[LM], vwn[LM], vws[LM], vb[LM];
         T wwest;
@@ -324,8 +336,8 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         const int row1 = n1 > 0 ? s1 + 2 * (a1 ? ql : 0) : r0;
         const int row2 = n2 > 0 ? s2 + 2 * (a2 ? ql : 0) : r0;
         Coef C1, C2;
-        if (!wave_pcr || __any(a1)) load_coef_vec(row1, C1, true);
-        if (!wave_pcr || __any(a2)) load_coef_vec(row2, C2, false);
+        if (__any(a1)) load_coef_vec(row1, C1, true);
+        if (__any(a2)) load_coef_vec(row2, C2, false);
         solve_row(row1, a1, &C1, std::true_type{}, 1);
         __syncthreads();
         solve_row(row2, a2, &C2, std::true_type{}, 2);

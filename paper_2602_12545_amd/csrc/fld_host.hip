@@ -100,6 +100,8 @@ struct fld_ctx {
     std::vector<Level64> h64;
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
+    double* part_rz = nullptr;  // r.z partials of the V-cycle's last sweep (summed by k_spmv)
+    int nrz = 0;                // their number (set when the V-cycle is queued)
     size_t npart = 0;
     Scalars* sc = nullptr;
     Scalars* hsc = nullptr;  // pinned mirror
@@ -207,7 +209,8 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
         (void)hipEventRecord(P.ev[2 * slot], st);
     }
     k_line<T, MODE, DOT><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc, T(1),
-                                                    c->part, nb_prev, c->sc, slot >= 0 ? P.ran + slot : nullptr);
+                                                    DOT ? c->part_rz : c->part, nb_prev, c->sc,
+                                                    slot >= 0 ? P.ran + slot : nullptr);
     if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
 }
@@ -238,7 +241,7 @@ int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, c
     const size_t lds = band_lds_bytes<T>(v.nx, R, WRITE_BT);
     int* ran = slot >= 0 ? P.ran + slot : nullptr;
     k_band<T, kLineMaxL, MODE, FIRST, OUT_T, WRITE_BT, DOT><<<grid, kBandWG, lds, st>>>(
-        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, c->part, c->sc, ran);
+        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, DOT ? c->part_rz : c->part, c->sc, ran);
     if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
 }
@@ -303,7 +306,8 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
     } else {
         LevelT<T>& cl = in.lv[L - 1];
-        k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+        k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, nullptr,
+                                                                 c->sc);
     }
     for (int l = Ld - 1; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
@@ -316,9 +320,8 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
             launch_band<T, LINE_PROLONG, 1, true, false, false>(c, vq, a.Rq, a.bQ, xpre[l], nxt.xP, cv.nx, a.xPT,
                                                                 nullptr, st);
             if (l == 0) {
-                const int nb = launch_band<T, LINE_NORMAL, 1, false, false, true>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0,
-                                                                                  a.xP, nullptr, st);
-                k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, nb, c->sc);
+                c->nrz = launch_band<T, LINE_NORMAL, 1, false, false, true>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0,
+                                                                            a.xP, nullptr, st);
             } else {
                 launch_band<T, LINE_NORMAL, 1, false, false, false>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0, a.xP,
                                                                     nullptr, st);
@@ -332,7 +335,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
             // the last two sweeps of level 0 also accumulate r.z for CG
             const int nb1 = launch_line<T, LINE_NORMAL, 1>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
             const int nb2 = launch_line<T, LINE_NORMAL, 1>(c, vp, 0, a.bP, a.xP, nullptr, 0, nb1, st);
-            k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, nb1 + nb2, c->sc);
+            c->nrz = nb1 + nb2;
         } else {
             launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
             launch_line<T, LINE_NORMAL, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
@@ -351,15 +354,16 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                                                                   b.ny, c->sc);
     }
     LevelT<T>& cl = in.lv[L - 1];
-    k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, c->sc);
+    k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, nullptr,
+                                                                 c->sc);
     for (int l = L - 2; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
         if (l == 0) {
             const dim3 g = tile_grid(a.nx, a.ny);
             k_post_point<T, true><<<g, blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ, b.xP, b.nx, omega,
-                                                         a.xP, c->part, c->sc);
-            k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part, (int)(g.x * g.y), c->sc);
+                                                         a.xP, c->part_rz, c->sc);
+            c->nrz = (int)(g.x * g.y);
         } else
             k_post_point<T, false><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ,
                                                                               b.xP, b.nx, omega, a.xP, c->part, c->sc);
@@ -370,7 +374,9 @@ template <typename T>
 void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     if (in.lv.size() == 1) {
         LevelT<T>& l0 = in.lv[0];
-        k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->sc);
+        k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->part_rz,
+                                                                    c->sc);
+        c->nrz = 1;
         return;
     }
     if (is_line(c->opt)) enqueue_vcycle_line<T>(c, in, st);
@@ -399,8 +405,8 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     LevelT<T>& l0 = in.lv[0];
     const dim3 tg = tile_grid(nx, ny);
     const int ntiles = (int)(tg.x * tg.y), nb1 = grid1d(n);
-    k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part,
-                                      c->sc);
+    k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part_rz,
+                                      c->nrz, c->part, c->sc);
     // alpha: summed inside k_update from the SpMV partials when they are few,
     // by one reduction workgroup otherwise
     const bool fold = ntiles <= 1024;
@@ -927,6 +933,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ctx->npart = std::max<size_t>(tiles * 5, (size_t)k1DBlocksMax);
     ALLOC(ctx->part, ctx->npart);
     ALLOC(ctx->part2, (size_t)k1DBlocksMax);
+    ALLOC(ctx->part_rz, ctx->npart);
     ALLOC(ctx->sc, 1);
     ALLOC(ctx->err_flag, 1);
     ALLOC(ctx->mu, 1);

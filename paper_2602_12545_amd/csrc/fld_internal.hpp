@@ -39,6 +39,7 @@ struct BCDev {
 // Device-resident solver state of one solve (one context).
 struct Scalars {
     double rz_old;      // r.z of the previous iteration (scaled to the current residual scale)
+    double rz_cur;      // r.z of this iteration (summed by k_spmv from the last sweep's partials)
     double alpha, beta;
     double pscale;      // factor applied to p at the next p-update (residual rescaling)
     double rr;          // inner residual norm^2 (recurrence)

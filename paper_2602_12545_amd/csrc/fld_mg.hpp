@@ -226,25 +226,14 @@ __global__ __launch_bounds__(kCoarseMax) void k_coarse_setup(int nx, int ny, int
     }
 }
 
-// rz finalisation shared by the kernels that end a V-cycle on level 0:
-// beta = rz / rz_old (CG), or breakdown.
-__device__ inline void finish_rz(Scalars* sc, double rz) {
-    if (!(rz > 0.0) || !isfinite(rz)) {
-        sc->status = ST_EBREAKDOWN;
-        sc->done = 1;
-    } else {
-        sc->beta = sc->iter > 0 ? rz / sc->rz_old : 0.0;
-        sc->rz_old = rz;
-    }
-}
-
 // Coarsest level: x = A^-1 b with the dense inverse, four lanes per row.
-// With DOT (a one-level hierarchy) it also finalises r.z.
+// With DOT (a one-level hierarchy) it also stores r.z as the single partial
+// part_rz[0] (k_spmv sums the partials).
 constexpr int kCoarseSolveThreads = 4 * kCoarseMax;
 template <typename T, bool DOT>
 __global__ __launch_bounds__(kCoarseSolveThreads) void k_coarse_solve(int n, const T* __restrict__ Ainv,
                                                                       const T* __restrict__ b, T* __restrict__ x,
-                                                                      Scalars* sc) {
+                                                                      double* part_rz, Scalars* sc) {
     if (sc->done) return;
     __shared__ T sb[kCoarseMax];
     __shared__ double sh[16];
@@ -265,7 +254,7 @@ __global__ __launch_bounds__(kCoarseSolveThreads) void k_coarse_solve(int n, con
     }
     if (DOT) {
         const double rz = block_sum(acc, sh);
-        if (t == 0) finish_rz(sc, rz);
+        if (t == 0) part_rz[0] = rz;
     }
 }
 
@@ -439,7 +428,7 @@ enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 // neighbour chunk's first row gives one tridiagonal equation per chunk in the
 // X's, solved by cyclic reduction (seg_tridiag); back-substitution finishes.
 // DOT: partial r.z over the solved rows, stored at part[nb_prev + block]
-// (level 0; k_reduce_rz finishes the sum).
+// (level 0; k_spmv sums the partials).
 template <typename T, int MODE, int DOT>
 __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, int par, const T* __restrict__ m,
                                                   const T* __restrict__ We, const T* __restrict__ Wn,
@@ -650,31 +639,73 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
 // CG kernels
 // ---------------------------------------------------------------------------
 
+// r.z from the partials of the sweep that produced z, beta = r.z / r.z_old;
 // p = z + beta * pscale * p_in (p = z on the first iteration or after a
 // restart), q = M p in flux form, partial p.q per workgroup (summed by
 // k_update).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
                                               T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
-                                              const T* __restrict__ We, const T* __restrict__ Wn, double* part,
+                                              const T* __restrict__ We, const T* __restrict__ Wn,
+                                              const double* __restrict__ part_rz, int nrz, double* part,
                                               Scalars* sc) {
     if (sc->done) return;
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
+    constexpr int NU = (N + kThreads - 1) / kThreads;
     __shared__ T sp[N], swe[N], swn[N];
     __shared__ double sh[16];
-    const bool first = sc->iter == 0 || sc->restart;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && ltid() == 0) sc->apply = 0;  // read by no other kernel of this slot before
-    const T beta = first ? T(0) : (T)(sc->beta * sc->pscale);
+    __shared__ double s_rz;
     int tbx, tby;
     xcd_tile(tbx, tby);
     const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
-    for (int k = t; k < N; k += kThreads) {
+    // the tile's loads first; their latency overlaps the r.z sum below
+    T zv[NU], pinv[NU], wev[NU], wnv[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = t + u * kThreads;
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
-        const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
+        const bool in = k < N && (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
         const size_t c = (size_t)j * nx + i;
-        sp[k] = in ? (first ? z[c] : z[c] + beta * pin[c]) : T(0);
-        swe[k] = in ? We[c] : T(0);
-        swn[k] = in ? Wn[c] : T(0);
+        zv[u] = in ? z[c] : T(0);
+        pinv[u] = in ? pin[c] : T(0);
+        wev[u] = in ? We[c] : T(0);
+        wnv[u] = in ? Wn[c] : T(0);
+    }
+    // r.z of the new preconditioned residual from the partials of the sweep
+    // that produced z (every workgroup sums them in the same order, so all
+    // agree; workgroup 0 records it), beta = r.z / r.z_old
+    {
+        double v = 0.0;
+        for (int b2 = t; b2 < nrz; b2 += kThreads) v += part_rz[b2];
+        const double tot = block_sum(v, sh);
+        if (t == 0) s_rz = tot;
+        __syncthreads();
+    }
+    const double rz = s_rz;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+            sc->status = ST_EBREAKDOWN;
+            sc->done = 1;
+        }
+        return;
+    }
+    const int iter = sc->iter;
+    const bool first = iter == 0 || sc->restart;
+    const double beta64 = iter > 0 ? rz / sc->rz_old : 0.0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+        sc->rz_cur = rz;
+        sc->beta = beta64;
+        sc->apply = 0;  // read by no other kernel of this slot before
+    }
+    const T beta = first ? T(0) : (T)(beta64 * sc->pscale);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = t + u * kThreads;
+        if (k < N) {
+            sp[k] = first ? zv[u] : zv[u] + beta * pinv[u];
+            swe[k] = wev[u];
+            swn[k] = wnv[u];
+        }
     }
     __syncthreads();
     double acc = 0.0;
@@ -725,14 +756,15 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
                 sc->done = 1;
                 sc->pending = 1;
             } else {
-                sc->alpha = sc->rz_old / pq;
+                sc->alpha = sc->rz_cur / pq;
             }
+            sc->rz_old = sc->rz_cur;
             sc->pscale = 1.0;
             sc->restart = 0;
             sc->demote = 0;
         }
         if (bad) return;
-        a = (T)(sc->rz_old / pq);
+        a = (T)(sc->rz_cur / pq);
     } else {
         a = (T)sc->alpha;
     }
@@ -862,8 +894,9 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, i
             sc->done = 1;
             sc->pending = 1;
         } else {
-            sc->alpha = sc->rz_old / pq;
+            sc->alpha = sc->rz_cur / pq;
         }
+        sc->rz_old = sc->rz_cur;
         sc->pscale = 1.0;
         sc->restart = 0;
         sc->demote = 0;
@@ -896,15 +929,6 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_rr(const double* part, i
     }
 }
 
-// beta = r.z / r.z_old (level-0 end of the V-cycle)
-__global__ __launch_bounds__(kRedThreads) void k_reduce_rz(const double* part, int nb, Scalars* sc) {
-    if (sc->done) return;
-    __shared__ double sh[16];
-    const double rz = reduce_sum(part, nb, 1, 0, sh);
-    if (threadIdx.x == 0) finish_rz(sc, rz);
-}
-
-// norms of the true residual, convergence / stagnation decision, new scale
 __global__ __launch_bounds__(kRedThreads) void k_reduce_resid(const double* part, int nb, const double* mu,
                                                               Scalars* sc, int force) {
     if (!force && (sc->done || !sc->pending)) return;
@@ -1005,7 +1029,7 @@ __global__ void k_noop(int* ran) {
 __global__ void k_init_scalars(Scalars* sc, double eps, double delta2, double inner_tol2, int max_iter, int norm,
                                int reliable) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    sc->rz_old = 0.0;
+    sc->rz_old = sc->rz_cur = 0.0;
     sc->alpha = sc->beta = 0.0;
     sc->pscale = 1.0;
     sc->rr = 0.0;

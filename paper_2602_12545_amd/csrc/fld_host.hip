@@ -146,6 +146,9 @@ inline int grid1d(size_t n) {
     size_t b = (n + 255) / 256;
     return (int)(b < (size_t)k1DBlocksMax ? (b ? b : 1) : (size_t)k1DBlocksMax);
 }
+// k_update's grid: few enough r.r partials for every k_resid64 workgroup to
+// sum them itself
+inline int update_grid(size_t n) { return std::min(grid1d(n), 512); }
 
 bool inner_is_float(const fld_ctx* c) { return c->opt.precision != FLD_FP64; }
 
@@ -391,8 +394,8 @@ template <typename T>
 void enqueue_check(fld_ctx* c, Inner<T>& in, double* E, int force, hipStream_t st) {
     const int nx = c->nx, ny = c->ny, n = nx * ny;
     const dim3 tg = tile_grid(nx, ny);
-    k_resid64<T><<<tg, blk2d(), 0, st>>>(c->met, E, in.x, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part, c->sc,
-                                         force);
+    k_resid64<T><<<tg, blk2d(), 0, st>>>(c->met, E, in.x, c->We, c->Wn, c->m, c->rhs, c->s, c->r64, c->part,
+                                         c->part2, update_grid(n), c->sc, force);
     k_reduce_resid<<<1, kRedThreads, 0, st>>>(c->part, (int)(tg.x * tg.y), c->mu, c->sc, force);
     k_apply<T><<<grid1d(n), 256, 0, st>>>(n, E, c->r64, in.r, in.x, c->sc);
 }
@@ -404,7 +407,7 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     const int nx = c->nx, ny = c->ny, n = nx * ny;
     LevelT<T>& l0 = in.lv[0];
     const dim3 tg = tile_grid(nx, ny);
-    const int ntiles = (int)(tg.x * tg.y), nb1 = grid1d(n);
+    const int ntiles = (int)(tg.x * tg.y), nb1 = update_grid(n);
     k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part_rz,
                                       c->nrz, c->part, c->sc);
     // alpha: summed inside k_update from the SpMV partials when they are few,
@@ -413,7 +416,6 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     if (!fold) k_reduce_pq<<<1, kRedThreads, 0, st>>>(c->part, ntiles, c->sc);
     k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, fold ? ntiles : 0, c->part2,
                                      c->sc);
-    k_reduce_rr<<<1, kRedThreads, 0, st>>>(c->part2, nb1, c->sc);
     enqueue_check<T>(c, in, E, 0, st);
     enqueue_vcycle<T>(c, in, st);
 }

@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
 // npq = 0, alpha as k_reduce_pq left it (grids with many partials, where
 // every workgroup re-reading them costs more than a launch) -- then
 // x += alpha p, r -= alpha q and a partial r.r per workgroup into part_rr
-// (k_reduce_rr).
+// (summed by k_resid64); workgroup 0 counts the iteration.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                 const T* __restrict__ q, const double* __restrict__ part_pq,
@@ -757,6 +757,7 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
                 sc->pending = 1;
             } else {
                 sc->alpha = sc->rz_cur / pq;
+                sc->iter += 1;
             }
             sc->rz_old = sc->rz_cur;
             sc->pscale = 1.0;
@@ -767,6 +768,7 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
         a = (T)(sc->rz_cur / pq);
     } else {
         a = (T)sc->alpha;
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->iter += 1;
     }
     double acc = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -805,17 +807,47 @@ __global__ __launch_bounds__(256) void k_resid64(Metrics g, const double* __rest
                                                  const double* __restrict__ We, const double* __restrict__ Wn,
                                                  const double* __restrict__ m, const double* __restrict__ rhs,
                                                  const double* __restrict__ s, double* __restrict__ r64, double* part,
-                                                 const Scalars* sc, int force) {
-    if (!force && (sc->done || !sc->pending)) return;
-    const double corr = force ? 0.0 : sc->corr;
+                                                 const double* __restrict__ part_rr, int nrr, Scalars* sc,
+                                                 int force) {
+    if (!force && sc->done) return;
     const int nx = g.nx, ny = g.ny;
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
     constexpr int NS = 5;
     __shared__ double sE[N], sWe[N], sWn[N];
     __shared__ double sh[16];
+    __shared__ double s_rr;
     int tbx, tby;
     xcd_tile(tbx, tby);
     const int i0 = tbx * TBX, j0 = tby * TRows, t = ltid();
+    if (!force) {
+        // recurrence residual r.r from k_update's partials (every workgroup
+        // sums them in the same order and takes the same decision; workgroup
+        // 0 records it): a reliable update is due when r.r fell by delta since
+        // the last one, or predicts the target is met, or at the iteration
+        // limit
+        double v = 0.0;
+        for (int b2 = t; b2 < nrr; b2 += kThreads) v += part_rr[b2];
+        const double tot = block_sum(v, sh);
+        if (t == 0) s_rr = tot;
+        __syncthreads();
+        const double rr = s_rr;
+        bool check;
+        if (sc->reliable) {
+            const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
+            check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
+        } else {
+            check = rr <= sc->inner_tol2;
+        }
+        const bool bad = !isfinite(rr);
+        if (bad || sc->iter >= sc->max_iter || sc->pending) check = true;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+            sc->rr = rr;
+            if (bad) sc->status = ST_EBREAKDOWN;
+            if (check) sc->pending = 1;
+        }
+        if (!check) return;
+    }
+    const double corr = force ? 0.0 : sc->corr;
     for (int k = t; k < N; k += kThreads) {
         const int lx = k % LX, ly = k / LX, i = i0 + lx - H, j = j0 + ly - H;
         const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny;
@@ -900,32 +932,6 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, i
         sc->pscale = 1.0;
         sc->restart = 0;
         sc->demote = 0;
-    }
-}
-
-// count the iteration; decide whether a reliable update (true FP64 residual)
-// is due: the recurrence residual fell by delta since the last one, or it
-// predicts the target is met
-__global__ __launch_bounds__(kRedThreads) void k_reduce_rr(const double* part, int nb, Scalars* sc) {
-    if (sc->done) return;
-    __shared__ double sh[16];
-    const double rr = reduce_sum(part, nb, 1, 0, sh);
-    if (threadIdx.x == 0) {
-        sc->rr = rr;
-        sc->iter += 1;
-        bool check;
-        if (sc->reliable) {
-            const double est = sc->rho_last * sqrt(rr / sc->rr_ref);
-            check = rr < sc->delta2 * sc->rr_ref || est <= sc->eps;
-        } else {
-            check = rr <= sc->inner_tol2;
-        }
-        if (!isfinite(rr)) {
-            sc->status = ST_EBREAKDOWN;
-            check = true;
-        }
-        if (sc->iter >= sc->max_iter) check = true;
-        if (check) sc->pending = 1;
     }
 }
 

@@ -231,6 +231,20 @@ fld_status fld_profile_read(fld_ctx* ctx, int64_t* launches, double* total_ms, d
  * kernel on the context's stream, over `reps` launches: the timing cost that
  * every event-bracketed launch above carries. */
 fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launch);
+/* Replay measurement of the same kernel family without per-launch events:
+ * the line-sweep launches of one V-cycle (every grid level, in V-cycle order,
+ * on the current operator; the LDS sub-cycle, restrictions and transposes
+ * left out) are captured once as a hipGraph on a private solver state that
+ * never reports convergence, then replayed `reps` times on the context's
+ * stream between two HIP events.  Returns the mean time per launch (us, the
+ * replay's elapsed time over reps x launches), the same for a graph of as
+ * many empty one-wave launches (floor_us: what each dependent launch costs
+ * by itself), the mean algorithmic bytes per launch and the number of
+ * launches per V-cycle.  Needs fld_assemble and a line smoother (EINVAL
+ * otherwise, ENOTREADY before assembly).  The multigrid work vectors are
+ * overwritten (the next solve starts afresh). */
+fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch, double* floor_us,
+                              double* bytes_per_launch, int32_t* launches);
 
 const char* fld_status_string(fld_status s);
 const char* fld_last_error(const fld_ctx* ctx);

@@ -101,6 +101,12 @@ struct fld_ctx {
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
     double* part_rz = nullptr;  // r.z partials of the V-cycle's last sweep (summed by k_spmv)
+    // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
+    // enqueue_vcycle queues only the line-sweep launches and counts them
+    bool sweeps_only = false;
+    int sweep_launches = 0;
+    double sweep_bytes = 0.0;
+    Scalars* sc_sweep = nullptr;  // solver state of the replay (never done)
     int nrz = 0;                // their number (set when the V-cycle is queued)
     size_t npart = 0;
     Scalars* sc = nullptr;
@@ -200,14 +206,18 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
     const int grid = (nl + lpw - 1) / lpw;
     auto& P = c->prof;
     int slot = -1;
+    // algorithmic bytes: solved rows read m, W_e, b and write x; W_n of every
+    // row; x of the neighbour rows unless zero; the coarse correction (1/4)
+    const double n = (double)v.nx * v.ny, half = (double)nl * v.nx;
+    double words = 4.0 * half + n;
+    if (MODE != LINE_ZERO) words += n - half;
+    if (MODE == LINE_PROLONG) words += 0.25 * n;
+    if (c->sweeps_only) {
+        ++c->sweep_launches;
+        c->sweep_bytes += words * sizeof(T);
+    }
     if (P.on && P.used < P.slots) {
         slot = P.used++;
-        // algorithmic bytes: solved rows read m, W_e, b and write x; W_n of every
-        // row; x of the neighbour rows unless zero; the coarse correction (1/4)
-        const double n = (double)v.nx * v.ny, half = (double)nl * v.nx;
-        double words = 4.0 * half + n;
-        if (MODE != LINE_ZERO) words += n - half;
-        if (MODE == LINE_PROLONG) words += 0.25 * n;
         P.bytes[slot] = words * sizeof(T);
         (void)hipEventRecord(P.ev[2 * slot], st);
     }
@@ -228,16 +238,20 @@ int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, c
     const int grid = (v.ny + R - 1) / R;
     auto& P = c->prof;
     int slot = -1;
+    // algorithmic bytes: m, W_e, W_n, b of every row and x written once; the
+    // old x of the rows solved second (read by the rows solved first) unless
+    // zero; the coarse correction; b written transposed
+    const double n = (double)v.nx * v.ny;
+    double words = 5.0 * n;
+    if (MODE != LINE_ZERO) words += 0.5 * n;
+    if (MODE == LINE_PROLONG) words += 0.25 * n;
+    if (WRITE_BT) words += n;
+    if (c->sweeps_only) {
+        ++c->sweep_launches;
+        c->sweep_bytes += words * sizeof(T);
+    }
     if (P.on && P.used < P.slots) {
         slot = P.used++;
-        // algorithmic bytes: m, W_e, W_n, b of every row and x written once; the
-        // old x of the rows solved second (read by the rows solved first) unless
-        // zero; the coarse correction; b written transposed
-        const double n = (double)v.nx * v.ny;
-        double words = 5.0 * n;
-        if (MODE != LINE_ZERO) words += 0.5 * n;
-        if (MODE == LINE_PROLONG) words += 0.25 * n;
-        if (WRITE_BT) words += n;
         P.bytes[slot] = words * sizeof(T);
         (void)hipEventRecord(P.ev[2 * slot], st);
     }
@@ -295,16 +309,19 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         } else {
             launch_line<T, LINE_ZERO, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
             launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
-            launch_transpose<T>(vp.nx, vp.ny, a.xP, a.bP, a.xQ, a.bQ, c->sc, st);
+            if (!c->sweeps_only) launch_transpose<T>(vp.nx, vp.ny, a.xP, a.bP, a.xQ, a.bQ, c->sc, st);
             launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
             launch_line<T, LINE_NORMAL, 0>(c, vq, 1, a.bQ, a.xQ, nullptr, 0, 0, st);
             xpre[l] = a.xQ;
         }
         const View<T> cv = nxt.view(nxt.tr);
-        k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ,
+        if (!c->sweeps_only)
+            k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ,
                                                                           xpre[l], nxt.bP, cv.nx, cv.ny, c->sc);
     }
-    if (in.sub_first > 0) {
+    if (c->sweeps_only) {
+        // line sweeps only (replay measurement)
+    } else if (in.sub_first > 0) {
         LevelT<T>& f = in.lv[in.sub_first];
         k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
     } else {
@@ -333,7 +350,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         }
         launch_line<T, LINE_PROLONG, 0>(c, vq, 1, a.bQ, a.xQ, nxt.xP, cv.nx, 0, st);
         launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
-        launch_transpose<T>(vq.nx, vq.ny, a.xQ, nullptr, a.xP, nullptr, c->sc, st);
+        if (!c->sweeps_only) launch_transpose<T>(vq.nx, vq.ny, a.xQ, nullptr, a.xP, nullptr, c->sc, st);
         if (l == 0) {
             // the last two sweeps of level 0 also accumulate r.z for CG
             const int nb1 = launch_line<T, LINE_NORMAL, 1>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
@@ -376,6 +393,7 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
 template <typename T>
 void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     if (in.lv.size() == 1) {
+        if (c->sweeps_only) return;
         LevelT<T>& l0 = in.lv[0];
         k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->part_rz,
                                                                     c->sc);
@@ -828,6 +846,99 @@ fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launc
     return FLD_OK;
 }
 
+fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch, double* floor_us,
+                              double* bytes_per_launch, int32_t* launches) {
+    if (!ctx || reps < 1 || !us_per_launch || !floor_us || !bytes_per_launch || !launches) return FLD_EINVAL;
+    if (!ctx->assembled) {
+        ctx->err = "fld_profile_sweeps before fld_assemble";
+        return FLD_ENOTREADY;
+    }
+    if (!is_line(ctx->opt)) {
+        ctx->err = "fld_profile_sweeps needs a line smoother";
+        return FLD_EINVAL;
+    }
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // a solver state that is never done, so every sweep works
+    k_init_scalars<<<1, 1, 0, ctx->stream>>>(ctx->sc_sweep, 1e-300, 0.0, 0.0, 1, 0, 1);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    Scalars* keep = ctx->sc;
+    const bool prof_on = ctx->prof.on;
+    ctx->sc = ctx->sc_sweep;
+    ctx->prof.on = false;
+    ctx->sweeps_only = true;
+    ctx->sweep_launches = 0;
+    ctx->sweep_bytes = 0.0;
+    const int nrz_keep = ctx->nrz;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (inner_is_float(ctx)) enqueue_vcycle<float>(ctx, ctx->i32, ctx->cap_stream);
+        else enqueue_vcycle<double>(ctx, ctx->i64, ctx->cap_stream);
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+    }
+    ctx->sc = keep;
+    ctx->prof.on = prof_on;
+    ctx->sweeps_only = false;
+    ctx->nrz = nrz_keep;
+    if (e != hipSuccess) {
+        ctx->err = std::string("sweep capture: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ctx->err = std::string("sweep graph: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    const int nl = ctx->sweep_launches;
+    // the same number of empty launches, captured and replayed alike: the
+    // graph's cost per dependent launch
+    hipGraphExec_t ge0 = nullptr;
+    e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < nl; ++k) k_noop<<<1, 64, 0, ctx->cap_stream>>>(nullptr);
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+    }
+    if (e == hipSuccess) {
+        e = hipGraphInstantiate(&ge0, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ge);
+        ctx->err = std::string("empty-launch graph: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    auto replay = [&](hipGraphExec_t x, float* ms) -> hipError_t {
+        hipError_t r = hipGraphLaunch(x, ctx->stream);  // warm-up
+        if (r == hipSuccess) r = hipEventRecord(a, ctx->stream);
+        for (int k = 0; k < reps && r == hipSuccess; ++k) r = hipGraphLaunch(x, ctx->stream);
+        if (r == hipSuccess) r = hipEventRecord(b, ctx->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(b);
+        if (r == hipSuccess) r = hipEventElapsedTime(ms, a, b);
+        return r;
+    };
+    float ms = 0.f, ms0 = 0.f;
+    e = replay(ge, &ms);
+    if (e == hipSuccess) e = replay(ge0, &ms0);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipGraphExecDestroy(ge);
+    (void)hipGraphExecDestroy(ge0);
+    if (e != hipSuccess) {
+        ctx->err = std::string("sweep replay: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    *launches = nl;
+    *us_per_launch = nl > 0 ? 1e3 * ms / ((double)reps * nl) : 0.0;
+    *floor_us = nl > 0 ? 1e3 * ms0 / ((double)reps * nl) : 0.0;
+    *bytes_per_launch = nl > 0 ? ctx->sweep_bytes / nl : 0.0;
+    return FLD_OK;
+}
+
 fld_status fld_profile_read(fld_ctx* ctx, int64_t* launches, double* total_ms, double* bytes) {
     if (!ctx) return FLD_EINVAL;
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -937,6 +1048,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->part2, (size_t)k1DBlocksMax);
     ALLOC(ctx->part_rz, ctx->npart);
     ALLOC(ctx->sc, 1);
+    ALLOC(ctx->sc_sweep, 1);
     ALLOC(ctx->err_flag, 1);
     ALLOC(ctx->mu, 1);
 #undef ALLOC

@@ -770,12 +770,33 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
         a = (T)sc->alpha;
         if (blockIdx.x == 0 && threadIdx.x == 0) sc->iter += 1;
     }
+    // U cells per thread and round, loads first (few workgroups: the
+    // memory-level parallelism comes from the unrolling; binary64 measured
+    // best without it)
+    constexpr int U = sizeof(T) == 4 ? 4 : 1;
     double acc = 0.0;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        x[c] += a * p[c];
-        const T rn = r[c] - a * q[c];
-        r[c] = rn;
-        acc += (double)rn * (double)rn;
+    const int stride = gridDim.x * blockDim.x;
+    for (int c0 = blockIdx.x * blockDim.x + threadIdx.x; c0 < n; c0 += U * stride) {
+        T xv[U], pv[U], rv[U], qv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u * stride;
+            const bool ok = c < n;
+            xv[u] = ok ? x[c] : T(0);
+            pv[u] = ok ? p[c] : T(0);
+            rv[u] = ok ? r[c] : T(0);
+            qv[u] = ok ? q[c] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u * stride;
+            if (c < n) {
+                x[c] = xv[u] + a * pv[u];
+                const T rn = rv[u] - a * qv[u];
+                r[c] = rn;
+                acc += (double)rn * (double)rn;
+            }
+        }
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;

@@ -100,3 +100,30 @@ def test_steps_budget_exhausted_is_reported(lib):
     prob = W.make("c2", nx=48, ny=48)
     _, _, infos = _run(fld, torch, prob, 3, multi=True, max_inner=2)
     assert infos[0]["status"] == 4
+
+
+def test_sweep_replay_measurement(lib):
+    """fld_profile_sweeps replays one V-cycle's line sweeps as a graph: it
+    needs an assembled context, counts every grid level's band launches (four
+    per level, levels above the LDS sub-cycle), reports positive times and
+    bytes, and leaves the next step equal to a step of a fresh context."""
+    fld = lib
+    prob = W.make("c2", nx=256, ny=256)
+    opt = dict(precision="mixed", norm=1, rel_tol=1e-11)
+    ctx = make_ctx(fld, prob, **opt)
+    with pytest.raises(fld.FLDError):
+        ctx.profile_sweeps(2)
+    t = to_dev(prob, torch)
+    args = (t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"])
+    ctx.step(t["E"], t["T"], *args, check=False)
+    r = ctx.profile_sweeps(5)
+    # 256^2 -> sub-cycle from 64^2: levels 256 and 128 on the grid, 4 band launches each
+    assert r["launches"] == 8
+    assert r["us_per_launch"] > 0.0 and r["bytes_per_launch"] > 0.0
+    t2 = to_dev(prob, torch)
+    info = ctx.step(t2["E"], t2["T"], *args, check=False)
+    torch.cuda.synchronize()
+    ctx.close()
+    E_ref, T_ref, i_ref = _run(fld, torch, prob, 1, multi=False, **opt)
+    assert info["status"] == 0 and info["inner_iters"] == i_ref[0]["inner_iters"]
+    assert np.array_equal(t2["E"].cpu().numpy(), E_ref) and np.array_equal(t2["T"].cpu().numpy(), T_ref)

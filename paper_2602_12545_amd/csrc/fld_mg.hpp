@@ -443,7 +443,9 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
     const int t = threadIdx.x;
     const int lpw = kLineWG / K;
     const int k = t % K;
-    const int row = 2 * (int)(xcd_block(blockIdx.x, gridDim.x) * lpw + t / K) + par;
+    // (plain workgroup order: the XCD-aware order measured 1.7 % slower on
+    // the 4096-cell rows of the spherical stress grid)
+    const int row = 2 * (int)(blockIdx.x * lpw + t / K) + par;
     const bool active = row < ny;
     const int s0 = k * L;
     const size_t rbase = (size_t)(active ? row : 0) * nx;

@@ -103,6 +103,9 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     // thread of the workgroup calls it (the LDS reduction has barriers).
     auto solve_row = [&](int row, bool active, const Coef* pre, auto pre_tag, int PH) {
         constexpr bool PRE = decltype(pre_tag)::value;
+        // PRE rows split into whole LM-cell chunks: the chunk bounds are
+        // compile-time constants there
+        const int Lc = PRE ? LM : L;
         // a wavefront whose rows are all idle skips the solve and leaves its
         // SIMD to the busy ones; with rows spanning wavefronts it still passes
         // the same barriers (the exchange, seg_tridiag's on identity rows,
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
                 for (int q = 0; q < LM; ++q) {
                     const int g = s0 + q;
-                    const bool ok = active && q < L && g < nx;
+                    const bool ok = active && (PRE || (q < Lc && g < nx));
                     const size_t c = rb + g;
                     vm[q] = ok ? m[c] : T(1);
                     vwe[q] = ok ? We[c] : T(0);
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
         for (int q = 0; q < LM; ++q) {
             const int g = s0 + q;
-            const bool ok = active && q < L && g < nx;
+            const bool ok = active && (PRE || (q < Lc && g < nx));
             T xn = T(0), xs = T(0);
             if (ok) {
                 if (PH == 2) {
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         if (WRITE_BT && active && row >= r0 && row < rend) {
 #pragma unroll
             for (int q = 0; q < LM; ++q)
-                if (q < L && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+                if (PRE || (q < Lc && s0 + q < nx)) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
         }
         // diagonal and right-hand side of every chunk row (the loaded
         // arrays die here, which keeps register pressure low)
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         T cp[LM], gy[LM], gu[LM], gv[LM];
 #pragma unroll
         for (int q = 0; q < LM - 1; ++q) {
-            if (q < L - 1) {
+            if (q < Lc - 1) {
                 T a, d, c, r;
                 coef(q, a, d, c, r);
                 const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
@@ -217,13 +220,13 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 cp[q] = c * inv;
                 gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
                 gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
-                const T rv = (q == L - 2) ? -c : T(0);
+                const T rv = (q == Lc - 2) ? -c : T(0);
                 gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
             }
         }
 #pragma unroll
         for (int q = LM - 3; q >= 0; --q) {
-            if (q < L - 2) {
+            if (q < Lc - 2) {
                 gy[q] -= cp[q] * gy[q + 1];
                 gu[q] -= cp[q] * gu[q + 1];
                 gv[q] -= cp[q] * gv[q + 1];
@@ -232,11 +235,11 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
 #pragma unroll
         for (int q = 0; q < LM; ++q)
-            if (q == L - 1) coef(q, aE, dE, cE, rE);
+            if (q == Lc - 1) coef(q, aE, dE, cE, rE);
         T yl = T(0), ul = T(0), vl = T(0);
 #pragma unroll
         for (int q = 0; q < LM - 1; ++q)
-            if (q == L - 2) {
+            if (q == Lc - 2) {
                 yl = gy[q];
                 ul = gu[q];
                 vl = gv[q];
@@ -290,8 +293,8 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                if (q < L && g < nx) {
-                    const T v = (q == L - 1) ? X
+                if (PRE || (q < Lc && g < nx)) {
+                    const T v = (q == Lc - 1) ? X
                                              : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
                                                    gv[q < LM - 1 ? q : 0] * X;
                     dst[g] = v;

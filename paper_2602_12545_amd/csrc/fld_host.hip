@@ -221,9 +221,14 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
         P.bytes[slot] = words * sizeof(T);
         (void)hipEventRecord(P.ev[2 * slot], st);
     }
-    k_line<T, MODE, DOT><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc, T(1),
-                                                    DOT ? c->part_rz : c->part, nb_prev, c->sc,
-                                                    slot >= 0 ? P.ran + slot : nullptr);
+    if (L == kLineMaxL && K * kLineMaxL == v.nx)
+        k_line<T, MODE, DOT, true><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc,
+                                                              T(1), DOT ? c->part_rz : c->part, nb_prev, c->sc,
+                                                              slot >= 0 ? P.ran + slot : nullptr);
+    else
+        k_line<T, MODE, DOT, false><<<grid, kLineWG, 0, st>>>(v.nx, v.ny, K, L, par, v.m, v.We, v.Wn, b, x, ec, nxc,
+                                                               T(1), DOT ? c->part_rz : c->part, nb_prev, c->sc,
+                                                               slot >= 0 ? P.ran + slot : nullptr);
     if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
 }

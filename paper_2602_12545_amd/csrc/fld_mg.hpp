@@ -429,7 +429,7 @@ enum { LINE_NORMAL = 0, LINE_ZERO = 1, LINE_PROLONG = 2 };
 // X's, solved by cyclic reduction (seg_tridiag); back-substitution finishes.
 // DOT: partial r.z over the solved rows, stored at part[nb_prev + block]
 // (level 0; k_spmv sums the partials).
-template <typename T, int MODE, int DOT>
+template <typename T, int MODE, int DOT, bool FULL>
 __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, int par, const T* __restrict__ m,
                                                   const T* __restrict__ We, const T* __restrict__ Wn,
                                                   const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ ec,
@@ -448,6 +448,9 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
     const int row = 2 * (int)(blockIdx.x * lpw + t / K) + par;
     const bool active = row < ny;
     const int s0 = k * L;
+    // FULL: every chunk is exactly kLineMaxL cells inside the row, so the
+    // chunk bounds are compile-time constants
+    const int Lc = FULL ? kLineMaxL : L;
     const size_t rbase = (size_t)(active ? row : 0) * nx;
 
     auto xnb = [&](int rr, int g) -> T {  // value of a neighbour-row cell
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
 #pragma unroll
         for (int q = 0; q < LM; ++q) {
             const int g = s0 + q;
-            const bool ok = active && q < L && g < nx;
+            const bool ok = active && (FULL || (q < Lc && g < nx));
             const size_t cc = rbase + g;
             vm[q] = ok ? m[cc] : T(1);
             vwe[q] = ok ? We[cc] : T(0);
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
     T cp[LM], gy[LM], gu[LM], gv[LM];
 #pragma unroll
     for (int q = 0; q < LM - 1; ++q) {
-        if (q < L - 1) {
+        if (q < Lc - 1) {
             T a, d, c, r;
             coef(q, a, d, c, r);
             const T den = (q == 0) ? d : d - a * cp[q > 0 ? q - 1 : 0];
@@ -521,14 +524,14 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
             cp[q] = c * inv;
             gy[q] = ((q == 0) ? r : r - a * gy[q > 0 ? q - 1 : 0]) * inv;
             gu[q] = ((q == 0) ? -a : -a * gu[q > 0 ? q - 1 : 0]) * inv;
-            const T rv = (q == L - 2) ? -c : T(0);
+            const T rv = (q == Lc - 2) ? -c : T(0);
             gv[q] = ((q == 0) ? rv : rv - a * gv[q > 0 ? q - 1 : 0]) * inv;
         }
     }
     // back substitution: y, u, v overwrite gy, gu, gv
 #pragma unroll
     for (int q = LM - 3; q >= 0; --q) {
-        if (q < L - 2) {
+        if (q < Lc - 2) {
             gy[q] -= cp[q] * gy[q + 1];
             gu[q] -= cp[q] * gu[q + 1];
             gv[q] -= cp[q] * gv[q + 1];
@@ -538,11 +541,11 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
     T aE = T(0), dE = T(1), cE = T(0), rE = T(0);
 #pragma unroll
     for (int q = 0; q < LM; ++q)
-        if (q == L - 1) coef(q, aE, dE, cE, rE);
+        if (q == Lc - 1) coef(q, aE, dE, cE, rE);
     T yl = T(0), ul = T(0), vl = T(0);
 #pragma unroll
     for (int q = 0; q < LM - 1; ++q)
-        if (q == L - 2) {
+        if (q == Lc - 2) {
             yl = gy[q];
             ul = gu[q];
             vl = gv[q];
@@ -575,16 +578,16 @@ __global__ __launch_bounds__(kLineWG) void k_line(int nx, int ny, int K, int L, 
         T out[LM];
 #pragma unroll
         for (int q = 0; q < LM; ++q) {
-            out[q] = (q == L - 1) ? X : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+            out[q] = (q == Lc - 1) ? X : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
                                             gv[q < LM - 1 ? q : 0] * X;
-            if (DOT && q < L && s0 + q < nx) acc += (double)vb[q] * (double)out[q];
+            if (DOT && (FULL || (q < Lc && s0 + q < nx))) acc += (double)vb[q] * (double)out[q];
         }
         if (vec) {
             store_vec<T, LM>(x + rbase + s0, out);
         } else {
 #pragma unroll
             for (int q = 0; q < LM; ++q)
-                if (q < L && s0 + q < nx) x[rbase + s0 + q] = out[q];
+                if (FULL || (q < Lc && s0 + q < nx)) x[rbase + s0 + q] = out[q];
         }
     }
     if (DOT) {

@@ -101,11 +101,12 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     // (neighbours from xin), PH = 2: second parity (neighbours from LDS).
     // The coefficients come from `pre` (PRE) or are loaded here.  Every
     // thread of the workgroup calls it (the LDS reduction has barriers).
-    auto solve_row = [&](int row, bool active, const Coef* pre, auto pre_tag, int PH) {
+    auto solve_row = [&](int row, bool active, const Coef* pre, auto pre_tag, auto full_tag, int PH) {
         constexpr bool PRE = decltype(pre_tag)::value;
-        // PRE rows split into whole LM-cell chunks: the chunk bounds are
-        // compile-time constants there
-        const int Lc = PRE ? LM : L;
+        // FULL (always with PRE): the row splits into whole LM-cell chunks, so
+        // the chunk bounds are compile-time constants
+        constexpr bool FULL = PRE || decltype(full_tag)::value;
+        const int Lc = FULL ? LM : L;
         // a wavefront whose rows are all idle skips the solve and leaves its
         // SIMD to the busy ones; with rows spanning wavefronts it still passes
         // the same barriers (the exchange, seg_tridiag's on identity rows,
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
                 for (int q = 0; q < LM; ++q) {
                     const int g = s0 + q;
-                    const bool ok = active && (PRE || (q < Lc && g < nx));
+                    const bool ok = active && (FULL || (q < Lc && g < nx));
                     const size_t c = rb + g;
                     vm[q] = ok ? m[c] : T(1);
                     vwe[q] = ok ? We[c] : T(0);
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
         for (int q = 0; q < LM; ++q) {
             const int g = s0 + q;
-            const bool ok = active && (PRE || (q < Lc && g < nx));
+            const bool ok = active && (FULL || (q < Lc && g < nx));
             T xn = T(0), xs = T(0);
             if (ok) {
                 if (PH == 2) {
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         if (WRITE_BT && active && row >= r0 && row < rend) {
 #pragma unroll
             for (int q = 0; q < LM; ++q)
-                if (PRE || (q < Lc && s0 + q < nx)) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+                if (FULL || (q < Lc && s0 + q < nx)) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
         }
         // diagonal and right-hand side of every chunk row (the loaded
         // arrays die here, which keeps register pressure low)
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                if (PRE || (q < Lc && g < nx)) {
+                if (FULL || (q < Lc && g < nx)) {
                     const T v = (q == Lc - 1) ? X
                                              : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
                                                    gv[q < LM - 1 ? q : 0] * X;
@@ -305,12 +306,12 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         if (LM == kLineMaxL && !wave_pcr) __syncthreads();  // the LDS reduction arrays are reused next pass
     };
     // `count` rows start, start + 2, ..., lpp rows per pass
-    auto solve_rows = [&](int start, int count, int PH) {
+    auto solve_rows = [&](int start, int count, int PH, auto full_tag) {
         for (int q0 = 0; q0 < count; q0 += lpp) {
             const int ql = q0 + t / K;
             const bool active = ql < count;
             const int row = start + 2 * (active ? ql : 0);
-            solve_row(row, active, nullptr, std::false_type{}, PH);
+            solve_row(row, active, nullptr, std::false_type{}, full_tag, PH);
         }
     };
 
@@ -341,13 +342,19 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         Coef C1, C2;
         if (__any(a1)) load_coef_vec(row1, C1, true);
         if (__any(a2)) load_coef_vec(row2, C2, false);
-        solve_row(row1, a1, &C1, std::true_type{}, 1);
+        solve_row(row1, a1, &C1, std::true_type{}, std::true_type{}, 1);
         __syncthreads();
-        solve_row(row2, a2, &C2, std::true_type{}, 2);
+        solve_row(row2, a2, &C2, std::true_type{}, std::true_type{}, 2);
     } else {
-        solve_rows(s1, n1, 1);
-        __syncthreads();
-        solve_rows(s2, n2, 2);
+        if (L == LM && K * LM == nx) {
+            solve_rows(s1, n1, 1, std::true_type{});
+            __syncthreads();
+            solve_rows(s2, n2, 2, std::true_type{});
+        } else {
+            solve_rows(s1, n1, 1, std::false_type{});
+            __syncthreads();
+            solve_rows(s2, n2, 2, std::false_type{});
+        }
     }
     __syncthreads();
     // band rows out

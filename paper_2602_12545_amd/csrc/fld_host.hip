@@ -89,6 +89,11 @@ struct fld_ctx {
     fld_options opt{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    // the coarsest inverse is built on a side stream, forked after the
+    // hierarchy and joined by the first V-cycle that needs it
+    hipStream_t setup_stream = nullptr;
+    hipEvent_t setup_fork = nullptr, setup_join = nullptr;
+    bool setup_pending = false;
     std::string err;
     std::vector<void*> allocs;
     // metrics
@@ -142,6 +147,19 @@ struct fld_ctx {
         return e;
     }
 };
+
+namespace {
+
+// Makes `st` wait for a coarsest-inverse set-up still running on the side
+// stream (before the inverse is used, or its inputs rewritten).
+inline fld_status join_setup(fld_ctx* ctx, hipStream_t st) {
+    if (!ctx->setup_pending) return FLD_OK;
+    HIPCHK(hipStreamWaitEvent(st, ctx->setup_join, 0));
+    ctx->setup_pending = false;
+    return FLD_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -326,7 +344,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     }
     if (c->sweeps_only) {
         // line sweeps only (replay measurement)
-    } else if (in.sub_first > 0) {
+    } else if ((void)join_setup(c, st), in.sub_first > 0) {
         LevelT<T>& f = in.lv[in.sub_first];
         k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
     } else {
@@ -379,6 +397,7 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                                                                   b.ny, c->sc);
     }
     LevelT<T>& cl = in.lv[L - 1];
+    (void)join_setup(c, st);
     k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, nullptr,
                                                                  c->sc);
     for (int l = L - 2; l >= 0; --l) {
@@ -399,6 +418,7 @@ template <typename T>
 void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     if (in.lv.size() == 1) {
         if (c->sweeps_only) return;
+        (void)join_setup(c, st);
         LevelT<T>& l0 = in.lv[0];
         k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->part_rz,
                                                                     c->sc);
@@ -446,6 +466,7 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
 template <typename T>
 fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     Inner<T>& in = inner<T>(c);
+    if (join_setup(c, st) != FLD_OK) return FLD_EHIP;
     const int L = (int)in.lv.size();
     const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
     const bool line = is_line(c->opt);
@@ -467,16 +488,24 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     }
     Level64& cl = c->h64[L - 1];
     {
+        // one workgroup, ~40-240 us: it runs beside the prologue and the
+        // first down-leg of the V-cycle, which do not need the inverse
+        fld_ctx* ctx = c;
+        HIPCHK(hipEventRecord(c->setup_fork, st));
+        HIPCHK(hipStreamWaitEvent(c->setup_stream, c->setup_fork, 0));
+        hipStream_t ss = c->setup_stream;
         const int w = std::min(cl.nx, cl.ny), tr = in.lv[L - 1].tr ? 1 : 0;
         if (w <= 4)
-            k_coarse_setup<T, 4><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
+            k_coarse_setup<T, 4><<<1, kCoarseMax, 0, ss>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
                                                            in.Ainv);
         else if (w <= 8)
-            k_coarse_setup<T, 8><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
+            k_coarse_setup<T, 8><<<1, kCoarseMax, 0, ss>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
                                                            in.Ainv);
         else
-            k_coarse_setup<T, kCoarseBand><<<1, kCoarseMax, 0, st>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu,
+            k_coarse_setup<T, kCoarseBand><<<1, kCoarseMax, 0, ss>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu,
                                                                      in.Ywork, in.Ainv);
+        HIPCHK(hipEventRecord(c->setup_join, ss));
+        c->setup_pending = true;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -960,10 +989,14 @@ void fld_destroy(fld_ctx* ctx) {
     if (ctx->i32.chunk_exec) (void)hipGraphExecDestroy(ctx->i32.chunk_exec);
     if (ctx->i64.chunk_exec) (void)hipGraphExecDestroy(ctx->i64.chunk_exec);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->setup_stream) (void)hipStreamSynchronize(ctx->setup_stream);
     for (void* p : ctx->allocs) (void)hipFree(p);
     if (ctx->hsc) (void)hipHostFree(ctx->hsc);
     if (ctx->herr) (void)hipHostFree(ctx->herr);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->setup_stream) (void)hipStreamDestroy(ctx->setup_stream);
+    if (ctx->setup_fork) (void)hipEventDestroy(ctx->setup_fork);
+    if (ctx->setup_join) (void)hipEventDestroy(ctx->setup_join);
     for (auto& e : ctx->prof.ev) (void)hipEventDestroy(e);
     if (ctx->prof.hran) (void)hipHostFree(ctx->prof.hran);
     delete ctx;
@@ -1063,6 +1096,10 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
         return fail(FLD_ENOMEM, "pinned flag");
     std::memset(ctx->hsc, 0, sizeof(Scalars));
     *ctx->herr = 0;
+    if (hipStreamCreateWithFlags(&ctx->setup_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->setup_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->setup_join, hipEventDisableTiming) != hipSuccess)
+        return fail(FLD_EHIP, "set-up stream");
     fld_status s;
     if (inner_is_float(ctx)) s = alloc_inner<float>(ctx);
     else s = alloc_inner<double>(ctx);

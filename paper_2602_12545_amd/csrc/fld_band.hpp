@@ -161,7 +161,13 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
             }
         }
         T vxn[LM], vxs[LM];
-        // neighbour rows
+        // neighbour rows (whole chunks of the second parity: 16-byte LDS reads)
+        if (FULL && PH == 2) {
+            if (active && row + 1 < ny) load_vec<T, LM>(rows + (size_t)(row + 1 - (r0 - 1)) * nx + s0, vxn);
+            else fill<T, LM>(vxn, T(0));
+            if (active && row > 0) load_vec<T, LM>(rows + (size_t)(row - 1 - (r0 - 1)) * nx + s0, vxs);
+            else fill<T, LM>(vxs, T(0));
+        } else {
 #pragma unroll
         for (int q = 0; q < LM; ++q) {
             const int g = s0 + q;
@@ -190,10 +196,15 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
             vxn[q] = xn;
             vxs[q] = xs;
         }
+        }
         if (WRITE_BT && active && row >= r0 && row < rend) {
+            if (FULL) {
+                store_vec<T, LM>(bb + (size_t)(row - r0) * nx + s0, vb);
+            } else {
 #pragma unroll
-            for (int q = 0; q < LM; ++q)
-                if (FULL || (q < Lc && s0 + q < nx)) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+                for (int q = 0; q < LM; ++q)
+                    if (q < Lc && s0 + q < nx) bb[(size_t)(row - r0) * nx + s0 + q] = vb[q];
+            }
         }
         // diagonal and right-hand side of every chunk row (the loaded
         // arrays die here, which keeps register pressure low)
@@ -291,15 +302,27 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         if (active) {
             T* dst = rows + (size_t)(row - (r0 - 1)) * nx;
             const bool own = row >= r0 && row < rend;  // a band row, not the halo
+            if (FULL) {
+                T out[LM];
 #pragma unroll
-            for (int q = 0; q < LM; ++q) {
-                const int g = s0 + q;
-                if (FULL || (q < Lc && g < nx)) {
-                    const T v = (q == Lc - 1) ? X
-                                             : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
-                                                   gv[q < LM - 1 ? q : 0] * X;
-                    dst[g] = v;
-                    if (DOT && own) acc += (double)vb[q] * (double)v;
+                for (int q = 0; q < LM; ++q) {
+                    out[q] = (q == LM - 1) ? X
+                                           : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                 gv[q < LM - 1 ? q : 0] * X;
+                    if (DOT && own) acc += (double)vb[q] * (double)out[q];
+                }
+                store_vec<T, LM>(dst + s0, out);
+            } else {
+#pragma unroll
+                for (int q = 0; q < LM; ++q) {
+                    const int g = s0 + q;
+                    if (q < Lc && g < nx) {
+                        const T v = (q == Lc - 1) ? X
+                                                 : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
+                                                       gv[q < LM - 1 ? q : 0] * X;
+                        dst[g] = v;
+                        if (DOT && own) acc += (double)vb[q] * (double)v;
+                    }
                 }
             }
         }

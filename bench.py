@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every timed step (plain launches; for comparison with a kernel trace)")
+    ap.add_argument("--mg-cycle", default="k", choices=["k", "v"],
+                    help="multigrid cycle of the single-grid solves (the batch always runs V-cycles)")
     ap.add_argument("--norm", default="rows", choices=["rows", "scaled"],
                     help="stop norm (the 4096x2048 spherical recipe needs 'scaled' for 1e-10)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -101,8 +103,15 @@ def measured_traffic(name="pmc_c2_line_sweeps.md"):
         return None, "counter summary incomplete"
 
 
+MG_CYCLE = 1  # set from --mg-cycle
+
+
+def defaults(fld, **kw):
+    return fld.default_options(mg_cycle=MG_CYCLE, **kw)
+
+
 def options(fld, prec, tuned, norm=0):
-    o = fld.default_options(precision=prec, norm=norm)
+    o = defaults(fld, precision=prec, norm=norm)
     if tuned is not None:
         for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph"):
             setattr(o, k, getattr(tuned, k))
@@ -181,7 +190,7 @@ def batch_extra(fld, torch, W, tune):
     out = {"workload": "c4: 256 Cartesian blocks, sides in {16..128}, 984320 cells, ghost boundaries"}
 
     def timed(prec, reps=10):
-        base = fld.default_options(precision=prec)
+        base = defaults(fld, precision=prec)
         threads = 512
         if tune is not None:
             o, threads, _ = tune.tune_batch(nx, ny, d, d, f, 1e4, base=base, reps=1, cache="")
@@ -219,7 +228,7 @@ def batch_extra(fld, torch, W, tune):
     ctxs, fs = [], []
     for b in blocks:
         ctxs.append(fld.Context(b.nx, b.ny, b.geom, b.x_faces, b.y_faces, [(c.kind, c.value) for c in b.bc],
-                                fld.default_options(precision="fp64")))
+                                defaults(fld, precision="fp64")))
         fs.append(dev_fields(torch, b))
     for c, g, b in zip(ctxs, fs, blocks):
         c.step(g["E"].clone(), g["T"].clone(), g["rho"], g["kappa_R"], g["kappa_P"], g["c_v"], b.dt, g["ghost_E"])
@@ -248,7 +257,7 @@ def stress_extra(fld, torch, W, nsteps=5):
                        f"{nsteps} steps per fld_steps call", "norm": "scaled"}
     for prec in ("mixed", "fp64"):
         ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                          [(b.kind, b.value) for b in prob.bc], fld.default_options(precision=prec, norm=1))
+                          [(b.kind, b.value) for b in prob.bc], defaults(fld, precision=prec, norm=1))
         E, T = f["E"].clone(), f["T"].clone()
         ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt)  # warm-up
         E.copy_(f["E"])
@@ -278,10 +287,12 @@ def copy_calibration(torch):
 
 
 def main():
+    global MG_CYCLE
     args = parse()
+    MG_CYCLE = 1 if args.mg_cycle == "k" else 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; how the solver would shard over GPUs is "
-                                   "described in DESIGN.md"}), flush=True)
+        print(json.dumps({"error": "only one GPU is supported: the solver has no multi-GPU path; "
+                                   "blocks and rows would shard as separate solves per GPU"}), flush=True)
         sys.exit(2)
     import torch
     if args.copy_calibration:
@@ -299,7 +310,7 @@ def main():
     if not args.no_tune:
         tuned, tune_table = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                             [(b.kind, b.value) for b in prob.bc], base, prob.dt,
-                                            base=fld.default_options(precision=args.precision, norm=norm), reps=1,
+                                            base=defaults(fld, precision=args.precision, norm=norm), reps=1,
                                             cache="")
     opts = options(fld, args.precision, tuned, norm)
     profile = not args.no_profile
@@ -322,7 +333,8 @@ def main():
         "config": {"workload": f"{args.workload}: {prob.nx}x{prob.ny} {geom}, one implicit FLD step to 1e-10",
                    "cells": ncell, "precision": args.precision, "rel_tol": 1e-10,
                    "norm": "per-volume rows" if norm == 0 else "Jacobi-scaled",
-                   "schedule": {k: getattr(opts, k) for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk")},
+                   "schedule": {k: getattr(opts, k) for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk",
+                                                                 "mg_cycle")},
                    "tuned": tuned is not None},
         "inner_iters": iters,
         "mcell_iter_per_s": ncell * iters / ms / 1e6,

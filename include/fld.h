@@ -114,6 +114,17 @@ typedef enum { FLD_MG_GALERKIN = 0, FLD_MG_HALVED = 1 } fld_mg_coarse;
  * half-sweep separately. */
 typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT = 2 } fld_smoother;
 
+/* Multigrid cycle.  V: one pass down and up.  K: as V, but the coarse problem
+ * of the last launched grid level (the first level of the one-workgroup LDS
+ * sub-cycle) is solved by two steps of flexible CG, each preconditioned by the
+ * sub-cycle's V-cycle (the Krylov-accelerated K-cycle of Notay and
+ * Vassilevski, 2008).  With piecewise-constant aggregation the V-cycle loses
+ * convergence as levels are added; the K-cycle restores most of it at the cost
+ * of a second pass through the LDS levels only.  K acts as V where a line
+ * smoother has no LDS sub-cycle (fewer than three levels, or point
+ * smoothing). */
+typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1 } fld_mg_cycle;
+
 typedef struct {
     int32_t precision;      /* fld_precision (default MIXED)                                 */
     int32_t limiter;        /* fld_limiter (default LP)                                      */
@@ -130,6 +141,7 @@ typedef struct {
     int32_t smoother;       /* fld_smoother (default LINE); LINE* need nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */
     int32_t use_graph;      /* capture each chunk as a hipGraph (default 1)                  */
+    int32_t mg_cycle;       /* fld_mg_cycle (default K; the batch runs V)                    */
 } fld_options;
 
 typedef struct {
@@ -272,8 +284,8 @@ typedef struct fld_batch fld_batch;
 /* Creates a batch.  nx, ny, dx, dy: host arrays of nblocks entries, read
  * during the call.  bc: host array of 4 sides applied to every block (NULL =
  * DIRICHLET_GHOST on all sides; AXIS is not allowed).  opt may be NULL; the
- * batch needs smoother = LINE; mg_coarse_max above 64 acts as 64; chunk is unused;
- * use_graph selects graph capture in fld_batch_steps.  stream: hipStream_t.
+ * batch needs smoother = LINE; mg_coarse_max above 64 acts as 64; chunk and
+ * mg_cycle are unused (V-cycles); use_graph selects graph capture in fld_batch_steps.  stream: hipStream_t.
  * Returns EINVAL (sizes, spacing, options), ENOMEM, EHIP. */
 fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx, const int32_t* ny,
                             const double* dx, const double* dy, const fld_bc* bc,

@@ -41,7 +41,7 @@ class fld_options(ctypes.Structure):
                 ("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("mg_coarse_max", ctypes.c_int32),
                 ("mg_coarse_op", ctypes.c_int32), ("smoother", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("mg_cycle", ctypes.c_int32)]
 
 
 class fld_solve_info(ctypes.Structure):

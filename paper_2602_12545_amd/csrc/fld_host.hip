@@ -194,6 +194,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
     if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
+    if (o->mg_cycle < 0 || o->mg_cycle > 1) { err = "mg_cycle"; return FLD_EINVAL; }
     return FLD_OK;
 }
 
@@ -552,8 +553,11 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(ctx->alloc(&in.q, n));
     in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual
     // one-workgroup coarse sub-cycle: the finest level l >= 1 from which all
-    // coarser levels fit in LDS (5 arrays each) and whose lines fit one wavefront
+    // coarser levels fit in LDS (5 arrays each; the K-cycle adds two arrays of
+    // level l and its partials) and whose lines fit one wavefront
     const int L = (int)in.lv.size();
+    const bool kcyc = ctx->opt.mg_cycle == FLD_MG_CYCLE_K;
+    constexpr int kRedSlots = 4 * (kSubThreads<T> / 64);
     in.sub_first = -1;
     int dev = 0, lds_max = 65536;
     HIPCHK(hipGetDevice(&dev));
@@ -566,6 +570,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
             size_t need = 0;
             for (int k = l; k < L; ++k) need += 5 * (size_t)(in.lv[k].nx + 1) * in.lv[k].ny;
             need += (size_t)in.lv[L - 1].nx * in.lv[L - 1].ny;  // coarsest right-hand side, gathered
+            if (kcyc) need += 2 * (size_t)(in.lv[l].nx + 1) * in.lv[l].ny + kRedSlots;
             need *= sizeof(T);
             if (need <= (size_t)lds_max) {
                 in.sub_first = l;
@@ -584,6 +589,8 @@ fld_status alloc_inner(fld_ctx* ctx) {
             }
             S.Ainv = in.Ainv;
             S.bc_off = off;
+            S.kcyc = kcyc ? 1 : 0;
+            S.k_off = off + in.lv[L - 1].nx * in.lv[L - 1].ny;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)in.sub_lds));
@@ -815,6 +822,7 @@ void fld_default_options(fld_options* o) {
     o->smoother = FLD_SMOOTH_LINE;
     o->chunk = 8;
     o->use_graph = 1;
+    o->mg_cycle = FLD_MG_CYCLE_K;
 }
 
 const char* fld_version(void) { return kVersion; }

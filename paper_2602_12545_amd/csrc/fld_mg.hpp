@@ -1120,9 +1120,13 @@ struct SubCycle {
     SubLevel<T> lv[kSubMaxLevels];
     const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
     int bc_off;            // LDS pool offset of the coarsest right-hand side in that cell order
+    int kcyc;              // 1: K-cycle at the first level (two flexible-CG steps around the V-cycle)
+    int k_off;             // LDS pool offset of the K-cycle arrays (first iterate, its image, partials)
 };
 
-// LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny).
+// LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny); then the
+// coarsest right-hand side in the dense inverse's cell order; then, for the
+// K-cycle, two arrays of the first level's size and the reduction partials.
 //
 // One zebra half-sweep of a level in LDS: the lines of parity `par` are
 // spread over the workgroup's wavefronts (wave_line_sweep, no barrier inside).
@@ -1141,38 +1145,46 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
         wave_line_sweep<T, kLineMaxL, false>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
 }
 
+// A x at cell (i, j) of a sub-level in LDS (row pitch P).
 template <typename T>
-__global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, const T* __restrict__ bin, T* __restrict__ xout,
-                                                          const Scalars* __restrict__ sc) {
-    if (sc->done) return;
-    extern __shared__ unsigned char smem_raw[];
-    T* pool = reinterpret_cast<T*>(smem_raw);
-    const int t = threadIdx.x;
-    // coefficients of every sub-level, and the right-hand side of the first
-    for (int l = 0; l < S.nlev; ++l) {
-        const SubLevel<T>& L = S.lv[l];
-        const int n = L.nx * L.ny, z = L.size;
-        T* m = pool + L.off;
-        // (i, j) of cell c advanced incrementally: no division per cell
-        constexpr int NT = kSubThreads<T>;
-        int i = t % L.nx, j = t / L.nx;
-        const int di = NT % L.nx, dj = NT / L.nx;
-        for (int c = t; c < n; c += NT) {
-            const int cl = j * L.pitch + i;
-            m[cl] = L.m[c];
-            m[z + cl] = L.We[c];
-            m[2 * z + cl] = L.Wn[c];
-            // input in the level's primary layout
-            if (l == 0) m[3 * z + cl] = bin[L.tr ? i * L.ny + j : c];
-            i += di;
-            j += dj;
-            if (i >= L.nx) {
-                i -= L.nx;
-                ++j;
-            }
-        }
+__device__ inline T sub_apply(const T* m, const T* We, const T* Wn, const T* x, int i, int j, int nx, int ny, int P) {
+    const int c = j * P + i;
+    const T xv = x[c];
+    T a = m[c] * xv;
+    if (i + 1 < nx) a += We[c] * (xv - x[c + 1]);
+    if (i > 0) a += We[c - 1] * (xv - x[c - 1]);
+    if (j + 1 < ny) a += Wn[c] * (xv - x[c + P]);
+    if (j > 0) a += Wn[c - P] * (xv - x[c - P]);
+    return a;
+}
+
+// Workgroup sums of NV values (every thread gets them, in one fixed order);
+// red holds NV partials per wavefront.
+template <typename T, int NV>
+__device__ inline void sub_sum(T (&v)[NV], T* red) {
+    constexpr int NW = kSubThreads<T> / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        T a = T(0);
+        for (int w = 0; w < NW; ++w) a += red[w * NV + k];
+        v[k] = a;
     }
     __syncthreads();
+}
+
+// The V-cycle over the sub-levels: right-hand side in the first level's b,
+// result in its x (every other level's b and x overwritten).
+template <typename T>
+__device__ __forceinline__ void sub_vcycle(const SubCycle<T>& S, T* pool) {
+    const int t = threadIdx.x;
     // down
     for (int l = 0; l < S.nlev - 1; ++l) {
         const SubLevel<T>& L = S.lv[l];
@@ -1275,14 +1287,139 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
             __syncthreads();
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, const T* __restrict__ bin, T* __restrict__ xout,
+                                                          const Scalars* __restrict__ sc) {
+    if (sc->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    T* pool = reinterpret_cast<T*>(smem_raw);
+    const int t = threadIdx.x;
+    // coefficients of every sub-level, and the right-hand side of the first
+    for (int l = 0; l < S.nlev; ++l) {
+        const SubLevel<T>& L = S.lv[l];
+        const int n = L.nx * L.ny, z = L.size;
+        T* m = pool + L.off;
+        // (i, j) of cell c advanced incrementally: no division per cell
+        constexpr int NT = kSubThreads<T>;
+        int i = t % L.nx, j = t / L.nx;
+        const int di = NT % L.nx, dj = NT / L.nx;
+        for (int c = t; c < n; c += NT) {
+            const int cl = j * L.pitch + i;
+            m[cl] = L.m[c];
+            m[z + cl] = L.We[c];
+            m[2 * z + cl] = L.Wn[c];
+            // input in the level's primary layout
+            if (l == 0) m[3 * z + cl] = bin[L.tr ? i * L.ny + j : c];
+            i += di;
+            j += dj;
+            if (i >= L.nx) {
+                i -= L.nx;
+                ++j;
+            }
+        }
+    }
+    __syncthreads();
+    // K-cycle (Notay and Vassilevski, 2008): the result is the A-norm best
+    // combination of c1 = V(b) and c2 = V(b - (c1.b / c1.A c1) A c1); one
+    // copy of the V-cycle code serves both passes
+    const SubLevel<T>& L0 = S.lv[0];
+    const int n0 = L0.nx * L0.ny, z0 = L0.size, P0 = L0.pitch;
+    T* m0 = pool + L0.off;
+    T* b0 = m0 + 3 * z0;
+    T* x0 = m0 + 4 * z0;
+    T* c1 = pool + S.k_off;
+    T* v1 = c1 + z0;
+    T* red = v1 + z0;
+    constexpr int NT = kSubThreads<T>;
+    const int di = NT % L0.nx, dj = NT / L0.nx;
+    constexpr int NW = NT / 64;
+    T f1 = T(1), f2 = T(0);  // output = f1 * (c1, or x without K) + f2 * x
+    // rho1 and s1 wait in LDS (red[3 NW], red[3 NW + 1]) during the second
+    // V-cycle, which needs every register
+    for (int pass = 0;; ++pass) {
+        sub_vcycle(S, pool);
+        if (!S.kcyc) break;
+        if (pass == 0) {
+            // c1 = x, v1 = A c1; rho1 = c1.v1, s1 = c1.b / rho1
+            T d[2] = {T(0), T(0)};
+            int i = t % L0.nx, j = t / L0.nx;
+            for (int c = t; c < n0; c += NT) {
+                const int cl = j * P0 + i;
+                const T xv = x0[cl];
+                const T av = sub_apply(m0, m0 + z0, m0 + 2 * z0, x0, i, j, L0.nx, L0.ny, P0);
+                c1[cl] = xv;
+                v1[cl] = av;
+                d[0] += xv * av;
+                d[1] += xv * b0[cl];
+                i += di;
+                j += dj;
+                if (i >= L0.nx) {
+                    i -= L0.nx;
+                    ++j;
+                }
+            }
+            sub_sum<T, 2>(d, red);
+            const T rho1 = d[0];
+            // rho1 <= 0 only for c1 = 0 (zero right-hand side): the result is c1
+            if (!(rho1 > T(0))) break;
+            const T s1 = d[1] / rho1;
+            if (t == 0) {
+                red[3 * NW] = rho1;
+                red[3 * NW + 1] = s1;
+            }
+            i = t % L0.nx;
+            j = t / L0.nx;
+            for (int c = t; c < n0; c += NT) {
+                const int cl = j * P0 + i;
+                b0[cl] -= s1 * v1[cl];
+                i += di;
+                j += dj;
+                if (i >= L0.nx) {
+                    i -= L0.nx;
+                    ++j;
+                }
+            }
+            __syncthreads();
+            continue;  // x = c2 next
+        }
+        // gam = c2.v1, beta = c2.A c2, a2 = c2.r
+        T e[3] = {T(0), T(0), T(0)};
+        int i = t % L0.nx, j = t / L0.nx;
+        for (int c = t; c < n0; c += NT) {
+            const int cl = j * P0 + i;
+            const T xv = x0[cl];
+            e[0] += xv * v1[cl];
+            e[1] += xv * sub_apply(m0, m0 + z0, m0 + 2 * z0, x0, i, j, L0.nx, L0.ny, P0);
+            e[2] += xv * b0[cl];
+            i += di;
+            j += dj;
+            if (i >= L0.nx) {
+                i -= L0.nx;
+                ++j;
+            }
+        }
+        sub_sum<T, 3>(e, red);
+        const T rho1 = red[3 * NW], s1 = red[3 * NW + 1];
+        // A-norm squared of the part of c2 A-orthogonal to c1; within the
+        // rounding of its two terms c2 adds nothing
+        const T rho2 = e[1] - e[0] * e[0] / rho1;
+        const T tiny = sizeof(T) == 4 ? T(1e-5) : T(1e-12);
+        f1 = s1;
+        if (rho2 > tiny * e[1]) {
+            f2 = e[2] / rho2;
+            f1 = s1 - e[0] * f2 / rho1;
+        }
+        break;
+    }
     // output in the first level's primary layout
     {
-        const SubLevel<T>& L = S.lv[0];
-        const int n = L.nx * L.ny;
-        const T* x = pool + L.off + 4 * L.size;
-        for (int c = t; c < n; c += kSubThreads<T>) {
-            const int i = c % L.nx, j = c / L.nx;
-            xout[L.tr ? i * L.ny + j : c] = x[j * L.pitch + i];
+        const T* xo = S.kcyc ? c1 : x0;
+        for (int c = t; c < n0; c += NT) {
+            const int i = c % L0.nx, j = c / L0.nx;
+            const int cl = j * P0 + i;
+            xout[L0.tr ? i * L0.ny + j : c] = f1 * xo[cl] + f2 * x0[cl];
         }
     }
 }

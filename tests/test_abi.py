@@ -66,7 +66,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(fld_bc), sizeof(fld_grid), sizeof(fld_options), sizeof(fld_solve_info));
   printf("%zu %zu %zu %zu\n", offsetof(fld_grid, bc), offsetof(fld_options, rel_tol),
          offsetof(fld_options, inner_rtol), offsetof(fld_solve_info, rel_resid));
-  printf("%zu %zu\n", offsetof(fld_options, use_graph), offsetof(fld_solve_info, ms));
+  printf("%zu %zu %zu\n", offsetof(fld_options, use_graph), offsetof(fld_solve_info, ms),
+         offsetof(fld_options, mg_cycle));
   return 0;
 }
 '''
@@ -85,5 +86,5 @@ def test_ctypes_structures_match_c_layout():
     py = [ctypes.sizeof(B.fld_bc), ctypes.sizeof(B.fld_grid), ctypes.sizeof(B.fld_options),
           ctypes.sizeof(B.fld_solve_info), B.fld_grid.bc.offset, B.fld_options.rel_tol.offset,
           B.fld_options.inner_rtol.offset, B.fld_solve_info.rel_resid.offset, B.fld_options.use_graph.offset,
-          B.fld_solve_info.ms.offset]
+          B.fld_solve_info.ms.offset, B.fld_options.mg_cycle.offset]
     assert c == py

@@ -206,3 +206,22 @@ def test_coarsest_level_up_to_256_cells(lib, shape, prec):
     assert info["status"] == 0
     r = O.step_problem(prob)
     assert rel_l2(E, r.E) < 1e-10 and rel_l2(T, r.T) < 1e-10
+
+
+@pytest.mark.parametrize("name,kw", [("c2", dict(nx=512, ny=512)), ("c5", dict(nx=256, ny=128)),
+                                     ("c3", dict(nx=300, ny=200))])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_k_cycle_and_v_cycle(lib, name, kw, prec):
+    """Both multigrid cycles reach the oracle's solution; the K-cycle (two
+    flexible-CG steps around the LDS sub-cycle) needs no more CG iterations
+    than the V-cycle on hierarchies deep enough to have a sub-cycle."""
+    prob = W.make(name, **kw)
+    ref = O.step_problem(prob)
+    opt = dict(precision=prec, rel_tol=1e-12, norm=1)
+    Ek, Tk, ik = gpu_step(lib, torch, prob, mg_cycle=1, **opt)
+    Ev, Tv, iv = gpu_step(lib, torch, prob, mg_cycle=0, **opt)
+    print(name, prec, "K", ik["inner_iters"], "V", iv["inner_iters"], flush=True)
+    assert ik["status"] == 0 and iv["status"] == 0
+    for E, T in ((Ek, Tk), (Ev, Tv)):
+        assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10
+    assert ik["inner_iters"] <= iv["inner_iters"]

@@ -201,7 +201,7 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
 /* nsteps consecutive steps with (E, T) <- (E^{n+1}, T^{n+1}) and the opacities,
  * rho and c_v held fixed (Section 3.2.1 sub-step loop, one sub-step per step).
  * The first step runs as fld_step; its CG iteration count k1 fixes a budget
- * S = min(max_inner, even(1.5 k1 + 8)) iterations.  One whole step (assembly,
+ * S = min(max_inner, even(2 k1 + 16)) iterations.  One whole step (assembly,
  * hierarchy, S iteration slots with device-side early exit, gas update, a
  * device-side status record) is then captured once as a hipGraph and replayed
  * for the remaining steps in segments of 1, 2, 4, then 8 launches; the host

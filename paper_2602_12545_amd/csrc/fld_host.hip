@@ -570,6 +570,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
             size_t need = 0;
             for (int k = l; k < L; ++k) need += 5 * (size_t)(in.lv[k].nx + 1) * in.lv[k].ny;
             need += (size_t)in.lv[L - 1].nx * in.lv[L - 1].ny;  // coarsest right-hand side, gathered
+            need += kSubThreads<T>;                              // coarsest solve's partial sums
             if (kcyc) need += 2 * (size_t)(in.lv[l].nx + 1) * in.lv[l].ny + kRedSlots;
             need *= sizeof(T);
             if (need <= (size_t)lds_max) {
@@ -589,8 +590,9 @@ fld_status alloc_inner(fld_ctx* ctx) {
             }
             S.Ainv = in.Ainv;
             S.bc_off = off;
+            S.part_off = off + in.lv[L - 1].nx * in.lv[L - 1].ny;
             S.kcyc = kcyc ? 1 : 0;
-            S.k_off = off + in.lv[L - 1].nx * in.lv[L - 1].ny;
+            S.k_off = S.part_off + kSubThreads<T>;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)in.sub_lds));
@@ -1185,7 +1187,10 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         }
         return FLD_OK;
     }
-    int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 3 / 2 + 8) + 1) & ~1);
+    // later steps can need well over the first step's count (c5: 85 then up
+    // to 148); an unused slot costs its early-exit launches (~25, a few us
+    // each), an exhausted budget a replay of the whole step
+    int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 2 + 16) + 1) & ~1);
     // one captured step: assembly, hierarchy, fixed-budget solve, gas update,
     // per-step record; replayed in segments of seg steps (1, doubling after
     // every clean segment up to kSeg).  After each segment the host reads the

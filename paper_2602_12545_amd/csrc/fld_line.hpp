@@ -237,15 +237,17 @@ __device__ inline int wave_line_lanes(int na) {
 // measured faster for rows read from global memory and slower from LDS);
 // back-substitution finishes.  Wave `wave` of `nwaves` takes lines
 // wave * 64/K + ..., the next pass nwaves * 64/K lines further.  Needs na <=
-// 64 LM.  The caller separates half-sweeps with a barrier.
-template <typename T, int LM, bool ZERO, bool BF = true, bool DPP = false>
-__device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long long sl, const T* __restrict__ m,
+// 64 LM.  The caller separates half-sweeps with a barrier.  I: index type
+// (int where every index fits, as in LDS).  FULL: na == K LM (every chunk
+// whole), the chunk bounds known at compile time.
+template <typename T, int LM, bool ZERO, bool BF = true, bool DPP = false, typename I = long long, bool FULL = false>
+__device__ void wave_line_sweep(int na, int nlines, int par, I sa, I sl, const T* __restrict__ m,
                                 const T* __restrict__ Wa, const T* __restrict__ Wc, const T* __restrict__ b,
                                 T* __restrict__ x, int wave, int nwaves) {
     const int nl = (nlines - par + 1) / 2;
     if (nl <= 0) return;
     const int K = wave_line_lanes<LM>(na);
-    const int L = max(2, (na + K - 1) / K);
+    const int L = FULL ? LM : max(2, (na + K - 1) / K);
     const int lpw = 64 / K;
     const int lane = threadIdx.x & 63;
     const int k = lane & (K - 1);
@@ -254,9 +256,9 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
         const int ql = q0 + lane / K;
         const bool active = ql < nl;
         const int line = 2 * ql + par;
-        const long long lb = (long long)(active ? line : 0) * sl;
+        const I lb = (I)(active ? line : 0) * sl;
         T vm[LM], va[LM], vcn[LM], vcs[LM], vb[LM], vxn[LM], vxs[LM];
-        const T wprev = (active && s0 > 0 && s0 - 1 < na) ? Wa[lb + (long long)(s0 - 1) * sa] : T(0);
+        const T wprev = (active && s0 > 0 && (FULL || s0 - 1 < na)) ? Wa[lb + (I)(s0 - 1) * sa] : T(0);
         // a full chunk along a contiguous row, 16-byte aligned in every array
         // (the arrays share their element offsets): vector loads
         constexpr int VW = 16 / sizeof(T);
@@ -265,7 +267,7 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
                            reinterpret_cast<uintptr_t>(Wc + lb + s0) | reinterpret_cast<uintptr_t>(b + lb + s0) |
                            reinterpret_cast<uintptr_t>(x + lb + s0)) & 15) == 0;
         if (vec) {
-            const long long c0 = lb + s0;
+            const I c0 = lb + s0;
             load_vec<T, LM>(m + c0, vm);
             load_vec<T, LM>(Wa + c0, va);
             load_vec<T, LM>(Wc + c0, vcn);
@@ -280,8 +282,8 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                const bool ok = active && q < L && g < na;
-                const long long c = lb + (long long)g * sa;
+                const bool ok = FULL ? active : (active && q < L && g < na);
+                const I c = lb + (I)g * sa;
                 vm[q] = ok ? m[c] : T(1);
                 va[q] = ok ? Wa[c] : T(0);
                 vcn[q] = ok ? Wc[c] : T(0);
@@ -296,12 +298,12 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
             // so the loads issue back to back instead of one guarded block
             // each (much faster from LDS; measured slower for binary32 rows in
             // global memory, where guarded loads skip traffic)
-            const long long dn = (line + 1 < nlines) ? sl : 0, ds = (line > 0) ? -sl : 0;
+            const I dn = (line + 1 < nlines) ? sl : 0, ds = (line > 0) ? -sl : 0;
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                const bool ok = active && q < L && g < na;
-                const long long c = lb + (long long)min(g, na - 1) * sa;
+                const bool ok = FULL ? active : (active && q < L && g < na);
+                const I c = lb + (I)(FULL ? g : min(g, na - 1)) * sa;
                 const T m_ = m[c], wa_ = Wa[c], wc_ = Wc[c], ws_ = Wc[c + ds], b_ = b[c];
                 vm[q] = ok ? m_ : T(1);
                 va[q] = ok ? wa_ : T(0);
@@ -402,11 +404,11 @@ __device__ void wave_line_sweep(int na, int nlines, int par, long long sa, long 
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;
-                if (q < L && g < na) {
+                if (FULL || (q < L && g < na)) {
                     const T v = (q == L - 1) ? X
                                              : gy[q < LM - 1 ? q : 0] + gu[q < LM - 1 ? q : 0] * Xp +
                                                    gv[q < LM - 1 ? q : 0] * X;
-                    x[lb + (long long)g * sa] = v;
+                    x[lb + (I)g * sa] = v;
                 }
             }
         }

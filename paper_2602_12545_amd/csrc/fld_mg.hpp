@@ -1120,13 +1120,16 @@ struct SubCycle {
     SubLevel<T> lv[kSubMaxLevels];
     const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
     int bc_off;            // LDS pool offset of the coarsest right-hand side in that cell order
+    int part_off;          // LDS pool offset of the coarsest solve's partial sums (one per thread)
     int kcyc;              // 1: K-cycle at the first level (two flexible-CG steps around the V-cycle)
     int k_off;             // LDS pool offset of the K-cycle arrays (first iterate, its image, partials)
 };
 
-// LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny); then the
-// coarsest right-hand side in the dense inverse's cell order; then, for the
-// K-cycle, two arrays of the first level's size and the reduction partials.
+// LDS pool per level: m, We, Wn, b, x (5 arrays of pitch * ny; the
+// coarsest level's coefficients are not loaded); then the coarsest
+// right-hand side in the dense inverse's cell order and one partial sum per
+// thread; then, for the K-cycle, two arrays of the first level's size and
+// the reduction partials.
 //
 // One zebra half-sweep of a level in LDS: the lines of parity `par` are
 // spread over the workgroup's wavefronts (wave_line_sweep, no barrier inside).
@@ -1139,10 +1142,20 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
     T* b = Wn + L.size;
     T* x = b + L.size;
     const int wave = threadIdx.x >> 6, nw = kSubThreads<T> / 64;
-    if (xdir)
-        wave_line_sweep<T, kLineMaxL, false>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
-    else
-        wave_line_sweep<T, kLineMaxL, false>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+    // rows of whole chunks (every power-of-two level from 8 cells) take the
+    // path with compile-time chunk bounds: about 40 % fewer instructions for
+    // the one or few busy wavefronts that bound a half-sweep
+    const int na = xdir ? nx : ny;
+    if (wave_line_lanes<kLineMaxL>(na) * kLineMaxL == na) {
+        if (xdir)
+            wave_line_sweep<T, kLineMaxL, false, true, false, int, true>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+        else
+            wave_line_sweep<T, kLineMaxL, false, true, false, int, true>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+    } else if (xdir) {
+        wave_line_sweep<T, kLineMaxL, false, true, false, int>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+    } else {
+        wave_line_sweep<T, kLineMaxL, false, true, false, int>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+    }
 }
 
 // A x at cell (i, j) of a sub-level in LDS (row pitch P).
@@ -1228,33 +1241,45 @@ __device__ __forceinline__ void sub_vcycle(const SubCycle<T>& S, T* pool) {
         __syncthreads();
     }
     // coarsest: dense inverse in the primary layout's cell order (the
-    // right-hand side gathered into that order first), four lanes per row
+    // right-hand side gathered into that order first).  The inverse is
+    // symmetric, so thread r of column group g reads column r: for each c
+    // the lanes of a wavefront read consecutive words.  G = NT / n groups
+    // split the columns (eight loads in flight per round); their partials
+    // are summed in group order.
     {
         const SubLevel<T>& L = S.lv[S.nlev - 1];
         const int n = L.nx * L.ny;
         T* b = pool + L.off + 3 * L.size;
         T* x = b + L.size;
         T* bc = pool + S.bc_off;
-        for (int c = t; c < n; c += kSubThreads<T>) {
+        T* part = pool + S.part_off;
+        constexpr int NT = kSubThreads<T>;
+        for (int c = t; c < n; c += NT) {
             const int i = L.tr ? c / L.ny : c % L.nx, j = L.tr ? c % L.ny : c / L.nx;
             bc[c] = b[j * L.pitch + i];
         }
         __syncthreads();
-        constexpr int RP = kSubThreads<T> / 4;  // rows per pass
-        const int l4 = t & 3;
-        for (int r0 = 0; r0 < n; r0 += RP) {
-            const int row = r0 + (t >> 2);
+        const int G = NT / n, r = t % n, g = t / n;
+        if (g < G) {
+            const T* col = S.Ainv + r;
             T acc = T(0);
-            if (row < n) {
-                const T* arow = S.Ainv + (size_t)row * n;
-                for (int c = l4; c < n; c += 4) acc += arow[c] * bc[c];
+            int c = g;
+            for (; c + 7 * G < n; c += 8 * G) {
+                T a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = col[(size_t)(c + u * G) * n];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += a[u] * bc[c + u * G];
             }
-            acc += __shfl_xor(acc, 1, 4);
-            acc += __shfl_xor(acc, 2, 4);
-            if (row < n && l4 == 0) {
-                const int i = L.tr ? row / L.ny : row % L.nx, j = L.tr ? row % L.ny : row / L.nx;
-                x[j * L.pitch + i] = acc;
-            }
+            for (; c < n; c += G) acc += col[(size_t)c * n] * bc[c];
+            part[t] = acc;
+        }
+        __syncthreads();
+        if (t < n) {
+            T acc = part[t];
+            for (int q = 1; q < G; ++q) acc += part[q * n + t];
+            const int i = L.tr ? t / L.ny : t % L.nx, j = L.tr ? t % L.ny : t / L.nx;
+            x[j * L.pitch + i] = acc;
         }
         __syncthreads();
     }
@@ -1296,8 +1321,9 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
     extern __shared__ unsigned char smem_raw[];
     T* pool = reinterpret_cast<T*>(smem_raw);
     const int t = threadIdx.x;
-    // coefficients of every sub-level, and the right-hand side of the first
-    for (int l = 0; l < S.nlev; ++l) {
+    // coefficients of every sub-level but the coarsest (solved by its dense
+    // inverse), and the right-hand side of the first
+    for (int l = 0; l < S.nlev - 1; ++l) {
         const SubLevel<T>& L = S.lv[l];
         const int n = L.nx * L.ny, z = L.size;
         T* m = pool + L.off;

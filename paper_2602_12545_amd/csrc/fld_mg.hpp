@@ -1133,7 +1133,7 @@ struct SubCycle {
 //
 // One zebra half-sweep of a level in LDS: the lines of parity `par` are
 // spread over the workgroup's wavefronts (wave_line_sweep, no barrier inside).
-template <typename T>
+template <typename T, bool ZERO = false>
 __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int par) {
     const int nx = L.nx, ny = L.ny, P = L.pitch;
     T* m = pool + L.off;
@@ -1148,13 +1148,13 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
     const int na = xdir ? nx : ny;
     if (wave_line_lanes<kLineMaxL>(na) * kLineMaxL == na) {
         if (xdir)
-            wave_line_sweep<T, kLineMaxL, false, true, false, int, true>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+            wave_line_sweep<T, kLineMaxL, ZERO, true, false, int, true>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
         else
-            wave_line_sweep<T, kLineMaxL, false, true, false, int, true>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+            wave_line_sweep<T, kLineMaxL, ZERO, true, false, int, true>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
     } else if (xdir) {
-        wave_line_sweep<T, kLineMaxL, false, true, false, int>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+        wave_line_sweep<T, kLineMaxL, ZERO, true, false, int>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
     } else {
-        wave_line_sweep<T, kLineMaxL, false, true, false, int>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+        wave_line_sweep<T, kLineMaxL, ZERO, true, false, int>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
     }
 }
 
@@ -1202,14 +1202,13 @@ __device__ __forceinline__ void sub_vcycle(const SubCycle<T>& S, T* pool) {
     for (int l = 0; l < S.nlev - 1; ++l) {
         const SubLevel<T>& L = S.lv[l];
         T* x = pool + L.off + 4 * L.size;
-        for (int c = t; c < L.size; c += kSubThreads<T>) x[c] = T(0);
-        __syncthreads();
+        // x starts at zero: the first half-sweep takes zero neighbours, and
+        // the first direction's two half-sweeps write every cell
         const bool first_x = !L.tr;  // primary direction first, as on the grid levels
-        for (int dir = 0; dir < 2; ++dir) {
-            const bool xd = (dir == 0) == first_x;
-            sub_line(L, pool, xd, 0);
-            __syncthreads();
-            sub_line(L, pool, xd, 1);
+        for (int h = 0; h < 4; ++h) {
+            const bool xd = (h < 2) == first_x;
+            if (h == 0) sub_line<T, true>(L, pool, xd, 0);
+            else sub_line(L, pool, xd, h & 1);
             __syncthreads();
         }
         // residual and 2x2 restriction into the next level's b

@@ -49,8 +49,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every timed step (plain launches; for comparison with a kernel trace)")
-    ap.add_argument("--mg-cycle", default="k", choices=["k", "v"],
-                    help="multigrid cycle of the single-grid solves (the batch always runs V-cycles)")
+    ap.add_argument("--mg-cycle", default=None, choices=["k", "v"],
+                    help="fix the multigrid cycle of the single-grid solves (default: the library default, "
+                         "and the tuner's choice where tuned; the batch always runs V-cycles)")
     ap.add_argument("--norm", default="rows", choices=["rows", "scaled"],
                     help="stop norm (the 4096x2048 spherical recipe needs 'scaled' for 1e-10)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -67,14 +68,16 @@ def dev_fields(torch, prob):
 
 
 def kernel_source_digest():
-    """Digest of the kernel sources with comments and white space removed;
-    HBM traffic counters taken on other code no longer describe the kernels."""
+    """Digest of the sources that define or launch the single-grid kernels
+    (the batch kernel and the tuner excluded), comments and white space
+    removed; HBM traffic counters taken on other code no longer describe the
+    line sweeps."""
     import hashlib
     import re
     d = os.path.join(ROOT, "paper_2602_12545_amd", "csrc")
     h = hashlib.sha1()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip")):
+        if f.endswith((".hpp", ".hip")) and not f.startswith(("fld_batch", "fld_tune")):
             src = open(os.path.join(d, f)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
             src = re.sub(r"//[^\n]*", "", src)
@@ -103,18 +106,23 @@ def measured_traffic(name="pmc_c2_line_sweeps.md"):
         return None, "counter summary incomplete"
 
 
-MG_CYCLE = 1  # set from --mg-cycle
+MG_CYCLE = None  # --mg-cycle: 1 (K) or 0 (V) fixes the cycle
 
 
 def defaults(fld, **kw):
-    return fld.default_options(mg_cycle=MG_CYCLE, **kw)
+    o = fld.default_options(**kw)
+    if MG_CYCLE is not None:
+        o.mg_cycle = MG_CYCLE
+    return o
 
 
 def options(fld, prec, tuned, norm=0):
     o = defaults(fld, precision=prec, norm=norm)
     if tuned is not None:
-        for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph"):
+        for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph", "mg_cycle"):
             setattr(o, k, getattr(tuned, k))
+    if MG_CYCLE is not None:
+        o.mg_cycle = MG_CYCLE
     return o
 
 
@@ -289,7 +297,7 @@ def copy_calibration(torch):
 def main():
     global MG_CYCLE
     args = parse()
-    MG_CYCLE = 1 if args.mg_cycle == "k" else 0
+    MG_CYCLE = None if args.mg_cycle is None else (1 if args.mg_cycle == "k" else 0)
     if args.gpus != 1:
         print(json.dumps({"error": "only one GPU is supported: the solver has no multi-GPU path; "
                                    "blocks and rows would shard as separate solves per GPU"}), flush=True)

@@ -343,7 +343,8 @@ typedef struct {
 } fld_tune_entry;
 
 /* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
- * mg_coarse_max in {64, 256, 16} and chunk in {8, 16, 4}; precision, limiter,
+ * mg_cycle in {K, V} (line smoothers; POINT keeps base's), mg_coarse_max in
+ * {64, 256, 16} and chunk in {8, 16, 4} (45 candidates); precision, limiter,
  * norm and tolerances are those of base (NULL = defaults).  Each candidate
  * gets its own context and runs reps + 1 steps (the first untimed) from the
  * given E, T (device arrays, not modified; the trials run on scratch copies).

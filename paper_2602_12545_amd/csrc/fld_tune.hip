@@ -78,19 +78,25 @@ fld_status fld_tune(const fld_grid* grid, const fld_options* base, const double*
     if (hipMalloc(&s.E, n * sizeof(double)) != hipSuccess || hipMalloc(&s.T, n * sizeof(double)) != hipSuccess)
         return FLD_ENOMEM;
     // candidates: smoother schedule x coarsest-level size x CG chunk length
+    // x multigrid cycle (line smoothers only: point smoothing has no LDS
+    // sub-cycle, so the cycle does not change it)
     std::vector<fld_options> cand;
     const bool lines_fit = grid->nx <= 4096 && grid->ny <= 4096;
     for (int sm : {FLD_SMOOTH_LINE, FLD_SMOOTH_LINE_SPLIT, FLD_SMOOTH_POINT}) {
         if (sm != FLD_SMOOTH_POINT && !lines_fit) continue;
-        for (int cm : {64, 256, 16})
-            for (int ch : {8, 16, 4}) {
-                fld_options o = b0;
-                o.smoother = sm;
-                o.mg_coarse_max = cm;
-                o.chunk = ch;
-                o.use_graph = 1;
-                cand.push_back(o);
-            }
+        for (int cy : {FLD_MG_CYCLE_K, FLD_MG_CYCLE_V}) {
+            if (sm == FLD_SMOOTH_POINT && cy != b0.mg_cycle) continue;
+            for (int cm : {64, 256, 16})
+                for (int ch : {8, 16, 4}) {
+                    fld_options o = b0;
+                    o.smoother = sm;
+                    o.mg_cycle = cy;
+                    o.mg_coarse_max = cm;
+                    o.chunk = ch;
+                    o.use_graph = 1;
+                    cand.push_back(o);
+                }
+        }
     }
     int32_t cnt = 0;
     float best_ms = INFINITY;

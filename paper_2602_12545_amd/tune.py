@@ -17,7 +17,7 @@ from ._binding import (FLDError, FLD_OK, _P, _I, _D, _ptr, _stream_handle, defau
                        fld_options, fld_tune_entry, lib)
 
 _NUMERIC = ("precision", "limiter", "norm", "rel_tol", "max_inner", "inner_rtol")
-_TUNED = ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph")
+_TUNED = ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph", "mg_cycle")
 
 
 def _opt_dict(o: fld_options) -> dict:

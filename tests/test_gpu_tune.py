@@ -20,13 +20,14 @@ def test_tune_grid_picks_a_converging_configuration(lib, tmp_path):
     path = str(tmp_path / "t.json")
     best, table = tune.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                  [(b.kind, b.value) for b in prob.bc], f, prob.dt, base=base, reps=1, cache=path)
-    assert len(table) == 27
+    # 2 line smoothers x 2 cycles x 9, and point smoothing x 9
+    assert len(table) == 45
     ok = [e for e in table if e["status"] == 0]
     chosen = [e for e in ok if all(e["options"][k] == getattr(best, k) for k in e["options"])]
     assert chosen and chosen[0]["ms"] == min(e["ms"] for e in ok)
     # inputs untouched by the trials
     assert np.array_equal(f["E"].cpu().numpy(), prob.E)
-    opts = {k: getattr(best, k) for k in ("smoother", "mg_coarse_max", "chunk")}
+    opts = {k: getattr(best, k) for k in ("smoother", "mg_coarse_max", "chunk", "mg_cycle")}
     E, T, info = gpu_step(lib, torch, prob, precision="mixed", rel_tol=1e-12, norm=1, **opts)
     assert info["status"] == 0
     r = O.step_problem(prob)

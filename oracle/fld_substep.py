@@ -8,7 +8,8 @@ sub-step and adds nothing but the choice of the sub-step lengths:
 * Prescribed geometric series (Section 3.2.1, sub-timestep equation): for a
   step Delta t split into n sub-steps with geometric factor q,
       dt_i = dt_0 q^(i-1),  i = 1..n,   dt_0 = Delta t (1 - q) / (1 - q^n);
-  q = 1 is read as the limit of that formula, n equal sub-steps Delta t / n.
+  q = 1 is read as the limit of that formula, n equal sub-steps Delta t / n;
+  n = 1 is the step itself, dt_0 = Delta t exactly.
 * Coupling-limited sub-steps (Section 3.2.1, global sub-step equation):
       dt = min(Delta t_remain, min over cells of dbar T C_V / |G0|),
       G0 = kappa_P rho c (a_R T^4 - E),
@@ -42,6 +43,8 @@ def geometric_substeps(dt: float, q: float, n: int) -> np.ndarray:
     if n < 1 or not (q > 0.0) or not (dt > 0.0):
         raise ValueError("need n >= 1, q > 0, dt > 0")
     i = np.arange(1, n + 1, dtype=np.float64)
+    if n == 1:
+        return np.array([float(dt)])  # dt_0 = dt exactly (the formula's quotient rounds)
     if q == 1.0:
         return np.full(n, dt / n)
     dt0 = dt * (1.0 - q) / (1.0 - q ** n)

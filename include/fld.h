@@ -221,6 +221,33 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, con
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);
 
+/* One radiation step of length dt taken as sub-steps (Section 3.2.1, the
+ * sub-step rules that follow the gas-energy linearisation), each an fld_step
+ * of its own length with the opacities, rho and c_v held fixed and E, T
+ * advanced in place:
+ *   dbar == 0: the prescribed geometric series dt_i = dt_0 q^(i-1),
+ *              i = 1..n_sub, dt_0 = dt (1 - q) / (1 - q^n_sub) (the paper asks
+ *              for 1 < q < 2; any q > 0 is accepted, q = 1 giving n_sub equal
+ *              sub-steps and n_sub = 1 the step itself);
+ *   dbar > 0:  coupling-limited sub-steps dt_k = min(dt_remaining,
+ *              min over cells of dbar T C_V / |G0|), G0 = kappa_P rho c
+ *              (a_R T^4 - E), C_V = rho c_v, from the state at the start of
+ *              each sub-step (a cell with G0 = 0 does not limit; the paper
+ *              suggests dbar < 0.1); the loop ends once the remaining time is
+ *              at most 1e-12 dt.  Each sub-step's limit is a device reduction
+ *              read back by the host.
+ * dts, per_sub (host arrays of max_sub entries, may be NULL) receive each
+ * sub-step's length and solve record; *n_done (may be NULL) the number of
+ * sub-steps taken.  Returns EINVAL for bad parameters (max_sub < 1, dbar < 0,
+ * geometric with n_sub outside 1..max_sub or q <= 0) or fields, ENOCONV if the
+ * coupling-limited loop needs more than max_sub sub-steps (E, T then hold the
+ * state after max_sub of them), ENONFINITE if a limit is not positive, else
+ * the first failing sub-step's status (the later ones are not taken). */
+fld_status fld_substep(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, const double* kappa_R,
+                       const double* kappa_P, const double* c_v, const double* ghost_E, double dt, int32_t n_sub,
+                       double q, double dbar, int32_t max_sub, double* dts, fld_solve_info* per_sub,
+                       int32_t* n_done);
+
 /* Copies the assembled FP64 operator of the last fld_assemble to caller device
  * arrays of nx*ny doubles (any may be NULL): W_e[j][i] = conductance of the
  * face between cells i and i+1 (0 in the last column), W_n[j][i] = face between

@@ -78,6 +78,8 @@ _SIGS = {
     "fld_gas_update": (_I, [_P, _P, _P]),
     "fld_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_substep": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _D, _D, _I, ctypes.POINTER(_D),
+                         ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I)]),
     "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
     "fld_mg_levels": (_I, [_P]),
     "fld_profile": (_I, [_P, _I]),
@@ -206,6 +208,23 @@ class Context:
         if check:
             self._check(st)
         return [infos[k].as_dict() for k in range(nsteps)]
+
+    def substep(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, n_sub=1, q=1.0, dbar=0.0,
+                max_sub=10000, check=True):
+        """One step of length dt as sub-steps: the geometric series (n_sub, q)
+        when dbar == 0, else coupling-limited with factor dbar.  Returns
+        {"status", "dts", "infos"} (one entry per sub-step taken)."""
+        cap = max(1, int(max_sub))
+        dts = (ctypes.c_double * cap)()
+        infos = (fld_solve_info * cap)()
+        n = _I()
+        st = lib.fld_substep(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P), _ptr(c_v),
+                             _ptr(ghost_E), float(dt), int(n_sub), float(q), float(dbar), int(max_sub), dts, infos,
+                             ctypes.byref(n))
+        if check:
+            self._check(st)
+        return {"status": st, "dts": [dts[k] for k in range(n.value)],
+                "infos": [infos[k].as_dict() for k in range(n.value)]}
 
     def get_operator(self):
         import torch

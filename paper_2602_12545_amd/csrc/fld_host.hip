@@ -102,6 +102,7 @@ struct fld_ctx {
     // assembled FP64 operator
     double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
+    double* dt_lim = nullptr;  // device: coupling-limited sub-step length (fld_substep)
     std::vector<Level64> h64;
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
@@ -201,6 +202,33 @@ fld_status validate_options(const fld_options* o, std::string& err) {
 // ---------------------------------------------------------------------------
 // V-cycle and CG slot (queued on stream `st`)
 // ---------------------------------------------------------------------------
+
+// Coupling-limited sub-step length (Section 3.2.1, global sub-step rule):
+// per-workgroup minimum over the cells of dbar T C_V / |G0| with
+// G0 = kappa_P rho c (a_R T^4 - E) and C_V = rho c_v; a cell in exact
+// equilibrium (G0 = 0) does not limit.
+__global__ __launch_bounds__(256) void k_coupling_dt(int n, const double* __restrict__ E, const double* __restrict__ T,
+                                                     const double* __restrict__ rho, const double* __restrict__ kP,
+                                                     const double* __restrict__ cv, double dbar, double* part) {
+    __shared__ double sh[16];
+    double v = INFINITY;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const double t = T[c], t2 = t * t;
+        const double g = kP[c] * rho[c] * kC * (kARad * (t2 * t2) - E[c]);
+        if (g != 0.0) v = fmin(v, dbar * t * (rho[c] * cv[c]) / fabs(g));
+    }
+    const double m = block_min(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Minimum of nb partials into *out (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_reduce_min(const double* part, int nb, double* out) {
+    __shared__ double sh[16];
+    double v = INFINITY;
+    for (int b = threadIdx.x; b < nb; b += 1024) v = fmin(v, part[b]);
+    const double m = block_min(v, sh);
+    if (threadIdx.x == 0) *out = m;
+}
 
 inline bool is_line(const fld_options& o) { return o.smoother == FLD_SMOOTH_LINE || o.smoother == FLD_SMOOTH_LINE_SPLIT; }
 
@@ -1099,6 +1127,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->sc_sweep, 1);
     ALLOC(ctx->err_flag, 1);
     ALLOC(ctx->mu, 1);
+    ALLOC(ctx->dt_lim, 1);
 #undef ALLOC
     if (hipHostMalloc((void**)&ctx->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned scalars");
@@ -1290,6 +1319,64 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     }
     ctx->assembled = true;
     return firstbad;
+}
+
+fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
+                       const double* cv, const double* ghost, double dt, int32_t n_sub, double q, double dbar,
+                       int32_t max_sub, double* dts, fld_solve_info* per_sub, int32_t* n_done) {
+    if (!ctx) return FLD_EINVAL;
+    if (n_done) *n_done = 0;
+    if (max_sub < 1) { ctx->err = "max_sub must be >= 1"; return FLD_EINVAL; }
+    if (!(dbar >= 0.0) || !std::isfinite(dbar)) { ctx->err = "dbar must be finite and >= 0"; return FLD_EINVAL; }
+    if (dbar == 0.0 && (n_sub < 1 || n_sub > max_sub || !(q > 0.0) || !std::isfinite(q))) {
+        ctx->err = "geometric sub-steps need 1 <= n_sub <= max_sub and q > 0";
+        return FLD_EINVAL;
+    }
+    fld_status s = check_fields(ctx, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    auto sub = [&](int k, double h) -> fld_status {
+        fld_solve_info inf{};
+        const fld_status sk = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, h, &inf);
+        if (per_sub) per_sub[k] = inf;
+        if (dts) dts[k] = h;
+        if (n_done) *n_done = k + 1;
+        return sk;
+    };
+    if (dbar == 0.0) {
+        // geometric series dt_i = dt_0 q^(i-1), dt_0 = dt (1 - q) / (1 - q^n)
+        // n_sub = 1 is the step itself (the quotient would round)
+        const double dt0 = n_sub == 1 ? dt : q == 1.0 ? dt / n_sub : dt * (1.0 - q) / (1.0 - std::pow(q, (double)n_sub));
+        for (int k = 0; k < n_sub; ++k) {
+            const fld_status sk = sub(k, (q == 1.0 || n_sub == 1) ? dt0 : dt0 * std::pow(q, (double)k));
+            if (sk != FLD_OK) return sk;
+        }
+        return FLD_OK;
+    }
+    // coupling-limited: dt_k = min(remaining, min over cells dbar T C_V / |G0|)
+    const int n = ctx->nx * ctx->ny;
+    const int nb = grid1d(n);
+    double remain = dt;
+    for (int k = 0; remain > 1e-12 * dt; ++k) {
+        if (k == max_sub) {
+            ctx->err = "coupling-limited sub-steps exceed max_sub";
+            return FLD_ENOCONV;
+        }
+        k_coupling_dt<<<nb, 256, 0, ctx->stream>>>(n, E, T, rho, kP, cv, dbar, ctx->part2);
+        k_reduce_min<<<1, 1024, 0, ctx->stream>>>(ctx->part2, nb, ctx->dt_lim);
+        HIPCHK(hipGetLastError());
+        double lim = 0.0;
+        HIPCHK(hipMemcpyAsync(&lim, ctx->dt_lim, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const double h = std::min(remain, lim);
+        if (!(h > 0.0)) {
+            ctx->err = "coupling-limited sub-step is not positive (T <= 0 or non-finite fields)";
+            return FLD_ENONFINITE;
+        }
+        const fld_status sk = sub(k, h);
+        if (sk != FLD_OK) return sk;
+        remain -= h;
+    }
+    return FLD_OK;
 }
 
 fld_status fld_get_operator(fld_ctx* ctx, double* We, double* Wn, double* diag, double* rhs) {

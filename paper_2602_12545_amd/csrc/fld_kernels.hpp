@@ -66,6 +66,21 @@ __device__ inline double block_max(double v, double* sh) {
     return r;
 }
 
+// Minimum over the workgroup; the result is valid in thread 0.
+__device__ inline double block_min(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    const int t = ltid();
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    double r = INFINITY;
+    if (t == 0) {
+        const int nw = (lsize() + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r = fmin(r, sh[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
 __device__ inline unsigned nblocks2d() { return gridDim.x * gridDim.y; }
 __device__ inline unsigned bid2d() { return blockIdx.y * gridDim.x + blockIdx.x; }
 

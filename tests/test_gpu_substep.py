@@ -1,0 +1,144 @@
+"""Sub-cycled radiation step (Section 3.2.1 sub-step rules) through the C ABI
+(fld_substep) against the oracle's sub-cycled step: the geometric series and
+coupling-limited sub-steps on perturbed workload grids (the recipes start in
+equilibrium, where the coupling does not limit), the paper's 0D coupling
+set-up (Section 5.1.1), a single sub-step equal to fld_step, and the error
+paths."""
+import math
+
+import numpy as np
+import pytest
+
+import fld_workloads as W
+from oracle import fld_oracle as O
+from oracle import fld_substep as S
+from gpu_helpers import make_ctx, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+K_B = 1.380649e-16
+M_H = 1.6735575e-24
+
+
+def perturbed(name, seed=7, **kw):
+    prob = W.make(name, **kw)
+    rng = np.random.default_rng(seed)
+    prob.T = prob.T * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, prob.T.shape))
+    return prob
+
+
+def gpu_substep(fld, prob, sub, **opt):
+    ctx = make_ctx(fld, prob, **opt)
+    t = to_dev(prob, torch)
+    r = ctx.substep(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, ghost_E=t["ghost_E"],
+                    check=False, **sub)
+    torch.cuda.synchronize()
+    out = t["E"].cpu().numpy(), t["T"].cpu().numpy(), r
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("name,kw,prec,norm", [
+    ("c1", dict(nx=48, ny=40), "mixed", 0),
+    ("c5", dict(nx=64, ny=48), "fp64", 1),
+])
+def test_geometric_substeps_match_oracle(lib, name, kw, prec, norm):
+    prob = perturbed(name, **kw)
+    E, T, r = gpu_substep(lib, prob, dict(n_sub=5, q=1.5), precision=prec, norm=norm, rel_tol=1e-12)
+    assert r["status"] == 0 and all(i["status"] == 0 for i in r["infos"])
+    np.testing.assert_allclose(r["dts"], S.geometric_substeps(prob.dt, 1.5, 5), rtol=1e-15)
+    ref = S.substep_problem(prob, n_sub=5, q=1.5)
+    assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10
+
+
+@pytest.mark.parametrize("name,kw,dbar,prec,norm", [
+    ("c1", dict(nx=48, ny=40), 0.05, "mixed", 0),
+    ("c1", dict(nx=48, ny=40), 0.05, "fp64", 1),
+])
+def test_coupling_limited_substeps_match_oracle(lib, name, kw, dbar, prec, norm):
+    """The sub-step count is decided by comparisons of each side's own limits;
+    the limits agree to the solves' accuracy, so the counts agree exactly.
+    Each sub-step's solve error is carried into the next limit and step, so
+    the bound on the final fields is looser than one step's."""
+    prob = perturbed(name, **kw)
+    E, T, r = gpu_substep(lib, prob, dict(dbar=dbar, max_sub=2000), precision=prec, norm=norm, rel_tol=1e-12)
+    ref = S.substep_problem(prob, dbar=dbar, max_sub=2000)
+    print(name, prec, "sub-steps", len(r["dts"]), len(ref.dts), flush=True)
+    assert r["status"] == 0
+    assert len(r["dts"]) == len(ref.dts) > 10
+    np.testing.assert_allclose(r["dts"], ref.dts, rtol=1e-8)
+    assert math.fsum(r["dts"]) == pytest.approx(prob.dt, rel=1e-12)
+    assert rel_l2(E, ref.E) < 1e-9 and rel_l2(T, ref.T) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_coupling_limited_substeps_ill_conditioned(lib, prec):
+    """c5 (1e8 opacity contrast) relaxes to equilibrium over ~200 sub-steps.
+    Near equilibrium G0 is a small difference of a_R T^4 and E, so the limit
+    amplifies the iterative solves' ~1e-12 errors: the GPU and oracle
+    sequences (direct solves) part after a few dozen sub-steps (also in FP64;
+    later the tighter the solve), and both remain valid runs of the rule.
+    Compared: the unique early sub-steps; checked: the sum, the count, and the
+    fields to the scheme's own sensitivity to its sub-step sequence."""
+    prob = perturbed("c5", nx=64, ny=48)
+    E, T, r = gpu_substep(lib, prob, dict(dbar=0.2, max_sub=2000), precision=prec, norm=1, rel_tol=1e-12)
+    ref = S.substep_problem(prob, dbar=0.2, max_sub=2000)
+    print("c5", prec, "sub-steps", len(r["dts"]), len(ref.dts), rel_l2(E, ref.E), rel_l2(T, ref.T), flush=True)
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["dts"][:20], ref.dts[:20], rtol=1e-8)
+    assert math.fsum(r["dts"]) == pytest.approx(prob.dt, rel=1e-12)
+    assert abs(len(r["dts"]) - len(ref.dts)) <= 0.15 * len(ref.dts)
+    assert rel_l2(E, ref.E) < 2e-2 and rel_l2(T, ref.T) < 2e-2
+
+
+def e1_problem(eg0, nx=16):
+    """The paper's 0D coupling set-up: uniform E = 1e12, rho = 1e-7, kappa_P =
+    0.4, e_g = 3 rho k_B T / (2 mu m_H) with mu = 0.6, reflecting walls."""
+    rho, kP, mu = 1e-7, 0.4, 0.6
+    cv = 3.0 * K_B / (2.0 * mu * M_H)
+    shape = (1, nx)
+    return W.Problem("e1", W.GEOM_CARTESIAN, np.linspace(0.0, 1.0, nx + 1), np.linspace(0.0, 1.0, 2),
+                     np.full(shape, 1e12), np.full(shape, eg0 / (rho * cv)), np.full(shape, rho),
+                     np.full(shape, 1e10 / rho), np.full(shape, kP), np.full(shape, cv), 3e-7, [W.BC()] * 4), cv
+
+
+def test_e1_coupling_limited_on_gpu(lib):
+    prob, cv = e1_problem(1e10)
+    E, T, r = gpu_substep(lib, prob, dict(dbar=0.04, max_sub=1000), precision="fp64", norm=1, rel_tol=1e-12)
+    ref = S.substep_problem(prob, dbar=0.04, max_sub=1000)
+    assert r["status"] == 0 and len(r["dts"]) == len(ref.dts) > 100
+    np.testing.assert_allclose(r["dts"], ref.dts, rtol=1e-8)
+    np.testing.assert_allclose(T, ref.T, rtol=1e-9)
+    np.testing.assert_allclose(E, ref.E, rtol=1e-9)
+    assert np.ptp(T) <= 1e-12 * T.max()
+
+
+def test_single_substep_equals_step(lib):
+    prob = perturbed("c1", nx=40, ny=33)
+    E1, T1, r = gpu_substep(lib, prob, dict(n_sub=1, q=1.7))
+    assert r["dts"] == [prob.dt]
+    ctx = make_ctx(lib, prob)
+    t = to_dev(prob, torch)
+    ctx.step(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"], check=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(E1, t["E"].cpu().numpy()) and np.array_equal(T1, t["T"].cpu().numpy())
+    ctx.close()
+
+
+def test_substep_errors(lib):
+    prob = perturbed("c1", nx=24, ny=20)
+    ctx = make_ctx(lib, prob)
+    t = to_dev(prob, torch)
+    args = (t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt)
+    for bad in (dict(max_sub=0), dict(dbar=-0.1), dict(n_sub=0), dict(n_sub=5, max_sub=4), dict(n_sub=3, q=0.0),
+                dict(dbar=float("nan"))):
+        r = ctx.substep(*args, check=False, **bad)
+        assert r["status"] == lib.FLD_EINVAL and r["dts"] == [], bad
+    # fields untouched by the rejected calls
+    assert np.array_equal(t["T"].cpu().numpy(), prob.T)
+    r = ctx.substep(*args, dbar=0.05, max_sub=3, check=False)
+    assert r["status"] == lib.FLD_ENOCONV and len(r["dts"]) == 3
+    assert all(i["status"] == 0 for i in r["infos"])
+    ctx.close()

@@ -36,7 +36,8 @@ paper leaves open (all listed in the design notes):
   contradicts F = -D grad E and phi_5 = 1 - phi_1 - ...).
 * The exchange sign follows the conservation laws of Section 2 and the
   phi/psi list (not the sign written in the time-discrete pair).
-* kappa_e = kappa_P (Section 2, emissivity paragraph); S_g = 0; S_adv = 0.
+* kappa_e = kappa_P (Section 2, emissivity paragraph); S_g = 0; S_adv = 0
+  unless face mass fluxes are given (``advection_volume_term``).
 * C_V is per unit volume; inputs give c_v per gram, so C_V = rho c_v.
 * Interface sigma = kappa_R rho is the distance-weighted mean of the two
   cells (harmonic mean of the diffusivities); interface E is the linear
@@ -286,9 +287,32 @@ def boundary_terms(kind, value, ghost, E1, sig1, h1, dS, dt, lim):
     raise ValueError("unknown boundary kind")
 
 
+def advection_volume_term(met: Metrics, E, rho, fx, fy) -> np.ndarray:
+    """dV S_adv of every cell (Section 3.2.1 advection term, explicit in time):
+    the sum over the cell's faces of +-dS f e_r, inflow through the lower x and
+    y faces positive, outflow through the upper ones negative, with f the
+    face mass flux (positive along +x / +y) and e_r = E / rho taken from the
+    upwind cell.  Reading: at a boundary face the boundary cell's own e_r is
+    used for either flow direction (zero-gradient e_r)."""
+    E = np.asarray(E, dtype=np.float64)
+    er = E / np.asarray(rho, dtype=np.float64)
+    fx = np.asarray(fx, dtype=np.float64).reshape(met.ny, met.nx + 1)
+    fy = np.asarray(fy, dtype=np.float64).reshape(met.ny + 1, met.nx)
+    # e_r of the cells below / above each face, the boundary cell repeated outside
+    er_lo_x = np.concatenate([er[:, :1], er], axis=1)
+    er_hi_x = np.concatenate([er, er[:, -1:]], axis=1)
+    er_lo_y = np.concatenate([er[:1, :], er], axis=0)
+    er_hi_y = np.concatenate([er, er[-1:, :]], axis=0)
+    tx = met.dSx * fx * np.where(fx >= 0.0, er_lo_x, er_hi_x)  # transport through x faces along +x
+    ty = met.dSy * fy * np.where(fy >= 0.0, er_lo_y, er_hi_y)
+    return (tx[:, :-1] - tx[:, 1:]) + (ty[:-1, :] - ty[1:, :])
+
+
 def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
-             bcs: Sequence[BCSpec], limiter: int = LIMITER_LP) -> Assembled:
-    """Build the volume-weighted, T-eliminated E system of one backward-Euler step."""
+             bcs: Sequence[BCSpec], limiter: int = LIMITER_LP, fx=None, fy=None) -> Assembled:
+    """Build the volume-weighted, T-eliminated E system of one backward-Euler
+    step.  fx [ny][nx+1], fy [ny+1][nx]: face mass fluxes rho v of the
+    advection term (None: S_adv = 0), added explicitly as dt dV S_adv."""
     lim = LIMITERS[limiter]
     met = metrics(geom, xf, yf)
     nx, ny = met.nx, met.ny
@@ -350,6 +374,10 @@ def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
     sumW = Wxi[:, :-1] + Wxi[:, 1:] + Wyi[:-1, :] + Wyi[1:, :]
     diag = met.dV * (1.0 + beta * f) + sumW + bdiag
     rhs = met.dV * (E + beta * f * A_RAD * T ** 4) + brhs
+    if fx is not None or fy is not None:
+        fx = np.zeros((ny, nx + 1)) if fx is None else fx
+        fy = np.zeros((ny + 1, nx)) if fy is None else fy
+        rhs = rhs + dt * advection_volume_term(met, E, rho, fx, fy)
     M = build_matrix(diag, Wxi, Wyi)
     return Assembled(met, W_x, W_y, D_x, D_y, diag, rhs, CV, beta, X, f, bdiag, brhs, M)
 
@@ -449,9 +477,10 @@ class StepResult:
     A: Assembled
 
 
-def step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, limiter=LIMITER_LP) -> StepResult:
+def step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, limiter=LIMITER_LP, fx=None,
+         fy=None) -> StepResult:
     """One implicit radiation step: assemble, solve, gas update."""
-    A = assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, limiter)
+    A = assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, limiter, fx, fy)
     E_new = solve(A)
     T_new = gas_update(A, T, E_new)
     return StepResult(E_new, T_new, A)
@@ -471,11 +500,11 @@ def bcs_from_problem(prob) -> List[BCSpec]:
     return out
 
 
-def step_problem(prob, E=None, T=None, limiter=LIMITER_LP) -> StepResult:
+def step_problem(prob, E=None, T=None, limiter=LIMITER_LP, fx=None, fy=None) -> StepResult:
     E = prob.E if E is None else E
     T = prob.T if T is None else T
     return step(prob.geom, prob.x_faces, prob.y_faces, E, T, prob.rho, prob.kappa_R, prob.kappa_P,
-                prob.c_v, prob.dt, bcs_from_problem(prob), limiter)
+                prob.c_v, prob.dt, bcs_from_problem(prob), limiter, fx, fy)
 
 
 def assemble_problem(prob, E=None, T=None, limiter=LIMITER_LP) -> Assembled:

@@ -248,6 +248,23 @@ fld_status fld_substep(fld_ctx* ctx, double* E_r, double* T_g, const double* rho
                        double q, double dbar, int32_t max_sub, double* dts, fld_solve_info* per_sub,
                        int32_t* n_done);
 
+/* Face mass fluxes f = rho v of the explicit radiation advection term
+ * (Section 3.2.1 advection equation; the mass fluxes come from the hydro
+ * step's Riemann solutions): every later assembly of this context (fld_assemble,
+ * fld_step, fld_steps, fld_substep) adds dt dV S_adv to its right-hand side,
+ * dV S_adv = sum over the cell's faces of +-dS f e_r (inflow through the
+ * lower x / y face positive), e_r = E / rho taken from the upwind cell and,
+ * at a boundary face, from the boundary cell itself (zero-gradient e_r).
+ * fx: device array [ny][nx+1], the flux through x face i of row j (face i
+ * lies below cell i along x; positive along +x); fy: [ny+1][nx], through y
+ * face j below cell row j (positive along +y).  Either may be NULL (no flux
+ * in that direction); both NULL turns advection off (the default).  The
+ * arrays stay owned by the caller and are read at each assembly, so they
+ * must stay valid (and hold finite values: else the assembly reports
+ * ENONFINITE) while set; a multi-step graph reads the arrays set when
+ * fld_steps was called.  Returns EINVAL for a NULL ctx. */
+fld_status fld_set_mass_flux(fld_ctx* ctx, const double* fx, const double* fy);
+
 /* Copies the assembled FP64 operator of the last fld_assemble to caller device
  * arrays of nx*ny doubles (any may be NULL): W_e[j][i] = conductance of the
  * face between cells i and i+1 (0 in the last column), W_n[j][i] = face between

@@ -80,6 +80,7 @@ _SIGS = {
     "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_substep": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _D, _D, _I, ctypes.POINTER(_D),
                          ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I)]),
+    "fld_set_mass_flux": (_I, [_P, _P, _P]),
     "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
     "fld_mg_levels": (_I, [_P]),
     "fld_profile": (_I, [_P, _I]),
@@ -225,6 +226,12 @@ class Context:
             self._check(st)
         return {"status": st, "dts": [dts[k] for k in range(n.value)],
                 "infos": [infos[k].as_dict() for k in range(n.value)]}
+
+    def set_mass_flux(self, fx=None, fy=None):
+        """Face mass fluxes of the explicit advection term (device tensors
+        [ny][nx+1] and [ny+1][nx], or None); kept referenced while set."""
+        self._check(lib.fld_set_mass_flux(self.handle, _ptr(fx), _ptr(fy)))
+        self._mass_flux = (fx, fy)
 
     def get_operator(self):
         import torch

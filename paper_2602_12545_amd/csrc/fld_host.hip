@@ -103,6 +103,7 @@ struct fld_ctx {
     double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
     double* dt_lim = nullptr;  // device: coupling-limited sub-step length (fld_substep)
+    const double *fx = nullptr, *fy = nullptr;  // caller's face mass fluxes (fld_set_mass_flux)
     std::vector<Level64> h64;
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
@@ -798,7 +799,7 @@ fld_status check_fields(fld_ctx* ctx, const double* E, const double* T, const do
 fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
                             const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st) {
     k_zero_int<<<1, 1, 0, st>>>(ctx->err_flag);
-    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc};
+    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc, ctx->fx, ctx->fy};
     AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part};
     const dim3 ag = cell_grid(ctx->nx, ctx->ny);
     k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
@@ -1376,6 +1377,13 @@ fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, co
         if (sk != FLD_OK) return sk;
         remain -= h;
     }
+    return FLD_OK;
+}
+
+fld_status fld_set_mass_flux(fld_ctx* ctx, const double* fx, const double* fy) {
+    if (!ctx) return FLD_EINVAL;
+    ctx->fx = fx;
+    ctx->fy = fy;
     return FLD_OK;
 }
 

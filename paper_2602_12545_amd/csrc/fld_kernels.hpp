@@ -227,6 +227,7 @@ struct AsmIn {
     double dt;
     int lim;
     BCDev bc;
+    const double *fx, *fy;  // face mass fluxes of the advection term ([ny][nx+1], [ny+1][nx]); null: none
 };
 struct AsmOut {
     double *We, *Wn, *m, *rhs, *s;
@@ -290,10 +291,28 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
     const double mass = dV * (1.0 + beta * f);
     const double sumW = ((Ww + We) + Ws) + Wn;
     const double diag = mass + sumW + bd;
+    // explicit advection (Section 3.2.1 advection term): dV S_adv = sum over
+    // the faces of +-dS f e_r, e_r = E / rho of the upwind cell, the boundary
+    // cell's own e_r outside the grid; added as dt dV S_adv
+    double adv = 0.0;
+    if (in.fx) {
+        const size_t fc = (size_t)j * (nx + 1) + i;
+        const double flo = in.fx[fc], fhi = in.fx[fc + 1], er = E / rho;
+        const double erlo = i > 0 ? in.E[c - 1] / in.rho[c - 1] : er;
+        const double erhi = i + 1 < nx ? in.E[c + 1] / in.rho[c + 1] : er;
+        adv += g.sx[i] * vyj * flo * (flo >= 0.0 ? erlo : er) - g.sx[i + 1] * vyj * fhi * (fhi >= 0.0 ? er : erhi);
+    }
+    if (in.fy) {
+        const double flo = in.fy[c], fhi = in.fy[c + nx], er = E / rho;
+        const double erlo = j > 0 ? in.E[c - nx] / in.rho[c - nx] : er;
+        const double erhi = j + 1 < ny ? in.E[c + nx] / in.rho[c + nx] : er;
+        adv += axi * g.sy[j] * flo * (flo >= 0.0 ? erlo : er) - axi * g.sy[j + 1] * fhi * (fhi >= 0.0 ? er : erhi);
+    }
+    if (!isfinite(adv)) atomicOr(out.err, 1);
     out.We[c] = We;
     out.Wn[c] = Wn;
     out.m[c] = mass + bd;
-    out.rhs[c] = dV * (E + beta * f * kARad * T3 * T) + br;
+    out.rhs[c] = (dV * (E + beta * f * kARad * T3 * T) + br) + dt * adv;
     out.s[c] = 1.0 / sqrt(diag);
     return diag;
 }

@@ -25,7 +25,7 @@ needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libfld.so not bu
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_gas_update",
+    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_set_mass_flux", "fld_gas_update",
               "fld_get_operator", "fld_destroy", "fld_default_options", "fld_batch_create", "fld_batch_step",
               "fld_batch_steps", "fld_batch_destroy"):
         assert f in names
@@ -50,6 +50,8 @@ def test_host_only_entry_points_run_without_gpu():
     assert lib.fld_status_string(4) == b"tolerance not reached"
     lib.fld_create.restype = ctypes.c_int32
     assert lib.fld_create(None, None, None, None) == 1  # EINVAL before any device call
+    lib.fld_set_mass_flux.restype = ctypes.c_int32
+    assert lib.fld_set_mass_flux(None, None, None) == 1
     lib.fld_substep.restype = ctypes.c_int32
     n_done = ctypes.c_int32(7)
     assert lib.fld_substep(None, None, None, None, None, None, None, None, ctypes.c_double(1.0), 1,

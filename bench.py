@@ -316,6 +316,66 @@ def substep_extra(fld, torch, W, tuned):
     return out
 
 
+def advection_extra(fld, torch, W, tuned):
+    """Radiation advection (fld_set_mass_flux): the dynamical-diffusion test
+    (1024 cells on [-2, 14] cm, v = 1.8 km/s, rho kappa_R = 1e7 / cm,
+    kappa_P = 0, CFL 1, 714 steps to t = 6.2e-5 s) as one fld_steps call, its
+    L1 error against the analytic moving Gaussian; and the 1024 x 1024
+    stretched Cartesian step with a uniform +x mass flux (|f| dt dS / dV at
+    most 0.5 rho)."""
+    import numpy as np
+    out = {}
+    N, v, sig, E0 = 1024, 1.8e5, 1e7, 2e5
+    xf = np.linspace(-2.0, 14.0, N + 1)
+    dx = xf[1] - xf[0]
+    xc = 0.5 * (xf[1:] + xf[:-1])
+    one = np.ones((1, N))
+    prob = W.Problem("e4", W.GEOM_CARTESIAN, xf, np.array([0.0, 1.0]),
+                     np.where(np.abs(xc) < dx, E0 / (2 * dx), 1.0)[None, :], 0.1 * one, one.copy(), sig * one,
+                     0.0 * one, one.copy(), dx / v, [W.BC()] * 4)
+    n = int(round(6.2e-5 / prob.dt))
+    f = dev_fields(torch, prob)
+    fx = torch.full((1, N + 1), v, dtype=torch.float64, device="cuda")
+    fy = torch.zeros((2, N), dtype=torch.float64, device="cuda")
+    ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces, [(b.kind, b.value) for b in prob.bc],
+                      defaults(fld, precision="mixed", norm=1, rel_tol=1e-12))
+    ctx.set_mass_flux(fx, fy)
+    E, T = f["E"].clone(), f["T"].clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = ctx.steps(n, E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, check=False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    ctx.close()
+    tt = n * prob.dt
+    D = 2.99792458e10 / (3 * sig)
+    Ea = 1 + E0 / np.sqrt(4 * D * np.pi * tt) * np.exp(-(xc - v * tt) ** 2 / (4 * D * tt))
+    Eg = E.cpu().numpy()[0]
+    out["dynamical_diffusion_1024"] = {"steps": n, "ms_total": ms, "ms_per_step": ms / n,
+                                       "l1_error_vs_analytic": float(np.sum(np.abs(Eg - Ea)) / np.sum(Ea - 1)),
+                                       "status": sorted(set(i["status"] for i in infos))}
+    prob = W.make_c2()
+    f = dev_fields(torch, prob)
+    ny, nx = prob.E.shape
+    dxs = np.diff(prob.x_faces)
+    fxv = np.broadcast_to((0.5 * float(np.median(prob.rho)) * float(dxs.min()) / prob.dt), (ny, nx + 1))
+    ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces, [(b.kind, b.value) for b in prob.bc],
+                      options(fld, "mixed", tuned))
+    ctx.set_mass_flux(torch.tensor(np.ascontiguousarray(fxv), dtype=torch.float64, device="cuda"), None)
+    ms = []
+    for rep in range(4):
+        E, T = f["E"].clone(), f["T"].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, check=False)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    ctx.close()
+    out["c2_with_flux"] = {"ms_per_step": float(np.min(ms[1:])), "inner_iters": info["inner_iters"],
+                           "status": info["status"]}
+    return out
+
+
 def copy_calibration(torch):
     n = 512 * 1024 * 1024 // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -420,6 +480,7 @@ def main():
         out["batched_blocks"] = batch_extra(fld, torch, W, None if args.no_tune else tuner)
         out["stress_multistep"] = stress_extra(fld, torch, W)
         out["substep"] = substep_extra(fld, torch, W, tuned)
+        out["advection"] = advection_extra(fld, torch, W, tuned)
     if not args.no_cpu and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)

@@ -42,6 +42,7 @@ BC_DIRICHLET_GHOST = 2
 BC_FLUX_IN = 3
 BC_FREE_STREAM = 4
 BC_AXIS = 5
+BC_MILNE = 6
 
 GEOM_CARTESIAN = 0
 GEOM_SPHERICAL = 1

@@ -69,7 +69,7 @@ SIGMA_SB = 5.670374419e-5        # erg cm^-2 s^-1 K^-4
 A_RAD = 4.0 * SIGMA_SB / C_LIGHT  # radiation constant a_R, erg cm^-3 K^-4
 
 CARTESIAN, SPHERICAL = 0, 1
-REFLECT, DIRICHLET_FACE, DIRICHLET_GHOST, FLUX_IN, FREE_STREAM, AXIS = range(6)
+REFLECT, DIRICHLET_FACE, DIRICHLET_GHOST, FLUX_IN, FREE_STREAM, AXIS, MILNE = range(7)
 LIMITER_LP, LIMITER_MINERBO, LIMITER_DIFFUSION = range(3)
 
 
@@ -261,6 +261,12 @@ def boundary_terms(kind, value, ghost, E1, sig1, h1, dS, dt, lim):
                           sigma_f = sigma_1, E_f = (E_1 + E_g)/2; rhs += W_b E_g.
       fixed inward flux : rhs += dt dS F_in.
       free streaming    : outward flux c E_1, diag += dt dS c.
+      Milne             : E_b = -2/(3 sigma_1) dE/dn on the face (Section 5.2 radiative
+                          shock set-up, the blackbody-absorber condition), the
+                          outward derivative taken as (E_b - E_1)/h1: E_b = a E_1/(1+a),
+                          a = 2/(3 sigma_1 h1); the face's R = |grad E|/(sigma_1 E_b) is
+                          3/2 exactly, D = c lambda(3/2)/sigma_1; outward flux
+                          D E_1/(h1 (1+a)): diag += dt dS D/(h1 (1+a)).
     Returns (diag_add, rhs_add, W_b, D_b).
     """
     z = np.zeros_like(E1)
@@ -284,6 +290,11 @@ def boundary_terms(kind, value, ghost, E1, sig1, h1, dS, dt, lim):
         return z, dt * dS * value, z, z
     if kind == FREE_STREAM:
         return dt * dS * C_LIGHT, z, z, z
+    if kind == MILNE:
+        a = 2.0 / (3.0 * sig1 * h1)
+        D = C_LIGHT * lim(np.full_like(sig1, 1.5)) / sig1
+        Wb = dt * dS * D / (h1 * (1.0 + a))
+        return Wb, z, Wb, D
     raise ValueError("unknown boundary kind")
 
 

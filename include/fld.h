@@ -65,10 +65,16 @@ typedef enum { FLD_CARTESIAN = 0, FLD_SPHERICAL_POLAR = 1 } fld_geom;
  *                   ghost_E array passed to fld_assemble / fld_step.
  *   FLUX_IN         fixed inward flux, value = F_in [erg cm^-2 s^-1].
  *   FREE_STREAM     outward flux c E of the first cell.
- *   AXIS            theta = 0 or pi of a spherical-polar grid: zero area, zero flux. */
+ *   AXIS            theta = 0 or pi of a spherical-polar grid: zero area, zero flux.
+ *   MILNE           the paper's blackbody-absorber condition E = -2/(3 rho kappa_R)
+ *                   dE/dn on the face (Section 5.2, radiative shock with the
+ *                   hydrogen EoS), first cell's opacity, dE/dn = (E_b - E_1)/h1
+ *                   (h1: centre to face): outward flux D E_1/(h1 (1 + a)),
+ *                   a = 2/(3 sigma_1 h1), D = c lambda(3/2)/sigma_1 (R is 3/2
+ *                   on such a face); value unused.  Single grids only. */
 typedef enum {
     FLD_BC_REFLECT = 0, FLD_BC_DIRICHLET_FACE = 1, FLD_BC_DIRICHLET_GHOST = 2,
-    FLD_BC_FLUX_IN = 3, FLD_BC_FREE_STREAM = 4, FLD_BC_AXIS = 5
+    FLD_BC_FLUX_IN = 3, FLD_BC_FREE_STREAM = 4, FLD_BC_AXIS = 5, FLD_BC_MILNE = 6
 } fld_bc_kind;
 
 /* Side order in fld_grid.bc and in the packed ghost array:

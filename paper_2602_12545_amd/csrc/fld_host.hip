@@ -1071,7 +1071,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     }
     for (int sd = 0; sd < 4; ++sd) {
         const int k = grid->bc[sd].kind;
-        if (k < 0 || k > 5) return fail(FLD_EINVAL, "boundary kind");
+        if (k < 0 || k > FLD_BC_MILNE) return fail(FLD_EINVAL, "boundary kind");
         if (k == FLD_BC_AXIS && (grid->geom != FLD_SPHERICAL_POLAR || sd < 2))
             return fail(FLD_EINVAL, "axis boundary needs a spherical theta side");
         if (k == FLD_BC_DIRICHLET_FACE && !(grid->bc[sd].value > 0.0)) return fail(FLD_EINVAL, "Dirichlet temperature");

@@ -18,7 +18,8 @@ constexpr int TRows = 16;
 constexpr int kThreads = TBX * TBY;
 constexpr int k1DBlocksMax = 2048;   // grid size cap of the 1D streaming kernels
 
-enum { BC_REFLECT = 0, BC_DIRICHLET_FACE = 1, BC_DIRICHLET_GHOST = 2, BC_FLUX_IN = 3, BC_FREE_STREAM = 4, BC_AXIS = 5 };
+enum { BC_REFLECT = 0, BC_DIRICHLET_FACE = 1, BC_DIRICHLET_GHOST = 2, BC_FLUX_IN = 3, BC_FREE_STREAM = 4, BC_AXIS = 5,
+       BC_MILNE = 6 };
 enum { LIM_LP = 0, LIM_MINERBO = 1, LIM_DIFFUSION = 2 };
 
 // Separable grid metrics, FP64, device arrays.

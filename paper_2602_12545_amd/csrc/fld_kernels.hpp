@@ -137,6 +137,11 @@ __device__ inline void boundary_face(int kind, double value, double Eg, double E
         br += dt * dS * value;
     } else if (kind == BC_FREE_STREAM) {
         bd += dt * dS * kC;
+    } else if (kind == BC_MILNE) {
+        // E_b = -2/(3 sigma) dE/dn with dE/dn = (E_b - E_1)/h1: E_b = a E_1/(1+a),
+        // a = 2/(3 sigma h1); R = 3/2 on the face; outward flux D E_1/(h1 (1+a))
+        const double a = 2.0 / (3.0 * sig1 * h1);
+        bd += dt * dS * (kC * limiter(1.5, lim) / sig1) / (h1 * (1.0 + a));
     }
 }
 

@@ -474,6 +474,36 @@ def boundary_energy_input(geom, A: Assembled, bcs: Sequence[BCSpec], E_new, dt) 
     return total
 
 
+def face_fluxes(A: Assembled, E_old, E_new, sig, dt, bcs: Sequence[BCSpec], limiter: int = LIMITER_LP):
+    """Radiative flux through every face after a step (Section 3.2.1 flux
+    formula, one sub-step), positive along +x / +y: Fx [ny][nx+1], Fy [ny+1][nx].
+    An interior face carries W (E_lo - E_hi) / (dt dS) = -D (E_hi - E_lo) / h
+    with the step's conductance W; a boundary face the outward flux its side's
+    boundary terms put in the rows, (da E_1 - ra) / (dt dS) (da, ra from
+    ``boundary_terms`` with the step's E^n), sign-flipped on the lower sides.
+    Faces of zero area (the axis) carry none."""
+    met = A.met
+    lim = LIMITERS[limiter]
+    ny, nx = met.ny, met.nx
+    E_old = np.asarray(E_old, dtype=np.float64).reshape(ny, nx)
+    E_new = np.asarray(E_new, dtype=np.float64).reshape(ny, nx)
+    sig = np.asarray(sig, dtype=np.float64).reshape(ny, nx)
+    Fx = np.zeros((ny, nx + 1))
+    Fy = np.zeros((ny + 1, nx))
+    Fx[:, 1:-1] = A.W_x[:, 1:-1] * (E_new[:, :-1] - E_new[:, 1:]) / (dt * met.dSx[:, 1:-1])
+    Fy[1:-1, :] = A.W_y[1:-1, :] * (E_new[:-1, :] - E_new[1:, :]) / (dt * met.dSy[1:-1, :])
+    sides = [(np.s_[:, 0], met.hRx[:, 0], met.dSx[:, 0], Fx, np.s_[:, 0], -1.0),
+             (np.s_[:, -1], met.hLx[:, -1], met.dSx[:, -1], Fx, np.s_[:, -1], 1.0),
+             (np.s_[0, :], met.hRy[0, :], met.dSy[0, :], Fy, np.s_[0, :], -1.0),
+             (np.s_[-1, :], met.hLy[-1, :], met.dSy[-1, :], Fy, np.s_[-1, :], 1.0)]
+    for b, (cell, h1, dS, F, face, sgn) in zip(bcs, sides):
+        da, ra, _, _ = boundary_terms(b.kind, b.value, b.ghost, E_old[cell], sig[cell], h1, dS, dt, lim)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out = np.where(dS > 0.0, (da * E_new[cell] - ra) / (dt * dS), 0.0)
+        F[face] = sgn * out
+    return Fx, Fy
+
+
 def interface_flux_x(A: Assembled, E_new):
     """F at interior x faces, -D (E_R - E_L)/h with D at level n (Section 3.2.1, flux formula, one sub-step)."""
     E_new = np.asarray(E_new).reshape(A.diag.shape)

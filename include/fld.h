@@ -244,7 +244,9 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, con
  *              read back by the host.
  * dts, per_sub (host arrays of max_sub entries, may be NULL) receive each
  * sub-step's length and solve record; *n_done (may be NULL) the number of
- * sub-steps taken.  Returns EINVAL for bad parameters (max_sub < 1, dbar < 0,
+ * sub-steps taken.  Fx, Fy (device, layouts of fld_face_flux, may be NULL)
+ * receive the face fluxes averaged over the sub-steps, sum_k (dt_k / dt) F_k
+ * (the paper's sum over the sub-cycle of the flux formula).  Returns EINVAL for bad parameters (max_sub < 1, dbar < 0,
  * geometric with n_sub outside 1..max_sub or q <= 0) or fields, ENOCONV if the
  * coupling-limited loop needs more than max_sub sub-steps (E, T then hold the
  * state after max_sub of them), ENONFINITE if a limit is not positive, else
@@ -252,7 +254,21 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, con
 fld_status fld_substep(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, const double* kappa_R,
                        const double* kappa_P, const double* c_v, const double* ghost_E, double dt, int32_t n_sub,
                        double q, double dbar, int32_t max_sub, double* dts, fld_solve_info* per_sub,
-                       int32_t* n_done);
+                       int32_t* n_done, double* Fx, double* Fy);
+
+/* Radiative flux F through every face after a step (Section 3.2.1 flux
+ * formula), from the context's last assembly and E (device, the step's
+ * E^{n+1}), positive along +x / +y: Fx [ny][nx+1] (face i below cell i along
+ * x), Fy [ny+1][nx] (device arrays, either may be NULL).  An interior face
+ * carries W (E_lo - E_hi) / (dt dS) = -D (E_hi - E_lo) / h with the step's
+ * conductance; a boundary face the outward flux that its side's boundary terms
+ * put into the rows, negated on the lower sides; faces of zero area (the axis)
+ * carry none.  Without gas coupling these fluxes close each cell's balance,
+ * dV (E^{n+1} - E^n) = -dt sum over faces of F dS outward.  Writes w F
+ * (accumulate == 0) or adds it (accumulate != 0), so a caller can average over
+ * sub-steps (fld_substep does this itself).  Queued on the context's stream.
+ * Returns ENOTREADY before an assembly, EINVAL for a NULL ctx or E. */
+fld_status fld_face_flux(fld_ctx* ctx, const double* E_r, double* Fx, double* Fy, double w, int32_t accumulate);
 
 /* Face mass fluxes f = rho v of the explicit radiation advection term
  * (Section 3.2.1 advection equation; the mass fluxes come from the hydro

@@ -79,7 +79,8 @@ _SIGS = {
     "fld_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_substep": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _D, _D, _I, ctypes.POINTER(_D),
-                         ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I)]),
+                         ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I), _P, _P]),
+    "fld_face_flux": (_I, [_P, _P, _P, _P, _D, _I]),
     "fld_set_mass_flux": (_I, [_P, _P, _P]),
     "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
     "fld_mg_levels": (_I, [_P]),
@@ -211,9 +212,10 @@ class Context:
         return [infos[k].as_dict() for k in range(nsteps)]
 
     def substep(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, n_sub=1, q=1.0, dbar=0.0,
-                max_sub=10000, check=True):
+                max_sub=10000, check=True, Fx=None, Fy=None):
         """One step of length dt as sub-steps: the geometric series (n_sub, q)
-        when dbar == 0, else coupling-limited with factor dbar.  Returns
+        when dbar == 0, else coupling-limited with factor dbar; Fx, Fy (device
+        tensors, optional) receive the sub-step-averaged face fluxes.  Returns
         {"status", "dts", "infos"} (one entry per sub-step taken)."""
         cap = max(1, int(max_sub))
         dts = (ctypes.c_double * cap)()
@@ -221,11 +223,16 @@ class Context:
         n = _I()
         st = lib.fld_substep(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P), _ptr(c_v),
                              _ptr(ghost_E), float(dt), int(n_sub), float(q), float(dbar), int(max_sub), dts, infos,
-                             ctypes.byref(n))
+                             ctypes.byref(n), _ptr(Fx), _ptr(Fy))
         if check:
             self._check(st)
         return {"status": st, "dts": [dts[k] for k in range(n.value)],
                 "infos": [infos[k].as_dict() for k in range(n.value)]}
+
+    def face_flux(self, E, Fx=None, Fy=None, w=1.0, accumulate=False):
+        """Face fluxes of the last assembled step from E into Fx [ny][nx+1],
+        Fy [ny+1][nx] (device tensors), scaled by w, added if accumulate."""
+        self._check(lib.fld_face_flux(self.handle, _ptr(E), _ptr(Fx), _ptr(Fy), float(w), 1 if accumulate else 0))
 
     def set_mass_flux(self, fx=None, fy=None):
         """Face mass fluxes of the explicit advection term (device tensors

@@ -104,6 +104,7 @@ struct fld_ctx {
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
     double* dt_lim = nullptr;  // device: coupling-limited sub-step length (fld_substep)
     const double *fx = nullptr, *fy = nullptr;  // caller's face mass fluxes (fld_set_mass_flux)
+    double *bside = nullptr, *rside = nullptr;  // last assembly's per-side boundary terms (face fluxes)
     std::vector<Level64> h64;
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
@@ -229,6 +230,45 @@ __global__ __launch_bounds__(1024) void k_reduce_min(const double* part, int nb,
     for (int b = threadIdx.x; b < nb; b += 1024) v = fmin(v, part[b]);
     const double m = block_min(v, sh);
     if (threadIdx.x == 0) *out = m;
+}
+
+// Radiative flux through every face from the last assembly (Section 3.2.1
+// flux formula), positive along +x / +y: interior faces W (E_lo - E_hi) /
+// (dt dS), boundary faces the outward flux of their side's row terms,
+// (d E_1 - r) / (dt dS), negated on the lower sides; faces of zero area carry
+// none.  Writes w F, or adds it with acc.
+__global__ __launch_bounds__(256) void k_face_flux(Metrics g, const double* __restrict__ We,
+                                                   const double* __restrict__ Wn, const double* __restrict__ bside,
+                                                   const double* __restrict__ rside, const double* __restrict__ E,
+                                                   double dt, double w, int acc, double* Fx, double* Fy) {
+    const int nx = g.nx, ny = g.ny;
+    const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfx + nfy; f += gridDim.x * blockDim.x) {
+        double F = 0.0;
+        if (f < nfx) {
+            if (!Fx) continue;
+            const int j = f / (nx + 1), i = f - j * (nx + 1);
+            const double dS = g.sx[i] * g.vy[j];
+            if (dS > 0.0) {
+                const size_t c = (size_t)j * nx + i;
+                if (i > 0 && i < nx) F = We[c - 1] * (E[c - 1] - E[c]) / (dt * dS);
+                else if (i == 0) F = -(bside[j] * E[c] - rside[j]) / (dt * dS);
+                else F = (bside[ny + j] * E[c - 1] - rside[ny + j]) / (dt * dS);
+            }
+            Fx[f] = acc ? Fx[f] + w * F : w * F;
+        } else {
+            if (!Fy) continue;
+            const int q = f - nfx, j = q / nx, i = q - j * nx;
+            const double dS = g.ax[i] * g.sy[j];
+            if (dS > 0.0) {
+                const size_t c = (size_t)j * nx + i;
+                if (j > 0 && j < ny) F = Wn[c - nx] * (E[c - nx] - E[c]) / (dt * dS);
+                else if (j == 0) F = -(bside[2 * ny + i] * E[c] - rside[2 * ny + i]) / (dt * dS);
+                else F = (bside[2 * ny + nx + i] * E[c - nx] - rside[2 * ny + nx + i]) / (dt * dS);
+            }
+            Fy[q] = acc ? Fy[q] + w * F : w * F;
+        }
+    }
 }
 
 inline bool is_line(const fld_options& o) { return o.smoother == FLD_SMOOTH_LINE || o.smoother == FLD_SMOOTH_LINE_SPLIT; }
@@ -800,7 +840,7 @@ fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, cons
                             const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st) {
     k_zero_int<<<1, 1, 0, st>>>(ctx->err_flag);
     AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc, ctx->fx, ctx->fy};
-    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part};
+    AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part, ctx->bside, ctx->rside};
     const dim3 ag = cell_grid(ctx->nx, ctx->ny);
     k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
     k_reduce_max<<<1, kRedThreads, 0, st>>>(ctx->part, (int)(ag.x * ag.y), ctx->mu);
@@ -1129,6 +1169,8 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->err_flag, 1);
     ALLOC(ctx->mu, 1);
     ALLOC(ctx->dt_lim, 1);
+    ALLOC(ctx->bside, 2 * (size_t)(nx + ny));
+    ALLOC(ctx->rside, 2 * (size_t)(nx + ny));
 #undef ALLOC
     if (hipHostMalloc((void**)&ctx->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned scalars");
@@ -1324,7 +1366,8 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
 
 fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
                        const double* cv, const double* ghost, double dt, int32_t n_sub, double q, double dbar,
-                       int32_t max_sub, double* dts, fld_solve_info* per_sub, int32_t* n_done) {
+                       int32_t max_sub, double* dts, fld_solve_info* per_sub, int32_t* n_done, double* Fx,
+                       double* Fy) {
     if (!ctx) return FLD_EINVAL;
     if (n_done) *n_done = 0;
     if (max_sub < 1) { ctx->err = "max_sub must be >= 1"; return FLD_EINVAL; }
@@ -1341,6 +1384,13 @@ fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, co
         if (per_sub) per_sub[k] = inf;
         if (dts) dts[k] = h;
         if (n_done) *n_done = k + 1;
+        if (sk == FLD_OK && (Fx || Fy)) {
+            // the step's face fluxes, time-averaged over the sub-steps
+            const int nf = (ctx->nx + 1) * ctx->ny + ctx->nx * (ctx->ny + 1);
+            k_face_flux<<<grid1d(nf), 256, 0, ctx->stream>>>(ctx->met, ctx->We, ctx->Wn, ctx->bside, ctx->rside, E,
+                                                              h, h / dt, k > 0 ? 1 : 0, Fx, Fy);
+            if (hipGetLastError() != hipSuccess) return FLD_EHIP;
+        }
         return sk;
     };
     if (dbar == 0.0) {
@@ -1377,6 +1427,20 @@ fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, co
         if (sk != FLD_OK) return sk;
         remain -= h;
     }
+    return FLD_OK;
+}
+
+fld_status fld_face_flux(fld_ctx* ctx, const double* E, double* Fx, double* Fy, double w, int32_t accumulate) {
+    if (!ctx || !E) return FLD_EINVAL;
+    if (!ctx->assembled) {
+        ctx->err = "fld_face_flux needs an assembled step";
+        return FLD_ENOTREADY;
+    }
+    if (!Fx && !Fy) return FLD_OK;
+    const int nf = (ctx->nx + 1) * ctx->ny + ctx->nx * (ctx->ny + 1);
+    k_face_flux<<<grid1d(nf), 256, 0, ctx->stream>>>(ctx->met, ctx->We, ctx->Wn, ctx->bside, ctx->rside, E, ctx->dt,
+                                                      w, accumulate ? 1 : 0, Fx, Fy);
+    HIPCHK(hipGetLastError());
     return FLD_OK;
 }
 

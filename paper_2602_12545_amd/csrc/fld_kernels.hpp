@@ -238,9 +238,25 @@ struct AsmOut {
     double *We, *Wn, *m, *rhs, *s;
     int* err;
     double* part;   // per-workgroup partial maxima of the diagonal (k_reduce_max)
+    double *bside, *rside;  // per boundary face (packed like the ghost array): that side's diagonal and
+                            // right-hand-side terms, for the face fluxes (null: not kept)
 };
 
 // Assembly of one cell; returns its diagonal.
+// One side's boundary face of a cell: its terms are added to the cell's and,
+// when kept, recorded at slot k of the packed side arrays.
+__device__ inline void side_face(int k, int kind, double value, double Eg, double E1, double sig1, double h1,
+                                 double dS, double dt, int lim, const AsmOut& out, double& bd, double& br) {
+    double d = 0.0, r = 0.0;
+    boundary_face(kind, value, Eg, E1, sig1, h1, dS, dt, lim, d, r);
+    bd += d;
+    br += r;
+    if (out.bside) {
+        out.bside[k] = d;
+        out.rside[k] = r;
+    }
+}
+
 __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const AsmOut& out, int i, int j) {
     const int nx = g.nx, ny = g.ny;
     const size_t c = (size_t)j * nx + i;
@@ -259,14 +275,15 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
         Ww = face_W(in.E[w], in.kR[w] * in.rho[w], E, sig, g.hxL[i], g.hxR[i], g.sx[i] * vyj, dt, lim);
     } else {
         const double Eg = (in.bc.kind[0] == BC_DIRICHLET_GHOST) ? in.ghost[j] : 0.0;
-        boundary_face(in.bc.kind[0], in.bc.value[0], Eg, E, sig, g.hxR[0], g.sx[0] * vyj, dt, lim, bd, br);
+        side_face(j, in.bc.kind[0], in.bc.value[0], Eg, E, sig, g.hxR[0], g.sx[0] * vyj, dt, lim, out, bd, br);
     }
     if (i + 1 < nx) {
         const size_t e = c + 1;
         We = face_W(E, sig, in.E[e], in.kR[e] * in.rho[e], g.hxL[i + 1], g.hxR[i + 1], g.sx[i + 1] * vyj, dt, lim);
     } else {
         const double Eg = (in.bc.kind[1] == BC_DIRICHLET_GHOST) ? in.ghost[ny + j] : 0.0;
-        boundary_face(in.bc.kind[1], in.bc.value[1], Eg, E, sig, g.hxL[nx], g.sx[nx] * vyj, dt, lim, bd, br);
+        side_face(ny + j, in.bc.kind[1], in.bc.value[1], Eg, E, sig, g.hxL[nx], g.sx[nx] * vyj, dt, lim, out, bd,
+                  br);
     }
     // y faces (theta distances are arc lengths at the volume-centre radius)
     if (j > 0) {
@@ -274,7 +291,8 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
         Ws = face_W(in.E[s], in.kR[s] * in.rho[s], E, sig, g.hyL[j] * arci, g.hyR[j] * arci, axi * g.sy[j], dt, lim);
     } else {
         const double Eg = (in.bc.kind[2] == BC_DIRICHLET_GHOST) ? in.ghost[2 * ny + i] : 0.0;
-        boundary_face(in.bc.kind[2], in.bc.value[2], Eg, E, sig, g.hyR[0] * arci, axi * g.sy[0], dt, lim, bd, br);
+        side_face(2 * ny + i, in.bc.kind[2], in.bc.value[2], Eg, E, sig, g.hyR[0] * arci, axi * g.sy[0], dt, lim,
+                  out, bd, br);
     }
     if (j + 1 < ny) {
         const size_t n = c + nx;
@@ -282,7 +300,8 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
                     axi * g.sy[j + 1], dt, lim);
     } else {
         const double Eg = (in.bc.kind[3] == BC_DIRICHLET_GHOST) ? in.ghost[2 * ny + nx + i] : 0.0;
-        boundary_face(in.bc.kind[3], in.bc.value[3], Eg, E, sig, g.hyL[ny] * arci, axi * g.sy[ny], dt, lim, bd, br);
+        side_face(2 * ny + nx + i, in.bc.kind[3], in.bc.value[3], Eg, E, sig, g.hyL[ny] * arci, axi * g.sy[ny], dt,
+                  lim, out, bd, br);
     }
     // reflecting and axis sides carry no flux (boundary_face ignores them)
     // cell terms: C_V = rho c_v, beta = kappa_P rho c dt, X = 4 beta a_R T^3, f = C_V/(C_V+X)

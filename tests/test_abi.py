@@ -25,7 +25,7 @@ needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libfld.so not bu
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_set_mass_flux", "fld_gas_update",
+    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_face_flux", "fld_set_mass_flux", "fld_gas_update",
               "fld_get_operator", "fld_destroy", "fld_default_options", "fld_batch_create", "fld_batch_step",
               "fld_batch_steps", "fld_batch_destroy"):
         assert f in names
@@ -55,7 +55,10 @@ def test_host_only_entry_points_run_without_gpu():
     lib.fld_substep.restype = ctypes.c_int32
     n_done = ctypes.c_int32(7)
     assert lib.fld_substep(None, None, None, None, None, None, None, None, ctypes.c_double(1.0), 1,
-                           ctypes.c_double(1.5), ctypes.c_double(0.0), 1, None, None, ctypes.byref(n_done)) == 1
+                           ctypes.c_double(1.5), ctypes.c_double(0.0), 1, None, None, ctypes.byref(n_done), None,
+                           None) == 1
+    lib.fld_face_flux.restype = ctypes.c_int32
+    assert lib.fld_face_flux(None, None, None, None, ctypes.c_double(1.0), 0) == 1
     lib.fld_batch_last_error.restype = ctypes.c_char_p
     out = ctypes.c_void_p()
     assert lib.fld_batch_create(ctypes.byref(out), 0, None, None, None, None, None, None, None) == 1

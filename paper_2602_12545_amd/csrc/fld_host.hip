@@ -768,7 +768,9 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     const fld_options& o = ctx->opt;
     const bool fp32only = o.precision == FLD_FP32;
     const bool mixed = o.precision == FLD_MIXED;
-    const double delta = mixed ? 0.1 : 1e-3;
+    // true-residual check once the binary32 recurrence residual has fallen 100x
+    // (10x checked twice as often for the same iteration count: c2 -2 %)
+    const double delta = mixed ? 0.01 : 1e-3;
     const int max_iter = o.max_inner;
     k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, max_iter, o.norm,
                                     fp32only ? 0 : 1);
@@ -862,7 +864,7 @@ void enqueue_solve_fixed(fld_ctx* ctx, double* E, int slots, hipStream_t st) {
     Inner<T>& in = inner<T>(ctx);
     const fld_options& o = ctx->opt;
     const int n = ctx->nx * ctx->ny;
-    const double delta = o.precision == FLD_MIXED ? 0.1 : 1e-3;
+    const double delta = o.precision == FLD_MIXED ? 0.01 : 1e-3;
     k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol, slots, o.norm,
                                     o.precision == FLD_FP32 ? 0 : 1);
     enqueue_check<T>(ctx, in, E, 1, st);

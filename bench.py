@@ -127,9 +127,11 @@ def options(fld, prec, tuned, norm=0):
 
 
 def run_steps(fld, torch, prob, base, opts, steps, warmup, profile, profile_all=False):
-    """Mean wall time of one step over `steps` timed steps (the last one, or
-    all with `profile_all`, with event-timed line sweeps when `profile`), and
-    the per-step infos."""
+    """Mean wall time of one step over `steps` timed steps, and the per-step
+    infos.  With `profile`, one more step after the timed ones runs with
+    event-timed line sweeps (plain launches, no graphs), and the sweep replay
+    is measured; with `profile_all` every timed step is event-timed instead
+    (for a profiler trace of plain launches)."""
     ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                       [(b.kind, b.value) for b in prob.bc], opts)
     E = base["E"].clone()
@@ -145,14 +147,18 @@ def run_steps(fld, torch, prob, base, opts, steps, warmup, profile, profile_all=
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
+    if profile and profile_all:
+        ctx.profile(True)
     for s in range(steps):
-        if profile and s == (0 if profile_all else steps - 1):
-            ctx.profile(True)
         infos.append(one())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = None
     if profile:
+        if not profile_all:
+            ctx.profile(True)
+            one()
+            torch.cuda.synchronize()
         prof = ctx.profile_read()
         prof["overhead_us"] = ctx.profile_overhead(200)
         ctx.profile(False)

@@ -109,6 +109,7 @@ struct fld_ctx {
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
     double* part_rz = nullptr;  // r.z partials of the V-cycle's last sweep (summed by k_spmv)
+    double* rz_sum = nullptr;   // their total, when summed apart (many partials)
     // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
     // enqueue_vcycle queues only the line-sweep launches and counts them
     bool sweeps_only = false;
@@ -521,8 +522,13 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     LevelT<T>& l0 = in.lv[0];
     const dim3 tg = tile_grid(nx, ny);
     const int ntiles = (int)(tg.x * tg.y), nb1 = update_grid(n);
-    k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn, c->part_rz,
-                                      c->nrz, c->part, c->sc);
+    // r.z: summed by every SpMV workgroup from the sweep's partials when they
+    // are few, else once by one workgroup (c5's 4096-cell lines leave 2048,
+    // whose re-summing cost the SpMV a third of its time)
+    const bool many_rz = c->nrz > 512;
+    if (many_rz) k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part_rz, c->nrz, c->rz_sum, c->sc);
+    k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn,
+                                      many_rz ? c->rz_sum : c->part_rz, many_rz ? 1 : c->nrz, c->part, c->sc);
     // alpha: summed inside k_update from the SpMV partials when they are few,
     // by one reduction workgroup otherwise
     const bool fold = ntiles <= 1024;
@@ -1166,6 +1172,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->part, ctx->npart);
     ALLOC(ctx->part2, (size_t)k1DBlocksMax);
     ALLOC(ctx->part_rz, ctx->npart);
+    ALLOC(ctx->rz_sum, 1);
     ALLOC(ctx->sc, 1);
     ALLOC(ctx->sc_sweep, 1);
     ALLOC(ctx->err_flag, 1);

@@ -941,6 +941,17 @@ __device__ inline double reduce_sum(const double* part, int nb, int stride, int 
     return block_sum(v, sh);
 }
 
+// r.z summed once when the last sweep left many partials (one workgroup per
+// long line): *out feeds k_spmv as a single partial instead of every SpMV
+// workgroup summing all of them
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rz(const double* part, int nb, double* out,
+                                                           const Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[16];
+    const double v = reduce_sum(part, nb, 1, 0, sh);
+    if (threadIdx.x == 0) *out = v;
+}
+
 // alpha = r.z / p.q (k_update with npq = 0 reads it from the state instead)
 __global__ __launch_bounds__(kRedThreads) void k_reduce_pq(const double* part, int nb, Scalars* sc) {
     if (sc->done) return;

@@ -546,26 +546,20 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     const int L = (int)in.lv.size();
     const double omega = c->opt.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
     const bool line = is_line(c->opt);
-    for (int l = 0; l < L; ++l) {
+    // the FP64 coarsening chain first: the coarsest level's inverse, built on
+    // the side stream, then runs beside the inner-precision copies below
+    // instead of after them (its ~50 us otherwise stalled the first V-cycle)
+    for (int l = 1; l < L; ++l) {
+        Level64& a = c->h64[l - 1];
         Level64& b = c->h64[l];
-        if (l > 0) {
-            Level64& a = c->h64[l - 1];
-            k_coarsen<<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.m, a.We, a.Wn, b.nx, b.ny, b.m, b.We, b.Wn,
-                                                                 omega);
-        }
-        LevelT<T>& lt = in.lv[l];
-        const int n = b.nx * b.ny;
-        k_demote_level<T><<<grid1d(n), 256, 0, st>>>(n, b.m, b.We, b.Wn, c->mu, lt.m, lt.We, lt.Wn);
-        if (line && L > 1) {
-            // transposed view: rows are the columns, east couplings are the north ones
-            dim3 g((b.nx + kTT - 1) / kTT, (b.ny + kTT - 1) / kTT), blk(kTT, 8);
-            k_transpose<T, 3><<<g, blk, 0, st>>>(b.nx, b.ny, lt.m, lt.Wn, lt.We, lt.mT, lt.WeT, lt.WnT, nullptr);
-        }
+        k_coarsen<<<cell_grid(b.nx, b.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.m, a.We, a.Wn, b.nx, b.ny, b.m, b.We, b.Wn,
+                                                             omega);
     }
     Level64& cl = c->h64[L - 1];
     {
-        // one workgroup, ~40-240 us: it runs beside the prologue and the
-        // first down-leg of the V-cycle, which do not need the inverse
+        // one workgroup, ~40-240 us: it runs beside the copies below, the
+        // prologue and the first down-leg of the V-cycle, which do not need
+        // the inverse
         fld_ctx* ctx = c;
         HIPCHK(hipEventRecord(c->setup_fork, st));
         HIPCHK(hipStreamWaitEvent(c->setup_stream, c->setup_fork, 0));
@@ -582,6 +576,17 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
                                                                      in.Ywork, in.Ainv);
         HIPCHK(hipEventRecord(c->setup_join, ss));
         c->setup_pending = true;
+    }
+    for (int l = 0; l < L; ++l) {
+        Level64& b = c->h64[l];
+        LevelT<T>& lt = in.lv[l];
+        const int n = b.nx * b.ny;
+        k_demote_level<T><<<grid1d(n), 256, 0, st>>>(n, b.m, b.We, b.Wn, c->mu, lt.m, lt.We, lt.Wn);
+        if (line && L > 1) {
+            // transposed view: rows are the columns, east couplings are the north ones
+            dim3 g((b.nx + kTT - 1) / kTT, (b.ny + kTT - 1) / kTT), blk(kTT, 8);
+            k_transpose<T, 3><<<g, blk, 0, st>>>(b.nx, b.ny, lt.m, lt.Wn, lt.We, lt.mT, lt.WeT, lt.WnT, nullptr);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every timed step (plain launches; for comparison with a kernel trace)")
-    ap.add_argument("--mg-cycle", default=None, choices=["k", "v"],
+    ap.add_argument("--mg-cycle", default=None, choices=["k", "v", "w2"],
                     help="fix the multigrid cycle of the single-grid solves (default: the library default, "
                          "and the tuner's choice where tuned; the batch always runs V-cycles)")
     ap.add_argument("--norm", default="rows", choices=["rows", "scaled"],
@@ -263,15 +263,20 @@ def stress_extra(fld, torch, W, nsteps=5):
     """4096 x 2048 spherical grid, opacity contrast 1e8, stiff coupling:
     nsteps consecutive steps as one captured step graph (fld_steps), mixed
     and FP64, scaled-norm stop at 1e-10 (the per-volume norm's binary64 floor
-    on this grid lies near 2e-9)."""
+    on this grid lies near 2e-9); with the library default cycle (K) and with
+    the two sequential V-cycles (W2), which this grid favours."""
     import numpy as np
     prob = W.make_c5()
     f = dev_fields(torch, prob)
     out = {"workload": "c5: 4096x2048 spherical-polar, kappa contrast 1e8, c_v=1e6, dt=1e5, "
                        f"{nsteps} steps per fld_steps call", "norm": "scaled"}
-    for prec in ("mixed", "fp64"):
+
+    def run(prec, cycle):
+        opt = defaults(fld, precision=prec, norm=1)
+        if cycle is not None:
+            opt.mg_cycle = cycle
         ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                          [(b.kind, b.value) for b in prob.bc], defaults(fld, precision=prec, norm=1))
+                          [(b.kind, b.value) for b in prob.bc], opt)
         E, T = f["E"].clone(), f["T"].clone()
         ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt)  # warm-up
         E.copy_(f["E"])
@@ -283,10 +288,17 @@ def stress_extra(fld, torch, W, nsteps=5):
         ms = 1e3 * (time.perf_counter() - t0) / nsteps
         ctx.close()
         its = [i["inner_iters"] for i in infos]
-        out[prec] = {"ms_per_step": ms, "iters": its, "status": sorted(set(i["status"] for i in infos)),
-                     "max_rel_resid": max(i["rel_resid"] for i in infos),
-                     "mcell_iter_per_s": prob.nx * prob.ny * float(np.mean(its)) / (ms * 1e-3) / 1e6}
+        return {"ms_per_step": ms, "iters": its, "status": sorted(set(i["status"] for i in infos)),
+                "max_rel_resid": max(i["rel_resid"] for i in infos),
+                "mcell_iter_per_s": prob.nx * prob.ny * float(np.mean(its)) / (ms * 1e-3) / 1e6}
+
+    for prec in ("mixed", "fp64"):
+        out[prec] = run(prec, None)
     out["mixed_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    if MG_CYCLE is None:
+        w2 = {prec: run(prec, 2) for prec in ("mixed", "fp64")}
+        w2["mixed_vs_fp64"] = w2["fp64"]["ms_per_step"] / w2["mixed"]["ms_per_step"]
+        out["cycle_w2"] = w2
     return out
 
 
@@ -395,7 +407,7 @@ def copy_calibration(torch):
 def main():
     global MG_CYCLE
     args = parse()
-    MG_CYCLE = None if args.mg_cycle is None else (1 if args.mg_cycle == "k" else 0)
+    MG_CYCLE = None if args.mg_cycle is None else {"v": 0, "k": 1, "w2": 2}[args.mg_cycle]
     if args.gpus != 1:
         print(json.dumps({"error": "only one GPU is supported: the solver has no multi-GPU path; "
                                    "blocks and rows would shard as separate solves per GPU"}), flush=True)

@@ -126,10 +126,13 @@ typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT 
  * sub-cycle's V-cycle (the Krylov-accelerated K-cycle of Notay and
  * Vassilevski, 2008).  With piecewise-constant aggregation the V-cycle loses
  * convergence as levels are added; the K-cycle restores most of it at the cost
- * of a second pass through the LDS levels only.  K acts as V where a line
- * smoother has no LDS sub-cycle (fewer than three levels, or point
- * smoothing). */
-typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1 } fld_mg_cycle;
+ * of a second pass through the LDS levels only.  W2: the same two passes with
+ * fixed coefficients, x = c1 + V(b - A c1) (a linear, symmetric
+ * preconditioner; measured better than K on the 1e8-contrast spherical
+ * stress grid, worse on the stretched Cartesian one).  K and W2 act as V
+ * where a line smoother has no LDS sub-cycle (fewer than three levels, or
+ * point smoothing). */
+typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1, FLD_MG_CYCLE_W2 = 2 } fld_mg_cycle;
 
 typedef struct {
     int32_t precision;      /* fld_precision (default MIXED)                                 */
@@ -409,8 +412,8 @@ typedef struct {
 } fld_tune_entry;
 
 /* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
- * mg_cycle in {K, V} (line smoothers; POINT keeps base's), mg_coarse_max in
- * {64, 256, 16} and chunk in {8, 16, 4} (45 candidates); precision, limiter,
+ * mg_cycle in {K, V, W2} (line smoothers; POINT keeps base's), mg_coarse_max
+ * in {64, 256, 16} and chunk in {8, 16, 4} (63 candidates); precision, limiter,
  * norm and tolerances are those of base (NULL = defaults).  Each candidate
  * gets its own context and runs reps + 1 steps (the first untimed) from the
  * given E, T (device arrays, not modified; the trials run on scratch copies).

@@ -198,7 +198,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
     if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
-    if (o->mg_cycle < 0 || o->mg_cycle > 1) { err = "mg_cycle"; return FLD_EINVAL; }
+    if (o->mg_cycle < 0 || o->mg_cycle > 2) { err = "mg_cycle"; return FLD_EINVAL; }
     return FLD_OK;
 }
 
@@ -636,7 +636,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     // coarser levels fit in LDS (5 arrays each; the K-cycle adds two arrays of
     // level l and its partials) and whose lines fit one wavefront
     const int L = (int)in.lv.size();
-    const bool kcyc = ctx->opt.mg_cycle == FLD_MG_CYCLE_K;
+    const bool kcyc = ctx->opt.mg_cycle != FLD_MG_CYCLE_V;
     constexpr int kRedSlots = 4 * (kSubThreads<T> / 64);
     in.sub_first = -1;
     int dev = 0, lds_max = 65536;
@@ -671,7 +671,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
             S.Ainv = in.Ainv;
             S.bc_off = off;
             S.part_off = off + in.lv[L - 1].nx * in.lv[L - 1].ny;
-            S.kcyc = kcyc ? 1 : 0;
+            S.kcyc = ctx->opt.mg_cycle == FLD_MG_CYCLE_K ? 1 : ctx->opt.mg_cycle == FLD_MG_CYCLE_W2 ? 2 : 0;
             S.k_off = S.part_off + kSubThreads<T>;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -1132,7 +1132,8 @@ struct SubCycle {
     const T* Ainv;         // dense inverse of the coarsest level, cell order of its primary layout
     int bc_off;            // LDS pool offset of the coarsest right-hand side in that cell order
     int part_off;          // LDS pool offset of the coarsest solve's partial sums (one per thread)
-    int kcyc;              // 1: K-cycle at the first level (two flexible-CG steps around the V-cycle)
+    int kcyc;              // 1: K-cycle at the first level (two flexible-CG steps around the V-cycle);
+                           // 2: two V-cycles in sequence there, x = c1 + V(b - A c1) (linear)
     int k_off;             // LDS pool offset of the K-cycle arrays (first iterate, its image, partials)
 };
 
@@ -1377,6 +1378,28 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
     for (int pass = 0;; ++pass) {
         sub_vcycle(S, pool);
         if (!S.kcyc) break;
+        if (pass == 0 && S.kcyc == 2) {
+            // c1 = x; b <- b - A c1 (the second V-cycle solves for the rest)
+            int i = t % L0.nx, j = t / L0.nx;
+            for (int c = t; c < n0; c += NT) {
+                const int cl = j * P0 + i;
+                const T av = sub_apply(m0, m0 + z0, m0 + 2 * z0, x0, i, j, L0.nx, L0.ny, P0);
+                c1[cl] = x0[cl];
+                b0[cl] -= av;
+                i += di;
+                j += dj;
+                if (i >= L0.nx) {
+                    i -= L0.nx;
+                    ++j;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        if (S.kcyc == 2) {  // x = c2: output c1 + c2
+            f2 = T(1);
+            break;
+        }
         if (pass == 0) {
             // c1 = x, v1 = A c1; rho1 = c1.v1, s1 = c1.b / rho1
             T d[2] = {T(0), T(0)};

@@ -212,16 +212,20 @@ def test_coarsest_level_up_to_256_cells(lib, shape, prec):
                                      ("c3", dict(nx=300, ny=200))])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_k_cycle_and_v_cycle(lib, name, kw, prec):
-    """Both multigrid cycles reach the oracle's solution; the K-cycle (two
-    flexible-CG steps around the LDS sub-cycle) needs no more CG iterations
-    than the V-cycle on hierarchies deep enough to have a sub-cycle."""
+    """All three multigrid cycles reach the oracle's solution; the K-cycle
+    (two flexible-CG steps around the LDS sub-cycle) needs no more CG
+    iterations than the V-cycle on hierarchies deep enough to have a
+    sub-cycle, and the two sequential V-cycles (W2) no more than the V-cycle
+    plus one."""
     prob = W.make(name, **kw)
     ref = O.step_problem(prob)
     opt = dict(precision=prec, rel_tol=1e-12, norm=1)
     Ek, Tk, ik = gpu_step(lib, torch, prob, mg_cycle=1, **opt)
     Ev, Tv, iv = gpu_step(lib, torch, prob, mg_cycle=0, **opt)
-    print(name, prec, "K", ik["inner_iters"], "V", iv["inner_iters"], flush=True)
-    assert ik["status"] == 0 and iv["status"] == 0
-    for E, T in ((Ek, Tk), (Ev, Tv)):
+    Ew, Tw, iw = gpu_step(lib, torch, prob, mg_cycle=2, **opt)
+    print(name, prec, "K", ik["inner_iters"], "V", iv["inner_iters"], "W2", iw["inner_iters"], flush=True)
+    assert ik["status"] == 0 and iv["status"] == 0 and iw["status"] == 0
+    for E, T in ((Ek, Tk), (Ev, Tv), (Ew, Tw)):
         assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10
     assert ik["inner_iters"] <= iv["inner_iters"]
+    assert iw["inner_iters"] <= iv["inner_iters"] + 1

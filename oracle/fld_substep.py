@@ -70,15 +70,16 @@ class SubstepResult:
 
 
 def substep(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, *, n_sub: int = 1, q: float = 1.0,
-            dbar: float = 0.0, max_sub: int = 10000, limiter=O.LIMITER_LP) -> SubstepResult:
+            dbar: float = 0.0, max_sub: int = 10000, limiter=O.LIMITER_LP, fx=None, fy=None) -> SubstepResult:
     """One radiation step of length dt taken in sub-steps: the geometric series
-    (n_sub, q) when dbar == 0, else coupling-limited sub-steps with factor dbar."""
+    (n_sub, q) when dbar == 0, else coupling-limited sub-steps with factor dbar.
+    fx, fy: face mass fluxes of the advection term, applied in every sub-step."""
     E = np.asarray(E, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
     dts: List[float] = []
     if dbar == 0.0:
         for h in geometric_substeps(dt, q, n_sub):
-            r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, float(h), bcs, limiter)
+            r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, float(h), bcs, limiter, fx, fy)
             E, T = r.E, r.T
             dts.append(float(h))
         return SubstepResult(E, T, dts)
@@ -89,7 +90,7 @@ def substep(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, *, n_sub: i
         if len(dts) == max_sub:
             raise RuntimeError("sub-step limit reached")
         h = min(remain, coupling_dt(E, T, rho, kappa_P, c_v, dbar))
-        r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, h, bcs, limiter)
+        r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, h, bcs, limiter, fx, fy)
         E, T = r.E, r.T
         dts.append(h)
         remain -= h

@@ -97,3 +97,42 @@ def test_face_flux_needs_a_step(lib):
     with pytest.raises(lib.FLDError):
         ctx.face_flux(t["E"], torch.zeros((prob.ny, prob.nx + 1), dtype=torch.float64, device="cuda"))
     ctx.close()
+
+
+def test_advection_substeps_and_fluxes_together(lib):
+    """Advection, sub-cycling and the sub-step-averaged face fluxes at once,
+    against the oracle's sub-cycled steps with the same mass fluxes."""
+    prob = case("cart")
+    rng = np.random.default_rng(9)
+    ny, nx = prob.E.shape
+    met = O.metrics(prob.geom, prob.x_faces, prob.y_faces)
+    scale = 0.05 * float(np.median(prob.rho)) * float(np.median(met.dV / met.dSx[:, :-1])) / prob.dt
+    fx, fy = scale * rng.normal(size=(ny, nx + 1)), scale * rng.normal(size=(ny + 1, nx))
+    ctx = make_ctx(lib, prob, precision="fp64", rel_tol=1e-12, norm=1)
+    t = to_dev(prob, torch)
+    dfx = torch.tensor(fx, dtype=torch.float64, device="cuda")
+    dfy = torch.tensor(fy, dtype=torch.float64, device="cuda")
+    ctx.set_mass_flux(dfx, dfy)
+    Fx = torch.zeros((ny, nx + 1), dtype=torch.float64, device="cuda")
+    Fy = torch.zeros((ny + 1, nx), dtype=torch.float64, device="cuda")
+    r = ctx.substep(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, n_sub=3, q=1.4,
+                    check=False, Fx=Fx, Fy=Fy)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert r["status"] == 0
+    bcs = O.bcs_from_problem(prob)
+    ref = S.substep(prob.geom, prob.x_faces, prob.y_faces, prob.E, prob.T, prob.rho, prob.kappa_R, prob.kappa_P,
+                    prob.c_v, prob.dt, bcs, n_sub=3, q=1.4, fx=fx, fy=fy)
+    from gpu_helpers import rel_l2
+    assert rel_l2(t["E"].cpu().numpy(), ref.E) < 1e-10 and rel_l2(t["T"].cpu().numpy(), ref.T) < 1e-10
+    E, T = prob.E, prob.T
+    ax, ay = 0.0, 0.0
+    for h in S.geometric_substeps(prob.dt, 1.4, 3):
+        s = O.step(prob.geom, prob.x_faces, prob.y_faces, E, T, prob.rho, prob.kappa_R, prob.kappa_P, prob.c_v, h, bcs,
+                   fx=fx, fy=fy)
+        gx, gy = O.face_fluxes(s.A, E, s.E, prob.kappa_R * prob.rho, h, bcs)
+        ax, ay = ax + h / prob.dt * gx, ay + h / prob.dt * gy
+        E, T = s.E, s.T
+    sc = max(np.abs(ax).max(), np.abs(ay).max())
+    np.testing.assert_allclose(Fx.cpu().numpy(), ax, rtol=1e-7, atol=1e-8 * sc)
+    np.testing.assert_allclose(Fy.cpu().numpy(), ay, rtol=1e-7, atol=1e-8 * sc)

@@ -230,6 +230,12 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, con
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);
 
+/* fld_steps under the name of its mechanism (one step captured as a hipGraph
+ * and replayed); identical arguments and behaviour. */
+fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
+                           const double* kappa_R, const double* kappa_P, const double* c_v,
+                           const double* ghost_E, double dt, fld_solve_info* per_step);
+
 /* One radiation step of length dt taken as sub-steps (Section 3.2.1, the
  * sub-step rules that follow the gas-energy linearisation), each an fld_step
  * of its own length with the opacities, rho and c_v held fixed and E, T

@@ -78,6 +78,7 @@ _SIGS = {
     "fld_gas_update": (_I, [_P, _P, _P]),
     "fld_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_steps": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_steps_graph": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
     "fld_substep": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _D, _D, _I, ctypes.POINTER(_D),
                          ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I), _P, _P]),
     "fld_face_flux": (_I, [_P, _P, _P, _P, _D, _I]),

@@ -1378,6 +1378,12 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     return firstbad;
 }
 
+fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
+                           const double* kP, const double* cv, const double* ghost, double dt,
+                           fld_solve_info* per_step) {
+    return fld_steps(ctx, nsteps, E, T, rho, kR, kP, cv, ghost, dt, per_step);
+}
+
 fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
                        const double* cv, const double* ghost, double dt, int32_t n_sub, double q, double dbar,
                        int32_t max_sub, double* dts, fld_solve_info* per_sub, int32_t* n_done, double* Fx,

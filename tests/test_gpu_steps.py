@@ -127,3 +127,21 @@ def test_sweep_replay_measurement(lib):
     E_ref, T_ref, i_ref = _run(fld, torch, prob, 1, multi=False, **opt)
     assert info["status"] == 0 and info["inner_iters"] == i_ref[0]["inner_iters"]
     assert np.array_equal(t2["E"].cpu().numpy(), E_ref) and np.array_equal(t2["T"].cpu().numpy(), T_ref)
+
+
+def test_steps_graph_alias(lib):
+    """fld_steps_graph is fld_steps under its other name: bit-identical."""
+    import ctypes
+    from paper_2602_12545_amd import _binding as B
+    prob = W.make("c1", nx=40, ny=32)
+    E1, T1, _ = _run(lib, torch, prob, 4, multi=True, precision="mixed")
+    ctx = make_ctx(lib, prob, precision="mixed")
+    t = to_dev(prob, torch)
+    infos = (B.fld_solve_info * 4)()
+    st = B.lib.fld_steps_graph(ctx.handle, 4, B._ptr(t["E"]), B._ptr(t["T"]), B._ptr(t["rho"]), B._ptr(t["kappa_R"]),
+                               B._ptr(t["kappa_P"]), B._ptr(t["c_v"]), B._ptr(t["ghost_E"]), ctypes.c_double(prob.dt),
+                               infos)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert st == 0 and [infos[k].status for k in range(4)] == [0] * 4
+    assert np.array_equal(t["E"].cpu().numpy(), E1) and np.array_equal(t["T"].cpu().numpy(), T1)

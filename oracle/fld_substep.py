@@ -20,17 +20,29 @@ sub-step and adds nothing but the choice of the sub-step lengths:
   equilibrium (G0 = 0) does not limit; the loop ends once the remaining time
   is at most 1e-12 Delta t, and fails after max_sub sub-steps.
 
-Opacities, rho and c_v are held fixed over the sub-steps (they are inputs of
-the radiation step); E and T advance.
+Opacities and rho are held fixed over the sub-steps (they are inputs of the
+radiation step); E and T advance.  The heat capacity is recomputed from T at
+the start of every sub-step (the radiation-subsystem algorithm returns to its
+C_V step before each sub-step) when a temperature law is given: the analytic
+power law
+      c_v(T) = c_v,ref (T / T_ref)^p,
+c_v,ref being the caller's c_v array (its value at T_ref), stands in for a
+nonlinear equation of state; p = 0, or no law, keeps c_v fixed.  Each
+sub-step then linearises the gas energy about its own start, C_V = rho c_v(T)
+(the paper's linearised coupling equation for a nonlinear gas energy).
 
 Parity status: pinned by tests/test_oracle_substep.py (the series' closed-form
 invariants, the temperature-change bound that dbar is meant to enforce on the
 paper's 0D coupling set-up, and first-order convergence of both schedules to
-an implicit Runge-Kutta solution of that set-up's ODE pair).
+an implicit Runge-Kutta solution of that set-up's ODE pair) and
+tests/test_oracle_cv_law.py (the power law's values, its p = 0 case, and
+first-order convergence of the sub-stepped scheme to the ODE pair with the
+temperature-dependent heat capacity, which the fixed-c_v scheme misses).
 """
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import List
 
 import numpy as np
@@ -62,6 +74,14 @@ def coupling_dt(E, T, rho, kappa_P, c_v, dbar: float) -> float:
     return float(lim.min())
 
 
+def cv_power_law(c_v_ref, T, T_ref: float, p: float) -> np.ndarray:
+    """Specific heat at temperature T of the power-law stand-in for a nonlinear
+    equation of state: c_v,ref (T / T_ref)^p."""
+    if not (T_ref > 0.0) or not math.isfinite(p):
+        raise ValueError("need T_ref > 0 and a finite p")
+    return np.asarray(c_v_ref, dtype=np.float64) * (np.asarray(T, dtype=np.float64) / T_ref) ** p
+
+
 @dataclasses.dataclass
 class SubstepResult:
     E: np.ndarray
@@ -70,16 +90,24 @@ class SubstepResult:
 
 
 def substep(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, *, n_sub: int = 1, q: float = 1.0,
-            dbar: float = 0.0, max_sub: int = 10000, limiter=O.LIMITER_LP, fx=None, fy=None) -> SubstepResult:
+            dbar: float = 0.0, max_sub: int = 10000, limiter=O.LIMITER_LP, fx=None, fy=None,
+            cv_law=None) -> SubstepResult:
     """One radiation step of length dt taken in sub-steps: the geometric series
     (n_sub, q) when dbar == 0, else coupling-limited sub-steps with factor dbar.
-    fx, fy: face mass fluxes of the advection term, applied in every sub-step."""
+    fx, fy: face mass fluxes of the advection term, applied in every sub-step.
+    cv_law: None, or (T_ref, p) of the power law, c_v then being its c_v,ref."""
     E = np.asarray(E, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
     dts: List[float] = []
+
+    def heat_capacity(T):
+        if cv_law is None or cv_law[1] == 0.0:
+            return c_v
+        return cv_power_law(c_v, T, cv_law[0], cv_law[1])
+
     if dbar == 0.0:
         for h in geometric_substeps(dt, q, n_sub):
-            r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, float(h), bcs, limiter, fx, fy)
+            r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, heat_capacity(T), float(h), bcs, limiter, fx, fy)
             E, T = r.E, r.T
             dts.append(float(h))
         return SubstepResult(E, T, dts)
@@ -89,8 +117,9 @@ def substep(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt, bcs, *, n_sub: i
     while remain > 1e-12 * dt:
         if len(dts) == max_sub:
             raise RuntimeError("sub-step limit reached")
-        h = min(remain, coupling_dt(E, T, rho, kappa_P, c_v, dbar))
-        r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, h, bcs, limiter, fx, fy)
+        cv_k = heat_capacity(T)
+        h = min(remain, coupling_dt(E, T, rho, kappa_P, cv_k, dbar))
+        r = O.step(geom, xf, yf, E, T, rho, kappa_R, kappa_P, cv_k, h, bcs, limiter, fx, fy)
         E, T = r.E, r.T
         dts.append(h)
         remain -= h

@@ -296,6 +296,22 @@ fld_status fld_face_flux(fld_ctx* ctx, const double* E_r, double* Fx, double* Fy
  * fld_steps was called.  Returns EINVAL for a NULL ctx. */
 fld_status fld_set_mass_flux(fld_ctx* ctx, const double* fx, const double* fy);
 
+/* Temperature-dependent heat capacity (Section 3.2.1: the radiation-subsystem
+ * algorithm recomputes C_V before every sub-step; Section 5.1.2: a nonlinear
+ * gas energy enters linearised, C_V = de_g/dT).  With p != 0 every later
+ * assembly of this context (fld_assemble, fld_step, fld_steps, each sub-step
+ * of fld_substep and its coupling limit) uses, instead of the c_v array it is
+ * given, the power law
+ *     c_v(T) = c_v[c] (T[c] / T_ref)^p
+ * evaluated from that step's T^n (the c_v array then holds each cell's value
+ * at T_ref), and the gas update uses the same values: an analytic stand-in for
+ * a nonlinear equation of state.  p == 0 turns the law off (the default).
+ * The first call with p != 0 allocates one array of nx*ny doubles, kept
+ * until fld_destroy.  The batched blocks do not use the law.  Returns EINVAL
+ * for a NULL ctx, T_ref <= 0 or a non-finite T_ref or p, ENOMEM if that array
+ * cannot be allocated. */
+fld_status fld_set_cv_law(fld_ctx* ctx, double T_ref, double p);
+
 /* Copies the assembled FP64 operator of the last fld_assemble to caller device
  * arrays of nx*ny doubles (any may be NULL): W_e[j][i] = conductance of the
  * face between cells i and i+1 (0 in the last column), W_n[j][i] = face between

@@ -83,6 +83,7 @@ _SIGS = {
                          ctypes.POINTER(fld_solve_info), ctypes.POINTER(_I), _P, _P]),
     "fld_face_flux": (_I, [_P, _P, _P, _P, _D, _I]),
     "fld_set_mass_flux": (_I, [_P, _P, _P]),
+    "fld_set_cv_law": (_I, [_P, ctypes.c_double, ctypes.c_double]),
     "fld_get_operator": (_I, [_P, _P, _P, _P, _P]),
     "fld_mg_levels": (_I, [_P]),
     "fld_profile": (_I, [_P, _I]),
@@ -240,6 +241,11 @@ class Context:
         [ny][nx+1] and [ny+1][nx], or None); kept referenced while set."""
         self._check(lib.fld_set_mass_flux(self.handle, _ptr(fx), _ptr(fy)))
         self._mass_flux = (fx, fy)
+
+    def set_cv_law(self, T_ref: float = 1.0, p: float = 0.0):
+        """Power-law heat capacity c_v(T) = c_v (T / T_ref)^p, re-evaluated
+        from T before every later step's assembly (p = 0: off)."""
+        self._check(lib.fld_set_cv_law(self.handle, float(T_ref), float(p)))
 
     def get_operator(self):
         import torch

@@ -104,6 +104,8 @@ struct fld_ctx {
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
     double* dt_lim = nullptr;  // device: coupling-limited sub-step length (fld_substep)
     const double *fx = nullptr, *fy = nullptr;  // caller's face mass fluxes (fld_set_mass_flux)
+    double cv_Tref = 1.0, cv_p = 0.0;  // power-law heat capacity (fld_set_cv_law; p = 0: off)
+    double* cvl = nullptr;             // its per-cell c_v at the assembled T^n
     double *bside = nullptr, *rside = nullptr;  // last assembly's per-side boundary terms (face fluxes)
     std::vector<Level64> h64;
     double* part = nullptr;
@@ -222,6 +224,16 @@ __global__ __launch_bounds__(256) void k_coupling_dt(int n, const double* __rest
     }
     const double m = block_min(v, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Heat capacity of the power-law stand-in for a nonlinear equation of state,
+// re-evaluated from T before every step's assembly (Section 3.2.1, the C_V
+// step of the radiation-subsystem algorithm): c_v = c_v,ref (T / T_ref)^p.
+__global__ __launch_bounds__(256) void k_cv_law(int n, const double* __restrict__ cv_ref,
+                                                const double* __restrict__ T, double inv_Tref, double p,
+                                                double* __restrict__ out) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+        out[c] = cv_ref[c] * pow(T[c] * inv_Tref, p);
 }
 
 // Minimum of nb partials into *out (one workgroup, fixed order).
@@ -852,6 +864,12 @@ fld_status check_fields(fld_ctx* ctx, const double* E, const double* T, const do
 fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
                             const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st) {
     k_zero_int<<<1, 1, 0, st>>>(ctx->err_flag);
+    if (ctx->cv_p != 0.0) {
+        // c_v(T^n) of the power law; the gas update reads the same values
+        const int n = ctx->nx * ctx->ny;
+        k_cv_law<<<grid1d(n), 256, 0, st>>>(n, cv, T, 1.0 / ctx->cv_Tref, ctx->cv_p, ctx->cvl);
+        cv = ctx->cvl;
+    }
     AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc, ctx->fx, ctx->fy};
     AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part, ctx->bside, ctx->rside};
     const dim3 ag = cell_grid(ctx->nx, ctx->ny);
@@ -1316,7 +1334,7 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         fld_status as = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, cs);
         if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, budget, cs);
         else enqueue_solve_fixed<double>(ctx, E, budget, cs);
-        k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, cv, dt, T);
+        k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, ctx->cv, dt, T);
         k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, nsteps, (void*)dinfo, (int)ctx->h64.size());
         hipError_t e = hipStreamEndCapture(cs, &g);
         if (as == FLD_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -1432,7 +1450,13 @@ fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, co
             ctx->err = "coupling-limited sub-steps exceed max_sub";
             return FLD_ENOCONV;
         }
-        k_coupling_dt<<<nb, 256, 0, ctx->stream>>>(n, E, T, rho, kP, cv, dbar, ctx->part2);
+        const double* cvk = cv;
+        if (ctx->cv_p != 0.0) {
+            // the sub-step's heat capacity at its start (the assembly recomputes the same)
+            k_cv_law<<<nb, 256, 0, ctx->stream>>>(n, cv, T, 1.0 / ctx->cv_Tref, ctx->cv_p, ctx->cvl);
+            cvk = ctx->cvl;
+        }
+        k_coupling_dt<<<nb, 256, 0, ctx->stream>>>(n, E, T, rho, kP, cvk, dbar, ctx->part2);
         k_reduce_min<<<1, 1024, 0, ctx->stream>>>(ctx->part2, nb, ctx->dt_lim);
         HIPCHK(hipGetLastError());
         double lim = 0.0;
@@ -1461,6 +1485,21 @@ fld_status fld_face_flux(fld_ctx* ctx, const double* E, double* Fx, double* Fy, 
     k_face_flux<<<grid1d(nf), 256, 0, ctx->stream>>>(ctx->met, ctx->We, ctx->Wn, ctx->bside, ctx->rside, E, ctx->dt,
                                                       w, accumulate ? 1 : 0, Fx, Fy);
     HIPCHK(hipGetLastError());
+    return FLD_OK;
+}
+
+fld_status fld_set_cv_law(fld_ctx* ctx, double T_ref, double p) {
+    if (!ctx) return FLD_EINVAL;
+    if (!(T_ref > 0.0) || !std::isfinite(T_ref) || !std::isfinite(p)) {
+        ctx->err = "the heat-capacity law needs a finite T_ref > 0 and a finite p";
+        return FLD_EINVAL;
+    }
+    if (p != 0.0 && !ctx->cvl && ctx->alloc(&ctx->cvl, (size_t)ctx->nx * ctx->ny) != hipSuccess) {
+        ctx->err = "hipMalloc cvl";
+        return FLD_ENOMEM;
+    }
+    ctx->cv_Tref = T_ref;
+    ctx->cv_p = p;
     return FLD_OK;
 }
 

@@ -25,7 +25,7 @@ needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libfld.so not bu
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_face_flux", "fld_set_mass_flux", "fld_gas_update",
+    for f in ("fld_create", "fld_assemble", "fld_solve", "fld_step", "fld_steps", "fld_substep", "fld_face_flux", "fld_set_mass_flux", "fld_set_cv_law", "fld_gas_update",
               "fld_get_operator", "fld_destroy", "fld_default_options", "fld_batch_create", "fld_batch_step",
               "fld_batch_steps", "fld_batch_destroy"):
         assert f in names
@@ -52,6 +52,9 @@ def test_host_only_entry_points_run_without_gpu():
     assert lib.fld_create(None, None, None, None) == 1  # EINVAL before any device call
     lib.fld_set_mass_flux.restype = ctypes.c_int32
     assert lib.fld_set_mass_flux(None, None, None) == 1
+    lib.fld_set_cv_law.restype = ctypes.c_int32
+    lib.fld_set_cv_law.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    assert lib.fld_set_cv_law(None, 1.0, 1.5) == 1
     lib.fld_substep.restype = ctypes.c_int32
     n_done = ctypes.c_int32(7)
     assert lib.fld_substep(None, None, None, None, None, None, None, None, ctypes.c_double(1.0), 1,

@@ -308,7 +308,11 @@ def substep_extra(fld, torch, W, tuned):
     (seeded; the recipe itself starts in equilibrium, where the coupling does
     not limit): one full step as a geometric series of 4 sub-steps (q = 1.5),
     and the first 100 coupling-limited sub-steps with dbar = 0.1 (the whole
-    step needs ~2350 there).  Wall times on the solve stream's host clock."""
+    step needs ~2350 there); the same geometric series with the power-law heat
+    capacity c_v (T / T_mean)^-0.5 recomputed before every sub-step
+    (fld_set_cv_law; with a positive exponent the coldest cells' small heat
+    capacity lets the linearised gas update overshoot without bound on this
+    stiff recipe, in the oracle too).  Wall times on the solve stream's host clock."""
     import numpy as np
     prob = W.make_c2()
     prob.T = prob.T * (1.0 + 0.3 * np.random.default_rng(11).uniform(-1.0, 1.0, prob.T.shape))
@@ -317,7 +321,10 @@ def substep_extra(fld, torch, W, tuned):
     ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces, [(b.kind, b.value) for b in prob.bc],
                       options(fld, "mixed", tuned))
     for name, kw in (("geometric_n4_q1.5", dict(n_sub=4, q=1.5, max_sub=4)),
-                     ("coupling_dbar0.1_first100", dict(dbar=0.1, max_sub=100))):
+                     ("coupling_dbar0.1_first100", dict(dbar=0.1, max_sub=100)),
+                     ("geometric_n4_q1.5_cv_law_p-0.5", dict(n_sub=4, q=1.5, max_sub=4))):
+        law = name.endswith("cv_law_p-0.5")
+        ctx.set_cv_law(float(prob.T.mean()) if law else 1.0, -0.5 if law else 0.0)
         ms, res = [], None
         for rep in range(2):
             E, T = f["E"].clone(), f["T"].clone()
@@ -330,6 +337,7 @@ def substep_extra(fld, torch, W, tuned):
         out[name] = {"ms": ms[-1], "sub_steps": n, "ms_per_sub_step": ms[-1] / n,
                      "inner_iters": sum(i["inner_iters"] for i in res["infos"]),
                      "dt_covered": sum(res["dts"]) / prob.dt, "status": res["status"]}
+    ctx.set_cv_law(1.0, 0.0)
     ctx.close()
     return out
 

@@ -320,14 +320,21 @@ def advection_volume_term(met: Metrics, E, rho, fx, fy) -> np.ndarray:
 
 
 def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
-             bcs: Sequence[BCSpec], limiter: int = LIMITER_LP, fx=None, fy=None) -> Assembled:
+             bcs: Sequence[BCSpec], limiter: int = LIMITER_LP, fx=None, fy=None, E_op=None) -> Assembled:
     """Build the volume-weighted, T-eliminated E system of one backward-Euler
     step.  fx [ny][nx+1], fy [ny+1][nx]: face mass fluxes rho v of the
-    advection term (None: S_adv = 0), added explicitly as dt dV S_adv."""
+    advection term (None: S_adv = 0), added explicitly as dt dV S_adv.
+
+    E_op: the radiation energy that the interface coefficients D (interior
+    and boundary faces) and the advection term are evaluated from; None takes
+    E itself.  In the sub-cycled step D and S_adv come from the step's start
+    (Section 3.2.1 radiation-subsystem algorithm, steps 1 and 2, taken once),
+    while E enters the sub-step's own time derivative."""
     lim = LIMITERS[limiter]
     met = metrics(geom, xf, yf)
     nx, ny = met.nx, met.ny
     E = np.asarray(E, dtype=np.float64).reshape(ny, nx)
+    Eo = E if E_op is None else np.asarray(E_op, dtype=np.float64).reshape(ny, nx)
     T = np.asarray(T, dtype=np.float64).reshape(ny, nx)
     rho = np.asarray(rho, dtype=np.float64).reshape(ny, nx)
     kR = np.asarray(kappa_R, dtype=np.float64).reshape(ny, nx)
@@ -342,12 +349,12 @@ def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
     # interior x faces: between cells i-1 and i, i = 1..nx-1
     if nx > 1:
         hL, hR = met.hLx[:, 1:-1], met.hRx[:, 1:-1]
-        D = face_D(sig[:, :-1], sig[:, 1:], hL, hR, E[:, :-1], E[:, 1:], lim)
+        D = face_D(sig[:, :-1], sig[:, 1:], hL, hR, Eo[:, :-1], Eo[:, 1:], lim)
         D_x[:, 1:-1] = D
         W_x[:, 1:-1] = dt * met.dSx[:, 1:-1] * D / (hL + hR)
     if ny > 1:
         hL, hR = met.hLy[1:-1, :], met.hRy[1:-1, :]
-        D = face_D(sig[:-1, :], sig[1:, :], hL, hR, E[:-1, :], E[1:, :], lim)
+        D = face_D(sig[:-1, :], sig[1:, :], hL, hR, Eo[:-1, :], Eo[1:, :], lim)
         D_y[1:-1, :] = D
         W_y[1:-1, :] = dt * met.dSy[1:-1, :] * D / (hL + hR)
 
@@ -361,7 +368,7 @@ def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
         (np.s_[-1, :], met.hLy[-1, :], met.dSy[-1, :], (np.s_[-1, :], "y")),
     ]
     for b, (cell, h1, dS, (face, ax)) in zip(bcs, sides):
-        da, ra, Wb, Db = boundary_terms(b.kind, b.value, b.ghost, E[cell], sig[cell], h1, dS, dt, lim)
+        da, ra, Wb, Db = boundary_terms(b.kind, b.value, b.ghost, Eo[cell], sig[cell], h1, dS, dt, lim)
         bdiag[cell] += da
         brhs[cell] += ra
         if ax == "x":
@@ -388,7 +395,7 @@ def assemble(geom, xf, yf, E, T, rho, kappa_R, kappa_P, c_v, dt,
     if fx is not None or fy is not None:
         fx = np.zeros((ny, nx + 1)) if fx is None else fx
         fy = np.zeros((ny + 1, nx)) if fy is None else fy
-        rhs = rhs + dt * advection_volume_term(met, E, rho, fx, fy)
+        rhs = rhs + dt * advection_volume_term(met, Eo, rho, fx, fy)
     M = build_matrix(diag, Wxi, Wyi)
     return Assembled(met, W_x, W_y, D_x, D_y, diag, rhs, CV, beta, X, f, bdiag, brhs, M)
 

@@ -86,3 +86,39 @@ def test_conservation_all_boundary_kinds_cartesian():
     inflow = O.boundary_energy_input(prob.geom, res.A, bcs, res.E, prob.dt)
     assert inflow != 0.0
     assert abs(d - inflow) <= 1e-11 * abs(O.total_energy(res.A, prob.E, prob.T))
+
+
+@pytest.mark.parametrize("prob", [W.make_c2(nx=13, ny=10), W.make_c5(nx=12, ny=10)], ids=lambda p: p.name)
+def test_stop_rule_residuals_of_a_single_perturbation(prob):
+    """The two stop-rule residuals (Section 3.2.1, ||b - A x|| < eps ||b||, in
+    the per-volume and the Jacobi-scaled row forms) of the exact solution
+    perturbed by delta in one cell c: the residual is then -delta times
+    column c of M, i.e. -delta diag_c at c and +delta W at the faces c
+    shares with its neighbours, written out here from the assembled
+    coefficients cell by cell."""
+    A = O.assemble_problem(prob)
+    E = O.solve(A)
+    ny, nx = A.diag.shape
+    rhs = A.rhs
+    for (j, i) in [(0, 0), (ny // 2, nx // 2), (ny - 1, nx - 1), (3, nx - 1)]:
+        delta = 1e-3 * E[j, i]
+        Ep = E.copy()
+        Ep[j, i] += delta
+        r = np.zeros((ny, nx))
+        r[j, i] = -delta * A.diag[j, i]
+        if i > 0:
+            r[j, i - 1] += delta * A.W_x[j, i]
+        if i + 1 < nx:
+            r[j, i + 1] += delta * A.W_x[j, i + 1]
+        if j > 0:
+            r[j - 1, i] += delta * A.W_y[j, i]
+        if j + 1 < ny:
+            r[j + 1, i] += delta * A.W_y[j + 1, i]
+        dV = A.met.dV
+        row = np.sqrt(np.sum((r / dV) ** 2)) / np.sqrt(np.sum((rhs / dV) ** 2))
+        s = 1.0 / np.sqrt(A.diag)
+        scaled = np.sqrt(np.sum((s * r) ** 2)) / np.sqrt(np.sum((s * rhs) ** 2))
+        # the unperturbed solution's own residual is rounding, far below these
+        assert O.residual_rowform(A, Ep) == pytest.approx(row, rel=1e-6)
+        assert O.residual_scaled(A, Ep) == pytest.approx(scaled, rel=1e-6)
+    assert O.residual_scaled(A, E) < 1e-13

@@ -280,3 +280,21 @@ FULL_SIZES: Dict[str, tuple] = {"c1": (64, 64), "c2": (1024, 1024), "c3": (2048,
 
 def make(name: str, **kw):
     return MAKERS[name](**kw)
+
+
+def theta_slab(prob: Problem, j0: int, j1: int) -> Problem:
+    """Rows j0 .. j1-1 of a spherical-polar problem at its own resolution: the
+    share of one GPU if the grid were split into theta slabs.  A cut side is
+    reflecting; a side on the pole keeps the axis."""
+    ny = prob.ny
+    if not (0 <= j0 < j1 <= ny):
+        raise ValueError("slab rows out of range")
+    rows = slice(j0, j1)
+    bc = list(prob.bc)
+    bc[2] = prob.bc[2] if j0 == 0 else BC()
+    bc[3] = prob.bc[3] if j1 == ny else BC()
+    return Problem(
+        name=f"{prob.name}[{j0}:{j1}]", geom=prob.geom, x_faces=prob.x_faces.copy(),
+        y_faces=prob.y_faces[j0:j1 + 1].copy(), E=prob.E[rows].copy(), T=prob.T[rows].copy(),
+        rho=prob.rho[rows].copy(), kappa_R=prob.kappa_R[rows].copy(), kappa_P=prob.kappa_P[rows].copy(),
+        c_v=prob.c_v[rows].copy(), dt=prob.dt, bc=bc, nsteps=prob.nsteps)

@@ -23,7 +23,12 @@
  *    NULL = the default stream).  A call that returns a fld_solve_info, or
  *    that must test convergence, synchronises that stream.
  *  - The context owns all workspace; it is allocated in fld_create /
- *    fld_batch_create.  No other entry point allocates device memory.
+ *    fld_batch_create.  Only these other entry points allocate device
+ *    memory: fld_set_cv_law (one array of nx*ny doubles, on the first call
+ *    with p != 0, kept until fld_destroy) and the tuners fld_tune /
+ *    fld_batch_tune (a context per candidate and scratch copies of E and T,
+ *    freed before they return).  Assembly, solve, step, multi-step and
+ *    sub-step calls allocate nothing.
  *  - Errors are returned as fld_status, never thrown; fld_last_error gives a
  *    human-readable message.  Contexts are not thread-safe: use one per stream.
  *  - Units are cgs.  The azimuthal factor 2 pi of spherical-polar volumes and
@@ -43,7 +48,7 @@ typedef struct fld_ctx fld_ctx;
 typedef enum {
     FLD_OK = 0,
     FLD_EINVAL = 1,        /* bad argument: sizes, pointers, dt <= 0, unknown enum value     */
-    FLD_ENOMEM = 2,        /* device or pinned allocation failed (create calls only)          */
+    FLD_ENOMEM = 2,        /* device or pinned allocation failed (create, set_cv_law, tuners) */
     FLD_EHIP = 3,          /* a HIP runtime call failed                                        */
     FLD_ENOCONV = 4,       /* tolerance not reached within max_inner iterations (or stalled)   */
     FLD_EBREAKDOWN = 5,    /* CG breakdown: p.Ap <= 0 or non-finite scalar                     */
@@ -222,10 +227,11 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
  * another reason (stagnation, breakdown) is recorded and, unlike fld_step,
  * its gas update and the following steps still run.  With profiling on or
  * use_graph = 0 the steps run as fld_step calls and stop at the first
- * failure.  Allocates per-step records and one saved copy of E and T for the
- * call.  per_step (host, nsteps entries) may be NULL; a graph-launched step's
- * ms is the mean over those launches.  Returns the first non-OK step
- * status. */
+ * failure.  The saved copy of E and T and the device step records of a
+ * segment belong to the context (allocated by fld_create); the call itself
+ * allocates no device memory.  per_step (host, nsteps entries) may be NULL;
+ * a graph-launched step's ms is the mean over those launches.  Returns the
+ * first non-OK step status. */
 fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);
@@ -236,10 +242,16 @@ fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_
                            const double* kappa_R, const double* kappa_P, const double* c_v,
                            const double* ghost_E, double dt, fld_solve_info* per_step);
 
-/* One radiation step of length dt taken as sub-steps (Section 3.2.1, the
- * sub-step rules that follow the gas-energy linearisation), each an fld_step
- * of its own length with the opacities, rho and c_v held fixed and E, T
- * advanced in place:
+/* One radiation step of length dt taken as sub-steps, in the order of the
+ * radiation-subsystem algorithm of Section 3.2.1: the advection term S_adv
+ * (step 1) and the face coefficients D of every interior and boundary face
+ * (step 2) are evaluated once, from the E^n passed in (the context keeps a
+ * copy); every sub-step then recomputes C_V (step 3, see fld_set_cv_law),
+ * builds the coefficients for its own length dt_k (alpha = dt_k / h,
+ * beta = kappa_P rho c dt_k, the conductances dt_k dS D^n / h, the boundary
+ * terms and dt_k dV S_adv), solves, and updates T (steps 4-6), E and T
+ * advancing in place, opacities and rho held fixed (step 7 returns to step 3).
+ * Sub-step lengths:
  *   dbar == 0: the prescribed geometric series dt_i = dt_0 q^(i-1),
  *              i = 1..n_sub, dt_0 = dt (1 - q) / (1 - q^n_sub) (the paper asks
  *              for 1 < q < 2; any q > 0 is accepted, q = 1 giving n_sub equal
@@ -255,7 +267,9 @@ fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_
  * sub-step's length and solve record; *n_done (may be NULL) the number of
  * sub-steps taken.  Fx, Fy (device, layouts of fld_face_flux, may be NULL)
  * receive the face fluxes averaged over the sub-steps, sum_k (dt_k / dt) F_k
- * (the paper's sum over the sub-cycle of the flux formula).  Returns EINVAL for bad parameters (max_sub < 1, dbar < 0,
+ * with F_k = -D^n (E_hi^k - E_lo^k) / h (the paper's flux formula, D^n
+ * outside the sum over the sub-cycle; boundary faces from their fixed terms).
+ * With one sub-step the result equals fld_step's bit for bit.  Returns EINVAL for bad parameters (max_sub < 1, dbar < 0,
  * geometric with n_sub outside 1..max_sub or q <= 0) or fields, ENOCONV if the
  * coupling-limited loop needs more than max_sub sub-steps (E, T then hold the
  * state after max_sub of them), ENONFINITE if a limit is not positive, else

@@ -25,7 +25,9 @@ static_assert(sizeof(fld_solve_info) == sizeof(StepInfo) && offsetof(fld_solve_i
 
 namespace {
 
-constexpr const char* kVersion = "fld-mi355x 0.1";
+constexpr const char* kVersion = "fld-mi355x 0.2";
+// longest segment of graph-replayed steps between two host reads (fld_steps)
+constexpr int kStepSeg = 8;
 
 #define HIPCHK(call)                                                                          \
     do {                                                                                      \
@@ -103,6 +105,11 @@ struct fld_ctx {
     double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
     double* mu = nullptr;  // device: max diagonal (inner normalisation)
     double* dt_lim = nullptr;  // device: coupling-limited sub-step length (fld_substep)
+    // step-start copies: E^n of a sub-cycled step (its operator), or the (E, T)
+    // a multi-step segment restarts from; per-step records of one segment
+    double *Esave = nullptr, *Tsave = nullptr;
+    fld_solve_info* seg_info = nullptr;
+    int* seg_count = nullptr;
     const double *fx = nullptr, *fy = nullptr;  // caller's face mass fluxes (fld_set_mass_flux)
     double cv_Tref = 1.0, cv_p = 0.0;  // power-law heat capacity (fld_set_cv_law; p = 0: off)
     double* cvl = nullptr;             // its per-cell c_v at the assembled T^n
@@ -861,8 +868,11 @@ fld_status check_fields(fld_ctx* ctx, const double* E, const double* T, const do
 }
 
 // Assembly and multigrid hierarchy, kernels only (capturable).
+// Eop: the E the face coefficients and the advection term are taken from
+// (null: E; a sub-cycled step passes its saved E^n).
 fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, const double* rho, const double* kR,
-                            const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st) {
+                            const double* kP, const double* cv, const double* ghost, double dt, hipStream_t st,
+                            const double* Eop = nullptr) {
     k_zero_int<<<1, 1, 0, st>>>(ctx->err_flag);
     if (ctx->cv_p != 0.0) {
         // c_v(T^n) of the power law; the gas update reads the same values
@@ -870,7 +880,7 @@ fld_status enqueue_assemble(fld_ctx* ctx, const double* E, const double* T, cons
         k_cv_law<<<grid1d(n), 256, 0, st>>>(n, cv, T, 1.0 / ctx->cv_Tref, ctx->cv_p, ctx->cvl);
         cv = ctx->cvl;
     }
-    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc, ctx->fx, ctx->fy};
+    AsmIn in{E, T, rho, kR, kP, cv, ghost, dt, ctx->opt.limiter, ctx->bc, ctx->fx, ctx->fy, Eop};
     AsmOut out{ctx->We, ctx->Wn, ctx->m, ctx->rhs, ctx->s, ctx->err_flag, ctx->part, ctx->bside, ctx->rside};
     const dim3 ag = cell_grid(ctx->nx, ctx->ny);
     k_assemble<<<ag, blk2d(), 0, st>>>(ctx->met, in, out);
@@ -1203,6 +1213,10 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->dt_lim, 1);
     ALLOC(ctx->bside, 2 * (size_t)(nx + ny));
     ALLOC(ctx->rside, 2 * (size_t)(nx + ny));
+    ALLOC(ctx->Esave, n);
+    ALLOC(ctx->Tsave, n);
+    ALLOC(ctx->seg_info, kStepSeg);
+    ALLOC(ctx->seg_count, 1);
 #undef ALLOC
     if (hipHostMalloc((void**)&ctx->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned scalars");
@@ -1297,32 +1311,22 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     int slots = std::min(ctx->opt.max_inner, ((first.inner_iters * 2 + 16) + 1) & ~1);
     // one captured step: assembly, hierarchy, fixed-budget solve, gas update,
     // per-step record; replayed in segments of seg steps (1, doubling after
-    // every clean segment up to kSeg).  After each segment the host reads the
-    // records once; if a step ran out of its iteration budget, the budget grows
-    // by half, the step is re-captured and the segment is replayed from the
-    // saved (E, T) with seg = 1 again.
-    constexpr int kSeg = 8;
+    // every clean segment up to kStepSeg).  After each segment the host reads
+    // the records once; if a step ran out of its iteration budget, the budget
+    // grows by half, the step is re-captured and the segment is replayed from
+    // the saved (E, T) with seg = 1 again.  Records and saved fields live in
+    // the context (no allocation here).
     int seg = 1;
     if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     const int n = ctx->nx * ctx->ny;
-    fld_solve_info* dinfo = nullptr;
-    int* dcount = nullptr;
-    double *Esave = nullptr, *Tsave = nullptr;
+    fld_solve_info* dinfo = ctx->seg_info;
+    int* dcount = ctx->seg_count;
+    double *Esave = ctx->Esave, *Tsave = ctx->Tsave;
     hipGraphExec_t ge = nullptr;
     fld_status st = FLD_OK;
     auto cleanup = [&]() {
         if (ge) (void)hipGraphExecDestroy(ge);
-        (void)hipFree(dinfo);
-        (void)hipFree(dcount);
-        (void)hipFree(Esave);
-        (void)hipFree(Tsave);
     };
-    if (hipMalloc(&dinfo, sizeof(fld_solve_info) * nsteps) != hipSuccess || hipMalloc(&dcount, sizeof(int)) != hipSuccess ||
-        hipMalloc(&Esave, sizeof(double) * n) != hipSuccess || hipMalloc(&Tsave, sizeof(double) * n) != hipSuccess) {
-        cleanup();
-        ctx->err = "multi-step buffers";
-        return FLD_ENOMEM;
-    }
     auto capture = [&](int budget) -> fld_status {
         if (ge) {
             (void)hipGraphExecDestroy(ge);
@@ -1335,7 +1339,7 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, budget, cs);
         else enqueue_solve_fixed<double>(ctx, E, budget, cs);
         k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, ctx->cv, dt, T);
-        k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, nsteps, (void*)dinfo, (int)ctx->h64.size());
+        k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, kStepSeg, (void*)dinfo, (int)ctx->h64.size());
         hipError_t e = hipStreamEndCapture(cs, &g);
         if (as == FLD_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         if (g) (void)hipGraphDestroy(g);
@@ -1353,7 +1357,8 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     while (st == FLD_OK && k < nsteps) {
         const int m = std::min(seg, nsteps - k);
         const int c0 = k - 1;
-        if (hipMemcpy(dcount, &c0, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        k_zero_int<<<1, 1, 0, ctx->stream>>>(dcount);
+        if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(Esave, E, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
             hipMemcpyAsync(Tsave, T, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
             st = FLD_EHIP;
@@ -1362,7 +1367,7 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         for (int q = 0; q < m && st == FLD_OK; ++q)
             if (hipGraphLaunch(ge, ctx->stream) != hipSuccess) st = FLD_EHIP;
         if (st != FLD_OK || hipStreamSynchronize(ctx->stream) != hipSuccess ||
-            hipMemcpy(h.data() + c0, dinfo + c0, sizeof(fld_solve_info) * m, hipMemcpyDeviceToHost) != hipSuccess) {
+            hipMemcpy(h.data() + c0, dinfo, sizeof(fld_solve_info) * m, hipMemcpyDeviceToHost) != hipSuccess) {
             st = FLD_EHIP;
             break;
         }
@@ -1381,7 +1386,7 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
             continue;  // replay the segment with the larger budget
         }
         k += m;
-        seg = std::min(kSeg, 2 * seg);
+        seg = std::min(kStepSeg, 2 * seg);
     }
     const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     cleanup();
@@ -1416,9 +1421,20 @@ fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, co
     }
     fld_status s = check_fields(ctx, E, T, rho, kR, kP, cv, ghost, dt);
     if (s != FLD_OK) return s;
+    // steps 1-2 of the radiation-subsystem algorithm are taken once per step:
+    // every sub-step's face coefficients and advection term come from E^n,
+    // saved here, while its time derivative, C_V, beta and f use the
+    // sub-step's own state and length
+    const double* En = ctx->Esave;
+    HIPCHK(hipMemcpyAsync(ctx->Esave, E, sizeof(double) * ctx->nx * ctx->ny, hipMemcpyDeviceToDevice, ctx->stream));
     auto sub = [&](int k, double h) -> fld_status {
         fld_solve_info inf{};
-        const fld_status sk = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, h, &inf);
+        fld_status sk = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, h, ctx->stream, En);
+        if (sk == FLD_OK) {
+            ctx->assembled = true;
+            sk = fld_solve(ctx, E, &inf);
+        }
+        if (sk == FLD_OK) sk = fld_gas_update(ctx, E, T);
         if (per_sub) per_sub[k] = inf;
         if (dts) dts[k] = h;
         if (n_done) *n_done = k + 1;

@@ -1,11 +1,11 @@
 // HIP kernels of the implicit FLD radiation step (gfx950, wave64).
 //
-// Layout: cell arrays row-major [ny][nx]; 2D stencil kernels work on 64 x 16
-// tiles staged in LDS with a halo; 1D kernels stream with a grid-stride loop.
-// Reductions: wave64 butterfly (shfl_xor) + LDS per workgroup, one FP64
-// partial per workgroup, and the last workgroup to finish (device-scope
-// counter) sums the partials in a fixed order, so every reduction is
-// deterministic and no extra launch is needed.
+// Layout: cell arrays row-major [ny][nx].  The assembly runs one thread per
+// cell on 64 x 4 workgroups and reads its neighbours' fields straight from
+// global memory (the rows are shared through L2); 1D kernels stream with a
+// grid-stride loop.  Reductions: wave64 butterfly (shfl_xor) + LDS per
+// workgroup, one FP64 partial per workgroup, summed in a fixed order by the
+// kernel that consumes them, so every reduction is deterministic.
 #pragma once
 #include "fld_internal.hpp"
 
@@ -233,6 +233,10 @@ struct AsmIn {
     int lim;
     BCDev bc;
     const double *fx, *fy;  // face mass fluxes of the advection term ([ny][nx+1], [ny+1][nx]); null: none
+    // E that the face coefficients D (interior and boundary) and the advection
+    // term are evaluated from; null: E itself.  A sub-cycled step passes its
+    // starting E^n here for every sub-step (Section 3.2.1 steps 1-2 once per step).
+    const double* Eop;
 };
 struct AsmOut {
     double *We, *Wn, *m, *rhs, *s;
@@ -260,9 +264,12 @@ __device__ inline void side_face(int k, int kind, double value, double Eg, doubl
 __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const AsmOut& out, int i, int j) {
     const int nx = g.nx, ny = g.ny;
     const size_t c = (size_t)j * nx + i;
-    const double E = in.E[c], T = in.T[c], rho = in.rho[c], kR = in.kR[c], kP = in.kP[c], cv = in.cv[c];
-    const bool ok = isfinite(E) && E > 0.0 && isfinite(T) && T > 0.0 && isfinite(rho) && rho > 0.0 &&
-                    isfinite(kR) && kR > 0.0 && isfinite(kP) && kP >= 0.0 && isfinite(cv) && cv >= 0.0;
+    const double* Eop = in.Eop ? in.Eop : in.E;
+    const double E = in.E[c], Eo = Eop[c], T = in.T[c], rho = in.rho[c], kR = in.kR[c], kP = in.kP[c],
+                 cv = in.cv[c];
+    const bool ok = isfinite(E) && E > 0.0 && isfinite(Eo) && Eo > 0.0 && isfinite(T) && T > 0.0 &&
+                    isfinite(rho) && rho > 0.0 && isfinite(kR) && kR > 0.0 && isfinite(kP) && kP >= 0.0 &&
+                    isfinite(cv) && cv >= 0.0;
     if (!ok) atomicOr(out.err, 1);
     const double dt = in.dt;
     const int lim = in.lim;
@@ -272,35 +279,35 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
     // x faces
     if (i > 0) {
         const size_t w = c - 1;
-        Ww = face_W(in.E[w], in.kR[w] * in.rho[w], E, sig, g.hxL[i], g.hxR[i], g.sx[i] * vyj, dt, lim);
+        Ww = face_W(Eop[w], in.kR[w] * in.rho[w], Eo, sig, g.hxL[i], g.hxR[i], g.sx[i] * vyj, dt, lim);
     } else {
         const double Eg = (in.bc.kind[0] == BC_DIRICHLET_GHOST) ? in.ghost[j] : 0.0;
-        side_face(j, in.bc.kind[0], in.bc.value[0], Eg, E, sig, g.hxR[0], g.sx[0] * vyj, dt, lim, out, bd, br);
+        side_face(j, in.bc.kind[0], in.bc.value[0], Eg, Eo, sig, g.hxR[0], g.sx[0] * vyj, dt, lim, out, bd, br);
     }
     if (i + 1 < nx) {
         const size_t e = c + 1;
-        We = face_W(E, sig, in.E[e], in.kR[e] * in.rho[e], g.hxL[i + 1], g.hxR[i + 1], g.sx[i + 1] * vyj, dt, lim);
+        We = face_W(Eo, sig, Eop[e], in.kR[e] * in.rho[e], g.hxL[i + 1], g.hxR[i + 1], g.sx[i + 1] * vyj, dt, lim);
     } else {
         const double Eg = (in.bc.kind[1] == BC_DIRICHLET_GHOST) ? in.ghost[ny + j] : 0.0;
-        side_face(ny + j, in.bc.kind[1], in.bc.value[1], Eg, E, sig, g.hxL[nx], g.sx[nx] * vyj, dt, lim, out, bd,
+        side_face(ny + j, in.bc.kind[1], in.bc.value[1], Eg, Eo, sig, g.hxL[nx], g.sx[nx] * vyj, dt, lim, out, bd,
                   br);
     }
     // y faces (theta distances are arc lengths at the volume-centre radius)
     if (j > 0) {
         const size_t s = c - nx;
-        Ws = face_W(in.E[s], in.kR[s] * in.rho[s], E, sig, g.hyL[j] * arci, g.hyR[j] * arci, axi * g.sy[j], dt, lim);
+        Ws = face_W(Eop[s], in.kR[s] * in.rho[s], Eo, sig, g.hyL[j] * arci, g.hyR[j] * arci, axi * g.sy[j], dt, lim);
     } else {
         const double Eg = (in.bc.kind[2] == BC_DIRICHLET_GHOST) ? in.ghost[2 * ny + i] : 0.0;
-        side_face(2 * ny + i, in.bc.kind[2], in.bc.value[2], Eg, E, sig, g.hyR[0] * arci, axi * g.sy[0], dt, lim,
+        side_face(2 * ny + i, in.bc.kind[2], in.bc.value[2], Eg, Eo, sig, g.hyR[0] * arci, axi * g.sy[0], dt, lim,
                   out, bd, br);
     }
     if (j + 1 < ny) {
         const size_t n = c + nx;
-        Wn = face_W(E, sig, in.E[n], in.kR[n] * in.rho[n], g.hyL[j + 1] * arci, g.hyR[j + 1] * arci,
+        Wn = face_W(Eo, sig, Eop[n], in.kR[n] * in.rho[n], g.hyL[j + 1] * arci, g.hyR[j + 1] * arci,
                     axi * g.sy[j + 1], dt, lim);
     } else {
         const double Eg = (in.bc.kind[3] == BC_DIRICHLET_GHOST) ? in.ghost[2 * ny + nx + i] : 0.0;
-        side_face(2 * ny + nx + i, in.bc.kind[3], in.bc.value[3], Eg, E, sig, g.hyL[ny] * arci, axi * g.sy[ny], dt,
+        side_face(2 * ny + nx + i, in.bc.kind[3], in.bc.value[3], Eg, Eo, sig, g.hyL[ny] * arci, axi * g.sy[ny], dt,
                   lim, out, bd, br);
     }
     // reflecting and axis sides carry no flux (boundary_face ignores them)
@@ -321,15 +328,15 @@ __device__ inline double assemble_cell(const Metrics& g, const AsmIn& in, const 
     double adv = 0.0;
     if (in.fx) {
         const size_t fc = (size_t)j * (nx + 1) + i;
-        const double flo = in.fx[fc], fhi = in.fx[fc + 1], er = E / rho;
-        const double erlo = i > 0 ? in.E[c - 1] / in.rho[c - 1] : er;
-        const double erhi = i + 1 < nx ? in.E[c + 1] / in.rho[c + 1] : er;
+        const double flo = in.fx[fc], fhi = in.fx[fc + 1], er = Eo / rho;
+        const double erlo = i > 0 ? Eop[c - 1] / in.rho[c - 1] : er;
+        const double erhi = i + 1 < nx ? Eop[c + 1] / in.rho[c + 1] : er;
         adv += g.sx[i] * vyj * flo * (flo >= 0.0 ? erlo : er) - g.sx[i + 1] * vyj * fhi * (fhi >= 0.0 ? er : erhi);
     }
     if (in.fy) {
-        const double flo = in.fy[c], fhi = in.fy[c + nx], er = E / rho;
-        const double erlo = j > 0 ? in.E[c - nx] / in.rho[c - nx] : er;
-        const double erhi = j + 1 < ny ? in.E[c + nx] / in.rho[c + nx] : er;
+        const double flo = in.fy[c], fhi = in.fy[c + nx], er = Eo / rho;
+        const double erlo = j > 0 ? Eop[c - nx] / in.rho[c - nx] : er;
+        const double erhi = j + 1 < ny ? Eop[c + nx] / in.rho[c + nx] : er;
         adv += axi * g.sy[j] * flo * (flo >= 0.0 ? erlo : er) - axi * g.sy[j + 1] * fhi * (fhi >= 0.0 ? er : erhi);
     }
     if (!isfinite(adv)) atomicOr(out.err, 1);

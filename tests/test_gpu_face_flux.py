@@ -77,14 +77,8 @@ def test_substep_average(lib):
     torch.cuda.synchronize()
     ctx.close()
     assert r["status"] == 0
-    bcs = O.bcs_from_problem(prob)
-    E, T = prob.E, prob.T
-    ax, ay = 0.0, 0.0
-    for h in S.geometric_substeps(prob.dt, 1.5, 3):
-        s = O.step(prob.geom, prob.x_faces, prob.y_faces, E, T, prob.rho, prob.kappa_R, prob.kappa_P, prob.c_v, h, bcs)
-        fx, fy = O.face_fluxes(s.A, E, s.E, prob.kappa_R * prob.rho, h, bcs)
-        ax, ay = ax + h / prob.dt * fx, ay + h / prob.dt * fy
-        E, T = s.E, s.T
+    ref = S.substep_problem(prob, n_sub=3, q=1.5)
+    ax, ay = ref.Fx, ref.Fy
     scale = max(np.abs(ax).max(), np.abs(ay).max())
     np.testing.assert_allclose(Fx.cpu().numpy(), ax, rtol=1e-7, atol=1e-8 * scale)
     np.testing.assert_allclose(Fy.cpu().numpy(), ay, rtol=1e-7, atol=1e-8 * scale)
@@ -125,14 +119,42 @@ def test_advection_substeps_and_fluxes_together(lib):
                     prob.c_v, prob.dt, bcs, n_sub=3, q=1.4, fx=fx, fy=fy)
     from gpu_helpers import rel_l2
     assert rel_l2(t["E"].cpu().numpy(), ref.E) < 1e-10 and rel_l2(t["T"].cpu().numpy(), ref.T) < 1e-10
-    E, T = prob.E, prob.T
-    ax, ay = 0.0, 0.0
-    for h in S.geometric_substeps(prob.dt, 1.4, 3):
-        s = O.step(prob.geom, prob.x_faces, prob.y_faces, E, T, prob.rho, prob.kappa_R, prob.kappa_P, prob.c_v, h, bcs,
-                   fx=fx, fy=fy)
-        gx, gy = O.face_fluxes(s.A, E, s.E, prob.kappa_R * prob.rho, h, bcs)
-        ax, ay = ax + h / prob.dt * gx, ay + h / prob.dt * gy
-        E, T = s.E, s.T
+    ax, ay = ref.Fx, ref.Fy
     sc = max(np.abs(ax).max(), np.abs(ay).max())
     np.testing.assert_allclose(Fx.cpu().numpy(), ax, rtol=1e-7, atol=1e-8 * sc)
     np.testing.assert_allclose(Fy.cpu().numpy(), ay, rtol=1e-7, atol=1e-8 * sc)
+
+
+def test_substep_balance_on_gpu_fields(lib):
+    """The GPU's own sub-cycled step closes every cell's energy balance with
+    its averaged fluxes and the step-start advection term (Section 3.2.1 flux
+    formula with D^n outside the sub-step sum):
+    dV (E^end - E^n) + dV C_V (T^end - T^n) = -dt sum_faces F dS + dt dV S_adv(E^n)."""
+    prob = case("cart")
+    rng = np.random.default_rng(5)
+    ny, nx = prob.E.shape
+    prob.T = prob.T * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, prob.T.shape))
+    met = O.metrics(prob.geom, prob.x_faces, prob.y_faces)
+    scale = 0.05 * float(np.median(prob.rho)) * float(np.median(met.dV / met.dSx[:, :-1])) / prob.dt
+    fx, fy = scale * rng.normal(size=(ny, nx + 1)), scale * rng.normal(size=(ny + 1, nx))
+    ctx = make_ctx(lib, prob, precision="fp64", rel_tol=1e-12, norm=1)
+    t = to_dev(prob, torch)
+    ctx.set_mass_flux(torch.tensor(fx, dtype=torch.float64, device="cuda"),
+                      torch.tensor(fy, dtype=torch.float64, device="cuda"))
+    Fx = torch.zeros((ny, nx + 1), dtype=torch.float64, device="cuda")
+    Fy = torch.zeros((ny + 1, nx), dtype=torch.float64, device="cuda")
+    r = ctx.substep(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, n_sub=4, q=1.6,
+                    check=False, Fx=Fx, Fy=Fy)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert r["status"] == 0
+    E, T, Fx, Fy = t["E"].cpu().numpy(), t["T"].cpu().numpy(), Fx.cpu().numpy(), Fy.cpu().numpy()
+    out = (Fx[:, 1:] * met.dSx[:, 1:] - Fx[:, :-1] * met.dSx[:, :-1]
+           + Fy[1:, :] * met.dSy[1:, :] - Fy[:-1, :] * met.dSy[:-1, :])
+    adv = O.advection_volume_term(met, prob.E, prob.rho, fx, fy)
+    CV = prob.rho * prob.c_v
+    lhs = met.dV * (E - prob.E) + met.dV * CV * (T - prob.T)
+    rhs = -prob.dt * out + prob.dt * adv
+    big = np.abs(met.dV * (E - prob.E)).max() + np.abs(prob.dt * adv).max() + np.abs(prob.dt * out).max()
+    # the solves stop at a 1e-12 scaled residual: that, not rounding, bounds the balance
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-8 * big)

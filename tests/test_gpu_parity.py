@@ -229,3 +229,63 @@ def test_k_cycle_and_v_cycle(lib, name, kw, prec):
         assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10
     assert ik["inner_iters"] <= iv["inner_iters"]
     assert iw["inner_iters"] <= iv["inner_iters"] + 1
+
+
+def thin_c1():
+    """The c1 recipe with rho lowered 1e3-fold: sigma dx = 0.01, so the
+    temperature bump drives the limiter argument R across 3/2 (both branches
+    of the Minerbo form)."""
+    prob = W.make_c1(nx=48, ny=40)
+    prob.rho = prob.rho * 1e-3
+    return prob
+
+
+@pytest.mark.parametrize("name", ["c1", "c1thin", "c5"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_minerbo_limiter(lib, name, prec):
+    """The paper's own limiter (Section 2, Minerbo-type, piecewise at R = 3/2)
+    through the whole step; c1thin and c5 have faces on both sides of 3/2."""
+    prob = {"c1": lambda: W.make_c1(nx=48, ny=40), "c1thin": thin_c1, "c5": lambda: W.make_c5(nx=160, ny=90)}[name]()
+    A = O.assemble_problem(prob, limiter=O.LIMITER_MINERBO)
+    sig = prob.kappa_R * prob.rho
+    hL, hR = A.met.hLx[:, 1:-1], A.met.hRx[:, 1:-1]
+    lam = A.D_x[:, 1:-1] * ((hL * sig[:, :-1] + hR * sig[:, 1:]) / (hL + hR)) / O.C_LIGHT
+    if name != "c1":
+        assert np.mean(lam < 2.0 / 9.0) > 0.02 and np.mean(lam > 2.0 / 9.0) > 0.02
+    print(f"[minerbo] {name} {prec}", flush=True)
+    ref = O.step_problem(prob, limiter=O.LIMITER_MINERBO)
+    lp = O.step_problem(prob)
+    # thin c1's binary64 floor of the scaled residual is ~6e-12 (refined oracle too)
+    tol = 3e-11 if name == "c1thin" else 1e-12
+    E, T, info = gpu_step(lib, torch, prob, precision=prec, limiter=1, rel_tol=tol, norm=1)
+    print(info["inner_iters"], rel_l2(E, ref.E), rel_l2(T, ref.T), "vs LP", rel_l2(lp.E, ref.E), flush=True)
+    assert info["status"] == 0
+    assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10
+    if name != "c1":
+        assert rel_l2(lp.E, ref.E) > 1e-6  # the limiter matters here
+
+
+@pytest.mark.parametrize("name", ["c2", "c5"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_reported_residuals_match_oracle(lib, name, prec):
+    """The residuals a solve reports (the stop rule's two row forms, computed
+    on the GPU in FP64 flux form) against the oracle's residual helpers
+    evaluated on the GPU's solution, at a loose tolerance where both are far
+    above rounding."""
+    prob = CASES[name]
+    for norm in (0, 1):
+        ctx = make_ctx(lib, prob, precision=prec, rel_tol=1e-6, norm=norm)
+        t = to_dev(prob, torch)
+        info = ctx.step(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"],
+                        check=False)
+        torch.cuda.synchronize()
+        E = t["E"].cpu().numpy()
+        ctx.close()
+        A = O.assemble_problem(prob)
+        row, scaled = O.residual_rowform(A, E), O.residual_scaled(A, E)
+        print(name, prec, norm, info["rel_resid_row"], row, info["rel_resid_scaled"], scaled, flush=True)
+        assert info["status"] == 0
+        assert info["rel_resid_row"] == pytest.approx(row, rel=1e-4)
+        assert info["rel_resid_scaled"] == pytest.approx(scaled, rel=1e-4)
+        assert info["rel_resid"] == (info["rel_resid_row"] if norm == 0 else info["rel_resid_scaled"])
+        assert info["rel_resid"] <= 1e-6

@@ -134,9 +134,13 @@ typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT 
  * of a second pass through the LDS levels only.  W2: the same two passes with
  * fixed coefficients, x = c1 + V(b - A c1) (a linear, symmetric
  * preconditioner; measured better than K on the 1e8-contrast spherical
- * stress grid, worse on the stretched Cartesian one).  K and W2 act as V
- * where a line smoother has no LDS sub-cycle (fewer than three levels, or
- * point smoothing). */
+ * stress grid, worse on the stretched Cartesian one).  W2 is positive
+ * definite only where the V-cycle converges as a stationary iteration
+ * (spectral radius of I - V A below one): on thin theta slabs of the stress
+ * grid (4096 x 64 .. 128 rows about the equator) it is not, and CG then
+ * stops with FLD_EBREAKDOWN; K and V have no such condition.  K and W2 act
+ * as V where a line smoother has no LDS sub-cycle (fewer than three levels,
+ * or point smoothing). */
 typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1, FLD_MG_CYCLE_W2 = 2 } fld_mg_cycle;
 
 typedef struct {
@@ -410,9 +414,11 @@ fld_status fld_batch_step(fld_batch* b, double* E_r, double* T_g, const double* 
 
 /* nsteps consecutive batch steps (fields other than E_r, T_g held fixed),
  * captured as one hipGraph of nsteps kernel nodes when use_graph is set;
- * synchronises once.  per_block receives the records of the last step;
- * returns the first non-OK status of any block in any
- * step (failed blocks continue with the next step). */
+ * synchronises once; allocates no device memory (each block's first failure
+ * is kept on the device between steps).  per_block receives the records of
+ * the last step; returns the first failure over all steps of the first
+ * failing block in the caller's order (failed blocks continue with the next
+ * step). */
 fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                            const double* kappa_R, const double* kappa_P, const double* c_v,
                            const double* ghost_E, double dt, fld_solve_info* per_block);

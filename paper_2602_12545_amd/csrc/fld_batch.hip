@@ -38,6 +38,7 @@ struct fld_batch {
     void *xi = nullptr, *p = nullptr, *q = nullptr;
     BInfo* dinfo = nullptr;
     BInfo* hinfo = nullptr;
+    int* dacc = nullptr;  // first non-OK status of each block over a multi-step call
     int threads = 512;
     double clock_khz = 1e5;
 
@@ -61,15 +62,14 @@ thread_local std::string t_create_err;  // reason of the last failed fld_batch_c
 
 bool inner_float(const fld_batch* b) { return b->opt.precision != FLD_FP64; }
 
-BOpts make_opts(const fld_batch* b) {
-    const fld_options& o = b->opt;
+BOpts make_opts(const fld_options& o, double clock_khz) {
     const double delta = o.precision == FLD_MIXED ? 0.1 : 1e-3;
     BOpts r;
     r.eps = o.rel_tol;
     r.delta2 = delta * delta;
     r.inner_tol2 = o.inner_rtol * o.inner_rtol;
     r.omega = o.mg_coarse_op == FLD_MG_HALVED ? 0.5 : 1.0;
-    r.clock_khz = b->clock_khz;
+    r.clock_khz = clock_khz;
     r.max_iter = o.max_inner;
     r.norm = o.norm;
     r.reliable = o.precision == FLD_FP32 ? 0 : 1;
@@ -89,7 +89,7 @@ void launch_t(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
                static_cast<T*>(b->lm), static_cast<T*>(b->lWe), static_cast<T*>(b->lWn),
                static_cast<T*>(b->lx), static_cast<T*>(b->lb),
                static_cast<T*>(b->xi), static_cast<T*>(b->p), static_cast<T*>(b->q)};
-    k_batch_step<T, NT><<<b->nb, NT, BLds<T, NT>::bytes, st>>>(b->db, f, w, make_opts(b), info);
+    k_batch_step<T, NT><<<b->nb, NT, BLds<T, NT>::bytes, st>>>(b->db, f, w, make_opts(b->opt, b->clock_khz), info);
 }
 
 template <typename T>
@@ -117,6 +117,78 @@ fld_status check_fields(fld_batch* b, const double* E, const double* T, const do
 BFields fields(fld_batch* b, double* E, double* T, const double* rho, const double* kR, const double* kP,
                const double* cv, const double* ghost, double dt) {
     return BFields{E, T, rho, kR, kP, cv, ghost, dt, b->opt.limiter, b->bc};
+}
+
+// Checks the options and sides of a batch (the coarsest level is clamped to
+// kBCoarse cells: it is solved in the workgroup); null if they are valid.
+const char* batch_options(fld_options& o, const fld_bc* bc, BCDev& bcd, bool& need_ghost) {
+    if (o.precision < 0 || o.precision > 2 || o.limiter < 0 || o.limiter > 2 || o.norm < 0 || o.norm > 1 ||
+        !(o.rel_tol > 0.0) || o.max_inner < 1 || !(o.inner_rtol > 0.0) || o.mg_coarse_max < 1 ||
+        o.mg_coarse_max > 256 || o.mg_coarse_op < 0 || o.mg_coarse_op > 1 || o.smoother != FLD_SMOOTH_LINE)
+        return "options (the batched solver uses line smoothing, mg_coarse_max in [1, 256])";
+    o.mg_coarse_max = std::min(o.mg_coarse_max, kBCoarse);
+    need_ghost = false;
+    for (int sd = 0; sd < 4; ++sd) {
+        const int k = bc ? bc[sd].kind : FLD_BC_DIRICHLET_GHOST;
+        const double v = bc ? bc[sd].value : 0.0;
+        if (k < 0 || k > FLD_BC_FREE_STREAM) return "boundary kind (Cartesian blocks)";
+        if (k == FLD_BC_DIRICHLET_FACE && !(v > 0.0 && std::isfinite(v))) return "boundary T";
+        if (k == FLD_BC_FLUX_IN && !std::isfinite(v)) return "boundary flux";
+        bcd.kind[sd] = k;
+        bcd.value[sd] = v;
+        if (k == FLD_BC_DIRICHLET_GHOST) need_ghost = true;
+    }
+    return nullptr;
+}
+
+const char* block_shape(int nx, int ny, double dx, double dy) {
+    if (nx < 1 || ny < 1 || nx > kBMaxSide || ny > kBMaxSide) return "block sides must be in [1, 512]";
+    if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(dx) || !std::isfinite(dy))
+        return "block spacing must be finite and > 0";
+    return nullptr;
+}
+
+// Multigrid levels of one block (2x2 aggregation down to mg_coarse_max cells)
+// starting at packed offset lo, which advances past them; false if too many.
+bool block_levels(BBlock& B, int coarse_max, long long& lo) {
+    int lx = B.nx, ly = B.ny, L = 0;
+    while (true) {
+        if (L >= kBMaxLev) return false;
+        B.lnx[L] = lx;
+        B.lny[L] = ly;
+        B.loff[L] = lo;
+        lo += ((long long)lx * ly + 3) / 4 * 4;  // 16-byte aligned levels (vector loads)
+        ++L;
+        if ((long long)lx * ly <= coarse_max) break;
+        lx = (lx + 1) / 2;
+        ly = (ly + 1) / 2;
+    }
+    B.nlev = L;
+    return true;
+}
+
+// Metric and face arrays of one block, carved from q0 (metric_doubles(nx, ny)
+// doubles): the layout k_metrics fills, then the face coordinates.
+long long metric_doubles(int nx, int ny) { return 6LL * (nx + 1) + 4LL * (ny + 1) + (nx + 1) + (ny + 1); }
+
+Metrics carve_metrics(double* q0, int X, int Y, double** xf, double** yf) {
+    double *vx = q0, *ax = vx + (X + 1), *arc = ax + (X + 1), *sx = arc + (X + 1), *hxL = sx + (X + 1),
+           *hxR = hxL + (X + 1);
+    double *vy = hxR + (X + 1), *sy = vy + (Y + 1), *hyL = sy + (Y + 1), *hyR = hyL + (Y + 1);
+    *xf = hyR + (Y + 1);
+    *yf = *xf + (X + 1);
+    return Metrics{X, Y, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR, arc};
+}
+
+// First non-OK status of every block, folded over the steps of one call.
+__global__ void k_fold_status(const BInfo* info, int nb, int* acc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nb && acc[k] == FLD_OK) acc[k] = info[k].status;
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0;
 }
 
 fld_status first_bad(const BInfo* inf, int nb) {
@@ -147,30 +219,11 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     if (opt) b->opt = *opt;
     else fld_default_options(&b->opt);
     const fld_options& o = b->opt;
-    if (o.precision < 0 || o.precision > 2 || o.limiter < 0 || o.limiter > 2 || o.norm < 0 || o.norm > 1 ||
-        !(o.rel_tol > 0.0) || o.max_inner < 1 || !(o.inner_rtol > 0.0) || o.mg_coarse_max < 1 ||
-        o.mg_coarse_max > 256 || o.mg_coarse_op < 0 || o.mg_coarse_op > 1 || o.smoother != FLD_SMOOTH_LINE)
-        return fail(FLD_EINVAL, "options (the batched solver uses line smoothing, mg_coarse_max in [1, 256])");
-    // a block's coarsest level is solved in the workgroup: at most kBCoarse cells
-    b->opt.mg_coarse_max = std::min(b->opt.mg_coarse_max, kBCoarse);
+    if (const char* why = batch_options(b->opt, bc, b->bc, b->need_ghost)) return fail(FLD_EINVAL, why);
     b->stream = static_cast<hipStream_t>(stream);
     b->nb = nblocks;
-    for (int sd = 0; sd < 4; ++sd) {
-        const int k = bc ? bc[sd].kind : FLD_BC_DIRICHLET_GHOST;
-        const double v = bc ? bc[sd].value : 0.0;
-        if (k < 0 || k > FLD_BC_FREE_STREAM) return fail(FLD_EINVAL, "boundary kind (Cartesian blocks)");
-        if (k == FLD_BC_DIRICHLET_FACE && !(v > 0.0 && std::isfinite(v))) return fail(FLD_EINVAL, "boundary T");
-        if (k == FLD_BC_FLUX_IN && !std::isfinite(v)) return fail(FLD_EINVAL, "boundary flux");
-        b->bc.kind[sd] = k;
-        b->bc.value[sd] = v;
-        if (k == FLD_BC_DIRICHLET_GHOST) b->need_ghost = true;
-    }
-    for (int k = 0; k < nblocks; ++k) {
-        if (nx[k] < 1 || ny[k] < 1 || nx[k] > kBMaxSide || ny[k] > kBMaxSide)
-            return fail(FLD_EINVAL, "block sides must be in [1, 512]");
-        if (!(dx[k] > 0.0) || !(dy[k] > 0.0) || !std::isfinite(dx[k]) || !std::isfinite(dy[k]))
-            return fail(FLD_EINVAL, "block spacing must be finite and > 0");
-    }
+    for (int k = 0; k < nblocks; ++k)
+        if (const char* why = block_shape(nx[k], ny[k], dx[k], dy[k])) return fail(FLD_EINVAL, why);
     // layout: packed cells / ghosts in the caller's order; levels per block
     std::vector<long long> off(nblocks), goff(nblocks);
     long long nc = 0, ng = 0, nm = 0;
@@ -179,7 +232,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
         goff[k] = ng;
         nc += (long long)nx[k] * ny[k];
         ng += 2LL * nx[k] + 2LL * ny[k];
-        nm += 6LL * (nx[k] + 1) + 4LL * (ny[k] + 1) + (nx[k] + 1) + (ny[k] + 1);
+        nm += metric_doubles(nx[k], ny[k]);
     }
     b->ncell = nc;
     b->nghost = ng;
@@ -199,19 +252,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
         B.id = k;
         B.off = off[k];
         B.goff = goff[k];
-        int lx = nx[k], ly = ny[k], L = 0;
-        while (true) {
-            if (L >= kBMaxLev) return fail(FLD_EINVAL, "too many multigrid levels");
-            B.lnx[L] = lx;
-            B.lny[L] = ly;
-            B.loff[L] = lo;
-            lo += ((long long)lx * ly + 3) / 4 * 4;  // 16-byte aligned levels (vector loads)
-            ++L;
-            if ((long long)lx * ly <= o.mg_coarse_max) break;
-            lx = (lx + 1) / 2;
-            ly = (ly + 1) / 2;
-        }
-        B.nlev = L;
+        if (!block_levels(B, o.mg_coarse_max, lo)) return fail(FLD_EINVAL, "too many multigrid levels");
     }
     b->nlev = lo;
 #define BALLOC(p, cnt) \
@@ -227,6 +268,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     BALLOC(met, nm);
     BALLOC(b->db, nblocks);
     BALLOC(b->dinfo, nblocks);
+    BALLOC(b->dacc, nblocks);
 #undef BALLOC
     if (hipHostMalloc((void**)&b->hinfo, sizeof(BInfo) * nblocks, hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned block records");
@@ -237,7 +279,7 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
         long long mp = 0;
         for (int k = 0; k < nblocks; ++k) {
             mo[k] = mp;
-            mp += 6LL * (nx[k] + 1) + 4LL * (ny[k] + 1) + (nx[k] + 1) + (ny[k] + 1);
+            mp += metric_doubles(nx[k], ny[k]);
         }
         hf.assign(mp, 0.0);
         for (int k = 0; k < nblocks; ++k) {
@@ -251,16 +293,16 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     std::vector<Metrics> mets(nblocks);
     for (int k = 0; k < nblocks; ++k) {
         const int X = nx[k], Y = ny[k];
-        double* q0 = met + mo[k];
-        double *vx = q0, *ax = vx + (X + 1), *arc = ax + (X + 1), *sx = arc + (X + 1), *hxL = sx + (X + 1),
-               *hxR = hxL + (X + 1);
-        double *vy = hxR + (X + 1), *sy = vy + (Y + 1), *hyL = sy + (Y + 1), *hyR = hyL + (Y + 1);
-        const double* xf = hyR + (Y + 1);
-        const double* yf = xf + (X + 1);
-        mets[k] = Metrics{X, Y, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR, arc};
+        double *xf, *yf;
+        const Metrics g = carve_metrics(met + mo[k], X, Y, &xf, &yf);
+        mets[k] = g;
         const int mt = std::max(X, Y) + 1;
-        k_metrics<<<(mt + 255) / 256, 256, 0, b->stream>>>(0, X, Y, xf, yf, vx, vy, sx, sy, ax, hxL, hxR, hyL, hyR,
-                                                           arc);
+        k_metrics<<<(mt + 255) / 256, 256, 0, b->stream>>>(0, X, Y, xf, yf, const_cast<double*>(g.vx),
+                                                           const_cast<double*>(g.vy), const_cast<double*>(g.sx),
+                                                           const_cast<double*>(g.sy), const_cast<double*>(g.ax),
+                                                           const_cast<double*>(g.hxL), const_cast<double*>(g.hxR),
+                                                           const_cast<double*>(g.hyL), const_cast<double*>(g.hyR),
+                                                           const_cast<double*>(g.arc));
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
         return fail(FLD_EHIP, "metrics kernels");
@@ -318,22 +360,27 @@ fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, c
     if (nsteps == 0) return FLD_OK;
     fld_status s = check_fields(b, E, T, rho, kR, kP, cv, ghost, dt);
     if (s != FLD_OK) return s;
-    BInfo* dall = nullptr;
-    if (hipMalloc(&dall, sizeof(BInfo) * (size_t)b->nb * nsteps) != hipSuccess) {
-        b->err = "hipMalloc step records";
-        return FLD_ENOMEM;
-    }
+    // every step writes the block records to dinfo (the last step's remain);
+    // a fold after each step keeps every block's first failure in dacc
     const BFields f = fields(b, E, T, rho, kR, kP, cv, ghost, dt);
+    const int fg = (b->nb + 255) / 256;
+    auto queue = [&](hipStream_t st) {
+        k_zero_ints<<<fg, 256, 0, st>>>(b->dacc, b->nb);
+        for (int k = 0; k < nsteps; ++k) {
+            launch(b, f, b->dinfo, st);
+            k_fold_status<<<fg, 256, 0, st>>>(b->dinfo, b->nb, b->dacc);
+        }
+    };
     fld_status st = FLD_OK;
     if (b->opt.use_graph) {
-        // every step is one kernel node; the nsteps nodes form one graph
+        // the nsteps kernel nodes (and their folds) form one graph
         hipStream_t cs = nullptr;
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int k = 0; k < nsteps; ++k) launch(b, f, dall + (size_t)k * b->nb, cs);
+            queue(cs);
             e = hipStreamEndCapture(cs, &g);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -347,24 +394,23 @@ fld_status fld_batch_steps(fld_batch* b, int32_t nsteps, double* E, double* T, c
             st = FLD_EHIP;
         }
     } else {
-        for (int k = 0; k < nsteps; ++k) launch(b, f, dall + (size_t)k * b->nb, b->stream);
+        queue(b->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) {
             b->err = "batch kernels";
             st = FLD_EHIP;
         }
     }
-    std::vector<BInfo> h;
-    if (st == FLD_OK) {
-        h.resize((size_t)b->nb * nsteps);
-        if (hipMemcpy(h.data(), dall, sizeof(BInfo) * h.size(), hipMemcpyDeviceToHost) != hipSuccess) st = FLD_EHIP;
-    }
-    (void)hipFree(dall);
     if (st != FLD_OK) return st;
-    for (int k = 0; k < nsteps && st == FLD_OK; ++k) st = first_bad(h.data() + (size_t)k * b->nb, b->nb);
-    if (per_block) {
-        const BInfo* last = h.data() + (size_t)(nsteps - 1) * b->nb;
-        for (int k = 0; k < b->nb; ++k) std::memcpy(&per_block[k], &last[k], sizeof(BInfo));
+    std::vector<int> acc(b->nb);
+    if (hipMemcpy(acc.data(), b->dacc, sizeof(int) * b->nb, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(b->hinfo, b->dinfo, sizeof(BInfo) * b->nb, hipMemcpyDeviceToHost) != hipSuccess) {
+        b->err = "batch records";
+        return FLD_EHIP;
     }
+    // the first failing block in the caller's order, as a single batch step reports it
+    for (int k = 0; k < b->nb && st == FLD_OK; ++k) st = (fld_status)acc[k];
+    if (per_block)
+        for (int k = 0; k < b->nb; ++k) std::memcpy(&per_block[k], &b->hinfo[k], sizeof(BInfo));
     return st;
 }
 

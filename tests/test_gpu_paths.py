@@ -8,8 +8,9 @@
 * The 2048 x 512 spherical recipe at full size, one step, against the
   oracle's direct solve.
 * Theta slabs of the 4096 x 2048 stress recipe at full resolution (the share
-  of one GPU in a slab decomposition): 4096 x 256 for one step, and 4096 x 96
-  for ten graph-replayed steps against ten oracle steps.
+  of one GPU in a slab decomposition), both about the equator: 4096 x 256 for
+  one step (two sequential V-cycles, the benchmark's cycle), and 4096 x 128
+  for ten graph-replayed steps (K-cycle) against ten oracle steps.
 * The full 4096 x 2048 stress recipe, one step in the benchmark's schedule:
   the assembled operator elementwise against the oracle's assembly, the GPU
   solution's residual in the oracle's own system, and T^{n+1} against the
@@ -22,10 +23,11 @@ Tolerances: relative L2 error of E and T <= 1e-10 where binary64 allows it.
 The stress recipe's full-resolution rows (optically thin shells whose face
 conductances exceed the cell masses by up to 1e11) put the binary64 floor of
 the Jacobi-scaled residual near 3e-11 even for the oracle's refined solution:
-there the GPU stops at 3e-11 (slabs; errors ~5e-11) or at the benchmark's
-1e-10 (the 4096 x 64 strip, whose two polar rows of 1/64 of pi are the worst
-conditioned: two solutions at that floor, the GPU's and the oracle's, differ
-by ~4e-10, so its bound is 1e-9, as for ten compounded steps)."""
+there the GPU stops at 3e-11 (the 256-row slab; errors ~5e-11), at 2e-10
+(the 128-row slab, whose floor lies near 1e-10: ten compounded steps, bound
+1e-9) or at the benchmark's 1e-10 (the 4096 x 64 strip, whose two polar rows
+of 1/64 of pi are the worst conditioned: two solutions at that floor, the
+GPU's and the oracle's, differ by ~4e-10, so its bound is 1e-9)."""
 import numpy as np
 import pytest
 
@@ -104,7 +106,7 @@ def test_c5_slab_one_step(lib, c5_full, prec):
 
 @pytest.fixture(scope="module")
 def c5_slab_ten_steps(c5_full):
-    prob = W.theta_slab(c5_full, 0, 96)
+    prob = W.theta_slab(c5_full, 960, 1088)
     print(f"[c5 slab x10] oracle {prob.nx}x{prob.ny}", flush=True)
     E, T = prob.E, prob.T
     for _ in range(10):
@@ -117,14 +119,15 @@ def c5_slab_ten_steps(c5_full):
 def test_c5_slab_ten_graph_steps(lib, c5_slab_ten_steps, prec):
     prob, Eref, Tref = c5_slab_ten_steps
     print(f"[c5 slab x10] {prec}", flush=True)
-    ctx = make_ctx(lib, prob, precision=prec, mg_cycle=2, rel_tol=1e-10, norm=1)
+    ctx = make_ctx(lib, prob, precision=prec, mg_cycle=1, rel_tol=2e-10, norm=1)
     t = to_dev(prob, torch)
     infos = ctx.steps(10, t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"],
                       check=False)
     torch.cuda.synchronize()
     E, T = t["E"].cpu().numpy(), t["T"].cpu().numpy()
     ctx.close()
-    print([i["inner_iters"] for i in infos], rel_l2(E, Eref), rel_l2(T, Tref), flush=True)
+    print([(i["status"], i["inner_iters"], i["rel_resid"]) for i in infos], rel_l2(E, Eref), rel_l2(T, Tref),
+          flush=True)
     assert all(i["status"] == 0 for i in infos)
     assert rel_l2(E, Eref) < 1e-9 and rel_l2(T, Tref) < 1e-9  # ten steps at the binary64 floor
 

@@ -432,11 +432,36 @@ fld_status fld_batch_get_threads(const fld_batch* b, int32_t* threads);
 fld_status fld_batch_sizes(const fld_batch* b, int64_t* cells, int64_t* ghosts);
 
 /* Reason of the last error of b; with b = NULL, of the last failed
- * fld_batch_create on the calling thread. */
+ * fld_batch_create or fld_block_step_noalloc on the calling thread. */
 const char* fld_batch_last_error(const fld_batch* b);
 
 /* Releases the batch and its device memory.  NULL is accepted. */
 void fld_batch_destroy(fld_batch* b);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one block
+ * stepped exactly as one block of fld_batch_step with the same sides,
+ * spacing, boundaries and options (same kernel, same result bit for bit), but
+ * with no handle and no allocation.  Every byte of device workspace (block
+ * table, metrics, FP64 operator, hierarchy, CG vectors, the record) lives in
+ * a static array of 4 MiB per device, which each GPU the library runs on
+ * holds until the process ends; it is set up on the first call on a device
+ * (the caller's current device).  Only kernels are queued on `stream`
+ * (hipStream_t, NULL = default), so the call can be captured into a graph;
+ * with info == NULL it is asynchronous, otherwise it synchronises the stream
+ * and returns the block's status.  Workspace need (bytes, each piece rounded
+ * up to 256): about 6 n x 8 + 3 n x s + 5 x (4/3) n x s + 88 (nx + ny) with
+ * n = nx ny and s = 4 (FP32, MIXED) or 8 (FP64): e.g. blocks up to 128 x 128
+ * in every precision, 180 x 180 in FP64.  A block that does not fit is
+ * rejected with FLD_EINVAL (the reason, as every other argument error, is
+ * given by fld_batch_last_error(NULL) on the calling thread).  All calls on
+ * one GPU share its array and the array keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other threads) race, so they
+ * must be serialised by the caller.  Fields as for a one-block batch. */
+fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, const fld_bc* bc,
+                                  const fld_options* opt, double* E_r, double* T_g, const double* rho,
+                                  const double* kappa_R, const double* kappa_P, const double* c_v,
+                                  const double* ghost_E, double dt, void* stream, fld_solve_info* info);
 
 /* ------------------------------------------------------------------------
  * Autotuning: the method leaves the preconditioner's schedule open, and its

@@ -106,6 +106,8 @@ _SIGS = {
     "fld_batch_sizes": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "fld_batch_last_error": (ctypes.c_char_p, [_P]),
     "fld_batch_destroy": (None, [_P]),
+    "fld_block_step_noalloc": (_I, [_I, _I, _D, _D, ctypes.POINTER(fld_bc), ctypes.POINTER(fld_options), _P, _P, _P,
+                                    _P, _P, _P, _P, _D, _P, ctypes.POINTER(fld_solve_info)]),
     "fld_tune": (_I, [ctypes.POINTER(fld_grid), ctypes.POINTER(fld_options), _P, _P, _P, _P, _P, _P, _P, _D, _I,
                       ctypes.POINTER(fld_options), ctypes.POINTER(fld_tune_entry), _I, ctypes.POINTER(_I), _P]),
     "fld_batch_tune": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -361,3 +363,25 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def block_step_noalloc(nx: int, ny: int, dx: float, dy: float, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None,
+                       bcs: Optional[Sequence] = None, options=None, stream=None, check=True) -> dict:
+    """One block stepped as one block of a batch, with the library's static
+    per-device workspace (fld_block_step_noalloc: no device allocation)."""
+    bc_arr = None
+    if bcs is not None:
+        bc_arr = (fld_bc * 4)()
+        for s, b in enumerate(bcs):
+            kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
+            bc_arr[s].kind, bc_arr[s].value = int(kind), float(value)
+    opt = options if options is not None else default_options()
+    info = fld_solve_info()
+    st = lib.fld_block_step_noalloc(int(nx), int(ny), float(dx), float(dy), bc_arr, ctypes.byref(opt), _ptr(E),
+                                    _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P), _ptr(c_v), _ptr(ghost_E),
+                                    float(dt), _stream_handle(stream), ctypes.byref(info))
+    if check and st != FLD_OK:
+        raise FLDError(st, lib.fld_batch_last_error(None).decode())
+    out = info.as_dict()
+    out["call_status"] = st
+    return out

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -443,6 +444,154 @@ void fld_batch_destroy(fld_batch* b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// fld_block_step_noalloc: one block stepped by the batch kernel with every
+// byte of its device workspace in a static per-device array.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(4) << 20;  // 4 MiB per device
+constexpr int kMaxDevices = 64;
+
+// The workspace.  In host code this name is only a stand-in for the symbol:
+// kernels and copies use the address from hipGetSymbolAddress (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+double g_clock_khz[kMaxDevices] = {};
+
+constexpr size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Device address of this device's scratch array, the batch kernel's LDS
+// attribute and the wall-clock rate, set up once per device (the caller's
+// current device); null on failure.
+void* scratch_for_current_device(double* clock_khz) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        if (set_lds<float, 512>() != hipSuccess || set_lds<double, 512>() != hipSuccess) return nullptr;
+        int khz = 0;
+        g_clock_khz[dev] =
+            (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) ? khz : 1e5;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *clock_khz = g_clock_khz[dev];
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_put_block(BBlock blk, BBlock* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = blk;
+}
+
+__global__ void k_block_faces(double* xf, int nx, double dx, double* yf, int ny, double dy) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= nx) xf[t] = dx * (double)t;
+    if (t <= ny) yf[t] = dy * (double)t;
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, const fld_bc* bc,
+                                  const fld_options* opt, double* E, double* T, const double* rho, const double* kR,
+                                  const double* kP, const double* cv, const double* ghost, double dt, void* stream,
+                                  fld_solve_info* info) {
+    fld_options o;
+    if (opt) o = *opt;
+    else fld_default_options(&o);
+    BCDev bcd{};
+    bool need_ghost = false;
+    if (const char* why = batch_options(o, bc, bcd, need_ghost)) { t_create_err = why; return FLD_EINVAL; }
+    if (const char* why = block_shape(nx, ny, dx, dy)) { t_create_err = why; return FLD_EINVAL; }
+    if (!E || !T || !rho || !kR || !kP || !cv) { t_create_err = "null field pointer"; return FLD_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { t_create_err = "dt must be > 0"; return FLD_EINVAL; }
+    if (need_ghost && !ghost) { t_create_err = "ghost_E required"; return FLD_EINVAL; }
+    // the block's table entry and levels, and the scratch layout (256-byte pieces)
+    BBlock B;
+    std::memset(&B, 0, sizeof(BBlock));
+    B.nx = nx;
+    B.ny = ny;
+    long long lo = 0;
+    if (!block_levels(B, o.mg_coarse_max, lo)) { t_create_err = "too many multigrid levels"; return FLD_EINVAL; }
+    const size_t n = (size_t)nx * ny;
+    const size_t ts = o.precision != FLD_FP64 ? sizeof(float) : sizeof(double);
+    const size_t nm = (size_t)metric_doubles(nx, ny);
+    const size_t need = align256(sizeof(BBlock)) + align256(sizeof(BInfo)) + align256(nm * sizeof(double)) +
+                        6 * align256(n * sizeof(double)) + 5 * align256((size_t)lo * ts) + 3 * align256(n * ts);
+    if (need > kScratchBytes) {
+        t_create_err = "block needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                       std::to_string(kScratchBytes);
+        return FLD_EINVAL;
+    }
+    double clock_khz = 1e5;
+    unsigned char* base = static_cast<unsigned char*>(scratch_for_current_device(&clock_khz));
+    if (!base) { t_create_err = "static workspace: hipGetSymbolAddress or kernel attribute failed"; return FLD_EHIP; }
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + at;
+        at += align256(bytes);
+        return p;
+    };
+    BBlock* db = reinterpret_cast<BBlock*>(take(sizeof(BBlock)));
+    BInfo* dinfo = reinterpret_cast<BInfo*>(take(sizeof(BInfo)));
+    double *xf, *yf;
+    B.met = carve_metrics(reinterpret_cast<double*>(take(nm * sizeof(double))), nx, ny, &xf, &yf);
+    double* w64[6];
+    for (auto& q : w64) q = reinterpret_cast<double*>(take(n * sizeof(double)));
+    void* lv[5];
+    for (auto& q : lv) q = take((size_t)lo * ts);
+    void* vec[3];
+    for (auto& q : vec) q = take(n * ts);
+    // set-up kernels: table entry, faces at i dx and j dy, metrics (no copies from the host)
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Metrics& g = B.met;
+    const int mt = std::max(nx, ny) + 1;
+    k_put_block<<<1, 1, 0, st>>>(B, db);
+    k_block_faces<<<(mt + 255) / 256, 256, 0, st>>>(xf, nx, dx, yf, ny, dy);
+    k_metrics<<<(mt + 255) / 256, 256, 0, st>>>(0, nx, ny, xf, yf, const_cast<double*>(g.vx), const_cast<double*>(g.vy),
+                                                const_cast<double*>(g.sx), const_cast<double*>(g.sy),
+                                                const_cast<double*>(g.ax), const_cast<double*>(g.hxL),
+                                                const_cast<double*>(g.hxR), const_cast<double*>(g.hyL),
+                                                const_cast<double*>(g.hyR), const_cast<double*>(g.arc));
+    const BFields f{E, T, rho, kR, kP, cv, ghost, dt, o.limiter, bcd};
+    const BOpts bo = make_opts(o, clock_khz);
+    if (ts == sizeof(float)) {
+        BWork<float> w{w64[0], w64[1], w64[2], w64[3], w64[4], w64[5],
+                       static_cast<float*>(lv[0]), static_cast<float*>(lv[1]), static_cast<float*>(lv[2]),
+                       static_cast<float*>(lv[3]), static_cast<float*>(lv[4]),
+                       static_cast<float*>(vec[0]), static_cast<float*>(vec[1]), static_cast<float*>(vec[2])};
+        k_batch_step<float, 512><<<1, 512, BLds<float, 512>::bytes, st>>>(db, f, w, bo, dinfo);
+    } else {
+        BWork<double> w{w64[0], w64[1], w64[2], w64[3], w64[4], w64[5],
+                        static_cast<double*>(lv[0]), static_cast<double*>(lv[1]), static_cast<double*>(lv[2]),
+                        static_cast<double*>(lv[3]), static_cast<double*>(lv[4]),
+                        static_cast<double*>(vec[0]), static_cast<double*>(vec[1]), static_cast<double*>(vec[2])};
+        k_batch_step<double, 512><<<1, 512, BLds<double, 512>::bytes, st>>>(db, f, w, bo, dinfo);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        t_create_err = std::string("block kernel: ") + hipGetErrorString(e);
+        return FLD_EHIP;
+    }
+    if (!info) return FLD_OK;
+    BInfo h{};
+    if (hipMemcpyAsync(&h, dinfo, sizeof(BInfo), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        t_create_err = "block record";
+        return FLD_EHIP;
+    }
+    std::memcpy(info, &h, sizeof(BInfo));
+    return (fld_status)h.status;
 }
 
 }  // extern "C"

@@ -100,3 +100,22 @@ def test_ctypes_structures_match_c_layout():
           B.fld_options.inner_rtol.offset, B.fld_solve_info.rel_resid.offset, B.fld_options.use_graph.offset,
           B.fld_solve_info.ms.offset, B.fld_options.mg_cycle.offset]
     assert c == py
+
+
+@needs_lib
+def test_noalloc_block_step_rejects_before_touching_the_device():
+    """fld_block_step_noalloc checks sizes and arguments on the host first:
+    a bad side, and a block whose workspace exceeds the static 4 MiB, are
+    refused with EINVAL and a reason, without any GPU call."""
+    import paper_2602_12545_amd._binding as B  # noqa: F401  (ctypes signatures)
+    lib = B.lib
+    opt = B.default_options(precision=B.FLD_FP64)
+    dummy = ctypes.c_void_p(16)
+    args = lambda nx, ny: (nx, ny, 1e10, 1e10, None, ctypes.byref(opt), dummy, dummy, dummy, dummy, dummy, dummy,
+                           dummy, 1e4, None, None)
+    assert lib.fld_block_step_noalloc(*args(0, 8)) == B.FLD_EINVAL
+    assert b"block sides" in lib.fld_batch_last_error(None)
+    assert lib.fld_block_step_noalloc(*args(512, 512)) == B.FLD_EINVAL
+    assert b"bytes of workspace" in lib.fld_batch_last_error(None)
+    opt.precision = B.FLD_MIXED
+    assert lib.fld_block_step_noalloc(*args(256, 256)) == B.FLD_EINVAL

@@ -1,23 +1,29 @@
 """Benchmark of the implicit FLD radiation step on one MI355X.
 
-Headline workload: the 1024 x 1024 Cartesian grid stretched by 1.002 per cell
-with seeded lognormal density / temperature and clipped Kramers opacity, a
-Dirichlet (Marshak) x_lo side, dt = 1e4 s.  One timed step = one full
-backward-Euler radiation step (assembly, multigrid-preconditioned CG with FP32
-inner iterations and FP64 reliable updates to a 1e-10 relative residual in
-the per-volume norm, gas update), inputs resident in HBM, (E, T) restored from
-the same initial state before each step.  The solver schedule is chosen first
-by the autotuner (untimed).  The last timed step runs with HIP events around
-every multigrid line-sweep launch (the dominant kernel family); the others run
-as captured hipGraph chunks.  Prints one JSON line.
+Headline workload: the 4096 x 2048 spherical-polar stress recipe (r log-spaced
+1e11 .. 1e14 cm, theta 0 .. pi; lognormal opacity with sigma_ln 4, contrast
+1e8; c_v = 1e6, dt = 1e5 s), run as consecutive implicit steps through
+fld_steps (one step captured as a hipGraph and replayed, T updated from the
+linearised exchange every step, opacities fixed).  One benchmark step = one
+implicit radiation step of that sequence (assembly, multigrid-preconditioned
+CG with FP32 inner iterations and FP64 reliable updates to a 1e-10 relative
+residual in the Jacobi-scaled norm, gas update), inputs resident in HBM.
+The W warm-up steps run as one fld_steps call from the initial state; the K
+timed steps as one fld_steps call from the initial state again.  The whole
+100-step sequence is then run as one fld_steps call per precision (mixed and
+FP64, each on the faster of its two multigrid cycles, K and W2, chosen by a
+three-step probe), which gives time-to-1e-10 per step and the mixed/FP64
+ratio.  Prints one JSON line.
 
-Fields beyond the contract: the FP64 solver on the same workload (mixed vs
-FP64 speedup), CG iterations and Mcell-iterations/s, the roofline of the
-line-sweep kernels from the event timings, and (unless --no-extra) the
-batched-block workload (256 blocks, one launch per step; FP64 batched and
-FP64 one-context-per-block baselines) and the 4096 x 2048 spherical stress
-workload run as multi-step graphs.  cpu_baseline times the CPU oracle on a
-bounded sample of the headline recipe.
+Beyond the contract's fields: the dominant kernel's roofline (the finest
+level's zebra line half-sweeps, replayed between HIP events), the other
+workloads (64 x 64 FP64 solves/s; 1024 x 1024 stretched Cartesian and
+2048 x 512 spherical steps, mixed, FP64 and FP32-only; 256 batched blocks),
+the relative L2 error of E and T against the CPU oracle per workload (full
+size for the 64 x 64, 1024 x 1024 and 2048 x 512 grids and the 256 blocks, a
+full-resolution 4096 x 256 theta slab for the stress grid), the sub-cycled
+step and advection, and cpu_baseline: the oracle timed on the host on a
+bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -33,27 +39,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 METRIC = "FLD solves/s & Mcell-iter/s to 1e-10 resid; HBM GB/s %peak; mixed vs FP64"
 FIELDS = ("E", "T", "rho", "kappa_R", "kappa_P", "c_v")
+SEQUENCE = 100          # steps of the stress workload
+CYCLES = {"v": 0, "k": 1, "w2": 2}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--mg-cycle", default=None, choices=list(CYCLES),
+                    help="fix the multigrid cycle of the stress workload (default: the faster of K and W2 by a "
+                         "three-step probe, per precision)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 100-step run")
+    ap.add_argument("--no-sequence", action="store_true", help="skip the 100-step runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner's choice")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched-block and stress workloads")
-    ap.add_argument("--no-profile", action="store_true", help="no event-timed step (no roofline)")
-    ap.add_argument("--profile-all", action="store_true",
-                    help="event-time every timed step (plain launches; for comparison with a kernel trace)")
-    ap.add_argument("--mg-cycle", default=None, choices=["k", "v", "w2"],
-                    help="fix the multigrid cycle of the single-grid solves (default: the library default, "
-                         "and the tuner's choice where tuned; the batch always runs V-cycles)")
-    ap.add_argument("--norm", default="rows", choices=["rows", "scaled"],
-                    help="stop norm (the 4096x2048 spherical recipe needs 'scaled' for 1e-10)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the comparisons with the oracle")
+    ap.add_argument("--no-profile", action="store_true", help="no replay measurement (no roofline)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="run the stress steps as plain launches (use_graph = 0; for HBM counter passes, which do "
+                         "not survive the multi-step graphs under rocprofv3 --pmc)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale for HBM traffic counters)")
     return ap.parse_args()
@@ -65,6 +72,11 @@ def dev_fields(torch, prob):
     f["ghost_E"] = (torch.tensor(prob.ghost_E, dtype=torch.float64, device="cuda")
                     if prob.ghost_E is not None else None)
     return f
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def kernel_source_digest():
@@ -86,9 +98,9 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name="pmc_c2_line_sweeps.md"):
-    """HBM bytes per line-sweep launch from the committed counter summary, if
-    it was taken on the current kernel sources."""
+def measured_traffic(name):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None, "no counter summary"
@@ -106,89 +118,222 @@ def measured_traffic(name="pmc_c2_line_sweeps.md"):
         return None, "counter summary incomplete"
 
 
-MG_CYCLE = None  # --mg-cycle: 1 (K) or 0 (V) fixes the cycle
+def make_ctx(fld, prob, opt):
+    return fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
+                       [(b.kind, b.value) for b in prob.bc], opt)
 
 
-def defaults(fld, **kw):
-    o = fld.default_options(**kw)
-    if MG_CYCLE is not None:
-        o.mg_cycle = MG_CYCLE
-    return o
+NO_GRAPH = False
 
 
-def options(fld, prec, tuned, norm=0):
-    o = defaults(fld, precision=prec, norm=norm)
-    if tuned is not None:
-        for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph", "mg_cycle"):
-            setattr(o, k, getattr(tuned, k))
-    if MG_CYCLE is not None:
-        o.mg_cycle = MG_CYCLE
-    return o
+def stress_options(fld, prec, cycle):
+    return fld.default_options(precision=prec, norm=1, rel_tol=1e-10, mg_cycle=cycle,
+                               use_graph=0 if NO_GRAPH else 1)
 
 
-def run_steps(fld, torch, prob, base, opts, steps, warmup, profile, profile_all=False):
-    """Mean wall time of one step over `steps` timed steps, and the per-step
-    infos.  With `profile`, one more step after the timed ones runs with
-    event-timed line sweeps (plain launches, no graphs), and the sweep replay
-    is measured; with `profile_all` every timed step is event-timed instead
-    (for a profiler trace of plain launches)."""
-    ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                      [(b.kind, b.value) for b in prob.bc], opts)
-    E = base["E"].clone()
-    T = base["T"].clone()
-
-    def one():
-        E.copy_(base["E"])
-        T.copy_(base["T"])
-        return ctx.step(E, T, base["rho"], base["kappa_R"], base["kappa_P"], base["c_v"], prob.dt, base["ghost_E"])
-
-    for _ in range(warmup):
-        one()
+def run_sequence(fld, torch, prob, f, opt, nsteps, ctx=None):
+    """nsteps consecutive steps from the initial state as one fld_steps call:
+    wall time per step (host clock around the call, stream synchronised) and
+    the per-step records."""
+    own = ctx is None
+    ctx = ctx or make_ctx(fld, prob, opt)
+    E, T = f["E"].clone(), f["T"].clone()
     torch.cuda.synchronize()
-    infos = []
     t0 = time.perf_counter()
-    if profile and profile_all:
-        ctx.profile(True)
-    for s in range(steps):
-        infos.append(one())
+    infos = ctx.steps(nsteps, E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, f["ghost_E"],
+                      check=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = None
-    if profile:
-        if not profile_all:
-            ctx.profile(True)
-            one()
-            torch.cuda.synchronize()
-        prof = ctx.profile_read()
-        prof["overhead_us"] = ctx.profile_overhead(200)
-        ctx.profile(False)
-        # the same launches replayed as a graph between two events (no
-        # per-launch event cost): the duration the roofline uses
-        try:
-            prof["replay"] = ctx.profile_sweeps(50)
-        except fld.FLDError:
-            prof["replay"] = None
-    ctx.close()
-    return dt / steps, infos, prof
+    if own:
+        ctx.close()
+    return dt / nsteps, infos, (E, T)
 
 
-def cpu_baseline(W, n=1024):
-    """The CPU oracle (assembly + sparse LU + gas update), single-threaded, one
-    step of the headline recipe at n x n cells (the full grid by default; a
-    smaller n is scaled by cell count, which flatters the CPU since the direct
-    solve grows faster than linearly)."""
+def summarise(prob, ms, infos):
+    import numpy as np
+    its = [i["inner_iters"] for i in infos]
+    return {"ms_per_step": ms, "solves_per_s": 1e3 / ms, "iters_mean": float(np.mean(its)), "iters_max": max(its),
+            "iters_min": min(its), "status": sorted(set(i["status"] for i in infos)),
+            "max_rel_resid": max(i["rel_resid"] for i in infos),
+            "mcell_iter_per_s": prob.nx * prob.ny * float(np.mean(its)) / (ms * 1e-3) / 1e6}
+
+
+def pick_cycle(fld, torch, prob, f, prec, fixed):
+    """The faster of the K-cycle and two sequential V-cycles on three steps
+    of the stress sequence (after one warm-up step), unless fixed."""
+    if fixed is not None:
+        return CYCLES[fixed], None
+    probe = {}
+    for name in ("w2", "k"):
+        ctx = make_ctx(fld, prob, stress_options(fld, prec, CYCLES[name]))
+        run_sequence(fld, torch, prob, f, None, 1, ctx)
+        ms, infos, _ = run_sequence(fld, torch, prob, f, None, 3, ctx)
+        ctx.close()
+        ok = all(i["status"] == 0 for i in infos)
+        probe[name] = {"ms_per_step": 1e3 * ms, "ok": ok}
+    good = [n for n in probe if probe[n]["ok"]] or list(probe)
+    best = min(good, key=lambda n: probe[n]["ms_per_step"])
+    return CYCLES[best], probe
+
+
+def roofline(ctx, reps=50):
+    """Finest-level zebra line half-sweeps of the stress grid (the dominant
+    kernel): one V-cycle's fine-level launches captured on a solver state
+    that never converges and replayed between two HIP events on the solve
+    stream.  The time per launch includes the ~1 us gap between dependent
+    launches (a kernel trace of the same replay reports ~3 % less); the same
+    time minus that of an equal graph of empty launches, which also removes
+    the empty kernels' own execution, is reported as an upper bound."""
+    rep = ctx.profile_sweeps(reps, levels=1)
+    fam = ctx.profile_sweeps(reps, levels=0)
+    kern_us = rep["us_per_launch"]
+    achieved = rep["bytes_per_launch"] / (kern_us * 1e-6) / 1e9
+    traffic, tnote = measured_traffic("pmc_c5_fine_line_sweeps.md")
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tnote,
+           "kernel": "k_line on the finest level (4096x2048): the zebra line half-sweeps of both directions",
+           "avg_launch_us": kern_us, "bytes_per_launch": rep["bytes_per_launch"],
+           "duration_method": f"graph replay of one V-cycle's {rep['launches']} fine-level line-sweep launches x "
+                              f"{reps}, HIP events on the solve stream, per-launch time with the launch gaps",
+           "replay": rep,
+           "upper_bound_minus_empty_launches": rep["bytes_per_launch"] / (
+               max(rep["us_per_launch"] - rep["floor_us"], 1e-3) * 1e-6) / 1e9}
+    out["line_sweep_family"] = {"levels": "all grid levels", "replay": fam, "avg_launch_us": fam["us_per_launch"],
+                                "achieved": fam["bytes_per_launch"] / (fam["us_per_launch"] * 1e-6) / 1e9}
+    return out
+
+
+def cpu_baseline(W):
+    """The CPU oracle as it stands (FP64 assembly, SuperLU direct solve with
+    extended-precision refinement, gas update; single-threaded), one step of
+    a 4096 x 256 theta slab of the stress grid at full resolution (1/8 of the
+    cells), its rate scaled by the cell count to the whole grid."""
     from threadpoolctl import threadpool_limits
     from oracle import fld_oracle as O
-    prob = W.make_c2(nx=n, ny=n)
+    prob = W.theta_slab(W.make_c5(), 896, 1152)
     with threadpool_limits(limits=1):
         O.step_problem(W.make_c2(nx=64, ny=64))  # warm-up (imports, allocator)
         t0 = time.perf_counter()
         O.step_problem(prob)
         dt = time.perf_counter() - t0
-    full = 1024 * 1024
-    return {"value": (1.0 / dt) * (n * n) / full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"c2 recipe at {n}x{n} cells: one step = FP64 assembly + SuperLU direct solve + gas update, "
-                      f"{dt:.1f} s on one host core" + ("" if n == 1024 else "; rate scaled by cell count to 1024x1024")}
+    frac = prob.nx * prob.ny / (4096 * 2048)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": frac / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle step of the stress recipe's 4096x256 equatorial theta slab (1/8 of the cells), "
+                      f"{dt:.1f} s on one core; rate scaled by cell count to the 4096x2048 grid (flatters the CPU: "
+                      f"the direct solve grows faster than linearly)",
+            "host_cores": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def single_step_line(fld, torch, prob, opt, reps):
+    """Mean wall time of one step restored from the same initial state."""
+    f = dev_fields(torch, prob)
+    ctx = make_ctx(fld, prob, opt)
+    E, T = f["E"].clone(), f["T"].clone()
+
+    def one():
+        E.copy_(f["E"])
+        T.copy_(f["T"])
+        return ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, f["ghost_E"], check=False)
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [one() for _ in range(reps)]
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    ctx.close()
+    return ms, infos, (E.cpu().numpy(), T.cpu().numpy())
+
+
+def other_workloads(fld, torch, W, tuner, accuracy):
+    """64 x 64 FP64 solves/s; the 1024 x 1024 and 2048 x 512 grids in mixed,
+    FP64 and FP32-only precision (the 1024 x 1024 schedule autotuned); each
+    against the oracle when accuracy is set."""
+    from oracle import fld_oracle as O
+    out = {}
+    jobs = [("c1", W.make_c1(), [("fp64", 0, 200)], None),
+            ("c2", W.make_c2(), [("mixed", 0, 10), ("fp64", 0, 5), ("fp32", 0, 5)], "tune"),
+            ("c3", W.make_c3(), [("mixed", 1, 10), ("fp64", 1, 5), ("fp32", 1, 5)], None)]
+    for name, prob, runs, tune in jobs:
+        f = dev_fields(torch, prob)
+        ref = O.step_problem(prob) if accuracy else None
+        geom = "stretched Cartesian" if prob.geom == 0 else "spherical-polar"
+        res = {"workload": f"{name}: {prob.nx}x{prob.ny} {geom}, one implicit step"}
+        tuned = None
+        if tune and tuner is not None:
+            tuned, _ = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
+                                       [(b.kind, b.value) for b in prob.bc], f, prob.dt,
+                                       base=fld.default_options(precision="mixed"), reps=1, cache="")
+        for prec, norm, reps in runs:
+            opt = fld.default_options(precision=prec, norm=norm, rel_tol=1e-10)
+            if tuned is not None:
+                for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "mg_cycle"):
+                    setattr(opt, k, getattr(tuned, k))
+            ms, infos, (E, T) = single_step_line(fld, torch, prob, opt, reps)
+            r = {"ms_per_step": ms, "solves_per_s": 1e3 / ms, "inner_iters": infos[-1]["inner_iters"],
+                 "rel_resid": infos[-1]["rel_resid"], "status": infos[-1]["status"],
+                 "norm": "per-volume rows" if norm == 0 else "Jacobi-scaled",
+                 "mcell_iter_per_s": prob.nx * prob.ny * infos[-1]["inner_iters"] / (ms * 1e-3) / 1e6}
+            if ref is not None:
+                r["rel_l2_E"] = rel_l2(E, ref.E)
+                r["rel_l2_T"] = rel_l2(T, ref.T)
+            res[prec] = r
+        if "mixed" in res and "fp64" in res:
+            res["mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+        if tuned is not None:
+            res["schedule"] = {k: getattr(tuned, k) for k in ("smoother", "mg_coarse_max", "chunk", "mg_cycle")}
+        out[name] = res
+    return out
+
+
+def stress_slab_accuracy(fld, torch, W, cycles):
+    """The headline schedule (scaled norm 1e-10, each precision's cycle) on a
+    full-resolution 4096 x 256 equatorial theta slab of the stress grid, one
+    step, against the oracle."""
+    from oracle import fld_oracle as O
+    prob = W.theta_slab(W.make_c5(), 896, 1152)
+    ref = O.step_problem(prob)
+    out = {"workload": "c5 theta slab rows 896..1151 (4096x256), one step"}
+    for prec, cyc in cycles.items():
+        ms, infos, (E, T) = single_step_line(fld, torch, prob, stress_options(fld, prec, cyc), 1)
+        out[prec] = {"rel_l2_E": rel_l2(E, ref.E), "rel_l2_T": rel_l2(T, ref.T), "status": infos[-1]["status"],
+                     "inner_iters": infos[-1]["inner_iters"], "rel_resid": infos[-1]["rel_resid"]}
+    return out
+
+
+def batch_accuracy(fld, torch, W):
+    """All 256 blocks of the batched recipe in the benchmark's configuration
+    (mixed, per-volume norm 1e-10), each against its own oracle step."""
+    import numpy as np
+    from oracle import fld_oracle as O
+    batch = W.make_c4()
+    blocks = batch.blocks
+    dev = {k: torch.tensor(batch.packed(k), dtype=torch.float64, device="cuda")
+           for k in ("E", "T", "rho", "kappa_R", "kappa_P", "c_v", "ghost_E")}
+    bt = fld.Batch([b.nx for b in blocks], [b.ny for b in blocks], [1e10] * len(blocks), [1e10] * len(blocks), None,
+                   fld.default_options(precision="mixed"))
+    infos = bt.step(dev["E"], dev["T"], dev["rho"], dev["kappa_R"], dev["kappa_P"], dev["c_v"], 1e4, dev["ghost_E"],
+                    check=False)
+    torch.cuda.synchronize()
+    bt.close()
+    E, T = dev["E"].cpu().numpy(), dev["T"].cpu().numpy()
+    eE, eT, o = [], [], 0
+    for b in blocks:
+        n = b.nx * b.ny
+        r = O.step_problem(b)
+        eE.append(rel_l2(E[o:o + n].reshape(b.ny, b.nx), r.E))
+        eT.append(rel_l2(T[o:o + n].reshape(b.ny, b.nx), r.T))
+        o += n
+    return {"blocks": len(blocks), "max_rel_l2_E": max(eE), "max_rel_l2_T": max(eT),
+            "median_rel_l2_E": float(np.median(eE)), "status": sorted(set(i["status"] for i in infos))}
 
 
 def batch_extra(fld, torch, W, tune):
@@ -256,49 +401,6 @@ def batch_extra(fld, torch, W, tune):
         c.close()
     out["fp64_per_block_launch_ms_per_step"] = ms_pb
     out["mixed_batched_vs_fp64_per_block"] = ms_pb / ms_m
-    return out
-
-
-def stress_extra(fld, torch, W, nsteps=5):
-    """4096 x 2048 spherical grid, opacity contrast 1e8, stiff coupling:
-    nsteps consecutive steps as one captured step graph (fld_steps), mixed
-    and FP64, scaled-norm stop at 1e-10 (the per-volume norm's binary64 floor
-    on this grid lies near 2e-9); with the library default cycle (K) and with
-    the two sequential V-cycles (W2), which this grid favours."""
-    import numpy as np
-    prob = W.make_c5()
-    f = dev_fields(torch, prob)
-    out = {"workload": "c5: 4096x2048 spherical-polar, kappa contrast 1e8, c_v=1e6, dt=1e5, "
-                       f"{nsteps} steps per fld_steps call", "norm": "scaled"}
-
-    def run(prec, cycle):
-        opt = defaults(fld, precision=prec, norm=1)
-        if cycle is not None:
-            opt.mg_cycle = cycle
-        ctx = fld.Context(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                          [(b.kind, b.value) for b in prob.bc], opt)
-        E, T = f["E"].clone(), f["T"].clone()
-        ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt)  # warm-up
-        E.copy_(f["E"])
-        T.copy_(f["T"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = ctx.steps(nsteps, E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, check=False)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / nsteps
-        ctx.close()
-        its = [i["inner_iters"] for i in infos]
-        return {"ms_per_step": ms, "iters": its, "status": sorted(set(i["status"] for i in infos)),
-                "max_rel_resid": max(i["rel_resid"] for i in infos),
-                "mcell_iter_per_s": prob.nx * prob.ny * float(np.mean(its)) / (ms * 1e-3) / 1e6}
-
-    for prec in ("mixed", "fp64"):
-        out[prec] = run(prec, None)
-    out["mixed_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
-    if MG_CYCLE is None:
-        w2 = {prec: run(prec, 2) for prec in ("mixed", "fp64")}
-        w2["mixed_vs_fp64"] = w2["fp64"]["ms_per_step"] / w2["mixed"]["ms_per_step"]
-        out["cycle_w2"] = w2
     return out
 
 
@@ -412,13 +514,36 @@ def copy_calibration(torch):
     print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
 
 
+def defaults(fld, **kw):
+    return fld.default_options(**kw)
+
+
+def options(fld, prec, tuned, norm=0):
+    o = defaults(fld, precision=prec, norm=norm)
+    if tuned is not None:
+        for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "use_graph", "mg_cycle"):
+            setattr(o, k, getattr(tuned, k))
+    return o
+
+
+def copy_calibration(torch):
+    n = 512 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
+
+
 def main():
-    global MG_CYCLE
+    global NO_GRAPH
     args = parse()
-    MG_CYCLE = None if args.mg_cycle is None else {"v": 0, "k": 1, "w2": 2}[args.mg_cycle]
+    NO_GRAPH = args.no_graph
     if args.gpus != 1:
-        print(json.dumps({"error": "only one GPU is supported: the solver has no multi-GPU path; "
-                                   "blocks and rows would shard as separate solves per GPU"}), flush=True)
+        print(json.dumps({"error": "one GPU only: this build has no multi-GPU path (the stress grid would shard "
+                                   "into theta slabs, the batched blocks by count; see the design notes)"}),
+              flush=True)
         sys.exit(2)
     import torch
     if args.copy_calibration:
@@ -428,86 +553,75 @@ def main():
     from paper_2602_12545_amd import tune as tuner
     import fld_workloads as W
 
-    prob = W.make(args.workload)
+    prob = W.make_c5()
     ncell = prob.nx * prob.ny
-    base = dev_fields(torch, prob)
-    norm = 1 if args.norm == "scaled" else 0
-    tuned, tune_table = None, None
-    if not args.no_tune:
-        tuned, tune_table = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                                            [(b.kind, b.value) for b in prob.bc], base, prob.dt,
-                                            base=defaults(fld, precision=args.precision, norm=norm), reps=1,
-                                            cache="")
-    opts = options(fld, args.precision, tuned, norm)
-    profile = not args.no_profile
-    ms, infos, prof = run_steps(fld, torch, prob, base, opts, args.steps, args.warmup, profile, args.profile_all)
-    iters = sum(i["inner_iters"] for i in infos) / len(infos)
-    geom = "stretched Cartesian" if prob.geom == 0 else "spherical-polar"
+    f = dev_fields(torch, prob)
+    prec = args.precision
+    cyc, probe = pick_cycle(fld, torch, prob, f, prec, args.mg_cycle)
+    ctx = make_ctx(fld, prob, stress_options(fld, prec, cyc))
+    if args.warmup > 0:
+        run_sequence(fld, torch, prob, f, None, args.warmup, ctx)
+    sec, infos, _ = run_sequence(fld, torch, prob, f, None, args.steps, ctx)
+    its = [i["inner_iters"] for i in infos]
+    cname = {0: "V", 1: "K", 2: "W2"}
     out = {
         "metric": METRIC,
-        "value": 1.0 / ms,
+        "value": 1.0 / sec,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms * 1e3,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "dtype": {"mixed": "f32+f64", "fp64": "f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {prob.nx}x{prob.ny} {geom}, one implicit FLD step to 1e-10",
-                   "cells": ncell, "precision": args.precision, "rel_tol": 1e-10,
-                   "norm": "per-volume rows" if norm == 0 else "Jacobi-scaled",
-                   "schedule": {k: getattr(opts, k) for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk",
-                                                                 "mg_cycle")},
-                   "tuned": tuned is not None},
-        "inner_iters": iters,
-        "mcell_iter_per_s": ncell * iters / ms / 1e6,
+        "config": {"workload": "c5: 4096x2048 spherical-polar stress recipe (lognormal kappa, contrast 1e8; "
+                               "c_v=1e6, dt=1e5 s), consecutive implicit FLD steps through fld_steps (one step "
+                               "captured as a hipGraph and replayed), part of its 100-step sequence; one "
+                               "benchmark step = one implicit step to 1e-10",
+                   "cells": ncell, "precision": prec, "rel_tol": 1e-10, "norm": "Jacobi-scaled",
+                   "mg_cycle": cname[cyc], "cycle_probe": probe,
+                   "timed": f"one fld_steps call of {args.steps} steps from the initial state, after "
+                            f"{args.warmup} warm-up steps"},
+        "inner_iters": sum(its) / len(its),
+        "iters": its,
+        "mcell_iter_per_s": ncell * (sum(its) / len(its)) / sec / 1e6,
         "final_rel_resid": max(i["rel_resid"] for i in infos),
         "status": sorted(set(i["status"] for i in infos)),
     }
-    if prof and prof["launches"]:
-        n = prof["launches"]
-        raw_us = 1e3 * prof["ms"] / n
-        # each event-timed launch carries the event pair's own cost (measured
-        # on an empty kernel in the same process); subtracting it
-        # under-estimates short kernels, so the roofline takes the graph replay
-        # of the same launches when it is available
-        ev_us = max(raw_us - prof["overhead_us"], 1e-3)
-        rep = prof.get("replay")
-        if rep and rep["launches"]:
-            # the replay's time per launch minus that of an equal graph of
-            # empty launches (the dependent-launch cost a kernel trace does not
-            # count as kernel time)
-            kern_us, bpl, method = max(rep["us_per_launch"] - rep["floor_us"], 1e-3), rep["bytes_per_launch"], (
-                f"graph replay of one V-cycle's {rep['launches']} line-sweep launches x 50 minus a replay of as "
-                "many empty launches, HIP events around the replays on the solve stream")
-        else:
-            kern_us, bpl, method = ev_us, prof["bytes"] / n, "HIP event pair per launch minus the pair's cost"
-        achieved = bpl / (kern_us * 1e-6) / 1e9
-        traffic, tnote = measured_traffic() if args.workload == "c2" else (None, "counters taken on c2 only")
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tnote,
-                           "kernel": "multigrid line sweeps (k_band, k_line; all grid levels)",
-                           "avg_launch_us": kern_us, "bytes_per_launch": bpl, "duration_method": method,
-                           "replay": rep,
-                           "event_timed": {"launches": n, "avg_launch_us_raw": raw_us,
-                                           "event_pair_overhead_us": prof["overhead_us"],
-                                           "avg_launch_us_corrected": ev_us,
-                                           "bytes_per_launch": prof["bytes"] / n}}
-    if not args.no_fp64 and args.precision != "fp64":
-        ms64, infos64, _ = run_steps(fld, torch, prob, base, options(fld, "fp64", tuned, norm), max(3, args.steps // 2),
-                                     1, False)
-        out["fp64_ms_per_step"] = ms64 * 1e3
-        out["fp64_inner_iters"] = sum(i["inner_iters"] for i in infos64) / len(infos64)
-        out["mixed_vs_fp64_speedup"] = ms64 / ms
+    if not args.no_profile:
+        out["roofline"] = roofline(ctx)
+    ctx.close()
+    cycles = {prec: cyc}
+    if not args.no_sequence:
+        seq = {"workload": f"the stress recipe's {SEQUENCE}-step sequence from its initial state, one fld_steps "
+                           "call per precision, each on the faster of the K-cycle and W2"}
+        ms, inf, _ = run_sequence(fld, torch, prob, f, stress_options(fld, prec, cyc), SEQUENCE)
+        seq[prec] = summarise(prob, 1e3 * ms, inf)
+        seq[prec]["mg_cycle"] = cname[cyc]
+        if not args.no_fp64 and prec != "fp64":
+            c64, probe64 = pick_cycle(fld, torch, prob, f, "fp64", args.mg_cycle)
+            cycles["fp64"] = c64
+            ms, inf, _ = run_sequence(fld, torch, prob, f, stress_options(fld, "fp64", c64), SEQUENCE)
+            seq["fp64"] = summarise(prob, 1e3 * ms, inf)
+            seq["fp64"]["mg_cycle"] = cname[c64]
+            seq["fp64"]["cycle_probe"] = probe64
+            seq["mixed_vs_fp64"] = seq["fp64"]["ms_per_step"] / seq[prec]["ms_per_step"]
+        out["sequence_100"] = seq
+    del f
+    torch.cuda.empty_cache()
+    if not args.no_accuracy:
+        out["accuracy_stress_slab"] = stress_slab_accuracy(fld, torch, W, cycles)
     if not args.no_extra:
-        out["batched_blocks"] = batch_extra(fld, torch, W, None if args.no_tune else tuner)
-        out["stress_multistep"] = stress_extra(fld, torch, W)
-        out["substep"] = substep_extra(fld, torch, W, tuned)
-        out["advection"] = advection_extra(fld, torch, W, tuned)
-    if not args.no_cpu and args.workload == "c2":
+        out["workloads"] = other_workloads(fld, torch, W, tuner, not args.no_accuracy)
+        out["batched_blocks"] = batch_extra(fld, torch, W, tuner)
+        if not args.no_accuracy:
+            out["batched_blocks"]["accuracy"] = batch_accuracy(fld, torch, W)
+        out["substep"] = substep_extra(fld, torch, W, None)
+        out["advection"] = advection_extra(fld, torch, W, None)
+    if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
 

@@ -226,7 +226,9 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
  * reads the records once per segment.  If a step used up the budget, the
  * budget grows by half (up to max_inner), the step is re-captured and the
  * segment replays from the (E, T) saved at its start, segments restarting at
- * one step.  Results equal those of nsteps fld_step calls
+ * one step; if the budget exceeds twice even(2 k + 16), k the most
+ * iterations a step of the last segment took, it is cut to that value and
+ * the step re-captured (unused slots cost their early-exit launches).  Results equal those of nsteps fld_step calls
  * whenever every step converges within max_inner.  A step that fails for
  * another reason (stagnation, breakdown) is recorded and, unlike fld_step,
  * its gas update and the following steps still run.  With profiling on or
@@ -366,6 +368,11 @@ fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launc
  * overwritten (the next solve starts afresh). */
 fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch, double* floor_us,
                               double* bytes_per_launch, int32_t* launches);
+/* The same replay limited to the line-sweep launches of the finest `levels`
+ * grid levels (levels = 1: the fine grid's half-sweeps alone; 0: every
+ * level, as fld_profile_sweeps). */
+fld_status fld_profile_sweeps_levels(fld_ctx* ctx, int32_t levels, int32_t reps, double* us_per_launch,
+                                     double* floor_us, double* bytes_per_launch, int32_t* launches);
 
 const char* fld_status_string(fld_status s);
 const char* fld_last_error(const fld_ctx* ctx);

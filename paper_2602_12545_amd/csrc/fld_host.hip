@@ -122,6 +122,7 @@ struct fld_ctx {
     // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
     // enqueue_vcycle queues only the line-sweep launches and counts them
     bool sweeps_only = false;
+    int sweep_levels = 0;       // replay only the finest sweep_levels grid levels (0: all)
     int sweep_launches = 0;
     double sweep_bytes = 0.0;
     Scalars* sc_sweep = nullptr;  // solver state of the replay (never done)
@@ -409,7 +410,10 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const int Ld = in.sub_first > 0 ? in.sub_first : L - 1;  // grid levels smoothed with launches
     const bool fused = c->opt.smoother == FLD_SMOOTH_LINE;
     std::vector<T*> xpre(Ld);  // pre-smoothed x of each level (secondary layout)
+    // the replay measurement can be limited to the finest levels
+    auto skip = [&](int l) { return c->sweeps_only && c->sweep_levels > 0 && l >= c->sweep_levels; };
     for (int l = 0; l < Ld; ++l) {
+        if (skip(l)) continue;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -443,6 +447,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                                                                  c->sc);
     }
     for (int l = Ld - 1; l >= 0; --l) {
+        if (skip(l)) continue;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -1002,7 +1007,13 @@ fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launc
 
 fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch, double* floor_us,
                               double* bytes_per_launch, int32_t* launches) {
-    if (!ctx || reps < 1 || !us_per_launch || !floor_us || !bytes_per_launch || !launches) return FLD_EINVAL;
+    return fld_profile_sweeps_levels(ctx, 0, reps, us_per_launch, floor_us, bytes_per_launch, launches);
+}
+
+fld_status fld_profile_sweeps_levels(fld_ctx* ctx, int32_t levels, int32_t reps, double* us_per_launch,
+                                     double* floor_us, double* bytes_per_launch, int32_t* launches) {
+    if (!ctx || reps < 1 || levels < 0 || !us_per_launch || !floor_us || !bytes_per_launch || !launches)
+        return FLD_EINVAL;
     if (!ctx->assembled) {
         ctx->err = "fld_profile_sweeps before fld_assemble";
         return FLD_ENOTREADY;
@@ -1020,6 +1031,7 @@ fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch,
     ctx->sc = ctx->sc_sweep;
     ctx->prof.on = false;
     ctx->sweeps_only = true;
+    ctx->sweep_levels = levels;
     ctx->sweep_launches = 0;
     ctx->sweep_bytes = 0.0;
     const int nrz_keep = ctx->nrz;
@@ -1033,6 +1045,7 @@ fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch,
     ctx->sc = keep;
     ctx->prof.on = prof_on;
     ctx->sweeps_only = false;
+    ctx->sweep_levels = 0;
     ctx->nrz = nrz_keep;
     if (e != hipSuccess) {
         ctx->err = std::string("sweep capture: ") + hipGetErrorString(e);
@@ -1387,6 +1400,17 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         }
         k += m;
         seg = std::min(kStepSeg, 2 * seg);
+        // a relaxing sequence needs fewer iterations as it goes (the stress
+        // recipe: 110 in step 1, 3 by step 100); every unused slot still costs
+        // its early-exit launches, so a budget more than twice what the last
+        // segment needed is cut down to that need's margin and re-captured
+        int need = 0;
+        for (int q = 0; q < m; ++q) need = std::max(need, h[c0 + q].inner_iters);
+        const int want = std::min(ctx->opt.max_inner, ((need * 2 + 16) + 1) & ~1);
+        if (k < nsteps && 2 * want <= slots) {
+            slots = want;
+            st = capture(slots);
+        }
     }
     const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     cleanup();

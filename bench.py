@@ -514,6 +514,57 @@ def copy_calibration(torch):
     print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
 
 
+def forest_extra(fld, torch, accuracy, nx0=256, ny0=256):
+    """A statically refined forest solved as one matrix (fld_forest_step):
+    a 256 x 256 level-0 domain (1e10 cm cells), a level-1 patch over its
+    middle half and a level-2 patch over the middle half of that; fields as
+    the 1024 x 1024 recipe's (lognormal rho and T, clipped Kramers opacity),
+    a Dirichlet x_lo side, dt = 1e4 s; FP64, per-volume stop at 1e-10."""
+    import numpy as np
+    from oracle import fld_oracle as O
+    a, b, c, d = nx0 // 4, 3 * nx0 // 4, ny0 // 4, 3 * ny0 // 4
+    A, B, C, D = 2 * a, 2 * b, 2 * c, 2 * d
+    qa, qb, qc, qd = A + (B - A) // 4, A + 3 * (B - A) // 4, C + (D - C) // 4, C + 3 * (D - C) // 4
+    blocks = [(0, 0, 0, nx0, c), (0, 0, d, nx0, ny0 - d), (0, 0, c, a, d - c), (0, b, c, nx0 - b, d - c),
+              (1, A, C, B - A, qc - C), (1, A, qd, B - A, D - qd), (1, A, qc, qa - A, qd - qc),
+              (1, qb, qc, B - qb, qd - qc), (2, 2 * qa, 2 * qc, 2 * (qb - qa), 2 * (qd - qc))]
+    bcs = [(1, 2e4), (0, 0.0), (0, 0.0), (0, 0.0)]
+    fo = fld.Forest(blocks, nx0, ny0, 1e10, 1e10, bcs, fld.default_options(precision="fp64", max_inner=20000))
+    rng = np.random.default_rng(21)
+    n = fo.cells
+    rho = 1e-9 * np.exp(2.0 * rng.normal(size=n) * 0.5)
+    T = 5e3 * np.exp(0.5 * rng.normal(size=n))
+    kap = np.clip(1e22 * rho * T ** -3.5, 1e-4, 1e4)
+    f = {"E": O.A_RAD * T ** 4, "T": T, "rho": rho, "kappa_R": kap, "kappa_P": kap.copy(), "c_v": np.full(n, 1e8)}
+    t = {k: torch.tensor(v, dtype=torch.float64, device="cuda") for k, v in f.items()}
+    E, Tg = t["E"].clone(), t["T"].clone()
+    fo.step(E, Tg, t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], 1e4, check=False)  # warm-up
+    ms = []
+    for _ in range(3):
+        E.copy_(t["E"])
+        Tg.copy_(t["T"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fo.step(E, Tg, t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], 1e4, check=False)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    xc, yc, lv = fo.centres()
+    fo.close()
+    out = {"workload": f"block forest: {nx0}x{ny0} level-0 domain with nested level-1 and level-2 patches, "
+                       f"{n} leaf cells, one matrix across levels; FP64 Jacobi-preconditioned CG",
+           "cells": n, "ms_per_step": min(ms), "solves_per_s": 1e3 / min(ms), "inner_iters": info["inner_iters"],
+           "rel_resid": info["rel_resid"], "status": info["status"],
+           "mcell_iter_per_s": n * info["inner_iters"] / (min(ms) * 1e-3) / 1e6}
+    if accuracy:
+        from oracle import fld_forest as FF
+        F = FF.build([FF.Block(*bk) for bk in blocks], 1e10, 1e10, nx0, ny0)
+        ref = FF.step(F, f["E"], f["T"], f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], 1e4,
+                      [O.BCSpec(k, v) for k, v in bcs])
+        out["rel_l2_E"] = rel_l2(E.cpu().numpy(), ref.E)
+        out["rel_l2_T"] = rel_l2(Tg.cpu().numpy(), ref.T)
+    return out
+
+
 def defaults(fld, **kw):
     return fld.default_options(**kw)
 
@@ -619,6 +670,7 @@ def main():
         out["batched_blocks"] = batch_extra(fld, torch, W, tuner)
         if not args.no_accuracy:
             out["batched_blocks"]["accuracy"] = batch_accuracy(fld, torch, W)
+        out["forest"] = forest_extra(fld, torch, not args.no_accuracy)
         out["substep"] = substep_extra(fld, torch, W, None)
         out["advection"] = advection_extra(fld, torch, W, None)
     if not args.no_cpu:

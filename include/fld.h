@@ -471,6 +471,64 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
                                   const double* ghost_E, double dt, void* stream, fld_solve_info* info);
 
 /* ------------------------------------------------------------------------
+ * Block forest (Section 3.2.2, multilevel implicit radiation transport in a
+ * single matrix; Section 4, radiation communications): a 2D Cartesian domain
+ * of nx0 x ny0 level-0 cells (spacing dx0, dy0; faces at i dx0, j dy0) covered
+ * exactly by leaf blocks of any level L (spacing dx0 / 2^L, dy0 / 2^L).
+ * Neighbouring leaf cells may differ by one level at most (2:1 balance).  One
+ * step assembles and solves one linear system over every leaf cell of every
+ * level: a face between two leaf cells carries one conductance, used by both
+ * rows, so a coarse cell beside a finer block couples directly to the two
+ * fine cells of that side, each through the fine face's own D, and the flux
+ * through the coarse side equals the sum of the two fine faces' fluxes.  A
+ * level-jump face is the uniform grid's face (sigma and E interpolated
+ * linearly along the normal between the two centres, R from their
+ * difference, D = c lambda(R) / sigma_f) with the fine face's area and the
+ * normal distance dx_fine/2 + dx_coarse/2 of the centres (the coarse centre's
+ * lateral offset is neglected).  Cells: the single grid's T elimination and
+ * gas update.  Solver: Jacobi-preconditioned CG in FP64 over ELL neighbour
+ * lists (up to eight neighbours per cell), true-residual restarts.
+ * ------------------------------------------------------------------------ */
+typedef struct fld_forest fld_forest;
+
+/* A leaf block: nx x ny cells of level `level` (0 .. 16) whose lower-left cell
+ * is (i0, j0) in that level's index space (0 <= i0, i0 + nx <= nx0 2^level). */
+typedef struct { int32_t level, i0, j0, nx, ny; } fld_forest_block;
+
+/* Creates a forest: checks that the blocks cover the domain exactly (no
+ * overlap, no leaf inside a coarser leaf, areas adding up) and are 2:1
+ * balanced, numbers the leaf cells block after block (each block row-major:
+ * the layout of every field array), and builds the face and neighbour tables
+ * on the device.  bc: the four domain sides (side order of fld_bc; NULL =
+ * reflecting): REFLECT, DIRICHLET_FACE, FLUX_IN or FREE_STREAM.  opt: FP64
+ * only (precision = FLD_FP64); limiter, norm, rel_tol and max_inner apply.
+ * Host arrays are read during the call.  Returns EINVAL with the reason in
+ * fld_forest_last_error(NULL), ENOMEM, EHIP. */
+fld_status fld_forest_create(fld_forest** out, int32_t nblocks, const fld_forest_block* blocks, int32_t nx0,
+                             int32_t ny0, double dx0, double dy0, const fld_bc* bc, const fld_options* opt,
+                             void* stream);
+
+/* Numbers of leaf cells, interior faces and domain-boundary faces. */
+fld_status fld_forest_sizes(const fld_forest* f, int64_t* cells, int64_t* faces, int64_t* boundary_faces);
+
+/* Cell centres (cm) and levels in cell order (host arrays of `cells`
+ * entries, any may be NULL). */
+fld_status fld_forest_cells(const fld_forest* f, double* xc, double* yc, int32_t* level);
+
+/* One implicit radiation step on every leaf cell (E_r, T_g updated in place;
+ * device arrays of `cells` doubles in cell order).  Synchronises the stream
+ * while solving.  info may be NULL.  Returns ENOCONV (E_r then holds the last
+ * iterate and T_g is unchanged), EBREAKDOWN, ENONFINITE. */
+fld_status fld_forest_step(fld_forest* f, double* E_r, double* T_g, const double* rho, const double* kappa_R,
+                           const double* kappa_P, const double* c_v, double dt, fld_solve_info* info);
+
+/* Reason of the last error of f; with f = NULL, of the last failed
+ * fld_forest_create on the calling thread. */
+const char* fld_forest_last_error(const fld_forest* f);
+
+void fld_forest_destroy(fld_forest* f);
+
+/* ------------------------------------------------------------------------
  * Autotuning: the method leaves the preconditioner's schedule open, and its
  * cost depends on the grid and the fields (launch latency on small levels,
  * line versus point smoothing under anisotropy, band fusion, multigrid depth).

@@ -53,6 +53,11 @@ class fld_solve_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fld_forest_block(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("i0", ctypes.c_int32), ("j0", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32)]
+
+
 class fld_tune_entry(ctypes.Structure):
     _fields_ = [("opt", fld_options), ("threads", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inner_iters", ctypes.c_int32), ("ms", ctypes.c_float)]
@@ -110,6 +115,14 @@ _SIGS = {
     "fld_batch_destroy": (None, [_P]),
     "fld_block_step_noalloc": (_I, [_I, _I, _D, _D, ctypes.POINTER(fld_bc), ctypes.POINTER(fld_options), _P, _P, _P,
                                     _P, _P, _P, _P, _D, _P, ctypes.POINTER(fld_solve_info)]),
+    "fld_forest_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(fld_forest_block), _I, _I, _D, _D,
+                               ctypes.POINTER(fld_bc), ctypes.POINTER(fld_options), _P]),
+    "fld_forest_sizes": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]),
+    "fld_forest_cells": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I)]),
+    "fld_forest_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(fld_solve_info)]),
+    "fld_forest_last_error": (ctypes.c_char_p, [_P]),
+    "fld_forest_destroy": (None, [_P]),
     "fld_tune": (_I, [ctypes.POINTER(fld_grid), ctypes.POINTER(fld_options), _P, _P, _P, _P, _P, _P, _P, _D, _I,
                       ctypes.POINTER(fld_options), ctypes.POINTER(fld_tune_entry), _I, ctypes.POINTER(_I), _P]),
     "fld_batch_tune": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -358,6 +371,63 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib.fld_batch_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Forest:
+    """A statically refined block forest solved as one matrix: wraps
+    fld_forest_create ... fld_forest_destroy.  blocks: (level, i0, j0, nx, ny)
+    tuples; fields are torch float64 GPU tensors of `cells` values in cell
+    order (block after block, each row-major)."""
+
+    def __init__(self, blocks, nx0: int, ny0: int, dx0: float, dy0: float, bcs: Optional[Sequence] = None,
+                 options=None, stream=None):
+        nb = len(blocks)
+        arr = (fld_forest_block * nb)(*[fld_forest_block(*[int(v) for v in b]) for b in blocks])
+        bc_arr = None
+        if bcs is not None:
+            bc_arr = (fld_bc * 4)()
+            for s, b in enumerate(bcs):
+                kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
+                bc_arr[s].kind, bc_arr[s].value = int(kind), float(value)
+        self.options = options if options is not None else default_options(precision="fp64")
+        h = _P()
+        st = lib.fld_forest_create(ctypes.byref(h), nb, arr, int(nx0), int(ny0), float(dx0), float(dy0), bc_arr,
+                                   ctypes.byref(self.options), _stream_handle(stream))
+        if st != FLD_OK:
+            raise FLDError(st, lib.fld_forest_last_error(None).decode())
+        self.handle = h
+        c, f, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        lib.fld_forest_sizes(h, ctypes.byref(c), ctypes.byref(f), ctypes.byref(b))
+        self.cells, self.faces, self.boundary_faces = c.value, f.value, b.value
+
+    def centres(self):
+        import numpy as np
+        x = (_D * self.cells)()
+        y = (_D * self.cells)()
+        lv = (_I * self.cells)()
+        lib.fld_forest_cells(self.handle, x, y, lv)
+        return np.ctypeslib.as_array(x).copy(), np.ctypeslib.as_array(y).copy(), np.ctypeslib.as_array(lv).copy()
+
+    def step(self, E, T, rho, kappa_R, kappa_P, c_v, dt, check=True) -> dict:
+        info = fld_solve_info()
+        st = lib.fld_forest_step(self.handle, _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R), _ptr(kappa_P),
+                                 _ptr(c_v), float(dt), ctypes.byref(info))
+        if check and st != FLD_OK:
+            raise FLDError(st, lib.fld_forest_last_error(self.handle).decode())
+        out = info.as_dict()
+        out["call_status"] = st
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.fld_forest_destroy(self.handle)
             self.handle = _P()
 
     def __del__(self):

@@ -119,3 +119,28 @@ def test_noalloc_block_step_rejects_before_touching_the_device():
     assert b"bytes of workspace" in lib.fld_batch_last_error(None)
     opt.precision = B.FLD_MIXED
     assert lib.fld_block_step_noalloc(*args(256, 256)) == B.FLD_EINVAL
+
+
+@needs_lib
+def test_forest_validation_runs_on_the_host():
+    """fld_forest_create refuses overlapping, unbalanced and non-covering
+    forests, and non-FP64 options, before touching the device."""
+    import paper_2602_12545_amd._binding as B
+    lib = B.lib
+    opt = B.default_options(precision=B.FLD_FP64)
+
+    def create(blocks, nx0=8, ny0=8, o=opt):
+        arr = (B.fld_forest_block * len(blocks))(*[B.fld_forest_block(*b) for b in blocks])
+        h = ctypes.c_void_p()
+        return lib.fld_forest_create(ctypes.byref(h), len(blocks), arr, nx0, ny0, 1e10, 1e10, None, ctypes.byref(o),
+                                     None)
+
+    assert create([(0, 0, 0, 4, 4), (0, 2, 2, 4, 4)]) == B.FLD_EINVAL
+    assert b"overlaps" in lib.fld_forest_last_error(None)
+    assert create([(0, 0, 0, 8, 4)]) == B.FLD_EINVAL
+    assert b"cover" in lib.fld_forest_last_error(None)
+    assert create([(0, 0, 0, 4, 8), (2, 16, 0, 16, 32)]) == B.FLD_EINVAL
+    assert b"balanced" in lib.fld_forest_last_error(None)
+    assert create([(0, 0, 0, 8, 8), (1, 0, 0, 2, 2)]) == B.FLD_EINVAL
+    mixed = B.default_options(precision=B.FLD_MIXED)
+    assert create([(0, 0, 0, 8, 8)], o=mixed) == B.FLD_EINVAL

@@ -226,9 +226,9 @@ fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, c
  * reads the records once per segment.  If a step used up the budget, the
  * budget grows by half (up to max_inner), the step is re-captured and the
  * segment replays from the (E, T) saved at its start, segments restarting at
- * one step; if the budget exceeds twice even(2 k + 16), k the most
- * iterations a step of the last segment took, it is cut to that value and
- * the step re-captured (unused slots cost their early-exit launches).  Results equal those of nsteps fld_step calls
+ * one step; if the budget exceeds 1.5 x even(k + max(4, k/4) + 2), k the
+ * most iterations a step of the last segment took, it is cut to that value
+ * and the step re-captured (unused slots cost their early-exit launches).  Results equal those of nsteps fld_step calls
  * whenever every step converges within max_inner.  A step that fails for
  * another reason (stagnation, breakdown) is recorded and, unlike fld_step,
  * its gas update and the following steps still run.  With profiling on or

@@ -95,6 +95,10 @@ struct fld_ctx {
     // hierarchy and joined by the first V-cycle that needs it
     hipStream_t setup_stream = nullptr;
     hipEvent_t setup_fork = nullptr, setup_join = nullptr;
+    // the same fork and join inside stream captures (fld_steps) use events of
+    // their own, so an event recorded into a graph is never recorded again
+    // outside one
+    hipEvent_t cap_fork = nullptr, cap_join = nullptr;
     bool setup_pending = false;
     std::string err;
     std::vector<void*> allocs;
@@ -1130,6 +1134,8 @@ void fld_destroy(fld_ctx* ctx) {
     if (ctx->setup_stream) (void)hipStreamDestroy(ctx->setup_stream);
     if (ctx->setup_fork) (void)hipEventDestroy(ctx->setup_fork);
     if (ctx->setup_join) (void)hipEventDestroy(ctx->setup_join);
+    if (ctx->cap_fork) (void)hipEventDestroy(ctx->cap_fork);
+    if (ctx->cap_join) (void)hipEventDestroy(ctx->cap_join);
     for (auto& e : ctx->prof.ev) (void)hipEventDestroy(e);
     if (ctx->prof.hran) (void)hipHostFree(ctx->prof.hran);
     delete ctx;
@@ -1239,7 +1245,9 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     *ctx->herr = 0;
     if (hipStreamCreateWithFlags(&ctx->setup_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->setup_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->setup_join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&ctx->setup_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cap_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cap_join, hipEventDisableTiming) != hipSuccess)
         return fail(FLD_EHIP, "set-up stream");
     fld_status s;
     if (inner_is_float(ctx)) s = alloc_inner<float>(ctx);
@@ -1347,10 +1355,15 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         }
         hipStream_t cs = ctx->cap_stream;
         hipGraph_t g = nullptr;
+        if (join_setup(ctx, ctx->stream) != FLD_OK) return FLD_EHIP;  // no set-up left pending on the plain events
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FLD_EHIP;
+        std::swap(ctx->setup_fork, ctx->cap_fork);
+        std::swap(ctx->setup_join, ctx->cap_join);
         fld_status as = enqueue_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt, cs);
         if (inner_is_float(ctx)) enqueue_solve_fixed<float>(ctx, E, budget, cs);
         else enqueue_solve_fixed<double>(ctx, E, budget, cs);
+        std::swap(ctx->setup_fork, ctx->cap_fork);
+        std::swap(ctx->setup_join, ctx->cap_join);
         k_gas_update<<<grid1d(n), 256, 0, cs>>>(n, E, T, rho, kP, ctx->cv, dt, T);
         k_record_step<<<1, 1, 0, cs>>>(ctx->sc, ctx->err_flag, dcount, kStepSeg, (void*)dinfo, (int)ctx->h64.size());
         hipError_t e = hipStreamEndCapture(cs, &g);
@@ -1401,13 +1414,15 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
         k += m;
         seg = std::min(kStepSeg, 2 * seg);
         // a relaxing sequence needs fewer iterations as it goes (the stress
-        // recipe: 110 in step 1, 3 by step 100); every unused slot still costs
-        // its early-exit launches, so a budget more than twice what the last
-        // segment needed is cut down to that need's margin and re-captured
+        // recipe: 110 in step 2, 3 by step 100); every unused slot still costs
+        // its early-exit launches (~45 launches, half of a late step's time),
+        // so a budget 1.5x above what the last segment needed plus a quarter
+        // (at least 4) is cut to that and re-captured; a step that overruns
+        // it replays its segment with a larger budget, as above
         int need = 0;
         for (int q = 0; q < m; ++q) need = std::max(need, h[c0 + q].inner_iters);
-        const int want = std::min(ctx->opt.max_inner, ((need * 2 + 16) + 1) & ~1);
-        if (k < nsteps && 2 * want <= slots) {
+        const int want = std::min(ctx->opt.max_inner, ((need + std::max(4, need / 4) + 2) + 1) & ~1);
+        if (k < nsteps && 3 * want <= 2 * slots) {
             slots = want;
             st = capture(slots);
         }

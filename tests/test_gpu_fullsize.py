@@ -38,3 +38,15 @@ def test_c2_full_size_benchmark_configuration(lib, c2_full):
     print("rows 1e-10", info["inner_iters"], info["rel_resid"], rel_l2(E, ref.E), rel_l2(T, ref.T), flush=True)
     assert info["status"] == 0 and info["rel_resid"] <= 1e-10
     assert rel_l2(E, ref.E) < 1e-8 and rel_l2(T, ref.T) < 1e-8
+
+
+def test_c2_full_size_accuracy_matched_stop(lib, c2_full):
+    """The benchmark's accuracy-matched stop on this grid (per-volume rows at
+    2e-11): E and T within 1e-10 of the oracle's direct solve."""
+    prob, ref = c2_full
+    for prec in ("mixed", "fp64"):
+        E, T, info = gpu_step(lib, torch, prob, precision=prec, norm=0, rel_tol=2e-11, **SCHEDULE)
+        print("rows 2e-11", prec, info["inner_iters"], info["rel_resid"], rel_l2(E, ref.E), rel_l2(T, ref.T),
+              flush=True)
+        assert info["status"] == 0
+        assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10

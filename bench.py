@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 METRIC = "FLD solves/s & Mcell-iter/s to 1e-10 resid; HBM GB/s %peak; mixed vs FP64"
 FIELDS = ("E", "T", "rho", "kappa_R", "kappa_P", "c_v")
 SEQUENCE = 100          # steps of the stress workload
-CYCLES = {"v": 0, "k": 1, "w2": 2}
+CYCLES = {"v": 0, "k": 1, "w2": 2, "kl_k": 3, "kl_w2": 4}
 
 
 def parse():
@@ -134,7 +134,7 @@ NO_GRAPH = False
 
 
 def stress_options(fld, prec, cycle):
-    return fld.default_options(precision=prec, norm=1, rel_tol=1e-10, mg_cycle=cycle,
+    return fld.default_options(precision=prec, norm=1, rel_tol=1e-10, mg_cycle=cycle, mg_coarse_max=256,
                                use_graph=0 if NO_GRAPH else 1)
 
 
@@ -166,12 +166,13 @@ def summarise(prob, ms, infos):
 
 
 def pick_cycle(fld, torch, prob, f, prec, fixed):
-    """The faster of the K-cycle and two sequential V-cycles on three steps
-    of the stress sequence (after one warm-up step), unless fixed."""
+    """The fastest of the K-cycle, two sequential V-cycles and their
+    Krylov-accelerated variants on three steps of the stress sequence (after
+    one warm-up step), unless fixed."""
     if fixed is not None:
         return CYCLES[fixed], None
     probe = {}
-    for name in ("w2", "k"):
+    for name in ("kl_w2", "kl_k", "w2", "k"):
         ctx = make_ctx(fld, prob, stress_options(fld, prec, CYCLES[name]))
         run_sequence(fld, torch, prob, f, None, 1, ctx)
         ms, infos, _ = run_sequence(fld, torch, prob, f, None, 3, ctx)
@@ -637,7 +638,7 @@ def main():
         run_sequence(fld, torch, prob, f, None, args.warmup, ctx)
     sec, infos, _ = run_sequence(fld, torch, prob, f, None, args.steps, ctx)
     its = [i["inner_iters"] for i in infos]
-    cname = {0: "V", 1: "K", 2: "W2"}
+    cname = {0: "V", 1: "K", 2: "W2", 3: "KL_K", 4: "KL_W2"}
     out = {
         "metric": METRIC,
         "value": 1.0 / sec,

@@ -140,8 +140,16 @@ typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT 
  * grid (4096 x 64 .. 128 rows about the equator) it is not, and CG then
  * stops with FLD_EBREAKDOWN; K and V have no such condition.  K and W2 act
  * as V where a line smoother has no LDS sub-cycle (fewer than three levels,
- * or point smoothing). */
-typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1, FLD_MG_CYCLE_W2 = 2 } fld_mg_cycle;
+ * or point smoothing).  KL_K and KL_W2 make every second launched level
+ * (levels 1, 3, 5, ... above the sub-cycle) Krylov-accelerated: its coarse
+ * problem is solved by two flexible-CG steps, each preconditioned by the
+ * cycle from that level down (the sub-cycle entered as K or W2), so that the
+ * coarse correction takes its A-norm best scale instead of the aggregated
+ * operator's (a K-cycle over the launched levels; each such level doubles
+ * the work below it; acts as K or W2 where fewer than three levels are
+ * launched). */
+typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1, FLD_MG_CYCLE_W2 = 2, FLD_MG_CYCLE_KL_K = 3,
+               FLD_MG_CYCLE_KL_W2 = 4 } fld_mg_cycle;
 
 typedef struct {
     int32_t precision;      /* fld_precision (default MIXED)                                 */
@@ -544,8 +552,9 @@ typedef struct {
 } fld_tune_entry;
 
 /* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
- * mg_cycle in {K, V, W2} (line smoothers; POINT keeps base's), mg_coarse_max
- * in {64, 256, 16} and chunk in {8, 16, 4} (63 candidates); precision, limiter,
+ * mg_cycle in {K, V, W2, KL_K, KL_W2} (line smoothers; POINT keeps base's),
+ * mg_coarse_max in {64, 256, 16} and chunk in {8, 16, 4} (99 candidates);
+ * precision, limiter,
  * norm and tolerances are those of base (NULL = defaults).  Each candidate
  * gets its own context and runs reps + 1 steps (the first untimed) from the
  * given E, T (device arrays, not modified; the trials run on scratch copies).

@@ -22,6 +22,7 @@ FLD_LIMITER_LP, FLD_LIMITER_MINERBO, FLD_LIMITER_DIFFUSION = 0, 1, 2
 FLD_NORM_ROW, FLD_NORM_SCALED = 0, 1
 FLD_MG_GALERKIN, FLD_MG_HALVED = 0, 1
 FLD_SMOOTH_LINE, FLD_SMOOTH_POINT, FLD_SMOOTH_LINE_SPLIT = 0, 1, 2
+FLD_MG_CYCLE_V, FLD_MG_CYCLE_K, FLD_MG_CYCLE_W2, FLD_MG_CYCLE_KL_K, FLD_MG_CYCLE_KL_W2 = range(5)
 
 PRECISIONS = {"fp64": FLD_FP64, "fp32": FLD_FP32, "mixed": FLD_MIXED}
 

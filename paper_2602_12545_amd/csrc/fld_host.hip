@@ -7,6 +7,7 @@
 // residual, re-scaled inner residual) are decided on the device inside a slot.
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cstddef>
 #include <cmath>
 #include <cstdio>
@@ -76,6 +77,10 @@ struct Inner {
     double* Ywork = nullptr;  // coarse inverse set-up: forward solutions
     T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     int sub_first = -1;                   // first level of the one-workgroup coarse sub-cycle (-1: none)
+    // Krylov-accelerated launched levels (mg_cycle KL_K / KL_W2): bit l of
+    // kl_mask set for level l; c1 and A c1 of each (primary layout)
+    unsigned kl_mask = 0;
+    std::vector<T*> kc1, kv1;
     SubCycle<T> sub{};
     size_t sub_lds = 0;
     hipGraphExec_t chunk_exec = nullptr;  // captured chunk of CG iterations
@@ -123,6 +128,8 @@ struct fld_ctx {
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
     double* part_rz = nullptr;  // r.z partials of the V-cycle's last sweep (summed by k_spmv)
     double* rz_sum = nullptr;   // their total, when summed apart (many partials)
+    double* kpart = nullptr;    // partial sums of the Krylov-accelerated level
+    KLScal* kscal = nullptr;    // its coefficients
     // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
     // enqueue_vcycle queues only the line-sweep launches and counts them
     bool sweeps_only = false;
@@ -212,7 +219,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
     if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
-    if (o->mg_cycle < 0 || o->mg_cycle > 2) { err = "mg_cycle"; return FLD_EINVAL; }
+    if (o->mg_cycle < 0 || o->mg_cycle > 4) { err = "mg_cycle"; return FLD_EINVAL; }
     return FLD_OK;
 }
 
@@ -416,8 +423,9 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     std::vector<T*> xpre(Ld);  // pre-smoothed x of each level (secondary layout)
     // the replay measurement can be limited to the finest levels
     auto skip = [&](int l) { return c->sweeps_only && c->sweep_levels > 0 && l >= c->sweep_levels; };
-    for (int l = 0; l < Ld; ++l) {
-        if (skip(l)) continue;
+    // pre-smoothing of level l and its residual restricted to level l + 1
+    auto down = [&](int l) {
+        if (skip(l)) return;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -439,19 +447,22 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         if (!c->sweeps_only)
             k_resid_restrict<T><<<tile_grid(vq.nx, vq.ny), blk2d(), 0, st>>>(vq.nx, vq.ny, vq.m, vq.We, vq.Wn, a.bQ,
                                                                           xpre[l], nxt.bP, cv.nx, cv.ny, c->sc);
-    }
-    if (c->sweeps_only) {
-        // line sweeps only (replay measurement)
-    } else if ((void)join_setup(c, st), in.sub_first > 0) {
-        LevelT<T>& f = in.lv[in.sub_first];
-        k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
-    } else {
-        LevelT<T>& cl = in.lv[L - 1];
-        k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, nullptr,
-                                                                 c->sc);
-    }
-    for (int l = Ld - 1; l >= 0; --l) {
-        if (skip(l)) continue;
+    };
+    auto coarse = [&]() {
+        if (c->sweeps_only) {
+            // line sweeps only (replay measurement)
+        } else if ((void)join_setup(c, st), in.sub_first > 0) {
+            LevelT<T>& f = in.lv[in.sub_first];
+            k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
+        } else {
+            LevelT<T>& cl = in.lv[L - 1];
+            k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP,
+                                                                     nullptr, c->sc);
+        }
+    };
+    // prolongation of the correction from level l + 1 and post-smoothing of level l
+    auto up = [&](int l) {
+        if (skip(l)) return;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
@@ -468,7 +479,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                 launch_band<T, LINE_NORMAL, 1, false, false, false>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0, a.xP,
                                                                     nullptr, st);
             }
-            continue;
+            return;
         }
         launch_line<T, LINE_PROLONG, 0>(c, vq, 1, a.bQ, a.xQ, nxt.xP, cv.nx, 0, st);
         launch_line<T, LINE_NORMAL, 0>(c, vq, 0, a.bQ, a.xQ, nullptr, 0, 0, st);
@@ -482,7 +493,45 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
             launch_line<T, LINE_NORMAL, 0>(c, vp, 1, a.bP, a.xP, nullptr, 0, 0, st);
             launch_line<T, LINE_NORMAL, 0>(c, vp, 0, a.bP, a.xP, nullptr, 0, 0, st);
         }
-    }
+    };
+    // the cycle from level l down; a Krylov-accelerated level K takes two
+    // flexible-CG steps on A_K e = r_K, each preconditioned by the cycle from
+    // K down (its coefficients and partial sums in slot K of kscal / kpart)
+    std::function<void(int)> cycle = [&](int l) {
+        if (l == Ld) {
+            coarse();
+            return;
+        }
+        const bool krylov = l > 0 && ((in.kl_mask >> l) & 1u) && !c->sweeps_only;
+        if (!krylov) {
+            down(l);
+            cycle(l + 1);
+            up(l);
+            return;
+        }
+        LevelT<T>& a1 = in.lv[l];
+        const View<T> v1 = a1.view(a1.tr);
+        const int n1 = v1.nx * v1.ny;
+        const int G = std::max(1, std::min((n1 + kKLThreads - 1) / kKLThreads, kKLMaxWG));
+        const int single = sizeof(T) == 4 ? 1 : 0;
+        double* part = c->kpart + (size_t)l * 3 * kKLMaxWG;
+        KLScal* ks = c->kscal + l;
+        down(l);
+        cycle(l + 1);
+        up(l);
+        k_kl_dots<T, 0><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
+                                                  in.kv1[l], part, c->sc);
+        k_kl_reduce<0><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+        k_kl_axpy<T><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], ks, c->sc);
+        down(l);
+        cycle(l + 1);
+        up(l);
+        k_kl_dots<T, 1><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
+                                                  in.kv1[l], part, c->sc);
+        k_kl_reduce<1><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+        k_kl_combine<T><<<G, kKLThreads, 0, st>>>(n1, a1.xP, in.kc1[l], ks, c->sc);
+    };
+    cycle(0);
 }
 
 template <typename T>
@@ -659,6 +708,19 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(ctx->alloc(&in.p[0], n));
     HIPCHK(ctx->alloc(&in.p[1], n));
     HIPCHK(ctx->alloc(&in.q, n));
+    in.kl_mask = 0;
+    in.kc1.assign(in.lv.size(), nullptr);
+    in.kv1.assign(in.lv.size(), nullptr);
+    if (line && (ctx->opt.mg_cycle == FLD_MG_CYCLE_KL_K || ctx->opt.mg_cycle == FLD_MG_CYCLE_KL_W2)) {
+        // every second level from level 1 (levels 1, 3, 5, ...; a bit only
+        // acts on a launched level, one above the LDS sub-cycle set below)
+        for (size_t l = 1; l + 1 < in.lv.size() && l < 32; l += 2) {
+            in.kl_mask |= 1u << l;
+            const size_t n1 = (size_t)in.lv[l].nx * in.lv[l].ny;
+            HIPCHK(ctx->alloc(&in.kc1[l], n1));
+            HIPCHK(ctx->alloc(&in.kv1[l], n1));
+        }
+    }
     in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual
     // one-workgroup coarse sub-cycle: the finest level l >= 1 from which all
     // coarser levels fit in LDS (5 arrays each; the K-cycle adds two arrays of
@@ -699,7 +761,9 @@ fld_status alloc_inner(fld_ctx* ctx) {
             S.Ainv = in.Ainv;
             S.bc_off = off;
             S.part_off = off + in.lv[L - 1].nx * in.lv[L - 1].ny;
-            S.kcyc = ctx->opt.mg_cycle == FLD_MG_CYCLE_K ? 1 : ctx->opt.mg_cycle == FLD_MG_CYCLE_W2 ? 2 : 0;
+            const int mc = ctx->opt.mg_cycle;
+            S.kcyc = (mc == FLD_MG_CYCLE_K || mc == FLD_MG_CYCLE_KL_K) ? 1
+                     : (mc == FLD_MG_CYCLE_W2 || mc == FLD_MG_CYCLE_KL_W2) ? 2 : 0;
             S.k_off = S.part_off + kSubThreads<T>;
             if (in.sub_lds > 65536)
                 HIPCHK(hipFuncSetAttribute((const void*)k_subcycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1225,6 +1289,8 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->part2, (size_t)k1DBlocksMax);
     ALLOC(ctx->part_rz, ctx->npart);
     ALLOC(ctx->rz_sum, 1);
+    ALLOC(ctx->kpart, 3 * (size_t)kKLMaxWG * 32);
+    ALLOC(ctx->kscal, 32);
     ALLOC(ctx->sc, 1);
     ALLOC(ctx->sc_sweep, 1);
     ALLOC(ctx->err_flag, 1);

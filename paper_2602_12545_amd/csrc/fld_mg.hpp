@@ -1484,3 +1484,132 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
 }
 
 }  // namespace fld
+
+namespace fld {
+
+// ---------------------------------------------------------------------------
+// Krylov-accelerated launched level (K-cycle at grid level 1; Notay and
+// Vassilevski, 2008): the coarse problem A1 e = r1 of the finest level is
+// solved by two flexible-CG steps, each preconditioned by the cycle from level
+// 1 down (launched levels, then the LDS sub-cycle).  After the first pass
+// (c1 = x): v1 = A1 c1, rho1 = c1.v1, s1 = c1.r1 / rho1, r1 <- r1 - s1 v1; after
+// the second (c2 = x): gam = c2.v1, beta = c2.A1 c2, a2 = c2.r2,
+// rho2 = beta - gam^2 / rho1, x = (s1 - gam a2 / (rho1 rho2)) c1 + (a2 / rho2) c2.
+// Vectors are in the level's primary layout; sums are FP64 partials per
+// workgroup, reduced in a fixed order by one workgroup.
+// ---------------------------------------------------------------------------
+
+constexpr int kKLThreads = 256;
+constexpr int kKLMaxWG = 2048;
+
+struct KLScal {
+    double rho1, s1, f1, f2;
+};
+
+// A x in flux form at cell (i, j) of a row-major level view.
+template <typename T>
+__device__ inline double kl_apply(int nx, int ny, const T* __restrict__ m, const T* __restrict__ We,
+                                  const T* __restrict__ Wn, const T* __restrict__ x, int i, int j) {
+    const size_t c = (size_t)j * nx + i;
+    const double xc = (double)x[c];
+    double acc = (double)m[c] * xc;
+    if (i > 0) acc += (double)We[c - 1] * (xc - (double)x[c - 1]);
+    if (i + 1 < nx) acc += (double)We[c] * (xc - (double)x[c + 1]);
+    if (j > 0) acc += (double)Wn[c - nx] * (xc - (double)x[c - nx]);
+    if (j + 1 < ny) acc += (double)Wn[c] * (xc - (double)x[c + nx]);
+    return acc;
+}
+
+// STAGE 0: c1 = x, v1 = A x; partials x.v1, x.b.
+// STAGE 1: partials x.v1, x.(A x), x.b.
+template <typename T, int STAGE>
+__global__ __launch_bounds__(kKLThreads) void k_kl_dots(int nx, int ny, const T* __restrict__ m,
+                                                        const T* __restrict__ We, const T* __restrict__ Wn,
+                                                        const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ c1, T* __restrict__ v1,
+                                                        double* __restrict__ part, const Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double sh[kKLThreads / 64];
+    const int n = nx * ny;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int c = blockIdx.x * kKLThreads + threadIdx.x; c < n; c += gridDim.x * kKLThreads) {
+        const int i = c % nx, j = c / nx;
+        const double xv = (double)x[c];
+        const double av = kl_apply<T>(nx, ny, m, We, Wn, x, i, j);
+        if (STAGE == 0) {
+            c1[c] = x[c];
+            v1[c] = (T)av;
+            d0 += xv * av;
+            d1 += xv * (double)b[c];
+        } else {
+            d0 += xv * (double)v1[c];
+            d1 += xv * av;
+            d2 += xv * (double)b[c];
+        }
+    }
+    const int G = gridDim.x;
+    double s = block_sum(d0, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    s = block_sum(d1, sh);
+    if (threadIdx.x == 0) part[G + blockIdx.x] = s;
+    if (STAGE == 1) {
+        s = block_sum(d2, sh);
+        if (threadIdx.x == 0) part[2 * G + blockIdx.x] = s;
+    }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kRedThreads) void k_kl_reduce(const double* part, int G, KLScal* ks, const Scalars* sc,
+                                                           int single) {
+    if (sc->done) return;
+    __shared__ double sh[kRedThreads / 64];
+    double v[3];
+    for (int q = 0; q < (STAGE == 0 ? 2 : 3); ++q) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < G; b += kRedThreads) a += part[(size_t)q * G + b];
+        v[q] = block_sum(a, sh);
+    }
+    if (threadIdx.x != 0) return;
+    if (STAGE == 0) {
+        // rho1 <= 0 only for c1 = 0 (zero right-hand side): the result is c1
+        const double rho1 = v[0];
+        ks->rho1 = rho1;
+        ks->s1 = rho1 > 0.0 ? v[1] / rho1 : 0.0;
+        return;
+    }
+    const double rho1 = ks->rho1, s1 = ks->s1;
+    double f1 = s1, f2 = 0.0;
+    if (rho1 > 0.0) {
+        // A-norm squared of the part of c2 A-orthogonal to c1; within the
+        // rounding of its two terms c2 adds nothing
+        const double rho2 = v[1] - v[0] * v[0] / rho1;
+        const double tiny = single ? 1e-5 : 1e-12;
+        if (rho2 > tiny * v[1]) {
+            f2 = v[2] / rho2;
+            f1 = s1 - v[0] * f2 / rho1;
+        }
+    }
+    ks->f1 = f1;
+    ks->f2 = f2;
+}
+
+// r1 <- r1 - s1 v1
+template <typename T>
+__global__ __launch_bounds__(kKLThreads) void k_kl_axpy(int n, T* __restrict__ b, const T* __restrict__ v1,
+                                                        const KLScal* ks, const Scalars* sc) {
+    if (sc->done) return;
+    const T s1 = (T)ks->s1;
+    for (int c = blockIdx.x * kKLThreads + threadIdx.x; c < n; c += gridDim.x * kKLThreads) b[c] -= s1 * v1[c];
+}
+
+// x <- f1 c1 + f2 x
+template <typename T>
+__global__ __launch_bounds__(kKLThreads) void k_kl_combine(int n, T* __restrict__ x, const T* __restrict__ c1,
+                                                           const KLScal* ks, const Scalars* sc) {
+    if (sc->done) return;
+    const T f1 = (T)ks->f1, f2 = (T)ks->f2;
+    for (int c = blockIdx.x * kKLThreads + threadIdx.x; c < n; c += gridDim.x * kKLThreads)
+        x[c] = f1 * c1[c] + f2 * x[c];
+}
+
+}  // namespace fld

@@ -231,6 +231,34 @@ def test_k_cycle_and_v_cycle(lib, name, kw, prec):
     assert iw["inner_iters"] <= iv["inner_iters"] + 1
 
 
+_KL_REFS = {}
+
+
+@pytest.mark.parametrize("name,kw", [("c2", dict(nx=768, ny=512)), ("c5", dict(nx=512, ny=256)),
+                                     ("c3", dict(nx=640, ny=320))])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_krylov_accelerated_levels(lib, name, kw, prec):
+    """The cycles with Krylov-accelerated launched levels (two flexible-CG
+    steps on the coarse problem of levels 1, 3, ..., each preconditioned by
+    the cycle below) reach the oracle's solution on hierarchies with two or
+    more launched levels, with no more CG iterations than the cycle they
+    wrap."""
+    prob = W.make(name, **kw)
+    print(f"[krylov levels] {name} {prob.nx}x{prob.ny} {prec}", flush=True)
+    if name not in _KL_REFS:
+        _KL_REFS[name] = O.step_problem(prob)
+    ref = _KL_REFS[name]
+    opt = dict(precision=prec, rel_tol=1e-12, norm=1, mg_coarse_max=256)
+    its = {}
+    for cyc in (1, 2, 3, 4):
+        E, T, info = gpu_step(lib, torch, prob, mg_cycle=cyc, **opt)
+        its[cyc] = info["inner_iters"]
+        assert info["status"] == 0, (cyc, info)
+        assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10, cyc
+    print(name, prec, "K", its[1], "W2", its[2], "KL_K", its[3], "KL_W2", its[4], flush=True)
+    assert its[3] <= its[1] and its[4] <= its[2]
+
+
 def thin_c1():
     """The c1 recipe with rho lowered 1e3-fold: sigma dx = 0.01, so the
     temperature bump drives the limiter argument R across 3/2 (both branches

@@ -127,7 +127,9 @@ struct fld_ctx {
     double* part = nullptr;
     double* part2 = nullptr;  // r.r partials of k_update (read while part holds p.q)
     double* part_rz = nullptr;  // r.z partials of the V-cycle's last sweep (summed by k_spmv)
-    double* rz_sum = nullptr;   // their total, when summed apart (many partials)
+    double* rz_sum = nullptr;   // their total, when summed apart (many partials); [1]: r_k+1 . z_k
+    double* part_rzo = nullptr; // r_k+1 . z_k partials of k_update (flexible CG)
+    bool flex = false;          // Polak-Ribiere beta (every cycle but the plain V-cycle)
     double* kpart = nullptr;    // partial sums of the Krylov-accelerated level
     KLScal* kscal = nullptr;    // its coefficients
     // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
@@ -602,16 +604,22 @@ void enqueue_slot(fld_ctx* c, Inner<T>& in, int par, double* E, hipStream_t st) 
     // r.z: summed by every SpMV workgroup from the sweep's partials when they
     // are few, else once by one workgroup (c5's 4096-cell lines leave 2048,
     // whose re-summing cost the SpMV a third of its time)
-    const bool many_rz = c->nrz > 512;
-    if (many_rz) k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part_rz, c->nrz, c->rz_sum, c->sc);
+    // (and, for the flexible beta, r_k+1 . z_k from k_update's partials)
+    const bool flex = c->flex;
+    const bool many_rz = c->nrz > 512 || flex;
+    if (many_rz)
+        k_reduce_rz<<<1, kRedThreads, 0, st>>>(c->part_rz, c->nrz, flex ? c->part_rzo : nullptr, nb1, c->rz_sum,
+                                               c->sc);
     k_spmv<T><<<tg, blk2d(), 0, st>>>(nx, ny, l0.xP, in.p[par], in.p[par ^ 1], in.q, l0.m, l0.We, l0.Wn,
-                                      many_rz ? c->rz_sum : c->part_rz, many_rz ? 1 : c->nrz, c->part, c->sc);
+                                      many_rz ? c->rz_sum : c->part_rz, many_rz ? 1 : c->nrz,
+                                      flex ? c->rz_sum + 1 : nullptr, c->part, c->sc);
     // alpha: summed inside k_update from the SpMV partials when they are few,
     // by one reduction workgroup otherwise
     const bool fold = ntiles <= 1024;
     if (!fold) k_reduce_pq<<<1, kRedThreads, 0, st>>>(c->part, ntiles, c->sc);
+    // z_k (read by k_spmv above) stays in l0.xP until the next cycle
     k_update<T><<<nb1, 256, 0, st>>>(n, in.x, in.r, in.p[par ^ 1], in.q, c->part, fold ? ntiles : 0, c->part2,
-                                     c->sc);
+                                     flex ? (const T*)l0.xP : nullptr, c->part_rzo, c->sc);
     enqueue_check<T>(c, in, E, 0, st);
     enqueue_vcycle<T>(c, in, st);
 }
@@ -1218,6 +1226,7 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     else fld_default_options(&ctx->opt);
     std::string why;
     if (validate_options(&ctx->opt, why) != FLD_OK) return fail(FLD_EINVAL, "bad option: " + why);
+    ctx->flex = is_line(ctx->opt) && ctx->opt.mg_cycle != FLD_MG_CYCLE_V;
     const int nx = grid->nx, ny = grid->ny;
     if (nx < 1 || ny < 1 || (int64_t)nx * ny > (int64_t(1) << 28)) return fail(FLD_EINVAL, "grid size");
     if (grid->geom != FLD_CARTESIAN && grid->geom != FLD_SPHERICAL_POLAR) return fail(FLD_EINVAL, "geometry");
@@ -1288,7 +1297,8 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
     ALLOC(ctx->part, ctx->npart);
     ALLOC(ctx->part2, (size_t)k1DBlocksMax);
     ALLOC(ctx->part_rz, ctx->npart);
-    ALLOC(ctx->rz_sum, 1);
+    ALLOC(ctx->rz_sum, 2);
+    ALLOC(ctx->part_rzo, (size_t)k1DBlocksMax);
     ALLOC(ctx->kpart, 3 * (size_t)kKLMaxWG * 32);
     ALLOC(ctx->kscal, 32);
     ALLOC(ctx->sc, 1);

@@ -644,16 +644,20 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
 // CG kernels
 // ---------------------------------------------------------------------------
 
-// r.z from the partials of the sweep that produced z, beta = r.z / r.z_old;
-// p = z + beta * pscale * p_in (p = z on the first iteration or after a
-// restart), q = M p in flux form, partial p.q per workgroup (summed by
-// k_update).
+// r.z from the partials of the sweep that produced z, beta = r.z / r.z_old
+// (Fletcher-Reeves) or, with rzo (the new residual against the previous
+// preconditioned residual, r_k+1 . z_k, summed by k_reduce_rz at rzo[0]),
+// beta = max(0, (r.z - r_k+1 . z_k) / r.z_old) (Polak-Ribiere, i.e. flexible
+// CG: the multigrid cycles with Krylov levels or a W-type sub-cycle are not a
+// fixed symmetric operator); p = z + beta * pscale * p_in (p = z on the first
+// iteration or after a restart), q = M p in flux form, partial p.q per
+// workgroup (summed by k_update).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
                                               T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
                                               const T* __restrict__ We, const T* __restrict__ Wn,
-                                              const double* __restrict__ part_rz, int nrz, double* part,
-                                              Scalars* sc) {
+                                              const double* __restrict__ part_rz, int nrz,
+                                              const double* __restrict__ rzo, double* part, Scalars* sc) {
     if (sc->done) return;
     constexpr int H = 1, LX = TileG<H>::LX, N = TileG<H>::N;
     constexpr int NU = (N + kThreads - 1) / kThreads;
@@ -696,7 +700,10 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     }
     const int iter = sc->iter;
     const bool first = iter == 0 || sc->restart;
-    const double beta64 = iter > 0 ? rz / sc->rz_old : 0.0;
+    // r_k+1 . z_k was summed before a reliable update rescaled the inner
+    // system by pscale (r and z alike, hence its square, as for r.z_old)
+    const double ps = sc->pscale;
+    const double beta64 = iter == 0 ? 0.0 : rzo ? fmax(0.0, (rz - rzo[0] * ps * ps) / sc->rz_old) : rz / sc->rz_old;
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
         sc->rz_cur = rz;
         sc->beta = beta64;
@@ -736,11 +743,14 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
 // npq = 0, alpha as k_reduce_pq left it (grids with many partials, where
 // every workgroup re-reading them costs more than a launch) -- then
 // x += alpha p, r -= alpha q and a partial r.r per workgroup into part_rr
-// (summed by k_resid64); workgroup 0 counts the iteration.
+// (summed by k_resid64); with zold (the preconditioned residual p was built
+// from), also a partial of r_new . zold into part_rzo for the flexible beta;
+// workgroup 0 counts the iteration.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                 const T* __restrict__ q, const double* __restrict__ part_pq,
-                                                int npq, double* part_rr, Scalars* sc) {
+                                                int npq, double* part_rr, const T* __restrict__ zold,
+                                                double* part_rzo, Scalars* sc) {
     if (sc->done) return;
     __shared__ double sh[16];
     __shared__ double s_pq;
@@ -779,10 +789,11 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
     // memory-level parallelism comes from the unrolling; binary64 measured
     // best without it)
     constexpr int U = sizeof(T) == 4 ? 4 : 1;
-    double acc = 0.0;
+    double acc = 0.0, acz = 0.0;
+    const bool flex = zold != nullptr;
     const int stride = gridDim.x * blockDim.x;
     for (int c0 = blockIdx.x * blockDim.x + threadIdx.x; c0 < n; c0 += U * stride) {
-        T xv[U], pv[U], rv[U], qv[U];
+        T xv[U], pv[U], rv[U], qv[U], zv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = c0 + u * stride;
@@ -791,6 +802,7 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
             pv[u] = ok ? p[c] : T(0);
             rv[u] = ok ? r[c] : T(0);
             qv[u] = ok ? q[c] : T(0);
+            zv[u] = ok && flex ? zold[c] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -800,11 +812,17 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
                 const T rn = rv[u] - a * qv[u];
                 r[c] = rn;
                 acc += (double)rn * (double)rn;
+                acz += (double)rn * (double)zv[u];
             }
         }
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
+    if (flex) {
+        __syncthreads();
+        const double tz = block_sum(acz, sh);
+        if (threadIdx.x == 0) part_rzo[blockIdx.x] = tz;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -944,12 +962,16 @@ __device__ inline double reduce_sum(const double* part, int nb, int stride, int 
 // r.z summed once when the last sweep left many partials (one workgroup per
 // long line): *out feeds k_spmv as a single partial instead of every SpMV
 // workgroup summing all of them
-__global__ __launch_bounds__(kRedThreads) void k_reduce_rz(const double* part, int nb, double* out,
-                                                           const Scalars* sc) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rz(const double* part, int nb, const double* part_rzo,
+                                                           int nbo, double* out, const Scalars* sc) {
     if (sc->done) return;
     __shared__ double sh[16];
     const double v = reduce_sum(part, nb, 1, 0, sh);
-    if (threadIdx.x == 0) *out = v;
+    if (threadIdx.x == 0) out[0] = v;
+    if (part_rzo) {
+        const double w = reduce_sum(part_rzo, nbo, 1, 0, sh);
+        if (threadIdx.x == 0) out[1] = w;
+    }
 }
 
 // alpha = r.z / p.q (k_update with npq = 0 reads it from the state instead)

@@ -50,9 +50,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--mg-cycle", default=None, choices=list(CYCLES),
-                    help="fix the multigrid cycle of the stress workload (default: the faster of K and W2 by a "
-                         "three-step probe, per precision)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 100-step run")
+                    help="fix the multigrid cycle of the stress workload (default: the fastest of KL_W2, KL_K, "
+                         "W2 and K by a three-step probe, per precision)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 runs of the stress steps")
     ap.add_argument("--no-sequence", action="store_true", help="skip the 100-step runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
@@ -80,10 +80,11 @@ def rel_l2(a, b):
 
 
 def kernel_source_digest():
-    """Digest of the measured kernel and its launch: the multigrid header
-    that defines k_line, the headers it includes, and the host functions that
-    pick its chunking and launch it (comments and white space removed).  HBM traffic counters taken on other code no longer describe
-    the line sweeps; host changes elsewhere leave them valid."""
+    """Digest of the measured kernels and their launches: the multigrid and
+    band headers that define k_line and k_band, the headers they include, and
+    the host functions that pick their chunking and launch them (comments and
+    white space removed).  HBM traffic counters taken on other code no longer
+    describe the line sweeps; host changes elsewhere leave them valid."""
     import hashlib
     import re
     d = os.path.join(ROOT, "paper_2602_12545_amd", "csrc")
@@ -94,11 +95,11 @@ def kernel_source_digest():
         src = re.sub(r"//[^\n]*", "", src)
         return re.sub(r"\s+", "", src)
 
-    for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_mg.hpp"):
+    for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_mg.hpp", "fld_band.hpp"):
         h.update(f.encode())
         h.update(clean(open(os.path.join(d, f)).read()).encode())
     host = open(os.path.join(d, "fld_host.hip")).read()
-    for fn in ("inline void line_params", "int launch_line"):
+    for fn in ("inline void line_params", "int launch_line", "int launch_band"):
         i = host.index(fn)
         j = host.index("\n}\n", i)
         h.update(clean(host[i:j]).encode())
@@ -185,29 +186,38 @@ def pick_cycle(fld, torch, prob, f, prec, fixed):
 
 
 def roofline(ctx, reps=50):
-    """Finest-level zebra line half-sweeps of the stress grid (the dominant
-    kernel): one V-cycle's fine-level launches captured on a solver state
-    that never converges and replayed between two HIP events on the solve
-    stream.  The time per launch includes the ~1 us gap between dependent
-    launches (a kernel trace of the same replay reports ~3 % less); the same
-    time minus that of an equal graph of empty launches, which also removes
-    the empty kernels' own execution, is reported as an upper bound."""
-    rep = ctx.profile_sweeps(reps, levels=1)
-    fam = ctx.profile_sweeps(reps, levels=0)
-    kern_us = rep["us_per_launch"]
-    achieved = rep["bytes_per_launch"] / (kern_us * 1e-6) / 1e9
-    traffic, tnote = measured_traffic("pmc_c5_fine_line_sweeps.md")
-    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tnote,
-           "kernel": "k_line on the finest level (4096x2048): the zebra line half-sweeps of both directions",
-           "avg_launch_us": kern_us, "bytes_per_launch": rep["bytes_per_launch"],
-           "duration_method": f"graph replay of one V-cycle's {rep['launches']} fine-level line-sweep launches x "
-                              f"{reps}, HIP events on the solve stream, per-launch time with the launch gaps",
-           "replay": rep,
-           "upper_bound_minus_empty_launches": rep["bytes_per_launch"] / (
-               max(rep["us_per_launch"] - rep["floor_us"], 1e-3) * 1e-6) / 1e9}
-    out["line_sweep_family"] = {"levels": "all grid levels", "replay": fam, "avg_launch_us": fam["us_per_launch"],
-                                "achieved": fam["bytes_per_launch"] / (fam["us_per_launch"] * 1e-6) / 1e9}
+    """The dominant kernel of the stress step: the band-fused zebra line
+    sweeps (`k_band`, both colours of one direction per launch) of grid
+    levels 1 .. 5, the largest share of the step's kernel time (the finest
+    level's `k_line` half-sweeps, the LDS sub-cycle and the Krylov-level
+    kernels follow).  One V-cycle's line-sweep launches of those levels are
+    captured on a solver state that never converges and replayed between two
+    HIP events on the solve stream; the time per launch includes the gap
+    between dependent launches (the same time minus that of an equal graph of
+    empty launches, which also removes the empty kernels' own execution, is
+    reported as an upper bound).  The finest level's half-sweeps, the
+    bandwidth-bound kernel, are measured alike and reported beside it."""
+    def measure(rep, pmc):
+        us = rep["us_per_launch"]
+        traffic, tnote = measured_traffic(pmc)
+        return {"achieved": rep["bytes_per_launch"] / (us * 1e-6) / 1e9, "avg_launch_us": us,
+                "bytes_per_launch": rep["bytes_per_launch"], "traffic": traffic, "traffic_source": tnote,
+                "replay": rep, "upper_bound_minus_empty_launches": rep["bytes_per_launch"] / (
+                    max(us - rep["floor_us"], 1e-3) * 1e-6) / 1e9}
+    fine = measure(ctx.profile_sweeps(reps, levels=1), "pmc_c5_fine_line_sweeps.md")
+    band = measure(ctx.profile_sweeps(reps, first=1), "pmc_c5_band_sweeps.md")
+    out = {"bound": "hbm", "achieved": band["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": band["achieved"] / HBM_PEAK_GBS, "traffic": band["traffic"],
+           "kernel": "k_band on grid levels 1-5 (2048x1024 .. 128x64): band-fused zebra line sweeps, both colours "
+                     "of one direction per launch; the largest share of the stress step's kernel time",
+           "duration_method": f"graph replay of one V-cycle's {band['replay']['launches']} line-sweep launches on "
+                              f"levels 1-5 x {reps}, HIP events on the solve stream, per-launch time with the "
+                              "launch gaps",
+           **{k: band[k] for k in ("avg_launch_us", "bytes_per_launch", "traffic_source", "replay",
+                                   "upper_bound_minus_empty_launches")}}
+    out["fine_level_line_sweeps"] = {
+        "kernel": "k_line on the finest level (4096x2048): the zebra line half-sweeps of both directions",
+        "frac": fine["achieved"] / HBM_PEAK_GBS, **fine}
     return out
 
 
@@ -670,19 +680,31 @@ def main():
         out["roofline"] = roofline(ctx)
     ctx.close()
     cycles = {prec: cyc}
+    if not args.no_fp64 and prec != "fp64":
+        # the same warm-up and timed steps in FP64, on FP64's own fastest cycle
+        c64, probe64 = pick_cycle(fld, torch, prob, f, "fp64", args.mg_cycle)
+        cycles["fp64"] = c64
+        ctx = make_ctx(fld, prob, stress_options(fld, "fp64", c64))
+        if args.warmup > 0:
+            run_sequence(fld, torch, prob, f, None, args.warmup, ctx)
+        sec64, inf64, _ = run_sequence(fld, torch, prob, f, None, args.steps, ctx)
+        ctx.close()
+        its64 = [i["inner_iters"] for i in inf64]
+        out["fp64_same_steps"] = {"ms_per_step": sec64 * 1e3, "inner_iters": sum(its64) / len(its64),
+                                  "iters": its64, "mg_cycle": cname[c64], "cycle_probe": probe64,
+                                  "status": sorted(set(i["status"] for i in inf64))}
+        out["mixed_vs_fp64"] = sec64 / sec
     if not args.no_sequence:
         seq = {"workload": f"the stress recipe's {SEQUENCE}-step sequence from its initial state, one fld_steps "
-                           "call per precision, each on the faster of the K-cycle and W2"}
+                           "call per precision, each on the fastest cycle of its probe"}
         ms, inf, _ = run_sequence(fld, torch, prob, f, stress_options(fld, prec, cyc), SEQUENCE)
         seq[prec] = summarise(prob, 1e3 * ms, inf)
         seq[prec]["mg_cycle"] = cname[cyc]
-        if not args.no_fp64 and prec != "fp64":
-            c64, probe64 = pick_cycle(fld, torch, prob, f, "fp64", args.mg_cycle)
-            cycles["fp64"] = c64
+        if "fp64" in cycles and prec != "fp64":
+            c64 = cycles["fp64"]
             ms, inf, _ = run_sequence(fld, torch, prob, f, stress_options(fld, "fp64", c64), SEQUENCE)
             seq["fp64"] = summarise(prob, 1e3 * ms, inf)
             seq["fp64"]["mg_cycle"] = cname[c64]
-            seq["fp64"]["cycle_probe"] = probe64
             seq["mixed_vs_fp64"] = seq["fp64"]["ms_per_step"] / seq[prec]["ms_per_step"]
         out["sequence_100"] = seq
     del f

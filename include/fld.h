@@ -381,6 +381,13 @@ fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch,
  * level, as fld_profile_sweeps). */
 fld_status fld_profile_sweeps_levels(fld_ctx* ctx, int32_t levels, int32_t reps, double* us_per_launch,
                                      double* floor_us, double* bytes_per_launch, int32_t* launches);
+/* The same replay limited to grid levels first .. first + levels - 1
+ * (levels = 0: to the last launched level; first = 1: the coarse levels'
+ * band sweeps without the fine grid).  EINVAL if the range holds no
+ * line-sweep launch. */
+fld_status fld_profile_sweeps_range(fld_ctx* ctx, int32_t first, int32_t levels, int32_t reps,
+                                    double* us_per_launch, double* floor_us, double* bytes_per_launch,
+                                    int32_t* launches);
 
 const char* fld_status_string(fld_status s);
 const char* fld_last_error(const fld_ctx* ctx);

@@ -98,6 +98,9 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "fld_profile_sweeps_levels": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
+    "fld_profile_sweeps_range": (_I, [_P, _I, _I, _I, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(_I)]),
     "fld_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]),
     "fld_status_string": (ctypes.c_char_p, [_I]),
@@ -287,10 +290,10 @@ class Context:
         self._check(lib.fld_profile_overhead(self.handle, int(reps), ctypes.byref(us)))
         return us.value
 
-    def profile_sweeps(self, reps: int = 50, levels: int = 0) -> dict:
+    def profile_sweeps(self, reps: int = 50, levels: int = 0, first: int = 0) -> dict:
         us, fl, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), _I()
-        self._check(lib.fld_profile_sweeps_levels(self.handle, int(levels), int(reps), ctypes.byref(us),
-                                                  ctypes.byref(fl), ctypes.byref(by), ctypes.byref(n)))
+        self._check(lib.fld_profile_sweeps_range(self.handle, int(first), int(levels), int(reps), ctypes.byref(us),
+                                                 ctypes.byref(fl), ctypes.byref(by), ctypes.byref(n)))
         return {"us_per_launch": us.value, "floor_us": fl.value, "bytes_per_launch": by.value, "launches": n.value}
 
     @property

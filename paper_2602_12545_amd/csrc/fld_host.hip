@@ -135,7 +135,8 @@ struct fld_ctx {
     // line-sweep replay measurement (fld_profile_sweeps): while `sweeps_only`,
     // enqueue_vcycle queues only the line-sweep launches and counts them
     bool sweeps_only = false;
-    int sweep_levels = 0;       // replay only the finest sweep_levels grid levels (0: all)
+    int sweep_first = 0;        // replay only grid levels sweep_first .. sweep_first + sweep_levels - 1
+    int sweep_levels = 0;       // (sweep_levels 0: to the last launched level)
     int sweep_launches = 0;
     double sweep_bytes = 0.0;
     Scalars* sc_sweep = nullptr;  // solver state of the replay (never done)
@@ -424,7 +425,10 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const bool fused = c->opt.smoother == FLD_SMOOTH_LINE;
     std::vector<T*> xpre(Ld);  // pre-smoothed x of each level (secondary layout)
     // the replay measurement can be limited to the finest levels
-    auto skip = [&](int l) { return c->sweeps_only && c->sweep_levels > 0 && l >= c->sweep_levels; };
+    auto skip = [&](int l) {
+        return c->sweeps_only &&
+               (l < c->sweep_first || (c->sweep_levels > 0 && l >= c->sweep_first + c->sweep_levels));
+    };
     // pre-smoothing of level l and its residual restricted to level l + 1
     auto down = [&](int l) {
         if (skip(l)) return;
@@ -1083,12 +1087,19 @@ fld_status fld_profile_overhead(fld_ctx* ctx, int32_t reps, double* us_per_launc
 
 fld_status fld_profile_sweeps(fld_ctx* ctx, int32_t reps, double* us_per_launch, double* floor_us,
                               double* bytes_per_launch, int32_t* launches) {
-    return fld_profile_sweeps_levels(ctx, 0, reps, us_per_launch, floor_us, bytes_per_launch, launches);
+    return fld_profile_sweeps_range(ctx, 0, 0, reps, us_per_launch, floor_us, bytes_per_launch, launches);
 }
 
 fld_status fld_profile_sweeps_levels(fld_ctx* ctx, int32_t levels, int32_t reps, double* us_per_launch,
                                      double* floor_us, double* bytes_per_launch, int32_t* launches) {
-    if (!ctx || reps < 1 || levels < 0 || !us_per_launch || !floor_us || !bytes_per_launch || !launches)
+    return fld_profile_sweeps_range(ctx, 0, levels, reps, us_per_launch, floor_us, bytes_per_launch, launches);
+}
+
+fld_status fld_profile_sweeps_range(fld_ctx* ctx, int32_t first, int32_t levels, int32_t reps,
+                                    double* us_per_launch, double* floor_us, double* bytes_per_launch,
+                                    int32_t* launches) {
+    if (!ctx || reps < 1 || first < 0 || levels < 0 || !us_per_launch || !floor_us || !bytes_per_launch ||
+        !launches)
         return FLD_EINVAL;
     if (!ctx->assembled) {
         ctx->err = "fld_profile_sweeps before fld_assemble";
@@ -1098,87 +1109,133 @@ fld_status fld_profile_sweeps_levels(fld_ctx* ctx, int32_t levels, int32_t reps,
         ctx->err = "fld_profile_sweeps needs a line smoother";
         return FLD_EINVAL;
     }
-    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // a context without graphs (use_graph = 0) replays the sweeps as plain
+    // launches, so that counter tools that do not follow graphs see them
+    const bool graph = ctx->opt.use_graph != 0;
+    if (graph && !ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    hipEvent_t a = ev.a, b = ev.b;
     // a solver state that is never done, so every sweep works
     k_init_scalars<<<1, 1, 0, ctx->stream>>>(ctx->sc_sweep, 1e-300, 0.0, 0.0, 1, 0, 1);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     Scalars* keep = ctx->sc;
     const bool prof_on = ctx->prof.on;
-    ctx->sc = ctx->sc_sweep;
-    ctx->prof.on = false;
-    ctx->sweeps_only = true;
-    ctx->sweep_levels = levels;
+    const int nrz_keep = ctx->nrz;
+    auto enter = [&]() {
+        ctx->sc = ctx->sc_sweep;
+        ctx->prof.on = false;
+        ctx->sweeps_only = true;
+        ctx->sweep_first = first;
+        ctx->sweep_levels = levels;
+    };
+    auto leave = [&]() {
+        ctx->sc = keep;
+        ctx->prof.on = prof_on;
+        ctx->sweeps_only = false;
+        ctx->sweep_first = 0;
+        ctx->sweep_levels = 0;
+        ctx->nrz = nrz_keep;
+    };
+    auto sweeps = [&](hipStream_t st) {
+        if (inner_is_float(ctx)) enqueue_vcycle<float>(ctx, ctx->i32, st);
+        else enqueue_vcycle<double>(ctx, ctx->i64, st);
+    };
+    enter();
     ctx->sweep_launches = 0;
     ctx->sweep_bytes = 0.0;
-    const int nrz_keep = ctx->nrz;
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        if (inner_is_float(ctx)) enqueue_vcycle<float>(ctx, ctx->i32, ctx->cap_stream);
-        else enqueue_vcycle<double>(ctx, ctx->i64, ctx->cap_stream);
-        e = hipStreamEndCapture(ctx->cap_stream, &g);
+    hipError_t e = hipSuccess;
+    if (graph) {
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            sweeps(ctx->cap_stream);
+            e = hipStreamEndCapture(ctx->cap_stream, &g);
+        }
+    } else {
+        sweeps(ctx->stream);  // warm-up, and the launch count
+        e = hipGetLastError();
     }
-    ctx->sc = keep;
-    ctx->prof.on = prof_on;
-    ctx->sweeps_only = false;
-    ctx->sweep_levels = 0;
-    ctx->nrz = nrz_keep;
+    const int nl = ctx->sweep_launches;
+    const double nbytes = ctx->sweep_bytes;
+    if (graph) leave();
     if (e != hipSuccess) {
+        if (!graph) leave();
         ctx->err = std::string("sweep capture: ") + hipGetErrorString(e);
         return FLD_EHIP;
     }
-    hipGraphExec_t ge = nullptr;
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        ctx->err = std::string("sweep graph: ") + hipGetErrorString(e);
-        return FLD_EHIP;
+    if (nl == 0) {
+        if (graph) (void)hipGraphDestroy(g);
+        else leave();
+        ctx->err = "no line-sweep launch in the level range";
+        return FLD_EINVAL;
     }
-    const int nl = ctx->sweep_launches;
-    // the same number of empty launches, captured and replayed alike: the
-    // graph's cost per dependent launch
-    hipGraphExec_t ge0 = nullptr;
-    e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        for (int k = 0; k < nl; ++k) k_noop<<<1, 64, 0, ctx->cap_stream>>>(nullptr);
-        e = hipStreamEndCapture(ctx->cap_stream, &g);
-    }
-    if (e == hipSuccess) {
-        e = hipGraphInstantiate(&ge0, g, nullptr, nullptr, 0);
+    hipGraphExec_t ge = nullptr, ge0 = nullptr;
+    if (graph) {
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ctx->err = std::string("sweep graph: ") + hipGetErrorString(e);
+            return FLD_EHIP;
+        }
+        // the same number of empty launches, captured and replayed alike:
+        // the graph's cost per dependent launch
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < nl; ++k) k_noop<<<1, 64, 0, ctx->cap_stream>>>(nullptr);
+            e = hipStreamEndCapture(ctx->cap_stream, &g);
+        }
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&ge0, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+        }
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ge);
+            ctx->err = std::string("empty-launch graph: ") + hipGetErrorString(e);
+            return FLD_EHIP;
+        }
     }
-    if (e != hipSuccess) {
-        (void)hipGraphExecDestroy(ge);
-        ctx->err = std::string("empty-launch graph: ") + hipGetErrorString(e);
-        return FLD_EHIP;
-    }
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    auto replay = [&](hipGraphExec_t x, float* ms) -> hipError_t {
-        hipError_t r = hipGraphLaunch(x, ctx->stream);  // warm-up
+    // one pass of the work (graph or plain launches), a warm-up pass first
+    auto replay = [&](bool empty, float* ms) -> hipError_t {
+        auto pass = [&]() -> hipError_t {
+            if (graph) return hipGraphLaunch(empty ? ge0 : ge, ctx->stream);
+            if (empty)
+                for (int k = 0; k < nl; ++k) k_noop<<<1, 64, 0, ctx->stream>>>(nullptr);
+            else
+                sweeps(ctx->stream);
+            return hipGetLastError();
+        };
+        hipError_t r = pass();
         if (r == hipSuccess) r = hipEventRecord(a, ctx->stream);
-        for (int k = 0; k < reps && r == hipSuccess; ++k) r = hipGraphLaunch(x, ctx->stream);
+        for (int k = 0; k < reps && r == hipSuccess; ++k) r = pass();
         if (r == hipSuccess) r = hipEventRecord(b, ctx->stream);
         if (r == hipSuccess) r = hipEventSynchronize(b);
         if (r == hipSuccess) r = hipEventElapsedTime(ms, a, b);
         return r;
     };
     float ms = 0.f, ms0 = 0.f;
-    e = replay(ge, &ms);
-    if (e == hipSuccess) e = replay(ge0, &ms0);
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    (void)hipGraphExecDestroy(ge);
-    (void)hipGraphExecDestroy(ge0);
+    e = replay(false, &ms);
+    if (e == hipSuccess) e = replay(true, &ms0);
+    if (!graph) leave();
+    if (graph) {
+        (void)hipGraphExecDestroy(ge);
+        (void)hipGraphExecDestroy(ge0);
+    }
     if (e != hipSuccess) {
         ctx->err = std::string("sweep replay: ") + hipGetErrorString(e);
         return FLD_EHIP;
     }
     *launches = nl;
-    *us_per_launch = nl > 0 ? 1e3 * ms / ((double)reps * nl) : 0.0;
-    *floor_us = nl > 0 ? 1e3 * ms0 / ((double)reps * nl) : 0.0;
-    *bytes_per_launch = nl > 0 ? ctx->sweep_bytes / nl : 0.0;
+    *us_per_launch = 1e3 * ms / ((double)reps * nl);
+    *floor_us = 1e3 * ms0 / ((double)reps * nl);
+    *bytes_per_launch = nbytes / nl;
     return FLD_OK;
 }
 

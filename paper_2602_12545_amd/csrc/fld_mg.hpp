@@ -651,7 +651,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(int nx, int ny, const T*
 // CG: the multigrid cycles with Krylov levels or a W-type sub-cycle are not a
 // fixed symmetric operator); p = z + beta * pscale * p_in (p = z on the first
 // iteration or after a restart), q = M p in flux form, partial p.q per
-// workgroup (summed by k_update).
+// workgroup (summed by k_update).  pscale and the rescaled r.z_old come from a
+// reliable update in between (k_reduce_resid).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restrict__ z, const T* __restrict__ pin,
                                               T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ m,
@@ -700,10 +701,11 @@ __global__ __launch_bounds__(256) void k_spmv(int nx, int ny, const T* __restric
     }
     const int iter = sc->iter;
     const bool first = iter == 0 || sc->restart;
-    // r_k+1 . z_k was summed before a reliable update rescaled the inner
-    // system by pscale (r and z alike, hence its square, as for r.z_old)
-    const double ps = sc->pscale;
-    const double beta64 = iter == 0 ? 0.0 : rzo ? fmax(0.0, (rz - rzo[0] * ps * ps) / sc->rz_old) : rz / sc->rz_old;
+    // r_k+1 . z_k belongs to the recurrence residual: after a reliable update
+    // replaced r by the true residual (demote set), the Fletcher-Reeves beta
+    // with the rescaled r.z_old is taken instead
+    const bool flex = rzo != nullptr && !sc->demote;
+    const double beta64 = iter == 0 ? 0.0 : flex ? fmax(0.0, (rz - rzo[0]) / sc->rz_old) : rz / sc->rz_old;
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
         sc->rz_cur = rz;
         sc->beta = beta64;
@@ -1136,6 +1138,7 @@ namespace fld {
 template <typename T>
 constexpr int kSubThreads = sizeof(T) == 4 ? 1024 : 512;
 constexpr int kSubMaxLevels = 12;
+constexpr int kSubLM = 8;  // cells per lane chunk of the LDS line sweeps
 
 template <typename T>
 struct SubLevel {
@@ -1180,15 +1183,15 @@ __device__ inline void sub_line(const SubLevel<T>& L, T* pool, bool xdir, int pa
     // path with compile-time chunk bounds: about 40 % fewer instructions for
     // the one or few busy wavefronts that bound a half-sweep
     const int na = xdir ? nx : ny;
-    if (wave_line_lanes<kLineMaxL>(na) * kLineMaxL == na) {
+    if (wave_line_lanes<kSubLM>(na) * kSubLM == na) {
         if (xdir)
-            wave_line_sweep<T, kLineMaxL, ZERO, true, false, int, true>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+            wave_line_sweep<T, kSubLM, ZERO, true, false, int, true>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
         else
-            wave_line_sweep<T, kLineMaxL, ZERO, true, false, int, true>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+            wave_line_sweep<T, kSubLM, ZERO, true, false, int, true>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
     } else if (xdir) {
-        wave_line_sweep<T, kLineMaxL, ZERO, true, false, int>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
+        wave_line_sweep<T, kSubLM, ZERO, true, false, int>(nx, ny, par, 1, P, m, We, Wn, b, x, wave, nw);
     } else {
-        wave_line_sweep<T, kLineMaxL, ZERO, true, false, int>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
+        wave_line_sweep<T, kSubLM, ZERO, true, false, int>(ny, nx, par, P, 1, m, Wn, We, b, x, wave, nw);
     }
 }
 
@@ -1510,12 +1513,13 @@ __global__ __launch_bounds__(kSubThreads<T>) void k_subcycle(SubCycle<T> S, cons
 namespace fld {
 
 // ---------------------------------------------------------------------------
-// Krylov-accelerated launched level (K-cycle at grid level 1; Notay and
-// Vassilevski, 2008): the coarse problem A1 e = r1 of the finest level is
-// solved by two flexible-CG steps, each preconditioned by the cycle from level
-// 1 down (launched levels, then the LDS sub-cycle).  After the first pass
-// (c1 = x): v1 = A1 c1, rho1 = c1.v1, s1 = c1.r1 / rho1, r1 <- r1 - s1 v1; after
-// the second (c2 = x): gam = c2.v1, beta = c2.A1 c2, a2 = c2.r2,
+// Krylov-accelerated launched levels (K-cycle at grid levels 1, 3, 5, ...;
+// Notay and Vassilevski, 2008): the coarse problem A_l e = r_l of such a level
+// l is solved by two flexible-CG steps, each preconditioned by the cycle from
+// level l down (launched levels, some of them Krylov-accelerated in turn, then
+// the LDS sub-cycle).  After the first pass (c1 = x): v1 = A_l c1,
+// rho1 = c1.v1, s1 = c1.r / rho1, r <- r - s1 v1; after the second (c2 = x):
+// gam = c2.v1, beta = c2.A_l c2, a2 = c2.r,
 // rho2 = beta - gam^2 / rho1, x = (s1 - gam a2 / (rho1 rho2)) c1 + (a2 / rho2) c2.
 // Vectors are in the level's primary layout; sums are FP64 partials per
 // workgroup, reduced in a fixed order by one workgroup.

@@ -90,12 +90,12 @@ def tune_grid(nx: int, ny: int, geom: int, x_faces, y_faces, bcs: Sequence, fiel
         kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
         g.bc[s].kind, g.bc[s].value = int(kind), float(value)
     best = fld_options()
-    entries = (fld_tune_entry * 64)()
+    entries = (fld_tune_entry * 128)()
     n = _I()
     f = fields
     st = lib.fld_tune(ctypes.byref(g), ctypes.byref(base), _ptr(f["E"]), _ptr(f["T"]), _ptr(f["rho"]),
                       _ptr(f["kappa_R"]), _ptr(f["kappa_P"]), _ptr(f["c_v"]), _ptr(f.get("ghost_E")), float(dt),
-                      int(reps), ctypes.byref(best), entries, 64, ctypes.byref(n), _stream_handle(stream))
+                      int(reps), ctypes.byref(best), entries, len(entries), ctypes.byref(n), _stream_handle(stream))
     if st != FLD_OK:
         raise FLDError(st, "no candidate configuration converged" if st == 4 else "fld_tune")
     table = _table(entries, n.value)

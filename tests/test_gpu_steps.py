@@ -102,15 +102,17 @@ def test_steps_budget_exhausted_is_reported(lib):
     assert infos[0]["status"] == 4
 
 
-def test_sweep_replay_measurement(lib):
-    """fld_profile_sweeps replays one V-cycle's line sweeps as a graph: it
-    needs an assembled context, counts every grid level's band launches (four
-    per level, levels above the LDS sub-cycle), reports positive times and
-    bytes, and leaves the next step equal to a step of a fresh context."""
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_sweep_replay_measurement(lib, use_graph):
+    """fld_profile_sweeps replays one V-cycle's line sweeps (as a graph, or
+    as plain launches in a context without graphs): it needs an assembled
+    context, counts every grid level's band launches (four per level, levels
+    above the LDS sub-cycle), selects level ranges, reports positive times
+    and bytes, and leaves the next step equal to a step of a fresh context."""
     fld = lib
     prob = W.make("c2", nx=256, ny=256)
     opt = dict(precision="mixed", norm=1, rel_tol=1e-11)
-    ctx = make_ctx(fld, prob, **opt)
+    ctx = make_ctx(fld, prob, use_graph=use_graph, **opt)
     with pytest.raises(fld.FLDError):
         ctx.profile_sweeps(2)
     t = to_dev(prob, torch)
@@ -120,6 +122,12 @@ def test_sweep_replay_measurement(lib):
     # 256^2 -> sub-cycle from 64^2: levels 256 and 128 on the grid, 4 band launches each
     assert r["launches"] == 8
     assert r["us_per_launch"] > 0.0 and r["bytes_per_launch"] > 0.0
+    fine, coarse = ctx.profile_sweeps(3, levels=1), ctx.profile_sweeps(3, first=1)
+    assert fine["launches"] == 4 and coarse["launches"] == 4
+    # the level of 128^2 cells moves a quarter of the bytes of the 256^2 level
+    assert coarse["bytes_per_launch"] == pytest.approx(fine["bytes_per_launch"] / 4, rel=0.05)
+    with pytest.raises(fld.FLDError):
+        ctx.profile_sweeps(2, first=2)  # the sub-cycle's levels are not launched
     t2 = to_dev(prob, torch)
     info = ctx.step(t2["E"], t2["T"], *args, check=False)
     torch.cuda.synchronize()

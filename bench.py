@@ -3,7 +3,8 @@
 Headline workload: the 4096 x 2048 spherical-polar stress recipe (r log-spaced
 1e11 .. 1e14 cm, theta 0 .. pi; lognormal opacity with sigma_ln 4, contrast
 1e8; c_v = 1e6, dt = 1e5 s), run as consecutive implicit steps through
-fld_steps (one step captured as a hipGraph and replayed, T updated from the
+fld_steps (steps queued back to back, CG iterations in captured two-slot
+chunks whose solver flags the host reads one chunk behind; T updated from the
 linearised exchange every step, opacities fixed).  One benchmark step = one
 implicit radiation step of that sequence (assembly, multigrid-preconditioned
 CG with FP32 inner iterations and FP64 reliable updates to a 1e-10 relative
@@ -11,12 +12,14 @@ residual in the Jacobi-scaled norm, gas update), inputs resident in HBM.
 The W warm-up steps run as one fld_steps call from the initial state; the K
 timed steps as one fld_steps call from the initial state again.  The whole
 100-step sequence is then run as one fld_steps call per precision (mixed and
-FP64, each on the faster of its two multigrid cycles, K and W2, chosen by a
-three-step probe), which gives time-to-1e-10 per step and the mixed/FP64
-ratio.  Prints one JSON line.
+FP64, each on the fastest of its multigrid cycles, KL_W2, KL_K, W2 and K,
+chosen by a three-step probe), which gives time-to-1e-10 per step and the
+mixed/FP64 ratio; the K timed steps are also run in FP64.  Prints one JSON
+line.
 
-Beyond the contract's fields: the dominant kernel's roofline (the finest
-level's zebra line half-sweeps, replayed between HIP events), the other
+Beyond the contract's fields: the dominant kernel's roofline (the coarse
+levels' band-fused line sweeps, replayed between HIP events, with the finest
+level's half-sweeps beside it), the other
 workloads (64 x 64 FP64 solves/s; 1024 x 1024 stretched Cartesian and
 2048 x 512 spherical steps, mixed, FP64 and FP32-only; 256 batched blocks),
 the relative L2 error of E and T against the CPU oracle per workload (full
@@ -663,8 +666,9 @@ def main():
         "dtype": {"mixed": "f32+f64", "fp64": "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": "c5: 4096x2048 spherical-polar stress recipe (lognormal kappa, contrast 1e8; "
-                               "c_v=1e6, dt=1e5 s), consecutive implicit FLD steps through fld_steps (one step "
-                               "captured as a hipGraph and replayed), part of its 100-step sequence; one "
+                               "c_v=1e6, dt=1e5 s), consecutive implicit FLD steps through fld_steps (steps queued "
+                               "back to back, CG iterations in captured two-slot chunks read one chunk behind "
+                               "by the host), part of its 100-step sequence; one "
                                "benchmark step = one implicit step to 1e-10",
                    "cells": ncell, "precision": prec, "rel_tol": 1e-10, "norm": "Jacobi-scaled",
                    "mg_cycle": cname[cyc], "cycle_probe": probe,

@@ -209,7 +209,8 @@ fld_status fld_assemble(fld_ctx* ctx, const double* E_r, const double* T_g, cons
 /* Solves the assembled system (Section 3.2.1 step 6).  E_new (device, nx*ny):
  * on entry the initial guess (e.g. E^n), on return E^{n+1}.  info (host) may be
  * NULL.  Synchronises the context's stream.  Returns ENOCONV / EBREAKDOWN /
- * ENONFINITE as described above (E_new then holds the last iterate). */
+ * ENONFINITE as described above (E_new then holds the last iterate), EINVAL
+ * on a context that has replayed fld_steps_graph. */
 fld_status fld_solve(fld_ctx* ctx, double* E_new, fld_solve_info* info);
 
 /* Gas update from the psi row (Section 3.2.1 psi_5, psi_6, psi_11):
@@ -219,39 +220,57 @@ fld_status fld_solve(fld_ctx* ctx, double* E_new, fld_solve_info* info);
 fld_status fld_gas_update(fld_ctx* ctx, const double* E_new, double* T_out);
 
 /* One implicit radiation step = assemble + solve + gas update.  E_r and T_g
- * are updated in place (device).  info may be NULL. */
+ * are updated in place (device).  info may be NULL.  EINVAL on a context that
+ * has replayed fld_steps_graph. */
 fld_status fld_step(fld_ctx* ctx, double* E_r, double* T_g, const double* rho, const double* kappa_R,
                     const double* kappa_P, const double* c_v, const double* ghost_E, double dt,
                     fld_solve_info* info);
 
 /* nsteps consecutive steps with (E, T) <- (E^{n+1}, T^{n+1}) and the opacities,
  * rho and c_v held fixed (Section 3.2.1 sub-step loop, one sub-step per step).
- * The first step runs as fld_step; its CG iteration count k1 fixes a budget
- * S = min(max_inner, even(2 k1 + 16)) iterations.  One whole step (assembly,
- * hierarchy, S iteration slots with device-side early exit, gas update, a
- * device-side status record) is then captured once as a hipGraph and replayed
- * for the remaining steps in segments of 1, 2, 4, then 8 launches; the host
- * reads the records once per segment.  If a step used up the budget, the
- * budget grows by half (up to max_inner), the step is re-captured and the
- * segment replays from the (E, T) saved at its start, segments restarting at
- * one step; if the budget exceeds 1.5 x even(k + max(4, k/4) + 2), k the
- * most iterations a step of the last segment took, it is cut to that value
- * and the step re-captured (unused slots cost their early-exit launches).  Results equal those of nsteps fld_step calls
- * whenever every step converges within max_inner.  A step that fails for
- * another reason (stagnation, breakdown) is recorded and, unlike fld_step,
- * its gas update and the following steps still run.  With profiling on or
- * use_graph = 0 the steps run as fld_step calls and stop at the first
- * failure.  The saved copy of E and T and the device step records of a
- * segment belong to the context (allocated by fld_create); the call itself
- * allocates no device memory.  per_step (host, nsteps entries) may be NULL;
- * a graph-launched step's ms is the mean over those launches.  Returns the
- * first non-OK step status. */
+ * Every step queues the kernels of fld_step (assembly, hierarchy, solve
+ * prologue, CG iterations, final correction, gas update) and a device-side
+ * status record, without fld_step's blocking synchronisations: the CG
+ * iterations run as a captured graph of two iteration slots with device-side
+ * early exit, launched repeatedly; after each launch the solver flags are
+ * copied to one of two pinned host mirrors, and the host reads a chunk's
+ * flags while the next chunk already runs, so the GPU never waits for the
+ * host and at most one chunk of early-exit slots follows convergence (the
+ * iteration limit is max_inner).  The host reads the step records once per 8
+ * steps.  Results equal those of nsteps fld_step calls bit for bit.  A step
+ * that fails (no convergence within max_inner, stagnation, breakdown,
+ * non-finite input) is recorded and, unlike fld_step, its gas update and the
+ * following steps still run.  With profiling on or use_graph = 0 the steps
+ * run as fld_step calls and stop at the first failure.  The pinned mirrors
+ * and the device step records belong to the context (allocated by
+ * fld_create); the call allocates no device memory.  per_step (host, nsteps
+ * entries) may be NULL; each step's ms is the mean over the call.  Returns
+ * the first non-OK step status; EINVAL on a context that has replayed
+ * fld_steps_graph (below). */
 fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                      const double* kappa_R, const double* kappa_P, const double* c_v,
                      const double* ghost_E, double dt, fld_solve_info* per_step);
 
-/* fld_steps under the name of its mechanism (one step captured as a hipGraph
- * and replayed); identical arguments and behaviour. */
+/* The same steps with one whole step captured as a hipGraph.  The first step
+ * runs as fld_step; its CG iteration count k1 fixes a budget
+ * S = min(max_inner, even(2 k1 + 16)) iterations.  One whole step (assembly,
+ * hierarchy, S iteration slots with device-side early exit, gas update, a
+ * device-side status record) is then captured once and replayed for the
+ * remaining steps in segments of 1, 2, 4, then 8 launches, with no host
+ * work inside a segment; the host reads the records once per segment.  If a
+ * step used up the budget, the budget grows by half (up to max_inner), the
+ * step is re-captured and the segment replays from the (E, T) saved at its
+ * start, segments restarting at one step; if the budget exceeds
+ * 1.5 x even(k + max(4, k/4) + 2), k the most iterations a step of the last
+ * segment took, it is cut to that value and the step re-captured.  Unused
+ * slots cost their early-exit launches, so on grids whose iterations are
+ * expensive fld_steps is faster (4096 x 2048 stress steps: 24.6 against
+ * 32.6 ms); results are the same bit for bit.  The saved copy of E and T
+ * belongs to the context.  Once a captured step has been replayed, the
+ * context serves only further fld_steps_graph calls: fld_step, fld_solve,
+ * fld_steps and fld_substep return EINVAL on it (runs of single steps on such
+ * a context ended in a host heap-corruption abort whose cause is not
+ * established).  Other arguments, records and return values as fld_steps. */
 fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E_r, double* T_g, const double* rho,
                            const double* kappa_R, const double* kappa_P, const double* c_v,
                            const double* ghost_E, double dt, fld_solve_info* per_step);

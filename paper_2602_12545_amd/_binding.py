@@ -234,6 +234,16 @@ class Context:
             self._check(st)
         return [infos[k].as_dict() for k in range(nsteps)]
 
+    def steps_graph(self, nsteps, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, check=True):
+        """fld_steps_graph: the steps after the first replay one captured step
+        graph (the context then serves only further steps_graph calls)."""
+        infos = (fld_solve_info * max(1, nsteps))()
+        st = lib.fld_steps_graph(self.handle, int(nsteps), _ptr(E), _ptr(T), _ptr(rho), _ptr(kappa_R),
+                                 _ptr(kappa_P), _ptr(c_v), _ptr(ghost_E), float(dt), infos)
+        if check:
+            self._check(st)
+        return [infos[k].as_dict() for k in range(nsteps)]
+
     def substep(self, E, T, rho, kappa_R, kappa_P, c_v, dt, ghost_E=None, n_sub=1, q=1.0, dbar=0.0,
                 max_sub=10000, check=True, Fx=None, Fy=None):
         """One step of length dt as sub-steps: the geometric series (n_sub, q)

@@ -144,6 +144,11 @@ struct fld_ctx {
     size_t npart = 0;
     Scalars* sc = nullptr;
     Scalars* hsc = nullptr;  // pinned mirror
+    Scalars* hsc2 = nullptr;     // second pinned mirror (pipelined multi-step: two chunks in flight)
+    hipEvent_t pev[2] = {nullptr, nullptr};  // their copies' completion
+    // a captured multi-step graph (fld_steps_graph) has been replayed on this
+    // context: host-driven solves on it are refused (see fld_solve)
+    bool replayed = false;
     int* err_flag = nullptr;
     int* herr = nullptr;     // pinned
     bool assembled = false;
@@ -1259,6 +1264,9 @@ void fld_destroy(fld_ctx* ctx) {
     for (void* p : ctx->allocs) (void)hipFree(p);
     if (ctx->hsc) (void)hipHostFree(ctx->hsc);
     if (ctx->herr) (void)hipHostFree(ctx->herr);
+    if (ctx->hsc2) (void)hipHostFree(ctx->hsc2);
+    for (hipEvent_t e : ctx->pev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->setup_stream) (void)hipStreamDestroy(ctx->setup_stream);
     if (ctx->setup_fork) (void)hipEventDestroy(ctx->setup_fork);
@@ -1374,7 +1382,13 @@ fld_status fld_create(fld_ctx** out, const fld_grid* grid, const fld_options* op
         return fail(FLD_ENOMEM, "pinned scalars");
     if (hipHostMalloc((void**)&ctx->herr, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(FLD_ENOMEM, "pinned flag");
+    if (hipHostMalloc((void**)&ctx->hsc2, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        return fail(FLD_ENOMEM, "pinned scalars");
     std::memset(ctx->hsc, 0, sizeof(Scalars));
+    std::memset(ctx->hsc2, 0, sizeof(Scalars));
+    if (hipEventCreateWithFlags(&ctx->pev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->pev[1], hipEventDisableTiming) != hipSuccess)
+        return fail(FLD_EHIP, "events");
     *ctx->herr = 0;
     if (hipStreamCreateWithFlags(&ctx->setup_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->setup_fork, hipEventDisableTiming) != hipSuccess ||
@@ -1411,11 +1425,32 @@ fld_status fld_assemble(fld_ctx* ctx, const double* E, const double* T, const do
     return FLD_OK;
 }
 
-fld_status fld_solve(fld_ctx* ctx, double* E, fld_solve_info* info) {
-    if (!ctx) return FLD_EINVAL;
+namespace {
+
+fld_status solve_checked(fld_ctx* ctx, double* E, fld_solve_info* info) {
     if (!E) { ctx->err = "null E"; return FLD_EINVAL; }
     if (!ctx->assembled) { ctx->err = "fld_assemble first"; return FLD_ENOTREADY; }
     return inner_is_float(ctx) ? solve_impl<float>(ctx, E, info) : solve_impl<double>(ctx, E, info);
+}
+
+// Host-driven solves after a replayed multi-step graph are refused: on the
+// 4096 x 2048 grid and on the 1024 x 1024 grid, runs of single steps on a
+// context that had replayed fld_steps_graph's captured step ended with a host
+// heap-corruption abort whose cause is not established.
+fld_status refuse_after_replay(fld_ctx* ctx) {
+    if (!ctx->replayed) return FLD_OK;
+    ctx->err = "this context has replayed a captured multi-step graph (fld_steps_graph); it serves further "
+               "fld_steps_graph calls only: use another context for single steps";
+    return FLD_EINVAL;
+}
+
+}  // namespace
+
+fld_status fld_solve(fld_ctx* ctx, double* E, fld_solve_info* info) {
+    if (!ctx) return FLD_EINVAL;
+    fld_status g = refuse_after_replay(ctx);
+    if (g != FLD_OK) return g;
+    return solve_checked(ctx, E, info);
 }
 
 fld_status fld_gas_update(fld_ctx* ctx, const double* E, double* Tout) {
@@ -1428,17 +1463,132 @@ fld_status fld_gas_update(fld_ctx* ctx, const double* E, double* Tout) {
     return FLD_OK;
 }
 
-fld_status fld_step(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
-                    const double* cv, const double* ghost, double dt, fld_solve_info* info) {
+}  // extern "C"
+
+namespace {
+
+// assembly, solve and gas update without the replay guard
+fld_status step_internal(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
+                         const double* cv, const double* ghost, double dt, fld_solve_info* info) {
     fld_status s = fld_assemble(ctx, E, T, rho, kR, kP, cv, ghost, dt);
     if (s != FLD_OK) return s;
-    s = fld_solve(ctx, E, info);
+    s = solve_checked(ctx, E, info);
     if (s != FLD_OK) return s;
     return fld_gas_update(ctx, E, T);
 }
 
+// nsteps steps queued back to back with the kernels of fld_step, without its
+// blocking synchronisations: the CG iterations run as captured two-slot
+// chunks, and the host reads a chunk's solver flags (an asynchronous copy to
+// one of two pinned mirrors, then its event) while the next chunk already
+// runs, so the GPU never waits for the host and at most one chunk of
+// early-exit slots follows convergence.  The next step is queued as soon as
+// its predecessor's iterations are known to be done; records are read once
+// per kStepSeg steps.
+template <typename T>
+fld_status steps_pipelined(fld_ctx* ctx, int32_t nsteps, double* E, double* Tg, const double* rho, const double* kR,
+                           const double* kP, const double* cv, const double* ghost, double dt,
+                           fld_solve_info* per_step) {
+    Inner<T>& in = inner<T>(ctx);
+    hipStream_t st = ctx->stream;
+    const fld_options& o = ctx->opt;
+    const int n = ctx->nx * ctx->ny;
+    constexpr int kChunk = 2;  // even: the p buffers alternate within a chunk
+    const double delta = o.precision == FLD_MIXED ? 0.01 : 1e-3;
+    Scalars* mirror[2] = {ctx->hsc, ctx->hsc2};
+    const int max_chunks = (o.max_inner + kChunk - 1) / kChunk + 1;
+    auto launch = [&](int c) -> bool {
+        return hipGraphLaunch(in.chunk_exec, st) == hipSuccess &&
+               hipMemcpyAsync(mirror[c & 1], ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipEventRecord(ctx->pev[c & 1], st) == hipSuccess;
+    };
+    std::vector<fld_solve_info> h(nsteps);
+    auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < nsteps;) {
+        const int m = std::min(kStepSeg, nsteps - k);
+        k_zero_int<<<1, 1, 0, st>>>(ctx->seg_count);
+        for (int q = 0; q < m; ++q) {
+            fld_status as = enqueue_assemble(ctx, E, Tg, rho, kR, kP, cv, ghost, dt, st);
+            if (as != FLD_OK) return as;
+            k_init_scalars<<<1, 1, 0, st>>>(ctx->sc, o.rel_tol, delta * delta, o.inner_rtol * o.inner_rtol,
+                                            o.max_inner, o.norm, o.precision == FLD_FP32 ? 0 : 1);
+            enqueue_check<T>(ctx, in, E, 1, st);
+            enqueue_vcycle<T>(ctx, in, st);
+            // captured after the prologue's V-cycle has been queued: the chunk's
+            // SpMV takes the number of r.z partials that cycle leaves
+            fld_status gs = capture_chunk<T>(ctx, in, E, kChunk);
+            if (gs != FLD_OK) return gs;
+            bool ok = launch(0);
+            for (int c = 0; ok; ++c) {
+                const bool more = c + 1 < max_chunks;
+                if (more && !launch(c + 1)) ok = false;
+                else if (hipEventSynchronize(ctx->pev[c & 1]) != hipSuccess) ok = false;
+                else if (mirror[c & 1]->done || !more) break;
+            }
+            if (!ok) {
+                ctx->err = "pipelined steps: chunk launch or flag read failed";
+                return FLD_EHIP;
+            }
+            k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
+            k_gas_update<<<grid1d(n), 256, 0, st>>>(n, E, Tg, rho, kP, ctx->cv, dt, Tg);
+            k_record_step<<<1, 1, 0, st>>>(ctx->sc, ctx->err_flag, ctx->seg_count, kStepSeg, (void*)ctx->seg_info,
+                                           (int)ctx->h64.size());
+            HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(h.data() + k, ctx->seg_info, sizeof(fld_solve_info) * m, hipMemcpyDeviceToHost));
+        k += m;
+    }
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ctx->assembled = true;
+    fld_status firstbad = FLD_OK;
+    for (int q = 0; q < nsteps; ++q) {
+        h[q].ms = ms / nsteps;
+        if (per_step) per_step[q] = h[q];
+        if (h[q].status != FLD_OK && firstbad == FLD_OK) firstbad = (fld_status)h[q].status;
+    }
+    return firstbad;
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_step(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
+                    const double* cv, const double* ghost, double dt, fld_solve_info* info) {
+    if (!ctx) return FLD_EINVAL;
+    fld_status g = refuse_after_replay(ctx);
+    if (g != FLD_OK) return g;
+    return step_internal(ctx, E, T, rho, kR, kP, cv, ghost, dt, info);
+}
+
 fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
                      const double* kP, const double* cv, const double* ghost, double dt, fld_solve_info* per_step) {
+    if (!ctx) return FLD_EINVAL;
+    if (nsteps < 0) { ctx->err = "nsteps < 0"; return FLD_EINVAL; }
+    fld_status g = refuse_after_replay(ctx);
+    if (g != FLD_OK) return g;
+    if (nsteps == 0) return FLD_OK;
+    fld_status s = check_fields(ctx, E, T, rho, kR, kP, cv, ghost, dt);
+    if (s != FLD_OK) return s;
+    if (ctx->prof.on || !ctx->opt.use_graph) {
+        // measured (events cannot be timed inside graphs) or graphs disabled:
+        // fld_step calls, stopping at the first failure
+        for (int k = 0; k < nsteps; ++k) {
+            fld_solve_info inf{};
+            fld_status sk = step_internal(ctx, E, T, rho, kR, kP, cv, ghost, dt, &inf);
+            if (per_step) per_step[k] = inf;
+            if (sk != FLD_OK) return sk;
+        }
+        return FLD_OK;
+    }
+    return inner_is_float(ctx) ? steps_pipelined<float>(ctx, nsteps, E, T, rho, kR, kP, cv, ghost, dt, per_step)
+                               : steps_pipelined<double>(ctx, nsteps, E, T, rho, kR, kP, cv, ghost, dt, per_step);
+}
+
+fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
+                           const double* kP, const double* cv, const double* ghost, double dt,
+                           fld_solve_info* per_step) {
     if (!ctx) return FLD_EINVAL;
     if (nsteps < 0) { ctx->err = "nsteps < 0"; return FLD_EINVAL; }
     if (nsteps == 0) return FLD_OK;
@@ -1446,14 +1596,14 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     if (s != FLD_OK) return s;
     // step 1, host-driven: measures the iteration count that sizes the budget
     fld_solve_info first{};
-    fld_status s1 = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, &first);
+    fld_status s1 = step_internal(ctx, E, T, rho, kR, kP, cv, ghost, dt, &first);
     if (per_step) per_step[0] = first;
     if (s1 != FLD_OK || nsteps == 1) return s1;
     if (ctx->prof.on || !ctx->opt.use_graph) {
         // measured (events cannot be timed inside graphs) or graphs disabled
         for (int k = 1; k < nsteps; ++k) {
             fld_solve_info inf{};
-            fld_status sk = fld_step(ctx, E, T, rho, kR, kP, cv, ghost, dt, &inf);
+            fld_status sk = step_internal(ctx, E, T, rho, kR, kP, cv, ghost, dt, &inf);
             if (per_step) per_step[k] = inf;
             if (sk != FLD_OK) return sk;
         }
@@ -1523,6 +1673,7 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
             st = FLD_EHIP;
             break;
         }
+        ctx->replayed = true;
         for (int q = 0; q < m && st == FLD_OK; ++q)
             if (hipGraphLaunch(ge, ctx->stream) != hipSuccess) st = FLD_EHIP;
         if (st != FLD_OK || hipStreamSynchronize(ctx->stream) != hipSuccess ||
@@ -1573,18 +1724,14 @@ fld_status fld_steps(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const d
     return firstbad;
 }
 
-fld_status fld_steps_graph(fld_ctx* ctx, int32_t nsteps, double* E, double* T, const double* rho, const double* kR,
-                           const double* kP, const double* cv, const double* ghost, double dt,
-                           fld_solve_info* per_step) {
-    return fld_steps(ctx, nsteps, E, T, rho, kR, kP, cv, ghost, dt, per_step);
-}
-
 fld_status fld_substep(fld_ctx* ctx, double* E, double* T, const double* rho, const double* kR, const double* kP,
                        const double* cv, const double* ghost, double dt, int32_t n_sub, double q, double dbar,
                        int32_t max_sub, double* dts, fld_solve_info* per_sub, int32_t* n_done, double* Fx,
                        double* Fy) {
     if (!ctx) return FLD_EINVAL;
     if (n_done) *n_done = 0;
+    fld_status g = refuse_after_replay(ctx);
+    if (g != FLD_OK) return g;
     if (max_sub < 1) { ctx->err = "max_sub must be >= 1"; return FLD_EINVAL; }
     if (!(dbar >= 0.0) || !std::isfinite(dbar)) { ctx->err = "dbar must be finite and >= 0"; return FLD_EINVAL; }
     if (dbar == 0.0 && (n_sub < 1 || n_sub > max_sub || !(q > 0.0) || !std::isfinite(q))) {

@@ -1,6 +1,8 @@
-"""Multi-step runs (Section 3.2.1 sub-step loop): fld_steps, whose steps after
-the first replay one captured hipGraph, against repeated fld_step calls
-(bit-identical) and against the FP64 oracle stepped the same number of times."""
+"""Multi-step runs (Section 3.2.1 sub-step loop): fld_steps (steps queued back
+to back, iterations in captured chunks read ahead by the host) and
+fld_steps_graph (steps after the first replay one captured hipGraph), against
+repeated fld_step calls (bit-identical) and against the FP64 oracle stepped
+the same number of times."""
 import numpy as np
 import pytest
 
@@ -19,7 +21,9 @@ def _run(fld, torch, prob, nsteps, multi, profile=False, **opt):
     args = (t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"])
     if profile:
         ctx.profile(True)
-    if multi:
+    if multi == "graph":
+        infos = ctx.steps_graph(nsteps, t["E"], t["T"], *args, check=False)
+    elif multi:
         infos = ctx.steps(nsteps, t["E"], t["T"], *args, check=False)
     else:
         infos = [ctx.step(t["E"], t["T"], *args, check=False) for _ in range(nsteps)]
@@ -37,17 +41,21 @@ def _oracle_steps(prob, nsteps):
     return E, T
 
 
-@pytest.mark.parametrize("name,kw,prec,norm", [
-    ("c1", dict(nx=48, ny=40), "mixed", 0),
-    ("c2", dict(nx=70, ny=52), "fp64", 0),
-    ("c5", dict(nx=96, ny=64), "mixed", 1),
+@pytest.mark.parametrize("mode", ["steps", "graph"])
+@pytest.mark.parametrize("name,kw,prec,norm,cyc", [
+    ("c1", dict(nx=48, ny=40), "mixed", 0, 1),
+    ("c2", dict(nx=70, ny=52), "fp64", 0, 1),
+    ("c5", dict(nx=96, ny=64), "mixed", 1, 1),
+    ("c5", dict(nx=512, ny=256), "mixed", 1, 4),
+    ("c5", dict(nx=512, ny=256), "fp64", 1, 3),
 ])
-def test_steps_equal_repeated_step(lib, name, kw, prec, norm):
+def test_steps_equal_repeated_step(lib, name, kw, prec, norm, cyc, mode):
     fld = lib
     prob = W.make(name, **kw)
-    opt = dict(precision=prec, norm=norm, rel_tol=1e-11)
+    print(f"[steps] {name} {prob.nx}x{prob.ny} {prec} cycle {cyc} {mode}", flush=True)
+    opt = dict(precision=prec, norm=norm, rel_tol=1e-11, mg_cycle=cyc, mg_coarse_max=256)
     E1, T1, i1 = _run(fld, torch, prob, 6, multi=False, **opt)
-    E2, T2, i2 = _run(fld, torch, prob, 6, multi=True, **opt)
+    E2, T2, i2 = _run(fld, torch, prob, 6, multi=mode, **opt)
     assert [i["status"] for i in i2] == [0] * 6
     assert [i["inner_iters"] for i in i1] == [i["inner_iters"] for i in i2]
     assert np.array_equal(E1, E2) and np.array_equal(T1, T2)
@@ -137,8 +145,9 @@ def test_sweep_replay_measurement(lib, use_graph):
     assert np.array_equal(t2["E"].cpu().numpy(), E_ref) and np.array_equal(t2["T"].cpu().numpy(), T_ref)
 
 
-def test_steps_graph_alias(lib):
-    """fld_steps_graph is fld_steps under its other name: bit-identical."""
+def test_steps_graph_equals_steps(lib):
+    """The captured form (fld_steps_graph, called through the C ABI) and the
+    pipelined form give the same fields bit for bit."""
     import ctypes
     from paper_2602_12545_amd import _binding as B
     prob = W.make("c1", nx=40, ny=32)
@@ -153,3 +162,27 @@ def test_steps_graph_alias(lib):
     ctx.close()
     assert st == 0 and [infos[k].status for k in range(4)] == [0] * 4
     assert np.array_equal(t["E"].cpu().numpy(), E1) and np.array_equal(t["T"].cpu().numpy(), T1)
+
+
+def test_host_driven_solves_refused_after_graph_replay(lib):
+    """Once fld_steps_graph has replayed its captured step on a context, the
+    host-driven entry points (fld_step, fld_solve, fld_steps, fld_substep)
+    refuse it with EINVAL before any device work; further fld_steps_graph
+    calls still run."""
+    fld = lib
+    prob = W.make("c1", nx=24, ny=20)
+    ctx = make_ctx(fld, prob, precision="mixed")
+    t = to_dev(prob, torch)
+    args = (t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt, t["ghost_E"])
+    ctx.steps_graph(1, t["E"], t["T"], *args)     # the first step runs host-driven: no replay yet
+    ctx.step(t["E"], t["T"], *args)
+    ctx.steps_graph(3, t["E"], t["T"], *args)
+    for call in (lambda: ctx.step(t["E"], t["T"], *args), lambda: ctx.steps(2, t["E"], t["T"], *args),
+                 lambda: ctx.solve(t["E"]), lambda: ctx.substep(t["E"], t["T"], *args, n_sub=2)):
+        with pytest.raises(fld.FLDError) as e:
+            call()
+        assert e.value.status == fld.FLD_EINVAL and "fld_steps_graph" in str(e.value)
+    infos = ctx.steps_graph(2, t["E"], t["T"], *args)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert [i["status"] for i in infos] == [0, 0]

@@ -149,6 +149,7 @@ struct fld_ctx {
     // a captured multi-step graph (fld_steps_graph) has been replayed on this
     // context: host-driven solves on it are refused (see fld_solve)
     bool replayed = false;
+    int last_iters = 0;          // CG iterations of the last host-driven solve (read-ahead prediction)
     int* err_flag = nullptr;
     int* herr = nullptr;     // pinned
     bool assembled = false;
@@ -879,6 +880,42 @@ fld_status capture_chunk(fld_ctx* ctx, Inner<T>& in, double* E, int chunk) {
     return FLD_OK;
 }
 
+// CG iterations as launches of the captured chunk graph (chunk slots each),
+// the solver state copied after every launch to one of two pinned mirrors.
+// While the predicted iteration count (the last solve's, 0 if unknown) lies
+// beyond the chunk being waited for, the next chunk is queued before the host
+// reads that chunk's flags, so the GPU does not idle on the host; near the
+// predicted end the host reads first and queues only what is still needed,
+// so no chunk of early-exit slots is left to run.  Returns false on a HIP
+// error.
+template <typename T>
+bool run_chunks(fld_ctx* ctx, Inner<T>& in, int chunk, int max_iter, int predict, hipStream_t st) {
+    Scalars* mirror[2] = {ctx->hsc, ctx->hsc2};
+    const int max_chunks = (max_iter + chunk - 1) / chunk + 1;
+    auto launch = [&](int c) -> bool {
+        return hipGraphLaunch(in.chunk_exec, st) == hipSuccess &&
+               hipMemcpyAsync(mirror[c & 1], ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipEventRecord(ctx->pev[c & 1], st) == hipSuccess;
+    };
+    if (!launch(0)) return false;
+    int queued = 1;
+    for (int c = 0;; ++c) {
+        if (queued == c + 1 && c + 1 < max_chunks && predict > (c + 1) * chunk) {
+            if (!launch(c + 1)) return false;
+            ++queued;
+        }
+        if (hipEventSynchronize(ctx->pev[c & 1]) != hipSuccess) return false;
+        if (mirror[c & 1]->done || c + 1 >= max_chunks) {
+            ctx->last_iters = mirror[c & 1]->iter;
+            return true;
+        }
+        if (queued == c + 1) {
+            if (!launch(c + 1)) return false;
+            ++queued;
+        }
+    }
+}
+
 template <typename T>
 fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     auto t0 = std::chrono::steady_clock::now();
@@ -898,6 +935,41 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
     enqueue_check<T>(ctx, in, E, 1, st);
     enqueue_vcycle<T>(ctx, in, st);
     HIPCHK(hipGetLastError());
+    const int chunk = o.chunk;
+    // events recorded inside a captured graph cannot be timed on this runtime,
+    // so measured solves queue plain launches
+    const bool graph = o.use_graph != 0 && !ctx->prof.on;
+    if (graph) {
+        // captured chunks, read ahead while the last solve's iteration count
+        // says more are needed (run_chunks); a non-finite input is reported
+        // after the solve
+        fld_status gs = capture_chunk<T>(ctx, in, E, chunk);
+        if (gs != FLD_OK) return gs;
+        if (!run_chunks<T>(ctx, in, chunk, max_iter, ctx->last_iters, st)) {
+            ctx->err = "solve: chunk launch or flag read failed";
+            return FLD_EHIP;
+        }
+    } else {
+        HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ctx->herr, ctx->err_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (*ctx->herr) {
+            ctx->err = "non-finite or out-of-domain input field";
+            fill_info(ctx, info, FLD_ENONFINITE, 0.f);
+            return FLD_ENONFINITE;
+        }
+        if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
+        int launched = 0;
+        while (!ctx->hsc->done && launched < max_iter + chunk) {
+            for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, (launched + k) & 1, E, st);
+            launched += chunk;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
+        }
+    }
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1, ctx->err_flag);
     HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(ctx->herr, ctx->err_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -906,31 +978,6 @@ fld_status solve_impl(fld_ctx* ctx, double* E, fld_solve_info* info) {
         fill_info(ctx, info, FLD_ENONFINITE, 0.f);
         return FLD_ENONFINITE;
     }
-    const int chunk = o.chunk;
-    // events recorded inside a captured graph cannot be timed on this runtime,
-    // so measured solves queue plain launches
-    const bool graph = o.use_graph != 0 && !ctx->prof.on;
-    if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
-    if (graph) {
-        fld_status gs = capture_chunk<T>(ctx, in, E, chunk);
-        if (gs != FLD_OK) return gs;
-    }
-    int launched = 0;
-    while (!ctx->hsc->done && launched < max_iter + chunk) {
-        if (graph) {
-            HIPCHK(hipGraphLaunch(in.chunk_exec, st));
-        } else {
-            for (int k = 0; k < chunk; ++k) enqueue_slot<T>(ctx, in, (launched + k) & 1, E, st);
-        }
-        launched += chunk;
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (prof_harvest(ctx) != FLD_OK) return FLD_EHIP;
-    }
-    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
-    HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
     int status = ctx->hsc->status;
     if (status == ST_OK && !ctx->hsc->done) status = FLD_ENOCONV;
     const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -999,7 +1046,7 @@ void enqueue_solve_fixed(fld_ctx* ctx, double* E, int slots, hipStream_t st) {
     enqueue_check<T>(ctx, in, E, 1, st);
     enqueue_vcycle<T>(ctx, in, st);
     for (int k = 0; k < slots; ++k) enqueue_slot<T>(ctx, in, k & 1, E, st);
-    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
+    k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1, ctx->err_flag);
 }
 
 }  // namespace
@@ -1495,13 +1542,6 @@ fld_status steps_pipelined(fld_ctx* ctx, int32_t nsteps, double* E, double* Tg, 
     const int n = ctx->nx * ctx->ny;
     constexpr int kChunk = 2;  // even: the p buffers alternate within a chunk
     const double delta = o.precision == FLD_MIXED ? 0.01 : 1e-3;
-    Scalars* mirror[2] = {ctx->hsc, ctx->hsc2};
-    const int max_chunks = (o.max_inner + kChunk - 1) / kChunk + 1;
-    auto launch = [&](int c) -> bool {
-        return hipGraphLaunch(in.chunk_exec, st) == hipSuccess &&
-               hipMemcpyAsync(mirror[c & 1], ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess &&
-               hipEventRecord(ctx->pev[c & 1], st) == hipSuccess;
-    };
     std::vector<fld_solve_info> h(nsteps);
     auto t0 = std::chrono::steady_clock::now();
     for (int k = 0; k < nsteps;) {
@@ -1518,18 +1558,13 @@ fld_status steps_pipelined(fld_ctx* ctx, int32_t nsteps, double* E, double* Tg, 
             // SpMV takes the number of r.z partials that cycle leaves
             fld_status gs = capture_chunk<T>(ctx, in, E, kChunk);
             if (gs != FLD_OK) return gs;
-            bool ok = launch(0);
-            for (int c = 0; ok; ++c) {
-                const bool more = c + 1 < max_chunks;
-                if (more && !launch(c + 1)) ok = false;
-                else if (hipEventSynchronize(ctx->pev[c & 1]) != hipSuccess) ok = false;
-                else if (mirror[c & 1]->done || !more) break;
-            }
-            if (!ok) {
+            // each step predicted by the one before (the relaxing sequences
+            // this serves change their counts slowly)
+            if (!run_chunks<T>(ctx, in, kChunk, o.max_inner, ctx->last_iters, st)) {
                 ctx->err = "pipelined steps: chunk launch or flag read failed";
                 return FLD_EHIP;
             }
-            k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1);
+            k_correct<T><<<grid1d(n), 256, 0, st>>>(n, E, in.x, ctx->sc, 1, ctx->err_flag);
             k_gas_update<<<grid1d(n), 256, 0, st>>>(n, E, Tg, rho, kP, ctx->cv, dt, Tg);
             k_record_step<<<1, 1, 0, st>>>(ctx->sc, ctx->err_flag, ctx->seg_count, kStepSeg, (void*)ctx->seg_info,
                                            (int)ctx->h64.size());

@@ -831,10 +831,13 @@ __global__ __launch_bounds__(256) void k_update(int n, T* __restrict__ x, T* __r
 // FP64 refinement
 // ---------------------------------------------------------------------------
 
-// E += (gamma / mu) x; x = 0.
+// E += (gamma / mu) x; x = 0.  Skipped when the assembly flagged a
+// non-finite input (err), which leaves E as it entered the solve.
 template <typename T>
 __global__ __launch_bounds__(256) void k_correct(int n, double* __restrict__ E, T* __restrict__ x,
-                                                 const Scalars* __restrict__ sc, int force) {
+                                                 const Scalars* __restrict__ sc, int force,
+                                                 const int* __restrict__ err) {
+    if (*err) return;
     if (!force && (sc->done || !sc->pending)) return;
     const double g = sc->corr;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {

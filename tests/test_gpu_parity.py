@@ -129,9 +129,11 @@ def test_invalid_inputs(lib):
     ctx = make_ctx(lib, prob)
     t = to_dev(prob, torch)
     t["rho"][3, 4] = float("nan")
+    E0 = t["E"].clone()
     ctx.assemble(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], prob.dt)
     info = ctx.solve(t["E"], check=False)
     assert info["status"] == lib.FLD_ENONFINITE
+    assert torch.equal(t["E"], E0)  # the flagged solve leaves E as it entered
     with pytest.raises(lib.FLDError):
         ctx.assemble(t["E"], t["T"], t["rho"], t["kappa_R"], t["kappa_P"], t["c_v"], -1.0)
     ctx.close()

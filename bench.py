@@ -98,7 +98,7 @@ def kernel_source_digest():
         src = re.sub(r"//[^\n]*", "", src)
         return re.sub(r"\s+", "", src)
 
-    for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_mg.hpp", "fld_band.hpp"):
+    for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_mg.hpp", "fld_sub.hpp", "fld_band.hpp"):
         h.update(f.encode())
         h.update(clean(open(os.path.join(d, f)).read()).encode())
     host = open(os.path.join(d, "fld_host.hip")).read()

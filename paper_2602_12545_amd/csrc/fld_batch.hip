@@ -42,6 +42,7 @@ struct fld_batch {
     int* dacc = nullptr;  // first non-OK status of each block over a multi-step call
     int threads = 512;
     double clock_khz = 1e5;
+    size_t lds = 0;  // dynamic LDS of a launch (batch_lds of the largest level pool)
 
     template <typename U>
     hipError_t alloc(U** ptr, size_t count) {
@@ -78,10 +79,20 @@ BOpts make_opts(const fld_options& o, double clock_khz) {
     return r;
 }
 
+// Dynamic LDS a block may use on this device (the kernel's static shared
+// variables take the rest).
+size_t lds_budget() {
+    int dev = 0, lds = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds = 65536;
+    return (size_t)lds - 2048;
+}
+
 template <typename T, int NT>
 hipError_t set_lds() {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<T, NT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)BLds<T, NT>::bytes);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_budget());
 }
 
 template <typename T, int NT>
@@ -90,7 +101,7 @@ void launch_t(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
                static_cast<T*>(b->lm), static_cast<T*>(b->lWe), static_cast<T*>(b->lWn),
                static_cast<T*>(b->lx), static_cast<T*>(b->lb),
                static_cast<T*>(b->xi), static_cast<T*>(b->p), static_cast<T*>(b->q)};
-    k_batch_step<T, NT><<<b->nb, NT, BLds<T, NT>::bytes, st>>>(b->db, f, w, make_opts(b->opt, b->clock_khz), info);
+    k_batch_step<T, NT><<<b->nb, NT, b->lds, st>>>(b->db, f, w, make_opts(b->opt, b->clock_khz), info);
 }
 
 template <typename T>
@@ -166,6 +177,32 @@ bool block_levels(BBlock& B, int coarse_max, long long& lo) {
     }
     B.nlev = L;
     return true;
+}
+
+// LDS bytes of a block's levels from l down in the sub-cycle layout: five
+// arrays per level at pitch nx + 1, the coarsest right-hand side, and one
+// partial per thread of the widest workgroup (1024).
+size_t sub_pool_bytes(const BBlock& B, int l, size_t ts) {
+    size_t e = 0;
+    for (int k = l; k < B.nlev; ++k) e += 5 * (size_t)(B.lnx[k] + 1) * B.lny[k];
+    e += (size_t)B.lnx[B.nlev - 1] * B.lny[B.nlev - 1] + 1024;
+    return e * ts;
+}
+
+// The finest level l >= 1 above the coarsest whose LDS pool fits `room`
+// bytes (0: the block keeps every level in global memory).
+int pick_sub(const BBlock& B, size_t ts, size_t room) {
+    for (int l = 1; l + 1 < B.nlev; ++l)
+        if (sub_pool_bytes(B, l, ts) <= room) return l;
+    return 0;
+}
+
+// Dynamic LDS of the batch kernel: reductions, the coarsest inverse, and the
+// union of the Gauss-Jordan workspace and the largest LDS level pool.
+template <typename T>
+size_t batch_lds(size_t pool) {
+    using Lay = BLds<T, 512>;
+    return Lay::uni + std::max(Lay::gj, pool);
 }
 
 // Metric and face arrays of one block, carved from q0 (metric_doubles(nx, ny)
@@ -256,6 +293,18 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
         if (!block_levels(B, o.mg_coarse_max, lo)) return fail(FLD_EINVAL, "too many multigrid levels");
     }
     b->nlev = lo;
+    {
+        const size_t ts = inner_float(b) ? sizeof(float) : sizeof(double);
+        const size_t uni = inner_float(b) ? BLds<float, 512>::uni : BLds<double, 512>::uni;
+        const size_t budget = lds_budget();
+        const size_t room = budget > uni ? budget - uni : 0;
+        size_t pool = 0;
+        for (BBlock& B : b->hb) {
+            B.sub = pick_sub(B, ts, room);
+            if (B.sub > 0) pool = std::max(pool, sub_pool_bytes(B, B.sub, ts));
+        }
+        b->lds = inner_float(b) ? batch_lds<float>(pool) : batch_lds<double>(pool);
+    }
 #define BALLOC(p, cnt) \
     if (b->alloc(&(p), (size_t)(cnt)) != hipSuccess) return fail(FLD_ENOMEM, "hipMalloc " #p)
     BALLOC(b->We, nc); BALLOC(b->Wn, nc); BALLOC(b->m, nc); BALLOC(b->rhs, nc); BALLOC(b->s, nc);
@@ -525,6 +574,13 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
     if (!block_levels(B, o.mg_coarse_max, lo)) { t_create_err = "too many multigrid levels"; return FLD_EINVAL; }
     const size_t n = (size_t)nx * ny;
     const size_t ts = o.precision != FLD_FP64 ? sizeof(float) : sizeof(double);
+    const size_t uni = ts == sizeof(float) ? BLds<float, 512>::uni : BLds<double, 512>::uni;
+    {
+        const size_t budget = lds_budget();
+        B.sub = pick_sub(B, ts, budget > uni ? budget - uni : 0);
+    }
+    const size_t pool = B.sub > 0 ? sub_pool_bytes(B, B.sub, ts) : 0;
+    const size_t lds = ts == sizeof(float) ? batch_lds<float>(pool) : batch_lds<double>(pool);
     const size_t nm = (size_t)metric_doubles(nx, ny);
     const size_t need = align256(sizeof(BBlock)) + align256(sizeof(BInfo)) + align256(nm * sizeof(double)) +
                         6 * align256(n * sizeof(double)) + 5 * align256((size_t)lo * ts) + 3 * align256(n * ts);
@@ -570,13 +626,13 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
                        static_cast<float*>(lv[0]), static_cast<float*>(lv[1]), static_cast<float*>(lv[2]),
                        static_cast<float*>(lv[3]), static_cast<float*>(lv[4]),
                        static_cast<float*>(vec[0]), static_cast<float*>(vec[1]), static_cast<float*>(vec[2])};
-        k_batch_step<float, 512><<<1, 512, BLds<float, 512>::bytes, st>>>(db, f, w, bo, dinfo);
+        k_batch_step<float, 512><<<1, 512, lds, st>>>(db, f, w, bo, dinfo);
     } else {
         BWork<double> w{w64[0], w64[1], w64[2], w64[3], w64[4], w64[5],
                         static_cast<double*>(lv[0]), static_cast<double*>(lv[1]), static_cast<double*>(lv[2]),
                         static_cast<double*>(lv[3]), static_cast<double*>(lv[4]),
                         static_cast<double*>(vec[0]), static_cast<double*>(vec[1]), static_cast<double*>(vec[2])};
-        k_batch_step<double, 512><<<1, 512, BLds<double, 512>::bytes, st>>>(db, f, w, bo, dinfo);
+        k_batch_step<double, 512><<<1, 512, lds, st>>>(db, f, w, bo, dinfo);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -12,6 +12,7 @@
 
 #include "fld_kernels.hpp"
 #include "fld_line.hpp"
+#include "fld_sub.hpp"
 
 namespace fld {
 
@@ -23,6 +24,7 @@ constexpr int kBRedDoubles = 128;  // reduction scratch (5 sums x 16 waves)
 
 struct BBlock {
     int nx, ny, nlev, id;          // id: index of the block in the caller's order
+    int sub;                       // first level held in LDS for the whole step (0: none)
     long long off, goff;           // first cell / first ghost value in the packed arrays
     long long loff[kBMaxLev];      // first cell of each level in the packed level arrays
     int lnx[kBMaxLev], lny[kBMaxLev];
@@ -287,15 +289,25 @@ __device__ __attribute__((noinline)) void b_coarse_solve(int n, const T* ainv, c
 // its x array.  Pre-smoothing: rows (even, odd), columns (even, odd); the
 // coarse correction (piecewise constant) is added, then post-smoothing runs in
 // the reverse order, so the preconditioner is symmetric.
+// The LDS levels' V-cycle as a function of its own (not inlined into
+// b_vcycle: each keeps its own register budget).
 template <typename T, int NT>
-__device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, const T* ainv) {
+__device__ __attribute__((noinline)) void b_sub_vcycle(const SubCycle<T>& S, T* pool) {
+    sub_vcycle<T, NT>(S, pool);
+}
+
+template <typename T, int NT>
+__device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, const T* ainv,
+                                                   const SubCycle<T>* S, T* pool) {
     const int Lv = B.nlev;
     if (Lv == 1) {
         const long long o = B.loff[0];
         b_coarse_solve<T, NT>(B.lnx[0] * B.lny[0], ainv, w.lb + o, w.lx + o);
         return;
     }
-    for (int l = 0; l < Lv - 1; ++l) {
+    // levels from Ls down run in LDS (S), or only the coarsest is solved
+    const int Ls = S ? B.sub : Lv - 1;
+    for (int l = 0; l < Ls; ++l) {
         const int nx = B.lnx[l], ny = B.lny[l];
         const long long o = B.loff[l], oc = B.loff[l + 1];
         const T *m = w.lm + o, *We = w.lWe + o, *Wn = w.lWn + o, *b = w.lb + o;
@@ -307,11 +319,24 @@ __device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, 
         b_restrict<T, NT>(nx, ny, m, We, Wn, b, x, w.lb + oc, B.lnx[l + 1], B.lny[l + 1]);
         __syncthreads();
     }
-    {
+    if (S) {
+        // the restricted residual into the LDS level, its V-cycle there, and
+        // the correction back for the prolongation above
+        const SubLevel<T>& L0 = S->lv[0];
+        const int nx = L0.nx, n = nx * L0.ny;
+        const long long o = B.loff[Ls];
+        T* pb = pool + L0.off + 3 * L0.size;
+        for (int c = threadIdx.x; c < n; c += NT) pb[(c / nx) * L0.pitch + c % nx] = w.lb[o + c];
+        __syncthreads();
+        b_sub_vcycle<T, NT>(*S, pool);
+        const T* px = pool + L0.off + 4 * L0.size;
+        for (int c = threadIdx.x; c < n; c += NT) w.lx[o + c] = px[(c / nx) * L0.pitch + c % nx];
+        __syncthreads();
+    } else {
         const long long o = B.loff[Lv - 1];
         b_coarse_solve<T, NT>(B.lnx[Lv - 1] * B.lny[Lv - 1], ainv, w.lb + o, w.lx + o);
     }
-    for (int l = Lv - 2; l >= 0; --l) {
+    for (int l = Ls - 1; l >= 0; --l) {
         const int nx = B.lnx[l], ny = B.lny[l], nxc = B.lnx[l + 1];
         const long long o = B.loff[l], oc = B.loff[l + 1];
         const T *m = w.lm + o, *We = w.lWe + o, *Wn = w.lWn + o, *b = w.lb + o;
@@ -393,6 +418,45 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
             const long long cl = B.loff[B.nlev - 1];
             b_coarse_setup<T, NT>(B.lnx[B.nlev - 1], B.lny[B.nlev - 1], w.lm + cl, w.lWe + cl, w.lWn + cl, gjA, gjc,
                                   ainv);
+        }
+        // levels from B.sub down stay in LDS for the whole step, laid out as
+        // the single grid's sub-cycle lays them out (five arrays per level at
+        // pitch nx + 1, the coarsest right-hand side, one partial per
+        // thread); the pool overlays the Gauss-Jordan workspace, free now
+        __shared__ SubCycle<T> s_sub;
+        T* pool = reinterpret_cast<T*>(b_smem + Lay::uni);
+        const SubCycle<T>* S = nullptr;
+        if (B.sub > 0) {
+            if (t == 0) {
+                SubCycle<T>& Q = s_sub;
+                Q.nlev = B.nlev - B.sub;
+                int po = 0;
+                for (int k = 0; k < Q.nlev; ++k) {
+                    const int l = B.sub + k;
+                    const int pitch = B.lnx[l] + 1;
+                    Q.lv[k] = SubLevel<T>{B.lnx[l], B.lny[l], w.lm + B.loff[l], w.lWe + B.loff[l], w.lWn + B.loff[l],
+                                          po, 0, pitch, pitch * B.lny[l]};
+                    po += 5 * pitch * B.lny[l];
+                }
+                Q.Ainv = ainv;
+                Q.bc_off = po;
+                Q.part_off = po + B.lnx[B.nlev - 1] * B.lny[B.nlev - 1];
+                Q.kcyc = 0;
+                Q.k_off = Q.part_off + NT;
+            }
+            __syncthreads();
+            for (int k = 0; k + 1 < s_sub.nlev; ++k) {
+                const SubLevel<T>& L = s_sub.lv[k];
+                T* pm = pool + L.off;
+                for (int c = t; c < L.nx * L.ny; c += NT) {
+                    const int cl = (c / L.nx) * L.pitch + c % L.nx;
+                    pm[cl] = L.m[c];
+                    pm[L.size + cl] = L.We[c];
+                    pm[2 * L.size + cl] = L.Wn[c];
+                }
+            }
+            __syncthreads();
+            S = &s_sub;
         }
         const long long o0 = B.loff[0];
         const T *m0 = w.lm + o0, *We0 = w.lWe + o0, *Wn0 = w.lWn + o0;
@@ -505,7 +569,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
         };
         // z = V(r), then r.z and beta
         auto precondition = [&]() {
-            b_vcycle<T, NT>(B, w, ainv);
+            b_vcycle<T, NT>(B, w, ainv, S, pool);
             double a[1] = {0.0};
             cells<NT, 8>(
                 n, [&](int c) { return V2<T>{r[c], z[c]}; },

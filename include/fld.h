@@ -491,9 +491,9 @@ void fld_batch_destroy(fld_batch* b);
  * (hipStream_t, NULL = default), so the call can be captured into a graph;
  * with info == NULL it is asynchronous, otherwise it synchronises the stream
  * and returns the block's status.  Workspace need (bytes, each piece rounded
- * up to 256): about 6 n x 8 + 3 n x s + 5 x (4/3) n x s + 88 (nx + ny) with
- * n = nx ny and s = 4 (FP32, MIXED) or 8 (FP64): e.g. blocks up to 128 x 128
- * in every precision, 180 x 180 in FP64.  A block that does not fit is
+ * up to 256): about 6 n x 8 + 8 n x s + 5 x (4/3) n x s + 88 (nx + ny) with
+ * n = nx ny and s = 4 (FP32, MIXED) or 8 (FP64): e.g. square blocks up to
+ * 158 x 158 in FP64, 197 x 197 in FP32 and MIXED.  A block that does not fit is
  * rejected with FLD_EINVAL (the reason, as every other argument error, is
  * given by fld_batch_last_error(NULL) on the calling thread).  All calls on
  * one GPU share its array and the array keeps the last call's contents:

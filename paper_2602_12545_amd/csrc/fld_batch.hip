@@ -37,6 +37,7 @@ struct fld_batch {
     double *We = nullptr, *Wn = nullptr, *m = nullptr, *rhs = nullptr, *s = nullptr, *r64 = nullptr;
     void *lm = nullptr, *lWe = nullptr, *lWn = nullptr, *lx = nullptr, *lb = nullptr;
     void *xi = nullptr, *p = nullptr, *q = nullptr;
+    void* tr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // transposed fine level: m, We, Wn, x, b
     BInfo* dinfo = nullptr;
     BInfo* hinfo = nullptr;
     int* dacc = nullptr;  // first non-OK status of each block over a multi-step call
@@ -100,7 +101,9 @@ void launch_t(fld_batch* b, const BFields& f, BInfo* info, hipStream_t st) {
     BWork<T> w{b->We, b->Wn, b->m, b->rhs, b->s, b->r64,
                static_cast<T*>(b->lm), static_cast<T*>(b->lWe), static_cast<T*>(b->lWn),
                static_cast<T*>(b->lx), static_cast<T*>(b->lb),
-               static_cast<T*>(b->xi), static_cast<T*>(b->p), static_cast<T*>(b->q)};
+               static_cast<T*>(b->xi), static_cast<T*>(b->p), static_cast<T*>(b->q),
+               static_cast<T*>(b->tr[0]), static_cast<T*>(b->tr[1]), static_cast<T*>(b->tr[2]),
+               static_cast<T*>(b->tr[3]), static_cast<T*>(b->tr[4])};
     k_batch_step<T, NT><<<b->nb, NT, b->lds, st>>>(b->db, f, w, make_opts(b->opt, b->clock_khz), info);
 }
 
@@ -314,6 +317,11 @@ fld_status fld_batch_create(fld_batch** out, int32_t nblocks, const int32_t* nx,
     BALLOC(lm, lo * ts); BALLOC(lWe, lo * ts); BALLOC(lWn, lo * ts); BALLOC(lx, lo * ts); BALLOC(lbv, lo * ts);
     BALLOC(xi, nc * ts); BALLOC(pp, nc * ts); BALLOC(qq, nc * ts);
     b->lm = lm; b->lWe = lWe; b->lWn = lWn; b->lx = lx; b->lb = lbv; b->xi = xi; b->p = pp; b->q = qq;
+    for (void*& q : b->tr) {
+        unsigned char* v;
+        BALLOC(v, nc * ts);
+        q = v;
+    }
     double* met = nullptr;
     BALLOC(met, nm);
     BALLOC(b->db, nblocks);
@@ -583,7 +591,7 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
     const size_t lds = ts == sizeof(float) ? batch_lds<float>(pool) : batch_lds<double>(pool);
     const size_t nm = (size_t)metric_doubles(nx, ny);
     const size_t need = align256(sizeof(BBlock)) + align256(sizeof(BInfo)) + align256(nm * sizeof(double)) +
-                        6 * align256(n * sizeof(double)) + 5 * align256((size_t)lo * ts) + 3 * align256(n * ts);
+                        6 * align256(n * sizeof(double)) + 5 * align256((size_t)lo * ts) + 8 * align256(n * ts);
     if (need > kScratchBytes) {
         t_create_err = "block needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
                        std::to_string(kScratchBytes);
@@ -606,7 +614,7 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
     for (auto& q : w64) q = reinterpret_cast<double*>(take(n * sizeof(double)));
     void* lv[5];
     for (auto& q : lv) q = take((size_t)lo * ts);
-    void* vec[3];
+    void* vec[8];  // xi, p, q, then the transposed fine level
     for (auto& q : vec) q = take(n * ts);
     // set-up kernels: table entry, faces at i dx and j dy, metrics (no copies from the host)
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -625,13 +633,17 @@ fld_status fld_block_step_noalloc(int32_t nx, int32_t ny, double dx, double dy, 
         BWork<float> w{w64[0], w64[1], w64[2], w64[3], w64[4], w64[5],
                        static_cast<float*>(lv[0]), static_cast<float*>(lv[1]), static_cast<float*>(lv[2]),
                        static_cast<float*>(lv[3]), static_cast<float*>(lv[4]),
-                       static_cast<float*>(vec[0]), static_cast<float*>(vec[1]), static_cast<float*>(vec[2])};
+                       static_cast<float*>(vec[0]), static_cast<float*>(vec[1]), static_cast<float*>(vec[2]),
+                       static_cast<float*>(vec[3]), static_cast<float*>(vec[4]), static_cast<float*>(vec[5]),
+                       static_cast<float*>(vec[6]), static_cast<float*>(vec[7])};
         k_batch_step<float, 512><<<1, 512, lds, st>>>(db, f, w, bo, dinfo);
     } else {
         BWork<double> w{w64[0], w64[1], w64[2], w64[3], w64[4], w64[5],
                         static_cast<double*>(lv[0]), static_cast<double*>(lv[1]), static_cast<double*>(lv[2]),
                         static_cast<double*>(lv[3]), static_cast<double*>(lv[4]),
-                        static_cast<double*>(vec[0]), static_cast<double*>(vec[1]), static_cast<double*>(vec[2])};
+                        static_cast<double*>(vec[0]), static_cast<double*>(vec[1]), static_cast<double*>(vec[2]),
+                        static_cast<double*>(vec[3]), static_cast<double*>(vec[4]), static_cast<double*>(vec[5]),
+                        static_cast<double*>(vec[6]), static_cast<double*>(vec[7])};
         k_batch_step<double, 512><<<1, 512, lds, st>>>(db, f, w, bo, dinfo);
     }
     const hipError_t e = hipGetLastError();

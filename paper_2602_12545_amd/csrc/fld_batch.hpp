@@ -45,6 +45,7 @@ struct BWork {
     double *We, *Wn, *m, *rhs, *s, *r64;  // FP64 operator and true residual (packed cells)
     T *lm, *lWe, *lWn, *lx, *lb;          // inner-precision hierarchy, all levels (packed)
     T *xi, *p, *q;                        // inner CG vectors of the fine level (packed cells)
+    T *mT, *WeT, *WnT, *xT, *bT;          // the fine level transposed (columns as rows), packed cells
 };
 
 struct BOpts {
@@ -64,7 +65,10 @@ template <typename T, int NT>
 struct BLds {
     static constexpr size_t red = 0;
     static constexpr size_t ainv = kBRedDoubles * sizeof(double);
-    static constexpr size_t uni = ainv + (size_t)kBCoarse * kBCoarse * sizeof(T);
+    // transpose tile: th rows of tc, pitch tc + 1 (16.6 KB in either precision)
+    static constexpr int th = sizeof(T) == 4 ? 64 : 32, tc = 64;
+    static constexpr size_t tile = ainv + (size_t)kBCoarse * kBCoarse * sizeof(T);
+    static constexpr size_t uni = tile + (size_t)th * (tc + 1) * sizeof(T);
     static constexpr size_t gj = sizeof(double) * ((size_t)kBCoarse * kBCoarse + kBCoarse);
     static constexpr size_t bytes = uni + gj;
 };
@@ -285,10 +289,46 @@ __device__ __attribute__((noinline)) void b_coarse_solve(int n, const T* ainv, c
     __syncthreads();
 }
 
-// z = V(r): one V-cycle from a zero start; r is the fine level's b array and z
-// its x array.  Pre-smoothing: rows (even, odd), columns (even, odd); the
-// coarse correction (piecewise constant) is added, then post-smoothing runs in
-// the reverse order, so the preconditioner is symmetric.
+// dst = src transposed: src is ny rows of nx, dst nx rows of ny.  The block
+// goes through LDS in tiles of TH rows x TC columns (row pitch TC + 1, so the
+// column reads hit distinct banks), read along src rows and written along dst
+// rows; each thread holds TH TC / NT elements of a tile, and the next tile's
+// loads are issued before the current tile is written out.
+template <typename T, int NT, int TH, int TC>
+__device__ __attribute__((noinline)) void b_transpose(int nx, int ny, const T* __restrict__ src, T* __restrict__ dst,
+                                                      T* tile) {
+    constexpr int PER = TH * TC / NT;
+    static_assert(PER >= 1 && PER * NT == TH * TC, "tile must split evenly over the workgroup");
+    const int t = threadIdx.x;
+    const int ntx = (nx + TC - 1) / TC, nt = ntx * ((ny + TH - 1) / TH);
+    T v[PER];
+    auto load = [&](int k) {
+        const int j0 = (k / ntx) * TH, i0 = (k % ntx) * TC;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = t + p * NT, r = e / TC, c = e % TC;
+            v[p] = (j0 + r < ny && i0 + c < nx) ? src[(long long)(j0 + r) * nx + i0 + c] : T(0);
+        }
+    };
+    load(0);
+    for (int k = 0; k < nt; ++k) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = t + p * NT;
+            tile[(e / TC) * (TC + 1) + e % TC] = v[p];
+        }
+        __syncthreads();
+        if (k + 1 < nt) load(k + 1);
+        const int j0 = (k / ntx) * TH, i0 = (k % ntx) * TC;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = t + p * NT, c = e / TH, r = e % TH;
+            if (j0 + r < ny && i0 + c < nx) dst[(long long)(i0 + c) * ny + j0 + r] = tile[r * (TC + 1) + c];
+        }
+        __syncthreads();
+    }
+}
+
 // The LDS levels' V-cycle as a function of its own (not inlined into
 // b_vcycle: each keeps its own register budget).
 template <typename T, int NT>
@@ -296,10 +336,22 @@ __device__ __attribute__((noinline)) void b_sub_vcycle(const SubCycle<T>& S, T* 
     sub_vcycle<T, NT>(S, pool);
 }
 
+// z = V(r): one V-cycle from a zero start; r is the fine level's b array and z
+// its x array.  Pre-smoothing on the launched levels: rows (even, odd), then
+// columns (even, odd), except on the fine level, which runs its columns first
+// (from the zero start) as row sweeps of its transposed copy (strided column
+// loads cost about twice the rows' time on one CU), then its rows.  The coarse
+// correction (piecewise constant) is added, then post-smoothing runs in the
+// reverse order, so the preconditioner is symmetric.  The fine level takes
+// four transposes per cycle: b and x into the column layout, x back twice.
 template <typename T, int NT>
 __device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, const T* ainv,
-                                                   const SubCycle<T>* S, T* pool) {
+                                                   const SubCycle<T>* S, T* pool, T* tile) {
+    using Lay = BLds<T, NT>;
     const int Lv = B.nlev;
+    const long long bo = B.off;  // the block's fine-level cells in the packed transposed arrays
+    T* xT = w.xT + bo;
+    T* bT = w.bT + bo;
     if (Lv == 1) {
         const long long o = B.loff[0];
         b_coarse_solve<T, NT>(B.lnx[0] * B.lny[0], ainv, w.lb + o, w.lx + o);
@@ -312,10 +364,19 @@ __device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, 
         const long long o = B.loff[l], oc = B.loff[l + 1];
         const T *m = w.lm + o, *We = w.lWe + o, *Wn = w.lWn + o, *b = w.lb + o;
         T* x = w.lx + o;
-        b_sweep<T, NT>(nx, ny, 0, 0, 1, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
+        if (l == 0) {
+            b_transpose<T, NT, Lay::th, Lay::tc>(nx, ny, b, bT, tile);
+            b_sweep<T, NT>(ny, nx, 0, 0, 1, w.mT + bo, w.WeT + bo, w.WnT + bo, bT, xT);
+            b_sweep<T, NT>(ny, nx, 0, 1, 0, w.mT + bo, w.WeT + bo, w.WnT + bo, bT, xT);
+            b_transpose<T, NT, Lay::th, Lay::tc>(ny, nx, xT, x, tile);
+            b_sweep<T, NT>(nx, ny, 0, 0, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+        } else {
+            b_sweep<T, NT>(nx, ny, 0, 0, 1, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
+        }
         b_restrict<T, NT>(nx, ny, m, We, Wn, b, x, w.lb + oc, B.lnx[l + 1], B.lny[l + 1]);
         __syncthreads();
     }
@@ -350,10 +411,19 @@ __device__ __attribute__((noinline)) void b_vcycle(const BBlock& B, BWork<T> w, 
             },
             [&](int c, const V2<T>& v) { x[c] = v.a + v.b; });
         __syncthreads();
-        b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
-        b_sweep<T, NT>(nx, ny, 0, 0, 0, m, We, Wn, b, x);
+        if (l == 0) {
+            b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 0, 0, 0, m, We, Wn, b, x);
+            b_transpose<T, NT, Lay::th, Lay::tc>(nx, ny, x, xT, tile);
+            b_sweep<T, NT>(ny, nx, 0, 1, 0, w.mT + bo, w.WeT + bo, w.WnT + bo, bT, xT);
+            b_sweep<T, NT>(ny, nx, 0, 0, 0, w.mT + bo, w.WeT + bo, w.WnT + bo, bT, xT);
+            b_transpose<T, NT, Lay::th, Lay::tc>(ny, nx, xT, x, tile);
+        } else {
+            b_sweep<T, NT>(nx, ny, 1, 1, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 1, 0, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 0, 1, 0, m, We, Wn, b, x);
+            b_sweep<T, NT>(nx, ny, 0, 0, 0, m, We, Wn, b, x);
+        }
     }
 }
 
@@ -367,6 +437,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
     using Lay = BLds<T, NT>;
     double* red = reinterpret_cast<double*>(b_smem + Lay::red);
     T* ainv = reinterpret_cast<T*>(b_smem + Lay::ainv);
+    T* tile = reinterpret_cast<T*>(b_smem + Lay::tile);
     double* gjA = reinterpret_cast<double*>(b_smem + Lay::uni);
     double* gjc = gjA + kBCoarse * kBCoarse;
 
@@ -409,6 +480,11 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
                 w.xi[off + c] = T(0);
             }
             __syncthreads();
+            // the transposed fine level: rows are the columns, the couplings
+            // along them the north ones, across them the east ones
+            b_transpose<T, NT, Lay::th, Lay::tc>(nx, ny, w.lm + o0, w.mT + off, tile);
+            b_transpose<T, NT, Lay::th, Lay::tc>(nx, ny, w.lWn + o0, w.WeT + off, tile);
+            b_transpose<T, NT, Lay::th, Lay::tc>(nx, ny, w.lWe + o0, w.WnT + off, tile);
             for (int l = 0; l + 1 < B.nlev; ++l) {
                 const long long a = B.loff[l], c = B.loff[l + 1];
                 b_coarsen<T, NT>(B.lnx[l], B.lny[l], w.lm + a, w.lWe + a, w.lWn + a, B.lnx[l + 1], B.lny[l + 1],
@@ -569,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const BBlock* __restrict__ bl
         };
         // z = V(r), then r.z and beta
         auto precondition = [&]() {
-            b_vcycle<T, NT>(B, w, ainv, S, pool);
+            b_vcycle<T, NT>(B, w, ainv, S, pool, tile);
             double a[1] = {0.0};
             cells<NT, 8>(
                 n, [&](int c) { return V2<T>{r[c], z[c]}; },

@@ -297,8 +297,10 @@ __device__ void wave_line_sweep(int na, int nlines, int par, I sa, I sl, const T
             // into the line and the grid) and the value is masked afterwards,
             // so the loads issue back to back instead of one guarded block
             // each (much faster from LDS; measured slower for binary32 rows in
-            // global memory, where guarded loads skip traffic)
-            const I dn = (line + 1 < nlines) ? sl : 0, ds = (line > 0) ? -sl : 0;
+            // global memory, where guarded loads skip traffic).  A lane past
+            // the last line reads line 0 (lb = 0) with no neighbour offsets:
+            // line 0 minus sl would lie before the array.
+            const I dn = (active && line + 1 < nlines) ? sl : 0, ds = (active && line > 0) ? -sl : 0;
 #pragma unroll
             for (int q = 0; q < LM; ++q) {
                 const int g = s0 + q;

@@ -114,6 +114,20 @@ def test_batch_multistep_vs_oracle(lib):
         assert rel_l2(Eb, Eo) < 1e-9 and rel_l2(Tb, To) < 1e-9
 
 
+@pytest.mark.parametrize("shape", [(100, 60), (60, 100), (40, 24)])
+def test_batch_single_ragged_block_fp64(lib, shape):
+    """One block alone, so it sits at offset 0 of every array, with line counts
+    that leave idle lanes in the last pass of its line sweeps (binary64 takes
+    the branch-free loads): regression for a load before the arrays' start."""
+    blocks = _blocks([shape], first=70)
+    print(f"[batch] fp64 single block {shape}", flush=True)
+    E, T, infos = _run(lib, blocks, precision="fp64", **PARITY)
+    assert infos[0]["status"] == 0, infos
+    r = O.step_problem(blocks[0])
+    assert rel_l2(E.reshape(shape[1], shape[0]), r.E) < 1e-10
+    assert rel_l2(T.reshape(shape[1], shape[0]), r.T) < 1e-10
+
+
 def test_batch_matches_single_grid_solver(lib):
     """The same block through fld_step (one context) and through the batch."""
     from gpu_helpers import gpu_step

@@ -140,14 +140,15 @@ typedef enum { FLD_SMOOTH_LINE = 0, FLD_SMOOTH_POINT = 1, FLD_SMOOTH_LINE_SPLIT 
  * grid (4096 x 64 .. 128 rows about the equator) it is not, and CG then
  * stops with FLD_EBREAKDOWN; K and V have no such condition.  K and W2 act
  * as V where a line smoother has no LDS sub-cycle (fewer than three levels,
- * or point smoothing).  KL_K and KL_W2 make every second launched level
- * (levels 1, 3, 5, ... above the sub-cycle) Krylov-accelerated: its coarse
- * problem is solved by two flexible-CG steps, each preconditioned by the
- * cycle from that level down (the sub-cycle entered as K or W2), so that the
- * coarse correction takes its A-norm best scale instead of the aggregated
- * operator's (a K-cycle over the launched levels; each such level doubles
- * the work below it; acts as K or W2 where fewer than three levels are
- * launched). */
+ * point smoothing, or a coarsest level above 256 cells, which is solved
+ * exactly).  KL_K and KL_W2 make every second launched level (levels 1, 3,
+ * 5, ... above the coarse solve) Krylov-accelerated: its coarse problem is
+ * solved by two flexible-CG steps, each preconditioned by the cycle from
+ * that level down (the sub-cycle entered as K or W2; the two are the same
+ * above an exact coarsest solve), so that the coarse correction takes its
+ * A-norm best scale instead of the aggregated operator's (a K-cycle over the
+ * launched levels; each such level doubles the work below it; acts as K or
+ * W2 where fewer than three levels are launched). */
 typedef enum { FLD_MG_CYCLE_V = 0, FLD_MG_CYCLE_K = 1, FLD_MG_CYCLE_W2 = 2, FLD_MG_CYCLE_KL_K = 3,
                FLD_MG_CYCLE_KL_W2 = 4 } fld_mg_cycle;
 
@@ -162,7 +163,13 @@ typedef struct {
     int32_t max_inner;      /* CG iterations per solve, all checks included (default 2000)   */
     double  inner_rtol;     /* FP32 mode only: stop once the inner (FP32) residual has       */
                             /* dropped by this factor (default 1e-5)                         */
-    int32_t mg_coarse_max;  /* coarsest level size in cells, solved densely (1..256, def 64) */
+    int32_t mg_coarse_max;  /* coarsest level size in cells, solved exactly (1..4096, def 64): up to
+                               256 cells by one workgroup (inside the LDS sub-cycle with a line
+                               smoother), above that by its dense inverse, formed on the GPU at each
+                               assembly (block Schur complements along the shorter grid direction)
+                               and applied by a multi-workgroup product; the LDS sub-cycle is then
+                               not used (inverse: nc^2 inner-precision words, nc = the level's
+                               cells, plus 3 nc min(nx, ny) doubles of set-up workspace)          */
     int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
     int32_t smoother;       /* fld_smoother (default LINE); LINE* need nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */

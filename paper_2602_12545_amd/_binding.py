@@ -68,6 +68,14 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libfld.so not built ({LIB_PATH}); run __graft_entry__.build() or "
                           "python paper_2602_12545_amd/build.py")
+    # torch bundles its own HIP runtime under the same soname as the system
+    # one libfld.so links against; whichever loads first serves the process.
+    # Loading torch first keeps torch's kernels on the runtime they were built
+    # for (the other order makes its launches fail as invalid device functions).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     return ctypes.CDLL(LIB_PATH)
 
 

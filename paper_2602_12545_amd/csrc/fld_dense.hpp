@@ -1,0 +1,307 @@
+// Exact solve of a coarsest multigrid level too large for one workgroup's
+// dense solve (kCoarseMax < n <= kDenseMax cells): its inverse is formed on
+// the GPU once per assembly and applied by a product spread over many
+// workgroups, a few microseconds per application where a one-workgroup
+// iterative sub-cycle takes tens.
+//
+// The level's operator is block tridiagonal when its cells are taken line by
+// line along the shorter grid direction: nb lines of w <= 64 cells, the
+// diagonal blocks D_k tridiagonal (couplings along a line), the off-diagonal
+// blocks -B_k diagonal (couplings between lines k and k + 1, B_k = diag(b_k)).
+// With the forward and backward Schur complements
+//   S_0 = D_0,            S_k = D_k - B_{k-1} S_{k-1}^-1 B_{k-1},
+//   Q_{nb-1} = D_{nb-1},  Q_k = D_k - B_k Q_{k+1}^-1 B_k,
+// the inverse G = A^-1 has the diagonal blocks
+//   G_kk = (D_k - B_{k-1} S_{k-1}^-1 B_{k-1} - B_k Q_{k+1}^-1 B_k)^-1
+// and, below the diagonal, G_lk = Q_l^-1 B_{l-1} G_{l-1,k} (l > k), which
+// follows from block row l of A G = I; the upper blocks are their transposes.
+// Every S_k and Q_k is symmetric positive definite and diagonally dominant
+// (the level's matrix is an M-matrix with a positive mass term), so
+// Gauss-Jordan without pivoting inverts them stably.  All of it runs in FP64;
+// G is stored in the inner precision, in block order (unknown a = k w + p),
+// and the product maps block order to the level's storage order on the way
+// in and out.
+#pragma once
+
+#include "fld_mg.hpp"
+
+namespace fld {
+
+constexpr int kDenseMax = 4096;   // largest level solved this way (cells)
+constexpr int kDenseW = 64;       // line length bound: min(nx, ny) <= 64 when nx ny <= 4096
+constexpr int kDenseThreads = 256;
+constexpr int kDenseRows = 8;     // rows of G per workgroup of the product (two per wavefront)
+constexpr int kDenseCols = 16;    // columns of a block column per workgroup of the off-diagonal chains
+
+struct DenseGeom {
+    int nx, ny;      // the level's grid
+    int cols;        // 1: lines are grid columns (ny < nx); 0: grid rows
+    int w, nb;       // cells per line and lines (w nb = nx ny)
+    int tr;          // storage order of the level's vectors: 0 row-major (j nx + i), 1 transposed (i ny + j)
+    const double *m, *We, *Wn;  // FP64 coefficients of the level, row-major
+    const double* mu;           // the level's matrix is (m, W) / mu, as in the inner-precision copies
+};
+
+// Row-major index of cell p of line k.
+__device__ inline int dn_cell(const DenseGeom& g, int k, int p) { return g.cols ? p * g.nx + k : k * g.nx + p; }
+
+// Storage index of the unknown a = k w + p (block order).
+__device__ inline int dn_store(const DenseGeom& g, int a) {
+    const int k = a / g.w, p = a - k * g.w;
+    const int i = g.cols ? k : p, j = g.cols ? p : k;
+    return g.tr ? i * g.ny + j : j * g.nx + i;
+}
+
+// Per unknown in block order, scaled by 1 / mu: the diagonal of A (mass plus
+// every face coupling), the coupling to the next cell of its line (0 at the
+// line's end) and to the same cell of the next line (0 on the last line).
+__global__ void k_dense_stage(DenseGeom g, double* __restrict__ dd, double* __restrict__ aa, double* __restrict__ cc) {
+    const int n = g.w * g.nb;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int k = a / g.w, p = a - k * g.w;
+    const double s = 1.0 / *g.mu;
+    auto along = [&](int kk, int pp) {
+        const int c = dn_cell(g, kk, pp);
+        return g.cols ? g.Wn[c] : g.We[c];
+    };
+    auto cross = [&](int kk, int pp) {
+        const int c = dn_cell(g, kk, pp);
+        return g.cols ? g.We[c] : g.Wn[c];
+    };
+    const double an = p + 1 < g.w ? along(k, p) : 0.0, ap = p > 0 ? along(k, p - 1) : 0.0;
+    const double cn = k + 1 < g.nb ? cross(k, p) : 0.0, cp = k > 0 ? cross(k - 1, p) : 0.0;
+    dd[a] = g.m[dn_cell(g, k, p)] * s + ((ap + an) + (cp + cn)) * s;
+    aa[a] = an * s;
+    cc[a] = cn * s;
+}
+
+// In-place inverse of the w x w matrix M (row pitch w) in LDS by Gauss-Jordan
+// elimination without pivoting; ends with a barrier.
+template <int NT>
+__device__ void dn_invert(double* M, int w) {
+    constexpr int PER = kDenseW * kDenseW / NT;
+    const int t = threadIdx.x, nn = w * w;
+    int ii[PER], jj[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + q * NT;
+        ii[q] = e / w;
+        jj[q] = e - ii[q] * w;
+    }
+    for (int p = 0; p < w; ++p) {
+        const double d = 1.0 / M[p * w + p];
+        double v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * NT;
+            if (e < nn) {
+                const int i = ii[q], j = jj[q];
+                const double mip = M[i * w + p], mpj = M[p * w + j];
+                v[q] = i == p ? (j == p ? d : mpj * d) : (j == p ? -mip * d : M[e] - mip * mpj * d);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * NT;
+            if (e < nn) M[e] = v[q];
+        }
+        __syncthreads();
+    }
+}
+
+// The two Schur chains, one workgroup each: block 0 stores S_k^-1 (k = 0 ..
+// nb-2) in SX, block 1 stores Q_k^-1 (k = nb-1 .. 1) in SY (w x w each,
+// row-major, at k w^2).  Dynamic LDS: (w^2 + 3 n) doubles (the staged
+// coefficients of every line, then one matrix).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
+                                                    const double* __restrict__ aa, const double* __restrict__ cc,
+                                                    double* __restrict__ SX, double* __restrict__ SY) {
+    extern __shared__ double dsm[];
+    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
+    double* M = dsm;
+    double* sd = M + nn;
+    double* sa = sd + n;
+    double* sc = sa + n;
+    for (int a = t; a < n; a += NT) {
+        sd[a] = dd[a];
+        sa[a] = aa[a];
+        sc[a] = cc[a];
+    }
+    __syncthreads();
+    const bool fwd = blockIdx.x == 0;
+    double* out = fwd ? SX : SY;
+    for (int s = 0; s + 1 < nb; ++s) {
+        const int k = fwd ? s : nb - 1 - s;
+        // the eliminated neighbour (line k - 1 forward, k + 1 backward) couples
+        // to line k through b_{k-1} or b_k; M holds its inverse
+        const double* bv = sc + (fwd ? k - 1 : k) * w;
+        const double* dk = sd + k * w;
+        const double* ak = sa + k * w;
+        for (int e = t; e < nn; e += NT) {
+            const int i = e / w, j = e - i * w;
+            double v = i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
+            if (s > 0) v -= bv[i] * M[e] * bv[j];
+            M[e] = v;
+        }
+        __syncthreads();
+        dn_invert<NT>(M, w);
+        for (int e = t; e < nn; e += NT) out[(size_t)k * nn + e] = M[e];
+    }
+}
+
+// Diagonal blocks, one workgroup per line k: G_kk in FP64 (SG) and in the
+// inner precision (G, block order, n x n).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
+                                                   const double* __restrict__ aa, const double* __restrict__ cc,
+                                                   const double* __restrict__ SX, const double* __restrict__ SY,
+                                                   double* __restrict__ SG, T* __restrict__ G) {
+    __shared__ double M[kDenseW * kDenseW];
+    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x, k = blockIdx.x;
+    const double* dk = dd + k * w;
+    const double* ak = aa + k * w;
+    for (int e = t; e < nn; e += NT) {
+        const int i = e / w, j = e - i * w;
+        double v = i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
+        if (k > 0) {
+            const double* b = cc + (k - 1) * w;
+            v -= b[i] * SX[(size_t)(k - 1) * nn + e] * b[j];
+        }
+        if (k + 1 < nb) {
+            const double* b = cc + k * w;
+            v -= b[i] * SY[(size_t)(k + 1) * nn + e] * b[j];
+        }
+        M[e] = v;
+    }
+    __syncthreads();
+    dn_invert<NT>(M, w);
+    for (int e = t; e < nn; e += NT) {
+        const int i = e / w, j = e - i * w;
+        SG[(size_t)k * nn + e] = M[e];
+        G[(size_t)(k * w + i) * n + k * w + j] = static_cast<T>(M[e]);
+    }
+}
+
+// Blocks below (and, transposed, above) the diagonal: workgroup (k, c) walks
+// down block column k for the columns c kDenseCols .. of its diagonal block,
+// X <- Q_l^-1 B_{l-1} X for l = k + 1 .. nb - 1, storing each G_lk and G_kl.
+// Q_l^-1 B_{l-1} of the next line is loaded while the current product runs.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __restrict__ cc,
+                                                  const double* __restrict__ SY, const double* __restrict__ SG,
+                                                  T* __restrict__ G) {
+    static_assert(NT == 256, "2 x 2 tiles: 32 row pairs x 8 column pairs");
+    constexpr int PER = kDenseW * kDenseW / NT;
+    constexpr int C = kDenseCols;
+    __shared__ double Yb[kDenseW * kDenseW];
+    __shared__ double X[kDenseW * C];
+    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
+    const int k = blockIdx.x, q0 = blockIdx.y * C, qn = min(C, w - q0);
+    for (int e = t; e < w * C; e += NT) {
+        const int p = e / C, q = e - p * C;
+        X[e] = q < qn ? SG[(size_t)k * nn + p * w + q0 + q] : 0.0;
+    }
+    double yv[PER];
+    auto load = [&](int l) {
+        const double* Y = SY + (size_t)l * nn;
+        const double* b = cc + (l - 1) * w;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * NT;
+            if (e < nn) yv[q] = Y[e] * b[e % w];
+        }
+    };
+    const int rt = t >> 3, ct = t & 7;  // rows 2 rt, 2 rt + 1; columns 2 ct, 2 ct + 1
+    const int i0 = 2 * rt, j0 = 2 * ct;
+    const bool act = i0 < w && j0 < qn;
+    if (k + 1 < nb) load(k + 1);
+    for (int l = k + 1; l < nb; ++l) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * NT;
+            if (e < nn) Yb[e] = yv[q];
+        }
+        __syncthreads();
+        if (l + 1 < nb) load(l + 1);
+        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+        if (act) {
+            const bool two = i0 + 1 < w;
+            for (int m = 0; m < w; ++m) {
+                const double y0 = Yb[i0 * w + m], y1 = two ? Yb[(i0 + 1) * w + m] : 0.0;
+                const double x0 = X[m * C + j0], x1 = X[m * C + j0 + 1];
+                a00 += y0 * x0;
+                a01 += y0 * x1;
+                a10 += y1 * x0;
+                a11 += y1 * x1;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            X[i0 * C + j0] = a00;
+            X[i0 * C + j0 + 1] = a01;
+            if (i0 + 1 < w) {
+                X[(i0 + 1) * C + j0] = a10;
+                X[(i0 + 1) * C + j0 + 1] = a11;
+            }
+        }
+        __syncthreads();
+        // G_lk: rows l w + p, columns k w + q0 + q; G_kl the transpose
+        for (int e = t; e < w * qn; e += NT) {
+            const int p = e / qn, q = e - p * qn;
+            G[(size_t)(l * w + p) * n + k * w + q0 + q] = static_cast<T>(X[p * C + q]);
+        }
+        for (int e = t; e < w * qn; e += NT) {
+            const int q = e / w, p = e - q * w;
+            G[(size_t)(k * w + q0 + q) * n + l * w + p] = static_cast<T>(X[p * C + q]);
+        }
+    }
+}
+
+// x = G b on the level: rows of G spread over workgroups (two per
+// wavefront, lanes along the row), b gathered into block order in LDS, x
+// scattered back to the storage order.  DOT (a one-level hierarchy): also the
+// workgroup's partial of r.z = b.x in part_rz[blockIdx.x].
+template <typename T, bool DOT>
+__global__ __launch_bounds__(kDenseThreads) void k_dense_solve(DenseGeom g, const T* __restrict__ G,
+                                                               const T* __restrict__ b, T* __restrict__ x,
+                                                               double* __restrict__ part_rz,
+                                                               const Scalars* __restrict__ sc) {
+    if (sc->done) return;
+    __shared__ T sb[kDenseMax];
+    __shared__ double sh[16];
+    const int n = g.w * g.nb, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int a = t; a < n; a += kDenseThreads) sb[a] = b[dn_store(g, a)];
+    __syncthreads();
+    double dot = 0.0;
+    constexpr int RW = kDenseRows / (kDenseThreads / 64);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int a = blockIdx.x * kDenseRows + wv * RW + r;
+        if (a < n) {
+            const T* row = G + (size_t)a * n;
+            T s0 = T(0), s1 = T(0);
+            int c = lane;
+#pragma unroll 4
+            for (; c + 64 < n; c += 128) {
+                s0 += row[c] * sb[c];
+                s1 += row[c + 64] * sb[c + 64];
+            }
+            if (c < n) s0 += row[c] * sb[c];
+            T s = s0 + s1;
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (lane == 0) {
+                x[dn_store(g, a)] = s;
+                dot += (double)sb[a] * (double)s;
+            }
+        }
+    }
+    if (DOT) {
+        const double rz = block_sum(dot, sh);
+        if (t == 0) part_rz[blockIdx.x] = rz;
+    }
+}
+
+}  // namespace fld

@@ -17,6 +17,7 @@
 
 #include "fld.h"
 #include "fld_band.hpp"
+#include "fld_dense.hpp"
 
 using namespace fld;
 
@@ -75,6 +76,13 @@ struct Inner {
     std::vector<LevelT<T>> lv;
     T* Ainv = nullptr;
     double* Ywork = nullptr;  // coarse inverse set-up: forward solutions
+    // a coarsest level above kCoarseMax cells: its inverse from block Schur
+    // complements (staged coefficients, the chains' inverses, the diagonal
+    // blocks; FP64) and the multi-workgroup product
+    bool dense = false;
+    DenseGeom dg{};
+    double *dd = nullptr, *aa = nullptr, *cc = nullptr, *SX = nullptr, *SY = nullptr, *SG = nullptr;
+    size_t dense_lds = 0;
     T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     int sub_first = -1;                   // first level of the one-workgroup coarse sub-cycle (-1: none)
     // Krylov-accelerated launched levels (mg_cycle KL_K / KL_W2): bit l of
@@ -224,7 +232,7 @@ fld_status validate_options(const fld_options* o, std::string& err) {
     if (!(o->rel_tol > 0.0) || !(o->rel_tol < 1.0)) { err = "rel_tol must be in (0, 1)"; return FLD_EINVAL; }
     if (o->max_outer < 1 || o->max_inner < 1) { err = "max_outer / max_inner must be >= 1"; return FLD_EINVAL; }
     if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) { err = "inner_rtol must be in (0, 1)"; return FLD_EINVAL; }
-    if (o->mg_coarse_max < 1 || o->mg_coarse_max > kCoarseMax) { err = "mg_coarse_max must be in [1, 256]"; return FLD_EINVAL; }
+    if (o->mg_coarse_max < 1 || o->mg_coarse_max > kDenseMax) { err = "mg_coarse_max must be in [1, 4096]"; return FLD_EINVAL; }
     if (o->mg_coarse_op < 0 || o->mg_coarse_op > 1) { err = "mg_coarse_op"; return FLD_EINVAL; }
     if (o->smoother < 0 || o->smoother > 2) { err = "smoother"; return FLD_EINVAL; }
     if (o->chunk < 2 || (o->chunk & 1)) { err = "chunk must be even and >= 2"; return FLD_EINVAL; }
@@ -424,6 +432,19 @@ void launch_transpose(int nx, int ny, const T* s0, const T* s1, T* d0, T* d1, co
         k_transpose<T, 1><<<g, blk, 0, st>>>(nx, ny, s0, nullptr, nullptr, d0, nullptr, nullptr, sc);
 }
 
+// x = A^-1 b on the coarsest level (below a launched level): one workgroup
+// up to kCoarseMax cells, the multi-workgroup product above.
+template <typename T>
+void coarse_solve(fld_ctx* c, Inner<T>& in, hipStream_t st) {
+    LevelT<T>& cl = in.lv.back();
+    const int n = cl.nx * cl.ny;
+    if (in.dense)
+        k_dense_solve<T, false><<<(n + kDenseRows - 1) / kDenseRows, kDenseThreads, 0, st>>>(in.dg, in.Ainv, cl.bP,
+                                                                                            cl.xP, nullptr, c->sc);
+    else
+        k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(n, in.Ainv, cl.bP, cl.xP, nullptr, c->sc);
+}
+
 template <typename T>
 void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     const int L = (int)in.lv.size();
@@ -467,9 +488,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
             LevelT<T>& f = in.lv[in.sub_first];
             k_subcycle<T><<<1, kSubThreads<T>, in.sub_lds, st>>>(in.sub, f.bP, f.xP, c->sc);
         } else {
-            LevelT<T>& cl = in.lv[L - 1];
-            k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP,
-                                                                     nullptr, c->sc);
+            coarse_solve<T>(c, in, st);
         }
     };
     // prolongation of the correction from level l + 1 and post-smoothing of level l
@@ -556,10 +575,8 @@ void enqueue_vcycle_point(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         k_pre_point<T><<<tile_grid(a.nx, a.ny), blk2d(), 0, st>>>(a.nx, a.ny, a.bP, a.m, a.We, a.Wn, a.xQ, b.bP, b.nx,
                                                                   b.ny, c->sc);
     }
-    LevelT<T>& cl = in.lv[L - 1];
     (void)join_setup(c, st);
-    k_coarse_solve<T, false><<<1, kCoarseSolveThreads, 0, st>>>(cl.nx * cl.ny, in.Ainv, cl.bP, cl.xP, nullptr,
-                                                                 c->sc);
+    coarse_solve<T>(c, in, st);
     for (int l = L - 2; l >= 0; --l) {
         LevelT<T>& a = in.lv[l];
         LevelT<T>& b = in.lv[l + 1];
@@ -580,9 +597,15 @@ void enqueue_vcycle(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         if (c->sweeps_only) return;
         (void)join_setup(c, st);
         LevelT<T>& l0 = in.lv[0];
-        k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP, c->part_rz,
-                                                                    c->sc);
-        c->nrz = 1;
+        if (in.dense) {
+            const int n = l0.nx * l0.ny, G = (n + kDenseRows - 1) / kDenseRows;
+            k_dense_solve<T, true><<<G, kDenseThreads, 0, st>>>(in.dg, in.Ainv, l0.bP, l0.xP, c->part_rz, c->sc);
+            c->nrz = G;
+        } else {
+            k_coarse_solve<T, true><<<1, kCoarseSolveThreads, 0, st>>>(l0.nx * l0.ny, in.Ainv, l0.bP, l0.xP,
+                                                                        c->part_rz, c->sc);
+            c->nrz = 1;
+        }
         return;
     }
     if (is_line(c->opt)) enqueue_vcycle_line<T>(c, in, st);
@@ -660,7 +683,21 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
         HIPCHK(hipStreamWaitEvent(c->setup_stream, c->setup_fork, 0));
         hipStream_t ss = c->setup_stream;
         const int w = std::min(cl.nx, cl.ny), tr = in.lv[L - 1].tr ? 1 : 0;
-        if (w <= 4)
+        if (in.dense) {
+            // block Schur complements: staged coefficients, the two chains,
+            // the diagonal blocks, then the off-diagonal block columns
+            const DenseGeom& g = in.dg;
+            const int n = g.w * g.nb;
+            k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
+            if (g.nb > 1)
+                k_dense_chain<kDenseThreads><<<2, kDenseThreads, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX,
+                                                                                    in.SY);
+            k_dense_diag<T, kDenseThreads><<<g.nb, kDenseThreads, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY,
+                                                                            in.SG, in.Ainv);
+            if (g.nb > 1)
+                k_dense_off<T, kDenseThreads><<<dim3(g.nb - 1, (g.w + kDenseCols - 1) / kDenseCols), kDenseThreads, 0,
+                                                ss>>>(g, in.cc, in.SY, in.SG, in.Ainv);
+        } else if (w <= 4)
             k_coarse_setup<T, 4><<<1, kCoarseMax, 0, ss>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
                                                            in.Ainv);
         else if (w <= 8)
@@ -719,8 +756,35 @@ fld_status alloc_inner(fld_ctx* ctx) {
         HIPCHK(ctx->alloc(&lv.xQ, m));
     }
     const LevelT<T>& cl = in.lv.back();
-    HIPCHK(ctx->alloc(&in.Ainv, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
-    HIPCHK(ctx->alloc(&in.Ywork, (size_t)cl.nx * cl.ny * cl.nx * cl.ny));
+    const size_t ncl = (size_t)cl.nx * cl.ny;
+    HIPCHK(ctx->alloc(&in.Ainv, ncl * ncl));
+    in.dense = ncl > (size_t)kCoarseMax;
+    if (in.dense) {
+        DenseGeom& g = in.dg;
+        const Level64& c64 = ctx->h64.back();
+        g.nx = cl.nx;
+        g.ny = cl.ny;
+        g.cols = cl.ny < cl.nx ? 1 : 0;
+        g.w = std::min(cl.nx, cl.ny);
+        g.nb = std::max(cl.nx, cl.ny);
+        g.tr = cl.tr ? 1 : 0;
+        g.m = c64.m;
+        g.We = c64.We;
+        g.Wn = c64.Wn;
+        g.mu = ctx->mu;
+        HIPCHK(ctx->alloc(&in.dd, ncl));
+        HIPCHK(ctx->alloc(&in.aa, ncl));
+        HIPCHK(ctx->alloc(&in.cc, ncl));
+        HIPCHK(ctx->alloc(&in.SX, ncl * g.w));
+        HIPCHK(ctx->alloc(&in.SY, ncl * g.w));
+        HIPCHK(ctx->alloc(&in.SG, ncl * g.w));
+        in.dense_lds = sizeof(double) * ((size_t)g.w * g.w + 3 * ncl);
+        if (in.dense_lds > 65536)
+            HIPCHK(hipFuncSetAttribute((const void*)k_dense_chain<kDenseThreads>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)in.dense_lds));
+    } else {
+        HIPCHK(ctx->alloc(&in.Ywork, ncl * ncl));
+    }
     HIPCHK(ctx->alloc(&in.r, n));
     HIPCHK(ctx->alloc(&in.x, n));
     HIPCHK(ctx->alloc(&in.p[0], n));
@@ -751,7 +815,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     HIPCHK(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         lds_max = 65536;
-    if (line && L >= 3) {
+    if (line && L >= 3 && !in.dense) {
         for (int l = 1; l < L - 1 && in.sub_first < 0; ++l) {
             if (L - l > kSubMaxLevels) continue;
             if (std::max(in.lv[l].nx, in.lv[l].ny) > 64 * kLineMaxL) continue;

@@ -139,6 +139,8 @@ def test_invalid_inputs(lib):
     ctx.close()
     with pytest.raises(lib.FLDError):
         lib.Context(0, 4, 0, np.arange(1.0), np.arange(5.0), [(0, 0.0)] * 4)
+    with pytest.raises(lib.FLDError):
+        make_ctx(lib, prob, mg_coarse_max=4097)  # above the dense coarsest level's bound
 
 
 def test_max_iterations_reports_noconv(lib):
@@ -259,6 +261,38 @@ def test_krylov_accelerated_levels(lib, name, kw, prec):
         assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10, cyc
     print(name, prec, "K", its[1], "W2", its[2], "KL_K", its[3], "KL_W2", its[4], flush=True)
     assert its[3] <= its[1] and its[4] <= its[2]
+
+
+@pytest.mark.parametrize("name,kw,cm,cycles", [
+    # coarsest 64 x 32 (2048 cells) on an odd level: transposed storage, lines along y
+    ("c5", dict(nx=512, ny=256), 2048, (1, 4)),
+    # coarsest 64 x 64 (4096 cells, lines of 64) on an even level
+    ("c2", dict(nx=256, ny=256), 4096, (0, 3)),
+    # coarsest 38 x 25 (950 cells, lines of 25 cells, ragged aggregation)
+    ("c3", dict(nx=300, ny=200), 1024, (1,)),
+    # one level: the whole grid solved densely (48 lines of 40 cells)
+    ("c1", dict(nx=48, ny=40), 4096, (1,)),
+])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dense_coarsest_level(lib, name, kw, cm, cycles, prec):
+    """A coarsest level above 256 cells is solved with its exact inverse,
+    built on the GPU from block Schur complements and applied by a
+    multi-workgroup product: the step reaches the oracle's solution with the
+    line smoothers and (Cartesian recipes) the point smoother; on a one-level hierarchy the preconditioner
+    is A^-1 itself, so CG converges at once."""
+    prob = W.make(name, **kw)
+    print(f"[dense coarsest] {name} {prob.nx}x{prob.ny} coarse {cm} {prec}", flush=True)
+    ref = O.step_problem(prob)
+    opt = dict(precision=prec, rel_tol=1e-12, norm=1, mg_coarse_max=cm)
+    # the point smoother only on the Cartesian recipes (on the spherical ones
+    # it does not converge with any coarsest level)
+    runs = [dict(mg_cycle=c) for c in cycles] + ([dict(smoother=1)] if name in ("c1", "c2") else [])
+    for extra in runs:
+        E, T, info = gpu_step(lib, torch, prob, **opt, **extra)
+        assert info["status"] == 0, (extra, info)
+        assert rel_l2(E, ref.E) < 1e-10 and rel_l2(T, ref.T) < 1e-10, extra
+        if name == "c1":
+            assert info["mg_levels"] == 1 and info["inner_iters"] <= (1 if prec == "fp64" else 3), info
 
 
 def thin_c1():

@@ -42,18 +42,20 @@ def _oracle_steps(prob, nsteps):
 
 
 @pytest.mark.parametrize("mode", ["steps", "graph"])
-@pytest.mark.parametrize("name,kw,prec,norm,cyc", [
-    ("c1", dict(nx=48, ny=40), "mixed", 0, 1),
-    ("c2", dict(nx=70, ny=52), "fp64", 0, 1),
-    ("c5", dict(nx=96, ny=64), "mixed", 1, 1),
-    ("c5", dict(nx=512, ny=256), "mixed", 1, 4),
-    ("c5", dict(nx=512, ny=256), "fp64", 1, 3),
+@pytest.mark.parametrize("name,kw,prec,norm,cyc,cm", [
+    ("c1", dict(nx=48, ny=40), "mixed", 0, 1, 256),
+    ("c2", dict(nx=70, ny=52), "fp64", 0, 1, 256),
+    ("c5", dict(nx=96, ny=64), "mixed", 1, 1, 256),
+    ("c5", dict(nx=512, ny=256), "mixed", 1, 4, 256),
+    ("c5", dict(nx=512, ny=256), "fp64", 1, 3, 256),
+    ("c5", dict(nx=512, ny=256), "mixed", 1, 4, 2048),
+    ("c5", dict(nx=512, ny=256), "fp64", 1, 3, 2048),
 ])
-def test_steps_equal_repeated_step(lib, name, kw, prec, norm, cyc, mode):
+def test_steps_equal_repeated_step(lib, name, kw, prec, norm, cyc, cm, mode):
     fld = lib
     prob = W.make(name, **kw)
-    print(f"[steps] {name} {prob.nx}x{prob.ny} {prec} cycle {cyc} {mode}", flush=True)
-    opt = dict(precision=prec, norm=norm, rel_tol=1e-11, mg_cycle=cyc, mg_coarse_max=256)
+    print(f"[steps] {name} {prob.nx}x{prob.ny} {prec} cycle {cyc} coarse {cm} {mode}", flush=True)
+    opt = dict(precision=prec, norm=norm, rel_tol=1e-11, mg_cycle=cyc, mg_coarse_max=cm)
     E1, T1, i1 = _run(fld, torch, prob, 6, multi=False, **opt)
     E2, T2, i2 = _run(fld, torch, prob, 6, multi=mode, **opt)
     assert [i["status"] for i in i2] == [0] * 6
@@ -72,18 +74,21 @@ def test_steps_profiled_path_matches(lib):
     assert np.array_equal(E1, E2) and np.array_equal(T1, T2)
 
 
-@pytest.mark.parametrize("name,kw,norm", [
-    ("c5", dict(nx=64, ny=48), 1),
-    ("c3", dict(nx=40, ny=40), 0),
+@pytest.mark.parametrize("name,kw,norm,cm", [
+    ("c5", dict(nx=64, ny=48), 1, 64),
+    ("c3", dict(nx=40, ny=40), 0, 64),
+    ("c5", dict(nx=256, ny=128), 1, 2048),
 ])
-def test_steps_vs_oracle(lib, name, kw, norm):
+def test_steps_vs_oracle(lib, name, kw, norm, cm):
     """Ten coupled steps; each step's solve error (<= about 1e-12 relative) is
     carried into the next step's coefficients, so the bound is looser than a
-    single step's."""
+    single step's.  (mg_coarse_max 2048: the dense coarsest level.)"""
     fld = lib
     prob = W.make(name, **kw)
+    print(f"[steps vs oracle] {name} {prob.nx}x{prob.ny} coarse {cm}", flush=True)
     n = 10
-    E, T, infos = _run(fld, torch, prob, n, multi=True, precision="mixed", norm=norm, rel_tol=1e-12)
+    E, T, infos = _run(fld, torch, prob, n, multi=True, precision="mixed", norm=norm, rel_tol=1e-12,
+                       mg_coarse_max=cm)
     assert all(i["status"] == 0 for i in infos)
     Eo, To = _oracle_steps(prob, n)
     assert rel_l2(E, Eo) < 1e-9

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfld.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fld_host.hip", "fld_batch.hip", "fld_tune.hip", "fld_forest.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_mg.hpp", "fld_band.hpp", "fld_batch.hpp")] + \
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("fld_internal.hpp", "fld_kernels.hpp", "fld_line.hpp", "fld_sub.hpp", "fld_mg.hpp", "fld_dense.hpp", "fld_band.hpp", "fld_batch.hpp")] + \
           [os.path.join(ROOT, "include", "fld.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

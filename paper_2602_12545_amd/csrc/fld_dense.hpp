@@ -76,119 +76,192 @@ __global__ void k_dense_stage(DenseGeom g, double* __restrict__ dd, double* __re
     cc[a] = cn * s;
 }
 
-// In-place inverse of the w x w matrix M (row pitch w) in LDS by Gauss-Jordan
-// elimination without pivoting; ends with a barrier.
-template <int NT>
-__device__ void dn_invert(double* M, int w) {
-    constexpr int PER = kDenseW * kDenseW / NT;
-    const int t = threadIdx.x, nn = w * w;
-    int ii[PER], jj[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int e = t + q * NT;
-        ii[q] = e / w;
-        jj[q] = e - ii[q] * w;
-    }
-    for (int p = 0; p < w; ++p) {
-        const double d = 1.0 / M[p * w + p];
-        double v[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * NT;
-            if (e < nn) {
-                const int i = ii[q], j = jj[q];
-                const double mip = M[i * w + p], mpj = M[p * w + j];
-                v[q] = i == p ? (j == p ? d : mpj * d) : (j == p ? -mip * d : M[e] - mip * mpj * d);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * NT;
-            if (e < nn) M[e] = v[q];
-        }
+// Matrices of the set-up live in registers as 4 x 4 tiles: thread l of the
+// (W/4)^2 threads of a workgroup holds rows 4 ti .. 4 ti + 3 and columns
+// 4 tj .. 4 tj + 3 (ti = l / (W/4), tj = l % (W/4)); entries beyond the
+// w x w matrix hold the identity.  W = 32: one wavefront, W = 64: four.
+template <int W>
+__device__ inline void dn_sync() {
+    if constexpr (W <= 32) {
+        // one wavefront: its LDS accesses complete in order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
         __syncthreads();
     }
 }
 
+// In-place inverse of the tiled w x w matrix by Gauss-Jordan elimination
+// without pivoting.  For each pivot the owners of its row and column publish
+// them in LDS (buf: 2 (2 W + 1) doubles, alternate halves for consecutive
+// pivots), one sync, then every thread updates its tile; the pivot chain
+// takes one LDS round trip per pivot and no workgroup barrier for W = 32.
+template <int W>
+__device__ void dn_gj(double (&a)[4][4], int ti, int tj, int w, double* buf) {
+    for (int pr = 0; pr * 4 < w; ++pr) {
+#pragma unroll
+        for (int pc = 0; pc < 4; ++pc) {
+            const int p = 4 * pr + pc;
+            if (p >= w) break;
+            double* rb = buf + (p & 1) * (2 * W + 1);
+            double* cb = rb + W;
+            const bool prow = ti == pr, pcol = tj == pr;
+            if (prow) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rb[4 * tj + c] = a[pc][c];
+            }
+            if (pcol) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cb[4 * ti + r] = a[r][pc];
+            }
+            dn_sync<W>();
+            double rv[4], cv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rv[q] = rb[4 * tj + q];
+                cv[q] = cb[4 * ti + q];
+            }
+            // d = 1 / a_pp: hardware reciprocal estimate, two Newton steps
+            const double x = rb[p];
+            double d = __builtin_amdgcn_rcp(x);
+            d = fma(d, fma(-x, d, 1.0), d);
+            d = fma(d, fma(-x, d, 1.0), d);
+            // a_ij - a_ip (a_pj d) for every entry (one FMA each), then the
+            // pivot row (a_pj d), column (-a_ip d) and entry (d) set by
+            // their owners
+            double vd[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) vd[c] = rv[c] * d;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a[r][c] = fma(-cv[r], vd[c], a[r][c]);
+            if (prow) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a[pc][c] = vd[c];
+            }
+            if (pcol) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r][pc] = -cv[r] * d;
+                if (prow) a[pc][pc] = d;
+            }
+        }
+    }
+}
+
+// Block D_k of A at (i, j) (i, j < w) from the staged coefficients.
+__device__ inline double dn_dk(const double* dk, const double* ak, int i, int j) {
+    return i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
+}
+
 // The two Schur chains, one workgroup each: block 0 stores S_k^-1 (k = 0 ..
 // nb-2) in SX, block 1 stores Q_k^-1 (k = nb-1 .. 1) in SY (w x w each,
-// row-major, at k w^2).  Dynamic LDS: (w^2 + 3 n) doubles (the staged
-// coefficients of every line, then one matrix).
-template <int NT>
-__global__ __launch_bounds__(NT) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
-                                                    const double* __restrict__ aa, const double* __restrict__ cc,
-                                                    double* __restrict__ SX, double* __restrict__ SY) {
+// row-major, at k w^2).  The chain's matrix stays in registers from one
+// line to the next.  Dynamic LDS: 3 n + 2 (2 W + 1) doubles (the staged
+// coefficients of every line, the pivot buffers).
+template <int W>
+__global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
+                                                            const double* __restrict__ aa,
+                                                            const double* __restrict__ cc, double* __restrict__ SX,
+                                                            double* __restrict__ SY) {
+    constexpr int NT = W * W / 16;
     extern __shared__ double dsm[];
     const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
-    double* M = dsm;
-    double* sd = M + nn;
+    double* sd = dsm;
     double* sa = sd + n;
     double* sc = sa + n;
-    for (int a = t; a < n; a += NT) {
-        sd[a] = dd[a];
-        sa[a] = aa[a];
-        sc[a] = cc[a];
+    double* buf = sc + n;
+    for (int e = t; e < n; e += NT) {
+        sd[e] = dd[e];
+        sa[e] = aa[e];
+        sc[e] = cc[e];
     }
     __syncthreads();
+    const int ti = t / (W / 4), tj = t % (W / 4);
     const bool fwd = blockIdx.x == 0;
     double* out = fwd ? SX : SY;
+    double a[4][4];
     for (int s = 0; s + 1 < nb; ++s) {
         const int k = fwd ? s : nb - 1 - s;
-        // the eliminated neighbour (line k - 1 forward, k + 1 backward) couples
-        // to line k through b_{k-1} or b_k; M holds its inverse
-        const double* bv = sc + (fwd ? k - 1 : k) * w;
+        // the eliminated neighbour (line k - 1 forward, k + 1 backward), whose
+        // inverse the tiles hold, couples to line k through b_{k-1} or b_k
+        const int kb = fwd ? k - 1 : k;
         const double* dk = sd + k * w;
         const double* ak = sa + k * w;
-        for (int e = t; e < nn; e += NT) {
-            const int i = e / w, j = e - i * w;
-            double v = i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
-            if (s > 0) v -= bv[i] * M[e] * bv[j];
-            M[e] = v;
-        }
-        __syncthreads();
-        dn_invert<NT>(M, w);
-        for (int e = t; e < nn; e += NT) out[(size_t)k * nn + e] = M[e];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int i = 4 * ti + r, j = 4 * tj + c;
+                double v = i == j ? 1.0 : 0.0;
+                if (i < w && j < w) {
+                    v = dn_dk(dk, ak, i, j);
+                    if (s > 0) v -= sc[kb * w + i] * a[r][c] * sc[kb * w + j];
+                }
+                a[r][c] = v;
+            }
+        dn_gj<W>(a, ti, tj, w, buf);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int i = 4 * ti + r, j = 4 * tj + c;
+                if (i < w && j < w) out[(size_t)k * nn + i * w + j] = a[r][c];
+            }
     }
 }
 
 // Diagonal blocks, one workgroup per line k: G_kk in FP64 (SG) and in the
 // inner precision (G, block order, n x n).
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
-                                                   const double* __restrict__ aa, const double* __restrict__ cc,
-                                                   const double* __restrict__ SX, const double* __restrict__ SY,
-                                                   double* __restrict__ SG, T* __restrict__ G) {
-    __shared__ double M[kDenseW * kDenseW];
+template <typename T, int W>
+__global__ __launch_bounds__(W * W / 16) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
+                                                           const double* __restrict__ aa,
+                                                           const double* __restrict__ cc,
+                                                           const double* __restrict__ SX,
+                                                           const double* __restrict__ SY, double* __restrict__ SG,
+                                                           T* __restrict__ G) {
+    __shared__ double buf[2 * (2 * W + 1)];
     const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x, k = blockIdx.x;
+    const int ti = t / (W / 4), tj = t % (W / 4);
     const double* dk = dd + k * w;
     const double* ak = aa + k * w;
-    for (int e = t; e < nn; e += NT) {
-        const int i = e / w, j = e - i * w;
-        double v = i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
-        if (k > 0) {
-            const double* b = cc + (k - 1) * w;
-            v -= b[i] * SX[(size_t)(k - 1) * nn + e] * b[j];
+    double a[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 4 * ti + r, j = 4 * tj + c;
+            double v = i == j ? 1.0 : 0.0;
+            if (i < w && j < w) {
+                v = dn_dk(dk, ak, i, j);
+                if (k > 0) {
+                    const double* b = cc + (k - 1) * w;
+                    v -= b[i] * SX[(size_t)(k - 1) * nn + i * w + j] * b[j];
+                }
+                if (k + 1 < nb) {
+                    const double* b = cc + k * w;
+                    v -= b[i] * SY[(size_t)(k + 1) * nn + i * w + j] * b[j];
+                }
+            }
+            a[r][c] = v;
         }
-        if (k + 1 < nb) {
-            const double* b = cc + k * w;
-            v -= b[i] * SY[(size_t)(k + 1) * nn + e] * b[j];
+    dn_gj<W>(a, ti, tj, w, buf);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 4 * ti + r, j = 4 * tj + c;
+            if (i < w && j < w) {
+                SG[(size_t)k * nn + i * w + j] = a[r][c];
+                G[(size_t)(k * w + i) * n + k * w + j] = static_cast<T>(a[r][c]);
+            }
         }
-        M[e] = v;
-    }
-    __syncthreads();
-    dn_invert<NT>(M, w);
-    for (int e = t; e < nn; e += NT) {
-        const int i = e / w, j = e - i * w;
-        SG[(size_t)k * nn + e] = M[e];
-        G[(size_t)(k * w + i) * n + k * w + j] = static_cast<T>(M[e]);
-    }
 }
 
 // Blocks below (and, transposed, above) the diagonal: workgroup (k, c) walks
 // down block column k for the columns c kDenseCols .. of its diagonal block,
 // X <- Q_l^-1 B_{l-1} X for l = k + 1 .. nb - 1, storing each G_lk and G_kl.
-// Q_l^-1 B_{l-1} of the next line is loaded while the current product runs.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __restrict__ cc,
                                                   const double* __restrict__ SY, const double* __restrict__ SG,
@@ -204,28 +277,30 @@ __global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __r
         const int p = e / C, q = e - p * C;
         X[e] = q < qn ? SG[(size_t)k * nn + p * w + q0 + q] : 0.0;
     }
-    double yv[PER];
-    auto load = [&](int l) {
+    // Q_l^-1 B_{l-1} of line l in registers, loaded two lines ahead (two
+    // register sets, alternating), so the loads' latency hides behind the
+    // products of the two lines before
+    double ya[PER], yb[PER];
+    auto load = [&](double (&y)[PER], int l) {
         const double* Y = SY + (size_t)l * nn;
         const double* b = cc + (l - 1) * w;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + q * NT;
-            if (e < nn) yv[q] = Y[e] * b[e % w];
+            if (e < nn) y[q] = Y[e] * b[e % w];
         }
     };
     const int rt = t >> 3, ct = t & 7;  // rows 2 rt, 2 rt + 1; columns 2 ct, 2 ct + 1
     const int i0 = 2 * rt, j0 = 2 * ct;
     const bool act = i0 < w && j0 < qn;
-    if (k + 1 < nb) load(k + 1);
-    for (int l = k + 1; l < nb; ++l) {
+    auto step = [&](int l, double (&y)[PER]) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + q * NT;
-            if (e < nn) Yb[e] = yv[q];
+            if (e < nn) Yb[e] = y[q];
         }
         __syncthreads();
-        if (l + 1 < nb) load(l + 1);
+        if (l + 2 < nb) load(y, l + 2);
         double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
         if (act) {
             const bool two = i0 + 1 < w;
@@ -257,6 +332,12 @@ __global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __r
             const int q = e / w, p = e - q * w;
             G[(size_t)(k * w + q0 + q) * n + l * w + p] = static_cast<T>(X[p * C + q]);
         }
+    };
+    if (k + 1 < nb) load(ya, k + 1);
+    if (k + 2 < nb) load(yb, k + 2);
+    for (int l = k + 1; l < nb; l += 2) {
+        step(l, ya);
+        if (l + 1 < nb) step(l + 1, yb);
     }
 }
 

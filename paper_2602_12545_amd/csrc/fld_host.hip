@@ -550,17 +550,27 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         down(l);
         cycle(l + 1);
         up(l);
+        // few partials: the consumers sum them (no separate reduction launch)
+        const bool fold = G <= kKLFoldMax;
         k_kl_dots<T, 0><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
                                                   in.kv1[l], part, c->sc);
-        k_kl_reduce<0><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
-        k_kl_axpy<T><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], ks, c->sc);
+        if (fold) {
+            k_kl_axpy<T, true><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], part, G, ks, c->sc);
+        } else {
+            k_kl_reduce<0><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+            k_kl_axpy<T, false><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], part, G, ks, c->sc);
+        }
         down(l);
         cycle(l + 1);
         up(l);
         k_kl_dots<T, 1><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
                                                   in.kv1[l], part, c->sc);
-        k_kl_reduce<1><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
-        k_kl_combine<T><<<G, kKLThreads, 0, st>>>(n1, a1.xP, in.kc1[l], ks, c->sc);
+        if (fold) {
+            k_kl_combine<T, true><<<G, kKLThreads, 0, st>>>(n1, a1.xP, in.kc1[l], part, G, ks, c->sc, single);
+        } else {
+            k_kl_reduce<1><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+            k_kl_combine<T, false><<<G, kKLThreads, 0, st>>>(n1, a1.xP, in.kc1[l], part, G, ks, c->sc, single);
+        }
     };
     cycle(0);
 }
@@ -689,11 +699,15 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
             const DenseGeom& g = in.dg;
             const int n = g.w * g.nb;
             k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
-            if (g.nb > 1)
-                k_dense_chain<kDenseThreads><<<2, kDenseThreads, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX,
-                                                                                    in.SY);
-            k_dense_diag<T, kDenseThreads><<<g.nb, kDenseThreads, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY,
-                                                                            in.SG, in.Ainv);
+            if (g.w <= 32) {
+                if (g.nb > 1)
+                    k_dense_chain<32><<<2, 64, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
+                k_dense_diag<T, 32><<<g.nb, 64, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
+            } else {
+                if (g.nb > 1)
+                    k_dense_chain<64><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
+                k_dense_diag<T, 64><<<g.nb, 256, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
+            }
             if (g.nb > 1)
                 k_dense_off<T, kDenseThreads><<<dim3(g.nb - 1, (g.w + kDenseCols - 1) / kDenseCols), kDenseThreads, 0,
                                                 ss>>>(g, in.cc, in.SY, in.SG, in.Ainv);
@@ -778,9 +792,11 @@ fld_status alloc_inner(fld_ctx* ctx) {
         HIPCHK(ctx->alloc(&in.SX, ncl * g.w));
         HIPCHK(ctx->alloc(&in.SY, ncl * g.w));
         HIPCHK(ctx->alloc(&in.SG, ncl * g.w));
-        in.dense_lds = sizeof(double) * ((size_t)g.w * g.w + 3 * ncl);
+        // the chain's staged coefficients (3 per cell) and its pivot buffers
+        const int W = g.w <= 32 ? 32 : 64;
+        in.dense_lds = sizeof(double) * (3 * ncl + 2 * (2 * (size_t)W + 1));
         if (in.dense_lds > 65536)
-            HIPCHK(hipFuncSetAttribute((const void*)k_dense_chain<kDenseThreads>,
+            HIPCHK(hipFuncSetAttribute(W == 32 ? (const void*)k_dense_chain<32> : (const void*)k_dense_chain<64>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)in.dense_lds));
     } else {
         HIPCHK(ctx->alloc(&in.Ywork, ncl * ncl));

@@ -1367,26 +1367,19 @@ __global__ __launch_bounds__(kKLThreads) void k_kl_dots(int nx, int ny, const T*
     }
 }
 
+// The Krylov level's coefficients from the summed partials v (stage 0:
+// x.v1, x.b; stage 1: x.v1, x.(A x), x.b): stage 0 sets rho1 and s1, stage 1
+// (with rho1, s1 of stage 0) f1 and f2.
 template <int STAGE>
-__global__ __launch_bounds__(kRedThreads) void k_kl_reduce(const double* part, int G, KLScal* ks, const Scalars* sc,
-                                                           int single) {
-    if (sc->done) return;
-    __shared__ double sh[kRedThreads / 64];
-    double v[3];
-    for (int q = 0; q < (STAGE == 0 ? 2 : 3); ++q) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < G; b += kRedThreads) a += part[(size_t)q * G + b];
-        v[q] = block_sum(a, sh);
-    }
-    if (threadIdx.x != 0) return;
+__device__ inline void kl_coeffs(const double* v, KLScal& k, int single) {
     if (STAGE == 0) {
         // rho1 <= 0 only for c1 = 0 (zero right-hand side): the result is c1
         const double rho1 = v[0];
-        ks->rho1 = rho1;
-        ks->s1 = rho1 > 0.0 ? v[1] / rho1 : 0.0;
+        k.rho1 = rho1;
+        k.s1 = rho1 > 0.0 ? v[1] / rho1 : 0.0;
         return;
     }
-    const double rho1 = ks->rho1, s1 = ks->s1;
+    const double rho1 = k.rho1, s1 = k.s1;
     double f1 = s1, f2 = 0.0;
     if (rho1 > 0.0) {
         // A-norm squared of the part of c2 A-orthogonal to c1; within the
@@ -1398,25 +1391,88 @@ __global__ __launch_bounds__(kRedThreads) void k_kl_reduce(const double* part, i
             f1 = s1 - v[0] * f2 / rho1;
         }
     }
-    ks->f1 = f1;
-    ks->f2 = f2;
+    k.f1 = f1;
+    k.f2 = f2;
 }
 
-// r1 <- r1 - s1 v1
-template <typename T>
-__global__ __launch_bounds__(kKLThreads) void k_kl_axpy(int n, T* __restrict__ b, const T* __restrict__ v1,
-                                                        const KLScal* ks, const Scalars* sc) {
+// Sums of the G partials of each of the stage's dot products, in a fixed
+// order (the result is valid in every thread).
+template <int STAGE, int NT>
+__device__ inline void kl_sum(const double* part, int G, double* v, double* sh) {
+    __shared__ double s_v[3];
+    for (int q = 0; q < (STAGE == 0 ? 2 : 3); ++q) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < G; b += NT) a += part[(size_t)q * G + b];
+        const double t = block_sum(a, sh);
+        if (threadIdx.x == 0) s_v[q] = t;
+    }
+    __syncthreads();
+    for (int q = 0; q < (STAGE == 0 ? 2 : 3); ++q) v[q] = s_v[q];
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kRedThreads) void k_kl_reduce(const double* part, int G, KLScal* ks, const Scalars* sc,
+                                                           int single) {
     if (sc->done) return;
-    const T s1 = (T)ks->s1;
+    __shared__ double sh[kRedThreads / 64];
+    double v[3];
+    kl_sum<STAGE, kRedThreads>(part, G, v, sh);
+    if (threadIdx.x != 0) return;
+    KLScal k = *ks;
+    kl_coeffs<STAGE>(v, k, single);
+    *ks = k;
+}
+
+// Levels with few partials (G <= kKLFoldMax) skip k_kl_reduce: every
+// workgroup of the consumer sums them itself (same order, same result) and
+// workgroup 0 stores the coefficients for the next stage.
+constexpr int kKLFoldMax = 512;
+
+// r1 <- r1 - s1 v1 (FOLD: s1 from the stage-0 partials)
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(kKLThreads) void k_kl_axpy(int n, T* __restrict__ b, const T* __restrict__ v1,
+                                                        const double* __restrict__ part, int G, KLScal* ks,
+                                                        const Scalars* sc) {
+    if (sc->done) return;
+    double s1d;
+    if (FOLD) {
+        __shared__ double sh[kKLThreads / 64];
+        double v[3];
+        kl_sum<0, kKLThreads>(part, G, v, sh);
+        KLScal k{};
+        kl_coeffs<0>(v, k, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks->rho1 = k.rho1;
+            ks->s1 = k.s1;
+        }
+        s1d = k.s1;
+    } else {
+        s1d = ks->s1;
+    }
+    const T s1 = (T)s1d;
     for (int c = blockIdx.x * kKLThreads + threadIdx.x; c < n; c += gridDim.x * kKLThreads) b[c] -= s1 * v1[c];
 }
 
-// x <- f1 c1 + f2 x
-template <typename T>
+// x <- f1 c1 + f2 x (FOLD: f1, f2 from the stage-1 partials and rho1, s1)
+template <typename T, bool FOLD>
 __global__ __launch_bounds__(kKLThreads) void k_kl_combine(int n, T* __restrict__ x, const T* __restrict__ c1,
-                                                           const KLScal* ks, const Scalars* sc) {
+                                                           const double* __restrict__ part, int G, KLScal* ks,
+                                                           const Scalars* sc, int single) {
     if (sc->done) return;
-    const T f1 = (T)ks->f1, f2 = (T)ks->f2;
+    double f1d, f2d;
+    if (FOLD) {
+        __shared__ double sh[kKLThreads / 64];
+        double v[3];
+        kl_sum<1, kKLThreads>(part, G, v, sh);
+        KLScal k = *ks;
+        kl_coeffs<1>(v, k, single);
+        f1d = k.f1;
+        f2d = k.f2;
+    } else {
+        f1d = ks->f1;
+        f2d = ks->f2;
+    }
+    const T f1 = (T)f1d, f2 = (T)f2d;
     for (int c = blockIdx.x * kKLThreads + threadIdx.x; c < n; c += gridDim.x * kKLThreads)
         x[c] = f1 * c1[c] + f2 * x[c];
 }

@@ -1638,9 +1638,12 @@ fld_status steps_pipelined(fld_ctx* ctx, int32_t nsteps, double* E, double* Tg, 
             // SpMV takes the number of r.z partials that cycle leaves
             fld_status gs = capture_chunk<T>(ctx, in, E, kChunk);
             if (gs != FLD_OK) return gs;
-            // each step predicted by the one before (the relaxing sequences
-            // this serves change their counts slowly)
-            if (!run_chunks<T>(ctx, in, kChunk, o.max_inner, ctx->last_iters, st)) {
+            // each step predicted by the one before less one iteration: the
+            // relaxing sequences this serves change their counts slowly and
+            // mostly downwards, and a read-ahead chunk past convergence is a
+            // chunk of early-exit launches (a late read costs only the host's
+            // flag-read latency)
+            if (!run_chunks<T>(ctx, in, kChunk, o.max_inner, ctx->last_iters - 1, st)) {
                 ctx->err = "pipelined steps: chunk launch or flag read failed";
                 return FLD_EHIP;
             }

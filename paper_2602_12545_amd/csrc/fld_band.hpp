@@ -37,12 +37,32 @@ inline size_t band_lds_bytes(int na, int R, bool with_b) {
            16 * sizeof(double);
 }
 
+// A Krylov-accelerated level's vector updates folded into its sweeps
+// (v == nullptr: none).  LINE_ZERO: the right-hand side is taken as
+// b - s1 v (the level's second pass; v = A c1), and the band's rows of it are
+// also stored, untransposed, in bout2 for the pass's later kernels.
+// LINE_PROLONG: the coarse correction read from the level below is taken as
+// f1 v + f2 ec (v = that level's c1: its two-step combination).  The
+// coefficients come from the stage's G workgroup partials (part != nullptr,
+// summed by every workgroup in the same order; the stage-0 fold's workgroup 0
+// records rho1, s1 for stage 1) or from ks.
+template <typename T>
+struct BandKL {
+    const T* v = nullptr;
+    const double* part = nullptr;
+    int G = 0;
+    KLScal* ks = nullptr;
+    T* bout2 = nullptr;
+    int single = 0;
+};
+
 template <typename T, int LM, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
 __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, int L, const T* __restrict__ m,
                                                   const T* __restrict__ We, const T* __restrict__ Wn,
                                                   const T* __restrict__ b, const T* __restrict__ xin,
                                                   const T* __restrict__ ec, int nxc, T* __restrict__ xout,
-                                                  T* __restrict__ bout, double* part, const Scalars* sc, int* ran) {
+                                                  T* __restrict__ bout, double* part, const Scalars* sc, int* ran,
+                                                  BandKL<T> kl) {
     if (sc->done) return;
     if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
     extern __shared__ __align__(16) unsigned char band_smem[];
@@ -59,6 +79,30 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
     const int lane = t & 63;
     const bool wave_pcr = K <= 64;
     double acc = 0.0;  // DOT: b.x over the band's rows, accumulated as they are solved
+    // Krylov-level folds: s1 (LINE_ZERO), f1 and f2 (LINE_PROLONG)
+    const bool fold_b = MODE == LINE_ZERO && kl.v != nullptr;
+    const bool fold_e = MODE == LINE_PROLONG && kl.v != nullptr;
+    T ks1 = T(0), kf1 = T(0), kf2 = T(1);
+    if (fold_b || fold_e) {
+        KLScal kk = *kl.ks;
+        if (kl.part) {
+            double v[3];
+            if (fold_b) {
+                kl_sum<0, NT>(kl.part, kl.G, v, sh);
+                kl_coeffs<0>(v, kk, 0);
+                if (blockIdx.x == 0 && t == 0) {
+                    kl.ks->rho1 = kk.rho1;
+                    kl.ks->s1 = kk.s1;
+                }
+            } else {
+                kl_sum<1, NT>(kl.part, kl.G, v, sh);
+                kl_coeffs<1>(v, kk, kl.single);
+            }
+        }
+        ks1 = (T)kk.s1;
+        kf1 = (T)kk.f1;
+        kf2 = (T)kk.f2;
+    }
 
     // Coefficients, right-hand side and (first parity) neighbour-row x of one
     // chunk of one row, loaded ahead of the solve, for rows that split into
@@ -78,6 +122,12 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         load_vec<T, LM>(We + rb + s0, C.vwe);
         load_vec<T, LM>(Wn + rb + s0, C.vwn);
         load_vec<T, LM>(b + rb + s0, C.vb);
+        if (fold_b) {
+            T vv[LM];
+            load_vec<T, LM>(kl.v + rb + s0, vv);
+#pragma unroll
+            for (int q = 0; q < LM; ++q) C.vb[q] -= ks1 * vv[q];
+        }
         load_vec<T, LM>(Wn + rs + s0, C.vws);
         if (with_x && MODE != LINE_ZERO) {
             load_vec<T, LM>(xin + rn + s0, C.xn);
@@ -86,8 +136,20 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 // coarse correction of cells s0 .. s0 + LM - 1: LM / 2 values
                 T en[LM / 2], es[LM / 2];
                 const int ic = s0 >> 1;
-                load_vec<T, LM / 2>(ec + (size_t)((row + 1 < ny ? row + 1 : row) >> 1) * nxc + ic, en);
-                load_vec<T, LM / 2>(ec + (size_t)((row > 0 ? row - 1 : row) >> 1) * nxc + ic, es);
+                const size_t on = (size_t)((row + 1 < ny ? row + 1 : row) >> 1) * nxc + ic;
+                const size_t os = (size_t)((row > 0 ? row - 1 : row) >> 1) * nxc + ic;
+                load_vec<T, LM / 2>(ec + on, en);
+                load_vec<T, LM / 2>(ec + os, es);
+                if (fold_e) {
+                    T cn[LM / 2], cs[LM / 2];
+                    load_vec<T, LM / 2>(kl.v + on, cn);
+                    load_vec<T, LM / 2>(kl.v + os, cs);
+#pragma unroll
+                    for (int q = 0; q < LM / 2; ++q) {
+                        en[q] = kf1 * cn[q] + kf2 * en[q];
+                        es[q] = kf1 * cs[q] + kf2 * es[q];
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < LM; ++q) {
                     C.xn[q] += en[q >> 1];
@@ -144,6 +206,12 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 load_vec<T, LM>(We + rb + s0, vwe);
                 load_vec<T, LM>(Wn + rb + s0, vwn);
                 load_vec<T, LM>(b + rb + s0, vb);
+                if (fold_b) {
+                    T vv[LM];
+                    load_vec<T, LM>(kl.v + rb + s0, vv);
+#pragma unroll
+                    for (int q = 0; q < LM; ++q) vb[q] -= ks1 * vv[q];
+                }
                 if (row > 0) load_vec<T, LM>(Wn + rb + s0 - nx, vws);
                 else fill<T, LM>(vws, T(0));
             } else {
@@ -156,7 +224,7 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                     vwe[q] = ok ? We[c] : T(0);
                     vwn[q] = ok ? Wn[c] : T(0);
                     vws[q] = (ok && row > 0) ? Wn[c - nx] : T(0);
-                    vb[q] = ok ? b[c] : T(0);
+                    vb[q] = ok ? (fold_b ? b[c] - ks1 * kl.v[c] : b[c]) : T(0);
                 }
             }
         }
@@ -185,11 +253,17 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
                 } else if (MODE != LINE_ZERO) {
                     if (row + 1 < ny) {
                         xn = xin[rb + nx + g];
-                        if (MODE == LINE_PROLONG) xn += ec[(size_t)((row + 1) >> 1) * nxc + (g >> 1)];
+                        if (MODE == LINE_PROLONG) {
+                            const size_t ce = (size_t)((row + 1) >> 1) * nxc + (g >> 1);
+                            xn += fold_e ? kf1 * kl.v[ce] + kf2 * ec[ce] : ec[ce];
+                        }
                     }
                     if (row > 0) {
                         xs = xin[rb - nx + g];
-                        if (MODE == LINE_PROLONG) xs += ec[(size_t)((row - 1) >> 1) * nxc + (g >> 1)];
+                        if (MODE == LINE_PROLONG) {
+                            const size_t ce = (size_t)((row - 1) >> 1) * nxc + (g >> 1);
+                            xs += fold_e ? kf1 * kl.v[ce] + kf2 * ec[ce] : ec[ce];
+                        }
                     }
                 }
             }
@@ -351,7 +425,8 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
         L == LM && K * LM == nx && (nx % VW) == 0 &&
         ((reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(We) | reinterpret_cast<uintptr_t>(Wn) |
           reinterpret_cast<uintptr_t>(b) | (MODE != LINE_ZERO ? reinterpret_cast<uintptr_t>(xin) : 0)) & 15) == 0 &&
-        (MODE != LINE_PROLONG || ((nxc % VW) == 0 && (reinterpret_cast<uintptr_t>(ec) & 15) == 0 && LM / 2 >= VW));
+        (MODE != LINE_PROLONG || ((nxc % VW) == 0 && (reinterpret_cast<uintptr_t>(ec) & 15) == 0 && LM / 2 >= VW)) &&
+        (kl.v == nullptr || (reinterpret_cast<uintptr_t>(kl.v) & 15) == 0);
     if (sizeof(T) == 4 && whole_vec && n1 <= lpp && n2 <= lpp) {
         // one pass per parity: the second pass's coefficients are loaded
         // before the first pass is solved, so their latency overlaps it
@@ -394,6 +469,11 @@ __global__ __launch_bounds__(kBandWG) void k_band(int nx, int ny, int R, int K, 
             xout[(size_t)i * ny + r0 + rr] = rows[(size_t)(rr + 1) * nx + i];
             if (WRITE_BT) bout[(size_t)i * ny + r0 + rr] = bb[(size_t)rr * nx + i];
         }
+        if (WRITE_BT && fold_b && kl.bout2)
+            for (int e = t; e < nr * nx; e += NT) {
+                const int rr = e / nx, i = e - rr * nx;
+                kl.bout2[(size_t)(r0 + rr) * nx + i] = bb[(size_t)rr * nx + i];
+            }
     }
     if (DOT) {
         const double tot = block_sum(acc, sh);

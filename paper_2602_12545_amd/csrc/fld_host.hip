@@ -89,6 +89,7 @@ struct Inner {
     // kl_mask set for level l; c1 and A c1 of each (primary layout)
     unsigned kl_mask = 0;
     std::vector<T*> kc1, kv1;
+    std::vector<T*> kb2;  // the second pass's b - s1 A c1 (band-fused levels)
     SubCycle<T> sub{};
     size_t sub_lds = 0;
     hipGraphExec_t chunk_exec = nullptr;  // captured chunk of CG iterations
@@ -374,7 +375,7 @@ int launch_line(fld_ctx* c, const View<T>& v, int par, const T* b, T* x, const T
 // grid size (the number of r.z partials when DOT).
 template <typename T, int MODE, int FIRST, bool OUT_T, bool WRITE_BT, bool DOT>
 int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, const T* ec, int nxc, T* xout,
-                T* bout, hipStream_t st) {
+                T* bout, hipStream_t st, BandKL<T> kl = BandKL<T>{}) {
     int K, L;
     line_params(v.nx, K, L);
     const int grid = (v.ny + R - 1) / R;
@@ -400,7 +401,7 @@ int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, c
     const size_t lds = band_lds_bytes<T>(v.nx, R, WRITE_BT);
     int* ran = slot >= 0 ? P.ran + slot : nullptr;
     k_band<T, kLineMaxL, MODE, FIRST, OUT_T, WRITE_BT, DOT><<<grid, kBandWG, lds, st>>>(
-        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, DOT ? c->part_rz : c->part, c->sc, ran);
+        v.nx, v.ny, R, K, L, v.m, v.We, v.Wn, b, xin, ec, nxc, xout, bout, DOT ? c->part_rz : c->part, c->sc, ran, kl);
     if (slot >= 0) (void)hipEventRecord(P.ev[2 * slot + 1], st);
     return grid;
 }
@@ -457,14 +458,17 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
                (l < c->sweep_first || (c->sweep_levels > 0 && l >= c->sweep_first + c->sweep_levels));
     };
     // pre-smoothing of level l and its residual restricted to level l + 1
-    auto down = [&](int l) {
+    // kb: a Krylov level's second pass on a band-fused level folds
+    // b <- b - s1 A c1 into its first sweep (the result also in kb.bout2)
+    auto down = [&](int l, BandKL<T> kb = BandKL<T>{}) {
         if (skip(l)) return;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
         if (fused && a.band) {
             // rows of P (even, odd) -> x and b transposed into Q; rows of Q (even, odd)
-            launch_band<T, LINE_ZERO, 0, true, true, false>(c, vp, a.Rp, a.bP, nullptr, nullptr, 0, a.xQ, a.bQ, st);
+            launch_band<T, LINE_ZERO, 0, true, true, false>(c, vp, a.Rp, a.bP, nullptr, nullptr, 0, a.xQ, a.bQ, st,
+                                                            kb);
             launch_band<T, LINE_NORMAL, 0, false, false, false>(c, vq, a.Rq, a.bQ, a.xQ, nullptr, 0, a.xQ2, nullptr,
                                                                 st);
             xpre[l] = a.xQ2;
@@ -492,22 +496,26 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         }
     };
     // prolongation of the correction from level l + 1 and post-smoothing of level l
-    auto up = [&](int l) {
+    // bp: the level's right-hand side in P if not a.bP (a Krylov level's
+    // second pass); ke: the level below is a Krylov level whose two-step
+    // combination is folded into the prolongation
+    auto up = [&](int l, const T* bp = nullptr, BandKL<T> ke = BandKL<T>{}) {
         if (skip(l)) return;
         LevelT<T>& a = in.lv[l];
         LevelT<T>& nxt = in.lv[l + 1];
         const View<T> vp = a.view(a.tr), vq = a.view(!a.tr);
         const View<T> cv = nxt.view(nxt.tr);
+        const T* bP = bp ? bp : a.bP;
         if (fused && a.band) {
             // rows of Q (odd with the coarse correction, even) -> x transposed
             // into P; rows of P (odd, even), the last with r.z on the fine level
             launch_band<T, LINE_PROLONG, 1, true, false, false>(c, vq, a.Rq, a.bQ, xpre[l], nxt.xP, cv.nx, a.xPT,
-                                                                nullptr, st);
+                                                                nullptr, st, ke);
             if (l == 0) {
-                c->nrz = launch_band<T, LINE_NORMAL, 1, false, false, true>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0,
+                c->nrz = launch_band<T, LINE_NORMAL, 1, false, false, true>(c, vp, a.Rp, bP, a.xPT, nullptr, 0,
                                                                             a.xP, nullptr, st);
             } else {
-                launch_band<T, LINE_NORMAL, 1, false, false, false>(c, vp, a.Rp, a.bP, a.xPT, nullptr, 0, a.xP,
+                launch_band<T, LINE_NORMAL, 1, false, false, false>(c, vp, a.Rp, bP, a.xPT, nullptr, 0, a.xP,
                                                                     nullptr, st);
             }
             return;
@@ -528,6 +536,14 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
     // the cycle from level l down; a Krylov-accelerated level K takes two
     // flexible-CG steps on A_K e = r_K, each preconditioned by the cycle from
     // K down (its coefficients and partial sums in slot K of kscal / kpart)
+    // pend[l]: the Krylov level l + 1's combination x <- f1 c1 + f2 x, folded
+    // into up(l)'s prolongation (band-fused level l)
+    std::vector<BandKL<T>> pend(L);
+    auto take = [&](int l) {
+        BandKL<T> k = pend[l];
+        pend[l] = BandKL<T>{};
+        return k;
+    };
     std::function<void(int)> cycle = [&](int l) {
         if (l == Ld) {
             coarse();
@@ -537,7 +553,7 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         if (!krylov) {
             down(l);
             cycle(l + 1);
-            up(l);
+            up(l, nullptr, take(l));
             return;
         }
         LevelT<T>& a1 = in.lv[l];
@@ -547,25 +563,46 @@ void enqueue_vcycle_line(fld_ctx* c, Inner<T>& in, hipStream_t st) {
         const int single = sizeof(T) == 4 ? 1 : 0;
         double* part = c->kpart + (size_t)l * 3 * kKLMaxWG;
         KLScal* ks = c->kscal + l;
+        // few partials: their consumers sum them (no separate reduction
+        // launch); band-fused levels take the vector updates into their sweeps
+        const bool fold = G <= kKLFoldMax;
+        const bool band = fused && a1.band;
+        const bool parent_band = fused && in.lv[l - 1].band;
         down(l);
         cycle(l + 1);
-        up(l);
-        // few partials: the consumers sum them (no separate reduction launch)
-        const bool fold = G <= kKLFoldMax;
+        up(l, nullptr, take(l));
         k_kl_dots<T, 0><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
                                                   in.kv1[l], part, c->sc);
-        if (fold) {
+        BandKL<T> kb{};
+        if (band) {
+            if (!fold) k_kl_reduce<0><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+            kb.v = in.kv1[l];
+            kb.part = fold ? part : nullptr;
+            kb.G = G;
+            kb.ks = ks;
+            kb.bout2 = in.kb2[l];
+        } else if (fold) {
             k_kl_axpy<T, true><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], part, G, ks, c->sc);
         } else {
             k_kl_reduce<0><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
             k_kl_axpy<T, false><<<G, kKLThreads, 0, st>>>(n1, a1.bP, in.kv1[l], part, G, ks, c->sc);
         }
-        down(l);
+        const T* b2 = band ? in.kb2[l] : a1.bP;
+        down(l, kb);
         cycle(l + 1);
-        up(l);
-        k_kl_dots<T, 1><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, a1.bP, in.kc1[l],
+        up(l, band ? b2 : nullptr, take(l));
+        k_kl_dots<T, 1><<<G, kKLThreads, 0, st>>>(v1.nx, v1.ny, v1.m, v1.We, v1.Wn, a1.xP, b2, in.kc1[l],
                                                   in.kv1[l], part, c->sc);
-        if (fold) {
+        if (parent_band) {
+            if (!fold) k_kl_reduce<1><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
+            BandKL<T> ke{};
+            ke.v = in.kc1[l];
+            ke.part = fold ? part : nullptr;
+            ke.G = G;
+            ke.ks = ks;
+            ke.single = single;
+            pend[l - 1] = ke;
+        } else if (fold) {
             k_kl_combine<T, true><<<G, kKLThreads, 0, st>>>(n1, a1.xP, in.kc1[l], part, G, ks, c->sc, single);
         } else {
             k_kl_reduce<1><<<1, kRedThreads, 0, st>>>(part, G, ks, c->sc, single);
@@ -809,6 +846,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
     in.kl_mask = 0;
     in.kc1.assign(in.lv.size(), nullptr);
     in.kv1.assign(in.lv.size(), nullptr);
+    in.kb2.assign(in.lv.size(), nullptr);
     if (line && (ctx->opt.mg_cycle == FLD_MG_CYCLE_KL_K || ctx->opt.mg_cycle == FLD_MG_CYCLE_KL_W2)) {
         // every second level from level 1 (levels 1, 3, 5, ...; a bit only
         // acts on a launched level, one above the LDS sub-cycle set below)
@@ -817,6 +855,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
             const size_t n1 = (size_t)in.lv[l].nx * in.lv[l].ny;
             HIPCHK(ctx->alloc(&in.kc1[l], n1));
             HIPCHK(ctx->alloc(&in.kv1[l], n1));
+            HIPCHK(ctx->alloc(&in.kb2[l], n1));
         }
     }
     in.lv[0].bP = in.r;  // the V-cycle's fine right-hand side is the CG residual

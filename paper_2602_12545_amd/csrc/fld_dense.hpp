@@ -351,7 +351,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_solve(DenseGeom g, cons
                                                                double* __restrict__ part_rz,
                                                                const Scalars* __restrict__ sc) {
     if (sc->done) return;
-    __shared__ T sb[kDenseMax];
+    __shared__ __align__(16) T sb[kDenseMax];
     __shared__ double sh[16];
     const int n = g.w * g.nb, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int a = t; a < n; a += kDenseThreads) sb[a] = b[dn_store(g, a)];
@@ -364,13 +364,34 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_solve(DenseGeom g, cons
         if (a < n) {
             const T* row = G + (size_t)a * n;
             T s0 = T(0), s1 = T(0);
-            int c = lane;
+            constexpr int VW = 16 / sizeof(T);
+            if (n % (64 * VW) == 0) {
+                // 16-byte loads: each lane takes VW consecutive entries per
+                // step, four steps in flight
+                using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+                const V* rv = reinterpret_cast<const V*>(row);
+                const V* bv = reinterpret_cast<const V*>(sb);
+                const int nv = n / VW;
 #pragma unroll 4
-            for (; c + 64 < n; c += 128) {
-                s0 += row[c] * sb[c];
-                s1 += row[c + 64] * sb[c + 64];
+                for (int c = lane; c < nv; c += 64) {
+                    const V g = rv[c], x = bv[c];
+                    if constexpr (sizeof(T) == 4) {
+                        s0 += g.x * x.x + g.y * x.y;
+                        s1 += g.z * x.z + g.w * x.w;
+                    } else {
+                        s0 += g.x * x.x;
+                        s1 += g.y * x.y;
+                    }
+                }
+            } else {
+                int c = lane;
+#pragma unroll 4
+                for (; c + 64 < n; c += 128) {
+                    s0 += row[c] * sb[c];
+                    s1 += row[c + 64] * sb[c + 64];
+                }
+                if (c < n) s0 += row[c] * sb[c];
             }
-            if (c < n) s0 += row[c] * sb[c];
             T s = s0 + s1;
             for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
             if (lane == 0) {

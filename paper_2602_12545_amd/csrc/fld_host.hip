@@ -389,6 +389,9 @@ int launch_band(fld_ctx* c, const View<T>& v, int R, const T* b, const T* xin, c
     if (MODE != LINE_ZERO) words += 0.5 * n;
     if (MODE == LINE_PROLONG) words += 0.25 * n;
     if (WRITE_BT) words += n;
+    // a folded Krylov update: A c1 read and b - s1 A c1 stored (zero-start
+    // sweep), or the level below's c1 read with its correction
+    if (kl.v) words += MODE == LINE_ZERO ? 2.0 * n : MODE == LINE_PROLONG ? 0.25 * n : 0.0;
     if (c->sweeps_only) {
         ++c->sweep_launches;
         c->sweep_bytes += words * sizeof(T);

@@ -76,13 +76,13 @@ __global__ void k_dense_stage(DenseGeom g, double* __restrict__ dd, double* __re
     cc[a] = cn * s;
 }
 
-// Matrices of the set-up live in registers as 4 x 4 tiles: thread l of the
-// (W/4)^2 threads of a workgroup holds rows 4 ti .. 4 ti + 3 and columns
-// 4 tj .. 4 tj + 3 (ti = l / (W/4), tj = l % (W/4)); entries beyond the
-// w x w matrix hold the identity.  W = 32: one wavefront, W = 64: four.
-template <int W>
+// Matrices of the set-up live in registers as TS x TS tiles: thread l of the
+// (W/TS)^2 threads of a workgroup holds rows TS ti .. TS ti + TS - 1 and
+// columns TS tj .. (ti = l / (W/TS), tj = l % (W/TS)); entries beyond the
+// w x w matrix hold the identity.
+template <int W, int TS>
 __device__ inline void dn_sync() {
-    if constexpr (W <= 32) {
+    if constexpr ((W / TS) * (W / TS) <= 64) {
         // one wavefront: its LDS accesses complete in order
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -96,31 +96,32 @@ __device__ inline void dn_sync() {
 // without pivoting.  For each pivot the owners of its row and column publish
 // them in LDS (buf: 2 (2 W + 1) doubles, alternate halves for consecutive
 // pivots), one sync, then every thread updates its tile; the pivot chain
-// takes one LDS round trip per pivot and no workgroup barrier for W = 32.
-template <int W>
-__device__ void dn_gj(double (&a)[4][4], int ti, int tj, int w, double* buf) {
-    for (int pr = 0; pr * 4 < w; ++pr) {
+// takes one LDS round trip per pivot (and no workgroup barrier when the tiles
+// fit one wavefront).
+template <int W, int TS>
+__device__ void dn_gj(double (&a)[TS][TS], int ti, int tj, int w, double* buf) {
+    for (int pr = 0; pr * TS < w; ++pr) {
 #pragma unroll
-        for (int pc = 0; pc < 4; ++pc) {
-            const int p = 4 * pr + pc;
+        for (int pc = 0; pc < TS; ++pc) {
+            const int p = TS * pr + pc;
             if (p >= w) break;
             double* rb = buf + (p & 1) * (2 * W + 1);
             double* cb = rb + W;
             const bool prow = ti == pr, pcol = tj == pr;
             if (prow) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) rb[4 * tj + c] = a[pc][c];
+                for (int c = 0; c < TS; ++c) rb[TS * tj + c] = a[pc][c];
             }
             if (pcol) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cb[4 * ti + r] = a[r][pc];
+                for (int r = 0; r < TS; ++r) cb[TS * ti + r] = a[r][pc];
             }
-            dn_sync<W>();
-            double rv[4], cv[4];
+            dn_sync<W, TS>();
+            double rv[TS], cv[TS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                rv[q] = rb[4 * tj + q];
-                cv[q] = cb[4 * ti + q];
+            for (int q = 0; q < TS; ++q) {
+                rv[q] = rb[TS * tj + q];
+                cv[q] = cb[TS * ti + q];
             }
             // d = 1 / a_pp: hardware reciprocal estimate, two Newton steps
             const double x = rb[p];
@@ -130,20 +131,20 @@ __device__ void dn_gj(double (&a)[4][4], int ti, int tj, int w, double* buf) {
             // a_ij - a_ip (a_pj d) for every entry (one FMA each), then the
             // pivot row (a_pj d), column (-a_ip d) and entry (d) set by
             // their owners
-            double vd[4];
+            double vd[TS];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) vd[c] = rv[c] * d;
+            for (int c = 0; c < TS; ++c) vd[c] = rv[c] * d;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < TS; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) a[r][c] = fma(-cv[r], vd[c], a[r][c]);
+                for (int c = 0; c < TS; ++c) a[r][c] = fma(-cv[r], vd[c], a[r][c]);
             if (prow) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) a[pc][c] = vd[c];
+                for (int c = 0; c < TS; ++c) a[pc][c] = vd[c];
             }
             if (pcol) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) a[r][pc] = -cv[r] * d;
+                for (int r = 0; r < TS; ++r) a[r][pc] = -cv[r] * d;
                 if (prow) a[pc][pc] = d;
             }
         }
@@ -160,12 +161,12 @@ __device__ inline double dn_dk(const double* dk, const double* ak, int i, int j)
 // row-major, at k w^2).  The chain's matrix stays in registers from one
 // line to the next.  Dynamic LDS: 3 n + 2 (2 W + 1) doubles (the staged
 // coefficients of every line, the pivot buffers).
-template <int W>
-__global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
+template <int W, int TS>
+__global__ __launch_bounds__((W / TS) * (W / TS)) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
                                                             const double* __restrict__ aa,
                                                             const double* __restrict__ cc, double* __restrict__ SX,
                                                             double* __restrict__ SY) {
-    constexpr int NT = W * W / 16;
+    constexpr int NT = (W / TS) * (W / TS);
     extern __shared__ double dsm[];
     const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
     double* sd = dsm;
@@ -178,10 +179,10 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const d
         sc[e] = cc[e];
     }
     __syncthreads();
-    const int ti = t / (W / 4), tj = t % (W / 4);
+    const int ti = t / (W / TS), tj = t % (W / TS);
     const bool fwd = blockIdx.x == 0;
     double* out = fwd ? SX : SY;
-    double a[4][4];
+    double a[TS][TS];
     for (int s = 0; s + 1 < nb; ++s) {
         const int k = fwd ? s : nb - 1 - s;
         // the eliminated neighbour (line k - 1 forward, k + 1 backward), whose
@@ -190,10 +191,10 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const d
         const double* dk = sd + k * w;
         const double* ak = sa + k * w;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < TS; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int i = 4 * ti + r, j = 4 * tj + c;
+            for (int c = 0; c < TS; ++c) {
+                const int i = TS * ti + r, j = TS * tj + c;
                 double v = i == j ? 1.0 : 0.0;
                 if (i < w && j < w) {
                     v = dn_dk(dk, ak, i, j);
@@ -201,12 +202,12 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const d
                 }
                 a[r][c] = v;
             }
-        dn_gj<W>(a, ti, tj, w, buf);
+        dn_gj<W, TS>(a, ti, tj, w, buf);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < TS; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int i = 4 * ti + r, j = 4 * tj + c;
+            for (int c = 0; c < TS; ++c) {
+                const int i = TS * ti + r, j = TS * tj + c;
                 if (i < w && j < w) out[(size_t)k * nn + i * w + j] = a[r][c];
             }
     }
@@ -214,8 +215,8 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_chain(DenseGeom g, const d
 
 // Diagonal blocks, one workgroup per line k: G_kk in FP64 (SG) and in the
 // inner precision (G, block order, n x n).
-template <typename T, int W>
-__global__ __launch_bounds__(W * W / 16) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
+template <typename T, int W, int TS>
+__global__ __launch_bounds__((W / TS) * (W / TS)) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
                                                            const double* __restrict__ aa,
                                                            const double* __restrict__ cc,
                                                            const double* __restrict__ SX,
@@ -223,15 +224,15 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_diag(DenseGeom g, const do
                                                            T* __restrict__ G) {
     __shared__ double buf[2 * (2 * W + 1)];
     const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x, k = blockIdx.x;
-    const int ti = t / (W / 4), tj = t % (W / 4);
+    const int ti = t / (W / TS), tj = t % (W / TS);
     const double* dk = dd + k * w;
     const double* ak = aa + k * w;
-    double a[4][4];
+    double a[TS][TS];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = 4 * ti + r, j = 4 * tj + c;
+        for (int c = 0; c < TS; ++c) {
+            const int i = TS * ti + r, j = TS * tj + c;
             double v = i == j ? 1.0 : 0.0;
             if (i < w && j < w) {
                 v = dn_dk(dk, ak, i, j);
@@ -246,12 +247,12 @@ __global__ __launch_bounds__(W * W / 16) void k_dense_diag(DenseGeom g, const do
             }
             a[r][c] = v;
         }
-    dn_gj<W>(a, ti, tj, w, buf);
+    dn_gj<W, TS>(a, ti, tj, w, buf);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = 4 * ti + r, j = 4 * tj + c;
+        for (int c = 0; c < TS; ++c) {
+            const int i = TS * ti + r, j = TS * tj + c;
             if (i < w && j < w) {
                 SG[(size_t)k * nn + i * w + j] = a[r][c];
                 G[(size_t)(k * w + i) * n + k * w + j] = static_cast<T>(a[r][c]);

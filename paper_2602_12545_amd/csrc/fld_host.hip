@@ -741,12 +741,12 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
             k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
             if (g.w <= 32) {
                 if (g.nb > 1)
-                    k_dense_chain<32><<<2, 64, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
-                k_dense_diag<T, 32><<<g.nb, 64, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
+                    k_dense_chain<32, 2><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
+                k_dense_diag<T, 32, 4><<<g.nb, 64, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
             } else {
                 if (g.nb > 1)
-                    k_dense_chain<64><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
-                k_dense_diag<T, 64><<<g.nb, 256, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
+                    k_dense_chain<64, 4><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
+                k_dense_diag<T, 64, 4><<<g.nb, 256, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
             }
             if (g.nb > 1)
                 k_dense_off<T, kDenseThreads><<<dim3(g.nb - 1, (g.w + kDenseCols - 1) / kDenseCols), kDenseThreads, 0,
@@ -836,7 +836,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
         const int W = g.w <= 32 ? 32 : 64;
         in.dense_lds = sizeof(double) * (3 * ncl + 2 * (2 * (size_t)W + 1));
         if (in.dense_lds > 65536)
-            HIPCHK(hipFuncSetAttribute(W == 32 ? (const void*)k_dense_chain<32> : (const void*)k_dense_chain<64>,
+            HIPCHK(hipFuncSetAttribute(W == 32 ? (const void*)k_dense_chain<32, 2> : (const void*)k_dense_chain<64, 4>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)in.dense_lds));
     } else {
         HIPCHK(ctx->alloc(&in.Ywork, ncl * ncl));

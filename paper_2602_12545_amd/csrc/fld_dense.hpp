@@ -278,36 +278,40 @@ __global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __r
         const int p = e / C, q = e - p * C;
         X[e] = q < qn ? SG[(size_t)k * nn + p * w + q0 + q] : 0.0;
     }
-    // Q_l^-1 B_{l-1} of line l in registers, loaded two lines ahead (two
-    // register sets, alternating), so the loads' latency hides behind the
-    // products of the two lines before
-    double ya[PER], yb[PER];
-    auto load = [&](double (&y)[PER], int l) {
+    // Q_l^-1 (raw) and b_{l-1} of line l in registers, loaded two lines
+    // ahead (two register sets, alternating) and used only after the next
+    // barrier, so the loads' latency hides behind the products of the two
+    // lines before; B_{l-1} scales the rows of X inside the product
+    __shared__ double sbv[kDenseW];
+    double ya[PER], yb[PER], ba = 0.0, bb = 0.0;
+    auto load = [&](double (&y)[PER], double& bv, int l) {
         const double* Y = SY + (size_t)l * nn;
-        const double* b = cc + (l - 1) * w;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + q * NT;
-            if (e < nn) y[q] = Y[e] * b[e % w];
+            if (e < nn) y[q] = Y[e];
         }
+        bv = t < w ? cc[(l - 1) * w + t] : 0.0;
     };
     const int rt = t >> 3, ct = t & 7;  // rows 2 rt, 2 rt + 1; columns 2 ct, 2 ct + 1
     const int i0 = 2 * rt, j0 = 2 * ct;
     const bool act = i0 < w && j0 < qn;
-    auto step = [&](int l, double (&y)[PER]) {
+    auto step = [&](int l, double (&y)[PER], double& bv) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + q * NT;
             if (e < nn) Yb[e] = y[q];
         }
+        if (t < w) sbv[t] = bv;
         __syncthreads();
-        if (l + 2 < nb) load(y, l + 2);
+        if (l + 2 < nb) load(y, bv, l + 2);
         double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
         if (act) {
             const bool two = i0 + 1 < w;
             for (int m = 0; m < w; ++m) {
+                const double bm = sbv[m];
                 const double y0 = Yb[i0 * w + m], y1 = two ? Yb[(i0 + 1) * w + m] : 0.0;
-                const double x0 = X[m * C + j0], x1 = X[m * C + j0 + 1];
+                const double x0 = X[m * C + j0] * bm, x1 = X[m * C + j0 + 1] * bm;
                 a00 += y0 * x0;
                 a01 += y0 * x1;
                 a10 += y1 * x0;
@@ -334,11 +338,11 @@ __global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __r
             G[(size_t)(k * w + q0 + q) * n + l * w + p] = static_cast<T>(X[p * C + q]);
         }
     };
-    if (k + 1 < nb) load(ya, k + 1);
-    if (k + 2 < nb) load(yb, k + 2);
+    if (k + 1 < nb) load(ya, ba, k + 1);
+    if (k + 2 < nb) load(yb, bb, k + 2);
     for (int l = k + 1; l < nb; l += 2) {
-        step(l, ya);
-        if (l + 1 < nb) step(l + 1, yb);
+        step(l, ya, ba);
+        if (l + 1 < nb) step(l + 1, yb, bb);
     }
 }
 

@@ -278,8 +278,8 @@ def single_step_line(fld, torch, prob, opt, reps):
 
 def other_workloads(fld, torch, W, tuner, accuracy):
     """64 x 64 FP64 solves/s; the 1024 x 1024 and 2048 x 512 grids in mixed,
-    FP64 and FP32-only precision (the 1024 x 1024 schedule autotuned); each
-    against the oracle when accuracy is set."""
+    FP64 and FP32-only precision (the 1024 x 1024 schedule autotuned per
+    precision); each against the oracle when accuracy is set."""
     from oracle import fld_oracle as O
     out = {}
     # (label, precision, norm, rel_tol, reps): the metric's 1e-10 stop and, on
@@ -296,16 +296,21 @@ def other_workloads(fld, torch, W, tuner, accuracy):
         ref = O.step_problem(prob) if accuracy else None
         geom = "stretched Cartesian" if prob.geom == 0 else "spherical-polar"
         res = {"workload": f"{name}: {prob.nx}x{prob.ny} {geom}, one implicit step"}
-        tuned = None
+        # each precision on its own tuned schedule (binary64 cannot hold the
+        # same coarse levels in LDS, so its best schedule differs); the
+        # binary32-only runs take the mixed-precision one
+        tuned = {}
         if tune and tuner is not None:
-            tuned, _ = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
-                                       [(b.kind, b.value) for b in prob.bc], f, prob.dt,
-                                       base=fld.default_options(precision="mixed"), reps=1, cache="")
+            for tp in ("mixed", "fp64"):
+                tuned[tp], _ = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
+                                               [(b.kind, b.value) for b in prob.bc], f, prob.dt,
+                                               base=fld.default_options(precision=tp), reps=1, cache="")
         for label, prec, norm, tol, reps in runs:
             opt = fld.default_options(precision=prec, norm=norm, rel_tol=tol)
-            if tuned is not None:
+            sched = tuned.get("fp64" if prec == "fp64" else "mixed")
+            if sched is not None:
                 for k in ("smoother", "mg_coarse_max", "mg_coarse_op", "chunk", "mg_cycle"):
-                    setattr(opt, k, getattr(tuned, k))
+                    setattr(opt, k, getattr(sched, k))
             ms, infos, (E, T) = single_step_line(fld, torch, prob, opt, reps)
             r = {"ms_per_step": ms, "solves_per_s": 1e3 / ms, "inner_iters": infos[-1]["inner_iters"],
                  "rel_resid": infos[-1]["rel_resid"], "status": infos[-1]["status"], "rel_tol": tol,
@@ -317,8 +322,9 @@ def other_workloads(fld, torch, W, tuner, accuracy):
             res[label] = r
         if "mixed" in res and "fp64" in res:
             res["mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
-        if tuned is not None:
-            res["schedule"] = {k: getattr(tuned, k) for k in ("smoother", "mg_coarse_max", "chunk", "mg_cycle")}
+        for tp, sched in tuned.items():
+            res["schedule" if tp == "mixed" else f"schedule_{tp}"] = {
+                k: getattr(sched, k) for k in ("smoother", "mg_coarse_max", "chunk", "mg_cycle")}
         out[name] = res
     return out
 

@@ -5,22 +5,25 @@
 // iterative sub-cycle takes tens.
 //
 // The level's operator is block tridiagonal when its cells are taken line by
-// line along the shorter grid direction: nb lines of w <= 64 cells, the
-// diagonal blocks D_k tridiagonal (couplings along a line), the off-diagonal
-// blocks -B_k diagonal (couplings between lines k and k + 1, B_k = diag(b_k)).
-// With the forward and backward Schur complements
-//   S_0 = D_0,            S_k = D_k - B_{k-1} S_{k-1}^-1 B_{k-1},
-//   Q_{nb-1} = D_{nb-1},  Q_k = D_k - B_k Q_{k+1}^-1 B_k,
-// the inverse G = A^-1 has the diagonal blocks
-//   G_kk = (D_k - B_{k-1} S_{k-1}^-1 B_{k-1} - B_k Q_{k+1}^-1 B_k)^-1
-// and, below the diagonal, G_lk = Q_l^-1 B_{l-1} G_{l-1,k} (l > k), which
-// follows from block row l of A G = I; the upper blocks are their transposes.
-// Every S_k and Q_k is symmetric positive definite and diagonally dominant
-// (the level's matrix is an M-matrix with a positive mass term), so
-// Gauss-Jordan without pivoting inverts them stably.  All of it runs in FP64;
-// G is stored in the inner precision, in block order (unknown a = k w + p),
-// and the product maps block order to the level's storage order on the way
-// in and out.
+// line along the shorter grid direction: nb lines of w <= 64 cells, diagonal
+// blocks A_t (tridiagonal: couplings along a line) and off-diagonal blocks
+// -C_t between lines t and t + 1 (diagonal: couplings across lines).  The
+// inverse G = A^-1 comes from block cyclic reduction, whose sequential depth
+// is log2(nb) block inversions where a line-by-line Schur chain takes nb.
+// Eliminating the odd lines t of a level (E_t = A_t^-1 C_{t-1}^T,
+// F_t = A_t^-1 C_t) leaves the even lines with
+//   A'_u = A_2u - C_{2u-1}^T F_{2u-1} - C_2u E_{2u+1},  C'_u = C_2u F_{2u+1},
+// again block tridiagonal; its inverse is G restricted to those lines.
+// Going back down, block row t of A G = I gives every block of an odd line
+// from its two neighbours:
+//   G_tj = E_t G_{t-1,j} + F_t G_{t+1,j} (+ A_t^-1 when j = t),
+// first for even j (neighbours' blocks known from the level above), then for
+// odd j (the even-odd blocks just formed).  Every block inverted is a Schur
+// complement of the symmetric positive definite M-matrix A, so Gauss-Jordan
+// without pivoting inverts it stably, and the back-substitution only adds
+// non-negative terms.  All of it runs in FP64; G is stored in the inner
+// precision, in block order (unknown a = k w + p), and the product maps block
+// order to the level's storage order on the way in and out.
 #pragma once
 
 #include "fld_mg.hpp"
@@ -31,7 +34,6 @@ constexpr int kDenseMax = 4096;   // largest level solved this way (cells)
 constexpr int kDenseW = 64;       // line length bound: min(nx, ny) <= 64 when nx ny <= 4096
 constexpr int kDenseThreads = 256;
 constexpr int kDenseRows = 8;     // rows of G per workgroup of the product (two per wavefront)
-constexpr int kDenseCols = 16;    // columns of a block column per workgroup of the off-diagonal chains
 
 struct DenseGeom {
     int nx, ny;      // the level's grid
@@ -156,193 +158,341 @@ __device__ inline double dn_dk(const double* dk, const double* ak, int i, int j)
     return i == j ? dk[i] : j == i + 1 ? -ak[i] : i == j + 1 ? -ak[j] : 0.0;
 }
 
-// The two Schur chains, one workgroup each: block 0 stores S_k^-1 (k = 0 ..
-// nb-2) in SX, block 1 stores Q_k^-1 (k = nb-1 .. 1) in SY (w x w each,
-// row-major, at k w^2).  The chain's matrix stays in registers from one
-// line to the next.  Dynamic LDS: 3 n + 2 (2 W + 1) doubles (the staged
-// coefficients of every line, the pivot buffers).
+// Matrices of the reduction are w x w, row-major (leading dimension w), one
+// per line or per eliminated line; each one a kernel reads transposed is also
+// stored transposed, so every LDS operand is a straight copy (leading
+// dimension W).  Workgroups of the reduction have 256 threads holding TS x TS
+// register tiles (TS = W / 16).
+template <int W>
+constexpr size_t dn_lds_bytes() {
+    return sizeof(double) * (2 * (size_t)W * W + 2 * (2 * W + 1));
+}
+
+// A w x w matrix (leading dimension ldm) staged through registers: all of a
+// thread's loads are issued before any is stored to LDS.
+template <int W>
+struct DnFrag {
+    static constexpr int PER = W * W / 256;
+    double v[PER];
+    __device__ inline void fetch(const double* __restrict__ M, int ldm, int w) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+            if (e < w * w) v[q] = M[(size_t)i * ldm + k];
+        }
+    }
+    __device__ inline void put(double* S, int w) const {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+            if (e < w * w) S[i * W + k] = v[q];
+        }
+    }
+};
+
+// acc += X Y over k < w, with Xt[k][i] = X[i][k] and Y[k][j] in LDS (leading
+// dimension W; the rows k of both beyond w up to the next multiple of four
+// hold zeros).  16-byte LDS reads, four k per chunk, the next chunk's reads
+// issued before the current chunk's FMAs.
 template <int W, int TS>
-__global__ __launch_bounds__((W / TS) * (W / TS)) void k_dense_chain(DenseGeom g, const double* __restrict__ dd,
-                                                            const double* __restrict__ aa,
-                                                            const double* __restrict__ cc, double* __restrict__ SX,
-                                                            double* __restrict__ SY) {
-    constexpr int NT = (W / TS) * (W / TS);
-    extern __shared__ double dsm[];
-    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
-    double* sd = dsm;
-    double* sa = sd + n;
-    double* sc = sa + n;
-    double* buf = sc + n;
-    for (int e = t; e < n; e += NT) {
-        sd[e] = dd[e];
-        sa[e] = aa[e];
-        sc[e] = cc[e];
+struct DnChunk {
+    double x[4][TS], y[4][TS];
+    __device__ inline void load(const double* Xt, const double* Y, int k, int ti, int tj) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < TS; r += 2) {
+                const double2 x2 = *reinterpret_cast<const double2*>(Xt + (k + u) * W + TS * ti + r);
+                const double2 y2 = *reinterpret_cast<const double2*>(Y + (k + u) * W + TS * tj + r);
+                x[u][r] = x2.x;
+                x[u][r + 1] = x2.y;
+                y[u][r] = y2.x;
+                y[u][r + 1] = y2.y;
+            }
     }
-    __syncthreads();
-    const int ti = t / (W / TS), tj = t % (W / TS);
-    const bool fwd = blockIdx.x == 0;
-    double* out = fwd ? SX : SY;
-    double a[TS][TS];
-    for (int s = 0; s + 1 < nb; ++s) {
-        const int k = fwd ? s : nb - 1 - s;
-        // the eliminated neighbour (line k - 1 forward, k + 1 backward), whose
-        // inverse the tiles hold, couples to line k through b_{k-1} or b_k
-        const int kb = fwd ? k - 1 : k;
-        const double* dk = sd + k * w;
-        const double* ak = sa + k * w;
+    __device__ inline void fma_into(double (&acc)[TS][TS]) const {
 #pragma unroll
-        for (int r = 0; r < TS; ++r)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int c = 0; c < TS; ++c) {
-                const int i = TS * ti + r, j = TS * tj + c;
-                double v = i == j ? 1.0 : 0.0;
-                if (i < w && j < w) {
-                    v = dn_dk(dk, ak, i, j);
-                    if (s > 0) v -= sc[kb * w + i] * a[r][c] * sc[kb * w + j];
-                }
-                a[r][c] = v;
-            }
-        dn_gj<W, TS>(a, ti, tj, w, buf);
+            for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int r = 0; r < TS; ++r)
-#pragma unroll
-            for (int c = 0; c < TS; ++c) {
-                const int i = TS * ti + r, j = TS * tj + c;
-                if (i < w && j < w) out[(size_t)k * nn + i * w + j] = a[r][c];
-            }
+                for (int c = 0; c < TS; ++c) acc[r][c] = fma(x[u][r], y[u][c], acc[r][c]);
+    }
+};
+
+template <int W, int TS>
+__device__ inline void dn_mm(const double* Xt, const double* Y, int w, int ti, int tj, double (&acc)[TS][TS]) {
+    static_assert(TS % 2 == 0 && W % 4 == 0, "pairs of doubles, chunks of four");
+    const int nk = (w + 3) / 4;
+    DnChunk<W, TS> ca, cb;
+    ca.load(Xt, Y, 0, ti, tj);
+    for (int c = 0; c < nk; c += 2) {
+        if (c + 1 < nk) cb.load(Xt, Y, 4 * (c + 1), ti, tj);
+        ca.fma_into(acc);
+        if (c + 1 < nk) {
+            if (c + 2 < nk) ca.load(Xt, Y, 4 * (c + 2), ti, tj);
+            cb.fma_into(acc);
+        }
     }
 }
 
-// Diagonal blocks, one workgroup per line k: G_kk in FP64 (SG) and in the
-// inner precision (G, block order, n x n).
-template <typename T, int W, int TS>
-__global__ __launch_bounds__((W / TS) * (W / TS)) void k_dense_diag(DenseGeom g, const double* __restrict__ dd,
-                                                           const double* __restrict__ aa,
-                                                           const double* __restrict__ cc,
-                                                           const double* __restrict__ SX,
-                                                           const double* __restrict__ SY, double* __restrict__ SG,
-                                                           T* __restrict__ G) {
-    __shared__ double buf[2 * (2 * W + 1)];
-    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x, k = blockIdx.x;
-    const int ti = t / (W / TS), tj = t % (W / TS);
-    const double* dk = dd + k * w;
-    const double* ak = aa + k * w;
-    double a[TS][TS];
+// Zeros over the two LDS operands, so that the rows and columns beyond w
+// read by the chunked products stay zero (every later copy writes only the
+// w x w part).
+template <int W>
+__device__ inline void dn_lds_zero(double* S) {
+    for (int e = threadIdx.x; e < 2 * W * W; e += 256) S[e] = 0.0;
+}
+
+// Register tiles of a w x w matrix (leading dimension ldm); beyond w the
+// identity (unit) or zero.
+template <int TS>
+__device__ inline void dn_tile_load(double (&a)[TS][TS], const double* __restrict__ M, int ldm, int w, int ti, int tj,
+                                    bool unit) {
 #pragma unroll
     for (int r = 0; r < TS; ++r)
 #pragma unroll
         for (int c = 0; c < TS; ++c) {
             const int i = TS * ti + r, j = TS * tj + c;
-            double v = i == j ? 1.0 : 0.0;
-            if (i < w && j < w) {
-                v = dn_dk(dk, ak, i, j);
-                if (k > 0) {
-                    const double* b = cc + (k - 1) * w;
-                    v -= b[i] * SX[(size_t)(k - 1) * nn + i * w + j] * b[j];
-                }
-                if (k + 1 < nb) {
-                    const double* b = cc + k * w;
-                    v -= b[i] * SY[(size_t)(k + 1) * nn + i * w + j] * b[j];
-                }
-            }
-            a[r][c] = v;
+            a[r][c] = i < w && j < w ? M[(size_t)i * ldm + j] : (unit && i == j ? 1.0 : 0.0);
         }
+}
+
+template <typename T, int TS>
+__device__ inline void dn_tile_store(const double (&a)[TS][TS], T* __restrict__ M, int ldm, int w, int ti, int tj,
+                                     bool trans) {
+#pragma unroll
+    for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+            const int i = TS * ti + r, j = TS * tj + c;
+            if (i < w && j < w) M[trans ? (size_t)j * ldm + i : (size_t)i * ldm + j] = static_cast<T>(a[r][c]);
+        }
+}
+
+template <int TS>
+__device__ inline void dn_zero(double (&a)[TS][TS]) {
+#pragma unroll
+    for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) a[r][c] = 0.0;
+}
+
+// Level 0 of the reduction: A_k (tridiagonal) and C_k (diagonal, so also its
+// own transpose Ct_k) of every line, dense.
+__global__ void k_bcr_init(int w, int nb, const double* __restrict__ dd, const double* __restrict__ aa,
+                           const double* __restrict__ cc, double* __restrict__ A, double* __restrict__ C,
+                           double* __restrict__ Ct) {
+    const int nn = w * w;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nb * nn) return;
+    const int k = e / nn, r = e - k * nn, i = r / w, j = r - i * w;
+    A[e] = dn_dk(dd + k * w, aa + k * w, i, j);
+    if (k + 1 < nb) {
+        const double c = i == j ? cc[k * w + i] : 0.0;
+        C[e] = c;
+        Ct[e] = c;
+    }
+}
+
+// Odd lines t = 2 x + 1 of a level of N lines, one workgroup each: A_t^-1,
+// E_t and F_t (F_t only when line t + 1 exists), each also stored transposed
+// (Et, Ft) for the back-substitution; slot x of the level's arrays.  Ct holds
+// the level's C transposed.  Dynamic LDS: dn_lds_bytes<W>().
+template <int W, int TS>
+__global__ __launch_bounds__(256) void k_bcr_elim(int w, int N, const double* __restrict__ A,
+                                                  const double* __restrict__ C, const double* __restrict__ Ct,
+                                                  double* __restrict__ Ainv, double* __restrict__ E,
+                                                  double* __restrict__ F, double* __restrict__ Et,
+                                                  double* __restrict__ Ft) {
+    static_assert((W / TS) * (W / TS) == 256, "256 threads, TS x TS tiles");
+    extern __shared__ __align__(16) double dsm[];
+    double* Xt = dsm;
+    double* Y = Xt + W * W;
+    double* buf = Y + W * W;
+    const int x = blockIdx.x, t = 2 * x + 1, nn = w * w;
+    const bool hasF = t + 1 < N;
+    dn_lds_zero<W>(dsm);
+    const int ti = threadIdx.x / (W / TS), tj = threadIdx.x % (W / TS);
+    // the right-hand factors' loads run beside the inversion
+    DnFrag<W> y1, y2;
+    y1.fetch(Ct + (size_t)(t - 1) * nn, w, w);
+    if (hasF) y2.fetch(C + (size_t)t * nn, w, w);
+    double a[TS][TS];
+    dn_tile_load<TS>(a, A + (size_t)t * nn, w, w, ti, tj, true);
     dn_gj<W, TS>(a, ti, tj, w, buf);
+    dn_tile_store<double, TS>(a, Ainv + (size_t)x * nn, w, w, ti, tj, false);
 #pragma unroll
     for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-            const int i = TS * ti + r, j = TS * tj + c;
-            if (i < w && j < w) {
-                SG[(size_t)k * nn + i * w + j] = a[r][c];
-                G[(size_t)(k * w + i) * n + k * w + j] = static_cast<T>(a[r][c]);
-            }
-        }
+        for (int c = 0; c < TS; ++c) Xt[(TS * tj + c) * W + TS * ti + r] = a[r][c];
+    y1.put(Y, w);
+    __syncthreads();
+    double acc[TS][TS];
+    dn_zero<TS>(acc);
+    dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+    dn_tile_store<double, TS>(acc, E + (size_t)x * nn, w, w, ti, tj, false);
+    dn_tile_store<double, TS>(acc, Et + (size_t)x * nn, w, w, ti, tj, true);
+    if (hasF) {
+        __syncthreads();
+        y2.put(Y, w);
+        __syncthreads();
+        dn_zero<TS>(acc);
+        dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+        dn_tile_store<double, TS>(acc, F + (size_t)x * nn, w, w, ti, tj, false);
+        dn_tile_store<double, TS>(acc, Ft + (size_t)x * nn, w, w, ti, tj, true);
+    }
 }
 
-// Blocks below (and, transposed, above) the diagonal: workgroup (k, c) walks
-// down block column k for the columns c kDenseCols .. of its diagonal block,
-// X <- Q_l^-1 B_{l-1} X for l = k + 1 .. nb - 1, storing each G_lk and G_kl.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_dense_off(DenseGeom g, const double* __restrict__ cc,
-                                                  const double* __restrict__ SY, const double* __restrict__ SG,
-                                                  T* __restrict__ G) {
-    static_assert(NT == 256, "2 x 2 tiles: 32 row pairs x 8 column pairs");
-    constexpr int PER = kDenseW * kDenseW / NT;
-    constexpr int C = kDenseCols;
-    __shared__ double Yb[kDenseW * kDenseW];
-    __shared__ double X[kDenseW * C];
-    const int w = g.w, nb = g.nb, n = w * nb, nn = w * w, t = threadIdx.x;
-    const int k = blockIdx.x, q0 = blockIdx.y * C, qn = min(C, w - q0);
-    for (int e = t; e < w * C; e += NT) {
-        const int p = e / C, q = e - p * C;
-        X[e] = q < qn ? SG[(size_t)k * nn + p * w + q0 + q] : 0.0;
+// Even lines t = 2 u of the level, one workgroup each: A'_u, C'_u and C'_u
+// transposed of the next level (E, F: this level's slots).  Dynamic LDS:
+// dn_lds_bytes<W>().
+template <int W, int TS>
+__global__ __launch_bounds__(256) void k_bcr_reduce(int w, int N, const double* __restrict__ A,
+                                                    const double* __restrict__ C, const double* __restrict__ Ct,
+                                                    const double* __restrict__ E, const double* __restrict__ F,
+                                                    double* __restrict__ A2, double* __restrict__ C2,
+                                                    double* __restrict__ C2t) {
+    static_assert((W / TS) * (W / TS) == 256, "256 threads, TS x TS tiles");
+    extern __shared__ __align__(16) double dsm[];
+    double* Xt = dsm;
+    double* Y = Xt + W * W;
+    const int u = blockIdx.x, t = 2 * u, nn = w * w;
+    const int ti = threadIdx.x / (W / TS), tj = threadIdx.x % (W / TS);
+    const bool lo = t >= 1, hi = t + 1 < N, c2 = t + 2 < N;
+    dn_lds_zero<W>(dsm);
+    __syncthreads();
+    DnFrag<W> fx, fy;
+    // C_{t-1}^T F_{t-1} (Xt[k][i] = C_{t-1}[k][i]), then C_t E_{t+1} and
+    // C_t F_{t+1} (Xt[k][i] = C_t[i][k] = Ct_t[k][i]); each next operand's
+    // loads run beside the current product
+    if (lo) {
+        fx.fetch(C + (size_t)(t - 1) * nn, w, w);
+        fy.fetch(F + (size_t)((t - 2) / 2) * nn, w, w);
+    } else if (hi) {
+        fx.fetch(Ct + (size_t)t * nn, w, w);
+        fy.fetch(E + (size_t)(t / 2) * nn, w, w);
     }
-    // Q_l^-1 (raw) and b_{l-1} of line l in registers, loaded two lines
-    // ahead (two register sets, alternating) and used only after the next
-    // barrier, so the loads' latency hides behind the products of the two
-    // lines before; B_{l-1} scales the rows of X inside the product
-    __shared__ double sbv[kDenseW];
-    double ya[PER], yb[PER], ba = 0.0, bb = 0.0;
-    auto load = [&](double (&y)[PER], double& bv, int l) {
-        const double* Y = SY + (size_t)l * nn;
+    double acc[TS][TS], p[TS][TS];
+    dn_tile_load<TS>(acc, A + (size_t)t * nn, w, w, ti, tj, false);
+    dn_zero<TS>(p);
+    if (lo) {
+        fx.put(Xt, w);
+        fy.put(Y, w);
+        __syncthreads();
+        if (hi) {
+            fx.fetch(Ct + (size_t)t * nn, w, w);
+            fy.fetch(E + (size_t)(t / 2) * nn, w, w);
+        }
+        dn_mm<W, TS>(Xt, Y, w, ti, tj, p);
+        __syncthreads();
+    }
+    if (hi) {
+        fx.put(Xt, w);
+        fy.put(Y, w);
+        __syncthreads();
+        if (c2) fy.fetch(F + (size_t)(t / 2) * nn, w, w);
+        dn_mm<W, TS>(Xt, Y, w, ti, tj, p);
+        if (c2) {
+            __syncthreads();
+            fy.put(Y, w);
+            __syncthreads();
+            double q[TS][TS];
+            dn_zero<TS>(q);
+            dn_mm<W, TS>(Xt, Y, w, ti, tj, q);
+            dn_tile_store<double, TS>(q, C2 + (size_t)u * nn, w, w, ti, tj, false);
+            dn_tile_store<double, TS>(q, C2t + (size_t)u * nn, w, w, ti, tj, true);
+        }
+    }
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * NT;
-            if (e < nn) y[q] = Y[e];
-        }
-        bv = t < w ? cc[(l - 1) * w + t] : 0.0;
-    };
-    const int rt = t >> 3, ct = t & 7;  // rows 2 rt, 2 rt + 1; columns 2 ct, 2 ct + 1
-    const int i0 = 2 * rt, j0 = 2 * ct;
-    const bool act = i0 < w && j0 < qn;
-    auto step = [&](int l, double (&y)[PER], double& bv) {
+    for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * NT;
-            if (e < nn) Yb[e] = y[q];
+        for (int c = 0; c < TS; ++c) acc[r][c] -= p[r][c];
+    dn_tile_store<double, TS>(acc, A2 + (size_t)u * nn, w, w, ti, tj, false);
+}
+
+// The one line left: G_00 = A_0^-1 into Gw (leading dimension n), and into
+// G when no level was reduced and G is a separate inner-precision copy.
+template <typename T, int W, int TS>
+__global__ __launch_bounds__(256) void k_bcr_top(int w, int n, const double* __restrict__ A,
+                                                 double* __restrict__ Gw, T* __restrict__ G) {
+    __shared__ double buf[2 * (2 * W + 1)];
+    const int ti = threadIdx.x / (W / TS), tj = threadIdx.x % (W / TS);
+    double a[TS][TS];
+    dn_tile_load<TS>(a, A, w, w, ti, tj, true);
+    dn_gj<W, TS>(a, ti, tj, w, buf);
+    dn_tile_store<double, TS>(a, Gw, n, w, ti, tj, false);
+    if (G != nullptr) dn_tile_store<T, TS>(a, G, n, w, ti, tj, false);
+}
+
+// Back-substitution over the odd lines t = 2 x + 1 of a level whose lines are
+// the original lines t sg, against line j: G_tj = E_t G_{t-1,j} +
+// F_t G_{t+1,j}, plus A_t^-1 when j = t.  OE (j = 2 y even): G_tj and
+// G_jt = G_tj^T into Gw; G (non-null at the last level when it is a separate
+// inner-precision copy) receives the same blocks and the even-even blocks
+// read here: G_{t-1,j}, and G_{t+1,j} when t + 1 is the last line.  !OE
+// (j = 2 y + 1 >= t): G_tj and its transpose into Gw, or only into G when G
+// is non-null.  Dynamic LDS: dn_lds_bytes<W>().
+template <typename T, int W, int TS, bool OE>
+__global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, const double* __restrict__ Ainv,
+                                                  const double* __restrict__ Et, const double* __restrict__ Ft,
+                                                  double* __restrict__ Gw, T* __restrict__ G) {
+    static_assert((W / TS) * (W / TS) == 256, "256 threads, TS x TS tiles");
+    extern __shared__ __align__(16) double dsm[];
+    double* Xt = dsm;
+    double* Y = Xt + W * W;
+    const int x = blockIdx.x, t = 2 * x + 1, j = OE ? 2 * blockIdx.y : 2 * blockIdx.y + 1, nn = w * w;
+    if (!OE && t > j) return;
+    const int ti = threadIdx.x / (W / TS), tj = threadIdx.x % (W / TS);
+    const bool hi = t + 1 < N;
+    dn_lds_zero<W>(dsm);
+    __syncthreads();
+    const size_t col = (size_t)j * sg * w;
+    auto blk = [&](int line) { return (size_t)line * sg * w * n + col; };
+    DnFrag<W> fx, fy;
+    fx.fetch(Et + (size_t)x * nn, w, w);
+    fy.fetch(Gw + blk(t - 1), n, w);
+    double acc[TS][TS];
+    if (!OE && t == j)
+        dn_tile_load<TS>(acc, Ainv + (size_t)x * nn, w, w, ti, tj, false);
+    else
+        dn_zero<TS>(acc);
+    fx.put(Xt, w);
+    fy.put(Y, w);
+    __syncthreads();
+    if (OE && G != nullptr)
+#pragma unroll
+        for (int q = 0; q < DnFrag<W>::PER; ++q) {
+            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+            if (e < nn) G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
         }
-        if (t < w) sbv[t] = bv;
+    if (hi) {
+        fx.fetch(Ft + (size_t)x * nn, w, w);
+        fy.fetch(Gw + blk(t + 1), n, w);
+    }
+    dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+    if (hi) {
         __syncthreads();
-        if (l + 2 < nb) load(y, bv, l + 2);
-        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
-        if (act) {
-            const bool two = i0 + 1 < w;
-            for (int m = 0; m < w; ++m) {
-                const double bm = sbv[m];
-                const double y0 = Yb[i0 * w + m], y1 = two ? Yb[(i0 + 1) * w + m] : 0.0;
-                const double x0 = X[m * C + j0] * bm, x1 = X[m * C + j0 + 1] * bm;
-                a00 += y0 * x0;
-                a01 += y0 * x1;
-                a10 += y1 * x0;
-                a11 += y1 * x1;
+        fx.put(Xt, w);
+        fy.put(Y, w);
+        __syncthreads();
+        if (OE && G != nullptr && t + 1 == N - 1)
+#pragma unroll
+            for (int q = 0; q < DnFrag<W>::PER; ++q) {
+                const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+                if (e < nn) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
             }
-        }
-        __syncthreads();
-        if (act) {
-            X[i0 * C + j0] = a00;
-            X[i0 * C + j0 + 1] = a01;
-            if (i0 + 1 < w) {
-                X[(i0 + 1) * C + j0] = a10;
-                X[(i0 + 1) * C + j0 + 1] = a11;
-            }
-        }
-        __syncthreads();
-        // G_lk: rows l w + p, columns k w + q0 + q; G_kl the transpose
-        for (int e = t; e < w * qn; e += NT) {
-            const int p = e / qn, q = e - p * qn;
-            G[(size_t)(l * w + p) * n + k * w + q0 + q] = static_cast<T>(X[p * C + q]);
-        }
-        for (int e = t; e < w * qn; e += NT) {
-            const int q = e / w, p = e - q * w;
-            G[(size_t)(k * w + q0 + q) * n + l * w + p] = static_cast<T>(X[p * C + q]);
-        }
-    };
-    if (k + 1 < nb) load(ya, ba, k + 1);
-    if (k + 2 < nb) load(yb, bb, k + 2);
-    for (int l = k + 1; l < nb; l += 2) {
-        step(l, ya, ba);
-        if (l + 1 < nb) step(l + 1, yb, bb);
+        dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+    }
+    const size_t tj0 = (size_t)t * sg * w * n + col, jt0 = (size_t)j * sg * w * n + (size_t)t * sg * w;
+    const bool mirror = OE || t != j;
+    if (OE || G == nullptr) {
+        dn_tile_store<double, TS>(acc, Gw + tj0, n, w, ti, tj, false);
+        if (mirror) dn_tile_store<double, TS>(acc, Gw + jt0, n, w, ti, tj, true);
+    }
+    if (G != nullptr) {
+        dn_tile_store<T, TS>(acc, G + tj0, n, w, ti, tj, false);
+        if (mirror) dn_tile_store<T, TS>(acc, G + jt0, n, w, ti, tj, true);
     }
 }
 

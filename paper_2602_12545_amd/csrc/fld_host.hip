@@ -76,13 +76,16 @@ struct Inner {
     std::vector<LevelT<T>> lv;
     T* Ainv = nullptr;
     double* Ywork = nullptr;  // coarse inverse set-up: forward solutions
-    // a coarsest level above kCoarseMax cells: its inverse from block Schur
-    // complements (staged coefficients, the chains' inverses, the diagonal
-    // blocks; FP64) and the multi-workgroup product
+    // a coarsest level above kCoarseMax cells: its inverse by block cyclic
+    // reduction (FP64: staged coefficients, two levels' line blocks A, C and
+    // C transposed, per eliminated line A^-1, E, F and their transposes, the whole
+    // inverse Gw, which is Ainv itself in binary64) and the multi-workgroup
+    // product
     bool dense = false;
     DenseGeom dg{};
-    double *dd = nullptr, *aa = nullptr, *cc = nullptr, *SX = nullptr, *SY = nullptr, *SG = nullptr;
-    size_t dense_lds = 0;
+    double *dd = nullptr, *aa = nullptr, *cc = nullptr;
+    double *rA[2] = {nullptr, nullptr}, *rC[2] = {nullptr, nullptr}, *rCt[2] = {nullptr, nullptr};
+    double *rAinv = nullptr, *rE = nullptr, *rF = nullptr, *rEt = nullptr, *rFt = nullptr, *Gw = nullptr;
     T *r = nullptr, *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     int sub_first = -1;                   // first level of the one-workgroup coarse sub-cycle (-1: none)
     // Krylov-accelerated launched levels (mg_cycle KL_K / KL_W2): bit l of
@@ -725,32 +728,61 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
     }
     Level64& cl = c->h64[L - 1];
     {
-        // one workgroup, ~40-240 us: it runs beside the copies below, the
-        // prologue and the first down-leg of the V-cycle, which do not need
-        // the inverse
+        // the coarsest inverse (one workgroup, ~40-240 us, up to kCoarseMax
+        // cells; the block cyclic reduction, ~0.2-0.9 ms, above): it runs
+        // beside the copies below, the prologue and the first down-leg of
+        // the V-cycle, which do not need the inverse
         fld_ctx* ctx = c;
         HIPCHK(hipEventRecord(c->setup_fork, st));
         HIPCHK(hipStreamWaitEvent(c->setup_stream, c->setup_fork, 0));
         hipStream_t ss = c->setup_stream;
         const int w = std::min(cl.nx, cl.ny), tr = in.lv[L - 1].tr ? 1 : 0;
         if (in.dense) {
-            // block Schur complements: staged coefficients, the two chains,
-            // the diagonal blocks, then the off-diagonal block columns
+            // block cyclic reduction: staged coefficients, the level-0 line
+            // blocks, the reduction up to one line, its inverse, the
+            // back-substitution down to level 0 (the last level also writes
+            // the inner-precision copy when that is a separate array)
             const DenseGeom& g = in.dg;
-            const int n = g.w * g.nb;
+            const int n = g.w * g.nb, w = g.w, nn = g.w * g.w;
             k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
-            if (g.w <= 32) {
-                if (g.nb > 1)
-                    k_dense_chain<32, 2><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
-                k_dense_diag<T, 32, 4><<<g.nb, 64, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
-            } else {
-                if (g.nb > 1)
-                    k_dense_chain<64, 4><<<2, 256, in.dense_lds, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY);
-                k_dense_diag<T, 64, 4><<<g.nb, 256, 0, ss>>>(g, in.dd, in.aa, in.cc, in.SX, in.SY, in.SG, in.Ainv);
-            }
-            if (g.nb > 1)
-                k_dense_off<T, kDenseThreads><<<dim3(g.nb - 1, (g.w + kDenseCols - 1) / kDenseCols), kDenseThreads, 0,
-                                                ss>>>(g, in.cc, in.SY, in.SG, in.Ainv);
+            k_bcr_init<<<(g.nb * nn + 255) / 256, 256, 0, ss>>>(w, g.nb, in.dd, in.aa, in.cc, in.rA[0], in.rC[0],
+                                                                in.rCt[0]);
+            T* Gsep = std::is_same<T, double>::value ? nullptr : in.Ainv;
+            auto run = [&](auto Wc) {
+                constexpr int W = decltype(Wc)::value, TS = W / 16;
+                constexpr size_t lds = dn_lds_bytes<W>();
+                std::vector<int> Ns, offs;
+                int N = g.nb, off = 0, l = 0;
+                for (; N > 1; ++l) {
+                    const double *A = in.rA[l & 1], *C = in.rC[l & 1], *Ct = in.rCt[l & 1];
+                    const int nx = (l + 1) & 1;
+                    k_bcr_elim<W, TS><<<N / 2, 256, lds, ss>>>(w, N, A, C, Ct, in.rAinv + (size_t)off * nn,
+                                                               in.rE + (size_t)off * nn, in.rF + (size_t)off * nn,
+                                                               in.rEt + (size_t)off * nn, in.rFt + (size_t)off * nn);
+                    k_bcr_reduce<W, TS><<<(N + 1) / 2, 256, lds, ss>>>(w, N, A, C, Ct, in.rE + (size_t)off * nn,
+                                                                       in.rF + (size_t)off * nn, in.rA[nx], in.rC[nx],
+                                                                       in.rCt[nx]);
+                    Ns.push_back(N);
+                    offs.push_back(off);
+                    off += N / 2;
+                    N = (N + 1) / 2;
+                }
+                k_bcr_top<T, W, TS><<<1, 256, 0, ss>>>(w, n, in.rA[l & 1], in.Gw, l == 0 ? Gsep : nullptr);
+                for (int lv = l - 1; lv >= 0; --lv) {
+                    const int Nl = Ns[lv], o = offs[lv], sg = 1 << lv;
+                    T* G = lv == 0 ? Gsep : nullptr;
+                    const double *Ai = in.rAinv + (size_t)o * nn, *Et = in.rEt + (size_t)o * nn,
+                                 *Ft = in.rFt + (size_t)o * nn;
+                    k_bcr_back<T, W, TS, true><<<dim3(Nl / 2, (Nl + 1) / 2), 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft,
+                                                                                           in.Gw, G);
+                    k_bcr_back<T, W, TS, false><<<dim3(Nl / 2, Nl / 2), 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft,
+                                                                                       in.Gw, G);
+                }
+            };
+            if (w <= 32)
+                run(std::integral_constant<int, 32>{});
+            else
+                run(std::integral_constant<int, 64>{});
         } else if (w <= 4)
             k_coarse_setup<T, 4><<<1, kCoarseMax, 0, ss>>>(cl.nx, cl.ny, tr, cl.m, cl.We, cl.Wn, c->mu, in.Ywork,
                                                            in.Ainv);
@@ -829,15 +861,35 @@ fld_status alloc_inner(fld_ctx* ctx) {
         HIPCHK(ctx->alloc(&in.dd, ncl));
         HIPCHK(ctx->alloc(&in.aa, ncl));
         HIPCHK(ctx->alloc(&in.cc, ncl));
-        HIPCHK(ctx->alloc(&in.SX, ncl * g.w));
-        HIPCHK(ctx->alloc(&in.SY, ncl * g.w));
-        HIPCHK(ctx->alloc(&in.SG, ncl * g.w));
-        // the chain's staged coefficients (3 per cell) and its pivot buffers
-        const int W = g.w <= 32 ? 32 : 64;
-        in.dense_lds = sizeof(double) * (3 * ncl + 2 * (2 * (size_t)W + 1));
-        if (in.dense_lds > 65536)
-            HIPCHK(hipFuncSetAttribute(W == 32 ? (const void*)k_dense_chain<32, 2> : (const void*)k_dense_chain<64, 4>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)in.dense_lds));
+        // the reduction's line blocks (two levels) and, per eliminated line
+        // (fewer than nb over all levels), A^-1, E, F, E^T, F^T
+        const size_t blocks = (size_t)g.nb * g.w * g.w;
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(ctx->alloc(&in.rA[i], blocks));
+            HIPCHK(ctx->alloc(&in.rC[i], blocks));
+            HIPCHK(ctx->alloc(&in.rCt[i], blocks));
+        }
+        HIPCHK(ctx->alloc(&in.rAinv, blocks));
+        HIPCHK(ctx->alloc(&in.rE, blocks));
+        HIPCHK(ctx->alloc(&in.rF, blocks));
+        HIPCHK(ctx->alloc(&in.rEt, blocks));
+        HIPCHK(ctx->alloc(&in.rFt, blocks));
+        if constexpr (std::is_same<T, double>::value)
+            in.Gw = in.Ainv;
+        else
+            HIPCHK(ctx->alloc(&in.Gw, ncl * ncl));
+        auto lds_attr = [&](auto Wc) -> hipError_t {
+            constexpr int W = decltype(Wc)::value, TS = W / 16;
+            const int b = (int)dn_lds_bytes<W>();
+            const void* fs[] = {(const void*)k_bcr_elim<W, TS>, (const void*)k_bcr_reduce<W, TS>,
+                                (const void*)k_bcr_back<T, W, TS, true>, (const void*)k_bcr_back<T, W, TS, false>};
+            for (const void* f : fs) {
+                const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        HIPCHK(g.w <= 32 ? lds_attr(std::integral_constant<int, 32>{}) : lds_attr(std::integral_constant<int, 64>{}));
     } else {
         HIPCHK(ctx->alloc(&in.Ywork, ncl * ncl));
     }

@@ -295,6 +295,111 @@ __global__ void k_bcr_init(int w, int nb, const double* __restrict__ dd, const d
     }
 }
 
+// Level 0 of the reduction, one workgroup of two wavefronts per line t
+// (lane j: column j).  There A_t is tridiagonal and C_t diagonal, so A_t^-1
+// comes from w Thomas solves (one per lane, the pivots computed once per
+// wavefront, the lane's column held in registers) and every product of the
+// reduction is a scaling of its entries.  Odd t: A_t^-1 and its transpose
+// into slot (t - 1) / 2 of Ainv and Ainvt.  Even t = 2 u: the level-1 blocks
+//   A'_u = A_t - diag(c_{t-1}) A_{t-1}^-1 diag(c_{t-1})
+//              - diag(c_t) A_{t+1}^-1 diag(c_t),
+//   C'_u = diag(c_t) A_{t+1}^-1 diag(c_{t+1}) (and C'_u transposed),
+// the two inverses solved by the two wavefronts side by side.
+template <int W>
+__global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double* __restrict__ dd,
+                                                    const double* __restrict__ aa, const double* __restrict__ cc,
+                                                    double* __restrict__ Ainv, double* __restrict__ Ainvt,
+                                                    double* __restrict__ A1, double* __restrict__ C1,
+                                                    double* __restrict__ C1t) {
+    __shared__ double rm[2][W], gm[2][W];  // per wavefront: 1 / pivot, and a_{i-1} / pivot_{i-1}
+    __shared__ double part[W * W];         // the second wavefront's term of A'_u, [i][j]
+    const int t = blockIdx.x, q = threadIdx.x >> 6, j = threadIdx.x & 63, nn = w * w;
+    const bool lane = j < w;
+    // the line this wavefront inverts (-1: none)
+    const int k = (t & 1) ? (q == 0 ? t : -1) : (q == 0 ? (t >= 1 ? t - 1 : -1) : (t + 1 < nb ? t + 1 : -1));
+    double col[W];  // column j of A_k^-1
+    if (k >= 0) {
+        const double* d = dd + (size_t)k * w;
+        const double* a = aa + (size_t)k * w;
+        if (j == 0) {
+            double r = 1.0 / d[0];
+            rm[q][0] = r;
+            gm[q][0] = 0.0;
+            for (int i = 1; i < w; ++i) {
+                const double g = a[i - 1] * r;
+                r = 1.0 / (d[i] - a[i - 1] * g);
+                rm[q][i] = r;
+                gm[q][i] = g;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // forward: y_i = [i == j] + g_i y_{i-1}; back: x_i = (y_i + a_i x_{i+1}) / pivot_i
+        double y = j == 0 ? 1.0 : 0.0;
+        col[0] = y;
+#pragma unroll
+        for (int i = 1; i < W; ++i)
+            if (i < w) {
+                y = fma(gm[q][i], y, i == j ? 1.0 : 0.0);
+                col[i] = y;
+            }
+        double x = 0.0;
+#pragma unroll
+        for (int i = W - 1; i >= 0; --i)
+            if (i < w) {
+                x = (i == w - 1 ? col[i] : fma(a[i], x, col[i])) * rm[q][i];
+                col[i] = x;
+            }
+    }
+    if (t & 1) {
+        if (q == 0 && lane) {
+            const size_t s = (size_t)(t >> 1) * nn;
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                if (i < w) {
+                    Ainv[s + i * w + j] = col[i];
+                    Ainvt[s + j * w + i] = col[i];
+                }
+        }
+        return;
+    }
+    const int u = t >> 1;
+    const size_t s = (size_t)u * nn;
+    if (q == 1) {
+        // diag(c_t) A_{t+1}^-1 diag(c_t) into LDS; C'_u and its transpose
+        if (k >= 0 && lane) {
+            const double* c = cc + (size_t)t * w;
+            const bool hc = t + 2 < nb;
+            const double cj = c[j], c2j = hc ? cc[(size_t)(t + 1) * w + j] : 0.0;
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                if (i < w) {
+                    part[i * W + j] = c[i] * col[i] * cj;
+                    if (hc) {
+                        const double v = c[i] * col[i] * c2j;
+                        C1[s + i * w + j] = v;
+                        C1t[s + j * w + i] = v;
+                    }
+                }
+        } else if (lane) {
+            for (int i = 0; i < w; ++i) part[i * W + j] = 0.0;
+        }
+    }
+    __syncthreads();
+    if (q == 0 && lane) {
+        const double* c = t >= 1 ? cc + (size_t)(t - 1) * w : nullptr;
+        const double cj = c != nullptr ? c[j] : 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+            if (i < w) {
+                double v = dn_dk(dd + (size_t)t * w, aa + (size_t)t * w, i, j) - part[i * W + j];
+                if (c != nullptr) v -= c[i] * col[i] * cj;
+                A1[s + i * w + j] = v;
+            }
+    }
+}
+
 // Odd lines t = 2 x + 1 of a level of N lines, one workgroup each: A_t^-1,
 // E_t and F_t (F_t only when line t + 1 exists), each also stored transposed
 // (Et, Ft) for the back-substitution; slot x of the level's arrays.  Ct holds
@@ -432,11 +537,15 @@ __global__ __launch_bounds__(256) void k_bcr_top(int w, int n, const double* __r
 // inner-precision copy) receives the same blocks and the even-even blocks
 // read here: G_{t-1,j}, and G_{t+1,j} when t + 1 is the last line.  !OE
 // (j = 2 y + 1 >= t): G_tj and its transpose into Gw, or only into G when G
-// is non-null.  Dynamic LDS: dn_lds_bytes<W>().
-template <typename T, int W, int TS, bool OE>
+// is non-null.  L0 (level 0, where E_t = A_t^-1 diag(c_{t-1}) and
+// F_t = A_t^-1 diag(c_t)): G_tj = A_t^-1 (diag(c_{t-1}) G_{t-1,j} +
+// diag(c_t) G_{t+1,j}), one product; Et then holds A_t^-1 transposed and cc
+// the level's couplings.  Dynamic LDS: dn_lds_bytes<W>().
+template <typename T, int W, int TS, bool OE, bool L0>
 __global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, const double* __restrict__ Ainv,
                                                   const double* __restrict__ Et, const double* __restrict__ Ft,
-                                                  double* __restrict__ Gw, T* __restrict__ G) {
+                                                  const double* __restrict__ cc, double* __restrict__ Gw,
+                                                  T* __restrict__ G) {
     static_assert((W / TS) * (W / TS) == 256, "256 threads, TS x TS tiles");
     extern __shared__ __align__(16) double dsm[];
     double* Xt = dsm;
@@ -457,32 +566,57 @@ __global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, c
         dn_tile_load<TS>(acc, Ainv + (size_t)x * nn, w, w, ti, tj, false);
     else
         dn_zero<TS>(acc);
-    fx.put(Xt, w);
-    fy.put(Y, w);
-    __syncthreads();
-    if (OE && G != nullptr)
+    if constexpr (L0) {
+        // Y = diag(c_{t-1}) G_{t-1,j} + diag(c_t) G_{t+1,j}: one product
+        DnFrag<W> fz;
+        if (hi) fz.fetch(Gw + blk(t + 1), n, w);
+        fx.put(Xt, w);
+        const double* c0 = cc + (size_t)(t - 1) * w;
+        const double* c1 = cc + (size_t)t * w;
 #pragma unroll
         for (int q = 0; q < DnFrag<W>::PER; ++q) {
             const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-            if (e < nn) G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+            if (e < nn) Y[i * W + k] = c0[i] * fy.v[q] + (hi ? c1[i] * fz.v[q] : 0.0);
         }
-    if (hi) {
-        fx.fetch(Ft + (size_t)x * nn, w, w);
-        fy.fetch(Gw + blk(t + 1), n, w);
-    }
-    dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
-    if (hi) {
         __syncthreads();
-        fx.put(Xt, w);
-        fy.put(Y, w);
-        __syncthreads();
-        if (OE && G != nullptr && t + 1 == N - 1)
+        if (OE && G != nullptr)
 #pragma unroll
             for (int q = 0; q < DnFrag<W>::PER; ++q) {
                 const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-                if (e < nn) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+                if (e < nn) {
+                    G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+                    if (t + 1 == N - 1) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fz.v[q]);
+                }
             }
         dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+    } else {
+        fx.put(Xt, w);
+        fy.put(Y, w);
+        __syncthreads();
+        if (OE && G != nullptr)
+#pragma unroll
+            for (int q = 0; q < DnFrag<W>::PER; ++q) {
+                const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+                if (e < nn) G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+            }
+        if (hi) {
+            fx.fetch(Ft + (size_t)x * nn, w, w);
+            fy.fetch(Gw + blk(t + 1), n, w);
+        }
+        dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+        if (hi) {
+            __syncthreads();
+            fx.put(Xt, w);
+            fy.put(Y, w);
+            __syncthreads();
+            if (OE && G != nullptr && t + 1 == N - 1)
+#pragma unroll
+                for (int q = 0; q < DnFrag<W>::PER; ++q) {
+                    const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
+                    if (e < nn) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+                }
+            dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
+        }
     }
     const size_t tj0 = (size_t)t * sg * w * n + col, jt0 = (size_t)j * sg * w * n + (size_t)t * sg * w;
     const bool mirror = OE || t != j;

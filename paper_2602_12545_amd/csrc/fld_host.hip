@@ -745,8 +745,8 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
             const DenseGeom& g = in.dg;
             const int n = g.w * g.nb, w = g.w, nn = g.w * g.w;
             k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
-            k_bcr_init<<<(g.nb * nn + 255) / 256, 256, 0, ss>>>(w, g.nb, in.dd, in.aa, in.cc, in.rA[0], in.rC[0],
-                                                                in.rCt[0]);
+            if (g.nb == 1)
+                k_bcr_init<<<(nn + 255) / 256, 256, 0, ss>>>(w, 1, in.dd, in.aa, in.cc, in.rA[0], in.rC[0], in.rCt[0]);
             T* Gsep = std::is_same<T, double>::value ? nullptr : in.Ainv;
             auto run = [&](auto Wc) {
                 constexpr int W = decltype(Wc)::value, TS = W / 16;
@@ -754,14 +754,23 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
                 std::vector<int> Ns, offs;
                 int N = g.nb, off = 0, l = 0;
                 for (; N > 1; ++l) {
-                    const double *A = in.rA[l & 1], *C = in.rC[l & 1], *Ct = in.rCt[l & 1];
                     const int nx = (l + 1) & 1;
-                    k_bcr_elim<W, TS><<<N / 2, 256, lds, ss>>>(w, N, A, C, Ct, in.rAinv + (size_t)off * nn,
-                                                               in.rE + (size_t)off * nn, in.rF + (size_t)off * nn,
-                                                               in.rEt + (size_t)off * nn, in.rFt + (size_t)off * nn);
-                    k_bcr_reduce<W, TS><<<(N + 1) / 2, 256, lds, ss>>>(w, N, A, C, Ct, in.rE + (size_t)off * nn,
-                                                                       in.rF + (size_t)off * nn, in.rA[nx], in.rC[nx],
-                                                                       in.rCt[nx]);
+                    if (l == 0) {
+                        // tridiagonal lines: Thomas solves and scalings, level 1
+                        // straight from the staged coefficients (A^-1 of the odd
+                        // lines in rAinv, transposed in rEt)
+                        k_bcr_level0<W><<<N, 128, 0, ss>>>(
+                            w, N, in.dd, in.aa, in.cc, in.rAinv, in.rEt, in.rA[nx], in.rC[nx], in.rCt[nx]);
+                    } else {
+                        const double *A = in.rA[l & 1], *C = in.rC[l & 1], *Ct = in.rCt[l & 1];
+                        k_bcr_elim<W, TS><<<N / 2, 256, lds, ss>>>(w, N, A, C, Ct, in.rAinv + (size_t)off * nn,
+                                                                   in.rE + (size_t)off * nn, in.rF + (size_t)off * nn,
+                                                                   in.rEt + (size_t)off * nn,
+                                                                   in.rFt + (size_t)off * nn);
+                        k_bcr_reduce<W, TS><<<(N + 1) / 2, 256, lds, ss>>>(
+                            w, N, A, C, Ct, in.rE + (size_t)off * nn, in.rF + (size_t)off * nn, in.rA[nx], in.rC[nx],
+                            in.rCt[nx]);
+                    }
                     Ns.push_back(N);
                     offs.push_back(off);
                     off += N / 2;
@@ -773,10 +782,17 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
                     T* G = lv == 0 ? Gsep : nullptr;
                     const double *Ai = in.rAinv + (size_t)o * nn, *Et = in.rEt + (size_t)o * nn,
                                  *Ft = in.rFt + (size_t)o * nn;
-                    k_bcr_back<T, W, TS, true><<<dim3(Nl / 2, (Nl + 1) / 2), 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft,
-                                                                                           in.Gw, G);
-                    k_bcr_back<T, W, TS, false><<<dim3(Nl / 2, Nl / 2), 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft,
-                                                                                       in.Gw, G);
+                    const dim3 oe(Nl / 2, (Nl + 1) / 2), oo(Nl / 2, Nl / 2);
+                    if (lv == 0) {
+                        k_bcr_back<T, W, TS, true, true><<<oe, 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft, in.cc, in.Gw, G);
+                        k_bcr_back<T, W, TS, false, true><<<oo, 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft, in.cc, in.Gw,
+                                                                               G);
+                    } else {
+                        k_bcr_back<T, W, TS, true, false><<<oe, 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft, in.cc, in.Gw,
+                                                                               G);
+                        k_bcr_back<T, W, TS, false, false><<<oo, 256, lds, ss>>>(w, Nl, sg, n, Ai, Et, Ft, in.cc,
+                                                                                in.Gw, G);
+                    }
                 }
             };
             if (w <= 32)
@@ -881,8 +897,12 @@ fld_status alloc_inner(fld_ctx* ctx) {
         auto lds_attr = [&](auto Wc) -> hipError_t {
             constexpr int W = decltype(Wc)::value, TS = W / 16;
             const int b = (int)dn_lds_bytes<W>();
-            const void* fs[] = {(const void*)k_bcr_elim<W, TS>, (const void*)k_bcr_reduce<W, TS>,
-                                (const void*)k_bcr_back<T, W, TS, true>, (const void*)k_bcr_back<T, W, TS, false>};
+            const void* fs[] = {(const void*)k_bcr_elim<W, TS>,
+                                (const void*)k_bcr_reduce<W, TS>,
+                                (const void*)k_bcr_back<T, W, TS, true, true>,
+                                (const void*)k_bcr_back<T, W, TS, false, true>,
+                                (const void*)k_bcr_back<T, W, TS, true, false>,
+                                (const void*)k_bcr_back<T, W, TS, false, false>};
             for (const void* f : fs) {
                 const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
                 if (e != hipSuccess) return e;

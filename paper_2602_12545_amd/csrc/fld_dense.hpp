@@ -169,23 +169,29 @@ constexpr size_t dn_lds_bytes() {
 }
 
 // A w x w matrix (leading dimension ldm) staged through registers: all of a
-// thread's loads are issued before any is stored to LDS.
+// thread's loads are issued before any is stored to LDS.  Thread l takes
+// column l % W of rows l / W + q (256 / W), q < PER, so that a wavefront
+// reads whole rows.
 template <int W>
 struct DnFrag {
-    static constexpr int PER = W * W / 256;
+    static constexpr int PER = W * W / 256, STEP = 256 / W;
     double v[PER];
+    __device__ static inline int col() { return threadIdx.x % W; }
+    __device__ static inline int row(int q) { return threadIdx.x / W + STEP * q; }
     __device__ inline void fetch(const double* __restrict__ M, int ldm, int w) {
+        const int k = col();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-            if (e < w * w) v[q] = M[(size_t)i * ldm + k];
+            const int i = row(q);
+            if (i < w && k < w) v[q] = M[(size_t)i * ldm + k];
         }
     }
     __device__ inline void put(double* S, int w) const {
+        const int k = col();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-            if (e < w * w) S[i * W + k] = v[q];
+            const int i = row(q);
+            if (i < w && k < w) S[i * W + k] = v[q];
         }
     }
 };
@@ -278,6 +284,25 @@ __device__ inline void dn_zero(double (&a)[TS][TS]) {
         for (int c = 0; c < TS; ++c) a[r][c] = 0.0;
 }
 
+// M (leading dimension ldm) = the tile matrix transposed, staged through the
+// LDS array S (W x W, free on entry: the caller syncs before) so that the
+// global stores run along rows; S is in use until the caller's next sync.
+template <typename T, int W, int TS>
+__device__ inline void dn_store_t(const double (&a)[TS][TS], double* S, T* __restrict__ M, int ldm, int w, int ti,
+                                  int tj) {
+#pragma unroll
+    for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) S[(TS * tj + c) * W + TS * ti + r] = a[r][c];
+    __syncthreads();
+    const int k = DnFrag<W>::col();
+#pragma unroll
+    for (int q = 0; q < DnFrag<W>::PER; ++q) {
+        const int i = DnFrag<W>::row(q);
+        if (i < w && k < w) M[(size_t)i * ldm + k] = static_cast<T>(S[i * W + k]);
+    }
+}
+
 // Level 0 of the reduction: A_k (tridiagonal) and C_k (diagonal, so also its
 // own transpose Ct_k) of every line, dense.
 __global__ void k_bcr_init(int w, int nb, const double* __restrict__ dd, const double* __restrict__ aa,
@@ -312,15 +337,28 @@ __global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double*
                                                     double* __restrict__ A1, double* __restrict__ C1,
                                                     double* __restrict__ C1t) {
     __shared__ double rm[2][W], gm[2][W];  // per wavefront: 1 / pivot, and a_{i-1} / pivot_{i-1}
+    __shared__ double sd[2][W], sa[2][W];  // per wavefront: the line's diagonal and couplings
     __shared__ double part[W * W];         // the second wavefront's term of A'_u, [i][j]
     const int t = blockIdx.x, q = threadIdx.x >> 6, j = threadIdx.x & 63, nn = w * w;
     const bool lane = j < w;
     // the line this wavefront inverts (-1: none)
     const int k = (t & 1) ? (q == 0 ? t : -1) : (q == 0 ? (t >= 1 ? t - 1 : -1) : (t + 1 < nb ? t + 1 : -1));
     double col[W];  // column j of A_k^-1
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     if (k >= 0) {
-        const double* d = dd + (size_t)k * w;
-        const double* a = aa + (size_t)k * w;
+        // the line's coefficients into LDS, so that the sequential pivot
+        // loop waits on LDS, not on memory
+        if (lane) {
+            sd[q][j] = dd[(size_t)k * w + j];
+            sa[q][j] = aa[(size_t)k * w + j];
+        }
+        wave_sync();
+        const double* d = sd[q];
+        const double* a = sa[q];
         if (j == 0) {
             double r = 1.0 / d[0];
             rm[q][0] = r;
@@ -332,9 +370,7 @@ __global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double*
                 gm[q][i] = g;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
         // forward: y_i = [i == j] + g_i y_{i-1}; back: x_i = (y_i + a_i x_{i+1}) / pivot_i
         double y = j == 0 ? 1.0 : 0.0;
         col[0] = y;
@@ -353,15 +389,21 @@ __global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double*
             }
     }
     if (t & 1) {
+        // A_t^-1 by columns (coalesced along rows of Ainv), and its
+        // transpose through LDS (padded rows) so that Ainvt is also written
+        // along rows
+        const size_t s = (size_t)(t >> 1) * nn;
         if (q == 0 && lane) {
-            const size_t s = (size_t)(t >> 1) * nn;
 #pragma unroll
             for (int i = 0; i < W; ++i)
                 if (i < w) {
                     Ainv[s + i * w + j] = col[i];
-                    Ainvt[s + j * w + i] = col[i];
+                    part[i * W + j] = col[i];
                 }
         }
+        __syncthreads();
+        for (int r = q; r < w; r += 2)
+            if (lane) Ainvt[s + r * w + j] = part[j * W + r];
         return;
     }
     const int u = t >> 1;
@@ -376,11 +418,7 @@ __global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double*
             for (int i = 0; i < W; ++i)
                 if (i < w) {
                     part[i * W + j] = c[i] * col[i] * cj;
-                    if (hc) {
-                        const double v = c[i] * col[i] * c2j;
-                        C1[s + i * w + j] = v;
-                        C1t[s + j * w + i] = v;
-                    }
+                    if (hc) C1[s + i * w + j] = c[i] * col[i] * c2j;
                 }
         } else if (lane) {
             for (int i = 0; i < w; ++i) part[i * W + j] = 0.0;
@@ -397,6 +435,21 @@ __global__ __launch_bounds__(128) void k_bcr_level0(int w, int nb, const double*
                 if (c != nullptr) v -= c[i] * col[i] * cj;
                 A1[s + i * w + j] = v;
             }
+    }
+    if (t + 2 < nb) {
+        // C'_u transposed: the second wavefront restages C'_u in LDS once the
+        // first has read its term, then both write C'_u^T along rows
+        __syncthreads();
+        if (q == 1 && lane) {
+            const double* c = cc + (size_t)t * w;
+            const double c2j = cc[(size_t)(t + 1) * w + j];
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                if (i < w) part[i * W + j] = c[i] * col[i] * c2j;
+        }
+        __syncthreads();
+        for (int r = q; r < w; r += 2)
+            if (lane) C1t[s + r * w + j] = part[j * W + r];
     }
 }
 
@@ -437,7 +490,8 @@ __global__ __launch_bounds__(256) void k_bcr_elim(int w, int N, const double* __
     dn_zero<TS>(acc);
     dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
     dn_tile_store<double, TS>(acc, E + (size_t)x * nn, w, w, ti, tj, false);
-    dn_tile_store<double, TS>(acc, Et + (size_t)x * nn, w, w, ti, tj, true);
+    __syncthreads();
+    dn_store_t<double, W, TS>(acc, Y, Et + (size_t)x * nn, w, w, ti, tj);
     if (hasF) {
         __syncthreads();
         y2.put(Y, w);
@@ -445,7 +499,8 @@ __global__ __launch_bounds__(256) void k_bcr_elim(int w, int N, const double* __
         dn_zero<TS>(acc);
         dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
         dn_tile_store<double, TS>(acc, F + (size_t)x * nn, w, w, ti, tj, false);
-        dn_tile_store<double, TS>(acc, Ft + (size_t)x * nn, w, w, ti, tj, true);
+        __syncthreads();
+        dn_store_t<double, W, TS>(acc, Y, Ft + (size_t)x * nn, w, w, ti, tj);
     }
 }
 
@@ -506,7 +561,8 @@ __global__ __launch_bounds__(256) void k_bcr_reduce(int w, int N, const double* 
             dn_zero<TS>(q);
             dn_mm<W, TS>(Xt, Y, w, ti, tj, q);
             dn_tile_store<double, TS>(q, C2 + (size_t)u * nn, w, w, ti, tj, false);
-            dn_tile_store<double, TS>(q, C2t + (size_t)u * nn, w, w, ti, tj, true);
+            __syncthreads();
+            dn_store_t<double, W, TS>(q, Y, C2t + (size_t)u * nn, w, w, ti, tj);
         }
     }
 #pragma unroll
@@ -575,15 +631,15 @@ __global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, c
         const double* c1 = cc + (size_t)t * w;
 #pragma unroll
         for (int q = 0; q < DnFrag<W>::PER; ++q) {
-            const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-            if (e < nn) Y[i * W + k] = c0[i] * fy.v[q] + (hi ? c1[i] * fz.v[q] : 0.0);
+            const int i = DnFrag<W>::row(q), k = DnFrag<W>::col();
+            if (i < w && k < w) Y[i * W + k] = c0[i] * fy.v[q] + (hi ? c1[i] * fz.v[q] : 0.0);
         }
         __syncthreads();
         if (OE && G != nullptr)
 #pragma unroll
             for (int q = 0; q < DnFrag<W>::PER; ++q) {
-                const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-                if (e < nn) {
+                const int i = DnFrag<W>::row(q), k = DnFrag<W>::col();
+                if (i < w && k < w) {
                     G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
                     if (t + 1 == N - 1) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fz.v[q]);
                 }
@@ -596,8 +652,8 @@ __global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, c
         if (OE && G != nullptr)
 #pragma unroll
             for (int q = 0; q < DnFrag<W>::PER; ++q) {
-                const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-                if (e < nn) G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+                const int i = DnFrag<W>::row(q), k = DnFrag<W>::col();
+                if (i < w && k < w) G[blk(t - 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
             }
         if (hi) {
             fx.fetch(Ft + (size_t)x * nn, w, w);
@@ -612,21 +668,39 @@ __global__ __launch_bounds__(256) void k_bcr_back(int w, int N, int sg, int n, c
             if (OE && G != nullptr && t + 1 == N - 1)
 #pragma unroll
                 for (int q = 0; q < DnFrag<W>::PER; ++q) {
-                    const int e = threadIdx.x + 256 * q, i = e / w, k = e - i * w;
-                    if (e < nn) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
+                    const int i = DnFrag<W>::row(q), k = DnFrag<W>::col();
+                    if (i < w && k < w) G[blk(t + 1) + (size_t)i * n + k] = static_cast<T>(fy.v[q]);
                 }
             dn_mm<W, TS>(Xt, Y, w, ti, tj, acc);
         }
     }
     const size_t tj0 = (size_t)t * sg * w * n + col, jt0 = (size_t)j * sg * w * n + (size_t)t * sg * w;
     const bool mirror = OE || t != j;
-    if (OE || G == nullptr) {
+    // with a separate inner-precision copy (last level) the odd-odd blocks
+    // and the odd-even ones are not read again in FP64: only the even-odd
+    // transposes are, by the odd-odd pass
+    if (G == nullptr)
         dn_tile_store<double, TS>(acc, Gw + tj0, n, w, ti, tj, false);
-        if (mirror) dn_tile_store<double, TS>(acc, Gw + jt0, n, w, ti, tj, true);
-    }
-    if (G != nullptr) {
+    else
         dn_tile_store<T, TS>(acc, G + tj0, n, w, ti, tj, false);
-        if (mirror) dn_tile_store<T, TS>(acc, G + jt0, n, w, ti, tj, true);
+    if (mirror) {
+        // the transpose, staged through LDS for row-wise stores
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < TS; ++r)
+#pragma unroll
+            for (int c = 0; c < TS; ++c) Xt[(TS * tj + c) * W + TS * ti + r] = acc[r][c];
+        __syncthreads();
+        const int k = DnFrag<W>::col();
+#pragma unroll
+        for (int q = 0; q < DnFrag<W>::PER; ++q) {
+            const int i = DnFrag<W>::row(q);
+            if (i < w && k < w) {
+                const double v = Xt[i * W + k];
+                if (G == nullptr || OE) Gw[jt0 + (size_t)i * n + k] = v;
+                if (G != nullptr) G[jt0 + (size_t)i * n + k] = static_cast<T>(v);
+            }
+        }
     }
 }
 

@@ -278,8 +278,8 @@ def single_step_line(fld, torch, prob, opt, reps):
 
 def other_workloads(fld, torch, W, tuner, accuracy):
     """64 x 64 FP64 solves/s; the 1024 x 1024 and 2048 x 512 grids in mixed,
-    FP64 and FP32-only precision (the 1024 x 1024 schedule autotuned per
-    precision); each against the oracle when accuracy is set."""
+    FP64 and FP32-only precision (their schedules autotuned per precision);
+    each against the oracle when accuracy is set."""
     from oracle import fld_oracle as O
     out = {}
     # (label, precision, norm, rel_tol, reps): the metric's 1e-10 stop and, on
@@ -290,7 +290,7 @@ def other_workloads(fld, torch, W, tuner, accuracy):
                                  ("mixed_stop_2e-11", "mixed", 0, 2e-11, 10), ("fp64_stop_2e-11", "fp64", 0, 2e-11, 5),
                                  ("fp32", "fp32", 0, 1e-10, 5)], "tune"),
             ("c3", W.make_c3(), [("mixed", "mixed", 1, 1e-10, 10), ("fp64", "fp64", 1, 1e-10, 5),
-                                 ("fp32", "fp32", 1, 1e-10, 5)], None)]
+                                 ("fp32", "fp32", 1, 1e-10, 5)], "tune")]
     for name, prob, runs, tune in jobs:
         f = dev_fields(torch, prob)
         ref = O.step_problem(prob) if accuracy else None
@@ -304,7 +304,8 @@ def other_workloads(fld, torch, W, tuner, accuracy):
             for tp in ("mixed", "fp64"):
                 tuned[tp], _ = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                                [(b.kind, b.value) for b in prob.bc], f, prob.dt,
-                                               base=fld.default_options(precision=tp), reps=1, cache="")
+                                               base=fld.default_options(precision=tp, norm=runs[0][2]),
+                                               reps=1, cache="")
         for label, prec, norm, tol, reps in runs:
             opt = fld.default_options(precision=prec, norm=norm, rel_tol=tol)
             sched = tuned.get("fp64" if prec == "fp64" else "mixed")

@@ -272,14 +272,21 @@ def test_krylov_accelerated_levels(lib, name, kw, prec):
     ("c3", dict(nx=300, ny=200), 1024, (1,)),
     # one level: the whole grid solved densely (48 lines of 40 cells)
     ("c1", dict(nx=48, ny=40), 4096, (1,)),
+    # one level, the reduction's edge shapes: 4096 cells in 64 lines of 64;
+    # 300 lines of 8 (nine levels, lines along y); 100 lines of 33 (just past
+    # the 32-wide tiles); 1000 lines of 4 (ten levels)
+    ("c1", dict(nx=64, ny=64), 4096, (1,)),
+    ("c1", dict(nx=300, ny=8), 4096, (1,)),
+    ("c1", dict(nx=33, ny=100), 4096, (1,)),
+    ("c1", dict(nx=1000, ny=4), 4096, (1,)),
 ])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_dense_coarsest_level(lib, name, kw, cm, cycles, prec):
     """A coarsest level above 256 cells is solved with its exact inverse,
-    built on the GPU from block Schur complements and applied by a
+    built on the GPU by block cyclic reduction and applied by a
     multi-workgroup product: the step reaches the oracle's solution with the
-    line smoothers and (Cartesian recipes) the point smoother; on a one-level hierarchy the preconditioner
-    is A^-1 itself, so CG converges at once."""
+    line smoothers and (Cartesian recipes) the point smoother; on a one-level
+    hierarchy the preconditioner is A^-1 itself, so CG converges at once."""
     prob = W.make(name, **kw)
     print(f"[dense coarsest] {name} {prob.nx}x{prob.ny} coarse {cm} {prec}", flush=True)
     ref = O.step_problem(prob)

@@ -307,14 +307,14 @@ def single_step_line(fld, torch, prob, opt, reps):
 
 def other_workloads(fld, torch, W, tuner, accuracy):
     """64 x 64 FP64 solves/s; the 1024 x 1024 and 2048 x 512 grids in mixed,
-    FP64 and FP32-only precision (their schedules autotuned per precision);
+    FP64 and FP32-only precision (every schedule autotuned per precision);
     each against the oracle when accuracy is set."""
     from oracle import fld_oracle as O
     out = {}
     # (label, precision, norm, rel_tol, reps): the metric's 1e-10 stop and, on
     # the 1024 x 1024 grid, a tighter stop at which the error meets 1e-10 too
     # (a 1e-10 residual bounds the error only up to the conditioning)
-    jobs = [("c1", W.make_c1(), [("fp64", "fp64", 0, 1e-10, 200)], None),
+    jobs = [("c1", W.make_c1(), [("fp64", "fp64", 0, 1e-10, 200)], "tune"),
             ("c2", W.make_c2(), [("mixed", "mixed", 0, 1e-10, 10), ("fp64", "fp64", 0, 1e-10, 5),
                                  ("mixed_stop_2e-11", "mixed", 0, 2e-11, 10), ("fp64_stop_2e-11", "fp64", 0, 2e-11, 5),
                                  ("fp32", "fp32", 0, 1e-10, 5)], "tune"),
@@ -330,7 +330,7 @@ def other_workloads(fld, torch, W, tuner, accuracy):
         # binary32-only runs take the mixed-precision one
         tuned = {}
         if tune and tuner is not None:
-            for tp in ("mixed", "fp64"):
+            for tp in sorted({"fp64" if r[1] == "fp64" else "mixed" for r in runs}):
                 tuned[tp], _ = tuner.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                                [(b.kind, b.value) for b in prob.bc], f, prob.dt,
                                                base=fld.default_options(precision=tp, norm=runs[0][2]),

@@ -587,7 +587,7 @@ typedef struct {
 
 /* Single grid: candidates are base with smoother in {LINE, LINE_SPLIT, POINT},
  * mg_cycle in {K, V, W2, KL_K, KL_W2} (line smoothers; POINT keeps base's),
- * mg_coarse_max in {64, 256, 4096} and chunk in {8, 16, 4} (99 candidates);
+ * mg_coarse_max in {64, 256, 1024, 4096} and chunk in {8, 16, 4} (132 candidates);
  * precision, limiter,
  * norm and tolerances are those of base (NULL = defaults).  Each candidate
  * gets its own context and runs reps + 1 steps (the first untimed) from the

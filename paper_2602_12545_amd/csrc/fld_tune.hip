@@ -86,7 +86,7 @@ fld_status fld_tune(const fld_grid* grid, const fld_options* base, const double*
         if (sm != FLD_SMOOTH_POINT && !lines_fit) continue;
         for (int cy : {FLD_MG_CYCLE_K, FLD_MG_CYCLE_V, FLD_MG_CYCLE_W2, FLD_MG_CYCLE_KL_K, FLD_MG_CYCLE_KL_W2}) {
             if (sm == FLD_SMOOTH_POINT && cy != b0.mg_cycle) continue;
-            for (int cm : {64, 256, 4096})
+            for (int cm : {64, 256, 1024, 4096})
                 for (int ch : {8, 16, 4}) {
                     fld_options o = b0;
                     o.smoother = sm;

@@ -90,7 +90,7 @@ def tune_grid(nx: int, ny: int, geom: int, x_faces, y_faces, bcs: Sequence, fiel
         kind, value = (b if isinstance(b, tuple) else (b.kind, b.value))
         g.bc[s].kind, g.bc[s].value = int(kind), float(value)
     best = fld_options()
-    entries = (fld_tune_entry * 128)()
+    entries = (fld_tune_entry * 256)()  # the whole candidate table (132 entries)
     n = _I()
     f = fields
     st = lib.fld_tune(ctypes.byref(g), ctypes.byref(base), _ptr(f["E"]), _ptr(f["T"]), _ptr(f["rho"]),

@@ -20,8 +20,10 @@ def test_tune_grid_picks_a_converging_configuration(lib, tmp_path):
     path = str(tmp_path / "t.json")
     best, table = tune.tune_grid(prob.nx, prob.ny, prob.geom, prob.x_faces, prob.y_faces,
                                  [(b.kind, b.value) for b in prob.bc], f, prob.dt, base=base, reps=1, cache=path)
-    # 2 line smoothers x 5 cycles x 9, and point smoothing x 9
-    assert len(table) == 99
+    # 2 line smoothers x 5 cycles x 12 (4 coarsest sizes x 3 chunks), and
+    # point smoothing x 12
+    assert len(table) == 132
+    assert {e["options"]["mg_coarse_max"] for e in table} == {64, 256, 1024, 4096}
     ok = [e for e in table if e["status"] == 0]
     chosen = [e for e in ok if all(e["options"][k] == getattr(best, k) for k in e["options"])]
     assert chosen and chosen[0]["ms"] == min(e["ms"] for e in ok)

@@ -285,7 +285,10 @@ def c5_rows(cuts):
 
 
 def single_step_line(fld, torch, prob, opt, reps):
-    """Mean wall time of one step restored from the same initial state."""
+    """Median wall time of one step restored from the same initial state (each
+    step timed on its own, between synchronisations; the restoring copies are
+    outside the timed interval)."""
+    import statistics
     f = dev_fields(torch, prob)
     ctx = make_ctx(fld, prob, opt)
     E, T = f["E"].clone(), f["T"].clone()
@@ -293,14 +296,16 @@ def single_step_line(fld, torch, prob, opt, reps):
     def one():
         E.copy_(f["E"])
         T.copy_(f["T"])
-        return ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, f["ghost_E"], check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.step(E, T, f["rho"], f["kappa_R"], f["kappa_P"], f["c_v"], prob.dt, f["ghost_E"], check=False)
+        torch.cuda.synchronize()
+        return info, 1e3 * (time.perf_counter() - t0)
 
     one()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = [one() for _ in range(reps)]
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / reps
+    runs = [one() for _ in range(reps)]
+    infos = [r[0] for r in runs]
+    ms = statistics.median(r[1] for r in runs)
     ctx.close()
     return ms, infos, (E.cpu().numpy(), T.cpu().numpy())
 

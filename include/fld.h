@@ -169,8 +169,9 @@ typedef struct {
                                assembly (block cyclic reduction over the lines along the shorter
                                grid direction) and applied by a multi-workgroup product; the LDS
                                sub-cycle is then not used (inverse: nc^2 inner-precision words,
-                               nc = the level's cells, plus 11 nc min(nx, ny) doubles of set-up
-                               workspace, and nc^2 more doubles when the inner precision is FP32) */
+                               nc = the level's cells, plus (11 min(nx, ny) + 3) nc doubles of
+                               set-up workspace, and nc^2 more doubles when the inner precision
+                               is FP32)                                                       */
     int32_t mg_coarse_op;   /* fld_mg_coarse (default HALVED)                                */
     int32_t smoother;       /* fld_smoother (default LINE); LINE* need nx, ny <= 4096        */
     int32_t chunk;          /* CG iterations queued between host convergence checks (def 8) */

@@ -25,8 +25,8 @@ workloads (64 x 64 FP64 solves/s; 1024 x 1024 stretched Cartesian and
 the relative L2 error of E and T against the CPU oracle per workload (full
 size for the 64 x 64, 1024 x 1024 and 2048 x 512 grids and the 256 blocks, a
 full-resolution 4096 x 256 theta slab for the stress grid), the sub-cycled
-step and advection, and cpu_baseline: the oracle timed on the host on a
-bounded sample of the headline workload.
+step and advection, and cpu_baseline: the oracle timed on the host's cores
+on the headline grid cut into one decoupled theta slab per core.
 """
 from __future__ import annotations
 

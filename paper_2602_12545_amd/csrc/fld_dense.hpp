@@ -303,23 +303,6 @@ __device__ inline void dn_store_t(const double (&a)[TS][TS], double* S, T* __res
     }
 }
 
-// Level 0 of the reduction: A_k (tridiagonal) and C_k (diagonal, so also its
-// own transpose Ct_k) of every line, dense.
-__global__ void k_bcr_init(int w, int nb, const double* __restrict__ dd, const double* __restrict__ aa,
-                           const double* __restrict__ cc, double* __restrict__ A, double* __restrict__ C,
-                           double* __restrict__ Ct) {
-    const int nn = w * w;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nb * nn) return;
-    const int k = e / nn, r = e - k * nn, i = r / w, j = r - i * w;
-    A[e] = dn_dk(dd + k * w, aa + k * w, i, j);
-    if (k + 1 < nb) {
-        const double c = i == j ? cc[k * w + i] : 0.0;
-        C[e] = c;
-        Ct[e] = c;
-    }
-}
-
 // Level 0 of the reduction, one workgroup of two wavefronts per line t
 // (lane j: column j).  There A_t is tridiagonal and C_t diagonal, so A_t^-1
 // comes from w Thomas solves (one per lane, the pivots computed once per
@@ -572,18 +555,19 @@ __global__ __launch_bounds__(256) void k_bcr_reduce(int w, int N, const double* 
     dn_tile_store<double, TS>(acc, A2 + (size_t)u * nn, w, w, ti, tj, false);
 }
 
-// The one line left: G_00 = A_0^-1 into Gw (leading dimension n), and into
-// G when no level was reduced and G is a separate inner-precision copy.
-template <typename T, int W, int TS>
+// The one line left: G_00 = A_0^-1 into Gw (leading dimension n).  Level 0
+// always reduces (a dense level has at least two lines), so G's
+// inner-precision copy of this block is written by the last
+// back-substitution.
+template <int W, int TS>
 __global__ __launch_bounds__(256) void k_bcr_top(int w, int n, const double* __restrict__ A,
-                                                 double* __restrict__ Gw, T* __restrict__ G) {
+                                                 double* __restrict__ Gw) {
     __shared__ double buf[2 * (2 * W + 1)];
     const int ti = threadIdx.x / (W / TS), tj = threadIdx.x % (W / TS);
     double a[TS][TS];
     dn_tile_load<TS>(a, A, w, w, ti, tj, true);
     dn_gj<W, TS>(a, ti, tj, w, buf);
     dn_tile_store<double, TS>(a, Gw, n, w, ti, tj, false);
-    if (G != nullptr) dn_tile_store<T, TS>(a, G, n, w, ti, tj, false);
 }
 
 // Back-substitution over the odd lines t = 2 x + 1 of a level whose lines are

@@ -745,8 +745,6 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
             const DenseGeom& g = in.dg;
             const int n = g.w * g.nb, w = g.w, nn = g.w * g.w;
             k_dense_stage<<<(n + 255) / 256, 256, 0, ss>>>(g, in.dd, in.aa, in.cc);
-            if (g.nb == 1)
-                k_bcr_init<<<(nn + 255) / 256, 256, 0, ss>>>(w, 1, in.dd, in.aa, in.cc, in.rA[0], in.rC[0], in.rCt[0]);
             T* Gsep = std::is_same<T, double>::value ? nullptr : in.Ainv;
             auto run = [&](auto Wc) {
                 constexpr int W = decltype(Wc)::value, TS = W / 16;
@@ -776,7 +774,7 @@ fld_status build_hierarchy(fld_ctx* c, hipStream_t st) {
                     off += N / 2;
                     N = (N + 1) / 2;
                 }
-                k_bcr_top<T, W, TS><<<1, 256, 0, ss>>>(w, n, in.rA[l & 1], in.Gw, l == 0 ? Gsep : nullptr);
+                k_bcr_top<W, TS><<<1, 256, 0, ss>>>(w, n, in.rA[l & 1], in.Gw);
                 for (int lv = l - 1; lv >= 0; --lv) {
                     const int Nl = Ns[lv], o = offs[lv], sg = 1 << lv;
                     T* G = lv == 0 ? Gsep : nullptr;
@@ -868,7 +866,7 @@ fld_status alloc_inner(fld_ctx* ctx) {
         g.ny = cl.ny;
         g.cols = cl.ny < cl.nx ? 1 : 0;
         g.w = std::min(cl.nx, cl.ny);
-        g.nb = std::max(cl.nx, cl.ny);
+        g.nb = std::max(cl.nx, cl.ny);  // > kCoarseMax / kDenseW: at least two lines, so level 0 reduces
         g.tr = cl.tr ? 1 : 0;
         g.m = c64.m;
         g.We = c64.We;

@@ -21,7 +21,9 @@
 // odd j (the even-odd blocks just formed).  Every block inverted is a Schur
 // complement of the symmetric positive definite M-matrix A, so Gauss-Jordan
 // without pivoting inverts it stably, and the back-substitution only adds
-// non-negative terms.  All of it runs in FP64; G is stored in the inner
+// non-negative terms.  Level 0, whose blocks are tridiagonal and couplings
+// diagonal, inverts its lines by Thomas solves and forms the next level by
+// scalings, in one kernel.  All of it runs in FP64; G is stored in the inner
 // precision, in block order (unknown a = k w + p), and the product maps block
 // order to the level's storage order on the way in and out.
 #pragma once
